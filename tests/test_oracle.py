@@ -1,0 +1,267 @@
+"""Pins for the FP64 CPU oracle against what the paper and the mathematics fix.
+
+None of these checks retypes the oracle's own formula: each compares it with an
+independent fact -- a hand-worked instance of the paper's distance example,
+brute force on tiny inputs, the Gram identity the paper's INT8 trick rests on,
+closed forms for A = b I + c 11^T, LAPACK through numpy, dense inverses, and
+invariants of the regularised system.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+
+def _tiny_genotypes(n, m, seed):
+    return np.random.default_rng(seed).integers(0, 3, size=(n, m)).astype(np.int8)
+
+
+# --- distances (Algorithm 5 / "Engaging INT8 Tensor Cores" subsection) ---------------
+
+def test_three_patient_example(golden_dir):
+    """The paper's 3-patient, 2-marker example: D~ = D + D^T - 2 G^T G."""
+    spec = json.load(open(os.path.join(golden_dir, "three_patients.json")))
+    for case in spec["cases"]:
+        pts = case["patients"]
+        G = np.array([pts["a"], pts["b"], pts["c"]], np.int8)  # patients as rows
+        D = oracle.sqdist(G)
+        assert D.tolist() == case["D_tilde"]
+        assert (G.astype(np.int64) ** 2).sum(1).tolist() == case["norms"]
+
+
+def test_sqdist_brute_force():
+    G = _tiny_genotypes(6, 9, 1)
+    T = _tiny_genotypes(4, 9, 2)
+    D = oracle.sqdist(T, G)
+    for i in range(4):
+        for j in range(6):
+            want = sum((int(T[i, k]) - int(G[j, k])) ** 2 for k in range(9))
+            assert D[i, j] == want
+
+
+def test_sqdist_gram_identity():
+    """d_ij = n_i + n_j - 2 g_i . g_j (the identity behind the INT8 GEMM)."""
+    G = _tiny_genotypes(37, 501, 3).astype(np.int64)
+    nrm = (G * G).sum(1)
+    want = nrm[:, None] + nrm[None, :] - 2 * (G @ G.T)
+    assert np.array_equal(oracle.sqdist(G.astype(np.int8)), want)
+
+
+def test_sqdist_special_cases():
+    # identical rows are at distance 0
+    G = _tiny_genotypes(5, 40, 4)
+    G2 = np.vstack([G, G])
+    D = oracle.sqdist(G2)
+    assert all(D[i, i + 5] == 0 for i in range(5))
+    # rows 2 * e_i (one-hot, M >= N): every off-diagonal distance is 2^2 + 2^2 = 8
+    n, m = 7, 11
+    H = np.zeros((n, m), np.int8)
+    H[np.arange(n), np.arange(n)] = 2
+    D = oracle.sqdist(H)
+    assert np.array_equal(D, 8 * (1 - np.eye(n, dtype=np.int64)))
+    # extreme values: all-2 row vs all-0 row over m SNPs -> 4 m
+    E = np.array([[2] * 300, [0] * 300], np.int8)
+    assert oracle.sqdist(E)[0, 1] == 1200
+
+
+def test_sqdist_metric_properties():
+    G = _tiny_genotypes(20, 64, 5)
+    D = oracle.sqdist(G).astype(np.float64)
+    assert np.array_equal(D, D.T) and np.all(np.diag(D) == 0) and np.all(D >= 0)
+    R = np.sqrt(D)  # Euclidean distance obeys the triangle inequality
+    for i in range(20):
+        for j in range(20):
+            assert np.all(R[i, j] <= R[i, :] + R[:, j] + 1e-12)
+
+
+# --- kernel matrix -------------------------------------------------------------------
+
+def test_gaussian_matches_library_exp():
+    D = oracle.sqdist(_tiny_genotypes(30, 80, 6))
+    g = 1.0 / 80
+    K = oracle.gaussian(D, g)
+    # libm exp vs numpy's vectorised exp: both faithfully rounded, so within 1 ulp
+    assert np.max(np.abs(K / np.exp(-g * D.astype(np.float64)) - 1)) <= 2.3e-16
+    assert np.allclose(np.diag(K), 1.0) and np.all(K > 0) and np.all(K <= 1.0)
+    assert np.array_equal(K, K.T)
+
+
+def test_kernel_is_psd():
+    """The Gaussian kernel matrix is positive semi-definite (so lambda_min(K + lambda I) >= lambda)."""
+    G = synth.WORKLOADS["small"].genotypes(rows=300)
+    K = oracle.build_kernel(G, 1.0 / G.shape[1])
+    w = np.linalg.eigvalsh(K)
+    assert w.min() > -1e-12
+
+
+# --- Cholesky and solves (Algorithm 3) ----------------------------------------------------
+
+def _bc_matrix(n, b, c):
+    return b * np.eye(n) + c * np.ones((n, n))
+
+
+def test_cholesky_closed_form():
+    """A = b I + c 11^T: with s_j = b + j c,
+    L_jj = sqrt(b s_{j+1} / s_j) and L_ij = c sqrt(b) / sqrt(s_j s_{j+1}) for i > j."""
+    n, b, c = 300, 0.6, 0.45
+    L = oracle.cholesky(_bc_matrix(n, b, c))
+    s = b + c * np.arange(n + 1)
+    for j in range(n):
+        assert abs(L[j, j] - np.sqrt(b * s[j + 1] / s[j])) <= 1e-14 * L[j, j]
+        col = c * np.sqrt(b) / np.sqrt(s[j] * s[j + 1])
+        if j + 1 < n:
+            assert np.max(np.abs(L[j + 1:, j] - col)) <= 1e-14 * abs(col)
+    assert np.all(np.triu(L, 1) == 0)
+
+
+def test_cholesky_vs_lapack_and_backward_error():
+    w = synth.WORKLOADS["small"]
+    G = w.genotypes(rows=512)
+    A = oracle.build_kernel(G, w.gamma)
+    A[np.diag_indices_from(A)] += w.lam
+    L = oracle.cholesky(A)
+    assert np.linalg.norm(A - L @ L.T) / np.linalg.norm(A) <= 1e-13
+    assert np.max(np.abs(L - np.linalg.cholesky(A))) <= 1e-12
+
+
+def test_cholesky_detects_indefinite():
+    A = _bc_matrix(10, 1.0, 0.5)
+    A[4, 4] = -1.0
+    with pytest.raises(np.linalg.LinAlgError):
+        oracle.cholesky(A)
+    # lambda = 0 with duplicated genotype rows: K is singular -> breakdown (or no positive pivot)
+    G = _tiny_genotypes(8, 16, 7)
+    K = oracle.build_kernel(np.vstack([G, G]), 1.0 / 16)
+    with pytest.raises(np.linalg.LinAlgError):
+        oracle.cholesky(K - 1e-9 * np.eye(16))
+
+
+def test_triangular_solves():
+    rng = np.random.default_rng(8)
+    n, r = 120, 5
+    A = _bc_matrix(n, 0.7, 0.3) + 0.01 * np.diag(rng.random(n))
+    L = oracle.cholesky(A)
+    B = rng.standard_normal((n, r))
+    Z = oracle.forward(L, B)
+    assert np.allclose(L @ Z, B, rtol=0, atol=1e-12)
+    X = oracle.backward(L, Z)
+    assert np.allclose(L.T @ X, Z, rtol=0, atol=1e-12)
+
+
+def test_sherman_morrison():
+    """(b I + c 11^T) x = y has x = (y - c (1^T y) / (b + n c) 1) / b."""
+    n, b, c = 257, 0.55, 0.48
+    y = np.random.default_rng(9).standard_normal((n, 3))
+    W, _ = oracle.associate(c * np.ones((n, n)), y, b)  # K = c 11^T, lambda = b
+    want = (y - c * y.sum(0) / (b + n * c)) / b
+    assert np.max(np.abs(W - want)) <= 1e-13 * np.max(np.abs(want))
+
+
+def test_dense_inverse_small():
+    """At N <= 256 the weights equal inv(K + lambda I) Y (numpy's LAPACK inverse)."""
+    w = synth.WORKLOADS["small"]
+    G = w.genotypes(rows=200)
+    Y = w.phenotypes(G)
+    W = oracle.fit(G, Y, w.gamma, w.lam)
+    A = oracle.build_kernel(G, w.gamma) + w.lam * np.eye(200)
+    want = np.linalg.inv(A) @ Y
+    assert np.max(np.abs(W - want)) <= 1e-10 * np.max(np.abs(want))
+
+
+def test_large_gamma_limit():
+    """Distinct rows and huge gamma: K -> I, so W = Y / (1 + lambda)."""
+    G = _tiny_genotypes(50, 64, 10)
+    assert len({g.tobytes() for g in G}) == 50
+    Y = np.random.default_rng(11).standard_normal((50, 2))
+    W = oracle.fit(G, Y, 50.0, 0.3)
+    assert np.allclose(W, Y / 1.3, rtol=1e-14, atol=0)
+
+
+# --- Predict (Algorithm 4) and residual ---------------------------------------------------
+
+def test_predict_on_training_set():
+    """Predicting the training patients gives K W = Y - lambda W."""
+    w = synth.WORKLOADS["small"]
+    G = w.genotypes(rows=256)
+    Y = w.phenotypes(G)
+    W = oracle.fit(G, Y, w.gamma, w.lam)
+    P = oracle.predict(G, G, W, w.gamma)
+    assert np.max(np.abs(P - (Y - w.lam * W))) <= 1e-9 * np.max(np.abs(Y))
+
+
+def test_predict_brute_force():
+    G = _tiny_genotypes(9, 13, 12)
+    T = _tiny_genotypes(4, 13, 13)
+    W = np.random.default_rng(14).standard_normal((9, 2))
+    g = 0.07
+    P = oracle.predict(G, T, W, g)
+    for i in range(4):
+        for c in range(2):
+            s = 0.0
+            for j in range(9):
+                d = sum((int(T[i, k]) - int(G[j, k])) ** 2 for k in range(13))
+                s += np.exp(-g * d) * W[j, c]
+            assert abs(P[i, c] - s) <= 1e-13 * (1 + abs(s))
+
+
+def test_residual_rows():
+    w = synth.WORKLOADS["small"]
+    G = w.genotypes(rows=300)
+    Y = w.phenotypes(G)
+    W = oracle.fit(G, Y, w.gamma, w.lam)
+    rows = [0, 17, 299]
+    R = oracle.residual_rows(G, w.gamma, w.lam, W, Y, rows)
+    assert np.max(np.abs(R)) <= 1e-10
+    R0 = oracle.residual_rows(G, w.gamma, w.lam, np.zeros_like(W), Y, rows)
+    assert np.array_equal(R0, Y[rows])
+
+
+def test_planted_mistake_is_caught():
+    """A Cholesky with a dropped term (no subtraction for the first column) fails the pins."""
+    n, b, c = 40, 0.6, 0.45
+    A = _bc_matrix(n, b, c)
+    good = oracle.cholesky(A)
+    bad = good.copy()
+    bad[1:, 1] += good[1:, 0] * good[1, 0] / good[1, 1]  # what skipping p=0 would leave
+    s = b + c * np.arange(n + 1)
+    col = c * np.sqrt(b) / np.sqrt(s[1] * s[2])
+    assert np.max(np.abs(good[2:, 1] - col)) <= 1e-14
+    assert np.max(np.abs(bad[2:, 1] - col)) > 1e-3
+
+
+# --- input generator ----------------------------------------------------------------
+
+def test_philox_known_answers():
+    """Philox4x32-10 known-answer vectors from Salmon et al. (SC'11)."""
+    assert synth.philox4x32_10([0, 0, 0, 0], [0, 0]).tolist() == \
+        [0x6627e8d5, 0xe169c58d, 0xbc57ac4c, 0x9b00dbd8]
+    assert synth.philox4x32_10([0xffffffff] * 4, [0xffffffff] * 2).tolist() == \
+        [0x408f276d, 0x41c83b0e, 0xa20bc7c6, 0x6d5451fd]
+    assert synth.philox4x32_10([0x243f6a88, 0x85a308d3, 0x13198a2e, 0x03707344],
+                               [0xa4093822, 0x299f31d0]).tolist() == \
+        [0xd16cfe09, 0x94fdcceb, 0x5001e420, 0x24126ea1]
+
+
+def test_generator_row_addressable_and_binomial():
+    w = synth.WORKLOADS["small"]
+    G = w.genotypes(rows=64)
+    G2 = w.genotypes(rows=16, row0=40)
+    assert np.array_equal(G[40:56], G2)
+    assert set(np.unique(G).tolist()) <= {0, 1, 2}
+    Gb = w.genotypes(rows=2048)
+    p = w.maf_vector()
+    assert abs(Gb.mean() - 2 * p.mean()) < 0.01
+
+
+def test_ld_blocks():
+    w = synth.WORKLOADS["large"]
+    spec = w.ld_spec()
+    founders, length, prob = spec
+    G = synth.genotypes(400, w.m, w.maf_vector(), w.seed, ld_blocks=spec)
+    f = founders[0]
+    same = (G[:, f + 1:f + length] == G[:, f:f + 1]).mean()
+    assert 0.85 < same < 0.99  # ~10% resampled, some of those equal by chance
