@@ -1,0 +1,199 @@
+"""Benchmark: kernel ridge regression Build + Factor + Solve on one MI355X.
+
+One step = the whole hot path on one batch of synthetic input already
+resident in HBM: INT8-MFMA Gram with the distance/exp epilogue, the
+adaptive-precision tile Cholesky of K + lambda I (FP64 diagonal tiles,
+FP32/FP16/FP8 trailing updates), FP32 triangular solves for all phenotypes
+and FP64 iterative refinement to a forward-error bound of 1e-6.
+
+Op count per step (the paper's complexity figures for Build and the
+Cholesky, plus the solves): n^2 m + n^3 / 3 + 2 n^2 r.
+
+Prints ONE JSON line (rank 0).  The same ops are timed on the plain FP32 GPU
+path (FP32 diagonal POTRF and updates, FP32 solves, no refinement) for the
+speed-up ratio, and the CPU oracle is timed on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK = {  # MI355X published dense peaks
+    "hbm_GBps": 8000.0,
+    "int8_TOPs": 5000.0,
+    "fp8_TFLOPs": 5000.0,
+    "fp16_TFLOPs": 2500.0,
+    "fp32_TFLOPs": 157.3,
+    "fp64_TFLOPs": 78.6,
+}
+
+
+def ops_per_step(n, m, r):
+    return float(n) * n * m + float(n) ** 3 / 3.0 + 2.0 * n * n * r
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="single", choices=["single", "small"])
+    ap.add_argument("--n", type=int, default=0, help="override the number of patients")
+    ap.add_argument("--plain-steps", type=int, default=1)
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=2048, help="patients in the oracle sample")
+    ap.add_argument("--eps", type=float, default=1.0)
+    ap.add_argument("--high-panels", type=int, default=1)
+    ap.add_argument("--tile", type=int, default=512)
+    ap.add_argument("--verbose", action="store_true")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synth
+    import paper_2409_01712_amd as krr
+
+    w = synth.WORKLOADS[args.workload]
+    n = args.n or w.n
+    m, r = w.m, w.r
+    t0 = time.time()
+    Gh = w.genotypes(rows=n)
+    Yh = w.phenotypes(Gh)
+    gen_s = time.time() - t0
+    dev = torch.device("cuda:0")
+    G = torch.from_numpy(Gh).to(dev)
+    Y = torch.from_numpy(Yh).to(dev)
+    torch.cuda.synchronize()
+    log = (lambda *a: print(*a, file=sys.stderr, flush=True)) if args.verbose else (lambda *a: None)
+    log("inputs: n=%d m=%d r=%d generated in %.1fs" % (n, m, r, gen_s))
+
+    ctx = krr.krr_create(0, tile=args.tile)
+    adaptive = krr.Policy(eps=args.eps, high_panels=args.high_panels)
+    plain = krr.plain_fp32_policy()
+    refine = krr.Refine(method=krr.KRR_REFINE_IR, max_iters=30, tol=1e-6)
+    no_refine = krr.Refine(method=krr.KRR_REFINE_NONE)
+
+    def step(policy, ref):
+        K = krr.krr_build_kernel(ctx, G, w.gamma, w.lam)
+        F = krr.krr_factor(ctx, K, policy)
+        X, info, st = krr.krr_solve(ctx, F, Y, ref, check=False)
+        finfo = krr.krr_factor_get_info(F)
+        F.release()
+        K.release()
+        return X, info, st, finfo
+
+    for i in range(args.warmup):
+        step(adaptive, refine)
+        log("warmup %d done" % i)
+    torch.cuda.synchronize()
+
+    krr.krr_timers_enable(ctx, True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        X, info, st, finfo = step(adaptive, refine)
+        log("step %d: iters=%d bound=%.2e" % (i, info.iters, info.fwd_err_bound))
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    stages = krr.krr_timers_read(ctx)
+    krr.krr_timers_enable(ctx, False)
+
+    ops = ops_per_step(n, m, r)
+    value = ops / dt
+    out = {
+        "metric": "KRR build+factor+solve Op/s vs plain FP32 GPU path at <=1e-5 rel err vs FP64",
+        "value": value,
+        "unit": "Op/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "mixed:i8,f8,f16,f32,f64",
+        "data": "synthetic (seeded Philox Binomial(2,p) genotypes, epistatic phenotypes)",
+        "config": {
+            "workload": "single KRR instance n=%d patients, m=%d SNPs, r=%d phenotypes, "
+                        "gamma=1/m, lambda=%g, tile %d, adaptive FP32/FP16/FP8 updates + FP64 "
+                        "diagonal + FP64 refinement" % (n, m, r, w.lam, args.tile),
+            "n": n, "m": m, "nrhs": r, "gamma": w.gamma, "lambda": w.lam, "tile": args.tile,
+            "eps": args.eps, "high_panels": args.high_panels,
+            "parallelism": "single GPU",
+        },
+        "ops_per_step": ops,
+        "refine": {"iters": info.iters, "fwd_err_bound": info.fwd_err_bound,
+                   "first_bound": info.first_bound, "converged": bool(info.converged)},
+        "updates": {"fp32": int(finfo.updates[0]), "fp16": int(finfo.updates[1]),
+                    "fp8": int(finfo.updates[2]), "promotions": int(finfo.promotions)},
+        "stages_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in stages.items() if v[1]},
+    }
+
+    # dominant kernel: the INT8 Gram (one launch per step)
+    g_ms, g_cnt = stages["gram"]
+    gram_avg_s = g_ms / g_cnt / 1e3
+    gram_ops = float(n) * n * m  # n^2/2 unique pairs x 2m ops (multiply + add)
+    achieved = gram_ops / gram_avg_s / 1e12
+    out["roofline"] = {
+        "kernel": "k_gram_tiles (INT8 MFMA Gram + distance/exp epilogue)",
+        "bound": "mfma", "achieved": achieved, "peak": PEAK["int8_TOPs"], "unit": "TOP/s",
+        "frac": achieved / PEAK["int8_TOPs"], "traffic": None,
+        "avg_launch_ms": gram_avg_s * 1e3,
+    }
+    u_ms, u_cnt = stages["update"]
+    out["update_stage"] = {"ms_per_step": u_ms / args.steps, "launches_per_step": u_cnt / args.steps}
+
+    if not args.no_plain:
+        for i in range(args.warmup):
+            step(plain, no_refine)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(args.plain_steps):
+            Xp, pinfo, _, _ = step(plain, no_refine)
+        torch.cuda.synchronize()
+        pdt = (time.perf_counter() - t0) / args.plain_steps
+        # accuracy of the plain path, measured by the FP64 residual bound
+        K = krr.krr_build_kernel(ctx, G, w.gamma, w.lam)
+        F = krr.krr_factor(ctx, K, plain)
+        _, pin, _ = krr.krr_solve(ctx, F, Y, krr.Refine(max_iters=0, tol=0.0), check=False)
+        F.release()
+        K.release()
+        out["plain_fp32"] = {"value": ops / pdt, "ms_per_step": pdt * 1e3,
+                             "fwd_err_bound": pin.fwd_err_bound}
+        out["speedup_vs_plain_fp32"] = pdt / dt
+
+    if not args.no_cpu:
+        import oracle
+        ns = min(args.cpu_sample, n)
+        Gs = np.ascontiguousarray(Gh[:ns])
+        Ys = np.ascontiguousarray(Yh[:ns])
+        t0 = time.perf_counter()
+        oracle.fit(Gs, Ys, w.gamma, w.lam)
+        cdt = time.perf_counter() - t0
+        out["cpu_baseline"] = {
+            "value": ops_per_step(ns, m, r) / cdt, "unit": "Op/s", "cores": oracle.threads(),
+            "kind": "oracle",
+            "sample": "first %d patients of the same genotype matrix (all %d SNPs, %d phenotypes): "
+                      "FP64 build + Cholesky + solves, %.1f s" % (ns, m, r, cdt),
+        }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

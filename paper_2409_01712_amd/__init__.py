@@ -1,0 +1,356 @@
+"""MI355X (gfx950) kernel ridge regression for multivariate GWAS.
+
+Python binding over the C ABI in include/krr.h (libkrr.so, built in-tree by
+``paper_2409_01712_amd.build``).  The functions carry the C names and only
+marshal arguments: torch tensors provide device memory and the stream, every
+step of the computation runs in the library's HIP kernels.  There is no CPU
+fallback: if the library is missing, loading raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libkrr.so")
+
+# status codes (krr_status)
+KRR_SUCCESS = 0
+KRR_ERROR_INVALID_VALUE = 1
+KRR_ERROR_BAD_GENOTYPE = 2
+KRR_ERROR_OUT_OF_MEMORY = 3
+KRR_ERROR_NOT_POSITIVE_DEFINITE = 4
+KRR_ERROR_NOT_CONVERGED = 5
+KRR_ERROR_HIP = 6
+KRR_ERROR_NOT_SUPPORTED = 7
+
+KRR_PREC_FP32, KRR_PREC_FP16, KRR_PREC_FP8 = 0, 1, 2
+KRR_POLICY_FP32, KRR_POLICY_ADAPTIVE, KRR_POLICY_FIXED = 0, 1, 2
+KRR_REFINE_NONE, KRR_REFINE_IR, KRR_REFINE_PCG, KRR_REFINE_AUTO = 0, 1, 2, 3
+
+
+class krr_options(ctypes.Structure):
+    _fields_ = [("tile", ctypes.c_int32), ("verbose", ctypes.c_int32),
+                ("workspace_limit", ctypes.c_int64)]
+
+
+class krr_precision_policy(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int32), ("allowed", ctypes.c_int32), ("eps", ctypes.c_double),
+                ("high_panels", ctypes.c_int32), ("fixed_prec", ctypes.c_int32),
+                ("allow_promotion", ctypes.c_int32), ("diag_fp64", ctypes.c_int32)]
+
+
+class krr_refine_opts(ctypes.Structure):
+    _fields_ = [("method", ctypes.c_int32), ("max_iters", ctypes.c_int32), ("tol", ctypes.c_double)]
+
+
+class krr_solve_info(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("converged", ctypes.c_int32),
+                ("fwd_err_bound", ctypes.c_double), ("backward_err", ctypes.c_double),
+                ("first_bound", ctypes.c_double)]
+
+
+class krr_factor_info(ctypes.Structure):
+    _fields_ = [("updates", ctypes.c_int64 * 3), ("promotions", ctypes.c_int32),
+                ("breakdown_col", ctypes.c_int64), ("nt", ctypes.c_int32), ("tile", ctypes.c_int32),
+                ("norm_a", ctypes.c_double)]
+
+
+_lib = None
+
+# (name, restype, argtypes) for every entry point of include/krr.h
+_P, _I64, _D, _I = ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_int
+_SIGS = [
+    ("krr_create", _I, [ctypes.POINTER(_P), _I, _P, ctypes.POINTER(krr_options)]),
+    ("krr_destroy", _I, [_P]),
+    ("krr_set_stream", _I, [_P, _P]),
+    ("krr_build_kernel", _I, [_P, _P, _I64, _I64, _I64, _D, _D, ctypes.POINTER(_P)]),
+    ("krr_kernel_release", _I, [_P]),
+    ("krr_factor", _I, [_P, _P, ctypes.POINTER(krr_precision_policy), ctypes.POINTER(_P)]),
+    ("krr_factor_release", _I, [_P]),
+    ("krr_factor_get_info", _I, [_P, ctypes.POINTER(krr_factor_info)]),
+    ("krr_solve", _I, [_P, _P, _P, _I64, _I64, _P, _I64, ctypes.POINTER(krr_refine_opts),
+                       ctypes.POINTER(krr_solve_info)]),
+    ("krr_predict", _I, [_P, _P, _P, _I64, _I64, _P, _I64, _I64, _P, _I64]),
+    ("krr_kernel_copy_distances", _I, [_P, _I64, _I64, _I64, _I64, _P, _I64]),
+    ("krr_kernel_copy_matrix", _I, [_P, _I64, _I64, _I64, _I64, _P, _I64]),
+    ("krr_factor_copy_l", _I, [_P, _I64, _I64, _I64, _I64, _P, _I64]),
+    ("krr_kernel_tile_norms", _I, [_P, _P, _I64]),
+    ("krr_factor_precision_map", _I, [_P, _P, _I64]),
+    ("krr_timers_enable", _I, [_P, ctypes.c_int32]),
+    ("krr_timers_read", _I, [_P, _P, _P, ctypes.c_int32]),
+    ("krr_stage_name", ctypes.c_char_p, [ctypes.c_int32]),
+    ("krr_status_string", ctypes.c_char_p, [_I]),
+]
+
+KRR_STAGE_COUNT = 11
+
+
+def load():
+    """Load libkrr.so (raises OSError if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise OSError("libkrr.so is not built: run paper_2409_01712_amd.build.build() "
+                          "(hipcc --offload-arch=gfx950)")
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, res, args in _SIGS:
+            f = getattr(lib, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = lib
+    return _lib
+
+
+class KRRError(RuntimeError):
+    def __init__(self, status: int, where: str = ""):
+        self.status = status
+        msg = load().krr_status_string(status).decode()
+        super().__init__("%s: %s (status %d)" % (where, msg, status))
+
+
+def _check(status: int, where: str):
+    if status != KRR_SUCCESS:
+        raise KRRError(status, where)
+
+
+def _ptr(t) -> int:
+    return t.data_ptr()
+
+
+def _stream_handle(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream
+
+
+class Context:
+    def __init__(self, handle, device):
+        self.handle = handle
+        self.device = device
+
+    def close(self):
+        if self.handle:
+            load().krr_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Kernel:
+    """Device-resident kernel matrix; keeps the genotype tensor alive."""
+
+    def __init__(self, handle, ctx, G, n, m, gamma, lam):
+        self.handle, self.ctx, self.G = handle, ctx, G
+        self.n, self.m, self.gamma, self.lam = n, m, gamma, lam
+
+    def release(self):
+        if self.handle:
+            load().krr_kernel_release(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.release()
+        except Exception:
+            pass
+
+
+class Factor:
+    def __init__(self, handle, kernel):
+        self.handle, self.kernel = handle, kernel
+
+    def release(self):
+        if self.handle:
+            load().krr_factor_release(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.release()
+        except Exception:
+            pass
+
+
+@dataclass
+class Policy:
+    mode: int = KRR_POLICY_ADAPTIVE
+    allowed: int = (1 << KRR_PREC_FP16) | (1 << KRR_PREC_FP8)
+    eps: float = 1.0
+    high_panels: int = 1
+    fixed_prec: int = KRR_PREC_FP16
+    allow_promotion: int = 1
+    diag_fp64: int = 1
+
+    def c(self):
+        return krr_precision_policy(self.mode, self.allowed, self.eps, self.high_panels,
+                                    self.fixed_prec, self.allow_promotion, self.diag_fp64)
+
+
+def plain_fp32_policy() -> Policy:
+    """Every update and the diagonal POTRF in FP32: the plain single-precision path."""
+    return Policy(mode=KRR_POLICY_FP32, allowed=0, diag_fp64=0, allow_promotion=0)
+
+
+@dataclass
+class Refine:
+    method: int = KRR_REFINE_IR
+    max_iters: int = 30
+    tol: float = 1e-6
+
+    def c(self):
+        return krr_refine_opts(self.method, self.max_iters, self.tol)
+
+
+def krr_create(device: int = 0, stream=None, tile: int = 512, verbose: int = 0,
+               workspace_limit: int = 0) -> Context:
+    lib = load()
+    h = ctypes.c_void_p()
+    opts = krr_options(tile, verbose, workspace_limit)
+    _check(lib.krr_create(ctypes.byref(h), device, _stream_handle(stream), ctypes.byref(opts)),
+           "krr_create")
+    return Context(h, device)
+
+
+def krr_set_stream(ctx: Context, stream=None):
+    _check(load().krr_set_stream(ctx.handle, _stream_handle(stream)), "krr_set_stream")
+
+
+def padded_genotypes(G):
+    """Return G (int8, n x m, on the GPU) with a row pitch that is a multiple of 16 bytes."""
+    import torch
+    assert G.dtype == torch.int8 and G.dim() == 2 and G.is_cuda
+    n, m = G.shape
+    if G.stride(1) == 1 and G.stride(0) % 16 == 0 and G.stride(0) >= m and G.data_ptr() % 16 == 0:
+        return G
+    pitch = (m + 15) // 16 * 16
+    buf = torch.zeros((n, pitch), dtype=torch.int8, device=G.device)
+    buf[:, :m] = G
+    return buf[:, :m]
+
+
+def krr_timers_enable(ctx: Context, enable: bool = True):
+    _check(load().krr_timers_enable(ctx.handle, 1 if enable else 0), "krr_timers_enable")
+
+
+def krr_timers_read(ctx: Context) -> dict:
+    """{stage name: (total GPU ms, number of timed intervals)} since the last enable."""
+    import numpy as np
+    ms = np.zeros(KRR_STAGE_COUNT, np.float64)
+    cnt = np.zeros(KRR_STAGE_COUNT, np.int64)
+    lib = load()
+    _check(lib.krr_timers_read(ctx.handle, ms.ctypes.data, cnt.ctypes.data, KRR_STAGE_COUNT),
+           "krr_timers_read")
+    return {lib.krr_stage_name(i).decode(): (float(ms[i]), int(cnt[i]))
+            for i in range(KRR_STAGE_COUNT)}
+
+
+def krr_build_kernel(ctx: Context, G, gamma: float, lam: float) -> Kernel:
+    G = padded_genotypes(G)
+    n, m = G.shape
+    h = ctypes.c_void_p()
+    _check(load().krr_build_kernel(ctx.handle, _ptr(G), n, m, G.stride(0), float(gamma),
+                                   float(lam), ctypes.byref(h)), "krr_build_kernel")
+    return Kernel(h, ctx, G, n, m, gamma, lam)
+
+
+def krr_factor(ctx: Context, K: Kernel, policy: Policy | None = None) -> Factor:
+    h = ctypes.c_void_p()
+    pol = (policy or Policy()).c()
+    _check(load().krr_factor(ctx.handle, K.handle, ctypes.byref(pol), ctypes.byref(h)),
+           "krr_factor")
+    return Factor(h, K)
+
+
+def krr_factor_get_info(F: Factor) -> krr_factor_info:
+    info = krr_factor_info()
+    _check(load().krr_factor_get_info(F.handle, ctypes.byref(info)), "krr_factor_get_info")
+    return info
+
+
+def _colmajor(Y, n):
+    import torch
+    Y = Y.to(torch.float64)
+    if Y.dim() == 1:
+        Y = Y[:, None]
+    assert Y.shape[0] == n
+    return Y.t().contiguous().t()  # column-major, leading dimension n
+
+
+def krr_solve(ctx: Context, F: Factor, Y, refine: Refine | None = None, check: bool = True):
+    """Solve (K + lambda I) X = Y; returns (X, info).  Y: (n, r) float64 on the GPU."""
+    import torch
+    n = F.kernel.n
+    Yc = _colmajor(Y, n)
+    r = Yc.shape[1]
+    X = torch.empty((r, n), dtype=torch.float64, device=Yc.device).t()
+    info = krr_solve_info()
+    opts = (refine or Refine()).c()
+    st = load().krr_solve(ctx.handle, F.handle, _ptr(Yc), r, n, _ptr(X), n, ctypes.byref(opts),
+                          ctypes.byref(info))
+    if check:
+        _check(st, "krr_solve")
+    return X, info, st
+
+
+def krr_predict(ctx: Context, K: Kernel, T, X):
+    """P = K_test X with K_test built from test genotypes T (n_test x m, int8, GPU)."""
+    import torch
+    T = padded_genotypes(T)
+    nt, m = T.shape
+    assert m == K.m
+    Xc = _colmajor(X, K.n)
+    r = Xc.shape[1]
+    P = torch.empty((r, nt), dtype=torch.float64, device=Xc.device).t()
+    _check(load().krr_predict(ctx.handle, K.handle, _ptr(T), nt, T.stride(0), _ptr(Xc), r, K.n,
+                              _ptr(P), nt), "krr_predict")
+    return P
+
+
+def krr_kernel_copy_distances(K: Kernel, i0: int, j0: int, rows: int, cols: int):
+    import torch
+    out = torch.empty((rows, cols), dtype=torch.int32, device=K.G.device)
+    _check(load().krr_kernel_copy_distances(K.handle, i0, j0, rows, cols, _ptr(out), cols),
+           "krr_kernel_copy_distances")
+    return out
+
+
+def krr_kernel_copy_matrix(K: Kernel, i0: int, j0: int, rows: int, cols: int):
+    import torch
+    out = torch.empty((rows, cols), dtype=torch.float32, device=K.G.device)
+    _check(load().krr_kernel_copy_matrix(K.handle, i0, j0, rows, cols, _ptr(out), cols),
+           "krr_kernel_copy_matrix")
+    return out
+
+
+def krr_factor_copy_l(F: Factor, i0: int, j0: int, rows: int, cols: int):
+    import torch
+    out = torch.empty((rows, cols), dtype=torch.float32, device=F.kernel.G.device)
+    _check(load().krr_factor_copy_l(F.handle, i0, j0, rows, cols, _ptr(out), cols),
+           "krr_factor_copy_l")
+    return out
+
+
+def krr_kernel_tile_norms(K: Kernel, nt: int):
+    import numpy as np
+    cnt = nt * (nt + 1) // 2
+    out = np.zeros(cnt, np.float64)
+    _check(load().krr_kernel_tile_norms(K.handle, out.ctypes.data, cnt), "krr_kernel_tile_norms")
+    return out
+
+
+def krr_factor_precision_map(F: Factor):
+    import numpy as np
+    info = krr_factor_get_info(F)
+    nt = info.nt
+    cnt = nt * nt * (nt + 1) // 2
+    out = np.zeros(cnt, np.uint8)
+    _check(load().krr_factor_precision_map(F.handle, out.ctypes.data, cnt),
+           "krr_factor_precision_map")
+    return out.reshape(nt, nt * (nt + 1) // 2)

@@ -1,0 +1,804 @@
+// C ABI of the KRR library: handles, argument validation and the host-side
+// orchestration of the Build / Associate / Predict phases of the paper's KRR
+// driver (arXiv 2409.01712, Algorithm 1).  Every arithmetic step runs in the
+// HIP kernels of build.hip, factor.hip and solve.hip.
+#include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "internal.h"
+
+using namespace krr;
+
+struct TimerRec {
+  int stage;
+  hipEvent_t a, b;
+};
+
+struct krr_context_s {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  krr_options opts{};
+  int64_t allocated = 0;
+  // stage timers
+  bool timing = false;
+  std::vector<TimerRec> recs;
+  std::vector<hipEvent_t> pool;
+  double total_ms[KRR_STAGE_COUNT] = {};
+  int64_t intervals[KRR_STAGE_COUNT] = {};
+};
+
+struct krr_kernel_s {
+  krr_context ctx = nullptr;
+  const int8_t *G = nullptr;
+  int64_t n = 0, m = 0, ldg = 0;
+  double gamma = 0, lambda = 0;
+  TileLayout L;
+  int32_t *D = nullptr;  // exact distances, packed lower tiles
+  float *A = nullptr;    // K + lambda I, FP32, packed lower tiles (null once consumed)
+  int32_t *nrm = nullptr;
+  double *etab = nullptr;
+  int64_t etab_len = 0;
+  double *tnorm = nullptr;      // per-tile Frobenius norms
+  double *tnorm_part = nullptr;
+  std::vector<double> tnorm_host;
+  double norm_a = -1.0;
+};
+
+struct krr_factor_s {
+  krr_kernel K = nullptr;
+  TileLayout L;
+  float *Lst = nullptr;   // FP32 factor, packed lower tiles
+  float *Linv = nullptr;  // inverses of the diagonal tiles, nt x nb x nb
+  krr_factor_info info{};
+  std::vector<uint8_t> pmap;
+};
+
+namespace {
+
+#define HIPCHK(x)                                  \
+  do {                                             \
+    hipError_t _e = (x);                           \
+    if (_e != hipSuccess) {                        \
+      if (getenv("KRR_DEBUG"))                     \
+        fprintf(stderr, "krr: %s failed: %s\n", #x, \
+                hipGetErrorString(_e));            \
+      return KRR_ERROR_HIP;                        \
+    }                                              \
+  } while (0)
+
+#define CHK(x)                    \
+  do {                            \
+    krr_status _s = (x);          \
+    if (_s != KRR_SUCCESS) return _s; \
+  } while (0)
+
+krr_status dalloc(krr_context ctx, void **p, size_t bytes) {
+  *p = nullptr;
+  if (bytes == 0) bytes = 16;
+  if (ctx->opts.workspace_limit > 0 && ctx->allocated + (int64_t)bytes > ctx->opts.workspace_limit)
+    return KRR_ERROR_OUT_OF_MEMORY;
+  hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    *p = nullptr;
+    return e == hipErrorOutOfMemory ? KRR_ERROR_OUT_OF_MEMORY : KRR_ERROR_HIP;
+  }
+  ctx->allocated += (int64_t)bytes;
+  return KRR_SUCCESS;
+}
+
+template <typename T>
+krr_status dalloc_t(krr_context ctx, T **p, int64_t count) {
+  return dalloc(ctx, (void **)p, (size_t)count * sizeof(T));
+}
+
+void dfree(krr_context ctx, void *p, size_t bytes) {
+  if (p) {
+    (void)hipFree(p);
+    ctx->allocated -= (int64_t)bytes;
+  }
+}
+
+krr_status launch_ok() {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) {
+    if (getenv("KRR_DEBUG")) fprintf(stderr, "krr: launch failed: %s\n", hipGetErrorString(e));
+    return KRR_ERROR_HIP;
+  }
+  return KRR_SUCCESS;
+}
+
+bool aligned16(const void *p) { return ((uintptr_t)p & 15u) == 0; }
+
+TileLayout make_layout(int64_t n, int nb) {
+  TileLayout L;
+  L.nb = nb;
+  L.n = n;
+  L.nt = (int)((n + nb - 1) / nb);
+  L.np = (int64_t)L.nt * nb;
+  return L;
+}
+
+struct Scoped {  // frees device buffers on scope exit unless released
+  krr_context ctx;
+  std::vector<std::pair<void *, size_t>> bufs;
+  explicit Scoped(krr_context c) : ctx(c) {}
+  template <typename T>
+  krr_status alloc(T **p, int64_t count) {
+    CHK(dalloc_t(ctx, p, count));
+    bufs.push_back({(void *)*p, (size_t)count * sizeof(T)});
+    return KRR_SUCCESS;
+  }
+  void release() { bufs.clear(); }
+  ~Scoped() {
+    for (auto &b : bufs) dfree(ctx, b.first, b.second);
+  }
+};
+
+hipEvent_t take_event(krr_context c) {
+  if (!c->pool.empty()) {
+    hipEvent_t e = c->pool.back();
+    c->pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  return e;
+}
+
+// Brackets the launches of one stage with events when timing is enabled.
+struct Stage {
+  krr_context c;
+  int64_t idx = -1;
+  Stage(krr_context ctx, int stage) : c(ctx) {
+    if (!c->timing) return;
+    TimerRec r{stage, take_event(c), take_event(c)};
+    if (!r.a || !r.b) return;
+    if (hipEventRecord(r.a, c->stream) != hipSuccess) return;
+    c->recs.push_back(r);
+    idx = (int64_t)c->recs.size() - 1;
+  }
+  ~Stage() {
+    if (idx >= 0) (void)hipEventRecord(c->recs[idx].b, c->stream);
+  }
+};
+
+void timers_drain(krr_context c) {
+  if (c->recs.empty()) return;
+  (void)hipEventSynchronize(c->recs.back().b);
+  for (auto &r : c->recs) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+      c->total_ms[r.stage] += ms;
+      c->intervals[r.stage] += 1;
+    } else {
+      (void)hipGetLastError();
+    }
+    c->pool.push_back(r.a);
+    c->pool.push_back(r.b);
+  }
+  c->recs.clear();
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *krr_stage_name(int32_t stage) {
+  static const char *names[KRR_STAGE_COUNT] = {
+      "row_norms", "gram", "potrf", "trsm", "convert", "update",
+      "fwd_sweep", "bwd_sweep", "residual", "cross_gram", "predict_apply"};
+  if (stage < 0 || stage >= KRR_STAGE_COUNT) return "unknown";
+  return names[stage];
+}
+
+krr_status krr_timers_enable(krr_context ctx, int32_t enable) {
+  if (!ctx) return KRR_ERROR_INVALID_VALUE;
+  HIPCHK(hipSetDevice(ctx->device));
+  timers_drain(ctx);
+  for (int i = 0; i < KRR_STAGE_COUNT; ++i) {
+    ctx->total_ms[i] = 0;
+    ctx->intervals[i] = 0;
+  }
+  ctx->timing = enable != 0;
+  return KRR_SUCCESS;
+}
+
+krr_status krr_timers_read(krr_context ctx, double *total_ms, int64_t *intervals, int32_t count) {
+  if (!ctx || count < 0) return KRR_ERROR_INVALID_VALUE;
+  HIPCHK(hipSetDevice(ctx->device));
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  timers_drain(ctx);
+  for (int i = 0; i < count && i < KRR_STAGE_COUNT; ++i) {
+    if (total_ms) total_ms[i] = ctx->total_ms[i];
+    if (intervals) intervals[i] = ctx->intervals[i];
+  }
+  return KRR_SUCCESS;
+}
+
+const char *krr_status_string(krr_status s) {
+  switch (s) {
+    case KRR_SUCCESS: return "success";
+    case KRR_ERROR_INVALID_VALUE: return "invalid value";
+    case KRR_ERROR_BAD_GENOTYPE: return "genotype value outside {0,1,2}";
+    case KRR_ERROR_OUT_OF_MEMORY: return "out of device memory or workspace limit";
+    case KRR_ERROR_NOT_POSITIVE_DEFINITE: return "matrix not positive definite (Cholesky breakdown)";
+    case KRR_ERROR_NOT_CONVERGED: return "refinement did not converge";
+    case KRR_ERROR_HIP: return "HIP runtime error";
+    case KRR_ERROR_NOT_SUPPORTED: return "not supported";
+  }
+  return "unknown status";
+}
+
+krr_status krr_create(krr_context *out, int device, void *stream, const krr_options *opts) {
+  if (!out) return KRR_ERROR_INVALID_VALUE;
+  *out = nullptr;
+  krr_options o{};
+  if (opts) o = *opts;
+  if (o.tile == 0) o.tile = 512;
+  if (o.tile != 256 && o.tile != 512) return KRR_ERROR_INVALID_VALUE;
+  if (o.workspace_limit < 0) return KRR_ERROR_INVALID_VALUE;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess) {
+    (void)hipGetLastError();
+    return KRR_ERROR_HIP;
+  }
+  if (device < 0 || device >= count) return KRR_ERROR_INVALID_VALUE;
+  HIPCHK(hipSetDevice(device));
+  krr_context c = new krr_context_s();
+  c->device = device;
+  c->stream = (hipStream_t)stream;
+  c->opts = o;
+  *out = c;
+  return KRR_SUCCESS;
+}
+
+krr_status krr_destroy(krr_context ctx) {
+  if (!ctx) return KRR_ERROR_INVALID_VALUE;
+  (void)hipSetDevice(ctx->device);
+  (void)hipStreamSynchronize(ctx->stream);
+  timers_drain(ctx);
+  for (hipEvent_t e : ctx->pool) (void)hipEventDestroy(e);
+  delete ctx;
+  return KRR_SUCCESS;
+}
+
+krr_status krr_set_stream(krr_context ctx, void *stream) {
+  if (!ctx) return KRR_ERROR_INVALID_VALUE;
+  ctx->stream = (hipStream_t)stream;
+  return KRR_SUCCESS;
+}
+
+static void kernel_free(krr_kernel K) {
+  krr_context c = K->ctx;
+  const TileLayout &L = K->L;
+  dfree(c, K->D, (size_t)L.elems() * 4);
+  dfree(c, K->A, (size_t)L.elems() * 4);
+  dfree(c, K->nrm, (size_t)L.np * 4);
+  dfree(c, K->etab, (size_t)K->etab_len * 8);
+  dfree(c, K->tnorm, (size_t)L.ntiles() * 8);
+  const int sb = L.nb / 256;
+  dfree(c, K->tnorm_part, (size_t)L.ntiles() * sb * sb * 8);
+}
+
+krr_status krr_build_kernel(krr_context ctx, const int8_t *G, int64_t n, int64_t m, int64_t ldg,
+                            double gamma, double lambda, krr_kernel *out) {
+  if (!out) return KRR_ERROR_INVALID_VALUE;
+  *out = nullptr;
+  if (!ctx || !G || n <= 0 || m <= 0 || ldg < m || (ldg % 16) != 0 || !aligned16(G))
+    return KRR_ERROR_INVALID_VALUE;
+  if (!(gamma > 0) || !isfinite(gamma) || !(lambda >= 0) || !isfinite(lambda))
+    return KRR_ERROR_INVALID_VALUE;
+  if (m > (1LL << 28) || n > (1LL << 30)) return KRR_ERROR_NOT_SUPPORTED;
+  HIPCHK(hipSetDevice(ctx->device));
+  hipStream_t s = ctx->stream;
+
+  krr_kernel K = new krr_kernel_s();
+  K->ctx = ctx;
+  K->G = G;
+  K->n = n;
+  K->m = m;
+  K->ldg = ldg;
+  K->gamma = gamma;
+  K->lambda = lambda;
+  K->L = make_layout(n, ctx->opts.tile);
+  const TileLayout &L = K->L;
+  K->etab_len = 4 * m + 1;
+  const int sb = L.nb / 256;
+  krr_status st = KRR_SUCCESS;
+  int32_t *flag = nullptr;
+  do {
+    if ((st = dalloc_t(ctx, &K->D, L.elems())) != KRR_SUCCESS) break;
+    if ((st = dalloc_t(ctx, &K->A, L.elems())) != KRR_SUCCESS) break;
+    if ((st = dalloc_t(ctx, &K->nrm, L.np)) != KRR_SUCCESS) break;
+    if ((st = dalloc_t(ctx, &K->etab, K->etab_len)) != KRR_SUCCESS) break;
+    if ((st = dalloc_t(ctx, &K->tnorm, L.ntiles())) != KRR_SUCCESS) break;
+    if ((st = dalloc_t(ctx, &K->tnorm_part, L.ntiles() * sb * sb)) != KRR_SUCCESS) break;
+    if ((st = dalloc_t(ctx, &flag, 1)) != KRR_SUCCESS) break;
+    launch_fill_i32(flag, 1, 0, s);
+    {
+      Stage t(ctx, KRR_STAGE_ROW_NORMS);
+      launch_row_norms(G, n, L.np, m, ldg, K->nrm, flag, s);
+    }
+    int32_t hflag = 0;
+    if (hipMemcpyAsync(&hflag, flag, 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) {
+      st = KRR_ERROR_HIP;
+      break;
+    }
+    if ((st = launch_ok()) != KRR_SUCCESS) break;
+    if (hflag) {
+      st = KRR_ERROR_BAD_GENOTYPE;
+      break;
+    }
+    launch_exp_table(K->etab, K->etab_len, gamma, s);
+    {
+      Stage t(ctx, KRR_STAGE_GRAM);
+      launch_gram_tiles(G, m, ldg, K->nrm, K->etab, K->etab_len, lambda, L, K->D, K->A,
+                        K->tnorm_part, s);
+    }
+    launch_tile_norms(K->tnorm_part, sb * sb, L.ntiles(), K->tnorm, s);
+    st = launch_ok();
+  } while (0);
+  if (flag) dfree(ctx, flag, 4);
+  if (st != KRR_SUCCESS) {
+    kernel_free(K);
+    delete K;
+    return st;
+  }
+  *out = K;
+  return KRR_SUCCESS;
+}
+
+krr_status krr_kernel_release(krr_kernel K) {
+  if (!K) return KRR_ERROR_INVALID_VALUE;
+  (void)hipSetDevice(K->ctx->device);
+  (void)hipStreamSynchronize(K->ctx->stream);
+  kernel_free(K);
+  delete K;
+  return KRR_SUCCESS;
+}
+
+static krr_status kernel_norm(krr_kernel K) {
+  if (K->norm_a >= 0) return KRR_SUCCESS;
+  const TileLayout &L = K->L;
+  K->tnorm_host.resize(L.ntiles());
+  HIPCHK(hipMemcpyAsync(K->tnorm_host.data(), K->tnorm, L.ntiles() * 8, hipMemcpyDeviceToHost,
+                        K->ctx->stream));
+  HIPCHK(hipStreamSynchronize(K->ctx->stream));
+  double s = 0.0;
+  for (int I = 0; I < L.nt; ++I)
+    for (int J = 0; J <= I; ++J) {
+      const double v = K->tnorm_host[TileLayout::tri(I, J)];
+      s += (I == J ? 1.0 : 2.0) * v * v;
+    }
+  // padding rows contribute identity entries (1 each) to the stored tiles
+  s -= (double)(L.np - L.n);
+  K->norm_a = sqrt(s > 0 ? s : 0.0);
+  return KRR_SUCCESS;
+}
+
+krr_status krr_kernel_tile_norms(krr_kernel K, double *host_dst, int64_t count) {
+  if (!K || !host_dst || count < K->L.ntiles()) return KRR_ERROR_INVALID_VALUE;
+  HIPCHK(hipSetDevice(K->ctx->device));
+  CHK(kernel_norm(K));
+  memcpy(host_dst, K->tnorm_host.data(), K->L.ntiles() * 8);
+  return KRR_SUCCESS;
+}
+
+static void factor_work_free(krr_context c, FactorWork &w, const TileLayout &L) {
+  const int64_t te = L.tile_elems(), pt = std::max(L.nt - 1, 1);
+  const int sb = L.nb / 128, parts = sb * sb;
+  dfree(c, w.W64, te * 8);
+  dfree(c, w.Winv64, te * 8);
+  dfree(c, w.Dinv64, (L.nb / 64) * 64 * 64 * 8);
+  dfree(c, w.P32, pt * te * 4);
+  dfree(c, w.P16, pt * te * 2);
+  dfree(c, w.P8, pt * te);
+  dfree(c, w.pnorm_part, pt * parts * 8);
+  dfree(c, w.pmax_part, pt * parts * 4);
+  dfree(c, w.pnorm, pt * 4);
+  dfree(c, w.pscale16, pt * 4);
+  dfree(c, w.pscale8, pt * 4);
+  dfree(c, w.flag, 4);
+  dfree(c, w.counts, 3 * 8);
+  w = FactorWork();
+}
+
+static krr_status factor_work_alloc(krr_context c, FactorWork &w, const TileLayout &L,
+                                    bool need16, bool need8) {
+  const int64_t te = L.tile_elems(), pt = std::max(L.nt - 1, 1);
+  const int sb = L.nb / 128, parts = sb * sb;
+  krr_status st;
+#define WA(ptr, cnt)                                                        \
+  if ((st = dalloc(c, (void **)&(ptr), (size_t)(cnt))) != KRR_SUCCESS) { \
+    factor_work_free(c, w, L);                                            \
+    return st;                                                            \
+  }
+  WA(w.W64, te * 8);
+  WA(w.Winv64, te * 8);
+  WA(w.Dinv64, (L.nb / 64) * 64 * 64 * 8);
+  WA(w.P32, pt * te * 4);
+  WA(w.P16, need16 ? pt * te * 2 : 16);
+  WA(w.P8, need8 ? pt * te : 16);
+  WA(w.pnorm_part, pt * parts * 8);
+  WA(w.pmax_part, pt * parts * 4);
+  WA(w.pnorm, pt * 4);
+  WA(w.pscale16, pt * 4);
+  WA(w.pscale8, pt * 4);
+  WA(w.flag, 4);
+  WA(w.counts, 3 * 8);
+#undef WA
+  return KRR_SUCCESS;
+}
+
+krr_status krr_factor(krr_context ctx, krr_kernel K, const krr_precision_policy *policy,
+                      krr_factorization *out) {
+  if (!out) return KRR_ERROR_INVALID_VALUE;
+  *out = nullptr;
+  if (!ctx || !K || K->ctx != ctx) return KRR_ERROR_INVALID_VALUE;
+  krr_precision_policy p{};
+  if (policy) {
+    p = *policy;
+  } else {
+    p.mode = KRR_POLICY_ADAPTIVE;
+    p.allowed = (1 << KRR_PREC_FP16) | (1 << KRR_PREC_FP8);
+    p.eps = 1.0;
+    p.high_panels = 1;
+    p.allow_promotion = 1;
+    p.diag_fp64 = 1;
+  }
+  if (p.mode < KRR_POLICY_FP32 || p.mode > KRR_POLICY_FIXED) return KRR_ERROR_INVALID_VALUE;
+  if (p.mode == KRR_POLICY_ADAPTIVE && !(p.eps > 0)) return KRR_ERROR_INVALID_VALUE;
+  if (p.mode == KRR_POLICY_FIXED && p.fixed_prec != KRR_PREC_FP16 && p.fixed_prec != KRR_PREC_FP8)
+    return KRR_ERROR_INVALID_VALUE;
+  if (p.high_panels < 0) return KRR_ERROR_INVALID_VALUE;
+  HIPCHK(hipSetDevice(ctx->device));
+  hipStream_t s = ctx->stream;
+  const TileLayout &L = K->L;
+  CHK(kernel_norm(K));
+
+  int allow16 = 0, allow8 = 0;
+  if (p.mode == KRR_POLICY_ADAPTIVE) {
+    allow16 = (p.allowed >> KRR_PREC_FP16) & 1;
+    allow8 = (p.allowed >> KRR_PREC_FP8) & 1;
+  } else if (p.mode == KRR_POLICY_FIXED) {
+    allow16 = p.fixed_prec == KRR_PREC_FP16;
+    allow8 = p.fixed_prec == KRR_PREC_FP8;
+  }
+  int mode = p.mode;
+  bool diag64 = p.diag_fp64 != 0;
+
+  krr_factorization F = new krr_factor_s();
+  F->K = K;
+  F->L = L;
+  F->info.nt = L.nt;
+  F->info.tile = L.nb;
+  F->info.norm_a = K->norm_a;
+  F->info.breakdown_col = -1;
+  FactorWork w;
+  krr_status st = KRR_SUCCESS;
+  uint8_t *dmap = nullptr;
+  const int64_t mapsz = L.nt <= 128 ? (int64_t)L.nt * L.ntiles() : 0;
+  do {
+    if (K->A) {  // consume the build's matrix in place
+      F->Lst = K->A;
+      K->A = nullptr;
+    } else {
+      if ((st = dalloc_t(ctx, &F->Lst, L.elems())) != KRR_SUCCESS) break;
+      launch_expand_tiles(K->D, K->etab, K->etab_len, K->lambda, L, F->Lst, s);
+    }
+    if ((st = dalloc_t(ctx, &F->Linv, (int64_t)L.nt * L.tile_elems())) != KRR_SUCCESS) break;
+    if ((st = factor_work_alloc(ctx, w, L, allow16 || p.allow_promotion, allow8)) != KRR_SUCCESS)
+      break;
+    if (mapsz && (st = dalloc_t(ctx, &dmap, mapsz)) != KRR_SUCCESS) break;
+    for (int attempt = 0;; ++attempt) {
+      if (attempt > 0) launch_expand_tiles(K->D, K->etab, K->etab_len, K->lambda, L, F->Lst, s);
+      launch_fill_i32(w.flag, 1, 0, s);
+      launch_fill_i32((int32_t *)w.counts, 6, 0, s);
+      if (dmap) launch_fill_u8(dmap, mapsz, 255, s);
+      UpdatePolicy up;
+      up.mode = mode;
+      up.allow16 = allow16;
+      up.allow8 = allow8;
+      up.high_panels = p.high_panels;
+      up.fixed_prec = p.fixed_prec;
+      up.thr = p.eps * K->norm_a / L.nt;
+      const bool need16 = allow16 != 0, need8 = allow8 != 0;
+      for (int k = 0; k < L.nt; ++k) {
+        float *Akk = F->Lst + TileLayout::tri(k, k) * L.tile_elems();
+        {
+          Stage t(ctx, KRR_STAGE_POTRF);
+          launch_potrf_tile(Akk, F->Linv + (int64_t)k * L.tile_elems(), k, L, diag64, w, s);
+        }
+        if (k + 1 < L.nt) {
+          {
+            Stage t(ctx, KRR_STAGE_TRSM);
+            launch_trsm_panel(F->Lst, F->Linv + (int64_t)k * L.tile_elems(), k, L, w, s);
+          }
+          {
+            Stage t(ctx, KRR_STAGE_CONVERT);
+            launch_convert_panel(F->Lst, k, L, w, need16, need8, s);
+          }
+          Stage t(ctx, KRR_STAGE_UPDATE);
+          launch_update(F->Lst, k, L, up, w, dmap, s);
+        }
+      }
+      if ((st = launch_ok()) != KRR_SUCCESS) break;
+      int32_t hflag = 0;
+      unsigned long long hc[3] = {0, 0, 0};
+      if (hipMemcpyAsync(&hflag, w.flag, 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+          hipMemcpyAsync(hc, w.counts, 24, hipMemcpyDeviceToHost, s) != hipSuccess ||
+          hipStreamSynchronize(s) != hipSuccess) {
+        st = KRR_ERROR_HIP;
+        break;
+      }
+      for (int q = 0; q < 3; ++q) F->info.updates[q] = (int64_t)hc[q];
+      if (hflag == 0) break;
+      F->info.breakdown_col = hflag - 1;
+      if (!p.allow_promotion) {
+        st = KRR_ERROR_NOT_POSITIVE_DEFINITE;
+        break;
+      }
+      // promotion: drop the lowest precision in use, then fall back to FP64 pivots
+      if (allow8) {
+        allow8 = 0;
+        if (mode == KRR_POLICY_FIXED) {
+          mode = KRR_POLICY_FIXED;
+          p.fixed_prec = KRR_PREC_FP16;
+          allow16 = 1;
+        }
+      } else if (allow16) {
+        allow16 = 0;
+        mode = KRR_POLICY_FP32;
+      } else if (!diag64) {
+        diag64 = true;
+      } else {
+        st = KRR_ERROR_NOT_POSITIVE_DEFINITE;
+        break;
+      }
+      F->info.promotions++;
+    }
+    if (st == KRR_SUCCESS && dmap) {
+      F->pmap.resize(mapsz);
+      if (hipMemcpy(F->pmap.data(), dmap, mapsz, hipMemcpyDeviceToHost) != hipSuccess)
+        st = KRR_ERROR_HIP;
+    }
+  } while (0);
+  if (dmap) dfree(ctx, dmap, mapsz);
+  factor_work_free(ctx, w, L);
+  if (st != KRR_SUCCESS) {
+    dfree(ctx, F->Lst, L.elems() * 4);
+    dfree(ctx, F->Linv, (size_t)L.nt * L.tile_elems() * 4);
+    delete F;
+    return st;
+  }
+  if (ctx->opts.verbose)
+    fprintf(stderr, "krr_factor: n=%lld nt=%d updates fp32=%lld fp16=%lld fp8=%lld promotions=%d\n",
+            (long long)L.n, L.nt, (long long)F->info.updates[0], (long long)F->info.updates[1],
+            (long long)F->info.updates[2], F->info.promotions);
+  *out = F;
+  return KRR_SUCCESS;
+}
+
+krr_status krr_factor_release(krr_factorization F) {
+  if (!F) return KRR_ERROR_INVALID_VALUE;
+  krr_context c = F->K->ctx;
+  (void)hipSetDevice(c->device);
+  (void)hipStreamSynchronize(c->stream);
+  dfree(c, F->Lst, F->L.elems() * 4);
+  dfree(c, F->Linv, (size_t)F->L.nt * F->L.tile_elems() * 4);
+  delete F;
+  return KRR_SUCCESS;
+}
+
+krr_status krr_factor_get_info(krr_factorization F, krr_factor_info *info) {
+  if (!F || !info) return KRR_ERROR_INVALID_VALUE;
+  *info = F->info;
+  return KRR_SUCCESS;
+}
+
+krr_status krr_factor_precision_map(krr_factorization F, uint8_t *host_dst, int64_t count) {
+  if (!F || !host_dst) return KRR_ERROR_INVALID_VALUE;
+  if (F->pmap.empty()) return KRR_ERROR_NOT_SUPPORTED;
+  if (count < (int64_t)F->pmap.size()) return KRR_ERROR_INVALID_VALUE;
+  memcpy(host_dst, F->pmap.data(), F->pmap.size());
+  return KRR_SUCCESS;
+}
+
+krr_status krr_solve(krr_context ctx, krr_factorization F, const double *Y, int64_t nrhs, int64_t ldy,
+                     double *X, int64_t ldx, const krr_refine_opts *opts, krr_solve_info *info) {
+  if (!ctx || !F || !Y || !X || nrhs <= 0 || nrhs > 4096) return KRR_ERROR_INVALID_VALUE;
+  krr_kernel K = F->K;
+  if (K->ctx != ctx) return KRR_ERROR_INVALID_VALUE;
+  const TileLayout &L = F->L;
+  if (ldy < L.n || ldx < L.n) return KRR_ERROR_INVALID_VALUE;
+  krr_refine_opts o{};
+  if (opts) {
+    o = *opts;
+  } else {
+    o.method = KRR_REFINE_IR;
+    o.max_iters = 30;
+    o.tol = 1e-6;
+  }
+  if (o.method < KRR_REFINE_NONE || o.method > KRR_REFINE_AUTO || o.max_iters < 0 || !(o.tol >= 0))
+    return KRR_ERROR_INVALID_VALUE;
+  if (o.method == KRR_REFINE_PCG) return KRR_ERROR_NOT_SUPPORTED;
+  HIPCHK(hipSetDevice(ctx->device));
+  hipStream_t s = ctx->stream;
+  const int r = (int)nrhs;
+  const int64_t cnt = L.np * r;
+  Scoped sc(ctx);
+  double *Yr, *Xr, *Rr, *cn;
+  float *Bf, *Zf, *Xf;
+  CHK(sc.alloc(&Yr, cnt));
+  CHK(sc.alloc(&Xr, cnt));
+  CHK(sc.alloc(&Rr, cnt));
+  CHK(sc.alloc(&cn, 2 * r));
+  CHK(sc.alloc(&Bf, cnt));
+  CHK(sc.alloc(&Zf, cnt));
+  CHK(sc.alloc(&Xf, cnt));
+  launch_colmajor_to_rows(Y, L.n, ldy, r, L.np, Yr, s);
+  launch_fill_f64(Xr, cnt, 0.0, s);
+  // unrefined solve in FP32
+  launch_f64_to_f32(Yr, cnt, Bf, s);
+  {
+    Stage t(ctx, KRR_STAGE_FWD);
+    launch_fwd_sweep(F->Lst, F->Linv, L, r, Bf, Zf, s);
+  }
+  {
+    Stage t(ctx, KRR_STAGE_BWD);
+    launch_bwd_sweep(F->Lst, F->Linv, L, r, Zf, Xf, s);
+  }
+  launch_axpy_f32_to_f64(Xf, cnt, 1.0, Xr, s);
+  CHK(launch_ok());
+  krr_solve_info inf{};
+  inf.first_bound = -1;
+  krr_status st = KRR_SUCCESS;
+  if (o.method != KRR_REFINE_NONE) {
+    std::vector<double> hn(2 * r), yn(r);
+    launch_col_norms(Yr, L.np, r, cn, s);
+    HIPCHK(hipMemcpyAsync(yn.data(), cn, r * 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    const double lam = K->lambda > 0 ? K->lambda : 1e-300;
+    int it = 0;
+    for (;; ++it) {
+      {
+        Stage t(ctx, KRR_STAGE_RESIDUAL);
+        launch_residual(K->D, K->etab, K->etab_len, K->lambda, L, r, Xr, Yr, Rr, s);
+      }
+      launch_col_norms(Rr, L.np, r, cn, s);
+      launch_col_norms(Xr, L.np, r, cn + r, s);
+      CHK(launch_ok());
+      HIPCHK(hipMemcpyAsync(hn.data(), cn, 2 * r * 8, hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      double bound = 0, berr = 0;
+      for (int c = 0; c < r; ++c) {
+        const double rn = sqrt(hn[c]), xn = sqrt(hn[r + c]), ynn = sqrt(yn[c]);
+        const double b = xn > 0 ? rn / (lam * xn) : (rn > 0 ? INFINITY : 0.0);
+        bound = std::max(bound, b);
+        const double den = K->norm_a * xn + ynn;
+        berr = std::max(berr, den > 0 ? rn / den : 0.0);
+      }
+      if (it == 0) inf.first_bound = bound;
+      inf.fwd_err_bound = bound;
+      inf.backward_err = berr;
+      if (bound <= o.tol) {
+        inf.converged = 1;
+        break;
+      }
+      if (it >= o.max_iters) break;
+      launch_f64_to_f32(Rr, cnt, Bf, s);
+      {
+        Stage t(ctx, KRR_STAGE_FWD);
+        launch_fwd_sweep(F->Lst, F->Linv, L, r, Bf, Zf, s);
+      }
+      {
+        Stage t(ctx, KRR_STAGE_BWD);
+        launch_bwd_sweep(F->Lst, F->Linv, L, r, Zf, Xf, s);
+      }
+      launch_axpy_f32_to_f64(Xf, cnt, 1.0, Xr, s);
+    }
+    inf.iters = it;
+    if (!inf.converged) st = KRR_ERROR_NOT_CONVERGED;
+  }
+  launch_rows_to_colmajor(Xr, L.n, r, X, ldx, s);
+  CHK(launch_ok());
+  HIPCHK(hipStreamSynchronize(s));
+  if (info) *info = inf;
+  if (ctx->opts.verbose)
+    fprintf(stderr, "krr_solve: iters=%d bound=%.3e first=%.3e\n", inf.iters, inf.fwd_err_bound,
+            inf.first_bound);
+  return st;
+}
+
+krr_status krr_predict(krr_context ctx, krr_kernel K, const int8_t *T, int64_t n_test, int64_t ldt,
+                       const double *X, int64_t nrhs, int64_t ldx, double *P, int64_t ldp) {
+  if (!ctx || !K || !T || !X || !P || n_test <= 0 || nrhs <= 0 || nrhs > 4096)
+    return KRR_ERROR_INVALID_VALUE;
+  if (K->ctx != ctx) return KRR_ERROR_INVALID_VALUE;
+  if (ldt < K->m || (ldt % 16) != 0 || !aligned16(T) || ldx < K->n || ldp < n_test)
+    return KRR_ERROR_INVALID_VALUE;
+  HIPCHK(hipSetDevice(ctx->device));
+  hipStream_t s = ctx->stream;
+  const TileLayout &L = K->L;
+  const int r = (int)nrhs;
+  // test rows per pass, so the int32 cross-distance block stays within ~2 GiB
+  int64_t chunk = std::max<int64_t>(256, ((int64_t)1 << 29) / L.np / 256 * 256);
+  chunk = std::min<int64_t>(chunk, (n_test + 255) / 256 * 256);
+  Scoped sc(ctx);
+  int32_t *nrm_t, *flag, *Dt;
+  double *Xr;
+  CHK(sc.alloc(&nrm_t, (n_test + 255) / 256 * 256));
+  CHK(sc.alloc(&flag, 1));
+  CHK(sc.alloc(&Dt, chunk * L.np));
+  CHK(sc.alloc(&Xr, L.np * r));
+  launch_fill_i32(flag, 1, 0, s);
+  launch_row_norms(T, n_test, n_test, K->m, ldt, nrm_t, flag, s);
+  int32_t hflag = 0;
+  HIPCHK(hipMemcpyAsync(&hflag, flag, 4, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  CHK(launch_ok());
+  if (hflag) return KRR_ERROR_BAD_GENOTYPE;
+  launch_colmajor_to_rows(X, K->n, ldx, r, L.np, Xr, s);
+  for (int64_t r0 = 0; r0 < n_test; r0 += chunk) {
+    const int64_t rows = std::min(chunk, n_test - r0);
+    {
+      Stage t(ctx, KRR_STAGE_CROSS_GRAM);
+      launch_cross_gram(T + r0 * ldt, rows, nrm_t + r0, K->G, K->n, K->m, ldt, K->ldg, K->nrm,
+                        L.np, Dt, L.np, s);
+    }
+    Stage t(ctx, KRR_STAGE_PREDICT);
+    launch_predict_apply(Dt, rows, L.np, L.np, K->etab, K->etab_len, Xr, r, P + r0, ldp, s);
+  }
+  CHK(launch_ok());
+  HIPCHK(hipStreamSynchronize(s));
+  return KRR_SUCCESS;
+}
+
+krr_status krr_kernel_copy_distances(krr_kernel K, int64_t i0, int64_t j0, int64_t rows,
+                                     int64_t cols, int32_t *dst, int64_t ld) {
+  if (!K || !dst || rows <= 0 || cols <= 0 || ld < cols || i0 < 0 || j0 < 0 ||
+      i0 + rows > K->n || j0 + cols > K->n)
+    return KRR_ERROR_INVALID_VALUE;
+  HIPCHK(hipSetDevice(K->ctx->device));
+  launch_copy_tiles_i32(K->D, K->L, i0, j0, rows, cols, dst, ld, K->ctx->stream);
+  CHK(launch_ok());
+  HIPCHK(hipStreamSynchronize(K->ctx->stream));
+  return KRR_SUCCESS;
+}
+
+krr_status krr_kernel_copy_matrix(krr_kernel K, int64_t i0, int64_t j0, int64_t rows,
+                                  int64_t cols, float *dst, int64_t ld) {
+  if (!K || !dst || rows <= 0 || cols <= 0 || ld < cols || i0 < 0 || j0 < 0 ||
+      i0 + rows > K->n || j0 + cols > K->n || !K->A)
+    return KRR_ERROR_INVALID_VALUE;
+  HIPCHK(hipSetDevice(K->ctx->device));
+  launch_copy_tiles_f32(K->A, K->L, i0, j0, rows, cols, false, dst, ld, K->ctx->stream);
+  CHK(launch_ok());
+  HIPCHK(hipStreamSynchronize(K->ctx->stream));
+  return KRR_SUCCESS;
+}
+
+krr_status krr_factor_copy_l(krr_factorization F, int64_t i0, int64_t j0, int64_t rows, int64_t cols,
+                             float *dst, int64_t ld) {
+  if (!F || !dst || rows <= 0 || cols <= 0 || ld < cols || i0 < 0 || j0 < 0 ||
+      i0 + rows > F->L.n || j0 + cols > F->L.n)
+    return KRR_ERROR_INVALID_VALUE;
+  krr_context c = F->K->ctx;
+  HIPCHK(hipSetDevice(c->device));
+  launch_copy_tiles_f32(F->Lst, F->L, i0, j0, rows, cols, true, dst, ld, c->stream);
+  CHK(launch_ok());
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return KRR_SUCCESS;
+}
+
+}  // extern "C"

@@ -1,0 +1,273 @@
+// Build phase: squared genotype distances through an INT8 MFMA Gram and the
+// Gaussian kernel, per tile (arXiv 2409.01712, Algorithm 2 with the
+// Gaussian kernel of Algorithm 5; "Engaging INT8 Tensor Cores for Distance
+// Calculations" and "TC-based Distance Computations").
+//
+// d_ij = n_i + n_j - 2 <g_i, g_j> with the per-patient squared norms n_i kept
+// as one vector (the paper's folded D), the Gram term from INT8 MFMA with
+// int32 accumulation (exact: every partial sum is at most 4m), and each entry
+// exponentiated before the tile leaves registers.  Only tiles I >= J of the
+// symmetric matrix are computed.
+#include "common.h"
+#include "internal.h"
+
+namespace krr {
+
+// exp(-gamma * d) for every integer distance d in [0, len): the FP64 kernel
+// value of any entry is then a table lookup, bit-identical to evaluating exp.
+__global__ void k_exp_table(double *tab, int64_t len, double gamma) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < len) tab[i] = exp(-gamma * (double)i);
+}
+
+void launch_exp_table(double *tab, int64_t len, double gamma, hipStream_t s) {
+  const int64_t blocks = (len + 255) / 256;
+  hipLaunchKernelGGL(k_exp_table, dim3((unsigned)blocks), dim3(256), 0, s, tab, len, gamma);
+}
+
+// Row norms n_i = sum_k g_ik^2 (one workgroup per row, 16-byte loads, dot4),
+// and the genotype check: any byte outside {0, 1, 2} sets *flag.  Rows
+// n .. rows_padded-1 are padding and get n_i = 0.
+__global__ __launch_bounds__(256) void k_row_norms(const int8_t *__restrict__ G, int64_t n,
+                                                   int64_t m, int64_t ldg, int32_t *nrm,
+                                                   int32_t *flag) {
+  __shared__ int sh[4];
+  const int64_t row = blockIdx.x;
+  if (row >= n) {
+    if (threadIdx.x == 0) nrm[row] = 0;
+    return;
+  }
+  const uint8_t *p = (const uint8_t *)G + row * ldg;
+  uint32_t acc = 0, bad = 0;
+  for (int64_t kb = (int64_t)threadIdx.x * 16; kb < m; kb += 256 * 16) {
+    v4i v = *(const v4i *)(p + kb);
+    const int64_t keep = m - kb;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      uint32_t w = (uint32_t)v[q];
+      const int64_t valid = keep - 4 * q;
+      if (valid <= 0) w = 0;
+      else if (valid < 4) w &= (1u << (8 * valid)) - 1u;
+      bad |= (w & 0xFCFCFCFCu) | ((w & (w >> 1)) & 0x01010101u);
+      acc = __builtin_amdgcn_udot4(w, w, acc, false);
+    }
+  }
+  int s = (int)acc;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+  if (bad) atomicOr(flag, 1);
+  __syncthreads();
+  if (threadIdx.x == 0) nrm[row] = sh[0] + sh[1] + sh[2] + sh[3];
+}
+
+void launch_row_norms(const int8_t *G, int64_t n, int64_t rows_padded, int64_t m, int64_t ldg,
+                      int32_t *nrm, int32_t *flag, hipStream_t s) {
+  hipLaunchKernelGGL(k_row_norms, dim3((unsigned)rows_padded), dim3(256), 0, s, G, n, m, ldg,
+                     nrm, flag);
+}
+
+// Symmetric Gram over the lower tile triangle.  Block (BM x BN) = one
+// sub-block of tile (I, J); SB x SB sub-blocks per tile.  Epilogue per
+// entry: d = n_i + n_j - 2 S (int32), A = exp(-gamma d) in FP64 rounded to
+// FP32 (table lookup), 1 + lambda on the diagonal, identity on padding; plus
+// the sub-block's FP64 sum of squares for the tile norms.
+template <int BM, int BN>
+__global__ __launch_bounds__(256) void k_gram_tiles(const int8_t *__restrict__ G, int64_t n,
+                                                    int64_t m, int64_t ldg,
+                                                    const int32_t *__restrict__ nrm,
+                                                    const double *__restrict__ etab,
+                                                    int64_t etab_len, double lambda, int nb,
+                                                    int SB, int32_t *__restrict__ D,
+                                                    float *__restrict__ A, double *part) {
+  typedef GemmShape<BM, BN> S;
+  __shared__ __attribute__((aligned(16))) uint8_t lds[S::LDS_BYTES];
+  __shared__ double shd[4];
+  const int64_t bid = xcd_remap(blockIdx.x, gridDim.x);
+  const int nsub = SB * SB;
+  const int sub = (int)(bid % nsub);
+  const int64_t t = bid / nsub;
+  int I, J;
+  tri_decode(t, I, J);
+  const int si = sub / SB, sj = sub % SB;
+  const int64_t row0 = (int64_t)I * nb + si * BM, col0 = (int64_t)J * nb + sj * BN;
+  const int arows = (int)max((int64_t)0, min((int64_t)BM, n - row0));
+  const int brows = (int)max((int64_t)0, min((int64_t)BN, n - col0));
+
+  OpI8::acc_t acc[S::WTM][S::WTN];
+  zero_acc(acc);
+  if (arows > 0 && brows > 0)
+    gemm_nt_core<OpI8, BM, BN>((const uint8_t *)G + row0 * ldg, ldg, arows,
+                               (const uint8_t *)G + col0 * ldg, ldg, brows, m, acc, lds);
+
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int64_t tbase = t * (int64_t)nb * nb;
+  double ss = 0.0;
+#pragma unroll
+  for (int tm = 0; tm < S::WTM; ++tm)
+#pragma unroll
+    for (int tn = 0; tn < S::WTN; ++tn)
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        const int r = wm * (BM / 2) + tm * 32 + mfma_row(i, lane);
+        const int c = wn * (BN / 2) + tn * 32 + mfma_col(lane);
+        const int64_t gi = row0 + r, gj = col0 + c;
+        int32_t d;
+        float a;
+        if (gi < n && gj < n) {
+          d = nrm[gi] + nrm[gj] - 2 * acc[tm][tn][i];
+          a = (gi == gj) ? (float)(1.0 + lambda) : (float)etab[min((int64_t)max(d, 0), etab_len - 1)];
+        } else {
+          d = 0;
+          a = (gi == gj) ? 1.0f : 0.0f;
+        }
+        const int64_t off = tbase + (int64_t)(si * BM + r) * nb + sj * BN + c;
+        D[off] = d;
+        A[off] = a;
+        ss += (double)a * (double)a;
+      }
+  ss = block_sum_256(ss, shd);
+  if (threadIdx.x == 0) part[bid] = ss;
+}
+
+void launch_gram_tiles(const int8_t *G, int64_t m, int64_t ldg, const int32_t *nrm,
+                       const double *etab, int64_t etab_len, double lambda, const TileLayout &L,
+                       int32_t *D, float *A, double *tnorm_part, hipStream_t s) {
+  constexpr int BM = 256, BN = 256;
+  const int SB = L.nb / BM;
+  const int64_t blocks = L.ntiles() * SB * SB;
+  hipLaunchKernelGGL((k_gram_tiles<BM, BN>), dim3((unsigned)blocks), dim3(256), 0, s, G, L.n, m,
+                     ldg, nrm, etab, etab_len, lambda, L.nb, SB, D, A, tnorm_part);
+}
+
+// Tile Frobenius norms from the per-sub-block partial sums, in fixed order.
+__global__ void k_tile_norms(const double *part, int parts, int64_t ntiles, double *tnorm) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= ntiles) return;
+  double s = 0.0;
+  for (int q = 0; q < parts; ++q) s += part[t * parts + q];
+  tnorm[t] = sqrt(s);
+}
+
+void launch_tile_norms(const double *part, int parts, int64_t ntiles, double *tnorm,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(k_tile_norms, dim3((unsigned)((ntiles + 255) / 256)), dim3(256), 0, s, part,
+                     parts, ntiles, tnorm);
+}
+
+// Re-expand K + lambda*I from the stored distances (same values the Gram
+// epilogue wrote), for a second factorization of one kernel.
+__global__ void k_expand_tiles(const int32_t *__restrict__ D, const double *__restrict__ etab,
+                               int64_t etab_len, double lambda, int64_t n, int nb, int64_t total,
+                               float *__restrict__ A) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= total) return;
+  const int64_t te = (int64_t)nb * nb;
+  const int64_t t = e / te, w = e % te;
+  int I, J;
+  tri_decode(t, I, J);
+  const int64_t gi = (int64_t)I * nb + w / nb, gj = (int64_t)J * nb + w % nb;
+  float a;
+  if (gi < n && gj < n)
+    a = (gi == gj) ? (float)(1.0 + lambda)
+                   : (float)etab[min((int64_t)max(D[e], 0), etab_len - 1)];
+  else
+    a = (gi == gj) ? 1.0f : 0.0f;
+  A[e] = a;
+}
+
+void launch_expand_tiles(const int32_t *D, const double *etab, int64_t etab_len, double lambda,
+                         const TileLayout &L, float *A, hipStream_t s) {
+  const int64_t total = L.elems();
+  hipLaunchKernelGGL(k_expand_tiles, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, D,
+                     etab, etab_len, lambda, L.n, L.nb, total, A);
+}
+
+// Cross distances for Predict (Algorithm 4's Build(gamma, T, G)):
+// Dt[i, j] = n^T_i + n^G_j - 2 <t_i, g_j> for i < rows, j < cols_padded
+// (0 for the padding columns j >= n).  Row-major with leading dimension ldd.
+template <int BM, int BN>
+__global__ __launch_bounds__(256) void k_cross_gram(const int8_t *__restrict__ T, int64_t rows,
+                                                    const int32_t *__restrict__ nrm_t,
+                                                    const int8_t *__restrict__ G, int64_t n,
+                                                    int64_t m, int64_t ldt, int64_t ldg,
+                                                    const int32_t *__restrict__ nrm_g,
+                                                    int64_t cols, int64_t nbc,
+                                                    int32_t *__restrict__ Dt, int64_t ldd) {
+  typedef GemmShape<BM, BN> S;
+  __shared__ __attribute__((aligned(16))) uint8_t lds[S::LDS_BYTES];
+  const int64_t bid = xcd_remap(blockIdx.x, gridDim.x);
+  const int64_t bi = bid / nbc, bj = bid % nbc;
+  const int64_t row0 = bi * BM, col0 = bj * BN;
+  const int arows = (int)max((int64_t)0, min((int64_t)BM, rows - row0));
+  const int brows = (int)max((int64_t)0, min((int64_t)BN, n - col0));
+  OpI8::acc_t acc[S::WTM][S::WTN];
+  zero_acc(acc);
+  if (arows > 0 && brows > 0)
+    gemm_nt_core<OpI8, BM, BN>((const uint8_t *)T + row0 * ldt, ldt, arows,
+                               (const uint8_t *)G + col0 * ldg, ldg, brows, m, acc, lds);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+#pragma unroll
+  for (int tm = 0; tm < S::WTM; ++tm)
+#pragma unroll
+    for (int tn = 0; tn < S::WTN; ++tn)
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        const int64_t gi = row0 + wm * (BM / 2) + tm * 32 + mfma_row(i, lane);
+        const int64_t gj = col0 + wn * (BN / 2) + tn * 32 + mfma_col(lane);
+        if (gi < rows && gj < cols)
+          Dt[gi * ldd + gj] = (gj < n) ? nrm_t[gi] + nrm_g[gj] - 2 * acc[tm][tn][i] : 0;
+      }
+}
+
+void launch_cross_gram(const int8_t *T, int64_t nt_rows, const int32_t *nrm_t, const int8_t *G,
+                       int64_t n, int64_t m, int64_t ldt, int64_t ldg, const int32_t *nrm_g,
+                       int64_t cols_padded, int32_t *Dt, int64_t ldd, hipStream_t s) {
+  constexpr int BM = 256, BN = 256;
+  const int64_t nbr = (nt_rows + BM - 1) / BM, nbc = (cols_padded + BN - 1) / BN;
+  hipLaunchKernelGGL((k_cross_gram<BM, BN>), dim3((unsigned)(nbr * nbc)), dim3(256), 0, s, T,
+                     nt_rows, nrm_t, G, n, m, ldt, ldg, nrm_g, cols_padded, nbc, Dt, ldd);
+}
+
+// Diagnostics: gather a rectangular block of a tile-packed symmetric matrix.
+template <typename T>
+__global__ void k_copy_tiles(const T *__restrict__ src, int nb, int64_t i0, int64_t j0,
+                             int64_t rows, int64_t cols, int lower_only, T *__restrict__ dst,
+                             int64_t ld) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= rows * cols) return;
+  const int64_t i = i0 + e / cols, j = j0 + e % cols;
+  T v;
+  if (lower_only && j > i) {
+    v = (T)0;
+  } else {
+    const int64_t a = i >= j ? i : j, b = i >= j ? j : i;  // symmetric: read lower
+    const int64_t I = a / nb, J = b / nb;
+    int64_t r = a % nb, c = b % nb;
+    if (I == J && !lower_only) {  // diagonal tiles are stored in full
+      r = i % nb;
+      c = j % nb;
+    }
+    v = src[(I * (I + 1) / 2 + J) * (int64_t)nb * nb + r * nb + c];
+  }
+  dst[(e / cols) * ld + e % cols] = v;
+}
+
+void launch_copy_tiles_i32(const int32_t *D, const TileLayout &L, int64_t i0, int64_t j0,
+                           int64_t rows, int64_t cols, int32_t *dst, int64_t ld, hipStream_t s) {
+  const int64_t tot = rows * cols;
+  hipLaunchKernelGGL(k_copy_tiles<int32_t>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s,
+                     D, L.nb, i0, j0, rows, cols, 0, dst, ld);
+}
+
+void launch_copy_tiles_f32(const float *A, const TileLayout &L, int64_t i0, int64_t j0,
+                           int64_t rows, int64_t cols, bool lower_only, float *dst, int64_t ld,
+                           hipStream_t s) {
+  const int64_t tot = rows * cols;
+  hipLaunchKernelGGL(k_copy_tiles<float>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, A,
+                     L.nb, i0, j0, rows, cols, lower_only ? 1 : 0, dst, ld);
+}
+
+}  // namespace krr

@@ -1,0 +1,98 @@
+// Host-side declarations shared by the library's translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/krr.h"
+
+namespace krr {
+
+// Lower-triangle tile layout of an np x np matrix (np = nt * nb).
+struct TileLayout {
+  int nb = 512;
+  int nt = 0;
+  int64_t n = 0;   // logical size
+  int64_t np = 0;  // padded size
+  int64_t ntiles() const { return (int64_t)nt * (nt + 1) / 2; }
+  int64_t tile_elems() const { return (int64_t)nb * nb; }
+  int64_t elems() const { return ntiles() * tile_elems(); }
+  static int64_t tri(int64_t I, int64_t J) { return I * (I + 1) / 2 + J; }
+};
+
+// ---- build.hip ----
+void launch_exp_table(double *tab, int64_t len, double gamma, hipStream_t s);
+void launch_row_norms(const int8_t *G, int64_t n, int64_t rows_padded, int64_t m, int64_t ldg,
+                      int32_t *nrm, int32_t *flag, hipStream_t s);
+void launch_gram_tiles(const int8_t *G, int64_t m, int64_t ldg, const int32_t *nrm,
+                       const double *etab, int64_t etab_len, double lambda, const TileLayout &L,
+                       int32_t *D, float *A, double *tnorm_part, hipStream_t s);
+void launch_tile_norms(const double *part, int parts, int64_t ntiles, double *tnorm, hipStream_t s);
+void launch_expand_tiles(const int32_t *D, const double *etab, int64_t etab_len, double lambda,
+                         const TileLayout &L, float *A, hipStream_t s);
+void launch_cross_gram(const int8_t *T, int64_t nt_rows, const int32_t *nrm_t, const int8_t *G,
+                       int64_t n, int64_t m, int64_t ldt, int64_t ldg, const int32_t *nrm_g,
+                       int64_t cols_padded, int32_t *Dt, int64_t ldd, hipStream_t s);
+void launch_copy_tiles_i32(const int32_t *D, const TileLayout &L, int64_t i0, int64_t j0,
+                           int64_t rows, int64_t cols, int32_t *dst, int64_t ld, hipStream_t s);
+void launch_copy_tiles_f32(const float *A, const TileLayout &L, int64_t i0, int64_t j0,
+                           int64_t rows, int64_t cols, bool lower_only, float *dst, int64_t ld,
+                           hipStream_t s);
+
+// ---- factor.hip ----
+struct UpdatePolicy {
+  int mode;          // KRR_POLICY_*
+  int allow16, allow8;
+  int high_panels;
+  int fixed_prec;
+  double thr;        // eps * ||A||_F / NT
+};
+// Workspace for the factorization, sized for nt tiles of nb.
+struct FactorWork {
+  double *W64 = nullptr;     // nb x nb FP64 (or FP32) diagonal workspace
+  double *Winv64 = nullptr;  // nb x nb
+  double *Dinv64 = nullptr;  // (nb/64) blocks of 64 x 64
+  float *P32 = nullptr;      // (nt-1) panel tiles FP32
+  _Float16 *P16 = nullptr;   // (nt-1) panel tiles FP16
+  uint8_t *P8 = nullptr;     // (nt-1) panel tiles FP8
+  double *pnorm_part = nullptr;  // (nt-1) * parts
+  float *pmax_part = nullptr;    // (nt-1) * parts
+  float *pnorm = nullptr;        // (nt-1)
+  float *pscale16 = nullptr;     // (nt-1)
+  float *pscale8 = nullptr;      // (nt-1)
+  int32_t *flag = nullptr;       // breakdown column + 1 (0 = none)
+  unsigned long long *counts = nullptr;  // [3] updates per precision
+};
+void launch_potrf_tile(float *Akk, float *Linv, int k, const TileLayout &L, bool fp64,
+                       FactorWork &w, hipStream_t s);
+void launch_trsm_panel(const float *Astore, const float *Linv, int k, const TileLayout &L,
+                       FactorWork &w, hipStream_t s);
+void launch_convert_panel(float *Astore, int k, const TileLayout &L, FactorWork &w, bool need16,
+                          bool need8, hipStream_t s);
+void launch_update(float *Astore, int k, const TileLayout &L, const UpdatePolicy &pol,
+                   FactorWork &w, uint8_t *pmap, hipStream_t s);
+
+// ---- solve.hip ----
+// Internal right-hand sides are row-major np x r.
+void launch_fwd_sweep(const float *Astore, const float *Linv, const TileLayout &L, int r,
+                      float *B, float *Z, hipStream_t s);
+void launch_bwd_sweep(const float *Astore, const float *Linv, const TileLayout &L, int r,
+                      float *Z, float *X, hipStream_t s);
+void launch_residual(const int32_t *D, const double *etab, int64_t etab_len, double lambda,
+                     const TileLayout &L, int r, const double *X, const double *Y, double *R,
+                     hipStream_t s);
+void launch_colmajor_to_rows(const double *src, int64_t n, int64_t ld, int r, int64_t np,
+                             double *dst, hipStream_t s);
+void launch_rows_to_colmajor(const double *src, int64_t n, int r, double *dst, int64_t ld,
+                             hipStream_t s);
+void launch_f64_to_f32(const double *src, int64_t count, float *dst, hipStream_t s);
+void launch_axpy_f32_to_f64(const float *src, int64_t count, double alpha, double *dst,
+                            hipStream_t s);
+void launch_col_norms(const double *A, int64_t n, int r, double *out, hipStream_t s);
+void launch_predict_apply(const int32_t *Dt, int64_t rows, int64_t cols, int64_t ldd,
+                          const double *etab, int64_t etab_len, const double *X, int r, double *P,
+                          int64_t ldp, hipStream_t s);
+void launch_fill_f64(double *p, int64_t count, double v, hipStream_t s);
+void launch_fill_i32(int32_t *p, int64_t count, int32_t v, hipStream_t s);
+void launch_fill_u8(uint8_t *p, int64_t count, uint8_t v, hipStream_t s);
+
+}  // namespace krr

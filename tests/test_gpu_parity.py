@@ -1,0 +1,283 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 CPU oracle.
+
+Integer work (squared distances) must match bit for bit.  Floating-point
+results are held to the tolerances of the benchmark target: 1e-5 relative
+error of the weights X and predictions P per phenotype column, after FP64
+refinement; the FP32 kernel matrix within 1 FP32 ulp of the FP64 value; the
+FP32 Cholesky factor within FP32 backward error.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_2409_01712_amd as krr  # noqa: E402
+
+DEV = "cuda:0"
+TOL = 1e-5
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = krr.krr_create(0)
+    yield c
+    c.close()
+
+
+def _gen(n, m, seed=12345, lo=0.05, hi=0.5):
+    p = synth.maf_uniform(m, lo, hi, seed)
+    return synth.genotypes(n, m, p, seed)
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def _colrel(A, B):
+    """max over columns of max|A - B| / max|B|."""
+    A = np.asarray(A).reshape(len(A), -1)
+    B = np.asarray(B).reshape(len(B), -1)
+    return max(np.max(np.abs(A[:, c] - B[:, c])) / np.max(np.abs(B[:, c])) for c in range(B.shape[1]))
+
+
+# --- Build: distances and kernel matrix ---------------------------------------------------
+
+@pytest.mark.parametrize("n,m", [(1, 1), (2, 16), (255, 63), (257, 65), (513, 4097), (300, 16),
+                                 (1100, 333)])
+def test_distances_bit_exact_ragged(ctx, n, m):
+    G = _gen(n, m, seed=n * 7 + m)
+    K = krr.krr_build_kernel(ctx, _dev(G), 1.0 / m, 0.1)
+    D = krr.krr_kernel_copy_distances(K, 0, 0, n, n).cpu().numpy()
+    assert np.array_equal(D.astype(np.int64), oracle.sqdist(G))
+
+
+def test_distances_bit_exact_small_config(ctx):
+    w = synth.WORKLOADS["small"]
+    G = w.genotypes()
+    K = krr.krr_build_kernel(ctx, _dev(G), w.gamma, w.lam)
+    D = krr.krr_kernel_copy_distances(K, 0, 0, w.n, w.n).cpu().numpy()
+    assert np.array_equal(D.astype(np.int64), oracle.sqdist(G))
+
+
+def test_distances_extreme_values(ctx):
+    """All-2 versus all-0 rows give the largest distance 4m (int32 accumulator range)."""
+    m = 70000
+    G = np.zeros((6, m), np.int8)
+    G[0] = 2
+    G[2, ::2] = 2
+    G[3] = 1
+    G[4] = 2
+    K = krr.krr_build_kernel(ctx, _dev(G), 1.0 / m, 0.1)
+    D = krr.krr_kernel_copy_distances(K, 0, 0, 6, 6).cpu().numpy()
+    want = oracle.sqdist(G)
+    assert want[0, 1] == 4 * m
+    assert np.array_equal(D.astype(np.int64), want)
+
+
+def test_kernel_matrix_fp32_within_one_ulp(ctx):
+    w = synth.WORKLOADS["small"]
+    n = 1300
+    G = w.genotypes(rows=n)
+    K = krr.krr_build_kernel(ctx, _dev(G), w.gamma, w.lam)
+    A = krr.krr_kernel_copy_matrix(K, 0, 0, n, n).cpu().numpy()
+    Ko = oracle.build_kernel(G, w.gamma)
+    Ko[np.diag_indices_from(Ko)] += w.lam
+    want = Ko.astype(np.float32)
+    ulps = np.abs(A.view(np.int32).astype(np.int64) - want.view(np.int32).astype(np.int64))
+    assert ulps.max() <= 1
+    assert np.array_equal(A, A.T)
+    assert np.all(np.diag(A) == np.float32(1.0 + w.lam))
+
+
+def test_tile_norms(ctx):
+    w = synth.WORKLOADS["small"]
+    n = 1100
+    G = w.genotypes(rows=n)
+    c2 = krr.krr_create(0, tile=256)
+    K = krr.krr_build_kernel(c2, _dev(G), w.gamma, w.lam)
+    A = krr.krr_kernel_copy_matrix(K, 0, 0, n, n).cpu().numpy().astype(np.float64)
+    nb, nt = 256, (n + 255) // 256
+    norms = krr.krr_kernel_tile_norms(K, nt)
+    for I in range(nt):
+        for J in range(I + 1):
+            blk = A[I * nb:(I + 1) * nb, J * nb:(J + 1) * nb]
+            want = np.sqrt((blk ** 2).sum() + (nb - blk.shape[0] if I == J else 0))
+            assert abs(norms[I * (I + 1) // 2 + J] - want) <= 1e-12 * want
+
+
+# --- Factor -------------------------------------------------------------------------------
+
+def test_factor_fp32_backward_error_and_oracle(ctx):
+    w = synth.WORKLOADS["small"]
+    n = 1000
+    G = w.genotypes(rows=n)
+    K = krr.krr_build_kernel(ctx, _dev(G), w.gamma, w.lam)
+    F = krr.krr_factor(ctx, K, krr.plain_fp32_policy())
+    L = krr.krr_factor_copy_l(F, 0, 0, n, n).cpu().numpy().astype(np.float64)
+    A = oracle.build_kernel(G, w.gamma)
+    A[np.diag_indices_from(A)] += w.lam
+    assert np.linalg.norm(A - L @ L.T) / np.linalg.norm(A) <= 1e-5
+    Lo = oracle.cholesky(A)
+    assert np.max(np.abs(L - Lo)) <= 1e-4
+    assert np.all(np.triu(L, 1) == 0)
+
+
+@pytest.mark.parametrize("diag64", [0, 1])
+def test_factor_closed_form(ctx, diag64):
+    """Rows 2 e_i give A = b I + c 11^T (c = exp(-8 gamma), b = 1 - c + lambda), whose
+    Cholesky factor has a closed form (pinned in the oracle tests)."""
+    n, m, lam = 1200, 1280, 0.1
+    G = np.zeros((n, m), np.int8)
+    G[np.arange(n), np.arange(n)] = 2
+    gamma = 1.0 / 64
+    K = krr.krr_build_kernel(ctx, _dev(G), gamma, lam)
+    pol = krr.plain_fp32_policy()
+    pol.diag_fp64 = diag64
+    F = krr.krr_factor(ctx, K, pol)
+    L = krr.krr_factor_copy_l(F, 0, 0, n, n).cpu().numpy().astype(np.float64)
+    c = np.exp(-8 * gamma)
+    b = 1 - c + lam
+    s = b + c * np.arange(n + 1)
+    d = np.sqrt(b * s[1:] / s[:-1])
+    col = c * np.sqrt(b) / np.sqrt(s[:-1] * s[1:])
+    assert np.max(np.abs(np.diag(L) - d) / d) <= 2e-5
+    low = np.tril(L, -1)
+    want = np.tril(np.ones((n, n)), -1) * col[None, :]
+    assert np.max(np.abs(low - want)) <= 2e-5 * np.max(col)
+
+
+def test_factor_deterministic_precision_map(ctx):
+    w = synth.WORKLOADS["small"]
+    G = w.genotypes()
+    maps = []
+    for _ in range(2):
+        K = krr.krr_build_kernel(ctx, _dev(G), w.gamma, w.lam)
+        F = krr.krr_factor(ctx, K, krr.Policy(eps=1.0))
+        maps.append(krr.krr_factor_precision_map(F))
+    assert np.array_equal(maps[0], maps[1])
+    nt = maps[0].shape[0]
+    # panel 0 (high panel) and every diagonal update are FP32
+    tri = lambda i, j: i * (i + 1) // 2 + j
+    for i in range(1, nt):
+        assert maps[0][0, tri(i, i)] == krr.KRR_PREC_FP32
+        for j in range(1, i + 1):
+            assert maps[0][0, tri(i, j)] == krr.KRR_PREC_FP32
+
+
+# --- Solve --------------------------------------------------------------------------------
+
+POLICIES = {
+    "plain_fp32_refined": krr.plain_fp32_policy(),
+    "adaptive": krr.Policy(),
+    "fixed_fp16": krr.Policy(mode=krr.KRR_POLICY_FIXED, fixed_prec=krr.KRR_PREC_FP16),
+    "fixed_fp8": krr.Policy(mode=krr.KRR_POLICY_FIXED, fixed_prec=krr.KRR_PREC_FP8),
+}
+
+
+@pytest.mark.parametrize("name", list(POLICIES))
+def test_solve_parity_small_config(ctx, name):
+    w = synth.WORKLOADS["small"]
+    G = w.genotypes()
+    Y = w.phenotypes(G)
+    Wo = oracle.fit(G, Y, w.gamma, w.lam)
+    K = krr.krr_build_kernel(ctx, _dev(G), w.gamma, w.lam)
+    F = krr.krr_factor(ctx, K, POLICIES[name])
+    X, info, st = krr.krr_solve(ctx, F, _dev(Y), krr.Refine(tol=1e-8))
+    assert info.converged == 1
+    assert _colrel(X.cpu().numpy(), Wo) <= TOL
+
+
+def test_solve_parity_ragged_many_rhs(ctx):
+    n, m, r = 1500, 2000, 40
+    G = _gen(n, m, seed=99)
+    Y = synth.phenotypes(G, r, n_pairs=10, n_add=5, seed=3, h2=0.5)
+    gamma, lam = 0.5 / m, 1e-2
+    Wo = oracle.fit(G, Y, gamma, lam)
+    c2 = krr.krr_create(0, tile=256)
+    K = krr.krr_build_kernel(c2, _dev(G), gamma, lam)
+    F = krr.krr_factor(c2, K)
+    X, info, st = krr.krr_solve(c2, F, _dev(Y), krr.Refine(tol=1e-8))
+    assert info.converged == 1
+    assert _colrel(X.cpu().numpy(), Wo) <= TOL
+
+
+def test_refactor_from_distances(ctx):
+    """A second factorization of one kernel re-expands K from the stored distances."""
+    w = synth.WORKLOADS["small"]
+    n = 900
+    G = w.genotypes(rows=n)
+    Y = w.phenotypes(G)
+    K = krr.krr_build_kernel(ctx, _dev(G), w.gamma, w.lam)
+    X1 = krr.krr_solve(ctx, krr.krr_factor(ctx, K, krr.plain_fp32_policy()), _dev(Y))[0]
+    X2 = krr.krr_solve(ctx, krr.krr_factor(ctx, K, krr.plain_fp32_policy()), _dev(Y))[0]
+    assert torch.equal(X1, X2)
+
+
+# --- Predict ------------------------------------------------------------------------------
+
+def test_predict_parity(ctx):
+    n, nt_, m, r = 1500, 333, 3000, 3
+    Gall = _gen(n + nt_, m, seed=7)
+    G, T = Gall[:n], Gall[n:]
+    Y = synth.phenotypes(G, r, n_pairs=10, n_add=5, seed=5, h2=0.5)
+    gamma, lam = 1.0 / m, 0.1
+    Wo = oracle.fit(G, Y, gamma, lam)
+    Po = oracle.predict(G, T, Wo, gamma)
+    K = krr.krr_build_kernel(ctx, _dev(G), gamma, lam)
+    F = krr.krr_factor(ctx, K)
+    X, info, st = krr.krr_solve(ctx, F, _dev(Y), krr.Refine(tol=1e-8))
+    P = krr.krr_predict(ctx, K, _dev(T), X).cpu().numpy()
+    assert _colrel(P, Po) <= TOL
+    # predicting with the oracle's weights isolates the predict step
+    P2 = krr.krr_predict(ctx, K, _dev(T), _dev(Wo)).cpu().numpy()
+    assert _colrel(P2, Po) <= 1e-12
+
+
+# --- error paths ---------------------------------------------------------------------------
+
+def test_bad_genotype(ctx):
+    G = _gen(100, 64)
+    G[37, 5] = 3
+    with pytest.raises(krr.KRRError) as e:
+        krr.krr_build_kernel(ctx, _dev(G), 0.01, 0.1)
+    assert e.value.status == krr.KRR_ERROR_BAD_GENOTYPE
+    G[37, 5] = 1
+    K = krr.krr_build_kernel(ctx, _dev(G), 0.01, 0.1)
+    F = krr.krr_factor(ctx, K)
+    T = _gen(10, 64, seed=4)
+    T[2, 63] = -1
+    with pytest.raises(krr.KRRError) as e:
+        krr.krr_predict(ctx, K, _dev(T), torch.zeros((100, 1), dtype=torch.float64, device=DEV))
+    assert e.value.status == krr.KRR_ERROR_BAD_GENOTYPE
+
+
+def test_breakdown_singular(ctx):
+    """Identical genotype rows and lambda = 0: K = 11^T has a zero pivot."""
+    G = np.ones((300, 48), np.int8)
+    K = krr.krr_build_kernel(ctx, _dev(G), 0.01, 0.0)
+    with pytest.raises(krr.KRRError) as e:
+        krr.krr_factor(ctx, K, krr.plain_fp32_policy())
+    assert e.value.status == krr.KRR_ERROR_NOT_POSITIVE_DEFINITE
+
+
+def test_not_converged_reports(ctx):
+    w = synth.WORKLOADS["small"]
+    G = w.genotypes(rows=600)
+    Y = w.phenotypes(G)
+    K = krr.krr_build_kernel(ctx, _dev(G), w.gamma, w.lam)
+    F = krr.krr_factor(ctx, K)
+    X, info, st = krr.krr_solve(ctx, F, _dev(Y), krr.Refine(max_iters=0, tol=1e-300), check=False)
+    assert st == krr.KRR_ERROR_NOT_CONVERGED
+    assert info.converged == 0 and info.fwd_err_bound > 0 and torch.isfinite(X).all()
+
+
+def test_workspace_limit(ctx):
+    c2 = krr.krr_create(0, workspace_limit=1 << 20)
+    G = _gen(2048, 256)
+    with pytest.raises(krr.KRRError) as e:
+        krr.krr_build_kernel(c2, _dev(G), 0.01, 0.1)
+    assert e.value.status == krr.KRR_ERROR_OUT_OF_MEMORY
