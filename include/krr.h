@@ -134,6 +134,9 @@ typedef struct krr_factor_info {
 /* Create a context on HIP device `device`, ordering work on `stream` (a
  * hipStream_t; NULL = the default stream).  opts may be NULL. */
 krr_status krr_create(krr_context *ctx, int device, void *stream, const krr_options *opts);
+/* Destroy a context.  If kernel or factor handles created on it are still
+ * alive, the context is freed when the last of them is released; it accepts
+ * no new work meanwhile. */
 krr_status krr_destroy(krr_context ctx);
 krr_status krr_set_stream(krr_context ctx, void *stream);
 
@@ -159,6 +162,7 @@ krr_status krr_kernel_release(krr_kernel K);
  */
 krr_status krr_factor(krr_context ctx, krr_kernel K, const krr_precision_policy *policy,
                       krr_factorization *out);
+/* The kernel handle must outlive its factors (solves read its distances). */
 krr_status krr_factor_release(krr_factorization F);
 krr_status krr_factor_get_info(krr_factorization F, krr_factor_info *info);
 

@@ -8,8 +8,10 @@ fallback: if the library is missing, loading raises.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
 import os
+import weakref
 from dataclasses import dataclass
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -126,56 +128,77 @@ def _stream_handle(stream):
     return stream.cuda_stream
 
 
-class Context:
-    def __init__(self, handle, device):
+# Live handles, released in dependency order (factors, kernels, contexts) at
+# interpreter exit, before the HIP runtime is torn down.
+_live = {"factor": weakref.WeakSet(), "kernel": weakref.WeakSet(), "context": weakref.WeakSet()}
+_exiting = False
+
+
+@atexit.register
+def _release_all():
+    global _exiting
+    for kind in ("factor", "kernel", "context"):
+        for h in list(_live[kind]):
+            try:
+                h._free()
+            except Exception:
+                pass
+    _exiting = True
+
+
+class _Handle:
+    kind = ""
+
+    def __init__(self, handle):
         self.handle = handle
+        _live[self.kind].add(self)
+
+    def _free(self):
+        if self.handle and not _exiting:
+            getattr(load(), self._release_fn)(self.handle)
+        self.handle = None
+
+    def __del__(self):
+        try:
+            self._free()
+        except Exception:
+            pass
+
+
+class Context(_Handle):
+    kind, _release_fn = "context", "krr_destroy"
+
+    def __init__(self, handle, device):
+        super().__init__(handle)
         self.device = device
 
     def close(self):
-        if self.handle:
-            load().krr_destroy(self.handle)
-            self.handle = None
-
-    def __del__(self):
-        try:
-            self.close()
-        except Exception:
-            pass
+        self._free()
 
 
-class Kernel:
-    """Device-resident kernel matrix; keeps the genotype tensor alive."""
+class Kernel(_Handle):
+    """Device-resident kernel matrix; keeps the genotype tensor and the context alive."""
+    kind, _release_fn = "kernel", "krr_kernel_release"
 
     def __init__(self, handle, ctx, G, n, m, gamma, lam):
-        self.handle, self.ctx, self.G = handle, ctx, G
+        super().__init__(handle)
+        self.ctx, self.G = ctx, G
         self.n, self.m, self.gamma, self.lam = n, m, gamma, lam
 
     def release(self):
-        if self.handle:
-            load().krr_kernel_release(self.handle)
-            self.handle = None
-
-    def __del__(self):
-        try:
-            self.release()
-        except Exception:
-            pass
+        self._free()
 
 
-class Factor:
+class Factor(_Handle):
+    """Cholesky factor; keeps its kernel alive (solves read the kernel's distances)."""
+    kind, _release_fn = "factor", "krr_factor_release"
+
     def __init__(self, handle, kernel):
-        self.handle, self.kernel = handle, kernel
+        super().__init__(handle)
+        self.kernel = kernel
 
     def release(self):
-        if self.handle:
-            load().krr_factor_release(self.handle)
-            self.handle = None
-
-    def __del__(self):
-        try:
-            self.release()
-        except Exception:
-            pass
+        self._free()
 
 
 @dataclass

@@ -30,6 +30,9 @@ struct krr_context_s {
   std::vector<hipEvent_t> pool;
   double total_ms[KRR_STAGE_COUNT] = {};
   int64_t intervals[KRR_STAGE_COUNT] = {};
+  // live kernel/factor handles; krr_destroy defers the free until they are released
+  int64_t live = 0;
+  bool destroy_pending = false;
 };
 
 struct krr_kernel_s {
@@ -50,7 +53,8 @@ struct krr_kernel_s {
 };
 
 struct krr_factor_s {
-  krr_kernel K = nullptr;
+  krr_context ctx = nullptr;
+  krr_kernel K = nullptr;  // must outlive the factor (its distances feed the residual)
   TileLayout L;
   float *Lst = nullptr;   // FP32 factor, packed lower tiles
   float *Linv = nullptr;  // inverses of the diagonal tiles, nt x nb x nb
@@ -261,13 +265,26 @@ krr_status krr_create(krr_context *out, int device, void *stream, const krr_opti
   return KRR_SUCCESS;
 }
 
-krr_status krr_destroy(krr_context ctx) {
-  if (!ctx) return KRR_ERROR_INVALID_VALUE;
+static void context_free(krr_context ctx) {
   (void)hipSetDevice(ctx->device);
   (void)hipStreamSynchronize(ctx->stream);
   timers_drain(ctx);
   for (hipEvent_t e : ctx->pool) (void)hipEventDestroy(e);
   delete ctx;
+}
+
+// A handle was released: free the context if it was destroyed while handles lived.
+static void context_unref(krr_context ctx) {
+  if (--ctx->live == 0 && ctx->destroy_pending) context_free(ctx);
+}
+
+krr_status krr_destroy(krr_context ctx) {
+  if (!ctx || ctx->destroy_pending) return KRR_ERROR_INVALID_VALUE;
+  if (ctx->live > 0) {
+    ctx->destroy_pending = true;  // freed when the last kernel/factor is released
+    return KRR_SUCCESS;
+  }
+  context_free(ctx);
   return KRR_SUCCESS;
 }
 
@@ -293,7 +310,8 @@ krr_status krr_build_kernel(krr_context ctx, const int8_t *G, int64_t n, int64_t
                             double gamma, double lambda, krr_kernel *out) {
   if (!out) return KRR_ERROR_INVALID_VALUE;
   *out = nullptr;
-  if (!ctx || !G || n <= 0 || m <= 0 || ldg < m || (ldg % 16) != 0 || !aligned16(G))
+  if (!ctx || ctx->destroy_pending || !G || n <= 0 || m <= 0 || ldg < m || (ldg % 16) != 0 ||
+      !aligned16(G))
     return KRR_ERROR_INVALID_VALUE;
   if (!(gamma > 0) || !isfinite(gamma) || !(lambda >= 0) || !isfinite(lambda))
     return KRR_ERROR_INVALID_VALUE;
@@ -354,16 +372,19 @@ krr_status krr_build_kernel(krr_context ctx, const int8_t *G, int64_t n, int64_t
     delete K;
     return st;
   }
+  ctx->live++;
   *out = K;
   return KRR_SUCCESS;
 }
 
 krr_status krr_kernel_release(krr_kernel K) {
   if (!K) return KRR_ERROR_INVALID_VALUE;
-  (void)hipSetDevice(K->ctx->device);
-  (void)hipStreamSynchronize(K->ctx->stream);
+  krr_context c = K->ctx;
+  (void)hipSetDevice(c->device);
+  (void)hipStreamSynchronize(c->stream);
   kernel_free(K);
   delete K;
+  context_unref(c);
   return KRR_SUCCESS;
 }
 
@@ -478,6 +499,7 @@ krr_status krr_factor(krr_context ctx, krr_kernel K, const krr_precision_policy 
   bool diag64 = p.diag_fp64 != 0;
 
   krr_factorization F = new krr_factor_s();
+  F->ctx = ctx;
   F->K = K;
   F->L = L;
   F->info.nt = L.nt;
@@ -585,18 +607,20 @@ krr_status krr_factor(krr_context ctx, krr_kernel K, const krr_precision_policy 
     fprintf(stderr, "krr_factor: n=%lld nt=%d updates fp32=%lld fp16=%lld fp8=%lld promotions=%d\n",
             (long long)L.n, L.nt, (long long)F->info.updates[0], (long long)F->info.updates[1],
             (long long)F->info.updates[2], F->info.promotions);
+  ctx->live++;
   *out = F;
   return KRR_SUCCESS;
 }
 
 krr_status krr_factor_release(krr_factorization F) {
   if (!F) return KRR_ERROR_INVALID_VALUE;
-  krr_context c = F->K->ctx;
+  krr_context c = F->ctx;
   (void)hipSetDevice(c->device);
   (void)hipStreamSynchronize(c->stream);
   dfree(c, F->Lst, F->L.elems() * 4);
   dfree(c, F->Linv, (size_t)F->L.nt * F->L.tile_elems() * 4);
   delete F;
+  context_unref(c);
   return KRR_SUCCESS;
 }
 
@@ -793,7 +817,7 @@ krr_status krr_factor_copy_l(krr_factorization F, int64_t i0, int64_t j0, int64_
   if (!F || !dst || rows <= 0 || cols <= 0 || ld < cols || i0 < 0 || j0 < 0 ||
       i0 + rows > F->L.n || j0 + cols > F->L.n)
     return KRR_ERROR_INVALID_VALUE;
-  krr_context c = F->K->ctx;
+  krr_context c = F->ctx;
   HIPCHK(hipSetDevice(c->device));
   launch_copy_tiles_f32(F->Lst, F->L, i0, j0, rows, cols, true, dst, ld, c->stream);
   CHK(launch_ok());

@@ -72,17 +72,17 @@ void launch_row_norms(const int8_t *G, int64_t n, int64_t rows_padded, int64_t m
 // entry: d = n_i + n_j - 2 S (int32), A = exp(-gamma d) in FP64 rounded to
 // FP32 (table lookup), 1 + lambda on the diagonal, identity on padding; plus
 // the sub-block's FP64 sum of squares for the tile norms.
-template <int BM, int BN>
-__global__ __launch_bounds__(256) void k_gram_tiles(const int8_t *__restrict__ G, int64_t n,
+template <class S>
+__global__ __launch_bounds__(S::THREADS) void k_gram_tiles(const int8_t *__restrict__ G, int64_t n,
                                                     int64_t m, int64_t ldg,
                                                     const int32_t *__restrict__ nrm,
                                                     const double *__restrict__ etab,
                                                     int64_t etab_len, double lambda, int nb,
                                                     int SB, int32_t *__restrict__ D,
                                                     float *__restrict__ A, double *part) {
-  typedef GemmShape<BM, BN> S;
+  constexpr int BM = S::kBM, BN = S::kBN, NW = S::THREADS / 64;
   __shared__ __attribute__((aligned(16))) uint8_t lds[S::LDS_BYTES];
-  __shared__ double shd[4];
+  __shared__ double shd[NW];
   const int64_t bid = xcd_remap(blockIdx.x, gridDim.x);
   const int nsub = SB * SB;
   const int sub = (int)(bid % nsub);
@@ -97,11 +97,10 @@ __global__ __launch_bounds__(256) void k_gram_tiles(const int8_t *__restrict__ G
   OpI8::acc_t acc[S::WTM][S::WTN];
   zero_acc(acc);
   if (arows > 0 && brows > 0)
-    gemm_nt_core<OpI8, BM, BN>((const uint8_t *)G + row0 * ldg, ldg, arows,
-                               (const uint8_t *)G + col0 * ldg, ldg, brows, m, acc, lds);
+    gemm_nt_core<OpI8, S>((const uint8_t *)G + row0 * ldg, ldg, arows,
+                          (const uint8_t *)G + col0 * ldg, ldg, brows, m, acc, lds);
 
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int wm = wave >> 1, wn = wave & 1;
   const int64_t tbase = t * (int64_t)nb * nb;
   double ss = 0.0;
 #pragma unroll
@@ -110,8 +109,8 @@ __global__ __launch_bounds__(256) void k_gram_tiles(const int8_t *__restrict__ G
     for (int tn = 0; tn < S::WTN; ++tn)
 #pragma unroll
       for (int i = 0; i < 16; ++i) {
-        const int r = wm * (BM / 2) + tm * 32 + mfma_row(i, lane);
-        const int c = wn * (BN / 2) + tn * 32 + mfma_col(lane);
+        const int r = S::row(wave, tm, i, lane);
+        const int c = S::col(wave, tn, lane);
         const int64_t gi = row0 + r, gj = col0 + c;
         int32_t d;
         float a;
@@ -127,17 +126,19 @@ __global__ __launch_bounds__(256) void k_gram_tiles(const int8_t *__restrict__ G
         A[off] = a;
         ss += (double)a * (double)a;
       }
-  ss = block_sum_256(ss, shd);
+  ss = block_sum<NW>(ss, shd);
   if (threadIdx.x == 0) part[bid] = ss;
 }
+
+typedef GemmShape<256, 256, 2, 4> GramShape;
 
 void launch_gram_tiles(const int8_t *G, int64_t m, int64_t ldg, const int32_t *nrm,
                        const double *etab, int64_t etab_len, double lambda, const TileLayout &L,
                        int32_t *D, float *A, double *tnorm_part, hipStream_t s) {
-  constexpr int BM = 256, BN = 256;
-  const int SB = L.nb / BM;
+  const int SB = L.nb / GramShape::kBM;
   const int64_t blocks = L.ntiles() * SB * SB;
-  hipLaunchKernelGGL((k_gram_tiles<BM, BN>), dim3((unsigned)blocks), dim3(256), 0, s, G, L.n, m,
+  hipLaunchKernelGGL((k_gram_tiles<GramShape>), dim3((unsigned)blocks), dim3(GramShape::THREADS), 0,
+                     s, G, L.n, m,
                      ldg, nrm, etab, etab_len, lambda, L.nb, SB, D, A, tnorm_part);
 }
 
@@ -187,15 +188,15 @@ void launch_expand_tiles(const int32_t *D, const double *etab, int64_t etab_len,
 // Cross distances for Predict (Algorithm 4's Build(gamma, T, G)):
 // Dt[i, j] = n^T_i + n^G_j - 2 <t_i, g_j> for i < rows, j < cols_padded
 // (0 for the padding columns j >= n).  Row-major with leading dimension ldd.
-template <int BM, int BN>
-__global__ __launch_bounds__(256) void k_cross_gram(const int8_t *__restrict__ T, int64_t rows,
+template <class S>
+__global__ __launch_bounds__(S::THREADS) void k_cross_gram(const int8_t *__restrict__ T, int64_t rows,
                                                     const int32_t *__restrict__ nrm_t,
                                                     const int8_t *__restrict__ G, int64_t n,
                                                     int64_t m, int64_t ldt, int64_t ldg,
                                                     const int32_t *__restrict__ nrm_g,
                                                     int64_t cols, int64_t nbc,
                                                     int32_t *__restrict__ Dt, int64_t ldd) {
-  typedef GemmShape<BM, BN> S;
+  constexpr int BM = S::kBM, BN = S::kBN;
   __shared__ __attribute__((aligned(16))) uint8_t lds[S::LDS_BYTES];
   const int64_t bid = xcd_remap(blockIdx.x, gridDim.x);
   const int64_t bi = bid / nbc, bj = bid % nbc;
@@ -205,18 +206,17 @@ __global__ __launch_bounds__(256) void k_cross_gram(const int8_t *__restrict__ T
   OpI8::acc_t acc[S::WTM][S::WTN];
   zero_acc(acc);
   if (arows > 0 && brows > 0)
-    gemm_nt_core<OpI8, BM, BN>((const uint8_t *)T + row0 * ldt, ldt, arows,
-                               (const uint8_t *)G + col0 * ldg, ldg, brows, m, acc, lds);
+    gemm_nt_core<OpI8, S>((const uint8_t *)T + row0 * ldt, ldt, arows,
+                          (const uint8_t *)G + col0 * ldg, ldg, brows, m, acc, lds);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int wm = wave >> 1, wn = wave & 1;
 #pragma unroll
   for (int tm = 0; tm < S::WTM; ++tm)
 #pragma unroll
     for (int tn = 0; tn < S::WTN; ++tn)
 #pragma unroll
       for (int i = 0; i < 16; ++i) {
-        const int64_t gi = row0 + wm * (BM / 2) + tm * 32 + mfma_row(i, lane);
-        const int64_t gj = col0 + wn * (BN / 2) + tn * 32 + mfma_col(lane);
+        const int64_t gi = row0 + S::row(wave, tm, i, lane);
+        const int64_t gj = col0 + S::col(wave, tn, lane);
         if (gi < rows && gj < cols)
           Dt[gi * ldd + gj] = (gj < n) ? nrm_t[gi] + nrm_g[gj] - 2 * acc[tm][tn][i] : 0;
       }
@@ -225,9 +225,10 @@ __global__ __launch_bounds__(256) void k_cross_gram(const int8_t *__restrict__ T
 void launch_cross_gram(const int8_t *T, int64_t nt_rows, const int32_t *nrm_t, const int8_t *G,
                        int64_t n, int64_t m, int64_t ldt, int64_t ldg, const int32_t *nrm_g,
                        int64_t cols_padded, int32_t *Dt, int64_t ldd, hipStream_t s) {
-  constexpr int BM = 256, BN = 256;
+  constexpr int BM = GramShape::kBM, BN = GramShape::kBN;
   const int64_t nbr = (nt_rows + BM - 1) / BM, nbc = (cols_padded + BN - 1) / BN;
-  hipLaunchKernelGGL((k_cross_gram<BM, BN>), dim3((unsigned)(nbr * nbc)), dim3(256), 0, s, T,
+  hipLaunchKernelGGL((k_cross_gram<GramShape>), dim3((unsigned)(nbr * nbc)),
+                     dim3(GramShape::THREADS), 0, s, T,
                      nt_rows, nrm_t, G, n, m, ldt, ldg, nrm_g, cols_padded, nbc, Dt, ldd);
 }
 

@@ -125,34 +125,54 @@ KRR_DEV int mfma_col(int lane) { return lane & 31; }
 
 // ---------------------------------------------------------------------------
 // NT-GEMM core: acc[BM x BN] += A[BM x K] * B[BN x K]^T for one workgroup of
-// 256 threads (4 waves in a 2 x 2 grid; each wave owns a (BM/2) x (BN/2)
-// block of 32x32 MFMA tiles).  A and B are row-major with byte leading
-// dimensions lda/ldb (multiples of 16) and K given in bytes (kbytes).  Rows
-// at or beyond arows/brows, and bytes at or beyond kbytes, read as zero.
-// K is staged through LDS in 64-byte slabs, double-buffered, with the next
-// slab's global loads issued before the current slab's MFMAs.
-template <int BM, int BN>
+// WGM x WGN waves; each wave owns a (BM/WGM) x (BN/WGN) block of 32x32 MFMA
+// tiles.  A and B are row-major with byte leading dimensions lda/ldb
+// (multiples of 16) and K given in bytes (kbytes).  Rows at or beyond
+// arows/brows, and bytes at or beyond kbytes, read as zero.  K is staged
+// through LDS in 64-byte slabs, double-buffered, with the next slab's global
+// loads issued before the current slab's MFMAs.
+template <int BM, int BN, int WGM = 2, int WGN = 2>
 struct GemmShape {
-  static constexpr int WTM = BM / 2 / 32;  // MFMA tiles per wave, rows
-  static constexpr int WTN = BN / 2 / 32;  // MFMA tiles per wave, cols
-  static constexpr int ROWB = 64 + 16;     // LDS row stride (bytes), padded
+  static constexpr int kBM = BM, kBN = BN, kWGM = WGM, kWGN = WGN;
+  static constexpr int THREADS = 64 * WGM * WGN;
+  static constexpr int WROWS = BM / WGM;        // rows per wave
+  static constexpr int WCOLS = BN / WGN;        // cols per wave
+  static constexpr int WTM = WROWS / 32;        // MFMA tiles per wave, rows
+  static constexpr int WTN = WCOLS / 32;        // MFMA tiles per wave, cols
+  static constexpr int ROWB = 64 + 16;          // LDS row stride (bytes), padded
   static constexpr int STAGE = (BM + BN) * ROWB;
   static constexpr int LDS_BYTES = 2 * STAGE;
-  static constexpr int LA = BM * 4 / 256;  // 16-byte loads per thread, A
-  static constexpr int LB = BN * 4 / 256;  // 16-byte loads per thread, B
+  static constexpr int LA = BM * 4 / THREADS;   // 16-byte loads per thread, A
+  static constexpr int LB = BN * 4 / THREADS;   // 16-byte loads per thread, B
+  static_assert(LA * THREADS == BM * 4 && LB * THREADS == BN * 4, "load split");
+  // row / column (within the block) of accumulator register i of tile (tm, tn)
+  KRR_DEV static int row(int wave, int tm, int i, int lane) {
+    return (wave / WGN) * WROWS + tm * 32 + 8 * (i >> 2) + 4 * (lane >> 5) + (i & 3);
+  }
+  KRR_DEV static int col(int wave, int tn, int lane) {
+    return (wave % WGN) * WCOLS + tn * 32 + (lane & 31);
+  }
 };
 
-template <class Op, int BM, int BN>
+KRR_DEV v4i mask_tail(v4i v, int64_t keep) {
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int64_t valid = keep - 4 * q;
+    if (valid <= 0) v[q] = 0;
+    else if (valid < 4) v[q] &= (int)((1u << (8 * valid)) - 1u);
+  }
+  return v;
+}
+
+template <class Op, class S>
 KRR_DEV void gemm_nt_core(const uint8_t *__restrict__ A, int64_t lda, int arows,
-                          const uint8_t *__restrict__ B, int64_t ldb, int brows,
-                          int64_t kbytes,
-                          typename Op::acc_t (&acc)[GemmShape<BM, BN>::WTM][GemmShape<BM, BN>::WTN],
-                          uint8_t *lds) {
-  typedef GemmShape<BM, BN> S;
+                          const uint8_t *__restrict__ B, int64_t ldb, int brows, int64_t kbytes,
+                          typename Op::acc_t (&acc)[S::WTM][S::WTN], uint8_t *lds) {
+  constexpr int BM = S::kBM, BN = S::kBN, T = S::THREADS;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
-  const int wm = wave >> 1, wn = wave & 1;
+  const int wm = wave / S::kWGN, wn = wave % S::kWGN;
 
   // global load assignment: thread handles 16-byte chunk c (0..3) of row r
   v4i ra[S::LA], rb[S::LB];
@@ -162,37 +182,25 @@ KRR_DEV void gemm_nt_core(const uint8_t *__restrict__ A, int64_t lda, int arows,
     const int64_t k0 = slab * 64;
 #pragma unroll
     for (int t = 0; t < S::LA; ++t) {
-      const int idx = tid + t * 256;
+      const int idx = tid + t * T;
       const int r = idx >> 2, c = idx & 3;
       const int64_t kb = k0 + c * 16;
       v4i v = {0, 0, 0, 0};
       if (r < arows && kb < kbytes) {
         v = *(const v4i *)(A + (int64_t)r * lda + kb);
-        if (kb + 16 > kbytes) {
-          const int keep = (int)(kbytes - kb);
-          uint8_t *p = (uint8_t *)&v;
-#pragma unroll
-          for (int q = 0; q < 16; ++q)
-            if (q >= keep) p[q] = 0;
-        }
+        if (kb + 16 > kbytes) v = mask_tail(v, kbytes - kb);
       }
       ra[t] = v;
     }
 #pragma unroll
     for (int t = 0; t < S::LB; ++t) {
-      const int idx = tid + t * 256;
+      const int idx = tid + t * T;
       const int r = idx >> 2, c = idx & 3;
       const int64_t kb = k0 + c * 16;
       v4i v = {0, 0, 0, 0};
       if (r < brows && kb < kbytes) {
         v = *(const v4i *)(B + (int64_t)r * ldb + kb);
-        if (kb + 16 > kbytes) {
-          const int keep = (int)(kbytes - kb);
-          uint8_t *p = (uint8_t *)&v;
-#pragma unroll
-          for (int q = 0; q < 16; ++q)
-            if (q >= keep) p[q] = 0;
-        }
+        if (kb + 16 > kbytes) v = mask_tail(v, kbytes - kb);
       }
       rb[t] = v;
     }
@@ -201,14 +209,14 @@ KRR_DEV void gemm_nt_core(const uint8_t *__restrict__ A, int64_t lda, int arows,
     uint8_t *base = lds + buf * S::STAGE;
 #pragma unroll
     for (int t = 0; t < S::LA; ++t) {
-      const int idx = tid + t * 256;
+      const int idx = tid + t * T;
       const int r = idx >> 2, c = idx & 3;
       *(v4i *)(base + r * S::ROWB + c * 16) = ra[t];
     }
     uint8_t *bb = base + BM * S::ROWB;
 #pragma unroll
     for (int t = 0; t < S::LB; ++t) {
-      const int idx = tid + t * 256;
+      const int idx = tid + t * T;
       const int r = idx >> 2, c = idx & 3;
       *(v4i *)(bb + r * S::ROWB + c * 16) = rb[t];
     }
@@ -228,13 +236,13 @@ KRR_DEV void gemm_nt_core(const uint8_t *__restrict__ A, int64_t lda, int arows,
     v4i bf0[S::WTN], bf1[S::WTN];
 #pragma unroll
     for (int tn = 0; tn < S::WTN; ++tn) {
-      const uint8_t *p = sb + (wn * (BN / 2) + tn * 32 + lrow) * S::ROWB + lhalf * 32;
+      const uint8_t *p = sb + (wn * S::WCOLS + tn * 32 + lrow) * S::ROWB + lhalf * 32;
       bf0[tn] = *(const v4i *)p;
       bf1[tn] = *(const v4i *)(p + 16);
     }
 #pragma unroll
     for (int tm = 0; tm < S::WTM; ++tm) {
-      const uint8_t *p = sa + (wm * (BM / 2) + tm * 32 + lrow) * S::ROWB + lhalf * 32;
+      const uint8_t *p = sa + (wm * S::WROWS + tm * 32 + lrow) * S::ROWB + lhalf * 32;
       const v4i a0 = *(const v4i *)p;
       const v4i a1 = *(const v4i *)(p + 16);
 #pragma unroll
@@ -243,6 +251,7 @@ KRR_DEV void gemm_nt_core(const uint8_t *__restrict__ A, int64_t lda, int arows,
     if (s + 1 < nslab) sstore(buf ^ 1);
     __syncthreads();
   }
+  (void)BN;
 }
 
 template <class AccT, int WTM, int WTN>
@@ -255,24 +264,30 @@ KRR_DEV void zero_acc(AccT (&acc)[WTM][WTN]) {
       for (int i = 0; i < 16; ++i) acc[a][b][i] = 0;
 }
 
-// Fixed-order block reduction of one double per thread (256 threads):
-// wave butterfly, then the four wave sums in order.  Result valid in all threads.
-KRR_DEV double block_sum_256(double v, double *sh) {
+// Fixed-order block reduction of one double per thread (NW waves): wave
+// butterfly, then the wave sums in index order.  Result valid in all threads.
+template <int NW = 4>
+KRR_DEV double block_sum(double v, double *sh) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
   if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
   __syncthreads();
-  const double r = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+  double r = sh[0];
+#pragma unroll
+  for (int w = 1; w < NW; ++w) r += sh[w];
   __syncthreads();
   return r;
 }
 
-KRR_DEV float block_max_256(float v, float *sh) {
+template <int NW = 4>
+KRR_DEV float block_max(float v, float *sh) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
   if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
   __syncthreads();
-  const float r = fmaxf(fmaxf(sh[0], sh[1]), fmaxf(sh[2], sh[3]));
+  float r = sh[0];
+#pragma unroll
+  for (int w = 1; w < NW; ++w) r = fmaxf(r, sh[w]);
   __syncthreads();
   return r;
 }

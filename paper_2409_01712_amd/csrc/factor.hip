@@ -30,16 +30,19 @@ __global__ void k_potrf_load(const float *__restrict__ Akk, T *__restrict__ W, i
   W[e] = (c <= r) ? (T)Akk[e] : (T)0;
 }
 
-// Factor sub-block (s, s) in LDS and invert it.  One workgroup.
+// Factor sub-block (s, s) and invert it with one wavefront (64 lanes, so a
+// workgroup barrier is only a wave barrier).  Lane i owns row i of the block
+// during the factorization and column i of the inverse afterwards; both
+// live in LDS, and every cross-lane read is a broadcast of one element.
 template <typename T>
-__global__ __launch_bounds__(256) void k_potrf_diag64(T *__restrict__ W, int nb, int s,
-                                                      T *__restrict__ Dinv, int32_t *flag,
-                                                      int64_t colbase) {
+__global__ __launch_bounds__(64) void k_potrf_diag64(T *__restrict__ W, int nb, int s,
+                                                     T *__restrict__ Dinv, int32_t *flag,
+                                                     int64_t colbase) {
   __shared__ T L[BS][BS + 1];
   __shared__ T Li[BS][BS + 1];
-  const int tid = threadIdx.x;
+  const int i = threadIdx.x;
   T *blk = W + (int64_t)(s * BS) * nb + s * BS;
-  for (int e = tid; e < BS * BS; e += 256) {
+  for (int e = i; e < BS * BS; e += BS) {
     const int r = e / BS, c = e % BS;
     L[r][c] = (c <= r) ? blk[(int64_t)r * nb + c] : (T)0;
   }
@@ -49,34 +52,40 @@ __global__ __launch_bounds__(256) void k_potrf_diag64(T *__restrict__ W, int nb,
     const bool bad = !(piv > (T)0);
     const T d = bad ? (T)1 : sqrt(piv);
     __syncthreads();
-    if (tid == 0) {
+    T lij = (T)0;
+    if (i > j) {
+      lij = L[i][j] / d;
+      L[i][j] = lij;
+    } else if (i == j) {
       L[j][j] = d;
       if (bad) atomicCAS(flag, 0, (int32_t)(colbase + s * BS + j + 1));
     }
-    for (int i = j + 1 + tid; i < BS; i += 256) L[i][j] /= d;
     __syncthreads();
-    const int w = BS - 1 - j;
-    for (int e = tid; e < w * w; e += 256) {
-      const int r = j + 1 + e / w, c = j + 1 + e % w;
-      if (c <= r) L[r][c] -= L[r][j] * L[c][j];
+    if (i > j) {
+#pragma unroll 4
+      for (int c = j + 1; c <= i; ++c) L[i][c] -= lij * L[c][j];
     }
     __syncthreads();
   }
-  if (tid < BS) {  // column c of the inverse of the lower-triangular block
-    const int c = tid;
-    for (int i = 0; i < c; ++i) Li[i][c] = (T)0;
-    Li[c][c] = (T)1 / L[c][c];
-    for (int i = c + 1; i < BS; ++i) {
-      T acc = 0;
-      for (int p = c; p < i; ++p) acc += L[i][p] * Li[p][c];
-      Li[i][c] = -acc / L[i][i];
+  // column c = i of inv(L) by forward substitution against e_c
+  const int c = i;
+  for (int k = 0; k < BS; ++k) {
+    T acc0 = (k == c) ? (T)1 : (T)0, acc1 = 0, acc2 = 0, acc3 = 0;
+    int p = c;
+    for (; p + 3 < k; p += 4) {
+      acc0 -= L[k][p] * Li[p][c];
+      acc1 -= L[k][p + 1] * Li[p + 1][c];
+      acc2 -= L[k][p + 2] * Li[p + 2][c];
+      acc3 -= L[k][p + 3] * Li[p + 3][c];
     }
+    for (; p < k; ++p) acc0 -= L[k][p] * Li[p][c];
+    Li[k][c] = (k < c) ? (T)0 : ((acc0 + acc1) + (acc2 + acc3)) / L[k][k];
   }
   __syncthreads();
-  for (int e = tid; e < BS * BS; e += 256) {
-    const int r = e / BS, c = e % BS;
-    blk[(int64_t)r * nb + c] = (c <= r) ? L[r][c] : (T)0;
-    Dinv[(int64_t)s * BS * BS + e] = Li[r][c];
+  for (int e = i; e < BS * BS; e += BS) {
+    const int r = e / BS, cc = e % BS;
+    Dinv[(int64_t)s * BS * BS + e] = Li[r][cc];
+    blk[(int64_t)r * nb + cc] = (cc <= r) ? L[r][cc] : (T)0;
   }
 }
 
@@ -99,9 +108,22 @@ __device__ __forceinline__ void mm64(const T (*X)[BS + 1], const T (*Yt)[BS + 1]
   }
 }
 
+// Stage a 64 x 64 block into LDS: all 16 loads of a thread are issued before
+// any LDS store, so their latencies overlap.
 template <typename T>
 __device__ __forceinline__ void load64(T (*dst)[BS + 1], const T *src, int64_t ld) {
-  for (int e = threadIdx.x; e < BS * BS; e += 256) dst[e / BS][e % BS] = src[(e / BS) * ld + e % BS];
+  constexpr int PER = BS * BS / 256;
+  T v[PER];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int e = threadIdx.x + q * 256;
+    v[q] = src[(int64_t)(e / BS) * ld + e % BS];
+  }
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int e = threadIdx.x + q * 256;
+    dst[e / BS][e % BS] = v[q];
+  }
 }
 
 // Panel of the diagonal tile: W_as <- W_as * inv(L_ss)^T for a > s.
@@ -209,7 +231,7 @@ static void potrf_tile_t(float *Akk, float *Linv, int k, const TileLayout &L, Fa
   const int64_t colbase = (int64_t)k * nb;
   hipLaunchKernelGGL(k_potrf_load<T>, dim3(eb), dim3(256), 0, s, Akk, W, nb);
   for (int st = 0; st < NB; ++st) {
-    hipLaunchKernelGGL(k_potrf_diag64<T>, dim3(1), dim3(256), 0, s, W, nb, st, Dinv, w.flag,
+    hipLaunchKernelGGL(k_potrf_diag64<T>, dim3(1), dim3(64), 0, s, W, nb, st, Dinv, w.flag,
                        colbase);
     const int rest = NB - 1 - st;
     if (rest > 0) {
@@ -238,13 +260,14 @@ void launch_potrf_tile(float *Akk, float *Linv, int k, const TileLayout &L, bool
 // same tile).  Each 128 x 128 block also leaves its FP64 sum of squares and
 // its max |entry| for the operand norms and scales.
 constexpr int UB = 128;  // block edge of the factorization GEMMs
+typedef GemmShape<UB, UB, 2, 2> UpdShape;
 
 __global__ __launch_bounds__(256) void k_trsm_panel(const float *__restrict__ Astore,
                                                     const float *__restrict__ Linv, int k, int nb,
                                                     int SB, float *__restrict__ P32,
                                                     double *__restrict__ pnorm_part,
                                                     float *__restrict__ pmax_part) {
-  typedef GemmShape<UB, UB> S;
+  typedef UpdShape S;
   __shared__ __attribute__((aligned(16))) uint8_t lds[S::LDS_BYTES];
   __shared__ double shd[4];
   __shared__ float shf[4];
@@ -260,10 +283,9 @@ __global__ __launch_bounds__(256) void k_trsm_panel(const float *__restrict__ As
   const int64_t kbytes = (int64_t)min(nb, (sj + 1) * UB) * 4;  // inv(L) is lower triangular
   OpF32::acc_t acc[S::WTM][S::WTN];
   zero_acc(acc);
-  gemm_nt_core<OpF32, UB, UB>((const uint8_t *)Ablk, (int64_t)nb * 4, UB, (const uint8_t *)Bblk,
-                              (int64_t)nb * 4, UB, kbytes, acc, lds);
+  gemm_nt_core<OpF32, S>((const uint8_t *)Ablk, (int64_t)nb * 4, UB, (const uint8_t *)Bblk,
+                         (int64_t)nb * 4, UB, kbytes, acc, lds);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int wm = wave >> 1, wn = wave & 1;
   float *out = P32 + t * te + (int64_t)si * UB * nb + sj * UB;
   double ss = 0.0;
   float mx = 0.0f;
@@ -273,15 +295,15 @@ __global__ __launch_bounds__(256) void k_trsm_panel(const float *__restrict__ As
     for (int tn = 0; tn < S::WTN; ++tn)
 #pragma unroll
       for (int e = 0; e < 16; ++e) {
-        const int r = wm * (UB / 2) + tm * 32 + mfma_row(e, lane);
-        const int c = wn * (UB / 2) + tn * 32 + mfma_col(lane);
+        const int r = S::row(wave, tm, e, lane);
+        const int c = S::col(wave, tn, lane);
         const float v = acc[tm][tn][e];
         out[(int64_t)r * nb + c] = v;
         ss += (double)v * (double)v;
         mx = fmaxf(mx, fabsf(v));
       }
-  ss = block_sum_256(ss, shd);
-  mx = block_max_256(mx, shf);
+  ss = block_sum<4>(ss, shd);
+  mx = block_max<4>(mx, shf);
   if (threadIdx.x == 0) {
     pnorm_part[bid] = ss;
     pmax_part[bid] = mx;
@@ -369,7 +391,7 @@ __global__ __launch_bounds__(256) void k_update(
     const float *__restrict__ pscale16, const float *__restrict__ pscale8, int k, int nb, int SB,
     int mode, int allow16, int allow8, int high_panels, int fixed_prec, double thr,
     unsigned long long *counts, uint8_t *pmap, int64_t ntiles_all) {
-  typedef GemmShape<UB, UB> S;
+  typedef UpdShape S;
   __shared__ __attribute__((aligned(16))) uint8_t lds[S::LDS_BYTES];
   const int64_t bid = xcd_remap(blockIdx.x, gridDim.x);
   const int nsub = SB * SB;
@@ -398,23 +420,22 @@ __global__ __launch_bounds__(256) void k_update(
   zero_acc(acc);
   float scale = 1.0f;
   if (prec == KRR_PREC_FP8) {
-    gemm_nt_core<OpF8, UB, UB>(P8 + a * te + (int64_t)si * UB * nb, nb, UB,
+    gemm_nt_core<OpF8, S>(P8 + a * te + (int64_t)si * UB * nb, nb, UB,
                                P8 + b * te + (int64_t)sj * UB * nb, nb, UB, nb, acc, lds);
     scale = 1.0f / (pscale8[a] * pscale8[b]);
   } else if (prec == KRR_PREC_FP16) {
-    gemm_nt_core<OpF16, UB, UB>((const uint8_t *)(P16 + a * te + (int64_t)si * UB * nb),
+    gemm_nt_core<OpF16, S>((const uint8_t *)(P16 + a * te + (int64_t)si * UB * nb),
                                 (int64_t)nb * 2, UB,
                                 (const uint8_t *)(P16 + b * te + (int64_t)sj * UB * nb),
                                 (int64_t)nb * 2, UB, (int64_t)nb * 2, acc, lds);
     scale = 1.0f / (pscale16[a] * pscale16[b]);
   } else {
-    gemm_nt_core<OpF32, UB, UB>((const uint8_t *)(P32 + a * te + (int64_t)si * UB * nb),
+    gemm_nt_core<OpF32, S>((const uint8_t *)(P32 + a * te + (int64_t)si * UB * nb),
                                 (int64_t)nb * 4, UB,
                                 (const uint8_t *)(P32 + b * te + (int64_t)sj * UB * nb),
                                 (int64_t)nb * 4, UB, (int64_t)nb * 4, acc, lds);
   }
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int wm = wave >> 1, wn = wave & 1;
   float *C = Astore + (i * (i + 1) / 2 + j) * te + (int64_t)si * UB * nb + sj * UB;
 #pragma unroll
   for (int tm = 0; tm < S::WTM; ++tm)
@@ -422,8 +443,8 @@ __global__ __launch_bounds__(256) void k_update(
     for (int tn = 0; tn < S::WTN; ++tn)
 #pragma unroll
       for (int e = 0; e < 16; ++e) {
-        const int r = wm * (UB / 2) + tm * 32 + mfma_row(e, lane);
-        const int c = wn * (UB / 2) + tn * 32 + mfma_col(lane);
+        const int r = S::row(wave, tm, e, lane);
+        const int c = S::col(wave, tn, lane);
         C[(int64_t)r * nb + c] -= scale * acc[tm][tn][e];
       }
   if (sub == 0 && threadIdx.x == 0) {

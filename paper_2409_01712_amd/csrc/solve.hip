@@ -13,19 +13,28 @@
 
 namespace krr {
 
-// ---------------------------------------------------------------------------
-// Out[rows] (=|-=) M * V or M^T * V for one nb x nb FP32 tile M (row-major)
-// and an nb x r block V (row-major, leading dimension r).  Workgroup = 64
-// output rows x 32 columns; M is staged through LDS in 64 x 64 blocks.
-// mode 0: M = Mbase, V = Vbase, Out = Obase (diagonal step; tri limits q)
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+// Skinny products on 16 x 16 x 4 MFMA tiles.  A wavefront owns 16 output rows
+// and 16 * NCB columns.  Lane l supplies, for each of four consecutive MFMAs,
+// the A element (row l % 16, k = 4 (l / 16) + e) and the B element
+// (k = 4 (l / 16) + e, column l % 16): both operands use the same k mapping,
+// so each group of four MFMAs sums k over a 16-wide block exactly once.  A
+// comes straight from memory (a tile of L, or exp(-gamma d) through the FP64
+// table), B from the right-hand-side block, with no LDS staging.
+// Output layout of a 16 x 16 MFMA accumulator: lane l, register i holds
+// row 4 (l / 16) + i, column l % 16.
+
+// Out[rows] (=|-=) M V or M^T V for one nb x nb FP32 tile M (row-major) and an
+// nb x r block V (row-major, leading dimension r).  64 rows per workgroup.
+// mode 0: M = Mbase, Out = Obase (diagonal step; tri limits the k range)
 // mode 1: forward panel, tile i = k + 1 + blockIdx.x: M = tile (i, k), Out row block i
 // mode 2: backward panel, tile j = blockIdx.x: M = tile (k, j) (transposed), Out row block j
-template <bool TRANS, bool SUB>
+template <bool TRANS, bool SUB, int NCB>
 __global__ __launch_bounds__(256) void k_tri_apply(const float *__restrict__ Mbase,
                                                    const float *__restrict__ V, float *Obase,
                                                    int mode, int k, int nb, int r, int tri) {
-  __shared__ float Ms[64][65];
-  __shared__ float Vs[64][33];
   const int64_t te = (int64_t)nb * nb;
   const float *M = Mbase;
   float *Out = Obase;
@@ -38,80 +47,137 @@ __global__ __launch_bounds__(256) void k_tri_apply(const float *__restrict__ Mba
     M = Mbase + ((int64_t)k * (k + 1) / 2 + j) * te;
     Out = Obase + j * nb * (int64_t)r;
   }
-  const int rb = blockIdx.y, cc = blockIdx.z;
-  const int tid = threadIdx.x;
-  const int orow = tid >> 2, oc = (tid & 3) * 8;
-  float acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, lg = lane >> 4;
+  const int rb = blockIdx.y;
+  const int row0 = rb * 64 + wave * 16;
+  const int col0 = blockIdx.z * 16 * NCB;
   int q_lo = 0, q_hi = nb;
   if (tri) {  // inverse of a lower-triangular tile
     if (!TRANS) q_hi = (rb + 1) * 64;
     else q_lo = rb * 64;
   }
-  for (int q0 = q_lo; q0 < q_hi; q0 += 64) {
-    for (int e = tid; e < 64 * 64; e += 256) {
-      const int x = e >> 6, y = e & 63;
-      if (!TRANS)
-        Ms[x][y] = M[(int64_t)(rb * 64 + x) * nb + q0 + y];  // row x of the block, col q
-      else
-        Ms[y][x] = M[(int64_t)(q0 + x) * nb + rb * 64 + y];  // M^T: Ms[row][q] = M[q][row]
-    }
-    for (int e = tid; e < 64 * 32; e += 256) {
-      const int x = e >> 5, y = e & 31;
-      const int col = cc * 32 + y;
-      Vs[x][y] = (col < r) ? V[(int64_t)(q0 + x) * r + col] : 0.0f;
-    }
-    __syncthreads();
-#pragma unroll 8
-    for (int q = 0; q < 64; ++q) {
-      const float a = Ms[orow][q];
+  v4f acc[NCB];
 #pragma unroll
-      for (int e = 0; e < 8; ++e) acc[e] += a * Vs[q][oc + e];
+  for (int c = 0; c < NCB; ++c) acc[c] = (v4f){0.f, 0.f, 0.f, 0.f};
+  const int R = row0 + li;
+  for (int q = q_lo; q < q_hi; q += 16) {
+    const int kk = q + 4 * lg;
+    float a[4];
+    if (!TRANS) {
+      const float4 v = *(const float4 *)(M + (int64_t)R * nb + kk);
+      a[0] = v.x; a[1] = v.y; a[2] = v.z; a[3] = v.w;
+    } else {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) a[e] = M[(int64_t)(kk + e) * nb + R];
     }
-    __syncthreads();
+    float b[NCB][4];
+#pragma unroll
+    for (int c = 0; c < NCB; ++c) {
+      const int col = col0 + c * 16 + li;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) b[c][e] = (col < r) ? V[(int64_t)(kk + e) * r + col] : 0.f;
+    }
+#pragma unroll
+    for (int c = 0; c < NCB; ++c)
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        acc[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[e], b[c][e], acc[c], 0, 0, 0);
   }
-  float *o = Out + (int64_t)(rb * 64 + orow) * r;
 #pragma unroll
-  for (int e = 0; e < 8; ++e) {
-    const int col = cc * 32 + oc + e;
-    if (col < r) {
-      if (SUB) o[col] -= acc[e];
-      else o[col] = acc[e];
+  for (int c = 0; c < NCB; ++c) {
+    const int col = col0 + c * 16 + li;
+    if (col >= r) continue;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      float *o = Out + (int64_t)(row0 + 4 * lg + i) * r + col;
+      if (SUB) *o -= acc[c][i];
+      else *o = acc[c][i];
     }
+  }
+}
+
+template <bool TRANS, bool SUB>
+static void tri_launch(dim3 grid, hipStream_t s, const float *M, const float *V, float *O, int mode,
+                       int k, int nb, int r, int tri) {
+  const int ncb = (r + 15) / 16;
+  if (ncb <= 1) {
+    grid.z = 1;
+    hipLaunchKernelGGL((k_tri_apply<TRANS, SUB, 1>), grid, dim3(256), 0, s, M, V, O, mode, k, nb, r, tri);
+  } else if (ncb <= 2) {
+    grid.z = 1;
+    hipLaunchKernelGGL((k_tri_apply<TRANS, SUB, 2>), grid, dim3(256), 0, s, M, V, O, mode, k, nb, r, tri);
+  } else {
+    grid.z = (unsigned)((r + 63) / 64);
+    hipLaunchKernelGGL((k_tri_apply<TRANS, SUB, 4>), grid, dim3(256), 0, s, M, V, O, mode, k, nb, r, tri);
   }
 }
 
 // L Z = B: for k: Z_k = inv(L_kk) B_k; B_i -= L_ik Z_k (i > k).
 void launch_fwd_sweep(const float *Astore, const float *Linv, const TileLayout &L, int r, float *B,
                       float *Z, hipStream_t s) {
-  const int nb = L.nb, NT = L.nt, RB = nb / 64, CC = (r + 31) / 32;
+  const int nb = L.nb, NT = L.nt, RB = nb / 64;
   const int64_t te = (int64_t)nb * nb, vb = (int64_t)nb * r;
   for (int k = 0; k < NT; ++k) {
-    hipLaunchKernelGGL((k_tri_apply<false, false>), dim3(1, RB, CC), dim3(256), 0, s,
-                       Linv + k * te, B + k * vb, Z + k * vb, 0, k, nb, r, 1);
+    tri_launch<false, false>(dim3(1, RB, 1), s, Linv + k * te, B + k * vb, Z + k * vb, 0, k, nb, r, 1);
     if (NT - 1 - k > 0)
-      hipLaunchKernelGGL((k_tri_apply<false, true>), dim3(NT - 1 - k, RB, CC), dim3(256), 0, s,
-                         Astore, Z + k * vb, B, 1, k, nb, r, 0);
+      tri_launch<false, true>(dim3(NT - 1 - k, RB, 1), s, Astore, Z + k * vb, B, 1, k, nb, r, 0);
   }
 }
 
 // L^T X = Z: for k descending: X_k = inv(L_kk)^T Z_k; Z_j -= L_kj^T X_k (j < k).
 void launch_bwd_sweep(const float *Astore, const float *Linv, const TileLayout &L, int r, float *Z,
                       float *X, hipStream_t s) {
-  const int nb = L.nb, NT = L.nt, RB = nb / 64, CC = (r + 31) / 32;
+  const int nb = L.nb, NT = L.nt, RB = nb / 64;
   const int64_t te = (int64_t)nb * nb, vb = (int64_t)nb * r;
   for (int k = NT - 1; k >= 0; --k) {
-    hipLaunchKernelGGL((k_tri_apply<true, false>), dim3(1, RB, CC), dim3(256), 0, s,
-                       Linv + k * te, Z + k * vb, X + k * vb, 0, k, nb, r, 1);
-    if (k > 0)
-      hipLaunchKernelGGL((k_tri_apply<true, true>), dim3(k, RB, CC), dim3(256), 0, s, Astore,
-                         X + k * vb, Z, 2, k, nb, r, 0);
+    tri_launch<true, false>(dim3(1, RB, 1), s, Linv + k * te, Z + k * vb, X + k * vb, 0, k, nb, r, 1);
+    if (k > 0) tri_launch<true, true>(dim3(k, RB, 1), s, Astore, X + k * vb, Z, 2, k, nb, r, 0);
   }
 }
 
 // ---------------------------------------------------------------------------
-// FP64 residual R = Y - (K + lambda I) X over the packed lower tiles of int32
-// distances: row block (64 rows of tile row I) x 32 columns per workgroup;
-// tiles (I, J <= I) are read directly and tiles (J > I, I) transposed.
+// FP64 products with the Gaussian kernel recomputed from exact distances:
+// acc[16 rows x 16 NCB cols] += sum_j exp(-gamma d(row, j)) X[j, cols].
+// DMODE 0: d(row, j) = D[row * ldd + j] (row-major block)
+// DMODE 1: d(row, j) = D[j * ldd + row] (transposed block)
+template <int DMODE, int NCB>
+__device__ __forceinline__ void exp_mfma_block(const int32_t *__restrict__ D, int64_t ldd, int row,
+                                               int64_t j0, int64_t jn, const double *__restrict__ etab,
+                                               int64_t emax, const double *__restrict__ X, int r,
+                                               int64_t xrow0, int col0, int li, int lg,
+                                               v4d (&acc)[NCB]) {
+  for (int64_t q = j0; q < jn; q += 16) {
+    const int64_t kk = q + 4 * lg;
+    int32_t d[4];
+    if (DMODE == 0) {
+      const int4 v = *(const int4 *)(D + (int64_t)row * ldd + kk);
+      d[0] = v.x; d[1] = v.y; d[2] = v.z; d[3] = v.w;
+    } else {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) d[e] = D[(kk + e) * ldd + row];
+    }
+    double a[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) a[e] = etab[min((int64_t)max(d[e], 0), emax)];
+#pragma unroll
+    for (int c = 0; c < NCB; ++c) {
+      const int col = col0 + c * 16 + li;
+      double b[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        b[e] = (col < r) ? X[(xrow0 + kk - j0 + e) * r + col] : 0.0;
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[e], b[e], acc[c], 0, 0, 0);
+    }
+  }
+}
+
+// Residual R = Y - (K + lambda I) X over the packed lower tiles of int32
+// distances: 64 rows (4 waves x 16) of tile row I per workgroup; tiles
+// (I, J <= I) are read directly and tiles (J > I, I) transposed.
+template <int NCB>
 __global__ __launch_bounds__(256) void k_residual(const int32_t *__restrict__ D,
                                                   const double *__restrict__ etab,
                                                   int64_t etab_len, double lambda, int64_t n,
@@ -119,50 +185,32 @@ __global__ __launch_bounds__(256) void k_residual(const int32_t *__restrict__ D,
                                                   const double *__restrict__ X,
                                                   const double *__restrict__ Y,
                                                   double *__restrict__ R) {
-  __shared__ double Ks[64][65];
-  __shared__ double Xs[64][33];
-  const int64_t rowblk = blockIdx.x;
-  const int cc = blockIdx.y;
-  const int64_t g0 = rowblk * 64;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, lg = lane >> 4;
+  const int64_t g0 = (int64_t)blockIdx.x * 64 + wave * 16;
   const int I = (int)(g0 / nb), rloc = (int)(g0 % nb);
-  const int tid = threadIdx.x;
-  const int orow = tid >> 2, oc = (tid & 3) * 8;
+  const int col0 = blockIdx.y * 16 * NCB;
   const int64_t te = (int64_t)nb * nb;
-  double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  v4d acc[NCB];
+#pragma unroll
+  for (int c = 0; c < NCB; ++c) acc[c] = (v4d){0.0, 0.0, 0.0, 0.0};
   for (int J = 0; J < NT; ++J) {
-    const bool direct = (J <= I);
-    const int32_t *T = direct ? D + ((int64_t)I * (I + 1) / 2 + J) * te
-                              : D + ((int64_t)J * (J + 1) / 2 + I) * te;
-    for (int q0 = 0; q0 < nb; q0 += 64) {
-      for (int e = tid; e < 64 * 64; e += 256) {
-        const int x = e >> 6, y = e & 63;
-        if (direct)
-          Ks[x][y] = etab[min((int64_t)max(T[(int64_t)(rloc + x) * nb + q0 + y], 0), etab_len - 1)];
-        else
-          Ks[y][x] = etab[min((int64_t)max(T[(int64_t)(q0 + x) * nb + rloc + y], 0), etab_len - 1)];
-      }
-      for (int e = tid; e < 64 * 32; e += 256) {
-        const int x = e >> 5, y = e & 31;
-        const int col = cc * 32 + y;
-        Xs[x][y] = (col < r) ? X[((int64_t)J * nb + q0 + x) * r + col] : 0.0;
-      }
-      __syncthreads();
-#pragma unroll 8
-      for (int q = 0; q < 64; ++q) {
-        const double a = Ks[orow][q];
-#pragma unroll
-        for (int e = 0; e < 8; ++e) acc[e] += a * Xs[q][oc + e];
-      }
-      __syncthreads();
-    }
+    if (J <= I)
+      exp_mfma_block<0, NCB>(D + ((int64_t)I * (I + 1) / 2 + J) * te, nb, rloc + li, 0, nb, etab,
+                             etab_len - 1, X, r, (int64_t)J * nb, col0, li, lg, acc);
+    else
+      exp_mfma_block<1, NCB>(D + ((int64_t)J * (J + 1) / 2 + I) * te, nb, rloc + li, 0, nb, etab,
+                             etab_len - 1, X, r, (int64_t)J * nb, col0, li, lg, acc);
   }
-  const int64_t g = g0 + orow;
 #pragma unroll
-  for (int e = 0; e < 8; ++e) {
-    const int col = cc * 32 + oc + e;
-    if (col < r) {
+  for (int c = 0; c < NCB; ++c) {
+    const int col = col0 + c * 16 + li;
+    if (col >= r) continue;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int64_t g = g0 + 4 * lg + i;
       const int64_t off = g * r + col;
-      R[off] = (g < n) ? Y[off] - acc[e] - lambda * X[off] : 0.0;
+      R[off] = (g < n) ? Y[off] - acc[c][i] - lambda * X[off] : 0.0;
     }
   }
 }
@@ -170,55 +218,48 @@ __global__ __launch_bounds__(256) void k_residual(const int32_t *__restrict__ D,
 void launch_residual(const int32_t *D, const double *etab, int64_t etab_len, double lambda,
                      const TileLayout &L, int r, const double *X, const double *Y, double *R,
                      hipStream_t s) {
-  const unsigned rb = (unsigned)(L.np / 64), cc = (unsigned)((r + 31) / 32);
-  hipLaunchKernelGGL(k_residual, dim3(rb, cc), dim3(256), 0, s, D, etab, etab_len, lambda, L.n, L.nb,
-                     L.nt, r, X, Y, R);
+  const unsigned rb = (unsigned)(L.np / 64);
+  const int ncb = (r + 15) / 16;
+  if (ncb <= 1)
+    hipLaunchKernelGGL(k_residual<1>, dim3(rb, 1), dim3(256), 0, s, D, etab, etab_len, lambda, L.n,
+                       L.nb, L.nt, r, X, Y, R);
+  else if (ncb <= 2)
+    hipLaunchKernelGGL(k_residual<2>, dim3(rb, 1), dim3(256), 0, s, D, etab, etab_len, lambda, L.n,
+                       L.nb, L.nt, r, X, Y, R);
+  else
+    hipLaunchKernelGGL(k_residual<4>, dim3(rb, (unsigned)((r + 63) / 64)), dim3(256), 0, s, D,
+                       etab, etab_len, lambda, L.n, L.nb, L.nt, r, X, Y, R);
 }
 
 // Predict: P[i, :] = sum_j exp(-gamma Dt[i, j]) X[j, :] in FP64 for a block of
-// test rows (Dt row-major rows x cols, X row-major cols x r).  Output written
-// column-major into P (leading dimension ldp).
+// test rows (Dt row-major rows x cols, cols a multiple of 16; X row-major
+// cols x r).  Output written column-major into P (leading dimension ldp).
+template <int NCB>
 __global__ __launch_bounds__(256) void k_predict_apply(const int32_t *__restrict__ Dt, int64_t rows,
                                                        int64_t cols, int64_t ldd,
                                                        const double *__restrict__ etab,
                                                        int64_t etab_len,
                                                        const double *__restrict__ X, int r,
                                                        double *__restrict__ P, int64_t ldp) {
-  __shared__ double Ks[64][65];
-  __shared__ double Xs[64][33];
-  const int64_t g0 = (int64_t)blockIdx.x * 64;
-  const int cc = blockIdx.y;
-  const int tid = threadIdx.x;
-  const int orow = tid >> 2, oc = (tid & 3) * 8;
-  double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  for (int64_t q0 = 0; q0 < cols; q0 += 64) {
-    for (int e = tid; e < 64 * 64; e += 256) {
-      const int x = e >> 6, y = e & 63;
-      const int64_t gi = g0 + x, gj = q0 + y;
-      Ks[x][y] = (gi < rows && gj < cols)
-                     ? etab[min((int64_t)max(Dt[gi * ldd + gj], 0), etab_len - 1)]
-                     : 0.0;
-    }
-    for (int e = tid; e < 64 * 32; e += 256) {
-      const int x = e >> 5, y = e & 31;
-      const int col = cc * 32 + y;
-      Xs[x][y] = (col < r && q0 + x < cols) ? X[(q0 + x) * r + col] : 0.0;
-    }
-    __syncthreads();
-#pragma unroll 8
-    for (int q = 0; q < 64; ++q) {
-      const double a = Ks[orow][q];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, lg = lane >> 4;
+  const int64_t g0 = (int64_t)blockIdx.x * 64 + wave * 16;
+  const int col0 = blockIdx.y * 16 * NCB;
+  v4d acc[NCB];
 #pragma unroll
-      for (int e = 0; e < 8; ++e) acc[e] += a * Xs[q][oc + e];
-    }
-    __syncthreads();
-  }
-  const int64_t g = g0 + orow;
-  if (g < rows) {
+  for (int c = 0; c < NCB; ++c) acc[c] = (v4d){0.0, 0.0, 0.0, 0.0};
+  // rows past the end read row rows-1 (valid memory); their outputs are dropped
+  const int64_t arow = min(g0 + li, rows - 1);
+  exp_mfma_block<0, NCB>(Dt + arow * ldd, ldd, 0, 0, cols, etab, etab_len - 1, X, r, 0, col0, li,
+                         lg, acc);
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      const int col = cc * 32 + oc + e;
-      if (col < r) P[(int64_t)col * ldp + g] = acc[e];
+  for (int c = 0; c < NCB; ++c) {
+    const int col = col0 + c * 16 + li;
+    if (col >= r) continue;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int64_t g = g0 + 4 * lg + i;
+      if (g < rows) P[(int64_t)col * ldp + g] = acc[c][i];
     }
   }
 }
@@ -226,9 +267,17 @@ __global__ __launch_bounds__(256) void k_predict_apply(const int32_t *__restrict
 void launch_predict_apply(const int32_t *Dt, int64_t rows, int64_t cols, int64_t ldd,
                           const double *etab, int64_t etab_len, const double *X, int r, double *P,
                           int64_t ldp, hipStream_t s) {
-  const unsigned rb = (unsigned)((rows + 63) / 64), cc = (unsigned)((r + 31) / 32);
-  hipLaunchKernelGGL(k_predict_apply, dim3(rb, cc), dim3(256), 0, s, Dt, rows, cols, ldd, etab,
-                     etab_len, X, r, P, ldp);
+  const unsigned rb = (unsigned)((rows + 63) / 64);
+  const int ncb = (r + 15) / 16;
+  if (ncb <= 1)
+    hipLaunchKernelGGL(k_predict_apply<1>, dim3(rb, 1), dim3(256), 0, s, Dt, rows, cols, ldd, etab,
+                       etab_len, X, r, P, ldp);
+  else if (ncb <= 2)
+    hipLaunchKernelGGL(k_predict_apply<2>, dim3(rb, 1), dim3(256), 0, s, Dt, rows, cols, ldd, etab,
+                       etab_len, X, r, P, ldp);
+  else
+    hipLaunchKernelGGL(k_predict_apply<4>, dim3(rb, (unsigned)((r + 63) / 64)), dim3(256), 0, s,
+                       Dt, rows, cols, ldd, etab, etab_len, X, r, P, ldp);
 }
 
 // ---------------------------------------------------------------------------
@@ -297,7 +346,7 @@ __global__ __launch_bounds__(256) void k_col_norms(const double *__restrict__ A,
     const double v = A[i * r + c];
     s += v * v;
   }
-  s = block_sum_256(s, sh);
+  s = block_sum<4>(s, sh);
   if (threadIdx.x == 0) out[c] = s;
 }
 
