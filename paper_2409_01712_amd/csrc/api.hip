@@ -33,6 +33,9 @@ struct krr_context_s {
   // live kernel/factor handles; krr_destroy defers the free until they are released
   int64_t live = 0;
   bool destroy_pending = false;
+  // second stream and events for the factorization's lookahead
+  hipStream_t aux = nullptr;
+  hipEvent_t ev_panel = nullptr, ev_update = nullptr;
 };
 
 struct krr_kernel_s {
@@ -161,17 +164,19 @@ hipEvent_t take_event(krr_context c) {
 // Brackets the launches of one stage with events when timing is enabled.
 struct Stage {
   krr_context c;
+  hipStream_t st;
   int64_t idx = -1;
-  Stage(krr_context ctx, int stage) : c(ctx) {
+  Stage(krr_context ctx, int stage, hipStream_t stream = nullptr) : c(ctx) {
+    st = stream ? stream : c->stream;
     if (!c->timing) return;
     TimerRec r{stage, take_event(c), take_event(c)};
     if (!r.a || !r.b) return;
-    if (hipEventRecord(r.a, c->stream) != hipSuccess) return;
+    if (hipEventRecord(r.a, st) != hipSuccess) return;
     c->recs.push_back(r);
     idx = (int64_t)c->recs.size() - 1;
   }
   ~Stage() {
-    if (idx >= 0) (void)hipEventRecord(c->recs[idx].b, c->stream);
+    if (idx >= 0) (void)hipEventRecord(c->recs[idx].b, st);
   }
 };
 
@@ -270,7 +275,22 @@ static void context_free(krr_context ctx) {
   (void)hipStreamSynchronize(ctx->stream);
   timers_drain(ctx);
   for (hipEvent_t e : ctx->pool) (void)hipEventDestroy(e);
+  if (ctx->aux) {
+    (void)hipStreamSynchronize(ctx->aux);
+    (void)hipStreamDestroy(ctx->aux);
+  }
+  if (ctx->ev_panel) (void)hipEventDestroy(ctx->ev_panel);
+  if (ctx->ev_update) (void)hipEventDestroy(ctx->ev_update);
   delete ctx;
+}
+
+// The lookahead stream (default priority) and its two ordering events.
+static krr_status context_aux(krr_context ctx) {
+  if (ctx->aux) return KRR_SUCCESS;
+  HIPCHK(hipStreamCreateWithFlags(&ctx->aux, hipStreamNonBlocking));
+  HIPCHK(hipEventCreateWithFlags(&ctx->ev_panel, hipEventDisableTiming));
+  HIPCHK(hipEventCreateWithFlags(&ctx->ev_update, hipEventDisableTiming));
+  return KRR_SUCCESS;
 }
 
 // A handle was released: free the context if it was destroyed while handles lived.
@@ -421,14 +441,16 @@ static void factor_work_free(krr_context c, FactorWork &w, const TileLayout &L) 
   dfree(c, w.W64, te * 8);
   dfree(c, w.Winv64, te * 8);
   dfree(c, w.Dinv64, (L.nb / 64) * 64 * 64 * 8);
-  dfree(c, w.P32, pt * te * 4);
-  dfree(c, w.P16, pt * te * 2);
-  dfree(c, w.P8, pt * te);
+  for (PanelBuf &pb : w.pb) {
+    dfree(c, pb.P32, pt * te * 4);
+    dfree(c, pb.P16, pt * te * 2);
+    dfree(c, pb.P8, pt * te);
+    dfree(c, pb.pnorm, pt * 4);
+    dfree(c, pb.pscale16, pt * 4);
+    dfree(c, pb.pscale8, pt * 4);
+  }
   dfree(c, w.pnorm_part, pt * parts * 8);
   dfree(c, w.pmax_part, pt * parts * 4);
-  dfree(c, w.pnorm, pt * 4);
-  dfree(c, w.pscale16, pt * 4);
-  dfree(c, w.pscale8, pt * 4);
   dfree(c, w.flag, 4);
   dfree(c, w.counts, 3 * 8);
   w = FactorWork();
@@ -447,14 +469,16 @@ static krr_status factor_work_alloc(krr_context c, FactorWork &w, const TileLayo
   WA(w.W64, te * 8);
   WA(w.Winv64, te * 8);
   WA(w.Dinv64, (L.nb / 64) * 64 * 64 * 8);
-  WA(w.P32, pt * te * 4);
-  WA(w.P16, need16 ? pt * te * 2 : 16);
-  WA(w.P8, need8 ? pt * te : 16);
+  for (PanelBuf &pb : w.pb) {
+    WA(pb.P32, pt * te * 4);
+    WA(pb.P16, need16 ? pt * te * 2 : 16);
+    WA(pb.P8, need8 ? pt * te : 16);
+    WA(pb.pnorm, pt * 4);
+    WA(pb.pscale16, pt * 4);
+    WA(pb.pscale8, pt * 4);
+  }
   WA(w.pnorm_part, pt * parts * 8);
   WA(w.pmax_part, pt * parts * 4);
-  WA(w.pnorm, pt * 4);
-  WA(w.pscale16, pt * 4);
-  WA(w.pscale8, pt * 4);
   WA(w.flag, 4);
   WA(w.counts, 3 * 8);
 #undef WA
@@ -497,6 +521,9 @@ krr_status krr_factor(krr_context ctx, krr_kernel K, const krr_precision_policy 
   }
   int mode = p.mode;
   bool diag64 = p.diag_fp64 != 0;
+  const char *la_env = getenv("KRR_NO_LOOKAHEAD");
+  const bool lookahead = !(la_env && atoi(la_env) != 0);
+  if (lookahead) CHK(context_aux(ctx));
 
   krr_factorization F = new krr_factor_s();
   F->ctx = ctx;
@@ -535,24 +562,55 @@ krr_status krr_factor(krr_context ctx, krr_kernel K, const krr_precision_policy 
       up.fixed_prec = p.fixed_prec;
       up.thr = p.eps * K->norm_a / L.nt;
       const bool need16 = allow16 != 0, need8 = allow8 != 0;
-      for (int k = 0; k < L.nt; ++k) {
-        float *Akk = F->Lst + TileLayout::tri(k, k) * L.tile_elems();
+      const int64_t te = L.tile_elems();
+      auto panel = [&](int k, hipStream_t ss) {  // POTRF, TRSM and operand copies of panel k
+        float *Akk = F->Lst + TileLayout::tri(k, k) * te;
         {
-          Stage t(ctx, KRR_STAGE_POTRF);
-          launch_potrf_tile(Akk, F->Linv + (int64_t)k * L.tile_elems(), k, L, diag64, w, s);
+          Stage t(ctx, KRR_STAGE_POTRF, ss);
+          launch_potrf_tile(Akk, F->Linv + (int64_t)k * te, k, L, diag64, w, ss);
         }
         if (k + 1 < L.nt) {
           {
-            Stage t(ctx, KRR_STAGE_TRSM);
-            launch_trsm_panel(F->Lst, F->Linv + (int64_t)k * L.tile_elems(), k, L, w, s);
+            Stage t(ctx, KRR_STAGE_TRSM, ss);
+            launch_trsm_panel(F->Lst, F->Linv + (int64_t)k * te, k, L, w, w.pb[k & 1], ss);
           }
-          {
-            Stage t(ctx, KRR_STAGE_CONVERT);
-            launch_convert_panel(F->Lst, k, L, w, need16, need8, s);
-          }
-          Stage t(ctx, KRR_STAGE_UPDATE);
-          launch_update(F->Lst, k, L, up, w, dmap, s);
+          Stage t(ctx, KRR_STAGE_CONVERT, ss);
+          launch_convert_panel(F->Lst, k, L, w, w.pb[k & 1], need16, need8, ss);
         }
+      };
+      if (!lookahead) {
+        for (int k = 0; k < L.nt; ++k) {
+          panel(k, s);
+          if (k + 1 < L.nt) {
+            Stage t(ctx, KRR_STAGE_UPDATE);
+            launch_update(F->Lst, k, 0, L, up, w, w.pb[k & 1], dmap, s);
+          }
+        }
+      } else {
+        // Lookahead: while the aux stream applies panel k to block columns
+        // >= k+2, the main stream updates block column k+1 and produces
+        // panel k+1, which is then ready when the aux stream gets to it.
+        hipStream_t s2 = ctx->aux;
+        panel(0, s);
+        if (hipEventRecord(ctx->ev_panel, s) != hipSuccess) { st = KRR_ERROR_HIP; break; }
+        bool ok = true;
+        for (int k = 0; k + 1 < L.nt && ok; ++k) {
+          ok = hipStreamWaitEvent(s2, ctx->ev_panel, 0) == hipSuccess;
+          {
+            Stage t(ctx, KRR_STAGE_UPDATE, s2);
+            launch_update(F->Lst, k, 2, L, up, w, w.pb[k & 1], dmap, s2);
+          }
+          if (k >= 1) ok = ok && hipStreamWaitEvent(s, ctx->ev_update, 0) == hipSuccess;
+          ok = ok && hipEventRecord(ctx->ev_update, s2) == hipSuccess;
+          {
+            Stage t(ctx, KRR_STAGE_UPDATE);
+            launch_update(F->Lst, k, 1, L, up, w, w.pb[k & 1], dmap, s);
+          }
+          panel(k + 1, s);
+          ok = ok && hipEventRecord(ctx->ev_panel, s) == hipSuccess;
+        }
+        if (L.nt > 1) ok = ok && hipStreamWaitEvent(s, ctx->ev_update, 0) == hipSuccess;
+        if (!ok) { st = KRR_ERROR_HIP; break; }
       }
       if ((st = launch_ok()) != KRR_SUCCESS) break;
       int32_t hflag = 0;

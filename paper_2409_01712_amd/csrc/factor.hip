@@ -311,12 +311,12 @@ __global__ __launch_bounds__(256) void k_trsm_panel(const float *__restrict__ As
 }
 
 void launch_trsm_panel(const float *Astore, const float *Linv, int k, const TileLayout &L,
-                       FactorWork &w, hipStream_t s) {
+                       FactorWork &w, const PanelBuf &pb, hipStream_t s) {
   const int SB = L.nb / UB;
   const int64_t tiles = L.nt - 1 - k;
   if (tiles <= 0) return;
   hipLaunchKernelGGL(k_trsm_panel, dim3((unsigned)(tiles * SB * SB)), dim3(256), 0, s, Astore,
-                     Linv, k, L.nb, SB, w.P32, w.pnorm_part, w.pmax_part);
+                     Linv, k, L.nb, SB, pb.P32, w.pnorm_part, w.pmax_part);
 }
 
 // Panel conversion: reduce each tile's partial norms (fixed order), pick the
@@ -368,15 +368,15 @@ __global__ __launch_bounds__(256) void k_convert_panel(
   }
 }
 
-void launch_convert_panel(float *Astore, int k, const TileLayout &L, FactorWork &w, bool need16,
-                          bool need8, hipStream_t s) {
+void launch_convert_panel(float *Astore, int k, const TileLayout &L, FactorWork &w,
+                          const PanelBuf &pb, bool need16, bool need8, hipStream_t s) {
   const int64_t tiles = L.nt - 1 - k;
   if (tiles <= 0) return;
   const int chunks = (int)((int64_t)L.nb * L.nb / CONV_CHUNK);
   const int SB = L.nb / UB;
-  hipLaunchKernelGGL(k_convert_panel, dim3((unsigned)(tiles * chunks)), dim3(256), 0, s, w.P32,
-                     Astore, w.P16, w.P8, w.pnorm_part, w.pmax_part, SB * SB, w.pnorm, w.pscale16,
-                     w.pscale8, k, L.nb, chunks, need16 ? 1 : 0, need8 ? 1 : 0);
+  hipLaunchKernelGGL(k_convert_panel, dim3((unsigned)(tiles * chunks)), dim3(256), 0, s, pb.P32,
+                     Astore, pb.P16, pb.P8, w.pnorm_part, w.pmax_part, SB * SB, pb.pnorm,
+                     pb.pscale16, pb.pscale8, k, L.nb, chunks, need16 ? 1 : 0, need8 ? 1 : 0);
 }
 
 // Trailing update A_ij -= L_ik L_jk^T over all k < j <= i < NT, one 128 x 128
@@ -388,18 +388,26 @@ void launch_convert_panel(float *Astore, int k, const TileLayout &L, FactorWork 
 __global__ __launch_bounds__(256) void k_update(
     float *__restrict__ Astore, const float *__restrict__ P32, const _Float16 *__restrict__ P16,
     const uint8_t *__restrict__ P8, const float *__restrict__ pnorm,
-    const float *__restrict__ pscale16, const float *__restrict__ pscale8, int k, int nb, int SB,
-    int mode, int allow16, int allow8, int high_panels, int fixed_prec, double thr,
-    unsigned long long *counts, uint8_t *pmap, int64_t ntiles_all) {
+    const float *__restrict__ pscale16, const float *__restrict__ pscale8, int k, int base,
+    int col_only, int nb, int SB, int mode, int allow16, int allow8, int high_panels,
+    int fixed_prec, double thr, unsigned long long *counts, uint8_t *pmap, int64_t ntiles_all) {
   typedef UpdShape S;
   __shared__ __attribute__((aligned(16))) uint8_t lds[S::LDS_BYTES];
   const int64_t bid = xcd_remap(blockIdx.x, gridDim.x);
   const int nsub = SB * SB;
   const int sub = (int)(bid % nsub);
   const int64_t tt = bid / nsub;
-  int a, b;
-  tri_decode(tt, a, b);
-  const int64_t i = k + 1 + a, j = k + 1 + b;
+  int64_t i, j;
+  if (col_only) {
+    i = base + tt;
+    j = base;
+  } else {
+    int ta, tb;
+    tri_decode(tt, ta, tb);
+    i = base + ta;
+    j = base + tb;
+  }
+  const int64_t a = i - k - 1, b = j - k - 1;  // panel tiles of the two operands
   const int si = sub / SB, sj = sub % SB;
   const int64_t te = (int64_t)nb * nb;
 
@@ -453,16 +461,19 @@ __global__ __launch_bounds__(256) void k_update(
   }
 }
 
-void launch_update(float *Astore, int k, const TileLayout &L, const UpdatePolicy &pol,
-                   FactorWork &w, uint8_t *pmap, hipStream_t s) {
-  const int64_t T = L.nt - 1 - k;
+void launch_update(float *Astore, int k, int which, const TileLayout &L, const UpdatePolicy &pol,
+                   FactorWork &w, const PanelBuf &pb, uint8_t *pmap, hipStream_t s) {
+  const int base = (which == 2) ? k + 2 : k + 1;
+  const int64_t T = L.nt - base;
   if (T <= 0) return;
   const int SB = L.nb / UB;
-  const int64_t blocks = T * (T + 1) / 2 * SB * SB;
-  hipLaunchKernelGGL(k_update, dim3((unsigned)blocks), dim3(256), 0, s, Astore, w.P32, w.P16,
-                     w.P8, w.pnorm, w.pscale16, w.pscale8, k, L.nb, SB, pol.mode, pol.allow16,
-                     pol.allow8, pol.high_panels, pol.fixed_prec, pol.thr, w.counts, pmap,
-                     L.ntiles());
+  const int col_only = (which == 1) ? 1 : 0;
+  const int64_t tiles = col_only ? T : T * (T + 1) / 2;
+  const int64_t blocks = tiles * SB * SB;
+  hipLaunchKernelGGL(k_update, dim3((unsigned)blocks), dim3(256), 0, s, Astore, pb.P32, pb.P16,
+                     pb.P8, pb.pnorm, pb.pscale16, pb.pscale8, k, base, col_only, L.nb, SB, pol.mode,
+                     pol.allow16, pol.allow8, pol.high_panels, pol.fixed_prec, pol.thr, w.counts,
+                     pmap, L.ntiles());
 }
 
 }  // namespace krr

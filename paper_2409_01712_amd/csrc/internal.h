@@ -46,30 +46,37 @@ struct UpdatePolicy {
   int fixed_prec;
   double thr;        // eps * ||A||_F / NT
 };
+// Operand copies of one panel (tiles k+1 .. nt-1 of block column k).  Two
+// are kept so that panel k+1 can be produced while panel k is still read.
+struct PanelBuf {
+  float *P32 = nullptr;       // FP32 L_ik
+  _Float16 *P16 = nullptr;    // scaled FP16 copies
+  uint8_t *P8 = nullptr;      // scaled FP8 E4M3 copies
+  float *pnorm = nullptr;     // ||L_ik||_F
+  float *pscale16 = nullptr;  // power-of-two scales
+  float *pscale8 = nullptr;
+};
 // Workspace for the factorization, sized for nt tiles of nb.
 struct FactorWork {
   double *W64 = nullptr;     // nb x nb FP64 (or FP32) diagonal workspace
   double *Winv64 = nullptr;  // nb x nb
   double *Dinv64 = nullptr;  // (nb/64) blocks of 64 x 64
-  float *P32 = nullptr;      // (nt-1) panel tiles FP32
-  _Float16 *P16 = nullptr;   // (nt-1) panel tiles FP16
-  uint8_t *P8 = nullptr;     // (nt-1) panel tiles FP8
+  PanelBuf pb[2];
   double *pnorm_part = nullptr;  // (nt-1) * parts
   float *pmax_part = nullptr;    // (nt-1) * parts
-  float *pnorm = nullptr;        // (nt-1)
-  float *pscale16 = nullptr;     // (nt-1)
-  float *pscale8 = nullptr;      // (nt-1)
   int32_t *flag = nullptr;       // breakdown column + 1 (0 = none)
   unsigned long long *counts = nullptr;  // [3] updates per precision
 };
 void launch_potrf_tile(float *Akk, float *Linv, int k, const TileLayout &L, bool fp64,
                        FactorWork &w, hipStream_t s);
 void launch_trsm_panel(const float *Astore, const float *Linv, int k, const TileLayout &L,
-                       FactorWork &w, hipStream_t s);
-void launch_convert_panel(float *Astore, int k, const TileLayout &L, FactorWork &w, bool need16,
-                          bool need8, hipStream_t s);
-void launch_update(float *Astore, int k, const TileLayout &L, const UpdatePolicy &pol,
-                   FactorWork &w, uint8_t *pmap, hipStream_t s);
+                       FactorWork &w, const PanelBuf &pb, hipStream_t s);
+void launch_convert_panel(float *Astore, int k, const TileLayout &L, FactorWork &w,
+                          const PanelBuf &pb, bool need16, bool need8, hipStream_t s);
+// Trailing update by panel k of: which = 0 all tiles (i, j), k < j <= i;
+// which = 1 block column k+1 only; which = 2 block columns j >= k+2.
+void launch_update(float *Astore, int k, int which, const TileLayout &L, const UpdatePolicy &pol,
+                   FactorWork &w, const PanelBuf &pb, uint8_t *pmap, hipStream_t s);
 
 // ---- solve.hip ----
 // Internal right-hand sides are row-major np x r.
