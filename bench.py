@@ -163,11 +163,14 @@ def main():
         for i in range(args.warmup):
             step(plain, no_refine)
         torch.cuda.synchronize()
+        krr.krr_timers_enable(ctx, True)
         t0 = time.perf_counter()
         for i in range(args.plain_steps):
             Xp, pinfo, _, _ = step(plain, no_refine)
         torch.cuda.synchronize()
         pdt = (time.perf_counter() - t0) / args.plain_steps
+        pstages = krr.krr_timers_read(ctx)
+        krr.krr_timers_enable(ctx, False)
         # accuracy of the plain path, measured by the FP64 residual bound
         K = krr.krr_build_kernel(ctx, G, w.gamma, w.lam)
         F = krr.krr_factor(ctx, K, plain)
@@ -175,7 +178,9 @@ def main():
         F.release()
         K.release()
         out["plain_fp32"] = {"value": ops / pdt, "ms_per_step": pdt * 1e3,
-                             "fwd_err_bound": pin.fwd_err_bound}
+                             "fwd_err_bound": pin.fwd_err_bound,
+                             "stages_ms_per_step": {k: round(v[0] / args.plain_steps, 4)
+                                                    for k, v in pstages.items() if v[1]}}
         out["speedup_vs_plain_fp32"] = pdt / dt
 
     if not args.no_cpu:

@@ -201,6 +201,9 @@ krr_status krr_kernel_copy_matrix(krr_kernel K, int64_t i0, int64_t j0, int64_t 
  * above the diagonal) into dst (row-major, device memory). */
 krr_status krr_factor_copy_l(krr_factorization F, int64_t i0, int64_t j0, int64_t rows, int64_t cols,
                              float *dst, int64_t ld);
+/* Test hook: encode n FP32 values (device) to OCP FP8 E4M3FN bytes (device)
+ * with the factorization's round-to-nearest-even, saturating encoder. */
+krr_status krr_debug_encode_fp8(krr_context ctx, const float *x, int64_t n, uint8_t *out);
 /* Per-tile FP64 Frobenius norms of K + lambda*I, NT(NT+1)/2 values in
  * packed lower-triangle tile order, copied to HOST memory. */
 krr_status krr_kernel_tile_norms(krr_kernel K, double *host_dst, int64_t count);

@@ -80,6 +80,7 @@ _SIGS = [
     ("krr_factor_copy_l", _I, [_P, _I64, _I64, _I64, _I64, _P, _I64]),
     ("krr_kernel_tile_norms", _I, [_P, _P, _I64]),
     ("krr_factor_precision_map", _I, [_P, _P, _I64]),
+    ("krr_debug_encode_fp8", _I, [_P, _P, _I64, _P]),
     ("krr_timers_enable", _I, [_P, ctypes.c_int32]),
     ("krr_timers_read", _I, [_P, _P, _P, ctypes.c_int32]),
     ("krr_stage_name", ctypes.c_char_p, [ctypes.c_int32]),
@@ -334,6 +335,16 @@ def krr_predict(ctx: Context, K: Kernel, T, X):
     _check(load().krr_predict(ctx.handle, K.handle, _ptr(T), nt, T.stride(0), _ptr(Xc), r, K.n,
                               _ptr(P), nt), "krr_predict")
     return P
+
+
+def krr_debug_encode_fp8(ctx: Context, x):
+    """FP8 E4M3FN bytes of a float32 GPU tensor, from the library's encoder."""
+    import torch
+    x = x.to(torch.float32).contiguous()
+    out = torch.empty(x.shape, dtype=torch.uint8, device=x.device)
+    _check(load().krr_debug_encode_fp8(ctx.handle, _ptr(x), x.numel(), _ptr(out)),
+           "krr_debug_encode_fp8")
+    return out
 
 
 def krr_kernel_copy_distances(K: Kernel, i0: int, j0: int, rows: int, cols: int):

@@ -441,13 +441,12 @@ static void factor_work_free(krr_context c, FactorWork &w, const TileLayout &L) 
   dfree(c, w.W64, te * 8);
   dfree(c, w.Winv64, te * 8);
   dfree(c, w.Dinv64, (L.nb / 64) * 64 * 64 * 8);
-  for (PanelBuf &pb : w.pb) {
+  for (PanelBuf &pb : w.pb) {  // unallocated slots hold null pointers
     dfree(c, pb.P32, pt * te * 4);
     dfree(c, pb.P16, pt * te * 2);
     dfree(c, pb.P8, pt * te);
     dfree(c, pb.pnorm, pt * 4);
-    dfree(c, pb.pscale16, pt * 4);
-    dfree(c, pb.pscale8, pt * 4);
+    dfree(c, pb.pexp8, pt * 4);
   }
   dfree(c, w.pnorm_part, pt * parts * 8);
   dfree(c, w.pmax_part, pt * parts * 4);
@@ -457,7 +456,7 @@ static void factor_work_free(krr_context c, FactorWork &w, const TileLayout &L) 
 }
 
 static krr_status factor_work_alloc(krr_context c, FactorWork &w, const TileLayout &L,
-                                    bool need16, bool need8) {
+                                    bool need16, bool need8, int slots) {
   const int64_t te = L.tile_elems(), pt = std::max(L.nt - 1, 1);
   const int sb = L.nb / 128, parts = sb * sb;
   krr_status st;
@@ -469,13 +468,13 @@ static krr_status factor_work_alloc(krr_context c, FactorWork &w, const TileLayo
   WA(w.W64, te * 8);
   WA(w.Winv64, te * 8);
   WA(w.Dinv64, (L.nb / 64) * 64 * 64 * 8);
-  for (PanelBuf &pb : w.pb) {
+  for (int q = 0; q < slots; ++q) {
+    PanelBuf &pb = w.pb[q];
     WA(pb.P32, pt * te * 4);
     WA(pb.P16, need16 ? pt * te * 2 : 16);
     WA(pb.P8, need8 ? pt * te : 16);
     WA(pb.pnorm, pt * 4);
-    WA(pb.pscale16, pt * 4);
-    WA(pb.pscale8, pt * 4);
+    WA(pb.pexp8, pt * 4);
   }
   WA(w.pnorm_part, pt * parts * 8);
   WA(w.pmax_part, pt * parts * 4);
@@ -523,6 +522,8 @@ krr_status krr_factor(krr_context ctx, krr_kernel K, const krr_precision_policy 
   bool diag64 = p.diag_fp64 != 0;
   const char *la_env = getenv("KRR_NO_LOOKAHEAD");
   const bool lookahead = !(la_env && atoi(la_env) != 0);
+  const char *g_env = getenv("KRR_GROUP");
+  const int g = std::max(1, std::min(KRR_MAX_GROUP, g_env ? atoi(g_env) : 4));
   if (lookahead) CHK(context_aux(ctx));
 
   krr_factorization F = new krr_factor_s();
@@ -546,7 +547,8 @@ krr_status krr_factor(krr_context ctx, krr_kernel K, const krr_precision_policy 
       launch_expand_tiles(K->D, K->etab, K->etab_len, K->lambda, L, F->Lst, s);
     }
     if ((st = dalloc_t(ctx, &F->Linv, (int64_t)L.nt * L.tile_elems())) != KRR_SUCCESS) break;
-    if ((st = factor_work_alloc(ctx, w, L, allow16 || p.allow_promotion, allow8)) != KRR_SUCCESS)
+    if ((st = factor_work_alloc(ctx, w, L, allow16 || p.allow_promotion, allow8,
+                                std::min(2 * g, 2 * KRR_MAX_GROUP))) != KRR_SUCCESS)
       break;
     if (mapsz && (st = dalloc_t(ctx, &dmap, mapsz)) != KRR_SUCCESS) break;
     for (int attempt = 0;; ++attempt) {
@@ -563,6 +565,10 @@ krr_status krr_factor(krr_context ctx, krr_kernel K, const krr_precision_policy 
       up.thr = p.eps * K->norm_a / L.nt;
       const bool need16 = allow16 != 0, need8 = allow8 != 0;
       const int64_t te = L.tile_elems();
+      // Panels are produced in groups of g block columns.  Inside a group
+      // each panel updates the group's later columns right away; everything
+      // to the right of the group gets one update by the whole group (K = g nb).
+      auto slot = [&](int k) -> PanelBuf & { return w.pb[((k / g) & 1) * g + (k % g)]; };
       auto panel = [&](int k, hipStream_t ss) {  // POTRF, TRSM and operand copies of panel k
         float *Akk = F->Lst + TileLayout::tri(k, k) * te;
         {
@@ -572,44 +578,56 @@ krr_status krr_factor(krr_context ctx, krr_kernel K, const krr_precision_policy 
         if (k + 1 < L.nt) {
           {
             Stage t(ctx, KRR_STAGE_TRSM, ss);
-            launch_trsm_panel(F->Lst, F->Linv + (int64_t)k * te, k, L, w, w.pb[k & 1], ss);
+            launch_trsm_panel(F->Lst, F->Linv + (int64_t)k * te, k, L, w, slot(k), ss);
           }
           Stage t(ctx, KRR_STAGE_CONVERT, ss);
-          launch_convert_panel(F->Lst, k, L, w, w.pb[k & 1], need16, need8, ss);
+          launch_convert_panel(F->Lst, k, L, w, slot(k), need16, need8, ss);
         }
       };
-      if (!lookahead) {
-        for (int k = 0; k < L.nt; ++k) {
-          panel(k, s);
-          if (k + 1 < L.nt) {
-            Stage t(ctx, KRR_STAGE_UPDATE);
-            launch_update(F->Lst, k, 0, L, up, w, w.pb[k & 1], dmap, s);
+      auto factor_group = [&](int G0, hipStream_t ss) {
+        const int gend = std::min(G0 + g, L.nt);
+        for (int k = G0; k < gend; ++k) {
+          panel(k, ss);
+          if (k + 1 < gend) {
+            const PanelBuf *one[1] = {&slot(k)};
+            Stage t(ctx, KRR_STAGE_UPDATE, ss);
+            launch_update(F->Lst, k, 1, k + 1, gend - 1, L, up, w, one, dmap, ss);
           }
+        }
+      };
+      auto group_update = [&](int G0, int jlo, int jhi, hipStream_t ss) {
+        const int npan = std::min(g, L.nt - G0);
+        if (jlo > jhi || jlo >= L.nt) return;
+        const PanelBuf *ps[KRR_MAX_GROUP];
+        for (int q = 0; q < npan; ++q) ps[q] = &slot(G0 + q);
+        Stage t(ctx, KRR_STAGE_UPDATE, ss);
+        launch_update(F->Lst, G0, npan, jlo, jhi, L, up, w, ps, dmap, ss);
+      };
+      if (!lookahead) {
+        for (int G0 = 0; G0 < L.nt; G0 += g) {
+          factor_group(G0, s);
+          group_update(G0, G0 + g, L.nt - 1, s);
         }
       } else {
-        // Lookahead: while the aux stream applies panel k to block columns
-        // >= k+2, the main stream updates block column k+1 and produces
-        // panel k+1, which is then ready when the aux stream gets to it.
+        // Lookahead: while the aux stream applies group G to the columns
+        // beyond the next group, the main stream updates the next group's
+        // columns and factors it, so its panels are ready in time.
         hipStream_t s2 = ctx->aux;
-        panel(0, s);
-        if (hipEventRecord(ctx->ev_panel, s) != hipSuccess) { st = KRR_ERROR_HIP; break; }
-        bool ok = true;
-        for (int k = 0; k + 1 < L.nt && ok; ++k) {
+        factor_group(0, s);
+        bool ok = hipEventRecord(ctx->ev_panel, s) == hipSuccess;
+        bool waited = false;
+        for (int G0 = 0; G0 + g < L.nt && ok; G0 += g) {
+          const int gend = G0 + g, nend = std::min(gend + g, L.nt);
           ok = hipStreamWaitEvent(s2, ctx->ev_panel, 0) == hipSuccess;
-          {
-            Stage t(ctx, KRR_STAGE_UPDATE, s2);
-            launch_update(F->Lst, k, 2, L, up, w, w.pb[k & 1], dmap, s2);
-          }
-          if (k >= 1) ok = ok && hipStreamWaitEvent(s, ctx->ev_update, 0) == hipSuccess;
+          group_update(G0, nend, L.nt - 1, s2);
+          if (G0 > 0) ok = ok && hipStreamWaitEvent(s, ctx->ev_update, 0) == hipSuccess;
           ok = ok && hipEventRecord(ctx->ev_update, s2) == hipSuccess;
-          {
-            Stage t(ctx, KRR_STAGE_UPDATE);
-            launch_update(F->Lst, k, 1, L, up, w, w.pb[k & 1], dmap, s);
-          }
-          panel(k + 1, s);
+          waited = true;
+          group_update(G0, gend, nend - 1, s);
+          factor_group(gend, s);
           ok = ok && hipEventRecord(ctx->ev_panel, s) == hipSuccess;
         }
-        if (L.nt > 1) ok = ok && hipStreamWaitEvent(s, ctx->ev_update, 0) == hipSuccess;
+        if (waited) ok = ok && hipStreamWaitEvent(s, ctx->ev_update, 0) == hipSuccess;
         if (!ok) { st = KRR_ERROR_HIP; break; }
       }
       if ((st = launch_ok()) != KRR_SUCCESS) break;
@@ -843,6 +861,15 @@ krr_status krr_predict(krr_context ctx, krr_kernel K, const int8_t *T, int64_t n
   }
   CHK(launch_ok());
   HIPCHK(hipStreamSynchronize(s));
+  return KRR_SUCCESS;
+}
+
+krr_status krr_debug_encode_fp8(krr_context ctx, const float *x, int64_t n, uint8_t *out) {
+  if (!ctx || !x || !out || n <= 0) return KRR_ERROR_INVALID_VALUE;
+  HIPCHK(hipSetDevice(ctx->device));
+  launch_encode_fp8(x, n, out, ctx->stream);
+  CHK(launch_ok());
+  HIPCHK(hipStreamSynchronize(ctx->stream));
   return KRR_SUCCESS;
 }
 

@@ -97,7 +97,7 @@ __global__ __launch_bounds__(S::THREADS) void k_gram_tiles(const int8_t *__restr
   OpI8::acc_t acc[S::WTM][S::WTN];
   zero_acc(acc);
   if (arows > 0 && brows > 0)
-    gemm_nt_core<OpI8, S>((const uint8_t *)G + row0 * ldg, ldg, arows,
+    gemm_nt_core<OpI8, S>(OpI8{}, (const uint8_t *)G + row0 * ldg, ldg, arows,
                           (const uint8_t *)G + col0 * ldg, ldg, brows, m, acc, lds);
 
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -206,7 +206,7 @@ __global__ __launch_bounds__(S::THREADS) void k_cross_gram(const int8_t *__restr
   OpI8::acc_t acc[S::WTM][S::WTN];
   zero_acc(acc);
   if (arows > 0 && brows > 0)
-    gemm_nt_core<OpI8, S>((const uint8_t *)T + row0 * ldt, ldt, arows,
+    gemm_nt_core<OpI8, S>(OpI8{}, (const uint8_t *)T + row0 * ldt, ldt, arows,
                           (const uint8_t *)G + col0 * ldg, ldg, brows, m, acc, lds);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll

@@ -41,6 +41,7 @@ KRR_DEV uint8_t f32_to_e4m3(float x) {
   const uint32_t sign = (__float_as_uint(x) >> 31) << 7;
   float a = fabsf(x);
   if (!(a < 448.0f)) return (uint8_t)(sign | 0x7E);  // saturate (NaN too)
+  if (a <= 0x1p-10f) return (uint8_t)sign;           // at most half the least subnormal: +-0
   int e;
   frexpf(a, &e);      // a = f * 2^e, f in [0.5, 1)
   e -= 1;             // a = m * 2^e, m in [1, 2)
@@ -76,7 +77,7 @@ struct OpI8 {  // int8 x int8 -> int32 (v_mfma_i32_32x32x32_i8)
   typedef int8_t elem;
   typedef v16i acc_t;
   static constexpr int ebytes = 1;
-  KRR_DEV static void mma(acc_t &c, const v4i &a0, const v4i &a1, const v4i &b0, const v4i &b1) {
+  KRR_DEV void mma(acc_t &c, const v4i &a0, const v4i &a1, const v4i &b0, const v4i &b1) const {
     c = __builtin_amdgcn_mfma_i32_32x32x32_i8(a0, b0, c, 0, 0, 0);
     c = __builtin_amdgcn_mfma_i32_32x32x32_i8(a1, b1, c, 0, 0, 0);
   }
@@ -86,21 +87,25 @@ struct OpF16 {  // fp16 x fp16 -> fp32 (v_mfma_f32_32x32x16_f16)
   typedef _Float16 elem;
   typedef v16f acc_t;
   static constexpr int ebytes = 2;
-  KRR_DEV static void mma(acc_t &c, const v4i &a0, const v4i &a1, const v4i &b0, const v4i &b1) {
+  KRR_DEV void mma(acc_t &c, const v4i &a0, const v4i &a1, const v4i &b0, const v4i &b1) const {
     c = __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(v8h, a0), __builtin_bit_cast(v8h, b0), c, 0, 0, 0);
     c = __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(v8h, a1), __builtin_bit_cast(v8h, b1), c, 0, 0, 0);
   }
 };
 
-struct OpF8 {  // OCP fp8 e4m3 x e4m3 -> fp32 (v_mfma_f32_32x32x64_f8f6f4, unit scales)
+// OCP fp8 e4m3 x e4m3 -> fp32 (v_mfma_scale_f32_32x32x64_f8f6f4).  The
+// operands are stored multiplied by powers of two; sa / sb are the E8M0
+// exponents (127 + e means 2^e) that undo them inside the instruction.
+struct OpF8 {
   typedef uint8_t elem;
   typedef v16f acc_t;
   static constexpr int ebytes = 1;
-  KRR_DEV static void mma(acc_t &c, const v4i &a0, const v4i &a1, const v4i &b0, const v4i &b1) {
+  int sa = 127, sb = 127;
+  KRR_DEV void mma(acc_t &c, const v4i &a0, const v4i &a1, const v4i &b0, const v4i &b1) const {
     v8i a = {a0[0], a0[1], a0[2], a0[3], a1[0], a1[1], a1[2], a1[3]};
     v8i b = {b0[0], b0[1], b0[2], b0[3], b1[0], b1[1], b1[2], b1[3]};
-    // format 0 = E4M3 for both operands; E8M0 scale 127 = 1.0
-    c = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b, c, 0, 0, 0, 127, 0, 127);
+    // format 0 = E4M3 for both operands
+    c = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, b, c, 0, 0, 0, sa, 0, sb);
   }
 };
 
@@ -108,7 +113,7 @@ struct OpF32 {  // fp32 x fp32 -> fp32 (v_mfma_f32_32x32x2f32, 8 per slab)
   typedef float elem;
   typedef v16f acc_t;
   static constexpr int ebytes = 4;
-  KRR_DEV static void mma(acc_t &c, const v4i &a0, const v4i &a1, const v4i &b0, const v4i &b1) {
+  KRR_DEV void mma(acc_t &c, const v4i &a0, const v4i &a1, const v4i &b0, const v4i &b1) const {
 #pragma unroll
     for (int e = 0; e < 4; ++e)
       c = __builtin_amdgcn_mfma_f32_32x32x2f32(__int_as_float(a0[e]), __int_as_float(b0[e]), c, 0, 0, 0);
@@ -165,7 +170,7 @@ KRR_DEV v4i mask_tail(v4i v, int64_t keep) {
 }
 
 template <class Op, class S>
-KRR_DEV void gemm_nt_core(const uint8_t *__restrict__ A, int64_t lda, int arows,
+KRR_DEV void gemm_nt_core(const Op &op, const uint8_t *__restrict__ A, int64_t lda, int arows,
                           const uint8_t *__restrict__ B, int64_t ldb, int brows, int64_t kbytes,
                           typename Op::acc_t (&acc)[S::WTM][S::WTN], uint8_t *lds) {
   constexpr int BM = S::kBM, BN = S::kBN, T = S::THREADS;
@@ -246,7 +251,7 @@ KRR_DEV void gemm_nt_core(const uint8_t *__restrict__ A, int64_t lda, int arows,
       const v4i a0 = *(const v4i *)p;
       const v4i a1 = *(const v4i *)(p + 16);
 #pragma unroll
-      for (int tn = 0; tn < S::WTN; ++tn) Op::mma(acc[tm][tn], a0, a1, bf0[tn], bf1[tn]);
+      for (int tn = 0; tn < S::WTN; ++tn) op.mma(acc[tm][tn], a0, a1, bf0[tn], bf1[tn]);
     }
     if (s + 1 < nslab) sstore(buf ^ 1);
     __syncthreads();

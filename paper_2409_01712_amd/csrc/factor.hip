@@ -283,7 +283,7 @@ __global__ __launch_bounds__(256) void k_trsm_panel(const float *__restrict__ As
   const int64_t kbytes = (int64_t)min(nb, (sj + 1) * UB) * 4;  // inv(L) is lower triangular
   OpF32::acc_t acc[S::WTM][S::WTN];
   zero_acc(acc);
-  gemm_nt_core<OpF32, S>((const uint8_t *)Ablk, (int64_t)nb * 4, UB, (const uint8_t *)Bblk,
+  gemm_nt_core<OpF32, S>(OpF32{}, (const uint8_t *)Ablk, (int64_t)nb * 4, UB, (const uint8_t *)Bblk,
                          (int64_t)nb * 4, UB, kbytes, acc, lds);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   float *out = P32 + t * te + (int64_t)si * UB * nb + sj * UB;
@@ -320,16 +320,15 @@ void launch_trsm_panel(const float *Astore, const float *Linv, int k, const Tile
 }
 
 // Panel conversion: reduce each tile's partial norms (fixed order), pick the
-// power-of-two scales, copy the FP32 L_ik into the factor storage and write
-// the scaled FP16 / FP8 operand copies.
+// FP8 power-of-two scale, copy the FP32 L_ik into the factor storage and
+// write the FP16 copy (unscaled) and the scaled FP8 E4M3 copy.
 constexpr int CONV_CHUNK = 4096;  // elements per workgroup
 
 __global__ __launch_bounds__(256) void k_convert_panel(
     const float *__restrict__ P32, float *__restrict__ Astore, _Float16 *__restrict__ P16,
     uint8_t *__restrict__ P8, const double *__restrict__ pnorm_part,
     const float *__restrict__ pmax_part, int parts, float *__restrict__ pnorm,
-    float *__restrict__ pscale16, float *__restrict__ pscale8, int k, int nb, int chunks,
-    int need16, int need8) {
+    int *__restrict__ pexp8, int k, int nb, int chunks, int need16, int need8) {
   const int64_t t = blockIdx.x / chunks;
   const int ch = blockIdx.x % chunks;
   const int64_t i = k + 1 + t;
@@ -339,7 +338,6 @@ __global__ __launch_bounds__(256) void k_convert_panel(
     ss += pnorm_part[t * parts + q];
     mx = fmaxf(mx, pmax_part[t * parts + q]);
   }
-  const float s16 = pow2_scale(mx, 32768.0f);
   const float s8 = pow2_scale(mx, 448.0f);
   const int64_t te = (int64_t)nb * nb;
   const float *src = P32 + t * te;
@@ -350,8 +348,7 @@ __global__ __launch_bounds__(256) void k_convert_panel(
     *(float4 *)(dstL + e) = v;
     if (need16) {
       typedef _Float16 h4 __attribute__((ext_vector_type(4)));
-      h4 h = {(_Float16)(v.x * s16), (_Float16)(v.y * s16), (_Float16)(v.z * s16),
-              (_Float16)(v.w * s16)};
+      h4 h = {(_Float16)v.x, (_Float16)v.y, (_Float16)v.z, (_Float16)v.w};
       *(h4 *)(P16 + t * te + e) = h;
     }
     if (need8) {
@@ -363,8 +360,7 @@ __global__ __launch_bounds__(256) void k_convert_panel(
   }
   if (ch == 0 && threadIdx.x == 0) {
     pnorm[t] = (float)sqrt(ss);
-    pscale16[t] = s16;
-    pscale8[t] = s8;
+    pexp8[t] = ilogbf(s8);  // s8 = 2^pexp8
   }
 }
 
@@ -375,73 +371,108 @@ void launch_convert_panel(float *Astore, int k, const TileLayout &L, FactorWork 
   const int chunks = (int)((int64_t)L.nb * L.nb / CONV_CHUNK);
   const int SB = L.nb / UB;
   hipLaunchKernelGGL(k_convert_panel, dim3((unsigned)(tiles * chunks)), dim3(256), 0, s, pb.P32,
-                     Astore, pb.P16, pb.P8, w.pnorm_part, w.pmax_part, SB * SB, pb.pnorm,
-                     pb.pscale16, pb.pscale8, k, L.nb, chunks, need16 ? 1 : 0, need8 ? 1 : 0);
+                     Astore, pb.P16, pb.P8, w.pnorm_part, w.pmax_part, SB * SB, pb.pnorm, pb.pexp8,
+                     k, L.nb, chunks, need16 ? 1 : 0, need8 ? 1 : 0);
 }
 
-// Trailing update A_ij -= L_ik L_jk^T over all k < j <= i < NT, one 128 x 128
-// block per workgroup.  The operand precision is chosen per tile update
-// (uniform across the workgroup):
+// Trailing update by a group of consecutive panels k0 .. k0+npan-1:
+//   A_ij -= sum_k L_ik L_jk^T   for the tiles (i, j), jlo <= j <= jhi, j <= i < NT,
+// one 128 x 128 block per workgroup, FP32 accumulation over all panels of
+// the group (the FP32 block of C is read and written once per group).  The
+// operand precision is chosen per (tile, panel), uniform across the
+// workgroup:
 //   FP32 on diagonal tiles, on panels k < high_panels and under the FP32 policy;
 //   FIXED: fixed_prec; ADAPTIVE: lowest allowed p with
 //   u_p ||L_ik||_F ||L_jk||_F <= thr (= eps ||A||_F / NT).
-__global__ __launch_bounds__(256) void k_update(
-    float *__restrict__ Astore, const float *__restrict__ P32, const _Float16 *__restrict__ P16,
-    const uint8_t *__restrict__ P8, const float *__restrict__ pnorm,
-    const float *__restrict__ pscale16, const float *__restrict__ pscale8, int k, int base,
-    int col_only, int nb, int SB, int mode, int allow16, int allow8, int high_panels,
-    int fixed_prec, double thr, unsigned long long *counts, uint8_t *pmap, int64_t ntiles_all) {
+struct PanelSet {
+  const float *P32[KRR_MAX_GROUP];
+  const _Float16 *P16[KRR_MAX_GROUP];
+  const uint8_t *P8[KRR_MAX_GROUP];
+  const float *pnorm[KRR_MAX_GROUP];
+  const int *pexp8[KRR_MAX_GROUP];
+};
+
+__global__ __launch_bounds__(256) void k_update(float *__restrict__ Astore, PanelSet ps, int k0,
+                                                int npan, int jlo, int jhi, int NT, int nb, int SB,
+                                                int mode, int allow16, int allow8, int high_panels,
+                                                int fixed_prec, double thr,
+                                                unsigned long long *counts, uint8_t *pmap,
+                                                int64_t ntiles_all) {
   typedef UpdShape S;
   __shared__ __attribute__((aligned(16))) uint8_t lds[S::LDS_BYTES];
   const int64_t bid = xcd_remap(blockIdx.x, gridDim.x);
   const int nsub = SB * SB;
   const int sub = (int)(bid % nsub);
-  const int64_t tt = bid / nsub;
+  int64_t tt = bid / nsub;
   int64_t i, j;
-  if (col_only) {
-    i = base + tt;
-    j = base;
-  } else {
+  if (jhi == NT - 1) {  // triangle of all tiles right of column jlo
     int ta, tb;
     tri_decode(tt, ta, tb);
-    i = base + ta;
-    j = base + tb;
+    i = jlo + ta;
+    j = jlo + tb;
+  } else {  // a few columns: walk them
+    j = jlo;
+    while (tt >= NT - j) {
+      tt -= NT - j;
+      ++j;
+    }
+    i = j + tt;
   }
-  const int64_t a = i - k - 1, b = j - k - 1;  // panel tiles of the two operands
   const int si = sub / SB, sj = sub % SB;
   const int64_t te = (int64_t)nb * nb;
 
-  int prec = KRR_PREC_FP32;
-  if (i != j && k >= high_panels) {
-    if (mode == KRR_POLICY_FIXED) {
-      prec = fixed_prec;
-    } else if (mode == KRR_POLICY_ADAPTIVE) {
-      const double prod = (double)pnorm[a] * (double)pnorm[b];
-      if (allow8 && 0.0625 * prod <= thr)
-        prec = KRR_PREC_FP8;
-      else if (allow16 && 0.00048828125 * prod <= thr)
-        prec = KRR_PREC_FP16;
+  auto choose = [&](int q) {
+    const int k = k0 + q;
+    const int64_t a = i - k - 1, b = j - k - 1;
+    int prec = KRR_PREC_FP32;
+    if (i != j && k >= high_panels) {
+      if (mode == KRR_POLICY_FIXED) {
+        prec = fixed_prec;
+      } else if (mode == KRR_POLICY_ADAPTIVE) {
+        const double prod = (double)ps.pnorm[q][a] * (double)ps.pnorm[q][b];
+        if (allow8 && 0.0625 * prod <= thr)
+          prec = KRR_PREC_FP8;
+        else if (allow16 && 0.00048828125 * prod <= thr)
+          prec = KRR_PREC_FP16;
+      }
     }
-  }
-
+    return prec;
+  };
+  // One pass per operand type (FP32 panels, then FP16, then FP8), so each
+  // MFMA flavour is instantiated once and the shared accumulator stays put.
   OpF32::acc_t acc[S::WTM][S::WTN];
   zero_acc(acc);
-  float scale = 1.0f;
-  if (prec == KRR_PREC_FP8) {
-    gemm_nt_core<OpF8, S>(P8 + a * te + (int64_t)si * UB * nb, nb, UB,
-                               P8 + b * te + (int64_t)sj * UB * nb, nb, UB, nb, acc, lds);
-    scale = 1.0f / (pscale8[a] * pscale8[b]);
-  } else if (prec == KRR_PREC_FP16) {
-    gemm_nt_core<OpF16, S>((const uint8_t *)(P16 + a * te + (int64_t)si * UB * nb),
-                                (int64_t)nb * 2, UB,
-                                (const uint8_t *)(P16 + b * te + (int64_t)sj * UB * nb),
-                                (int64_t)nb * 2, UB, (int64_t)nb * 2, acc, lds);
-    scale = 1.0f / (pscale16[a] * pscale16[b]);
-  } else {
-    gemm_nt_core<OpF32, S>((const uint8_t *)(P32 + a * te + (int64_t)si * UB * nb),
-                                (int64_t)nb * 4, UB,
-                                (const uint8_t *)(P32 + b * te + (int64_t)sj * UB * nb),
-                                (int64_t)nb * 4, UB, (int64_t)nb * 4, acc, lds);
+  for (int q = 0; q < npan; ++q) {
+    if (choose(q) != KRR_PREC_FP32) continue;
+    const int64_t a = i - (k0 + q) - 1, b = j - (k0 + q) - 1;
+    gemm_nt_core<OpF32, S>(OpF32{}, (const uint8_t *)(ps.P32[q] + a * te + (int64_t)si * UB * nb),
+                           (int64_t)nb * 4, UB,
+                           (const uint8_t *)(ps.P32[q] + b * te + (int64_t)sj * UB * nb),
+                           (int64_t)nb * 4, UB, (int64_t)nb * 4, acc, lds);
+  }
+  for (int q = 0; q < npan; ++q) {
+    if (choose(q) != KRR_PREC_FP16) continue;
+    const int64_t a = i - (k0 + q) - 1, b = j - (k0 + q) - 1;
+    gemm_nt_core<OpF16, S>(OpF16{}, (const uint8_t *)(ps.P16[q] + a * te + (int64_t)si * UB * nb),
+                           (int64_t)nb * 2, UB,
+                           (const uint8_t *)(ps.P16[q] + b * te + (int64_t)sj * UB * nb),
+                           (int64_t)nb * 2, UB, (int64_t)nb * 2, acc, lds);
+  }
+  for (int q = 0; q < npan; ++q) {
+    if (choose(q) != KRR_PREC_FP8) continue;
+    const int64_t a = i - (k0 + q) - 1, b = j - (k0 + q) - 1;
+    OpF8 op;
+    op.sa = 127 - ps.pexp8[q][a];
+    op.sb = 127 - ps.pexp8[q][b];
+    gemm_nt_core<OpF8, S>(op, ps.P8[q] + a * te + (int64_t)si * UB * nb, nb, UB,
+                          ps.P8[q] + b * te + (int64_t)sj * UB * nb, nb, UB, nb, acc, lds);
+  }
+  if (sub == 0 && threadIdx.x == 0) {
+    for (int q = 0; q < npan; ++q) {
+      const int prec = choose(q);
+      atomicAdd(&counts[prec], 1ULL);
+      if (pmap) pmap[(int64_t)(k0 + q) * ntiles_all + i * (i + 1) / 2 + j] = (uint8_t)prec;
+    }
   }
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   float *C = Astore + (i * (i + 1) / 2 + j) * te + (int64_t)si * UB * nb + sj * UB;
@@ -453,27 +484,46 @@ __global__ __launch_bounds__(256) void k_update(
       for (int e = 0; e < 16; ++e) {
         const int r = S::row(wave, tm, e, lane);
         const int c = S::col(wave, tn, lane);
-        C[(int64_t)r * nb + c] -= scale * acc[tm][tn][e];
+        C[(int64_t)r * nb + c] -= acc[tm][tn][e];
       }
-  if (sub == 0 && threadIdx.x == 0) {
-    atomicAdd(&counts[prec], 1ULL);
-    if (pmap) pmap[(int64_t)k * ntiles_all + i * (i + 1) / 2 + j] = (uint8_t)prec;
-  }
 }
 
-void launch_update(float *Astore, int k, int which, const TileLayout &L, const UpdatePolicy &pol,
-                   FactorWork &w, const PanelBuf &pb, uint8_t *pmap, hipStream_t s) {
-  const int base = (which == 2) ? k + 2 : k + 1;
-  const int64_t T = L.nt - base;
-  if (T <= 0) return;
+void launch_update(float *Astore, int k0, int npan, int jlo, int jhi, const TileLayout &L,
+                   const UpdatePolicy &pol, FactorWork &w, const PanelBuf *const *pbs,
+                   uint8_t *pmap, hipStream_t s) {
+  const int NT = L.nt;
+  if (npan <= 0 || jlo > jhi || jlo >= NT) return;
+  if (jhi > NT - 1) jhi = NT - 1;
+  int64_t tiles = 0;
+  if (jhi == NT - 1) {
+    const int64_t T = NT - jlo;
+    tiles = T * (T + 1) / 2;
+  } else {
+    for (int j = jlo; j <= jhi; ++j) tiles += NT - j;
+  }
+  PanelSet ps{};
+  for (int q = 0; q < npan; ++q) {
+    ps.P32[q] = pbs[q]->P32;
+    ps.P16[q] = pbs[q]->P16;
+    ps.P8[q] = pbs[q]->P8;
+    ps.pnorm[q] = pbs[q]->pnorm;
+    ps.pexp8[q] = pbs[q]->pexp8;
+  }
   const int SB = L.nb / UB;
-  const int col_only = (which == 1) ? 1 : 0;
-  const int64_t tiles = col_only ? T : T * (T + 1) / 2;
   const int64_t blocks = tiles * SB * SB;
-  hipLaunchKernelGGL(k_update, dim3((unsigned)blocks), dim3(256), 0, s, Astore, pb.P32, pb.P16,
-                     pb.P8, pb.pnorm, pb.pscale16, pb.pscale8, k, base, col_only, L.nb, SB, pol.mode,
-                     pol.allow16, pol.allow8, pol.high_panels, pol.fixed_prec, pol.thr, w.counts,
-                     pmap, L.ntiles());
+  hipLaunchKernelGGL(k_update, dim3((unsigned)blocks), dim3(256), 0, s, Astore, ps, k0, npan, jlo,
+                     jhi, NT, L.nb, SB, pol.mode, pol.allow16, pol.allow8, pol.high_panels,
+                     pol.fixed_prec, pol.thr, w.counts, pmap, L.ntiles());
+}
+
+// Test hook: the factorization's FP8 encoder applied elementwise.
+__global__ void k_encode_fp8(const float *__restrict__ x, int64_t n, uint8_t *__restrict__ out) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < n) out[e] = f32_to_e4m3(x[e]);
+}
+
+void launch_encode_fp8(const float *x, int64_t n, uint8_t *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_encode_fp8, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, x, n, out);
 }
 
 }  // namespace krr

@@ -50,18 +50,18 @@ struct UpdatePolicy {
 // are kept so that panel k+1 can be produced while panel k is still read.
 struct PanelBuf {
   float *P32 = nullptr;       // FP32 L_ik
-  _Float16 *P16 = nullptr;    // scaled FP16 copies
-  uint8_t *P8 = nullptr;      // scaled FP8 E4M3 copies
+  _Float16 *P16 = nullptr;    // FP16 copies
+  uint8_t *P8 = nullptr;      // FP8 E4M3 copies of 2^pexp8 L_ik
   float *pnorm = nullptr;     // ||L_ik||_F
-  float *pscale16 = nullptr;  // power-of-two scales
-  float *pscale8 = nullptr;
+  int *pexp8 = nullptr;       // FP8 scale exponents
 };
+constexpr int KRR_MAX_GROUP = 8;  // panels per grouped trailing update
 // Workspace for the factorization, sized for nt tiles of nb.
 struct FactorWork {
   double *W64 = nullptr;     // nb x nb FP64 (or FP32) diagonal workspace
   double *Winv64 = nullptr;  // nb x nb
   double *Dinv64 = nullptr;  // (nb/64) blocks of 64 x 64
-  PanelBuf pb[2];
+  PanelBuf pb[2 * KRR_MAX_GROUP];  // two groups of panel operand copies
   double *pnorm_part = nullptr;  // (nt-1) * parts
   float *pmax_part = nullptr;    // (nt-1) * parts
   int32_t *flag = nullptr;       // breakdown column + 1 (0 = none)
@@ -73,10 +73,13 @@ void launch_trsm_panel(const float *Astore, const float *Linv, int k, const Tile
                        FactorWork &w, const PanelBuf &pb, hipStream_t s);
 void launch_convert_panel(float *Astore, int k, const TileLayout &L, FactorWork &w,
                           const PanelBuf &pb, bool need16, bool need8, hipStream_t s);
-// Trailing update by panel k of: which = 0 all tiles (i, j), k < j <= i;
-// which = 1 block column k+1 only; which = 2 block columns j >= k+2.
-void launch_update(float *Astore, int k, int which, const TileLayout &L, const UpdatePolicy &pol,
-                   FactorWork &w, const PanelBuf &pb, uint8_t *pmap, hipStream_t s);
+// Trailing update of the tiles (i, j), jlo <= j <= jhi, j <= i, by the npan
+// consecutive panels k0 .. k0+npan-1 whose operand copies are *pbs[q].
+void launch_update(float *Astore, int k0, int npan, int jlo, int jhi, const TileLayout &L,
+                   const UpdatePolicy &pol, FactorWork &w, const PanelBuf *const *pbs,
+                   uint8_t *pmap, hipStream_t s);
+
+void launch_encode_fp8(const float *x, int64_t n, uint8_t *out, hipStream_t s);
 
 // ---- solve.hip ----
 // Internal right-hand sides are row-major np x r.

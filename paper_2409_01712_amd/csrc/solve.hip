@@ -23,8 +23,9 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 // so each group of four MFMAs sums k over a 16-wide block exactly once.  A
 // comes straight from memory (a tile of L, or exp(-gamma d) through the FP64
 // table), B from the right-hand-side block, with no LDS staging.
-// Output layout of a 16 x 16 MFMA accumulator: lane l, register i holds
-// row 4 (l / 16) + i, column l % 16.
+// Output layouts (checked on the device): the FP32 16 x 16 x 4 accumulator
+// holds row 4 (l / 16) + i, column l % 16 in lane l, register i; the FP64
+// one holds row 4 i + l / 16, column l % 16.
 
 // Out[rows] (=|-=) M V or M^T V for one nb x nb FP32 tile M (row-major) and an
 // nb x r block V (row-major, leading dimension r).  64 rows per workgroup.
@@ -208,7 +209,7 @@ __global__ __launch_bounds__(256) void k_residual(const int32_t *__restrict__ D,
     if (col >= r) continue;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const int64_t g = g0 + 4 * lg + i;
+      const int64_t g = g0 + 4 * i + lg;
       const int64_t off = g * r + col;
       R[off] = (g < n) ? Y[off] - acc[c][i] - lambda * X[off] : 0.0;
     }
@@ -258,7 +259,7 @@ __global__ __launch_bounds__(256) void k_predict_apply(const int32_t *__restrict
     if (col >= r) continue;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      const int64_t g = g0 + 4 * lg + i;
+      const int64_t g = g0 + 4 * i + lg;
       if (g < rows) P[(int64_t)col * ldp + g] = acc[c][i];
     }
   }

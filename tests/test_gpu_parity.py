@@ -109,6 +109,19 @@ def test_tile_norms(ctx):
             assert abs(norms[I * (I + 1) // 2 + J] - want) <= 1e-12 * want
 
 
+def test_fp8_encoder_matches_torch(ctx):
+    """The factorization's E4M3 encoder: RNE, saturating at 448, zeros and subnormals."""
+    g = torch.Generator().manual_seed(5)
+    vals = [0.0, -0.0, 1.0, -1.0, 448.0, 500.0, -1e9, 2 ** -6, 2 ** -9, 2 ** -10, 1.5 * 2 ** -10,
+            2 ** -11, 1e-30, 0.0625 + 2 ** -8, 1.0625, 1.1875, 240.0, 464.0, 3.0e-3]
+    x = torch.cat([torch.tensor(vals, dtype=torch.float32),
+                   torch.randn(20000, generator=g) * torch.exp2(torch.randint(-14, 9, (20000,),
+                                                                              generator=g).float())])
+    got = krr.krr_debug_encode_fp8(ctx, x.to(DEV)).cpu()
+    want = x.clamp(-448.0, 448.0).to(torch.float8_e4m3fn).view(torch.uint8)
+    assert torch.equal(got, want), (x[got != want][:8], got[got != want][:8], want[got != want][:8])
+
+
 # --- Factor -------------------------------------------------------------------------------
 
 def test_factor_fp32_backward_error_and_oracle(ctx):
