@@ -441,6 +441,7 @@ static void factor_work_free(krr_context c, FactorWork &w, const TileLayout &L) 
   dfree(c, w.W64, te * 8);
   dfree(c, w.Winv64, te * 8);
   dfree(c, w.Dinv64, (L.nb / 64) * 64 * 64 * 8);
+  dfree(c, w.Tmp64, te / 2 * 8);
   for (PanelBuf &pb : w.pb) {  // unallocated slots hold null pointers
     dfree(c, pb.P32, pt * te * 4);
     dfree(c, pb.P16, pt * te * 2);
@@ -468,6 +469,7 @@ static krr_status factor_work_alloc(krr_context c, FactorWork &w, const TileLayo
   WA(w.W64, te * 8);
   WA(w.Winv64, te * 8);
   WA(w.Dinv64, (L.nb / 64) * 64 * 64 * 8);
+  WA(w.Tmp64, te / 2 * 8);
   for (int q = 0; q < slots; ++q) {
     PanelBuf &pb = w.pb[q];
     WA(pb.P32, pt * te * 4);

@@ -136,20 +136,22 @@ KRR_DEV int mfma_col(int lane) { return lane & 31; }
 // arows/brows, and bytes at or beyond kbytes, read as zero.  K is staged
 // through LDS in 64-byte slabs, double-buffered, with the next slab's global
 // loads issued before the current slab's MFMAs.
-template <int BM, int BN, int WGM = 2, int WGN = 2>
+template <int BM, int BN, int WGM = 2, int WGN = 2, int SLABS = 1>
 struct GemmShape {
-  static constexpr int kBM = BM, kBN = BN, kWGM = WGM, kWGN = WGN;
+  static constexpr int kBM = BM, kBN = BN, kWGM = WGM, kWGN = WGN, kSLABS = SLABS;
   static constexpr int THREADS = 64 * WGM * WGN;
   static constexpr int WROWS = BM / WGM;        // rows per wave
   static constexpr int WCOLS = BN / WGN;        // cols per wave
   static constexpr int WTM = WROWS / 32;        // MFMA tiles per wave, rows
   static constexpr int WTN = WCOLS / 32;        // MFMA tiles per wave, cols
-  static constexpr int ROWB = 64 + 16;          // LDS row stride (bytes), padded
+  static constexpr int KB = 64 * SLABS;         // K bytes per pipeline stage
+  static constexpr int ROWB = KB + 16;          // LDS row stride (bytes), padded
   static constexpr int STAGE = (BM + BN) * ROWB;
   static constexpr int LDS_BYTES = 2 * STAGE;
-  static constexpr int LA = BM * 4 / THREADS;   // 16-byte loads per thread, A
-  static constexpr int LB = BN * 4 / THREADS;   // 16-byte loads per thread, B
-  static_assert(LA * THREADS == BM * 4 && LB * THREADS == BN * 4, "load split");
+  static constexpr int CPR = KB / 16;           // 16-byte chunks per row per stage
+  static constexpr int LA = BM * CPR / THREADS; // 16-byte loads per thread, A
+  static constexpr int LB = BN * CPR / THREADS; // 16-byte loads per thread, B
+  static_assert(LA * THREADS == BM * CPR && LB * THREADS == BN * CPR, "load split");
   // row / column (within the block) of accumulator register i of tile (tm, tn)
   KRR_DEV static int row(int wave, int tm, int i, int lane) {
     return (wave / WGN) * WROWS + tm * 32 + 8 * (i >> 2) + 4 * (lane >> 5) + (i & 3);
@@ -179,16 +181,17 @@ KRR_DEV void gemm_nt_core(const Op &op, const uint8_t *__restrict__ A, int64_t l
   const int wave = tid >> 6;
   const int wm = wave / S::kWGN, wn = wave % S::kWGN;
 
-  // global load assignment: thread handles 16-byte chunk c (0..3) of row r
+  // global load assignment: thread handles 16-byte chunk c of row r
+  constexpr int CPR = S::CPR, KB = S::KB;
   v4i ra[S::LA], rb[S::LB];
-  const int64_t nslab = (kbytes + 63) / 64;
+  const int64_t nslab = (kbytes + KB - 1) / KB;
 
   auto gload = [&](int64_t slab) {
-    const int64_t k0 = slab * 64;
+    const int64_t k0 = slab * KB;
 #pragma unroll
     for (int t = 0; t < S::LA; ++t) {
       const int idx = tid + t * T;
-      const int r = idx >> 2, c = idx & 3;
+      const int r = idx / CPR, c = idx % CPR;
       const int64_t kb = k0 + c * 16;
       v4i v = {0, 0, 0, 0};
       if (r < arows && kb < kbytes) {
@@ -200,7 +203,7 @@ KRR_DEV void gemm_nt_core(const Op &op, const uint8_t *__restrict__ A, int64_t l
 #pragma unroll
     for (int t = 0; t < S::LB; ++t) {
       const int idx = tid + t * T;
-      const int r = idx >> 2, c = idx & 3;
+      const int r = idx / CPR, c = idx % CPR;
       const int64_t kb = k0 + c * 16;
       v4i v = {0, 0, 0, 0};
       if (r < brows && kb < kbytes) {
@@ -215,14 +218,14 @@ KRR_DEV void gemm_nt_core(const Op &op, const uint8_t *__restrict__ A, int64_t l
 #pragma unroll
     for (int t = 0; t < S::LA; ++t) {
       const int idx = tid + t * T;
-      const int r = idx >> 2, c = idx & 3;
+      const int r = idx / CPR, c = idx % CPR;
       *(v4i *)(base + r * S::ROWB + c * 16) = ra[t];
     }
     uint8_t *bb = base + BM * S::ROWB;
 #pragma unroll
     for (int t = 0; t < S::LB; ++t) {
       const int idx = tid + t * T;
-      const int r = idx >> 2, c = idx & 3;
+      const int r = idx / CPR, c = idx % CPR;
       *(v4i *)(bb + r * S::ROWB + c * 16) = rb[t];
     }
   };
@@ -238,20 +241,23 @@ KRR_DEV void gemm_nt_core(const Op &op, const uint8_t *__restrict__ A, int64_t l
     if (s + 1 < nslab) gload(s + 1);
     const uint8_t *sa = lds + buf * S::STAGE;
     const uint8_t *sb = sa + BM * S::ROWB;
-    v4i bf0[S::WTN], bf1[S::WTN];
 #pragma unroll
-    for (int tn = 0; tn < S::WTN; ++tn) {
-      const uint8_t *p = sb + (wn * S::WCOLS + tn * 32 + lrow) * S::ROWB + lhalf * 32;
-      bf0[tn] = *(const v4i *)p;
-      bf1[tn] = *(const v4i *)(p + 16);
-    }
+    for (int sl = 0; sl < S::kSLABS; ++sl) {
+      v4i bf0[S::WTN], bf1[S::WTN];
 #pragma unroll
-    for (int tm = 0; tm < S::WTM; ++tm) {
-      const uint8_t *p = sa + (wm * S::WROWS + tm * 32 + lrow) * S::ROWB + lhalf * 32;
-      const v4i a0 = *(const v4i *)p;
-      const v4i a1 = *(const v4i *)(p + 16);
+      for (int tn = 0; tn < S::WTN; ++tn) {
+        const uint8_t *p = sb + (wn * S::WCOLS + tn * 32 + lrow) * S::ROWB + sl * 64 + lhalf * 32;
+        bf0[tn] = *(const v4i *)p;
+        bf1[tn] = *(const v4i *)(p + 16);
+      }
 #pragma unroll
-      for (int tn = 0; tn < S::WTN; ++tn) op.mma(acc[tm][tn], a0, a1, bf0[tn], bf1[tn]);
+      for (int tm = 0; tm < S::WTM; ++tm) {
+        const uint8_t *p = sa + (wm * S::WROWS + tm * 32 + lrow) * S::ROWB + sl * 64 + lhalf * 32;
+        const v4i a0 = *(const v4i *)p;
+        const v4i a1 = *(const v4i *)(p + 16);
+#pragma unroll
+        for (int tn = 0; tn < S::WTN; ++tn) op.mma(acc[tm][tn], a0, a1, bf0[tn], bf1[tn]);
+      }
     }
     if (s + 1 < nslab) sstore(buf ^ 1);
     __syncthreads();

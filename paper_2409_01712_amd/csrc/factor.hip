@@ -30,82 +30,141 @@ __global__ void k_potrf_load(const float *__restrict__ Akk, T *__restrict__ W, i
   W[e] = (c <= r) ? (T)Akk[e] : (T)0;
 }
 
-// Factor sub-block (s, s) and invert it with one wavefront (64 lanes, so a
-// workgroup barrier is only a wave barrier).  Lane i owns row i of the block
-// during the factorization and column i of the inverse afterwards; both
-// live in LDS, and every cross-lane read is a broadcast of one element.
+// Factor sub-block (s, s) and invert it with one workgroup of 256 threads.
+// Factorization: thread (i, q) = (tid / 4, tid % 4) keeps A[i][16q .. 16q+15]
+// in registers.  At step j the owner of column j (q = j / 16) scales it by
+// the pivot and publishes it in LDS; every thread then updates its 16
+// entries from the broadcast column.  Inverse: thread (c, q) keeps rows
+// 16q .. 16q+15 of column c of inv(L) and runs the column-oriented forward
+// substitution L x = e_c the same way.  Two barriers per step.
 template <typename T>
-__global__ __launch_bounds__(64) void k_potrf_diag64(T *__restrict__ W, int nb, int s,
-                                                     T *__restrict__ Dinv, int32_t *flag,
-                                                     int64_t colbase) {
-  __shared__ T L[BS][BS + 1];
-  __shared__ T Li[BS][BS + 1];
-  const int i = threadIdx.x;
+__global__ __launch_bounds__(256) void k_potrf_diag64(T *__restrict__ W, int nb, int s,
+                                                      T *__restrict__ Dinv, int32_t *flag,
+                                                      int64_t colbase) {
+  __shared__ __attribute__((aligned(16))) T col[BS];
+  __shared__ __attribute__((aligned(16))) T LT[BS][BS];  // LT[j][r] = L[r][j]
+  __shared__ T xs[BS];
+  __shared__ T sd;
+  const int tid = threadIdx.x, i = tid >> 2, qt = tid & 3, c0 = qt * 16;
   T *blk = W + (int64_t)(s * BS) * nb + s * BS;
-  for (int e = i; e < BS * BS; e += BS) {
-    const int r = e / BS, c = e % BS;
-    L[r][c] = (c <= r) ? blk[(int64_t)r * nb + c] : (T)0;
+  T a[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) a[q] = (c0 + q <= i) ? blk[(int64_t)i * nb + c0 + q] : (T)0;
+  for (int jq = 0; jq < 4; ++jq) {
+#pragma unroll
+    for (int jr = 0; jr < 16; ++jr) {
+      const int j = 16 * jq + jr;
+      if (i == j && qt == jq) {
+        const T piv = a[jr];
+        const bool bad = !(piv > (T)0);
+        if (bad) atomicCAS(flag, 0, (int32_t)(colbase + s * BS + j + 1));
+        sd = bad ? (T)1 : sqrt(piv);
+      }
+      __syncthreads();
+      if (qt == jq) {
+        const T d = sd;
+        const T l = (i > j) ? a[jr] / d : (i == j ? d : (T)0);
+        a[jr] = l;
+        col[i] = l;
+        LT[j][i] = l;
+      }
+      __syncthreads();
+      // branch-free: rows i <= j use li = 0, columns c <= j use L[c][j] = 0
+      const T li = (i > j) ? col[i] : (T)0;
+      T cv[16];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) cv[q] = col[c0 + q];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) a[q] -= li * ((c0 + q > j) ? cv[q] : (T)0);
+    }
   }
   __syncthreads();
-  for (int j = 0; j < BS; ++j) {
-    const T piv = L[j][j];
-    const bool bad = !(piv > (T)0);
-    const T d = bad ? (T)1 : sqrt(piv);
-    __syncthreads();
-    T lij = (T)0;
-    if (i > j) {
-      lij = L[i][j] / d;
-      L[i][j] = lij;
-    } else if (i == j) {
-      L[j][j] = d;
-      if (bad) atomicCAS(flag, 0, (int32_t)(colbase + s * BS + j + 1));
+#pragma unroll
+  for (int q = 0; q < 16; ++q)
+    blk[(int64_t)i * nb + c0 + q] = (c0 + q <= i) ? LT[c0 + q][i] : (T)0;
+  // inverse: thread (c, qt) owns rows r0 .. r0+15 of column c
+  const int c = i, r0 = c0;
+  T b[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) b[q] = (r0 + q == c) ? (T)1 : (T)0;
+  for (int pq = 0; pq < 4; ++pq) {
+#pragma unroll
+    for (int pr = 0; pr < 16; ++pr) {
+      const int p = 16 * pq + pr;
+      if (qt == pq) {
+        const T x = b[pr] / LT[p][p];
+        b[pr] = x;
+        xs[c] = x;
+      }
+      __syncthreads();
+      const T x = xs[c];
+      T lv[16];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) lv[q] = LT[p][r0 + q];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) b[q] -= ((r0 + q > p) ? lv[q] : (T)0) * x;
+      __syncthreads();
     }
-    __syncthreads();
-    if (i > j) {
+  }
+#pragma unroll
+  for (int q = 0; q < 16; ++q) Dinv[(int64_t)s * BS * BS + (int64_t)(r0 + q) * BS + c] = b[q];
+}
+
+// 64 x 64 block products on 16 x 16 x 4 MFMA tiles (FP64 or FP32): wave w
+// computes rows 16w .. 16w+15 of C = A op(B) for all 64 columns.  A, B are
+// [64][BS + 1] LDS arrays; op(B)[k][j] = B[j][k] if BT else B[k][j].
+// acc[ct] holds C rows (layout of the MFMA type), columns 16 ct + l % 16.
+template <typename T> struct M16;
+template <> struct M16<double> {
+  typedef double v4 __attribute__((ext_vector_type(4)));
+  KRR_DEV static v4 mma(double a, double b, v4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  KRR_DEV static int row(int r, int lane) { return 4 * r + (lane >> 4); }
+};
+template <> struct M16<float> {
+  typedef float v4 __attribute__((ext_vector_type(4)));
+  KRR_DEV static v4 mma(float a, float b, v4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  KRR_DEV static int row(int r, int lane) { return 4 * (lane >> 4) + r; }
+};
+
+template <typename T, bool BT>
+__device__ __forceinline__ void mm64(const T (*A)[BS + 1], const T (*B)[BS + 1],
+                                     typename M16<T>::v4 (&acc)[4]) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, lg = lane >> 4;
 #pragma unroll 4
-      for (int c = j + 1; c <= i; ++c) L[i][c] -= lij * L[c][j];
+  for (int k0 = 0; k0 < BS; k0 += 4) {
+    const T av = A[16 * wave + li][k0 + lg];
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct) {
+      const T bv = BT ? B[16 * ct + li][k0 + lg] : B[k0 + lg][16 * ct + li];
+      acc[ct] = M16<T>::mma(av, bv, acc[ct]);
     }
-    __syncthreads();
-  }
-  // column c = i of inv(L) by forward substitution against e_c
-  const int c = i;
-  for (int k = 0; k < BS; ++k) {
-    T acc0 = (k == c) ? (T)1 : (T)0, acc1 = 0, acc2 = 0, acc3 = 0;
-    int p = c;
-    for (; p + 3 < k; p += 4) {
-      acc0 -= L[k][p] * Li[p][c];
-      acc1 -= L[k][p + 1] * Li[p + 1][c];
-      acc2 -= L[k][p + 2] * Li[p + 2][c];
-      acc3 -= L[k][p + 3] * Li[p + 3][c];
-    }
-    for (; p < k; ++p) acc0 -= L[k][p] * Li[p][c];
-    Li[k][c] = (k < c) ? (T)0 : ((acc0 + acc1) + (acc2 + acc3)) / L[k][k];
-  }
-  __syncthreads();
-  for (int e = i; e < BS * BS; e += BS) {
-    const int r = e / BS, cc = e % BS;
-    Dinv[(int64_t)s * BS * BS + e] = Li[r][cc];
-    blk[(int64_t)r * nb + cc] = (cc <= r) ? L[r][cc] : (T)0;
   }
 }
 
-// 64x64x64 product helper: each of 256 threads owns a 4 x 4 output patch.
-// acc[a][b] += sum_p X[r0 + a][p] * Y(p, c0 + b), where Y(p, c) = Yt[c][p]
-// if YT (Y given transposed) else Yt[p][c].
-template <typename T, bool YT>
-__device__ __forceinline__ void mm64(const T (*X)[BS + 1], const T (*Yt)[BS + 1], T (&acc)[4][4],
-                                     int r0, int c0) {
-  for (int p = 0; p < BS; ++p) {
-    T xa[4], yb[4];
+template <typename T>
+__device__ __forceinline__ void zero4(typename M16<T>::v4 (&acc)[4]) {
 #pragma unroll
-    for (int a = 0; a < 4; ++a) xa[a] = X[r0 + a][p];
+  for (int ct = 0; ct < 4; ++ct) acc[ct] = (typename M16<T>::v4){0, 0, 0, 0};
+}
+
+// dst (ld) = alpha * acc, or dst += alpha * acc when ADD
+template <typename T, bool ADD>
+__device__ __forceinline__ void store64(T *dst, int64_t ld, const typename M16<T>::v4 (&acc)[4],
+                                        T alpha) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
-    for (int b = 0; b < 4; ++b) yb[b] = YT ? Yt[c0 + b][p] : Yt[p][c0 + b];
+  for (int ct = 0; ct < 4; ++ct)
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-      for (int b = 0; b < 4; ++b) acc[a][b] += xa[a] * yb[b];
-  }
+    for (int r = 0; r < 4; ++r) {
+      T *p = dst + (int64_t)(16 * wave + M16<T>::row(r, lane)) * ld + 16 * ct + (lane & 15);
+      if (ADD) *p += alpha * acc[ct][r];
+      else *p = alpha * acc[ct][r];
+    }
 }
 
 // Stage a 64 x 64 block into LDS: all 16 loads of a thread are issued before
@@ -137,13 +196,10 @@ __global__ __launch_bounds__(256) void k_potrf_trsm64(T *__restrict__ W, int nb,
   load64(X, blk, nb);
   load64(Li, Dinv + (int64_t)s * BS * BS, BS);
   __syncthreads();
-  const int r0 = (threadIdx.x >> 4) * 4, c0 = (threadIdx.x & 15) * 4;
-  T acc[4][4] = {};
-  mm64<T, true>(X, Li, acc, r0, c0);
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) blk[(int64_t)(r0 + i) * nb + c0 + j] = acc[i][j];
+  typename M16<T>::v4 acc[4];
+  zero4<T>(acc);
+  mm64<T, true>(X, Li, acc);
+  store64<T, false>(blk, nb, acc, (T)1);
 }
 
 // Trailing update inside the diagonal tile: W_ab -= W_as W_bs^T, s < b <= a.
@@ -158,80 +214,84 @@ __global__ __launch_bounds__(256) void k_potrf_syrk64(T *__restrict__ W, int nb,
   load64(Xa, W + (int64_t)(a * BS) * nb + s * BS, nb);
   load64(Xb, W + (int64_t)(b * BS) * nb + s * BS, nb);
   __syncthreads();
-  const int r0 = (threadIdx.x >> 4) * 4, c0 = (threadIdx.x & 15) * 4;
-  T acc[4][4] = {};
-  mm64<T, true>(Xa, Xb, acc, r0, c0);
-  T *blk = W + (int64_t)(a * BS) * nb + b * BS;
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) blk[(int64_t)(r0 + i) * nb + c0 + j] -= acc[i][j];
+  typename M16<T>::v4 acc[4];
+  zero4<T>(acc);
+  mm64<T, true>(Xa, Xb, acc);
+  store64<T, true>(W + (int64_t)(a * BS) * nb + b * BS, nb, acc, (T)-1);
 }
 
-// Off-diagonal blocks of inv(L) at block distance delta = a - b:
-// Winv_ab = -inv(L_aa) * sum_{c=b}^{a-1} L_ac Winv_cb, with Winv_bb = inv(L_bb).
+// Inverse of the whole lower-triangular tile by recursive doubling: with the
+// inverses of the diagonal blocks of size b known,
+//   inv([A 0; B C]) = [inv(A) 0; -inv(C) B inv(A)  inv(C)],
+// so each level doubles the block size with two block products.
 template <typename T>
-__global__ __launch_bounds__(256) void k_trtri_off64(const T *__restrict__ W, T *__restrict__ Winv,
-                                                     int nb, int delta,
-                                                     const T *__restrict__ Dinv) {
-  __shared__ T X[BS][BS + 1];
-  __shared__ T Y[BS][BS + 1];
-  const int b = blockIdx.x, a = b + delta;
-  const int r0 = (threadIdx.x >> 4) * 4, c0 = (threadIdx.x & 15) * 4;
-  T acc[4][4] = {};
-  for (int c = b; c < a; ++c) {
-    load64(X, W + (int64_t)(a * BS) * nb + c * BS, nb);
-    if (c == b)
-      load64(Y, Dinv + (int64_t)b * BS * BS, BS);
-    else
-      load64(Y, Winv + (int64_t)(c * BS) * nb + b * BS, nb);
+__global__ void k_trtri_init(const T *__restrict__ Dinv, T *__restrict__ Winv, int nb) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)nb * nb) return;
+  const int r = (int)(e / nb), c = (int)(e % nb);
+  Winv[e] = (r / BS == c / BS) ? Dinv[(int64_t)(r / BS) * BS * BS + (r % BS) * BS + c % BS] : (T)0;
+}
+
+// C = alpha * A * B for b x b blocks (b a multiple of 64), pair p = blockIdx.z
+// at diagonal offset 2 p b.  Output block (blockIdx.y, blockIdx.x) of 64 x 64.
+// step 0: Tmp_p = L[(2p+1)b.., 2pb..] * Winv[2pb.., 2pb..]
+// step 1: Winv[(2p+1)b.., 2pb..] = -Winv[(2p+1)b.., (2p+1)b..] * Tmp_p
+template <typename T>
+__global__ __launch_bounds__(256) void k_trtri_level(const T *__restrict__ W, T *__restrict__ Winv,
+                                                     T *__restrict__ Tmp, int nb, int b, int step) {
+  __shared__ T As[BS][BS + 1];
+  __shared__ T Bs[BS][BS + 1];
+  const int64_t p = blockIdx.z, o = 2 * p * b;
+  const T *A;
+  const T *B;
+  T *C;
+  int64_t lda, ldb, ldc;
+  T alpha;
+  if (step == 0) {
+    A = W + (o + b) * nb + o;       lda = nb;
+    B = Winv + o * nb + o;          ldb = nb;
+    C = Tmp + p * (int64_t)b * b;   ldc = b;
+    alpha = (T)1;
+  } else {
+    A = Winv + (o + b) * nb + o + b; lda = nb;
+    B = Tmp + p * (int64_t)b * b;    ldb = b;
+    C = Winv + (o + b) * nb + o;     ldc = nb;
+    alpha = (T)-1;
+  }
+  const int rb = blockIdx.y, cb = blockIdx.x;
+  typename M16<T>::v4 acc[4];
+  zero4<T>(acc);
+  for (int k0 = 0; k0 < b; k0 += BS) {
+    load64(As, A + (int64_t)(rb * BS) * lda + k0, lda);
+    load64(Bs, B + (int64_t)k0 * ldb + cb * BS, ldb);
     __syncthreads();
-    mm64<T, false>(X, Y, acc, r0, c0);
+    mm64<T, false>(As, Bs, acc);
     __syncthreads();
   }
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) X[r0 + i][c0 + j] = acc[i][j];
-  load64(Y, Dinv + (int64_t)a * BS * BS, BS);
-  __syncthreads();
-  T out[4][4] = {};
-  mm64<T, false>(Y, X, out, r0, c0);
-  T *blk = Winv + (int64_t)(a * BS) * nb + b * BS;
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) blk[(int64_t)(r0 + i) * nb + c0 + j] = -out[i][j];
+  store64<T, false>(C + (int64_t)(rb * BS) * ldc + cb * BS, ldc, acc, alpha);
 }
 
 // Write L_kk (lower, zero above) and inv(L_kk) as FP32.
 template <typename T>
 __global__ void k_potrf_store(const T *__restrict__ W, const T *__restrict__ Winv,
-                              const T *__restrict__ Dinv, float *__restrict__ Akk,
-                              float *__restrict__ Linv, int nb) {
+                              float *__restrict__ Akk, float *__restrict__ Linv, int nb) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= (int64_t)nb * nb) return;
   const int r = (int)(e / nb), c = (int)(e % nb);
-  const int a = r / BS, b = c / BS;
   Akk[e] = (c <= r) ? (float)W[e] : 0.0f;
-  T v = (T)0;
-  if (a == b)
-    v = Dinv[(int64_t)a * BS * BS + (r % BS) * BS + (c % BS)];
-  else if (a > b)
-    v = Winv[e];
-  Linv[e] = (float)v;
+  Linv[e] = (c <= r) ? (float)Winv[e] : 0.0f;
 }
 
 template <typename T>
 static void potrf_tile_t(float *Akk, float *Linv, int k, const TileLayout &L, FactorWork &w,
                          hipStream_t s) {
   const int nb = L.nb, NB = nb / BS;
-  T *W = (T *)w.W64, *Winv = (T *)w.Winv64, *Dinv = (T *)w.Dinv64;
+  T *W = (T *)w.W64, *Winv = (T *)w.Winv64, *Dinv = (T *)w.Dinv64, *Tmp = (T *)w.Tmp64;
   const unsigned eb = (unsigned)(((int64_t)nb * nb + 255) / 256);
   const int64_t colbase = (int64_t)k * nb;
   hipLaunchKernelGGL(k_potrf_load<T>, dim3(eb), dim3(256), 0, s, Akk, W, nb);
   for (int st = 0; st < NB; ++st) {
-    hipLaunchKernelGGL(k_potrf_diag64<T>, dim3(1), dim3(64), 0, s, W, nb, st, Dinv, w.flag,
+    hipLaunchKernelGGL(k_potrf_diag64<T>, dim3(1), dim3(256), 0, s, W, nb, st, Dinv, w.flag,
                        colbase);
     const int rest = NB - 1 - st;
     if (rest > 0) {
@@ -240,10 +300,15 @@ static void potrf_tile_t(float *Akk, float *Linv, int k, const TileLayout &L, Fa
                          st);
     }
   }
-  for (int delta = 1; delta < NB; ++delta)
-    hipLaunchKernelGGL(k_trtri_off64<T>, dim3(NB - delta), dim3(256), 0, s, W, Winv, nb, delta,
-                       Dinv);
-  hipLaunchKernelGGL(k_potrf_store<T>, dim3(eb), dim3(256), 0, s, W, Winv, Dinv, Akk, Linv, nb);
+  hipLaunchKernelGGL(k_trtri_init<T>, dim3(eb), dim3(256), 0, s, Dinv, Winv, nb);
+  for (int b = BS; b < nb; b *= 2) {
+    const unsigned nbk = (unsigned)(b / BS), pairs = (unsigned)(nb / (2 * b));
+    hipLaunchKernelGGL(k_trtri_level<T>, dim3(nbk, nbk, pairs), dim3(256), 0, s, W, Winv, Tmp, nb,
+                       b, 0);
+    hipLaunchKernelGGL(k_trtri_level<T>, dim3(nbk, nbk, pairs), dim3(256), 0, s, W, Winv, Tmp, nb,
+                       b, 1);
+  }
+  hipLaunchKernelGGL(k_potrf_store<T>, dim3(eb), dim3(256), 0, s, W, Winv, Akk, Linv, nb);
 }
 
 void launch_potrf_tile(float *Akk, float *Linv, int k, const TileLayout &L, bool fp64,
@@ -260,7 +325,7 @@ void launch_potrf_tile(float *Akk, float *Linv, int k, const TileLayout &L, bool
 // same tile).  Each 128 x 128 block also leaves its FP64 sum of squares and
 // its max |entry| for the operand norms and scales.
 constexpr int UB = 128;  // block edge of the factorization GEMMs
-typedef GemmShape<UB, UB, 2, 2> UpdShape;
+typedef GemmShape<UB, UB, 2, 2, 1> UpdShape;
 
 __global__ __launch_bounds__(256) void k_trsm_panel(const float *__restrict__ Astore,
                                                     const float *__restrict__ Linv, int k, int nb,

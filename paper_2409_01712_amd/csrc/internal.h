@@ -61,6 +61,7 @@ struct FactorWork {
   double *W64 = nullptr;     // nb x nb FP64 (or FP32) diagonal workspace
   double *Winv64 = nullptr;  // nb x nb
   double *Dinv64 = nullptr;  // (nb/64) blocks of 64 x 64
+  double *Tmp64 = nullptr;   // nb x nb / 2 scratch for the tile inverse
   PanelBuf pb[2 * KRR_MAX_GROUP];  // two groups of panel operand copies
   double *pnorm_part = nullptr;  // (nt-1) * parts
   float *pmax_part = nullptr;    // (nt-1) * parts

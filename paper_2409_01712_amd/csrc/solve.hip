@@ -62,28 +62,39 @@ __global__ __launch_bounds__(256) void k_tri_apply(const float *__restrict__ Mba
 #pragma unroll
   for (int c = 0; c < NCB; ++c) acc[c] = (v4f){0.f, 0.f, 0.f, 0.f};
   const int R = row0 + li;
-  for (int q = q_lo; q < q_hi; q += 16) {
-    const int kk = q + 4 * lg;
-    float a[4];
-    if (!TRANS) {
-      const float4 v = *(const float4 *)(M + (int64_t)R * nb + kk);
-      a[0] = v.x; a[1] = v.y; a[2] = v.z; a[3] = v.w;
-    } else {
+  // k advances 64 at a time (q_lo, q_hi are multiples of 64): the loads of
+  // four 16-wide steps are issued before their MFMAs.
+  for (int q = q_lo; q < q_hi; q += 64) {
+    float a[4][4];
+    float b[4][NCB][4];
 #pragma unroll
-      for (int e = 0; e < 4; ++e) a[e] = M[(int64_t)(kk + e) * nb + R];
+    for (int u = 0; u < 4; ++u) {
+      const int kk = q + 16 * u + 4 * lg;
+      if (!TRANS) {
+        const float4 v = *(const float4 *)(M + (int64_t)R * nb + kk);
+        a[u][0] = v.x; a[u][1] = v.y; a[u][2] = v.z; a[u][3] = v.w;
+      } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) a[u][e] = M[(int64_t)(kk + e) * nb + R];
+      }
+#pragma unroll
+      for (int c = 0; c < NCB; ++c) {
+        const int col = col0 + c * 16 + li;
+        const int cc = min(col, r - 1);  // in-bounds load, zeroed below when col >= r
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const float v = V[(int64_t)(kk + e) * r + cc];
+          b[u][c][e] = (col < r) ? v : 0.f;
+        }
+      }
     }
-    float b[NCB][4];
 #pragma unroll
-    for (int c = 0; c < NCB; ++c) {
-      const int col = col0 + c * 16 + li;
+    for (int u = 0; u < 4; ++u)
 #pragma unroll
-      for (int e = 0; e < 4; ++e) b[c][e] = (col < r) ? V[(int64_t)(kk + e) * r + col] : 0.f;
-    }
+      for (int c = 0; c < NCB; ++c)
 #pragma unroll
-    for (int c = 0; c < NCB; ++c)
-#pragma unroll
-      for (int e = 0; e < 4; ++e)
-        acc[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[e], b[c][e], acc[c], 0, 0, 0);
+        for (int e = 0; e < 4; ++e)
+          acc[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u][e], b[u][c][e], acc[c], 0, 0, 0);
   }
 #pragma unroll
   for (int c = 0; c < NCB; ++c) {
@@ -148,29 +159,43 @@ __device__ __forceinline__ void exp_mfma_block(const int32_t *__restrict__ D, in
                                                int64_t emax, const double *__restrict__ X, int r,
                                                int64_t xrow0, int col0, int li, int lg,
                                                v4d (&acc)[NCB]) {
-  for (int64_t q = j0; q < jn; q += 16) {
-    const int64_t kk = q + 4 * lg;
-    int32_t d[4];
-    if (DMODE == 0) {
-      const int4 v = *(const int4 *)(D + (int64_t)row * ldd + kk);
-      d[0] = v.x; d[1] = v.y; d[2] = v.z; d[3] = v.w;
-    } else {
+  // j advances 64 at a time (the ranges are multiples of 64): the distance
+  // loads and table lookups of four 16-wide steps are issued before their MFMAs.
+  for (int64_t q = j0; q < jn; q += 64) {
+    int32_t d[4][4];
 #pragma unroll
-      for (int e = 0; e < 4; ++e) d[e] = D[(kk + e) * ldd + row];
+    for (int u = 0; u < 4; ++u) {
+      const int64_t kk = q + 16 * u + 4 * lg;
+      if (DMODE == 0) {
+        const int4 v = *(const int4 *)(D + (int64_t)row * ldd + kk);
+        d[u][0] = v.x; d[u][1] = v.y; d[u][2] = v.z; d[u][3] = v.w;
+      } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) d[u][e] = D[(kk + e) * ldd + row];
+      }
     }
-    double a[4];
+    double a[4][4];
 #pragma unroll
-    for (int e = 0; e < 4; ++e) a[e] = etab[min((int64_t)max(d[e], 0), emax)];
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) a[u][e] = etab[min((int64_t)max(d[u][e], 0), emax)];
 #pragma unroll
     for (int c = 0; c < NCB; ++c) {
       const int col = col0 + c * 16 + li;
-      double b[4];
+      const int cc = min(col, r - 1);  // in-bounds load, zeroed below when col >= r
+      double b[4][4];
 #pragma unroll
-      for (int e = 0; e < 4; ++e)
-        b[e] = (col < r) ? X[(xrow0 + kk - j0 + e) * r + col] : 0.0;
+      for (int u = 0; u < 4; ++u)
 #pragma unroll
-      for (int e = 0; e < 4; ++e)
-        acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[e], b[e], acc[c], 0, 0, 0);
+        for (int e = 0; e < 4; ++e) {
+          const double v = X[(xrow0 + q - j0 + 16 * u + 4 * lg + e) * r + cc];
+          b[u][e] = (col < r) ? v : 0.0;
+        }
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u][e], b[u][e], acc[c], 0, 0, 0);
     }
   }
 }
