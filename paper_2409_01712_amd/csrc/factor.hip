@@ -30,86 +30,6 @@ __global__ void k_potrf_load(const float *__restrict__ Akk, T *__restrict__ W, i
   W[e] = (c <= r) ? (T)Akk[e] : (T)0;
 }
 
-// Factor sub-block (s, s) and invert it with one workgroup of 256 threads.
-// Factorization: thread (i, q) = (tid / 4, tid % 4) keeps A[i][16q .. 16q+15]
-// in registers.  At step j the owner of column j (q = j / 16) scales it by
-// the pivot and publishes it in LDS; every thread then updates its 16
-// entries from the broadcast column.  Inverse: thread (c, q) keeps rows
-// 16q .. 16q+15 of column c of inv(L) and runs the column-oriented forward
-// substitution L x = e_c the same way.  Two barriers per step.
-template <typename T>
-__global__ __launch_bounds__(256) void k_potrf_diag64(T *__restrict__ W, int nb, int s,
-                                                      T *__restrict__ Dinv, int32_t *flag,
-                                                      int64_t colbase) {
-  __shared__ __attribute__((aligned(16))) T col[BS];
-  __shared__ __attribute__((aligned(16))) T LT[BS][BS];  // LT[j][r] = L[r][j]
-  __shared__ T xs[BS];
-  __shared__ T sd;
-  const int tid = threadIdx.x, i = tid >> 2, qt = tid & 3, c0 = qt * 16;
-  T *blk = W + (int64_t)(s * BS) * nb + s * BS;
-  T a[16];
-#pragma unroll
-  for (int q = 0; q < 16; ++q) a[q] = (c0 + q <= i) ? blk[(int64_t)i * nb + c0 + q] : (T)0;
-  for (int jq = 0; jq < 4; ++jq) {
-#pragma unroll
-    for (int jr = 0; jr < 16; ++jr) {
-      const int j = 16 * jq + jr;
-      if (i == j && qt == jq) {
-        const T piv = a[jr];
-        const bool bad = !(piv > (T)0);
-        if (bad) atomicCAS(flag, 0, (int32_t)(colbase + s * BS + j + 1));
-        sd = bad ? (T)1 : sqrt(piv);
-      }
-      __syncthreads();
-      if (qt == jq) {
-        const T d = sd;
-        const T l = (i > j) ? a[jr] / d : (i == j ? d : (T)0);
-        a[jr] = l;
-        col[i] = l;
-        LT[j][i] = l;
-      }
-      __syncthreads();
-      // branch-free: rows i <= j use li = 0, columns c <= j use L[c][j] = 0
-      const T li = (i > j) ? col[i] : (T)0;
-      T cv[16];
-#pragma unroll
-      for (int q = 0; q < 16; ++q) cv[q] = col[c0 + q];
-#pragma unroll
-      for (int q = 0; q < 16; ++q) a[q] -= li * ((c0 + q > j) ? cv[q] : (T)0);
-    }
-  }
-  __syncthreads();
-#pragma unroll
-  for (int q = 0; q < 16; ++q)
-    blk[(int64_t)i * nb + c0 + q] = (c0 + q <= i) ? LT[c0 + q][i] : (T)0;
-  // inverse: thread (c, qt) owns rows r0 .. r0+15 of column c
-  const int c = i, r0 = c0;
-  T b[16];
-#pragma unroll
-  for (int q = 0; q < 16; ++q) b[q] = (r0 + q == c) ? (T)1 : (T)0;
-  for (int pq = 0; pq < 4; ++pq) {
-#pragma unroll
-    for (int pr = 0; pr < 16; ++pr) {
-      const int p = 16 * pq + pr;
-      if (qt == pq) {
-        const T x = b[pr] / LT[p][p];
-        b[pr] = x;
-        xs[c] = x;
-      }
-      __syncthreads();
-      const T x = xs[c];
-      T lv[16];
-#pragma unroll
-      for (int q = 0; q < 16; ++q) lv[q] = LT[p][r0 + q];
-#pragma unroll
-      for (int q = 0; q < 16; ++q) b[q] -= ((r0 + q > p) ? lv[q] : (T)0) * x;
-      __syncthreads();
-    }
-  }
-#pragma unroll
-  for (int q = 0; q < 16; ++q) Dinv[(int64_t)s * BS * BS + (int64_t)(r0 + q) * BS + c] = b[q];
-}
-
 // 64 x 64 block products on 16 x 16 x 4 MFMA tiles (FP64 or FP32): wave w
 // computes rows 16w .. 16w+15 of C = A op(B) for all 64 columns.  A, B are
 // [64][BS + 1] LDS arrays; op(B)[k][j] = B[j][k] if BT else B[k][j].
@@ -129,6 +49,178 @@ template <> struct M16<float> {
   }
   KRR_DEV static int row(int r, int lane) { return 4 * (lane >> 4) + r; }
 };
+
+// Value of v held by lane src (wave-uniform), broadcast to the wave.
+KRR_DEV double bcast(double v, int src) {
+  const uint64_t u = __builtin_bit_cast(uint64_t, v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, src);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), src);
+  return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+KRR_DEV float bcast(float v, int src) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), src));
+}
+
+// 1 / sqrt(x): hardware estimate refined by two Newton-Raphson steps
+// y <- y + (y / 2)(1 - x y^2), each of which doubles the correct bits.
+KRR_DEV double rsqrt_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+#pragma unroll
+  for (int it = 0; it < 2; ++it) {
+    const double h = fma(-x * y, y, 1.0);
+    y = fma(0.5 * y, h, y);
+  }
+  return y;
+}
+KRR_DEV float rsqrt_nr(float x) { return 1.0f / sqrtf(x); }
+
+// LDS reads after LDS writes of other lanes of the same wave: the wave's LDS
+// operations complete in order, so only the compiler must be kept in order.
+KRR_DEV void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Factor sub-block (s, s) of the tile and invert it, one workgroup of four
+// waves, blocked by 16 columns (block kb = 0..3):
+//   wave 0 factors the 16 x 16 diagonal block in registers (lane i holds row
+//   i; pivots and columns move between lanes by readlane, no barriers) and
+//   forms its inverse by column-oriented forward substitution (lane c holds
+//   column c);
+//   panel   L_ib,kb = A_ib,kb inv(L_kb,kb)^T     (16 x 16 x 4 MFMA, one wave per block)
+//   update  A_ib,jb -= L_ib,kb L_jb,kb^T, kb < jb <= ib  (MFMA, blocks spread over waves)
+// The inverse of the 64 x 64 factor is then completed block column by block
+// column (wave jb owns column jb):
+//   X_ib,jb = -inv(L_ib,ib) sum_{kb=jb}^{ib-1} L_ib,kb X_kb,jb.
+template <typename T>
+__global__ __launch_bounds__(256) void k_potrf_diag64(T *__restrict__ W, int nb, int s,
+                                                      T *__restrict__ Dinv, int32_t *flag,
+                                                      int64_t colbase) {
+  typedef typename M16<T>::v4 v4;
+  __shared__ T S[BS][BS + 1];  // the block, overwritten by L
+  __shared__ T X[BS][BS + 1];  // inv(L)
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 15, lg = lane >> 4;
+  T *blk = W + (int64_t)(s * BS) * nb + s * BS;
+  {
+    T v[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int e = tid + 256 * q, r = e / BS, c = e % BS;
+      v[q] = (c <= r) ? blk[(int64_t)r * nb + c] : (T)0;
+    }
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int e = tid + 256 * q;
+      S[e / BS][e % BS] = v[q];
+    }
+  }
+  __syncthreads();
+  for (int kb = 0; kb < 4; ++kb) {
+    const int b = 16 * kb;
+    if (wave == 0) {
+      T d[16], rv[16];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) d[q] = S[b + li][b + q];
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        T piv = bcast(d[j], j);
+        if (!(piv > (T)0)) {
+          if (lane == 0) atomicCAS(flag, 0, (int32_t)(colbase + s * BS + b + j + 1));
+          piv = (T)1;
+        }
+        const T r = rsqrt_nr(piv);
+        rv[j] = r;
+        const T l = (li == j) ? piv * r : d[j] * r;
+        d[j] = l;
+#pragma unroll
+        for (int k = j + 1; k < 16; ++k) d[k] -= l * bcast(l, k);
+      }
+      // column li of inv(L_kb,kb): x_q = (e_li - sum_{p<q} L_qp x_p)_q / L_qq
+      T x[16];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) x[q] = (q == li) ? (T)1 : (T)0;
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        x[q] *= rv[q];
+#pragma unroll
+        for (int p = q + 1; p < 16; ++p) x[p] -= bcast(d[q], p) * x[q];
+      }
+      if (lane < 16) {
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+          S[b + li][b + q] = (q <= li) ? d[q] : (T)0;
+          X[b + q][b + li] = x[q];
+        }
+      }
+    }
+    __syncthreads();
+    if (kb == 3) break;
+    {
+      const int ib = kb + 1 + wave;
+      if (ib < 4) {
+        v4 acc = {0, 0, 0, 0};
+#pragma unroll
+        for (int k0 = 0; k0 < 16; k0 += 4)
+          acc = M16<T>::mma(S[16 * ib + li][b + k0 + lg], X[b + li][b + k0 + lg], acc);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) S[16 * ib + M16<T>::row(r, lane)][b + li] = acc[r];
+      }
+    }
+    __syncthreads();
+    {
+      const int rem = 3 - kb, npair = rem * (rem + 1) / 2;
+      for (int pi = wave; pi < npair; pi += 4) {
+        int jb = kb + 1, ib = 0, t = pi;
+        while (t >= 4 - jb) { t -= 4 - jb; ++jb; }
+        ib = jb + t;
+        v4 acc;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) acc[r] = S[16 * ib + M16<T>::row(r, lane)][16 * jb + li];
+#pragma unroll
+        for (int k0 = 0; k0 < 16; k0 += 4)
+          acc = M16<T>::mma(-S[16 * ib + li][b + k0 + lg], S[16 * jb + li][b + k0 + lg], acc);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) S[16 * ib + M16<T>::row(r, lane)][16 * jb + li] = acc[r];
+      }
+    }
+    __syncthreads();
+  }
+  if (wave < 3) {
+    const int jb = wave;
+    for (int ib = jb + 1; ib < 4; ++ib) {
+      v4 acc = {0, 0, 0, 0};
+      for (int kb = jb; kb < ib; ++kb)
+#pragma unroll
+        for (int k0 = 0; k0 < 16; k0 += 4)
+          acc = M16<T>::mma(S[16 * ib + li][16 * kb + k0 + lg], X[16 * kb + k0 + lg][16 * jb + li],
+                            acc);
+      // stage the sum in the output block, then X_ib,jb = -inv(L_ib,ib) * sum
+#pragma unroll
+      for (int r = 0; r < 4; ++r) X[16 * ib + M16<T>::row(r, lane)][16 * jb + li] = acc[r];
+      wave_lds_sync();
+      T bv[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) bv[r] = X[16 * ib + 4 * r + lg][16 * jb + li];
+      v4 out = {0, 0, 0, 0};
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        out = M16<T>::mma(-X[16 * ib + li][16 * ib + 4 * r + lg], bv[r], out);
+      wave_lds_sync();
+#pragma unroll
+      for (int r = 0; r < 4; ++r) X[16 * ib + M16<T>::row(r, lane)][16 * jb + li] = out[r];
+      wave_lds_sync();
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    const int e = tid + 256 * q, r = e / BS, c = e % BS;
+    blk[(int64_t)r * nb + c] = (c <= r) ? S[r][c] : (T)0;
+    Dinv[(int64_t)s * BS * BS + e] = (c <= r) ? X[r][c] : (T)0;
+  }
+}
 
 template <typename T, bool BT>
 __device__ __forceinline__ void mm64(const T (*A)[BS + 1], const T (*B)[BS + 1],
