@@ -81,7 +81,7 @@ __global__ __launch_bounds__(S::THREADS) void k_gram_tiles(const int8_t *__restr
                                                     int SB, int32_t *__restrict__ D,
                                                     float *__restrict__ A, double *part) {
   constexpr int BM = S::kBM, BN = S::kBN, NW = S::THREADS / 64;
-  __shared__ __attribute__((aligned(16))) uint8_t lds[S::LDS_BYTES];
+  extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
   __shared__ double shd[NW];
   const int64_t bid = xcd_remap(blockIdx.x, gridDim.x);
   const int nsub = SB * SB;
@@ -97,8 +97,9 @@ __global__ __launch_bounds__(S::THREADS) void k_gram_tiles(const int8_t *__restr
   OpI8::acc_t acc[S::WTM][S::WTN];
   zero_acc(acc);
   if (arows > 0 && brows > 0)
-    gemm_nt_core<OpI8, S>(OpI8{}, (const uint8_t *)G + row0 * ldg, ldg, arows,
-                          (const uint8_t *)G + col0 * ldg, ldg, brows, m, acc, lds);
+    gemm_nt_stream<OpI8, S>(
+        ContigSrc<OpI8>{(const uint8_t *)G + row0 * ldg, (const uint8_t *)G + col0 * ldg, OpI8{}},
+        ldg, arows, ldg, brows, m, acc, lds);
 
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int64_t tbase = t * (int64_t)nb * nb;
@@ -130,15 +131,21 @@ __global__ __launch_bounds__(S::THREADS) void k_gram_tiles(const int8_t *__restr
   if (threadIdx.x == 0) part[bid] = ss;
 }
 
-typedef GemmShape<256, 256, 2, 4> GramShape;
+typedef StreamShape<256, 256, 2, 4, 4> GramShape;
 
 void launch_gram_tiles(const int8_t *G, int64_t m, int64_t ldg, const int32_t *nrm,
                        const double *etab, int64_t etab_len, double lambda, const TileLayout &L,
                        int32_t *D, float *A, double *tnorm_part, hipStream_t s) {
   const int SB = L.nb / GramShape::kBM;
   const int64_t blocks = L.ntiles() * SB * SB;
-  hipLaunchKernelGGL((k_gram_tiles<GramShape>), dim3((unsigned)blocks), dim3(GramShape::THREADS), 0,
-                     s, G, L.n, m,
+  static bool attr = false;
+  if (!attr) {
+    hipFuncSetAttribute((const void *)k_gram_tiles<GramShape>,
+                        hipFuncAttributeMaxDynamicSharedMemorySize, GramShape::LDS_BYTES);
+    attr = true;
+  }
+  hipLaunchKernelGGL((k_gram_tiles<GramShape>), dim3((unsigned)blocks), dim3(GramShape::THREADS),
+                     GramShape::LDS_BYTES, s, G, L.n, m,
                      ldg, nrm, etab, etab_len, lambda, L.nb, SB, D, A, tnorm_part);
 }
 
@@ -197,7 +204,7 @@ __global__ __launch_bounds__(S::THREADS) void k_cross_gram(const int8_t *__restr
                                                     int64_t cols, int64_t nbc,
                                                     int32_t *__restrict__ Dt, int64_t ldd) {
   constexpr int BM = S::kBM, BN = S::kBN;
-  __shared__ __attribute__((aligned(16))) uint8_t lds[S::LDS_BYTES];
+  extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
   const int64_t bid = xcd_remap(blockIdx.x, gridDim.x);
   const int64_t bi = bid / nbc, bj = bid % nbc;
   const int64_t row0 = bi * BM, col0 = bj * BN;
@@ -206,8 +213,9 @@ __global__ __launch_bounds__(S::THREADS) void k_cross_gram(const int8_t *__restr
   OpI8::acc_t acc[S::WTM][S::WTN];
   zero_acc(acc);
   if (arows > 0 && brows > 0)
-    gemm_nt_core<OpI8, S>(OpI8{}, (const uint8_t *)T + row0 * ldt, ldt, arows,
-                          (const uint8_t *)G + col0 * ldg, ldg, brows, m, acc, lds);
+    gemm_nt_stream<OpI8, S>(
+        ContigSrc<OpI8>{(const uint8_t *)T + row0 * ldt, (const uint8_t *)G + col0 * ldg, OpI8{}},
+        ldt, arows, ldg, brows, m, acc, lds);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
   for (int tm = 0; tm < S::WTM; ++tm)
@@ -227,8 +235,14 @@ void launch_cross_gram(const int8_t *T, int64_t nt_rows, const int32_t *nrm_t, c
                        int64_t cols_padded, int32_t *Dt, int64_t ldd, hipStream_t s) {
   constexpr int BM = GramShape::kBM, BN = GramShape::kBN;
   const int64_t nbr = (nt_rows + BM - 1) / BM, nbc = (cols_padded + BN - 1) / BN;
+  static bool attr = false;
+  if (!attr) {
+    hipFuncSetAttribute((const void *)k_cross_gram<GramShape>,
+                        hipFuncAttributeMaxDynamicSharedMemorySize, GramShape::LDS_BYTES);
+    attr = true;
+  }
   hipLaunchKernelGGL((k_cross_gram<GramShape>), dim3((unsigned)(nbr * nbc)),
-                     dim3(GramShape::THREADS), 0, s, T,
+                     dim3(GramShape::THREADS), GramShape::LDS_BYTES, s, T,
                      nt_rows, nrm_t, G, n, m, ldt, ldg, nrm_g, cols_padded, nbc, Dt, ldd);
 }
 

@@ -265,6 +265,191 @@ KRR_DEV void gemm_nt_core(const Op &op, const uint8_t *__restrict__ A, int64_t l
   (void)BN;
 }
 
+// ---------------------------------------------------------------------------
+// Streamed NT-GEMM core, same product as gemm_nt_core, for large blocks.
+// Full 64-byte K slabs go global -> LDS by direct-to-LDS loads
+// (global_load_lds_dwordx4: lane l of an instruction fills bytes 16l .. 16l+15
+// of a 1 KiB LDS run, no register staging) into an NST-deep ring; a partial
+// last slab goes through registers with zero fill.  LDS rows are 64 bytes,
+// unpadded: 16-byte chunk c of row r sits at chunk position c ^ swz(r), which
+// puts the fragment reads of 8 or 16 consecutive rows on distinct banks.
+// Each wave double-buffers its MFMA fragments (slab s+1 is read from LDS
+// while the MFMAs of slab s run); one barrier per slab.
+//
+// Rows at or beyond arows / brows are read as copies of the last valid row:
+// they only feed accumulator rows / columns that the caller discards.
+template <int BM, int BN, int WGM, int WGN, int NST>
+struct StreamShape {
+  static constexpr int kBM = BM, kBN = BN, kWGM = WGM, kWGN = WGN, kNST = NST;
+  static constexpr int THREADS = 64 * WGM * WGN, NWAVE = WGM * WGN;
+  static constexpr int WROWS = BM / WGM, WCOLS = BN / WGN;
+  static constexpr int WTM = WROWS / 32, WTN = WCOLS / 32;
+  static constexpr int STAGE = (BM + BN) * 64;          // bytes per ring stage
+  static constexpr int LDS_BYTES = NST * STAGE;
+  static constexpr int LPW = (BM + BN) / 16 / NWAVE;    // 1 KiB loads per wave per slab
+  static_assert(LPW * 16 * NWAVE == BM + BN && BM % 32 == 0 && BN % 32 == 0, "shape");
+  static_assert(NST >= 2 && (NST - 2) * LPW <= 63, "ring depth");
+  KRR_DEV static int row(int wave, int tm, int i, int lane) {
+    return (wave / WGN) * WROWS + tm * 32 + 8 * (i >> 2) + 4 * (lane >> 5) + (i & 3);
+  }
+  KRR_DEV static int col(int wave, int tn, int lane) {
+    return (wave % WGN) * WCOLS + tn * 32 + (lane & 31);
+  }
+};
+
+KRR_DEV int lds_swz(int r) { return ((r >> 1) ^ (r >> 2)) & 3; }
+
+// Counter waits and the workgroup barrier of the streamed core, as inline
+// assembly with a memory clobber: the compiler may neither drop the waits nor
+// move memory operations across them (a fenced __syncthreads() would instead
+// wait for every direct-to-LDS load in flight).
+// Wait until at most N of this wave's vector-memory operations are pending.
+template <int N>
+KRR_DEV void vm_wait() {
+  static_assert(N >= 0 && N < 64, "vmcnt");
+  __builtin_amdgcn_sched_barrier(0);
+  asm volatile("s_waitcnt vmcnt(%0)" ::"n"(N) : "memory");
+  __builtin_amdgcn_sched_barrier(0);
+}
+// Barrier after this wave's LDS reads and writes have completed.
+KRR_DEV void bar_nofence() {
+  __builtin_amdgcn_sched_barrier(0);
+  asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+  __builtin_amdgcn_sched_barrier(0);
+}
+
+// K source of one product: slab s (64 bytes of K) of row 0 of A and of B,
+// and the MFMA operation for that slab.  Plain contiguous operands:
+template <class Op>
+struct ContigSrc {
+  const uint8_t *A, *B;
+  Op o;
+  KRR_DEV const uint8_t *a(int64_t s) const { return A + s * 64; }
+  KRR_DEV const uint8_t *b(int64_t s) const { return B + s * 64; }
+  KRR_DEV Op op(int64_t) const { return o; }
+};
+
+template <class Op, class S, class Src>
+KRR_DEV void gemm_nt_stream(const Src &src, int64_t lda, int arows, int64_t ldb, int brows,
+                            int64_t kbytes, typename Op::acc_t (&acc)[S::WTM][S::WTN],
+                            uint8_t *lds) {
+  constexpr int BM = S::kBM, NST = S::kNST, LPW = S::LPW, WTM = S::WTM, WTN = S::WTN;
+  static_assert(BM % (LPW * 16) == 0, "each wave loads rows of one operand only");
+  typedef __attribute__((address_space(3))) void lds_void;
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int wm = wave / S::kWGN, wn = wave % S::kWGN;
+  const int64_t nfull = kbytes >> 6;
+  const int tailb = (int)(kbytes & 63);
+
+  // rows this wave moves: 16 LPW consecutive rows of A (waves in front) or B
+  const bool side_a = wave * LPW * 16 < BM;
+  const int r0 = side_a ? wave * LPW * 16 : wave * LPW * 16 - BM;
+  const int rows = side_a ? arows : brows;
+  const int64_t ld = side_a ? lda : ldb;
+  uint32_t off[LPW];
+#pragma unroll
+  for (int t = 0; t < LPW; ++t) {
+    const int R = r0 + t * 16 + (lane >> 2);
+    off[t] = (uint32_t)((int64_t)min(R, rows - 1) * ld) + 16u * ((lane & 3) ^ lds_swz(R));
+  }
+  // Direct loads of slab s into ring stage `slot`.  Every call site issues
+  // unconditionally (slabs past the end repeat the last one), so the number
+  // of loads in flight -- and the counter waits below -- never vary.
+  auto issue = [&](int slot, int64_t s) {
+    const uint8_t *base = side_a ? src.a(s) : src.b(s);
+    uint8_t *dst = lds + slot * S::STAGE + wave * LPW * 1024;
+#pragma unroll
+    for (int t = 0; t < LPW; ++t)
+      __builtin_amdgcn_global_load_lds((const void *)(base + off[t]), (lds_void *)(dst + t * 1024),
+                                       16, 0, 0);
+  };
+
+  const int lrow = lane & 31, lhalf = lane >> 5, sw = lds_swz(lrow);
+  const int off0 = lrow * 64 + 16 * ((2 * lhalf) ^ sw);
+  const int off1 = lrow * 64 + 16 * ((2 * lhalf + 1) ^ sw);
+  auto frag = [&](int stage, v4i (&a0)[WTM], v4i (&a1)[WTM], v4i (&b0)[WTN], v4i (&b1)[WTN]) {
+    const uint8_t *base = lds + stage * S::STAGE;
+#pragma unroll
+    for (int tn = 0; tn < WTN; ++tn) {
+      const uint8_t *p = base + (BM + wn * S::WCOLS + tn * 32) * 64;
+      b0[tn] = *(const v4i *)(p + off0);
+      b1[tn] = *(const v4i *)(p + off1);
+    }
+#pragma unroll
+    for (int tm = 0; tm < WTM; ++tm) {
+      const uint8_t *p = base + (wm * S::WROWS + tm * 32) * 64;
+      a0[tm] = *(const v4i *)(p + off0);
+      a1[tm] = *(const v4i *)(p + off1);
+    }
+  };
+  auto mma_all = [&](const Op &o, v4i (&a0)[WTM], v4i (&a1)[WTM], v4i (&b0)[WTN],
+                     v4i (&b1)[WTN]) {
+#pragma unroll
+    for (int tm = 0; tm < WTM; ++tm)
+#pragma unroll
+      for (int tn = 0; tn < WTN; ++tn) o.mma(acc[tm][tn], a0[tm], a1[tm], b0[tn], b1[tn]);
+  };
+
+  v4i xa0[WTM], xa1[WTM], xb0[WTN], xb1[WTN];  // fragments, even slabs
+  v4i ya0[WTM], ya1[WTM], yb0[WTN], yb1[WTN];  // fragments, odd slabs
+  if (nfull > 0) {
+    const int64_t last = nfull - 1;
+#pragma unroll
+    for (int s = 0; s < NST; ++s) issue(s, min((int64_t)s, last));
+    vm_wait<(NST - 1) * LPW>();  // slab 0 landed
+    bar_nofence();
+    frag(0, xa0, xa1, xb0, xb1);
+    Op ox = src.op(0), oy = ox;
+    // Before the MFMAs of slab s: slab s+1 must have landed (slabs s+2 ..
+    // s+NST-1 may still be in flight), every wave must be past its fragment
+    // reads of slab s (whose stage then takes slab s+NST), and slab s+1 is
+    // read into the other fragment set while slab s's MFMAs run.
+    auto advance = [&](int64_t s, v4i (&a0)[WTM], v4i (&a1)[WTM], v4i (&b0)[WTN],
+                       v4i (&b1)[WTN], Op &o) {
+      vm_wait<(NST - 2) * LPW>();
+      bar_nofence();
+      issue((int)(s % NST), min(s + NST, last));
+      frag((int)((s + 1) % NST), a0, a1, b0, b1);
+      o = src.op(min(s + 1, last));
+    };
+    // Fragment reads past the last slab see a repeated slab; for an odd
+    // slab count the extra set is zeroed (branch-free) before its MFMAs.
+    for (int64_t s = 0; s < nfull; s += 2) {
+      advance(s, ya0, ya1, yb0, yb1, oy);
+      mma_all(ox, xa0, xa1, xb0, xb1);
+      advance(s + 1, xa0, xa1, xb0, xb1, ox);
+      const int keep = -(int)(s + 1 < nfull);
+#pragma unroll
+      for (int tm = 0; tm < WTM; ++tm) {
+        ya0[tm] &= keep;
+        ya1[tm] &= keep;
+      }
+      mma_all(oy, ya0, ya1, yb0, yb1);
+    }
+    vm_wait<0>();  // no direct load may land after the ring is handed back
+  }
+  if (tailb) {  // partial last slab through registers, bytes past kbytes zero
+    bar_nofence();  // every wave is past its ring reads
+    const uint8_t *base = side_a ? src.a(nfull) : src.b(nfull);
+    uint8_t *dst = lds + wave * LPW * 1024;
+#pragma unroll
+    for (int t = 0; t < LPW; ++t) {
+      const int c16 = 16 * ((lane & 3) ^ lds_swz(lane >> 2));
+      v4i v = {0, 0, 0, 0};
+      if (c16 < tailb) {
+        v = *(const __attribute__((address_space(1))) v4i *)(base + off[t]);
+        if (c16 + 16 > tailb) v = mask_tail(v, tailb - c16);
+      }
+      *(v4i *)(dst + t * 1024 + lane * 16) = v;
+    }
+    bar_nofence();
+    frag(0, xa0, xa1, xb0, xb1);
+    mma_all(src.op(nfull), xa0, xa1, xb0, xb1);
+  }
+  bar_nofence();  // the ring is free for the caller's next use
+}
+
 template <class AccT, int WTM, int WTN>
 KRR_DEV void zero_acc(AccT (&acc)[WTM][WTN]) {
 #pragma unroll

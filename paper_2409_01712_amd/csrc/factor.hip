@@ -11,6 +11,8 @@
 //   update  A_ij -= L_ik L_jk^T for k < j <= i: FP32 on diagonal tiles and
 //           early panels, otherwise FP16 or FP8 operands chosen per update
 //           from the operand tile norms, always accumulated in FP32.
+#include <type_traits>
+
 #include "common.h"
 #include "internal.h"
 
@@ -549,14 +551,57 @@ struct PanelSet {
   const int *pexp8[KRR_MAX_GROUP];
 };
 
-__global__ __launch_bounds__(256) void k_update(float *__restrict__ Astore, PanelSet ps, int k0,
-                                                int npan, int jlo, int jhi, int NT, int nb, int SB,
-                                                int mode, int allow16, int allow8, int high_panels,
-                                                int fixed_prec, double thr,
-                                                unsigned long long *counts, uint8_t *pmap,
-                                                int64_t ntiles_all) {
-  typedef UpdShape S;
-  __shared__ __attribute__((aligned(16))) uint8_t lds[S::LDS_BYTES];
+// Trailing update of one group of panels: 256 x 256 sub-block (si, sj) of
+// tile (i, j) gets A_ij -= sum_q L_i,k0+q L_j,k0+q^T.  Each panel's operands
+// take the precision chosen for this update; the panels of one precision
+// form one streamed K range (one segment per panel), so a sub-block runs at
+// most three products (FP32, FP16, FP8 operands) into one FP32 accumulator.
+typedef StreamShape<256, 256, 2, 4, 4> UpdStream;
+
+// Segment table in LDS: per precision, the row-0 addresses of the A and B
+// operand blocks of each selected panel (and the FP8 scale codes).
+struct SegTable {
+  uint64_t a[3][KRR_MAX_GROUP];
+  uint64_t b[3][KRR_MAX_GROUP];
+  int sa[KRR_MAX_GROUP], sb[KRR_MAX_GROUP];
+  int cnt[3];
+};
+
+typedef const __attribute__((address_space(3))) SegTable *LdsSegTable;
+typedef const __attribute__((address_space(3))) uint64_t *LdsU64;
+
+template <class Op>
+struct SegSrc {
+  LdsSegTable t;  // LDS address space: plain LDS reads, no flat accesses
+  int p, sh;      // precision index, log2(slabs per panel)
+  KRR_DEV uint64_t seg_base(LdsU64 v, int64_t s) const {
+    const uint64_t x = v[s >> sh];
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)x);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(x >> 32));
+    return ((uint64_t)hi << 32 | lo) + (uint64_t)((s & ((1 << sh) - 1)) << 6);
+  }
+  KRR_DEV const uint8_t *a(int64_t s) const { return (const uint8_t *)seg_base(t->a[p], s); }
+  KRR_DEV const uint8_t *b(int64_t s) const { return (const uint8_t *)seg_base(t->b[p], s); }
+  KRR_DEV Op op(int64_t s) const {
+    if constexpr (std::is_same<Op, OpF8>::value) {
+      OpF8 o;
+      o.sa = __builtin_amdgcn_readfirstlane(t->sa[s >> sh]);
+      o.sb = __builtin_amdgcn_readfirstlane(t->sb[s >> sh]);
+      return o;
+    } else {
+      return Op{};
+    }
+  }
+};
+
+__global__ __launch_bounds__(UpdStream::THREADS) void k_update(
+    float *__restrict__ Astore, PanelSet ps, int k0, int npan, int jlo, int jhi, int NT, int nb,
+    int SB, int mode, int allow16, int allow8, int high_panels, int fixed_prec, double thr,
+    unsigned long long *counts, uint8_t *pmap, int64_t ntiles_all) {
+  typedef UpdStream S;
+  constexpr int BM = S::kBM;
+  extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
+  __shared__ SegTable tab;
   const int64_t bid = xcd_remap(blockIdx.x, gridDim.x);
   const int nsub = SB * SB;
   const int sub = (int)(bid % nsub);
@@ -578,61 +623,67 @@ __global__ __launch_bounds__(256) void k_update(float *__restrict__ Astore, Pane
   const int si = sub / SB, sj = sub % SB;
   const int64_t te = (int64_t)nb * nb;
 
-  auto choose = [&](int q) {
-    const int k = k0 + q;
-    const int64_t a = i - k - 1, b = j - k - 1;
-    int prec = KRR_PREC_FP32;
-    if (i != j && k >= high_panels) {
-      if (mode == KRR_POLICY_FIXED) {
-        prec = fixed_prec;
-      } else if (mode == KRR_POLICY_ADAPTIVE) {
-        const double prod = (double)ps.pnorm[q][a] * (double)ps.pnorm[q][b];
-        if (allow8 && 0.0625 * prod <= thr)
-          prec = KRR_PREC_FP8;
-        else if (allow16 && 0.00048828125 * prod <= thr)
-          prec = KRR_PREC_FP16;
+  if (threadIdx.x == 0) {
+    int cnt[3] = {0, 0, 0};
+    for (int q = 0; q < npan; ++q) {
+      const int k = k0 + q;
+      const int64_t a = i - k - 1, b = j - k - 1;
+      int prec = KRR_PREC_FP32;
+      if (i != j && k >= high_panels) {
+        if (mode == KRR_POLICY_FIXED) {
+          prec = fixed_prec;
+        } else if (mode == KRR_POLICY_ADAPTIVE) {
+          const double prod = (double)ps.pnorm[q][a] * (double)ps.pnorm[q][b];
+          if (allow8 && 0.0625 * prod <= thr)
+            prec = KRR_PREC_FP8;
+          else if (allow16 && 0.00048828125 * prod <= thr)
+            prec = KRR_PREC_FP16;
+        }
+      }
+      const int c = cnt[prec]++;
+      const int64_t ra = a * te + (int64_t)si * BM * nb, rb = b * te + (int64_t)sj * BM * nb;
+      if (prec == KRR_PREC_FP32) {
+        tab.a[0][c] = (uint64_t)(ps.P32[q] + ra);
+        tab.b[0][c] = (uint64_t)(ps.P32[q] + rb);
+      } else if (prec == KRR_PREC_FP16) {
+        tab.a[1][c] = (uint64_t)(ps.P16[q] + ra);
+        tab.b[1][c] = (uint64_t)(ps.P16[q] + rb);
+      } else {
+        tab.a[2][c] = (uint64_t)(ps.P8[q] + ra);
+        tab.b[2][c] = (uint64_t)(ps.P8[q] + rb);
+        tab.sa[c] = 127 - ps.pexp8[q][a];
+        tab.sb[c] = 127 - ps.pexp8[q][b];
+      }
+      if (sub == 0) {
+        atomicAdd(&counts[prec], 1ULL);
+        if (pmap) pmap[(int64_t)k * ntiles_all + i * (i + 1) / 2 + j] = (uint8_t)prec;
       }
     }
-    return prec;
-  };
-  // One pass per operand type (FP32 panels, then FP16, then FP8), so each
-  // MFMA flavour is instantiated once and the shared accumulator stays put.
+    tab.cnt[0] = cnt[0];
+    tab.cnt[1] = cnt[1];
+    tab.cnt[2] = cnt[2];
+  }
+  __syncthreads();
+  const int c32 = __builtin_amdgcn_readfirstlane(tab.cnt[0]);
+  const int c16 = __builtin_amdgcn_readfirstlane(tab.cnt[1]);
+  const int c8 = __builtin_amdgcn_readfirstlane(tab.cnt[2]);
+  // slabs (64 bytes of K) per panel: nb * element size / 64
+  const int sh8 = 31 - __builtin_clz(nb / 64);
+
   OpF32::acc_t acc[S::WTM][S::WTN];
   zero_acc(acc);
-  for (int q = 0; q < npan; ++q) {
-    if (choose(q) != KRR_PREC_FP32) continue;
-    const int64_t a = i - (k0 + q) - 1, b = j - (k0 + q) - 1;
-    gemm_nt_core<OpF32, S>(OpF32{}, (const uint8_t *)(ps.P32[q] + a * te + (int64_t)si * UB * nb),
-                           (int64_t)nb * 4, UB,
-                           (const uint8_t *)(ps.P32[q] + b * te + (int64_t)sj * UB * nb),
-                           (int64_t)nb * 4, UB, (int64_t)nb * 4, acc, lds);
-  }
-  for (int q = 0; q < npan; ++q) {
-    if (choose(q) != KRR_PREC_FP16) continue;
-    const int64_t a = i - (k0 + q) - 1, b = j - (k0 + q) - 1;
-    gemm_nt_core<OpF16, S>(OpF16{}, (const uint8_t *)(ps.P16[q] + a * te + (int64_t)si * UB * nb),
-                           (int64_t)nb * 2, UB,
-                           (const uint8_t *)(ps.P16[q] + b * te + (int64_t)sj * UB * nb),
-                           (int64_t)nb * 2, UB, (int64_t)nb * 2, acc, lds);
-  }
-  for (int q = 0; q < npan; ++q) {
-    if (choose(q) != KRR_PREC_FP8) continue;
-    const int64_t a = i - (k0 + q) - 1, b = j - (k0 + q) - 1;
-    OpF8 op;
-    op.sa = 127 - ps.pexp8[q][a];
-    op.sb = 127 - ps.pexp8[q][b];
-    gemm_nt_core<OpF8, S>(op, ps.P8[q] + a * te + (int64_t)si * UB * nb, nb, UB,
-                          ps.P8[q] + b * te + (int64_t)sj * UB * nb, nb, UB, nb, acc, lds);
-  }
-  if (sub == 0 && threadIdx.x == 0) {
-    for (int q = 0; q < npan; ++q) {
-      const int prec = choose(q);
-      atomicAdd(&counts[prec], 1ULL);
-      if (pmap) pmap[(int64_t)(k0 + q) * ntiles_all + i * (i + 1) / 2 + j] = (uint8_t)prec;
-    }
-  }
+  if (c32 > 0)
+    gemm_nt_stream<OpF32, S>(SegSrc<OpF32>{(LdsSegTable)&tab, 0, sh8 + 2}, (int64_t)nb * 4, BM,
+                             (int64_t)nb * 4, BM, (int64_t)c32 * nb * 4, acc, lds);
+  if (c16 > 0)
+    gemm_nt_stream<OpF16, S>(SegSrc<OpF16>{(LdsSegTable)&tab, 1, sh8 + 1}, (int64_t)nb * 2, BM,
+                             (int64_t)nb * 2, BM, (int64_t)c16 * nb * 2, acc, lds);
+  if (c8 > 0)
+    gemm_nt_stream<OpF8, S>(SegSrc<OpF8>{(LdsSegTable)&tab, 2, sh8}, (int64_t)nb, BM, (int64_t)nb, BM,
+                            (int64_t)c8 * nb, acc, lds);
+
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  float *C = Astore + (i * (i + 1) / 2 + j) * te + (int64_t)si * UB * nb + sj * UB;
+  float *C = Astore + (i * (i + 1) / 2 + j) * te + (int64_t)si * BM * nb + sj * BM;
 #pragma unroll
   for (int tm = 0; tm < S::WTM; ++tm)
 #pragma unroll
@@ -666,11 +717,18 @@ void launch_update(float *Astore, int k0, int npan, int jlo, int jhi, const Tile
     ps.pnorm[q] = pbs[q]->pnorm;
     ps.pexp8[q] = pbs[q]->pexp8;
   }
-  const int SB = L.nb / UB;
+  static bool attr = false;
+  if (!attr) {
+    hipFuncSetAttribute((const void *)k_update, hipFuncAttributeMaxDynamicSharedMemorySize,
+                        UpdStream::LDS_BYTES);
+    attr = true;
+  }
+  const int SB = L.nb / UpdStream::kBM;
   const int64_t blocks = tiles * SB * SB;
-  hipLaunchKernelGGL(k_update, dim3((unsigned)blocks), dim3(256), 0, s, Astore, ps, k0, npan, jlo,
-                     jhi, NT, L.nb, SB, pol.mode, pol.allow16, pol.allow8, pol.high_panels,
-                     pol.fixed_prec, pol.thr, w.counts, pmap, L.ntiles());
+  hipLaunchKernelGGL(k_update, dim3((unsigned)blocks), dim3(UpdStream::THREADS),
+                     UpdStream::LDS_BYTES, s, Astore, ps, k0, npan, jlo, jhi, NT, L.nb, SB,
+                     pol.mode, pol.allow16, pol.allow8, pol.high_panels, pol.fixed_prec, pol.thr,
+                     w.counts, pmap, L.ntiles());
 }
 
 // Test hook: the factorization's FP8 encoder applied elementwise.
