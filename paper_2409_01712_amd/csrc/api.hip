@@ -539,7 +539,10 @@ krr_status krr_factor(krr_context ctx, krr_kernel K, const krr_precision_policy 
   FactorWork w;
   krr_status st = KRR_SUCCESS;
   uint8_t *dmap = nullptr;
-  const int64_t mapsz = L.nt <= 128 ? (int64_t)L.nt * L.ntiles() : 0;
+  // precision of every (panel, tile) update; copied to the host (for the
+  // diagnostics accessor) when it is small
+  const int64_t mapsz = (int64_t)L.nt * L.ntiles();
+  const bool keep_map = L.nt <= 128;
   do {
     if (K->A) {  // consume the build's matrix in place
       F->Lst = K->A;
@@ -552,12 +555,12 @@ krr_status krr_factor(krr_context ctx, krr_kernel K, const krr_precision_policy 
     if ((st = factor_work_alloc(ctx, w, L, allow16 || p.allow_promotion, allow8,
                                 std::min(2 * g, 2 * KRR_MAX_GROUP))) != KRR_SUCCESS)
       break;
-    if (mapsz && (st = dalloc_t(ctx, &dmap, mapsz)) != KRR_SUCCESS) break;
+    if ((st = dalloc_t(ctx, &dmap, mapsz)) != KRR_SUCCESS) break;
     for (int attempt = 0;; ++attempt) {
       if (attempt > 0) launch_expand_tiles(K->D, K->etab, K->etab_len, K->lambda, L, F->Lst, s);
       launch_fill_i32(w.flag, 1, 0, s);
       launch_fill_i32((int32_t *)w.counts, 6, 0, s);
-      if (dmap) launch_fill_u8(dmap, mapsz, 255, s);
+      launch_fill_u8(dmap, mapsz, 255, s);
       UpdatePolicy up;
       up.mode = mode;
       up.allow16 = allow16;
@@ -632,6 +635,7 @@ krr_status krr_factor(krr_context ctx, krr_kernel K, const krr_precision_policy 
         if (waited) ok = ok && hipStreamWaitEvent(s, ctx->ev_update, 0) == hipSuccess;
         if (!ok) { st = KRR_ERROR_HIP; break; }
       }
+      launch_count_pmap(dmap, mapsz, w.counts, s);
       if ((st = launch_ok()) != KRR_SUCCESS) break;
       int32_t hflag = 0;
       unsigned long long hc[3] = {0, 0, 0};
@@ -667,7 +671,7 @@ krr_status krr_factor(krr_context ctx, krr_kernel K, const krr_precision_policy 
       }
       F->info.promotions++;
     }
-    if (st == KRR_SUCCESS && dmap) {
+    if (st == KRR_SUCCESS && keep_map) {
       F->pmap.resize(mapsz);
       if (hipMemcpy(F->pmap.data(), dmap, mapsz, hipMemcpyDeviceToHost) != hipSuccess)
         st = KRR_ERROR_HIP;

@@ -318,14 +318,14 @@ KRR_DEV void bar_nofence() {
   __builtin_amdgcn_sched_barrier(0);
 }
 
-// K source of one product: slab s (64 bytes of K) of row 0 of A and of B,
-// and the MFMA operation for that slab.  Plain contiguous operands:
+// K source of one product: ptr(side_a, s) is the address of slab s (64 bytes
+// of K) in row 0 of A (side_a) or of B; op(s) is the MFMA operation for slab
+// s.  Both are branch-free.  Plain contiguous operands:
 template <class Op>
 struct ContigSrc {
   const uint8_t *A, *B;
   Op o;
-  KRR_DEV const uint8_t *a(int64_t s) const { return A + s * 64; }
-  KRR_DEV const uint8_t *b(int64_t s) const { return B + s * 64; }
+  KRR_DEV const uint8_t *ptr(bool side_a, int64_t s) const { return (side_a ? A : B) + s * 64; }
   KRR_DEV Op op(int64_t) const { return o; }
 };
 
@@ -335,12 +335,14 @@ KRR_DEV void gemm_nt_stream(const Src &src, int64_t lda, int arows, int64_t ldb,
                             uint8_t *lds) {
   constexpr int BM = S::kBM, NST = S::kNST, LPW = S::LPW, WTM = S::WTM, WTN = S::WTN;
   static_assert(BM % (LPW * 16) == 0, "each wave loads rows of one operand only");
+  static_assert(WTM % 2 == 0, "MFMA halves");
   typedef __attribute__((address_space(3))) void lds_void;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int wm = wave / S::kWGN, wn = wave % S::kWGN;
-  const int64_t nfull = kbytes >> 6;
-  const int tailb = (int)(kbytes & 63);
+  const int64_t nfull = kbytes >> 6;       // whole 64-byte slabs
+  const int64_t nmain = nfull & ~(int64_t)1;  // pairs of them go through the ring
+  const int64_t nslab = (kbytes + 63) >> 6;
 
   // rows this wave moves: 16 LPW consecutive rows of A (waves in front) or B
   const bool side_a = wave * LPW * 16 < BM;
@@ -353,11 +355,11 @@ KRR_DEV void gemm_nt_stream(const Src &src, int64_t lda, int arows, int64_t ldb,
     const int R = r0 + t * 16 + (lane >> 2);
     off[t] = (uint32_t)((int64_t)min(R, rows - 1) * ld) + 16u * ((lane & 3) ^ lds_swz(R));
   }
-  // Direct loads of slab s into ring stage `slot`.  Every call site issues
-  // unconditionally (slabs past the end repeat the last one), so the number
-  // of loads in flight -- and the counter waits below -- never vary.
+  // Direct loads of slab s into ring stage `slot`.  Issued unconditionally
+  // (slabs past the last repeat it), so the number of loads in flight -- and
+  // the counter waits -- never vary.
   auto issue = [&](int slot, int64_t s) {
-    const uint8_t *base = side_a ? src.a(s) : src.b(s);
+    const uint8_t *base = src.ptr(side_a, s);
     uint8_t *dst = lds + slot * S::STAGE + wave * LPW * 1024;
 #pragma unroll
     for (int t = 0; t < LPW; ++t)
@@ -383,69 +385,70 @@ KRR_DEV void gemm_nt_stream(const Src &src, int64_t lda, int arows, int64_t ldb,
       a1[tm] = *(const v4i *)(p + off1);
     }
   };
-  auto mma_all = [&](const Op &o, v4i (&a0)[WTM], v4i (&a1)[WTM], v4i (&b0)[WTN],
-                     v4i (&b1)[WTN]) {
+  auto mma_rows = [&](int tm0, int tm1, const Op &o, v4i (&a0)[WTM], v4i (&a1)[WTM],
+                      v4i (&b0)[WTN], v4i (&b1)[WTN]) {
 #pragma unroll
-    for (int tm = 0; tm < WTM; ++tm)
+    for (int tm = tm0; tm < tm1; ++tm)
 #pragma unroll
       for (int tn = 0; tn < WTN; ++tn) o.mma(acc[tm][tn], a0[tm], a1[tm], b0[tn], b1[tn]);
   };
 
   v4i xa0[WTM], xa1[WTM], xb0[WTN], xb1[WTN];  // fragments, even slabs
   v4i ya0[WTM], ya1[WTM], yb0[WTN], yb1[WTN];  // fragments, odd slabs
-  if (nfull > 0) {
-    const int64_t last = nfull - 1;
+  if (nmain > 0) {
+    const int64_t last = nmain - 1;
 #pragma unroll
     for (int s = 0; s < NST; ++s) issue(s, min((int64_t)s, last));
     vm_wait<(NST - 1) * LPW>();  // slab 0 landed
     bar_nofence();
     frag(0, xa0, xa1, xb0, xb1);
     Op ox = src.op(0), oy = ox;
-    // Before the MFMAs of slab s: slab s+1 must have landed (slabs s+2 ..
-    // s+NST-1 may still be in flight), every wave must be past its fragment
-    // reads of slab s (whose stage then takes slab s+NST), and slab s+1 is
-    // read into the other fragment set while slab s's MFMAs run.
-    auto advance = [&](int64_t s, v4i (&a0)[WTM], v4i (&a1)[WTM], v4i (&b0)[WTN],
-                       v4i (&b1)[WTN], Op &o) {
+    // Slab s, fragments in (c*): once slab s+1 has landed everywhere (slabs
+    // s+2 .. s+NST-1 may still be in flight) and every wave holds slab s in
+    // registers, the MFMAs of slab s are issued in two halves with the direct
+    // loads of slab s+NST (into slab s's stage) and the fragment reads of
+    // slab s+1 (into n*) between them.  The scheduling barriers pin this
+    // order; nothing in the step branches.
+    auto step = [&](int64_t s, const Op &co, v4i (&ca0)[WTM], v4i (&ca1)[WTM], v4i (&cb0)[WTN],
+                    v4i (&cb1)[WTN], Op &no, v4i (&na0)[WTM], v4i (&na1)[WTM],
+                    v4i (&nb0)[WTN], v4i (&nb1)[WTN]) {
       vm_wait<(NST - 2) * LPW>();
       bar_nofence();
+      mma_rows(0, WTM / 2, co, ca0, ca1, cb0, cb1);
+      __builtin_amdgcn_sched_barrier(0);
       issue((int)(s % NST), min(s + NST, last));
-      frag((int)((s + 1) % NST), a0, a1, b0, b1);
-      o = src.op(min(s + 1, last));
+      frag((int)((s + 1) % NST), na0, na1, nb0, nb1);
+      no = src.op(min(s + 1, last));
+      __builtin_amdgcn_sched_barrier(0);
+      mma_rows(WTM / 2, WTM, co, ca0, ca1, cb0, cb1);
     };
-    // Fragment reads past the last slab see a repeated slab; for an odd
-    // slab count the extra set is zeroed (branch-free) before its MFMAs.
-    for (int64_t s = 0; s < nfull; s += 2) {
-      advance(s, ya0, ya1, yb0, yb1, oy);
-      mma_all(ox, xa0, xa1, xb0, xb1);
-      advance(s + 1, xa0, xa1, xb0, xb1, ox);
-      const int keep = -(int)(s + 1 < nfull);
-#pragma unroll
-      for (int tm = 0; tm < WTM; ++tm) {
-        ya0[tm] &= keep;
-        ya1[tm] &= keep;
-      }
-      mma_all(oy, ya0, ya1, yb0, yb1);
+    for (int64_t s = 0; s < nmain; s += 2) {
+      step(s, ox, xa0, xa1, xb0, xb1, oy, ya0, ya1, yb0, yb1);
+      // past the last pair this reads a repeated slab that is never used
+      step(s + 1, oy, ya0, ya1, yb0, yb1, ox, xa0, xa1, xb0, xb1);
     }
     vm_wait<0>();  // no direct load may land after the ring is handed back
   }
-  if (tailb) {  // partial last slab through registers, bytes past kbytes zero
-    bar_nofence();  // every wave is past its ring reads
-    const uint8_t *base = side_a ? src.a(nfull) : src.b(nfull);
+  // odd last whole slab and partial slab: through registers, one at a time,
+  // bytes past kbytes read as zero
+  for (int64_t s = nmain; s < nslab; ++s) {
+    const int valid = (int)min((int64_t)64, kbytes - s * 64);
+    bar_nofence();  // every wave is past its reads of the ring
+    const uint8_t *base = src.ptr(side_a, s);
     uint8_t *dst = lds + wave * LPW * 1024;
 #pragma unroll
     for (int t = 0; t < LPW; ++t) {
       const int c16 = 16 * ((lane & 3) ^ lds_swz(lane >> 2));
       v4i v = {0, 0, 0, 0};
-      if (c16 < tailb) {
+      if (c16 < valid) {
         v = *(const __attribute__((address_space(1))) v4i *)(base + off[t]);
-        if (c16 + 16 > tailb) v = mask_tail(v, tailb - c16);
+        if (c16 + 16 > valid) v = mask_tail(v, valid - c16);
       }
       *(v4i *)(dst + t * 1024 + lane * 16) = v;
     }
     bar_nofence();
     frag(0, xa0, xa1, xb0, xb1);
-    mma_all(src.op(nfull), xa0, xa1, xb0, xb1);
+    mma_rows(0, WTM, src.op(s), xa0, xa1, xb0, xb1);
   }
   bar_nofence();  // the ring is free for the caller's next use
 }

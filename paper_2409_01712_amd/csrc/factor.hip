@@ -580,8 +580,9 @@ struct SegSrc {
     const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(x >> 32));
     return ((uint64_t)hi << 32 | lo) + (uint64_t)((s & ((1 << sh) - 1)) << 6);
   }
-  KRR_DEV const uint8_t *a(int64_t s) const { return (const uint8_t *)seg_base(t->a[p], s); }
-  KRR_DEV const uint8_t *b(int64_t s) const { return (const uint8_t *)seg_base(t->b[p], s); }
+  KRR_DEV const uint8_t *ptr(bool side_a, int64_t s) const {
+    return (const uint8_t *)seg_base(side_a ? t->a[p] : t->b[p], s);
+  }
   KRR_DEV Op op(int64_t s) const {
     if constexpr (std::is_same<Op, OpF8>::value) {
       OpF8 o;
@@ -597,66 +598,90 @@ struct SegSrc {
 __global__ __launch_bounds__(UpdStream::THREADS) void k_update(
     float *__restrict__ Astore, PanelSet ps, int k0, int npan, int jlo, int jhi, int NT, int nb,
     int SB, int mode, int allow16, int allow8, int high_panels, int fixed_prec, double thr,
-    unsigned long long *counts, uint8_t *pmap, int64_t ntiles_all) {
+    uint8_t *__restrict__ pmap, int64_t ntiles_all) {
   typedef UpdStream S;
   constexpr int BM = S::kBM;
   extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
   __shared__ SegTable tab;
-  const int64_t bid = xcd_remap(blockIdx.x, gridDim.x);
-  const int nsub = SB * SB;
-  const int sub = (int)(bid % nsub);
-  int64_t tt = bid / nsub;
+  // Blocks of the diagonal tiles (FP32 operands, the longest) are dispatched
+  // first; only their lower sub-blocks are computed.  The off-diagonal blocks
+  // follow, remapped so that the sub-blocks of one tile share an XCD.
+  const int nsd = SB * (SB + 1) / 2, nsub = SB * SB;
+  const int64_t ndb = (int64_t)(jhi - jlo + 1) * nsd;
   int64_t i, j;
-  if (jhi == NT - 1) {  // triangle of all tiles right of column jlo
-    int ta, tb;
-    tri_decode(tt, ta, tb);
-    i = jlo + ta;
-    j = jlo + tb;
-  } else {  // a few columns: walk them
-    j = jlo;
-    while (tt >= NT - j) {
-      tt -= NT - j;
-      ++j;
+  int si, sj;
+  if ((int64_t)blockIdx.x < ndb) {
+    i = j = jlo + blockIdx.x / nsd;
+    tri_decode(blockIdx.x % nsd, si, sj);
+  } else {
+    const int64_t h = blockIdx.x - ndb;
+    const int64_t bid = xcd_remap(h, (int64_t)gridDim.x - ndb);
+    const int sub = (int)(bid % nsub);
+    int64_t tt = bid / nsub;
+    si = sub / SB;
+    sj = sub % SB;
+    if (jhi == NT - 1) {  // strict lower triangle of the tiles right of column jlo
+      int ta, tb;
+      tri_decode(tt, ta, tb);
+      i = jlo + ta + 1;
+      j = jlo + tb;
+    } else {  // a few columns: walk them
+      j = jlo;
+      while (tt >= NT - 1 - j) {
+        tt -= NT - 1 - j;
+        ++j;
+      }
+      i = j + 1 + tt;
     }
-    i = j + tt;
   }
-  const int si = sub / SB, sj = sub % SB;
   const int64_t te = (int64_t)nb * nb;
+  const bool first_sub = (si == 0 && sj == 0);
 
+  // Thread q < npan picks the operand precision of panel q (all panels'
+  // loads in flight together); thread 0 then lists the panels per precision.
+  __shared__ uint64_t qa[KRR_MAX_GROUP], qb[KRR_MAX_GROUP];
+  __shared__ int qp[KRR_MAX_GROUP], qsa[KRR_MAX_GROUP], qsb[KRR_MAX_GROUP];
+  if (threadIdx.x < npan) {
+    const int q = threadIdx.x, k = k0 + q;
+    const int64_t a = i - k - 1, b = j - k - 1;
+    int prec = KRR_PREC_FP32;
+    if (i != j && k >= high_panels) {
+      if (mode == KRR_POLICY_FIXED) {
+        prec = fixed_prec;
+      } else if (mode == KRR_POLICY_ADAPTIVE) {
+        const double prod = (double)ps.pnorm[q][a] * (double)ps.pnorm[q][b];
+        if (allow8 && 0.0625 * prod <= thr)
+          prec = KRR_PREC_FP8;
+        else if (allow16 && 0.00048828125 * prod <= thr)
+          prec = KRR_PREC_FP16;
+      }
+    }
+    const int64_t ra = a * te + (int64_t)si * BM * nb, rb = b * te + (int64_t)sj * BM * nb;
+    if (prec == KRR_PREC_FP32) {
+      qa[q] = (uint64_t)(ps.P32[q] + ra);
+      qb[q] = (uint64_t)(ps.P32[q] + rb);
+    } else if (prec == KRR_PREC_FP16) {
+      qa[q] = (uint64_t)(ps.P16[q] + ra);
+      qb[q] = (uint64_t)(ps.P16[q] + rb);
+    } else {
+      qa[q] = (uint64_t)(ps.P8[q] + ra);
+      qb[q] = (uint64_t)(ps.P8[q] + rb);
+      qsa[q] = 127 - ps.pexp8[q][a];
+      qsb[q] = 127 - ps.pexp8[q][b];
+    }
+    qp[q] = prec;
+    if (first_sub) pmap[(int64_t)k * ntiles_all + i * (i + 1) / 2 + j] = (uint8_t)prec;
+  }
+  __syncthreads();
   if (threadIdx.x == 0) {
     int cnt[3] = {0, 0, 0};
     for (int q = 0; q < npan; ++q) {
-      const int k = k0 + q;
-      const int64_t a = i - k - 1, b = j - k - 1;
-      int prec = KRR_PREC_FP32;
-      if (i != j && k >= high_panels) {
-        if (mode == KRR_POLICY_FIXED) {
-          prec = fixed_prec;
-        } else if (mode == KRR_POLICY_ADAPTIVE) {
-          const double prod = (double)ps.pnorm[q][a] * (double)ps.pnorm[q][b];
-          if (allow8 && 0.0625 * prod <= thr)
-            prec = KRR_PREC_FP8;
-          else if (allow16 && 0.00048828125 * prod <= thr)
-            prec = KRR_PREC_FP16;
-        }
-      }
-      const int c = cnt[prec]++;
-      const int64_t ra = a * te + (int64_t)si * BM * nb, rb = b * te + (int64_t)sj * BM * nb;
-      if (prec == KRR_PREC_FP32) {
-        tab.a[0][c] = (uint64_t)(ps.P32[q] + ra);
-        tab.b[0][c] = (uint64_t)(ps.P32[q] + rb);
-      } else if (prec == KRR_PREC_FP16) {
-        tab.a[1][c] = (uint64_t)(ps.P16[q] + ra);
-        tab.b[1][c] = (uint64_t)(ps.P16[q] + rb);
-      } else {
-        tab.a[2][c] = (uint64_t)(ps.P8[q] + ra);
-        tab.b[2][c] = (uint64_t)(ps.P8[q] + rb);
-        tab.sa[c] = 127 - ps.pexp8[q][a];
-        tab.sb[c] = 127 - ps.pexp8[q][b];
-      }
-      if (sub == 0) {
-        atomicAdd(&counts[prec], 1ULL);
-        if (pmap) pmap[(int64_t)k * ntiles_all + i * (i + 1) / 2 + j] = (uint8_t)prec;
+      const int p = qp[q], c = cnt[p]++;
+      tab.a[p][c] = qa[q];
+      tab.b[p][c] = qb[q];
+      if (p == KRR_PREC_FP8) {
+        tab.sa[c] = qsa[q];
+        tab.sb[c] = qsb[q];
       }
     }
     tab.cnt[0] = cnt[0];
@@ -692,7 +717,10 @@ __global__ __launch_bounds__(UpdStream::THREADS) void k_update(
       for (int e = 0; e < 16; ++e) {
         const int r = S::row(wave, tm, e, lane);
         const int c = S::col(wave, tn, lane);
-        C[(int64_t)r * nb + c] -= acc[tm][tn][e];
+        // one FP32 add per element in L2, no read round trip; every element
+        // gets exactly one add per launch, so the result is C - acc rounded
+        // once, as a plain read-modify-write would give
+        unsafeAtomicAdd(C + (int64_t)r * nb + c, -acc[tm][tn][e]);
       }
 }
 
@@ -702,12 +730,12 @@ void launch_update(float *Astore, int k0, int npan, int jlo, int jhi, const Tile
   const int NT = L.nt;
   if (npan <= 0 || jlo > jhi || jlo >= NT) return;
   if (jhi > NT - 1) jhi = NT - 1;
-  int64_t tiles = 0;
+  int64_t offdiag = 0;  // tiles (i, j), jlo <= j <= jhi, i > j
   if (jhi == NT - 1) {
     const int64_t T = NT - jlo;
-    tiles = T * (T + 1) / 2;
+    offdiag = T * (T - 1) / 2;
   } else {
-    for (int j = jlo; j <= jhi; ++j) tiles += NT - j;
+    for (int j = jlo; j <= jhi; ++j) offdiag += NT - 1 - j;
   }
   PanelSet ps{};
   for (int q = 0; q < npan; ++q) {
@@ -724,11 +752,33 @@ void launch_update(float *Astore, int k0, int npan, int jlo, int jhi, const Tile
     attr = true;
   }
   const int SB = L.nb / UpdStream::kBM;
-  const int64_t blocks = tiles * SB * SB;
+  const int64_t blocks = (int64_t)(jhi - jlo + 1) * SB * (SB + 1) / 2 + offdiag * SB * SB;
   hipLaunchKernelGGL(k_update, dim3((unsigned)blocks), dim3(UpdStream::THREADS),
                      UpdStream::LDS_BYTES, s, Astore, ps, k0, npan, jlo, jhi, NT, L.nb, SB,
                      pol.mode, pol.allow16, pol.allow8, pol.high_panels, pol.fixed_prec, pol.thr,
-                     w.counts, pmap, L.ntiles());
+                     pmap, L.ntiles());
+}
+
+// Updates per operand precision, from the precision map (255 = no update).
+__global__ void k_count_pmap(const uint8_t *__restrict__ pmap, int64_t n,
+                             unsigned long long *counts) {
+  unsigned long long c[3] = {0, 0, 0};
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int v = pmap[e];
+    if (v < 3) c[v]++;
+  }
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    unsigned long long v = c[q];
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if ((threadIdx.x & 63) == 0 && v) atomicAdd(&counts[q], v);
+  }
+}
+
+void launch_count_pmap(const uint8_t *pmap, int64_t n, unsigned long long *counts,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(k_count_pmap, dim3(256), dim3(256), 0, s, pmap, n, counts);
 }
 
 // Test hook: the factorization's FP8 encoder applied elementwise.

@@ -79,6 +79,9 @@ void launch_convert_panel(float *Astore, int k, const TileLayout &L, FactorWork 
 void launch_update(float *Astore, int k0, int npan, int jlo, int jhi, const TileLayout &L,
                    const UpdatePolicy &pol, FactorWork &w, const PanelBuf *const *pbs,
                    uint8_t *pmap, hipStream_t s);
+// counts[p] += number of entries of pmap equal to p (p = 0, 1, 2)
+void launch_count_pmap(const uint8_t *pmap, int64_t n, unsigned long long *counts,
+                       hipStream_t s);
 
 void launch_encode_fp8(const float *x, int64_t n, uint8_t *out, hipStream_t s);
 
