@@ -335,8 +335,7 @@ KRR_DEV void gemm_nt_stream(const Src &src, int64_t lda, int arows, int64_t ldb,
                             uint8_t *lds) {
   constexpr int BM = S::kBM, NST = S::kNST, LPW = S::LPW, WTM = S::WTM, WTN = S::WTN;
   static_assert(BM % (LPW * 16) == 0, "each wave loads rows of one operand only");
-  static_assert(WTM % 2 == 0, "MFMA halves");
-  typedef __attribute__((address_space(3))) void lds_void;
+    typedef __attribute__((address_space(3))) void lds_void;
   const int lane = threadIdx.x & 63;
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int wm = wave / S::kWGN, wn = wave % S::kWGN;
@@ -405,22 +404,18 @@ KRR_DEV void gemm_nt_stream(const Src &src, int64_t lda, int arows, int64_t ldb,
     Op ox = src.op(0), oy = ox;
     // Slab s, fragments in (c*): once slab s+1 has landed everywhere (slabs
     // s+2 .. s+NST-1 may still be in flight) and every wave holds slab s in
-    // registers, the MFMAs of slab s are issued in two halves with the direct
-    // loads of slab s+NST (into slab s's stage) and the fragment reads of
-    // slab s+1 (into n*) between them.  The scheduling barriers pin this
-    // order; nothing in the step branches.
+    // registers, the direct loads of slab s+NST (into slab s's stage) and the
+    // fragment reads of slab s+1 (into n*) are issued with the MFMAs of slab
+    // s.  Nothing in the step branches.
     auto step = [&](int64_t s, const Op &co, v4i (&ca0)[WTM], v4i (&ca1)[WTM], v4i (&cb0)[WTN],
                     v4i (&cb1)[WTN], Op &no, v4i (&na0)[WTM], v4i (&na1)[WTM],
                     v4i (&nb0)[WTN], v4i (&nb1)[WTN]) {
       vm_wait<(NST - 2) * LPW>();
       bar_nofence();
-      mma_rows(0, WTM / 2, co, ca0, ca1, cb0, cb1);
-      __builtin_amdgcn_sched_barrier(0);
       issue((int)(s % NST), min(s + NST, last));
       frag((int)((s + 1) % NST), na0, na1, nb0, nb1);
       no = src.op(min(s + 1, last));
-      __builtin_amdgcn_sched_barrier(0);
-      mma_rows(WTM / 2, WTM, co, ca0, ca1, cb0, cb1);
+      mma_rows(0, WTM, co, ca0, ca1, cb0, cb1);  // the compiler interleaves
     };
     for (int64_t s = 0; s < nmain; s += 2) {
       step(s, ox, xa0, xa1, xb0, xb1, oy, ya0, ya1, yb0, yb1);

@@ -16,9 +16,9 @@ namespace krr {
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef double v4d __attribute__((ext_vector_type(4)));
 
-// Skinny products on 16 x 16 x 4 MFMA tiles.  A wavefront owns 16 output rows
-// and 16 * NCB columns.  Lane l supplies, for each of four consecutive MFMAs,
-// the A element (row l % 16, k = 4 (l / 16) + e) and the B element
+// Skinny products on 16 x 16 x 4 MFMA tiles.  A wavefront owns a job of 16
+// output rows and 16 columns.  Lane l supplies, for each of four consecutive
+// MFMAs, the A element (row l % 16, k = 4 (l / 16) + e) and the B element
 // (k = 4 (l / 16) + e, column l % 16): both operands use the same k mapping,
 // so each group of four MFMAs sums k over a 16-wide block exactly once.  A
 // comes straight from memory (a tile of L, or exp(-gamma d) through the FP64
@@ -27,49 +27,27 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 // holds row 4 (l / 16) + i, column l % 16 in lane l, register i; the FP64
 // one holds row 4 i + l / 16, column l % 16.
 
-// Out[rows] (=|-=) M V or M^T V for one nb x nb FP32 tile M (row-major) and an
-// nb x r block V (row-major, leading dimension r).  64 rows per workgroup.
-// mode 0: M = Mbase, Out = Obase (diagonal step; tri limits the k range)
-// mode 1: forward panel, tile i = k + 1 + blockIdx.x: M = tile (i, k), Out row block i
-// mode 2: backward panel, tile j = blockIdx.x: M = tile (k, j) (transposed), Out row block j
-template <bool TRANS, bool SUB, int NCB>
-__global__ __launch_bounds__(256) void k_tri_apply(const float *__restrict__ Mbase,
-                                                   const float *__restrict__ V, float *Obase,
-                                                   int mode, int k, int nb, int r, int tri) {
-  const int64_t te = (int64_t)nb * nb;
-  const float *M = Mbase;
-  float *Out = Obase;
-  if (mode == 1) {
-    const int64_t i = k + 1 + blockIdx.x;
-    M = Mbase + (i * (i + 1) / 2 + k) * te;
-    Out = Obase + i * nb * (int64_t)r;
-  } else if (mode == 2) {
-    const int64_t j = blockIdx.x;
-    M = Mbase + ((int64_t)k * (k + 1) / 2 + j) * te;
-    Out = Obase + j * nb * (int64_t)r;
-  }
+// One 16 x 16 output job per workgroup: out = M[row0 .. row0+15, klo .. khi)
+// V[klo .. khi, col0 .. col0+15] for an nb x nb FP32 tile M (row-major; with
+// TRANS read transposed, M(row, k) = Mt[k][row]) and an nb x r row-major
+// block V; klo, khi multiples of 16.  The four waves take the 16-wide k
+// blocks round robin, each with all its loads in flight at once (at most
+// eight blocks: nb <= 512), and the partial sums are added in wave order.
+template <bool TRANS>
+__device__ __forceinline__ v4f job_product(const float *__restrict__ M, const float *V, int nb,
+                                           int r, int row0, int col0, int klo, int khi,
+                                           v4f (*red)[64]) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int li = lane & 15, lg = lane >> 4;
-  const int rb = blockIdx.y;
-  const int row0 = rb * 64 + wave * 16;
-  const int col0 = blockIdx.z * 16 * NCB;
-  int q_lo = 0, q_hi = nb;
-  if (tri) {  // inverse of a lower-triangular tile
-    if (!TRANS) q_hi = (rb + 1) * 64;
-    else q_lo = rb * 64;
-  }
-  v4f acc[NCB];
+  const int R = row0 + li, col = col0 + li;
+  const int cc = min(col, r - 1);  // in-bounds load, zeroed below when col >= r
+  const bool cv = col < r;
+  float a[8][4], b[8][4];
 #pragma unroll
-  for (int c = 0; c < NCB; ++c) acc[c] = (v4f){0.f, 0.f, 0.f, 0.f};
-  const int R = row0 + li;
-  // k advances 64 at a time (q_lo, q_hi are multiples of 64): the loads of
-  // four 16-wide steps are issued before their MFMAs.
-  for (int q = q_lo; q < q_hi; q += 64) {
-    float a[4][4];
-    float b[4][NCB][4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int kk = q + 16 * u + 4 * lg;
+  for (int u = 0; u < 8; ++u) {
+    const int k16 = klo + 16 * (wave + 4 * u);
+    const int kk = k16 + 4 * lg;
+    if (k16 < khi) {
       if (!TRANS) {
         const float4 v = *(const float4 *)(M + (int64_t)R * nb + kk);
         a[u][0] = v.x; a[u][1] = v.y; a[u][2] = v.z; a[u][3] = v.w;
@@ -78,73 +56,98 @@ __global__ __launch_bounds__(256) void k_tri_apply(const float *__restrict__ Mba
         for (int e = 0; e < 4; ++e) a[u][e] = M[(int64_t)(kk + e) * nb + R];
       }
 #pragma unroll
-      for (int c = 0; c < NCB; ++c) {
-        const int col = col0 + c * 16 + li;
-        const int cc = min(col, r - 1);  // in-bounds load, zeroed below when col >= r
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const float v = V[(int64_t)(kk + e) * r + cc];
-          b[u][c][e] = (col < r) ? v : 0.f;
-        }
+      for (int e = 0; e < 4; ++e) {
+        const float v = V[(int64_t)(kk + e) * r + cc];
+        b[u][e] = cv ? v : 0.f;
       }
+    } else {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) a[u][e] = b[u][e] = 0.f;
     }
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-#pragma unroll
-      for (int c = 0; c < NCB; ++c)
-#pragma unroll
-        for (int e = 0; e < 4; ++e)
-          acc[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u][e], b[u][c][e], acc[c], 0, 0, 0);
   }
+  v4f acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-  for (int c = 0; c < NCB; ++c) {
-    const int col = col0 + c * 16 + li;
-    if (col >= r) continue;
+  for (int u = 0; u < 8; ++u)
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      float *o = Out + (int64_t)(row0 + 4 * lg + i) * r + col;
-      if (SUB) *o -= acc[c][i];
-      else *o = acc[c][i];
-    }
+    for (int e = 0; e < 4; ++e)
+      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u][e], b[u][e], acc, 0, 0, 0);
+  red[wave][lane] = acc;
+  __syncthreads();
+  v4f sum = red[0][lane];
+#pragma unroll
+  for (int q = 1; q < 4; ++q) sum += red[q][lane];
+  return sum;
+}
+
+// Sweep step k, diagonal part:
+//   forward  Z_k = inv(L_kk) B_k     (rows of the inverse need k <= row)
+//   backward X_k = inv(L_kk)^T Z_k   (its transpose, k >= row)
+template <bool FWD>
+__global__ __launch_bounds__(256) void k_sweep_diag(const float *__restrict__ Linv_k,
+                                                    const float *In_k, float *Out_k, int nb,
+                                                    int r) {
+  __shared__ v4f red[4][64];
+  const int CJ = (r + 15) / 16;
+  const int rj = blockIdx.x / CJ, cj = blockIdx.x % CJ;
+  const int row0 = rj * 16, col0 = cj * 16;
+  const v4f acc = job_product<!FWD>(Linv_k, In_k, nb, r, row0, col0, FWD ? 0 : row0,
+                                    FWD ? row0 + 16 : nb, red);
+  const int lane = threadIdx.x & 63, col = col0 + (lane & 15);
+  if (threadIdx.x < 64 && col < r) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) Out_k[(int64_t)(row0 + 4 * (lane >> 4) + e) * r + col] = acc[e];
   }
 }
 
-template <bool TRANS, bool SUB>
-static void tri_launch(dim3 grid, hipStream_t s, const float *M, const float *V, float *O, int mode,
-                       int k, int nb, int r, int tri) {
-  const int ncb = (r + 15) / 16;
-  if (ncb <= 1) {
-    grid.z = 1;
-    hipLaunchKernelGGL((k_tri_apply<TRANS, SUB, 1>), grid, dim3(256), 0, s, M, V, O, mode, k, nb, r, tri);
-  } else if (ncb <= 2) {
-    grid.z = 1;
-    hipLaunchKernelGGL((k_tri_apply<TRANS, SUB, 2>), grid, dim3(256), 0, s, M, V, O, mode, k, nb, r, tri);
-  } else {
-    grid.z = (unsigned)((r + 63) / 64);
-    hipLaunchKernelGGL((k_tri_apply<TRANS, SUB, 4>), grid, dim3(256), 0, s, M, V, O, mode, k, nb, r, tri);
+// Sweep step k, update part (one job per workgroup):
+//   forward  B_i -= L_ik Z_k,   i > k
+//   backward Z_j -= L_kj^T X_k, j < k
+template <bool FWD>
+__global__ __launch_bounds__(256) void k_sweep_panel(const float *__restrict__ Lst,
+                                                     const float *V_k, float *In, int k, int nb,
+                                                     int r) {
+  __shared__ v4f red[4][64];
+  const int CJ = (r + 15) / 16, per = (nb / 16) * CJ;
+  const int64_t t = blockIdx.x / per;
+  const int rem = (int)(blockIdx.x % per), rj = rem / CJ, cj = rem % CJ;
+  const int64_t i = FWD ? k + 1 + t : t;
+  const int64_t te = (int64_t)nb * nb;
+  const float *M = Lst + (FWD ? i * (i + 1) / 2 + k : (int64_t)k * (k + 1) / 2 + i) * te;
+  const int row0 = rj * 16, col0 = cj * 16;
+  const v4f acc = job_product<!FWD>(M, V_k, nb, r, row0, col0, 0, nb, red);
+  const int lane = threadIdx.x & 63, col = col0 + (lane & 15);
+  if (threadIdx.x < 64 && col < r) {
+    float *o = In + i * (int64_t)nb * r;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) o[(int64_t)(row0 + 4 * (lane >> 4) + e) * r + col] -= acc[e];
   }
 }
 
-// L Z = B: for k: Z_k = inv(L_kk) B_k; B_i -= L_ik Z_k (i > k).
+// L Z = B (B is overwritten).
 void launch_fwd_sweep(const float *Astore, const float *Linv, const TileLayout &L, int r, float *B,
                       float *Z, hipStream_t s) {
-  const int nb = L.nb, NT = L.nt, RB = nb / 64;
+  const int nb = L.nb, NT = L.nt, CJ = (r + 15) / 16, per = (nb / 16) * CJ;
   const int64_t te = (int64_t)nb * nb, vb = (int64_t)nb * r;
   for (int k = 0; k < NT; ++k) {
-    tri_launch<false, false>(dim3(1, RB, 1), s, Linv + k * te, B + k * vb, Z + k * vb, 0, k, nb, r, 1);
+    hipLaunchKernelGGL(k_sweep_diag<true>, dim3(per), dim3(256), 0, s, Linv + k * te, B + k * vb,
+                       Z + k * vb, nb, r);
     if (NT - 1 - k > 0)
-      tri_launch<false, true>(dim3(NT - 1 - k, RB, 1), s, Astore, Z + k * vb, B, 1, k, nb, r, 0);
+      hipLaunchKernelGGL(k_sweep_panel<true>, dim3((unsigned)((NT - 1 - k) * per)), dim3(256), 0,
+                         s, Astore, Z + k * vb, B, k, nb, r);
   }
 }
 
-// L^T X = Z: for k descending: X_k = inv(L_kk)^T Z_k; Z_j -= L_kj^T X_k (j < k).
+// L^T X = Z (Z is overwritten).
 void launch_bwd_sweep(const float *Astore, const float *Linv, const TileLayout &L, int r, float *Z,
                       float *X, hipStream_t s) {
-  const int nb = L.nb, NT = L.nt, RB = nb / 64;
+  const int nb = L.nb, NT = L.nt, CJ = (r + 15) / 16, per = (nb / 16) * CJ;
   const int64_t te = (int64_t)nb * nb, vb = (int64_t)nb * r;
   for (int k = NT - 1; k >= 0; --k) {
-    tri_launch<true, false>(dim3(1, RB, 1), s, Linv + k * te, Z + k * vb, X + k * vb, 0, k, nb, r, 1);
-    if (k > 0) tri_launch<true, true>(dim3(k, RB, 1), s, Astore, X + k * vb, Z, 2, k, nb, r, 0);
+    hipLaunchKernelGGL(k_sweep_diag<false>, dim3(per), dim3(256), 0, s, Linv + k * te, Z + k * vb,
+                       X + k * vb, nb, r);
+    if (k > 0)
+      hipLaunchKernelGGL(k_sweep_panel<false>, dim3((unsigned)(k * per)), dim3(256), 0, s, Astore,
+                         X + k * vb, Z, k, nb, r);
   }
 }
 
