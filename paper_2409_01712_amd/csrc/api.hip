@@ -439,6 +439,7 @@ static void factor_work_free(krr_context c, FactorWork &w, const TileLayout &L) 
   const int64_t te = L.tile_elems(), pt = std::max(L.nt - 1, 1);
   const int sb = L.nb / 128, parts = sb * sb;
   dfree(c, w.W64, te * 8);
+  dfree(c, w.WL64, te * 8);
   dfree(c, w.Winv64, te * 8);
   dfree(c, w.Dinv64, (L.nb / 64) * 64 * 64 * 8);
   dfree(c, w.Tmp64, te / 2 * 8);
@@ -467,6 +468,7 @@ static krr_status factor_work_alloc(krr_context c, FactorWork &w, const TileLayo
     return st;                                                            \
   }
   WA(w.W64, te * 8);
+  WA(w.WL64, te * 8);
   WA(w.Winv64, te * 8);
   WA(w.Dinv64, (L.nb / 64) * 64 * 64 * 8);
   WA(w.Tmp64, te / 2 * 8);

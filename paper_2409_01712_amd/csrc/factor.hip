@@ -96,49 +96,45 @@ KRR_DEV void wave_lds_sync() {
 // column (wave jb owns column jb):
 //   X_ib,jb = -inv(L_ib,ib) sum_{kb=jb}^{ib-1} L_ib,kb X_kb,jb.
 template <typename T>
-__global__ __launch_bounds__(256) void k_potrf_diag64(T *__restrict__ W, int nb, int s,
-                                                      T *__restrict__ Dinv, int32_t *flag,
-                                                      int64_t colbase) {
+KRR_DEV void diag64_body(T (*S)[BS + 1], T (*X)[BS + 1], T *colv, int32_t *flag,
+                            int64_t col0) {
   typedef typename M16<T>::v4 v4;
-  __shared__ T S[BS][BS + 1];  // the block, overwritten by L
-  __shared__ T X[BS][BS + 1];  // inv(L)
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, lg = lane >> 4;
-  T *blk = W + (int64_t)(s * BS) * nb + s * BS;
-  {
-    T v[16];
-#pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int e = tid + 256 * q, r = e / BS, c = e % BS;
-      v[q] = (c <= r) ? blk[(int64_t)r * nb + c] : (T)0;
-    }
-#pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int e = tid + 256 * q;
-      S[e / BS][e % BS] = v[q];
-    }
-  }
-  __syncthreads();
   for (int kb = 0; kb < 4; ++kb) {
     const int b = 16 * kb;
     if (wave == 0) {
+      // lane li holds row li of the block (lanes 16..63 mirror lanes 0..15)
       T d[16], rv[16];
 #pragma unroll
       for (int q = 0; q < 16; ++q) d[q] = S[b + li][b + q];
+      int badj = -1;
 #pragma unroll
       for (int j = 0; j < 16; ++j) {
         T piv = bcast(d[j], j);
-        if (!(piv > (T)0)) {
-          if (lane == 0) atomicCAS(flag, 0, (int32_t)(colbase + s * BS + b + j + 1));
-          piv = (T)1;
-        }
+        const bool bad = !(piv > (T)0);
+        badj = (bad && badj < 0) ? j : badj;
+        piv = bad ? (T)1 : piv;
         const T r = rsqrt_nr(piv);
         rv[j] = r;
         const T l = (li == j) ? piv * r : d[j] * r;
         d[j] = l;
+        if (j < 15) {
+          // column j of L: the next pivot row's entry straight from lane j+1,
+          // the rest through LDS (broadcast reads)
+          if (lane < 16) colv[li] = l;
+          wave_lds_sync();
+          d[j + 1] -= l * bcast(l, j + 1);
 #pragma unroll
-        for (int k = j + 1; k < 16; ++k) d[k] -= l * bcast(l, k);
+          for (int k = j + 2; k < 16; ++k) d[k] -= l * colv[k];
+        }
       }
+      if (badj >= 0 && lane == 0) atomicCAS(flag, 0, (int32_t)(col0 + b + badj + 1));
+      if (lane < 16) {
+#pragma unroll
+        for (int q = 0; q < 16; ++q) S[b + li][b + q] = (q <= li) ? d[q] : (T)0;
+      }
+      wave_lds_sync();
       // column li of inv(L_kb,kb): x_q = (e_li - sum_{p<q} L_qp x_p)_q / L_qq
       T x[16];
 #pragma unroll
@@ -147,14 +143,11 @@ __global__ __launch_bounds__(256) void k_potrf_diag64(T *__restrict__ W, int nb,
       for (int q = 0; q < 16; ++q) {
         x[q] *= rv[q];
 #pragma unroll
-        for (int p = q + 1; p < 16; ++p) x[p] -= bcast(d[q], p) * x[q];
+        for (int p = q + 1; p < 16; ++p) x[p] -= S[b + p][b + q] * x[q];
       }
       if (lane < 16) {
 #pragma unroll
-        for (int q = 0; q < 16; ++q) {
-          S[b + li][b + q] = (q <= li) ? d[q] : (T)0;
-          X[b + q][b + li] = x[q];
-        }
+        for (int q = 0; q < 16; ++q) X[b + q][b + li] = x[q];
       }
     }
     __syncthreads();
@@ -216,12 +209,44 @@ __global__ __launch_bounds__(256) void k_potrf_diag64(T *__restrict__ W, int nb,
     }
   }
   __syncthreads();
+}
+
+// Write L (zero above the diagonal) and inv(L) of a factored 64 x 64 block.
+template <typename T>
+__device__ __forceinline__ void diag64_store(const T (*S)[BS + 1], const T (*X)[BS + 1], T *Lblk,
+                                             int64_t ld, T *Dblk) {
 #pragma unroll
   for (int q = 0; q < 16; ++q) {
-    const int e = tid + 256 * q, r = e / BS, c = e % BS;
-    blk[(int64_t)r * nb + c] = (c <= r) ? S[r][c] : (T)0;
-    Dinv[(int64_t)s * BS * BS + e] = (c <= r) ? X[r][c] : (T)0;
+    const int e = threadIdx.x + 256 * q, r = e / BS, c = e % BS;
+    Lblk[(int64_t)r * ld + c] = (c <= r) ? S[r][c] : (T)0;
+    Dblk[e] = (c <= r) ? X[r][c] : (T)0;
   }
+}
+
+// First diagonal block of the tile: W_00 -> L_00 (in WL) and inv(L_00).
+template <typename T>
+__global__ __launch_bounds__(256) void k_potrf_diag64(const T *__restrict__ W, T *__restrict__ WL,
+                                                      int nb, T *__restrict__ Dinv, int32_t *flag,
+                                                      int64_t colbase) {
+  __shared__ T S[BS][BS + 1];  // the block, overwritten by L
+  __shared__ T X[BS][BS + 1];  // inv(L)
+  __shared__ T colv[16];       // current column of a 16 x 16 factor
+  {
+    T v[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int e = threadIdx.x + 256 * q, r = e / BS, c = e % BS;
+      v[q] = (c <= r) ? W[(int64_t)r * nb + c] : (T)0;
+    }
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int e = threadIdx.x + 256 * q;
+      S[e / BS][e % BS] = v[q];
+    }
+  }
+  __syncthreads();
+  diag64_body<T>(S, X, colv, flag, colbase);
+  diag64_store<T>(S, X, WL, nb, Dinv);
 }
 
 template <typename T, bool BT>
@@ -279,39 +304,75 @@ __device__ __forceinline__ void load64(T (*dst)[BS + 1], const T *src, int64_t l
   }
 }
 
-// Panel of the diagonal tile: W_as <- W_as * inv(L_ss)^T for a > s.
+// acc (layout of mm64) into a 64 x 64 LDS block.
 template <typename T>
-__global__ __launch_bounds__(256) void k_potrf_trsm64(T *__restrict__ W, int nb, int s,
-                                                      const T *__restrict__ Dinv) {
-  __shared__ T X[BS][BS + 1];
-  __shared__ T Li[BS][BS + 1];
-  const int a = s + 1 + blockIdx.x;
-  T *blk = W + (int64_t)(a * BS) * nb + s * BS;
-  load64(X, blk, nb);
-  load64(Li, Dinv + (int64_t)s * BS * BS, BS);
-  __syncthreads();
-  typename M16<T>::v4 acc[4];
-  zero4<T>(acc);
-  mm64<T, true>(X, Li, acc);
-  store64<T, false>(blk, nb, acc, (T)1);
+__device__ __forceinline__ void store_lds64(T (*dst)[BS + 1], const typename M16<T>::v4 (&acc)[4]) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int ct = 0; ct < 4; ++ct)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) dst[16 * wave + M16<T>::row(r, lane)][16 * ct + (lane & 15)] = acc[ct][r];
 }
 
-// Trailing update inside the diagonal tile: W_ab -= W_as W_bs^T, s < b <= a.
+// Step s of the tile factorization, one workgroup per block pair (a, b) with
+// s < b <= a < nb / 64:
+//   P_a = W_as inv(L_ss)^T   (block (a, s) of L; written by the pair (a, a)),
+//   W_ab -= P_a P_b^T,
+// and the pair (s+1, s+1) goes on to factor its updated block -- the next
+// diagonal step -- without writing it back.  Block column s of W is only
+// read in this step (the factor goes to WL), so the pairs need no ordering.
 template <typename T>
-__global__ __launch_bounds__(256) void k_potrf_syrk64(T *__restrict__ W, int nb, int s) {
-  __shared__ T Xa[BS][BS + 1];
-  __shared__ T Xb[BS][BS + 1];
+__global__ __launch_bounds__(256) void k_potrf_step(T *__restrict__ W, T *__restrict__ WL, int nb,
+                                                    int s, T *__restrict__ Dinv, int32_t *flag,
+                                                    int64_t colbase) {
+  typedef typename M16<T>::v4 v4;
+  __shared__ T buf[3][BS][BS + 1];
+  __shared__ T colv[16];
   int a, b;
   tri_decode(blockIdx.x, a, b);
   a += s + 1;
   b += s + 1;
+  T(*Xa)[BS + 1] = buf[0];
+  T(*Xb)[BS + 1] = buf[1];
+  T(*Li)[BS + 1] = buf[2];
   load64(Xa, W + (int64_t)(a * BS) * nb + s * BS, nb);
-  load64(Xb, W + (int64_t)(b * BS) * nb + s * BS, nb);
+  load64(Li, Dinv + (int64_t)s * BS * BS, BS);
+  if (a != b) load64(Xb, W + (int64_t)(b * BS) * nb + s * BS, nb);
   __syncthreads();
-  typename M16<T>::v4 acc[4];
+  v4 pa[4], pb[4];
+  zero4<T>(pa);
+  mm64<T, true>(Xa, Li, pa);
+  if (a != b) {
+    zero4<T>(pb);
+    mm64<T, true>(Xb, Li, pb);
+  }
+  __syncthreads();
+  store_lds64<T>(Xa, pa);
+  if (a != b) store_lds64<T>(Xb, pb);
+  else store64<T, false>(WL + (int64_t)(a * BS) * nb + s * BS, nb, pa, (T)1);
+  __syncthreads();
+  v4 acc[4];
   zero4<T>(acc);
-  mm64<T, true>(Xa, Xb, acc);
-  store64<T, true>(W + (int64_t)(a * BS) * nb + b * BS, nb, acc, (T)-1);
+  mm64<T, true>(Xa, a == b ? Xa : Xb, acc);
+  T *Wab = W + (int64_t)(a * BS) * nb + b * BS;
+  if (a == s + 1 && b == s + 1) {
+    // buf[2] (inv(L_ss)) and buf[1] (unused: a == b) take the next block
+    T(*S)[BS + 1] = buf[2];
+    T(*X)[BS + 1] = buf[1];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = 16 * wave + M16<T>::row(r, lane), col = 16 * ct + (lane & 15);
+        S[row][col] = (col <= row) ? Wab[(int64_t)row * nb + col] - acc[ct][r] : (T)0;
+      }
+    __syncthreads();
+    diag64_body<T>(S, X, colv, flag, colbase + (int64_t)a * BS);
+    diag64_store<T>(S, X, WL + (int64_t)(a * BS) * nb + a * BS, nb, Dinv + (int64_t)a * BS * BS);
+  } else {
+    store64<T, true>(Wab, nb, acc, (T)-1);
+  }
 }
 
 // Inverse of the whole lower-triangular tile by recursive doubling: with the
@@ -331,7 +392,7 @@ __global__ void k_trtri_init(const T *__restrict__ Dinv, T *__restrict__ Winv, i
 // step 0: Tmp_p = L[(2p+1)b.., 2pb..] * Winv[2pb.., 2pb..]
 // step 1: Winv[(2p+1)b.., 2pb..] = -Winv[(2p+1)b.., (2p+1)b..] * Tmp_p
 template <typename T>
-__global__ __launch_bounds__(256) void k_trtri_level(const T *__restrict__ W, T *__restrict__ Winv,
+__global__ __launch_bounds__(256) void k_trtri_level(const T *__restrict__ WL, T *__restrict__ Winv,
                                                      T *__restrict__ Tmp, int nb, int b, int step) {
   __shared__ T As[BS][BS + 1];
   __shared__ T Bs[BS][BS + 1];
@@ -342,7 +403,7 @@ __global__ __launch_bounds__(256) void k_trtri_level(const T *__restrict__ W, T 
   int64_t lda, ldb, ldc;
   T alpha;
   if (step == 0) {
-    A = W + (o + b) * nb + o;       lda = nb;
+    A = WL + (o + b) * nb + o;      lda = nb;
     B = Winv + o * nb + o;          ldb = nb;
     C = Tmp + p * (int64_t)b * b;   ldc = b;
     alpha = (T)1;
@@ -380,29 +441,27 @@ template <typename T>
 static void potrf_tile_t(float *Akk, float *Linv, int k, const TileLayout &L, FactorWork &w,
                          hipStream_t s) {
   const int nb = L.nb, NB = nb / BS;
-  T *W = (T *)w.W64, *Winv = (T *)w.Winv64, *Dinv = (T *)w.Dinv64, *Tmp = (T *)w.Tmp64;
+  T *W = (T *)w.W64, *WL = (T *)w.WL64, *Winv = (T *)w.Winv64, *Dinv = (T *)w.Dinv64,
+    *Tmp = (T *)w.Tmp64;
   const unsigned eb = (unsigned)(((int64_t)nb * nb + 255) / 256);
   const int64_t colbase = (int64_t)k * nb;
   hipLaunchKernelGGL(k_potrf_load<T>, dim3(eb), dim3(256), 0, s, Akk, W, nb);
-  for (int st = 0; st < NB; ++st) {
-    hipLaunchKernelGGL(k_potrf_diag64<T>, dim3(1), dim3(256), 0, s, W, nb, st, Dinv, w.flag,
-                       colbase);
+  hipLaunchKernelGGL(k_potrf_diag64<T>, dim3(1), dim3(256), 0, s, W, WL, nb, Dinv, w.flag,
+                     colbase);
+  for (int st = 0; st + 1 < NB; ++st) {
     const int rest = NB - 1 - st;
-    if (rest > 0) {
-      hipLaunchKernelGGL(k_potrf_trsm64<T>, dim3(rest), dim3(256), 0, s, W, nb, st, Dinv);
-      hipLaunchKernelGGL(k_potrf_syrk64<T>, dim3(rest * (rest + 1) / 2), dim3(256), 0, s, W, nb,
-                         st);
-    }
+    hipLaunchKernelGGL(k_potrf_step<T>, dim3(rest * (rest + 1) / 2), dim3(256), 0, s, W, WL, nb,
+                       st, Dinv, w.flag, colbase);
   }
   hipLaunchKernelGGL(k_trtri_init<T>, dim3(eb), dim3(256), 0, s, Dinv, Winv, nb);
   for (int b = BS; b < nb; b *= 2) {
     const unsigned nbk = (unsigned)(b / BS), pairs = (unsigned)(nb / (2 * b));
-    hipLaunchKernelGGL(k_trtri_level<T>, dim3(nbk, nbk, pairs), dim3(256), 0, s, W, Winv, Tmp, nb,
+    hipLaunchKernelGGL(k_trtri_level<T>, dim3(nbk, nbk, pairs), dim3(256), 0, s, WL, Winv, Tmp, nb,
                        b, 0);
-    hipLaunchKernelGGL(k_trtri_level<T>, dim3(nbk, nbk, pairs), dim3(256), 0, s, W, Winv, Tmp, nb,
+    hipLaunchKernelGGL(k_trtri_level<T>, dim3(nbk, nbk, pairs), dim3(256), 0, s, WL, Winv, Tmp, nb,
                        b, 1);
   }
-  hipLaunchKernelGGL(k_potrf_store<T>, dim3(eb), dim3(256), 0, s, W, Winv, Akk, Linv, nb);
+  hipLaunchKernelGGL(k_potrf_store<T>, dim3(eb), dim3(256), 0, s, WL, Winv, Akk, Linv, nb);
 }
 
 void launch_potrf_tile(float *Akk, float *Linv, int k, const TileLayout &L, bool fp64,
@@ -551,12 +610,14 @@ struct PanelSet {
   const int *pexp8[KRR_MAX_GROUP];
 };
 
-// Trailing update of one group of panels: 256 x 256 sub-block (si, sj) of
-// tile (i, j) gets A_ij -= sum_q L_i,k0+q L_j,k0+q^T.  Each panel's operands
+// Trailing update of one group of panels: sub-block (si, sj) of tile (i, j)
+// (256 x 256 off the diagonal, 128 x 128 on it) gets
+// A_ij -= sum_q L_i,k0+q L_j,k0+q^T.  Each panel's operands
 // take the precision chosen for this update; the panels of one precision
 // form one streamed K range (one segment per panel), so a sub-block runs at
 // most three products (FP32, FP16, FP8 operands) into one FP32 accumulator.
-typedef StreamShape<256, 256, 2, 4, 4> UpdStream;
+typedef StreamShape<256, 256, 2, 4, 4> UpdStream;   // off-diagonal tiles
+typedef StreamShape<128, 128, 2, 2, 4> UpdDiagStream;  // diagonal tiles
 
 // Segment table in LDS: per precision, the row-0 addresses of the A and B
 // operand blocks of each selected panel (and the FP8 scale codes).
@@ -595,27 +656,27 @@ struct SegSrc {
   }
 };
 
-__global__ __launch_bounds__(UpdStream::THREADS) void k_update(
+// DIAG: the diagonal tiles (j, j), jlo <= j <= jhi -- FP32 operands, the
+// longest work per output, so they run in smaller blocks of their own launch
+// (lower sub-blocks only).  Otherwise the off-diagonal tiles, remapped so that
+// the sub-blocks of one tile share an XCD.
+template <class S, bool DIAG>
+__global__ __launch_bounds__(S::THREADS) void k_update(
     float *__restrict__ Astore, PanelSet ps, int k0, int npan, int jlo, int jhi, int NT, int nb,
     int SB, int mode, int allow16, int allow8, int high_panels, int fixed_prec, double thr,
     uint8_t *__restrict__ pmap, int64_t ntiles_all) {
-  typedef UpdStream S;
   constexpr int BM = S::kBM;
   extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
   __shared__ SegTable tab;
-  // Blocks of the diagonal tiles (FP32 operands, the longest) are dispatched
-  // first; only their lower sub-blocks are computed.  The off-diagonal blocks
-  // follow, remapped so that the sub-blocks of one tile share an XCD.
-  const int nsd = SB * (SB + 1) / 2, nsub = SB * SB;
-  const int64_t ndb = (int64_t)(jhi - jlo + 1) * nsd;
   int64_t i, j;
   int si, sj;
-  if ((int64_t)blockIdx.x < ndb) {
+  if constexpr (DIAG) {
+    const int nsd = SB * (SB + 1) / 2;
     i = j = jlo + blockIdx.x / nsd;
     tri_decode(blockIdx.x % nsd, si, sj);
   } else {
-    const int64_t h = blockIdx.x - ndb;
-    const int64_t bid = xcd_remap(h, (int64_t)gridDim.x - ndb);
+    const int nsub = SB * SB;
+    const int64_t bid = xcd_remap(blockIdx.x, gridDim.x);
     const int sub = (int)(bid % nsub);
     int64_t tt = bid / nsub;
     si = sub / SB;
@@ -747,16 +808,39 @@ void launch_update(float *Astore, int k0, int npan, int jlo, int jhi, const Tile
   }
   static bool attr = false;
   if (!attr) {
-    hipFuncSetAttribute((const void *)k_update, hipFuncAttributeMaxDynamicSharedMemorySize,
-                        UpdStream::LDS_BYTES);
+    hipFuncSetAttribute((const void *)k_update<UpdStream, false>,
+                        hipFuncAttributeMaxDynamicSharedMemorySize, UpdStream::LDS_BYTES);
+    hipFuncSetAttribute((const void *)k_update<UpdDiagStream, true>,
+                        hipFuncAttributeMaxDynamicSharedMemorySize, UpdDiagStream::LDS_BYTES);
+    hipFuncSetAttribute((const void *)k_update<UpdDiagStream, false>,
+                        hipFuncAttributeMaxDynamicSharedMemorySize, UpdDiagStream::LDS_BYTES);
     attr = true;
   }
-  const int SB = L.nb / UpdStream::kBM;
-  const int64_t blocks = (int64_t)(jhi - jlo + 1) * SB * (SB + 1) / 2 + offdiag * SB * SB;
-  hipLaunchKernelGGL(k_update, dim3((unsigned)blocks), dim3(UpdStream::THREADS),
-                     UpdStream::LDS_BYTES, s, Astore, ps, k0, npan, jlo, jhi, NT, L.nb, SB,
-                     pol.mode, pol.allow16, pol.allow8, pol.high_panels, pol.fixed_prec, pol.thr,
-                     pmap, L.ntiles());
+  {  // diagonal tiles first: they are the longest per block
+    const int SB = L.nb / UpdDiagStream::kBM;
+    const int64_t blocks = (int64_t)(jhi - jlo + 1) * SB * (SB + 1) / 2;
+    hipLaunchKernelGGL((k_update<UpdDiagStream, true>), dim3((unsigned)blocks),
+                       dim3(UpdDiagStream::THREADS), UpdDiagStream::LDS_BYTES, s, Astore, ps, k0,
+                       npan, jlo, jhi, NT, L.nb, SB, pol.mode, pol.allow16, pol.allow8,
+                       pol.high_panels, pol.fixed_prec, pol.thr, pmap, L.ntiles());
+  }
+  if (offdiag > 0 && offdiag * 4 < 8 * 256) {
+    // few tiles (the updates inside a panel group, on the critical path):
+    // small blocks, several per CU, for latency
+    const int SB = L.nb / UpdDiagStream::kBM;
+    const int64_t blocks = offdiag * SB * SB;
+    hipLaunchKernelGGL((k_update<UpdDiagStream, false>), dim3((unsigned)blocks),
+                       dim3(UpdDiagStream::THREADS), UpdDiagStream::LDS_BYTES, s, Astore, ps, k0,
+                       npan, jlo, jhi, NT, L.nb, SB, pol.mode, pol.allow16, pol.allow8,
+                       pol.high_panels, pol.fixed_prec, pol.thr, pmap, L.ntiles());
+  } else if (offdiag > 0) {
+    const int SB = L.nb / UpdStream::kBM;
+    const int64_t blocks = offdiag * SB * SB;
+    hipLaunchKernelGGL((k_update<UpdStream, false>), dim3((unsigned)blocks), dim3(UpdStream::THREADS),
+                       UpdStream::LDS_BYTES, s, Astore, ps, k0, npan, jlo, jhi, NT, L.nb, SB,
+                       pol.mode, pol.allow16, pol.allow8, pol.high_panels, pol.fixed_prec, pol.thr,
+                       pmap, L.ntiles());
+  }
 }
 
 // Updates per operand precision, from the precision map (255 = no update).

@@ -59,6 +59,7 @@ constexpr int KRR_MAX_GROUP = 8;  // panels per grouped trailing update
 // Workspace for the factorization, sized for nt tiles of nb.
 struct FactorWork {
   double *W64 = nullptr;     // nb x nb FP64 (or FP32) diagonal workspace
+  double *WL64 = nullptr;    // nb x nb: its factor
   double *Winv64 = nullptr;  // nb x nb
   double *Dinv64 = nullptr;  // (nb/64) blocks of 64 x 64
   double *Tmp64 = nullptr;   // nb x nb / 2 scratch for the tile inverse
