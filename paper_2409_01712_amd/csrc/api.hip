@@ -34,8 +34,8 @@ struct krr_context_s {
   int64_t live = 0;
   bool destroy_pending = false;
   // second stream and events for the factorization's lookahead
-  hipStream_t aux = nullptr;
-  hipEvent_t ev_panel = nullptr, ev_update = nullptr;
+  hipStream_t aux = nullptr, side = nullptr, fmain = nullptr;
+  std::vector<hipEvent_t> sched_ev;  // ordering events of the factorization schedule
 };
 
 struct krr_kernel_s {
@@ -275,21 +275,21 @@ static void context_free(krr_context ctx) {
   (void)hipStreamSynchronize(ctx->stream);
   timers_drain(ctx);
   for (hipEvent_t e : ctx->pool) (void)hipEventDestroy(e);
-  if (ctx->aux) {
-    (void)hipStreamSynchronize(ctx->aux);
-    (void)hipStreamDestroy(ctx->aux);
+  for (hipStream_t x : {ctx->aux, ctx->side, ctx->fmain}) {
+    if (x) {
+      (void)hipStreamSynchronize(x);
+      (void)hipStreamDestroy(x);
+    }
   }
-  if (ctx->ev_panel) (void)hipEventDestroy(ctx->ev_panel);
-  if (ctx->ev_update) (void)hipEventDestroy(ctx->ev_update);
+  for (hipEvent_t e : ctx->sched_ev) (void)hipEventDestroy(e);
   delete ctx;
 }
 
-// The lookahead stream (default priority) and its two ordering events.
+// The factorization's three streams (default priority): its own main stream
+// (the critical path), a side stream and an aux stream.
 static krr_status context_aux(krr_context ctx) {
-  if (ctx->aux) return KRR_SUCCESS;
-  HIPCHK(hipStreamCreateWithFlags(&ctx->aux, hipStreamNonBlocking));
-  HIPCHK(hipEventCreateWithFlags(&ctx->ev_panel, hipEventDisableTiming));
-  HIPCHK(hipEventCreateWithFlags(&ctx->ev_update, hipEventDisableTiming));
+  for (hipStream_t *x : {&ctx->fmain, &ctx->side, &ctx->aux})
+    if (!*x) HIPCHK(hipStreamCreateWithFlags(x, hipStreamNonBlocking));
   return KRR_SUCCESS;
 }
 
@@ -437,12 +437,13 @@ krr_status krr_kernel_tile_norms(krr_kernel K, double *host_dst, int64_t count) 
 
 static void factor_work_free(krr_context c, FactorWork &w, const TileLayout &L) {
   const int64_t te = L.tile_elems(), pt = std::max(L.nt - 1, 1);
-  const int sb = L.nb / 128, parts = sb * sb;
+  const int parts = std::max((L.nb / 64) * (L.nb / 64), L.nb / 16);
+  const int64_t chunk = std::min(w.inv_chunk, L.nt);
   dfree(c, w.W64, te * 8);
-  dfree(c, w.WL64, te * 8);
-  dfree(c, w.Winv64, te * 8);
-  dfree(c, w.Dinv64, (L.nb / 64) * 64 * 64 * 8);
-  dfree(c, w.Tmp64, te / 2 * 8);
+  dfree(c, w.WL64, L.nt * te * 8);
+  dfree(c, w.Dinv64, (int64_t)L.nt * L.nb * 64 * 8);
+  dfree(c, w.Winv64, chunk * te * 8);
+  dfree(c, w.Tmp64, chunk * te / 2 * 8);
   for (PanelBuf &pb : w.pb) {  // unallocated slots hold null pointers
     dfree(c, pb.P32, pt * te * 4);
     dfree(c, pb.P16, pt * te * 2);
@@ -460,7 +461,8 @@ static void factor_work_free(krr_context c, FactorWork &w, const TileLayout &L) 
 static krr_status factor_work_alloc(krr_context c, FactorWork &w, const TileLayout &L,
                                     bool need16, bool need8, int slots) {
   const int64_t te = L.tile_elems(), pt = std::max(L.nt - 1, 1);
-  const int sb = L.nb / 128, parts = sb * sb;
+  const int parts = std::max((L.nb / 64) * (L.nb / 64), L.nb / 16);
+  const int64_t chunk = std::min(w.inv_chunk, L.nt);
   krr_status st;
 #define WA(ptr, cnt)                                                        \
   if ((st = dalloc(c, (void **)&(ptr), (size_t)(cnt))) != KRR_SUCCESS) { \
@@ -468,10 +470,10 @@ static krr_status factor_work_alloc(krr_context c, FactorWork &w, const TileLayo
     return st;                                                            \
   }
   WA(w.W64, te * 8);
-  WA(w.WL64, te * 8);
-  WA(w.Winv64, te * 8);
-  WA(w.Dinv64, (L.nb / 64) * 64 * 64 * 8);
-  WA(w.Tmp64, te / 2 * 8);
+  WA(w.WL64, L.nt * te * 8);
+  WA(w.Dinv64, (int64_t)L.nt * L.nb * 64 * 8);
+  WA(w.Winv64, chunk * te * 8);
+  WA(w.Tmp64, chunk * te / 2 * 8);
   for (int q = 0; q < slots; ++q) {
     PanelBuf &pb = w.pb[q];
     WA(pb.P32, pt * te * 4);
@@ -576,66 +578,141 @@ krr_status krr_factor(krr_context ctx, krr_kernel K, const krr_precision_policy 
       // each panel updates the group's later columns right away; everything
       // to the right of the group gets one update by the whole group (K = g nb).
       auto slot = [&](int k) -> PanelBuf & { return w.pb[((k / g) & 1) * g + (k % g)]; };
-      auto panel = [&](int k, hipStream_t ss) {  // POTRF, TRSM and operand copies of panel k
-        float *Akk = F->Lst + TileLayout::tri(k, k) * te;
+      auto panels = [&](int G0, int npan, const PanelBuf **ps) {
+        for (int q = 0; q < npan; ++q) ps[q] = &slot(G0 + q);
+      };
+      // POTRF(k); the updates of tile (k, k) by panels q0 .. q0+nq-1 are folded in
+      auto potrf = [&](int k, int q0, int nq, hipStream_t st) {
+        DiagUpdate du{};
+        du.npan = nq;
+        du.pmap = dmap;
+        for (int q = 0; q < nq; ++q) {
+          du.P[q] = slot(q0 + q).P32 + (int64_t)(k - (q0 + q) - 1) * te;
+          du.pmap_at[q] = (int64_t)(q0 + q) * L.ntiles() + TileLayout::tri(k, k);
+        }
+        Stage t(ctx, KRR_STAGE_POTRF, st);
+        launch_potrf_tile(F->Lst + TileLayout::tri(k, k) * te, k, L, diag64, w, du, st);
+      };
+      // TRSM of panel k, tiles k+1+t_lo .. : by substitution (no inverse) or
+      // as a product with inv(L_kk) after forming it
+      auto trsm_subst = [&](int k, int t_lo, int t_hi, hipStream_t st) {
+        Stage t(ctx, KRR_STAGE_TRSM, st);
+        launch_trsm_subst(F->Lst, k, L, diag64, w, slot(k), t_lo, t_hi, st);
+      };
+      auto trsm_gemm = [&](int k, int t_lo, int t_hi, hipStream_t st) {
         {
-          Stage t(ctx, KRR_STAGE_POTRF, ss);
-          launch_potrf_tile(Akk, F->Linv + (int64_t)k * te, k, L, diag64, w, ss);
+          Stage t(ctx, KRR_STAGE_POTRF, st);
+          launch_tile_inverses(F->Lst, F->Linv, k, k + 1, L, diag64, w, st);
         }
-        if (k + 1 < L.nt) {
-          {
-            Stage t(ctx, KRR_STAGE_TRSM, ss);
-            launch_trsm_panel(F->Lst, F->Linv + (int64_t)k * te, k, L, w, slot(k), ss);
-          }
-          Stage t(ctx, KRR_STAGE_CONVERT, ss);
-          launch_convert_panel(F->Lst, k, L, w, slot(k), need16, need8, ss);
-        }
+        Stage t(ctx, KRR_STAGE_TRSM, st);
+        launch_trsm_gemm(F->Lst, F->Linv + (int64_t)k * te, k, L, w, slot(k), t_lo, t_hi, st);
       };
-      auto factor_group = [&](int G0, hipStream_t ss) {
-        const int gend = std::min(G0 + g, L.nt);
-        for (int k = G0; k < gend; ++k) {
-          panel(k, ss);
-          if (k + 1 < gend) {
-            const PanelBuf *one[1] = {&slot(k)};
-            Stage t(ctx, KRR_STAGE_UPDATE, ss);
-            launch_update(F->Lst, k, 1, k + 1, gend - 1, L, up, w, one, dmap, ss);
-          }
-        }
+      auto convert = [&](int k, hipStream_t st) {
+        Stage t(ctx, KRR_STAGE_CONVERT, st);
+        launch_convert_panel(F->Lst, k, L, w, slot(k), need16, need8, st);
       };
-      auto group_update = [&](int G0, int jlo, int jhi, hipStream_t ss) {
-        const int npan = std::min(g, L.nt - G0);
+      // panels G0 .. G0+npan-1 onto the tiles of columns jlo .. jhi (which: UPD_*)
+      auto update = [&](int G0, int npan, int jlo, int jhi, int which, hipStream_t st) {
         if (jlo > jhi || jlo >= L.nt) return;
         const PanelBuf *ps[KRR_MAX_GROUP];
-        for (int q = 0; q < npan; ++q) ps[q] = &slot(G0 + q);
-        Stage t(ctx, KRR_STAGE_UPDATE, ss);
-        launch_update(F->Lst, G0, npan, jlo, jhi, L, up, w, ps, dmap, ss);
+        panels(G0, npan, ps);
+        Stage t(ctx, KRR_STAGE_UPDATE, st);
+        launch_update(F->Lst, G0, npan, jlo, jhi, L, up, w, ps, dmap, which, st);
       };
-      if (!lookahead) {
-        for (int G0 = 0; G0 < L.nt; G0 += g) {
-          factor_group(G0, s);
-          group_update(G0, G0 + g, L.nt - 1, s);
+      const int NT = L.nt;
+      if (!lookahead) {  // one stream, in program order
+        for (int G0 = 0; G0 < NT; G0 += g) {
+          const int gend = std::min(G0 + g, NT);
+          for (int k = G0; k < gend; ++k) {
+            potrf(k, 0, 0, s);
+            trsm_gemm(k, 0, NT, s);
+            if (k + 1 < NT) convert(k, s);
+            update(k, 1, k + 1, gend - 1, UPD_ALL, s);
+          }
+          update(G0, gend - G0, gend, NT - 1, UPD_ALL, s);
         }
       } else {
-        // Lookahead: while the aux stream applies group G to the columns
-        // beyond the next group, the main stream updates the next group's
-        // columns and factors it, so its panels are ready in time.
-        hipStream_t s2 = ctx->aux;
-        factor_group(0, s);
-        bool ok = hipEventRecord(ctx->ev_panel, s) == hipSuccess;
-        bool waited = false;
-        for (int G0 = 0; G0 + g < L.nt && ok; G0 += g) {
-          const int gend = G0 + g, nend = std::min(gend + g, L.nt);
-          ok = hipStreamWaitEvent(s2, ctx->ev_panel, 0) == hipSuccess;
-          group_update(G0, nend, L.nt - 1, s2);
-          if (G0 > 0) ok = ok && hipStreamWaitEvent(s, ctx->ev_update, 0) == hipSuccess;
-          ok = ok && hipEventRecord(ctx->ev_update, s2) == hipSuccess;
-          waited = true;
-          group_update(G0, gend, nend - 1, s);
-          factor_group(gend, s);
-          ok = ok && hipEventRecord(ctx->ev_panel, s) == hipSuccess;
+        // Three streams.  Main, the critical path: POTRF(k) (with the tile's
+        // last updates folded into its load) and the TRSM of row k+1 alone.  Side: the
+        // rest of each panel's TRSM, its operand copies, its updates of the
+        // group's later columns, and the group's update of the next group's
+        // columns.  Aux: each group's update of every column beyond the next
+        // group.  Events order all updates of any one tile, so the factor
+        // does not depend on the schedule.
+        hipStream_t sm = ctx->fmain, sd = ctx->side, sx = ctx->aux;
+        const int ngroups = (NT + g - 1) / g;
+        std::vector<hipEvent_t> &E = ctx->sched_ev;
+        const size_t need = (size_t)3 * NT + 2 * ngroups + 4;
+        bool ok = true;
+        while (ok && E.size() < need) {
+          hipEvent_t e;
+          ok = hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess;
+          if (ok) E.push_back(e);
         }
-        if (waited) ok = ok && hipStreamWaitEvent(s, ctx->ev_update, 0) == hipSuccess;
+        hipEvent_t *e_t1 = E.data(), *e_conv = e_t1 + NT, *e_uin = e_conv + NT,
+                   *e_aux = e_uin + NT, *e_narrow = e_aux + ngroups, *e_join = e_narrow + ngroups;
+        auto rec = [&](hipEvent_t e, hipStream_t st) {
+          ok = ok && hipEventRecord(e, st) == hipSuccess;
+        };
+        auto wait = [&](hipStream_t st, hipEvent_t e) {
+          ok = ok && hipStreamWaitEvent(st, e, 0) == hipSuccess;
+        };
+        // all three start after the work already on the caller's stream
+        rec(e_join[0], s);
+        wait(sm, e_join[0]);
+        wait(sd, e_join[0]);
+        wait(sx, e_join[0]);
+        for (int G0 = 0; G0 < NT && ok; G0 += g) {
+          const int gi = G0 / g, gend = std::min(G0 + g, NT), nend = std::min(gend + g, NT);
+          for (int k = G0; k < gend; ++k) {
+            // tile (k, k) still lacks panel k-1 (inside the group) or the
+            // whole previous group (at its start)
+            if (k > G0) potrf(k, k - 1, 1, sm);
+            else potrf(k, std::max(G0 - g, 0), G0 > 0 ? g : 0, sm);
+            if (k + 1 >= NT) break;
+            // column k below the diagonal: in-group updates (side), or the
+            // previous group's update of this group's columns (side)
+            if (k > G0) wait(sm, e_uin[k - 1]);
+            else if (gi > 0) wait(sm, e_narrow[gi - 1]);
+            trsm_subst(k, 0, 1, sm);
+            rec(e_t1[k], sm);
+            wait(sd, e_t1[k]);
+            trsm_gemm(k, 1, NT, sd);
+            convert(k, sd);
+            rec(e_conv[k], sd);
+            update(k, 1, k + 1, gend - 1, UPD_OFFDIAG, sd);
+            update(k, 1, k + 2, gend - 1, UPD_DIAG, sd);
+            rec(e_uin[k], sd);
+          }
+          if (gend >= NT) break;
+          const int npan = gend - G0;
+          if (nend < NT) {  // aux: everything right of the next group
+            wait(sx, e_conv[gend - 1]);
+            update(G0, npan, nend, NT - 1, UPD_ALL, sx);
+          }
+          rec(e_aux[gi], sx);
+          // the next group's columns, after the previous group's aux update
+          // reached them; its first diagonal tile on the main stream
+          if (gi > 0) {
+            wait(sm, e_aux[gi - 1]);
+            wait(sd, e_aux[gi - 1]);
+          }
+          update(G0, npan, gend, nend - 1, UPD_OFFDIAG, sd);
+          update(G0, npan, gend + 1, nend - 1, UPD_DIAG, sd);
+          rec(e_narrow[gi], sd);
+        }
+        // join on the caller's stream
+        rec(e_join[1], sd);
+        rec(e_join[2], sx);
+        rec(e_join[3], sm);
+        wait(s, e_join[1]);
+        wait(s, e_join[2]);
+        wait(s, e_join[3]);
         if (!ok) { st = KRR_ERROR_HIP; break; }
+      }
+      if (lookahead) {  // the last tile has no panel below it
+        Stage t(ctx, KRR_STAGE_POTRF, s);
+        launch_tile_inverses(F->Lst, F->Linv, NT - 1, NT, L, diag64, w, s);
       }
       launch_count_pmap(dmap, mapsz, w.counts, s);
       if ((st = launch_ok()) != KRR_SUCCESS) break;

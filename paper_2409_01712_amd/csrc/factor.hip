@@ -11,6 +11,7 @@
 //   update  A_ij -= L_ik L_jk^T for k < j <= i: FP32 on diagonal tiles and
 //           early panels, otherwise FP16 or FP8 operands chosen per update
 //           from the operand tile norms, always accumulated in FP32.
+#include <algorithm>
 #include <type_traits>
 
 #include "common.h"
@@ -24,13 +25,6 @@ constexpr int BS = 64;  // sub-block of the diagonal-tile factorization
 // Diagonal tile: blocked Cholesky and triangular inverse, 64 x 64 sub-blocks.
 // W holds the nb x nb tile (row-major) in T = double or float.
 
-template <typename T>
-__global__ void k_potrf_load(const float *__restrict__ Akk, T *__restrict__ W, int nb) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= (int64_t)nb * nb) return;
-  const int r = (int)(e / nb), c = (int)(e % nb);
-  W[e] = (c <= r) ? (T)Akk[e] : (T)0;
-}
 
 // 64 x 64 block products on 16 x 16 x 4 MFMA tiles (FP64 or FP32): wave w
 // computes rows 16w .. 16w+15 of C = A op(B) for all 64 columns.  A, B are
@@ -375,28 +369,37 @@ __global__ __launch_bounds__(256) void k_potrf_step(T *__restrict__ W, T *__rest
   }
 }
 
-// Inverse of the whole lower-triangular tile by recursive doubling: with the
-// inverses of the diagonal blocks of size b known,
+// Inverses of the diagonal tiles k0 .. k0+C-1 (tile c = blockIdx.y or
+// blockIdx.z / pairs) by recursive doubling: with the inverses of the
+// diagonal blocks of size b known,
 //   inv([A 0; B C]) = [inv(A) 0; -inv(C) B inv(A)  inv(C)],
-// so each level doubles the block size with two block products.
+// so each level doubles the block size with two block products.  WL, Dinv:
+// the factors and 64-block inverses of all tiles; Winv, Tmp: C tiles.
 template <typename T>
-__global__ void k_trtri_init(const T *__restrict__ Dinv, T *__restrict__ Winv, int nb) {
+__global__ void k_trtri_init(const T *__restrict__ Dinv, T *__restrict__ Winv, int nb, int k0) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= (int64_t)nb * nb) return;
-  const int r = (int)(e / nb), c = (int)(e % nb);
-  Winv[e] = (r / BS == c / BS) ? Dinv[(int64_t)(r / BS) * BS * BS + (r % BS) * BS + c % BS] : (T)0;
+  const int c = blockIdx.y, NB = nb / BS;
+  const T *D = Dinv + (int64_t)(k0 + c) * NB * BS * BS;
+  const int r = (int)(e / nb), q = (int)(e % nb);
+  Winv[(int64_t)c * nb * nb + e] =
+      (r / BS == q / BS) ? D[(int64_t)(r / BS) * BS * BS + (r % BS) * BS + q % BS] : (T)0;
 }
 
-// C = alpha * A * B for b x b blocks (b a multiple of 64), pair p = blockIdx.z
-// at diagonal offset 2 p b.  Output block (blockIdx.y, blockIdx.x) of 64 x 64.
+// C = alpha * A * B for b x b blocks (b a multiple of 64), pair p at
+// diagonal offset 2 p b.  Output block (blockIdx.y, blockIdx.x) of 64 x 64.
 // step 0: Tmp_p = L[(2p+1)b.., 2pb..] * Winv[2pb.., 2pb..]
 // step 1: Winv[(2p+1)b.., 2pb..] = -Winv[(2p+1)b.., (2p+1)b..] * Tmp_p
 template <typename T>
-__global__ __launch_bounds__(256) void k_trtri_level(const T *__restrict__ WL, T *__restrict__ Winv,
-                                                     T *__restrict__ Tmp, int nb, int b, int step) {
+__global__ __launch_bounds__(256) void k_trtri_level(const T *__restrict__ WLall,
+                                                     T *__restrict__ Winvc, T *__restrict__ Tmpc,
+                                                     int nb, int b, int step, int k0, int pairs) {
   __shared__ T As[BS][BS + 1];
   __shared__ T Bs[BS][BS + 1];
-  const int64_t p = blockIdx.z, o = 2 * p * b;
+  const int c = blockIdx.z / pairs;
+  const int64_t p = blockIdx.z % pairs, o = 2 * p * b, te = (int64_t)nb * nb;
+  const T *WL = WLall + (int64_t)(k0 + c) * te;
+  T *Winv = Winvc + (int64_t)c * te, *Tmp = Tmpc + (int64_t)c * (te / 2);
   const T *A;
   const T *B;
   T *C;
@@ -416,9 +419,9 @@ __global__ __launch_bounds__(256) void k_trtri_level(const T *__restrict__ WL, T
   const int rb = blockIdx.y, cb = blockIdx.x;
   typename M16<T>::v4 acc[4];
   zero4<T>(acc);
-  for (int k0 = 0; k0 < b; k0 += BS) {
-    load64(As, A + (int64_t)(rb * BS) * lda + k0, lda);
-    load64(Bs, B + (int64_t)k0 * ldb + cb * BS, ldb);
+  for (int kk = 0; kk < b; kk += BS) {
+    load64(As, A + (int64_t)(rb * BS) * lda + kk, lda);
+    load64(Bs, B + (int64_t)kk * ldb + cb * BS, ldb);
     __syncthreads();
     mm64<T, false>(As, Bs, acc);
     __syncthreads();
@@ -426,26 +429,93 @@ __global__ __launch_bounds__(256) void k_trtri_level(const T *__restrict__ WL, T
   store64<T, false>(C + (int64_t)(rb * BS) * ldc + cb * BS, ldc, acc, alpha);
 }
 
-// Write L_kk (lower, zero above) and inv(L_kk) as FP32.
+// Write L_kk (lower, zero above) into the factor storage and inv(L_kk), FP32.
 template <typename T>
-__global__ void k_potrf_store(const T *__restrict__ W, const T *__restrict__ Winv,
-                              float *__restrict__ Akk, float *__restrict__ Linv, int nb) {
+__global__ void k_potrf_store(const T *__restrict__ WLall, const T *__restrict__ Winvc,
+                              float *__restrict__ Lst, float *__restrict__ Linv, int nb, int k0) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= (int64_t)nb * nb) return;
-  const int r = (int)(e / nb), c = (int)(e % nb);
-  Akk[e] = (c <= r) ? (float)W[e] : 0.0f;
-  Linv[e] = (c <= r) ? (float)Winv[e] : 0.0f;
+  const int c = blockIdx.y;
+  const int64_t k = k0 + c, te = (int64_t)nb * nb;
+  const int r = (int)(e / nb), q = (int)(e % nb);
+  Lst[(k * (k + 1) / 2 + k) * te + e] = (q <= r) ? (float)WLall[k * te + e] : 0.0f;
+  Linv[k * te + e] = (q <= r) ? (float)Winvc[(int64_t)c * te + e] : 0.0f;
 }
 
 template <typename T>
-static void potrf_tile_t(float *Akk, float *Linv, int k, const TileLayout &L, FactorWork &w,
-                         hipStream_t s) {
-  const int nb = L.nb, NB = nb / BS;
-  T *W = (T *)w.W64, *WL = (T *)w.WL64, *Winv = (T *)w.Winv64, *Dinv = (T *)w.Dinv64,
-    *Tmp = (T *)w.Tmp64;
+static void tile_inverses_t(float *Lst, float *Linv, int k_lo, int k_hi, const TileLayout &L,
+                            FactorWork &w, hipStream_t s) {
+  const int nb = L.nb;
   const unsigned eb = (unsigned)(((int64_t)nb * nb + 255) / 256);
+  for (int k0 = k_lo; k0 < k_hi; k0 += w.inv_chunk) {
+    const int C = std::min(w.inv_chunk, k_hi - k0);
+    hipLaunchKernelGGL(k_trtri_init<T>, dim3(eb, C), dim3(256), 0, s, (const T *)w.Dinv64,
+                       (T *)w.Winv64, nb, k0);
+    for (int b = BS; b < nb; b *= 2) {
+      const unsigned nbk = (unsigned)(b / BS);
+      const int pairs = nb / (2 * b);
+      for (int step = 0; step < 2; ++step)
+        hipLaunchKernelGGL(k_trtri_level<T>, dim3(nbk, nbk, pairs * C), dim3(256), 0, s,
+                           (const T *)w.WL64, (T *)w.Winv64, (T *)w.Tmp64, nb, b, step, k0,
+                           pairs);
+    }
+    hipLaunchKernelGGL(k_potrf_store<T>, dim3(eb, C), dim3(256), 0, s, (const T *)w.WL64,
+                       (const T *)w.Winv64, Lst, Linv, nb, k0);
+  }
+}
+
+void launch_tile_inverses(float *Lst, float *Linv, int k_lo, int k_hi, const TileLayout &L,
+                          bool fp64, FactorWork &w, hipStream_t s) {
+  if (fp64)
+    tile_inverses_t<double>(Lst, Linv, k_lo, k_hi, L, w, s);
+  else
+    tile_inverses_t<float>(Lst, Linv, k_lo, k_hi, L, w, s);
+}
+
+// Load the diagonal tile with its last updates folded in:
+//   W = A_kk - sum_q P_q P_q^T   (lower 64 x 64 blocks; the upper ones are never read)
+// where P_q is tile k of panel buffer q (the panels whose update of this tile
+// was left to the factorization), as an FP32 MFMA product with FP32
+// accumulation -- the same arithmetic as the trailing update of a diagonal
+// tile -- and the difference formed in T.
+typedef GemmShape<64, 64, 2, 2> DiagUpdShape;
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_potrf_load(const float *__restrict__ Akk, T *__restrict__ W,
+                                                    int nb, DiagUpdate du) {
+  typedef DiagUpdShape S;
+  __shared__ __attribute__((aligned(16))) uint8_t lds[S::LDS_BYTES];
+  int bi, bj;
+  tri_decode(blockIdx.x, bi, bj);
+  OpF32::acc_t acc[S::WTM][S::WTN];
+  zero_acc(acc);
+  for (int q = 0; q < du.npan; ++q)
+    gemm_nt_core<OpF32, S>(OpF32{}, (const uint8_t *)(du.P[q] + (int64_t)bi * 64 * nb),
+                           (int64_t)nb * 4, 64, (const uint8_t *)(du.P[q] + (int64_t)bj * 64 * nb),
+                           (int64_t)nb * 4, 64, (int64_t)nb * 4, acc, lds);
+  if (blockIdx.x == 0 && threadIdx.x < du.npan && du.pmap)
+    du.pmap[du.pmap_at[threadIdx.x]] = (uint8_t)KRR_PREC_FP32;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int tm = 0; tm < S::WTM; ++tm)
+#pragma unroll
+    for (int tn = 0; tn < S::WTN; ++tn)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const int r = bi * 64 + S::row(wave, tm, e, lane), c = bj * 64 + S::col(wave, tn, lane);
+        const int64_t o = (int64_t)r * nb + c;
+        W[o] = (c <= r) ? (T)Akk[o] - (T)acc[tm][tn][e] : (T)0;
+      }
+}
+
+template <typename T>
+static void potrf_tile_t(float *Akk, int k, const TileLayout &L, FactorWork &w,
+                         const DiagUpdate &du, hipStream_t s) {
+  const int nb = L.nb, NB = nb / BS;
+  const int64_t te = (int64_t)nb * nb;
+  T *W = (T *)w.W64, *WL = (T *)w.WL64 + k * te, *Dinv = (T *)w.Dinv64 + (int64_t)k * NB * BS * BS;
   const int64_t colbase = (int64_t)k * nb;
-  hipLaunchKernelGGL(k_potrf_load<T>, dim3(eb), dim3(256), 0, s, Akk, W, nb);
+  hipLaunchKernelGGL(k_potrf_load<T>, dim3(NB * (NB + 1) / 2), dim3(256), 0, s, Akk, W, nb, du);
   hipLaunchKernelGGL(k_potrf_diag64<T>, dim3(1), dim3(256), 0, s, W, WL, nb, Dinv, w.flag,
                      colbase);
   for (int st = 0; st + 1 < NB; ++st) {
@@ -453,58 +523,159 @@ static void potrf_tile_t(float *Akk, float *Linv, int k, const TileLayout &L, Fa
     hipLaunchKernelGGL(k_potrf_step<T>, dim3(rest * (rest + 1) / 2), dim3(256), 0, s, W, WL, nb,
                        st, Dinv, w.flag, colbase);
   }
-  hipLaunchKernelGGL(k_trtri_init<T>, dim3(eb), dim3(256), 0, s, Dinv, Winv, nb);
-  for (int b = BS; b < nb; b *= 2) {
-    const unsigned nbk = (unsigned)(b / BS), pairs = (unsigned)(nb / (2 * b));
-    hipLaunchKernelGGL(k_trtri_level<T>, dim3(nbk, nbk, pairs), dim3(256), 0, s, WL, Winv, Tmp, nb,
-                       b, 0);
-    hipLaunchKernelGGL(k_trtri_level<T>, dim3(nbk, nbk, pairs), dim3(256), 0, s, WL, Winv, Tmp, nb,
-                       b, 1);
-  }
-  hipLaunchKernelGGL(k_potrf_store<T>, dim3(eb), dim3(256), 0, s, WL, Winv, Akk, Linv, nb);
 }
 
-void launch_potrf_tile(float *Akk, float *Linv, int k, const TileLayout &L, bool fp64,
-                       FactorWork &w, hipStream_t s) {
+void launch_potrf_tile(float *Akk, int k, const TileLayout &L, bool fp64, FactorWork &w,
+                       const DiagUpdate &du, hipStream_t s) {
   if (fp64)
-    potrf_tile_t<double>(Akk, Linv, k, L, w, s);
+    potrf_tile_t<double>(Akk, k, L, w, du, s);
   else
-    potrf_tile_t<float>(Akk, Linv, k, L, w, s);
+    potrf_tile_t<float>(Akk, k, L, w, du, s);
 }
 
 // ---------------------------------------------------------------------------
-// Panel TRSM as an FP32 MFMA product: P_i = A_ik * inv(L_kk)^T, i > k.  The
-// output goes to the panel buffer (A_ik is read by other workgroups of the
-// same tile).  Each 128 x 128 block also leaves its FP64 sum of squares and
-// its max |entry| for the operand norms and scales.
-constexpr int UB = 128;  // block edge of the factorization GEMMs
-typedef GemmShape<UB, UB, 2, 2, 1> UpdShape;
+// Panel TRSM: P_i = A_ik inv(L_kk)^T, i.e. P_i L_kk^T = A_ik, by block forward
+// substitution with the diagonal tile's factor and its 64-block inverses:
+//   P[:, s] = (A[:, s] - sum_{t<s} P[:, t] L_st^T) inv(L_ss)^T,  s = 0 .. nb/64-1.
+// Rows are independent: one workgroup per 16 rows of one tile i = k+1+t
+// (t_lo <= t), keeping its rows of P in LDS in T (the diagonal factor's
+// precision); wave w owns columns 16w .. 16w+15 of each 64-column block.
+// The panel buffer gets P in FP32, and each workgroup leaves the FP64 sum of
+// squares and the max |entry| of its rows (for the operand norms and scales).
+// It needs no inverse of the whole tile, so no tile inverse lies on the
+// factorization's critical path.
+constexpr int TRSM_ROWS = 16;
 
+template <typename T>
 __global__ __launch_bounds__(256) void k_trsm_panel(const float *__restrict__ Astore,
-                                                    const float *__restrict__ Linv, int k, int nb,
-                                                    int SB, float *__restrict__ P32,
+                                                    const T *__restrict__ WLk,
+                                                    const T *__restrict__ Dinvk, int k, int t_lo,
+                                                    int nb, int parts, float *__restrict__ P32,
                                                     double *__restrict__ pnorm_part,
                                                     float *__restrict__ pmax_part) {
-  typedef UpdShape S;
+  typedef typename M16<T>::v4 v4;
+  __shared__ T Pr[TRSM_ROWS][512 + 1];
+  __shared__ T Tb[TRSM_ROWS][BS + 1];
+  __shared__ double shd[4];
+  __shared__ float shf[4];
+  const int RS = nb / TRSM_ROWS;
+  const int64_t t = t_lo + blockIdx.x / RS;
+  const int r0 = (blockIdx.x % RS) * TRSM_ROWS;
+  const int64_t i = k + 1 + t, te = (int64_t)nb * nb;
+  const float *A = Astore + (i * (i + 1) / 2 + k) * te + (int64_t)r0 * nb;
+  float *Pout = P32 + t * te + (int64_t)r0 * nb;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, li = lane & 15, lg = lane >> 4;
+  double ss = 0.0;
+  float mx = 0.0f;
+  for (int s = 0; s < nb / BS; ++s) {
+    const int c0 = BS * s + 16 * wave;  // this wave's 16 output columns
+    // B(kk, c) = L[c0 + c][kk] over kk < 64 s
+    const T *Lrow = WLk + (int64_t)(c0 + li) * nb;
+    v4 acc = {0, 0, 0, 0};
+#pragma unroll 2
+    for (int kk = 0; kk < BS * s; kk += 16) {
+      T bv[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) bv[u] = Lrow[kk + 4 * u + lg];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc = M16<T>::mma(Pr[li][kk + 4 * u + lg], bv[u], acc);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = M16<T>::row(r, lane);
+      Tb[row][16 * wave + li] = (T)A[(int64_t)row * nb + c0 + li] - acc[r];
+    }
+    __syncthreads();
+    // P[:, c0 ..] = Tb inv(L_ss)^T: B(j, c) = inv(L_ss)[16 w + c][j]
+    const T *Drow = Dinvk + (int64_t)s * BS * BS + (16 * wave + li) * BS;
+    v4 acc2 = {0, 0, 0, 0};
+#pragma unroll
+    for (int j = 0; j < BS; j += 16) {
+      T bv[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) bv[u] = Drow[j + 4 * u + lg];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc2 = M16<T>::mma(Tb[li][j + 4 * u + lg], bv[u], acc2);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = M16<T>::row(r, lane);
+      const float f = (float)acc2[r];
+      Pr[row][c0 + li] = acc2[r];
+      Pout[(int64_t)row * nb + c0 + li] = f;
+      ss += (double)f * (double)f;
+      mx = fmaxf(mx, fabsf(f));
+    }
+    __syncthreads();
+  }
+  ss = block_sum<4>(ss, shd);
+  mx = block_max<4>(mx, shf);
+  if (threadIdx.x == 0) {
+    pnorm_part[t * parts + blockIdx.x % RS] = ss;
+    pmax_part[t * parts + blockIdx.x % RS] = mx;
+  }
+  // a tile has `parts` slots; the ones past RS stay empty here
+  if (blockIdx.x % RS == 0 && threadIdx.x >= RS && threadIdx.x < parts) {
+    pnorm_part[t * parts + threadIdx.x] = 0.0;
+    pmax_part[t * parts + threadIdx.x] = 0.0f;
+  }
+}
+
+// Partial-norm slots per tile: the substitution TRSM fills nb/16 of them, the
+// product form one per 64 x 64 block.
+static int trsm_parts(int nb) { return std::max((nb / 64) * (nb / 64), nb / TRSM_ROWS); }
+
+template <typename T>
+static void trsm_subst_t(const float *Astore, int k, const TileLayout &L, FactorWork &w,
+                         const PanelBuf &pb, int t_lo, int t_hi, hipStream_t s) {
+  const int nb = L.nb, RS = nb / TRSM_ROWS, NB = nb / BS;
+  const int64_t te = (int64_t)nb * nb;
+  hipLaunchKernelGGL(k_trsm_panel<T>, dim3((unsigned)((t_hi - t_lo) * RS)), dim3(256), 0, s, Astore,
+                     (const T *)w.WL64 + k * te, (const T *)w.Dinv64 + (int64_t)k * NB * BS * BS,
+                     k, t_lo, nb, trsm_parts(nb), pb.P32, w.pnorm_part, w.pmax_part);
+}
+
+void launch_trsm_subst(const float *Astore, int k, const TileLayout &L, bool fp64, FactorWork &w,
+                       const PanelBuf &pb, int t_lo, int t_hi, hipStream_t s) {
+  t_hi = std::min(t_hi, L.nt - 1 - k);
+  if (t_hi <= t_lo) return;
+  if (fp64)
+    trsm_subst_t<double>(Astore, k, L, w, pb, t_lo, t_hi, s);
+  else
+    trsm_subst_t<float>(Astore, k, L, w, pb, t_lo, t_hi, s);
+}
+
+// Panel TRSM as an FP32 MFMA product with the tile inverse:
+// P_i = A_ik inv(L_kk)^T for the tiles i = k+1+t, t >= t_lo, 64 x 64 blocks,
+// each leaving its FP64 sum of squares and max |entry|.
+typedef GemmShape<64, 64, 2, 2> TrsmShape;
+
+__global__ __launch_bounds__(256) void k_trsm_gemm(const float *__restrict__ Astore,
+                                                   const float *__restrict__ Linv, int k, int t_lo,
+                                                   int nb, int parts, float *__restrict__ P32,
+                                                   double *__restrict__ pnorm_part,
+                                                   float *__restrict__ pmax_part) {
+  typedef TrsmShape S;
+  constexpr int B = S::kBM;
   __shared__ __attribute__((aligned(16))) uint8_t lds[S::LDS_BYTES];
   __shared__ double shd[4];
   __shared__ float shf[4];
+  const int SB = nb / B, nsub = SB * SB;
   const int64_t bid = xcd_remap(blockIdx.x, gridDim.x);
-  const int nsub = SB * SB;
   const int sub = (int)(bid % nsub);
-  const int64_t t = bid / nsub;
+  const int64_t t = t_lo + bid / nsub;
   const int64_t i = k + 1 + t;
   const int si = sub / SB, sj = sub % SB;
   const int64_t te = (int64_t)nb * nb;
-  const float *Ablk = Astore + (i * (i + 1) / 2 + k) * te + (int64_t)si * UB * nb;
-  const float *Bblk = Linv + (int64_t)sj * UB * nb;
-  const int64_t kbytes = (int64_t)min(nb, (sj + 1) * UB) * 4;  // inv(L) is lower triangular
+  const float *Ablk = Astore + (i * (i + 1) / 2 + k) * te + (int64_t)si * B * nb;
+  const float *Bblk = Linv + (int64_t)sj * B * nb;
+  const int64_t kbytes = (int64_t)min(nb, (sj + 1) * B) * 4;  // inv(L) is lower triangular
   OpF32::acc_t acc[S::WTM][S::WTN];
   zero_acc(acc);
-  gemm_nt_core<OpF32, S>(OpF32{}, (const uint8_t *)Ablk, (int64_t)nb * 4, UB, (const uint8_t *)Bblk,
-                         (int64_t)nb * 4, UB, kbytes, acc, lds);
+  gemm_nt_core<OpF32, S>(OpF32{}, (const uint8_t *)Ablk, (int64_t)nb * 4, B, (const uint8_t *)Bblk,
+                         (int64_t)nb * 4, B, kbytes, acc, lds);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  float *out = P32 + t * te + (int64_t)si * UB * nb + sj * UB;
+  float *out = P32 + t * te + (int64_t)si * B * nb + sj * B;
   double ss = 0.0;
   float mx = 0.0f;
 #pragma unroll
@@ -523,18 +694,23 @@ __global__ __launch_bounds__(256) void k_trsm_panel(const float *__restrict__ As
   ss = block_sum<4>(ss, shd);
   mx = block_max<4>(mx, shf);
   if (threadIdx.x == 0) {
-    pnorm_part[bid] = ss;
-    pmax_part[bid] = mx;
+    pnorm_part[t * parts + sub] = ss;
+    pmax_part[t * parts + sub] = mx;
+  }
+  if (sub == 0 && threadIdx.x >= nsub && threadIdx.x < parts) {
+    pnorm_part[t * parts + threadIdx.x] = 0.0;
+    pmax_part[t * parts + threadIdx.x] = 0.0f;
   }
 }
 
-void launch_trsm_panel(const float *Astore, const float *Linv, int k, const TileLayout &L,
-                       FactorWork &w, const PanelBuf &pb, hipStream_t s) {
-  const int SB = L.nb / UB;
-  const int64_t tiles = L.nt - 1 - k;
-  if (tiles <= 0) return;
-  hipLaunchKernelGGL(k_trsm_panel, dim3((unsigned)(tiles * SB * SB)), dim3(256), 0, s, Astore,
-                     Linv, k, L.nb, SB, pb.P32, w.pnorm_part, w.pmax_part);
+void launch_trsm_gemm(const float *Astore, const float *Linv_k, int k, const TileLayout &L,
+                      FactorWork &w, const PanelBuf &pb, int t_lo, int t_hi, hipStream_t s) {
+  t_hi = std::min(t_hi, L.nt - 1 - k);
+  if (t_hi <= t_lo) return;
+  const int SB = L.nb / TrsmShape::kBM;
+  hipLaunchKernelGGL(k_trsm_gemm, dim3((unsigned)((t_hi - t_lo) * SB * SB)), dim3(256), 0, s,
+                     Astore, Linv_k, k, t_lo, L.nb, trsm_parts(L.nb), pb.P32, w.pnorm_part,
+                     w.pmax_part);
 }
 
 // Panel conversion: reduce each tile's partial norms (fixed order), pick the
@@ -587,9 +763,9 @@ void launch_convert_panel(float *Astore, int k, const TileLayout &L, FactorWork 
   const int64_t tiles = L.nt - 1 - k;
   if (tiles <= 0) return;
   const int chunks = (int)((int64_t)L.nb * L.nb / CONV_CHUNK);
-  const int SB = L.nb / UB;
   hipLaunchKernelGGL(k_convert_panel, dim3((unsigned)(tiles * chunks)), dim3(256), 0, s, pb.P32,
-                     Astore, pb.P16, pb.P8, w.pnorm_part, w.pmax_part, SB * SB, pb.pnorm, pb.pexp8,
+                     Astore, pb.P16, pb.P8, w.pnorm_part, w.pmax_part, trsm_parts(L.nb), pb.pnorm,
+                     pb.pexp8,
                      k, L.nb, chunks, need16 ? 1 : 0, need8 ? 1 : 0);
 }
 
@@ -787,7 +963,7 @@ __global__ __launch_bounds__(S::THREADS) void k_update(
 
 void launch_update(float *Astore, int k0, int npan, int jlo, int jhi, const TileLayout &L,
                    const UpdatePolicy &pol, FactorWork &w, const PanelBuf *const *pbs,
-                   uint8_t *pmap, hipStream_t s) {
+                   uint8_t *pmap, int which, hipStream_t s) {
   const int NT = L.nt;
   if (npan <= 0 || jlo > jhi || jlo >= NT) return;
   if (jhi > NT - 1) jhi = NT - 1;
@@ -816,7 +992,7 @@ void launch_update(float *Astore, int k0, int npan, int jlo, int jhi, const Tile
                         hipFuncAttributeMaxDynamicSharedMemorySize, UpdDiagStream::LDS_BYTES);
     attr = true;
   }
-  {  // diagonal tiles first: they are the longest per block
+  if (which != UPD_OFFDIAG) {  // diagonal tiles first: they are the longest per block
     const int SB = L.nb / UpdDiagStream::kBM;
     const int64_t blocks = (int64_t)(jhi - jlo + 1) * SB * (SB + 1) / 2;
     hipLaunchKernelGGL((k_update<UpdDiagStream, true>), dim3((unsigned)blocks),
@@ -824,6 +1000,7 @@ void launch_update(float *Astore, int k0, int npan, int jlo, int jhi, const Tile
                        npan, jlo, jhi, NT, L.nb, SB, pol.mode, pol.allow16, pol.allow8,
                        pol.high_panels, pol.fixed_prec, pol.thr, pmap, L.ntiles());
   }
+  if (which == UPD_DIAG) return;
   if (offdiag > 0 && offdiag * 4 < 8 * 256) {
     // few tiles (the updates inside a panel group, on the critical path):
     // small blocks, several per CU, for latency

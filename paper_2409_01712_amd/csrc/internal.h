@@ -58,28 +58,50 @@ struct PanelBuf {
 constexpr int KRR_MAX_GROUP = 8;  // panels per grouped trailing update
 // Workspace for the factorization, sized for nt tiles of nb.
 struct FactorWork {
-  double *W64 = nullptr;     // nb x nb FP64 (or FP32) diagonal workspace
-  double *WL64 = nullptr;    // nb x nb: its factor
-  double *Winv64 = nullptr;  // nb x nb
-  double *Dinv64 = nullptr;  // (nb/64) blocks of 64 x 64
-  double *Tmp64 = nullptr;   // nb x nb / 2 scratch for the tile inverse
+  // diagonal tiles, FP64 (or FP32 under the plain policy)
+  double *W64 = nullptr;     // nb x nb: the tile being factored
+  double *WL64 = nullptr;    // nt x nb x nb: the factors L_kk
+  double *Dinv64 = nullptr;  // nt x (nb/64) inverses of their 64 x 64 diagonal blocks
+  double *Winv64 = nullptr;  // inv_chunk x nb x nb: tile inverses, a chunk at a time
+  double *Tmp64 = nullptr;   // inv_chunk x nb x nb / 2
+  int inv_chunk = 16;
   PanelBuf pb[2 * KRR_MAX_GROUP];  // two groups of panel operand copies
-  double *pnorm_part = nullptr;  // (nt-1) * parts
+  double *pnorm_part = nullptr;  // (nt-1) * parts (max((nb/64)^2, nb/16))
   float *pmax_part = nullptr;    // (nt-1) * parts
   int32_t *flag = nullptr;       // breakdown column + 1 (0 = none)
   unsigned long long *counts = nullptr;  // [3] updates per precision
 };
-void launch_potrf_tile(float *Akk, float *Linv, int k, const TileLayout &L, bool fp64,
-                       FactorWork &w, hipStream_t s);
-void launch_trsm_panel(const float *Astore, const float *Linv, int k, const TileLayout &L,
-                       FactorWork &w, const PanelBuf &pb, hipStream_t s);
+// Updates of a diagonal tile left to its factorization: P[q] points at tile
+// k of panel buffer q; pmap_at[q] is the precision-map entry to mark FP32.
+struct DiagUpdate {
+  const float *P[KRR_MAX_GROUP];
+  int64_t pmap_at[KRR_MAX_GROUP];
+  uint8_t *pmap;
+  int npan;
+};
+// Diagonal tile k: L_kk = chol(A_kk - sum_q P_q P_q^T) into the work's
+// factor store (tile k), with the inverses of its 64 x 64 diagonal blocks.
+void launch_potrf_tile(float *Akk, int k, const TileLayout &L, bool fp64, FactorWork &w,
+                       const DiagUpdate &du, hipStream_t s);
+// L_kk into the factor storage and inv(L_kk), FP32, for the diagonal tiles
+// k_lo .. k_hi-1 (factored before).
+void launch_tile_inverses(float *Lst, float *Linv, int k_lo, int k_hi, const TileLayout &L,
+                          bool fp64, FactorWork &w, hipStream_t s);
+// P_i = A_ik inv(L_kk)^T for the tiles i = k+1+t, t_lo <= t < t_hi: by
+// substitution with the factor of tile k (no inverse needed), or as a product
+// with inv(L_kk) (launch_tile_inverses first).
+void launch_trsm_subst(const float *Astore, int k, const TileLayout &L, bool fp64, FactorWork &w,
+                       const PanelBuf &pb, int t_lo, int t_hi, hipStream_t s);
+void launch_trsm_gemm(const float *Astore, const float *Linv_k, int k, const TileLayout &L,
+                      FactorWork &w, const PanelBuf &pb, int t_lo, int t_hi, hipStream_t s);
 void launch_convert_panel(float *Astore, int k, const TileLayout &L, FactorWork &w,
                           const PanelBuf &pb, bool need16, bool need8, hipStream_t s);
 // Trailing update of the tiles (i, j), jlo <= j <= jhi, j <= i, by the npan
 // consecutive panels k0 .. k0+npan-1 whose operand copies are *pbs[q].
 void launch_update(float *Astore, int k0, int npan, int jlo, int jhi, const TileLayout &L,
                    const UpdatePolicy &pol, FactorWork &w, const PanelBuf *const *pbs,
-                   uint8_t *pmap, hipStream_t s);
+                   uint8_t *pmap, int which, hipStream_t s);
+enum { UPD_ALL = 0, UPD_DIAG = 1, UPD_OFFDIAG = 2 };  // tiles launch_update covers
 // counts[p] += number of entries of pmap equal to p (p = 0, 1, 2)
 void launch_count_pmap(const uint8_t *pmap, int64_t n, unsigned long long *counts,
                        hipStream_t s);
