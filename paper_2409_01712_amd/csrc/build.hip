@@ -15,6 +15,15 @@ namespace krr {
 
 // exp(-gamma * d) for every integer distance d in [0, len): the FP64 kernel
 // value of any entry is then a table lookup, bit-identical to evaluating exp.
+// The FP32 matrix handed to the factorization takes the value in two factors,
+// exp(-gamma d) = exp(-gamma 512 hi) exp(-gamma lo), d = 512 hi + lo: two
+// small tables that stay in LDS, the FP64 product rounded to FP32 (within one
+// FP32 ulp of the correctly rounded value).
+constexpr int EXP_LO = 512;         // entries of the low table
+constexpr int EXP_HI_MAX = 2048;    // largest high table kept in LDS
+KRR_DEV double exp_two_level(const double *hi, const double *lo, int32_t d) {
+  return hi[d / EXP_LO] * lo[d % EXP_LO];
+}
 __global__ void k_exp_table(double *tab, int64_t len, double gamma) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < len) tab[i] = exp(-gamma * (double)i);
@@ -69,26 +78,35 @@ void launch_row_norms(const int8_t *G, int64_t n, int64_t rows_padded, int64_t m
 
 // Symmetric Gram over the lower tile triangle.  Block (BM x BN) = one
 // sub-block of tile (I, J); SB x SB sub-blocks per tile.  Epilogue per
-// entry: d = n_i + n_j - 2 S (int32), A = exp(-gamma d) in FP64 rounded to
-// FP32 (table lookup), 1 + lambda on the diagonal, identity on padding; plus
-// the sub-block's FP64 sum of squares for the tile norms.
+// entry: d = n_i + n_j - 2 S (int32), A = exp(-gamma d) (two-level table in
+// LDS, FP64 product rounded to FP32), 1 + lambda on the diagonal, identity
+// on padding; plus the sub-block's FP64 sum of squares for the tile norms.
 template <class S>
 __global__ __launch_bounds__(S::THREADS) void k_gram_tiles(const int8_t *__restrict__ G, int64_t n,
                                                     int64_t m, int64_t ldg,
                                                     const int32_t *__restrict__ nrm,
                                                     const double *__restrict__ etab,
                                                     int64_t etab_len, double lambda, int nb,
-                                                    int SB, int32_t *__restrict__ D,
+                                                    int nt, int SB, int32_t *__restrict__ D,
                                                     float *__restrict__ A, double *part) {
   constexpr int BM = S::kBM, BN = S::kBN, NW = S::THREADS / 64;
   extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
   __shared__ double shd[NW];
+  __shared__ double ehi[EXP_HI_MAX], elo[EXP_LO];
+  const int64_t dmax = etab_len - 1;
+  const int nhi = (int)(dmax / EXP_LO) + 1;
+  const bool two_level = nhi <= EXP_HI_MAX;
+  if (two_level) {  // visible to the epilogue through the GEMM's barriers
+    for (int q = threadIdx.x; q < EXP_LO; q += S::THREADS) elo[q] = etab[min((int64_t)q, dmax)];
+    for (int q = threadIdx.x; q < nhi; q += S::THREADS) ehi[q] = etab[(int64_t)q * EXP_LO];
+  }
   const int64_t bid = xcd_remap(blockIdx.x, gridDim.x);
   const int nsub = SB * SB;
   const int sub = (int)(bid % nsub);
-  const int64_t t = bid / nsub;
+  const int64_t t = bid / nsub;  // tile in the order of the launch
   int I, J;
   tri_decode(t, I, J);
+  const int64_t tt = tri_index(I, J);  // its place in the packed storage
   const int si = sub / SB, sj = sub % SB;
   const int64_t row0 = (int64_t)I * nb + si * BM, col0 = (int64_t)J * nb + sj * BN;
   const int arows = (int)max((int64_t)0, min((int64_t)BM, n - row0));
@@ -100,9 +118,10 @@ __global__ __launch_bounds__(S::THREADS) void k_gram_tiles(const int8_t *__restr
     gemm_nt_stream<OpI8, S>(
         ContigSrc<OpI8>{(const uint8_t *)G + row0 * ldg, (const uint8_t *)G + col0 * ldg, OpI8{}},
         ldg, arows, ldg, brows, m, acc, lds);
+  __syncthreads();  // the tables (also when the product was skipped)
 
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int64_t tbase = t * (int64_t)nb * nb;
+  const int64_t tbase = tt * (int64_t)nb * nb;
   double ss = 0.0;
 #pragma unroll
   for (int tm = 0; tm < S::WTM; ++tm)
@@ -117,7 +136,9 @@ __global__ __launch_bounds__(S::THREADS) void k_gram_tiles(const int8_t *__restr
         float a;
         if (gi < n && gj < n) {
           d = nrm[gi] + nrm[gj] - 2 * acc[tm][tn][i];
-          a = (gi == gj) ? (float)(1.0 + lambda) : (float)etab[min((int64_t)max(d, 0), etab_len - 1)];
+          const int32_t dc = (int32_t)min((int64_t)max(d, 0), dmax);
+          const double e = two_level ? exp_two_level(ehi, elo, dc) : etab[dc];
+          a = (gi == gj) ? (float)(1.0 + lambda) : (float)e;
         } else {
           d = 0;
           a = (gi == gj) ? 1.0f : 0.0f;
@@ -128,7 +149,7 @@ __global__ __launch_bounds__(S::THREADS) void k_gram_tiles(const int8_t *__restr
         ss += (double)a * (double)a;
       }
   ss = block_sum<NW>(ss, shd);
-  if (threadIdx.x == 0) part[bid] = ss;
+  if (threadIdx.x == 0) part[tt * nsub + sub] = ss;
 }
 
 typedef StreamShape<256, 256, 2, 4, 4> GramShape;
@@ -146,7 +167,7 @@ void launch_gram_tiles(const int8_t *G, int64_t m, int64_t ldg, const int32_t *n
   }
   hipLaunchKernelGGL((k_gram_tiles<GramShape>), dim3((unsigned)blocks), dim3(GramShape::THREADS),
                      GramShape::LDS_BYTES, s, G, L.n, m,
-                     ldg, nrm, etab, etab_len, lambda, L.nb, SB, D, A, tnorm_part);
+                     ldg, nrm, etab, etab_len, lambda, L.nb, L.nt, SB, D, A, tnorm_part);
 }
 
 // Tile Frobenius norms from the per-sub-block partial sums, in fixed order.
@@ -177,11 +198,16 @@ __global__ void k_expand_tiles(const int32_t *__restrict__ D, const double *__re
   tri_decode(t, I, J);
   const int64_t gi = (int64_t)I * nb + w / nb, gj = (int64_t)J * nb + w % nb;
   float a;
-  if (gi < n && gj < n)
-    a = (gi == gj) ? (float)(1.0 + lambda)
-                   : (float)etab[min((int64_t)max(D[e], 0), etab_len - 1)];
-  else
+  if (gi < n && gj < n) {  // the same value as the Gram epilogue
+    const int64_t dmax = etab_len - 1;
+    const int32_t dc = (int32_t)min((int64_t)max(D[e], 0), dmax);
+    const double ev = (dmax / EXP_LO + 1 <= EXP_HI_MAX)
+                          ? etab[(int64_t)(dc / EXP_LO) * EXP_LO] * etab[dc % EXP_LO]
+                          : etab[dc];
+    a = (gi == gj) ? (float)(1.0 + lambda) : (float)ev;
+  } else {
     a = (gi == gj) ? 1.0f : 0.0f;
+  }
   A[e] = a;
 }
 
