@@ -85,7 +85,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="single", choices=["single", "small"])
+    ap.add_argument("--workload", default="single", choices=["single", "small", "batched"])
+    ap.add_argument("--batch", type=int, default=48, help="instances of the batched workload")
     ap.add_argument("--n", type=int, default=0, help="override the number of patients")
     ap.add_argument("--plain-steps", type=int, default=1)
     ap.add_argument("--no-plain", action="store_true")
@@ -122,6 +123,8 @@ def main():
     import synth
     import paper_2409_01712_amd as krr
 
+    if args.workload == "batched":
+        return main_batched(args)
     w = synth.WORKLOADS[args.workload]
     n = args.n or w.n
     m, r = w.m, w.r
@@ -254,6 +257,99 @@ def main():
             "sample": "first %d patients of the same genotype matrix (all %d SNPs, %d phenotypes): "
                       "FP64 build + Cholesky + solves, %.1f s" % (ns, m, r, cdt),
         }
+    print(json.dumps(out), flush=True)
+
+
+def main_batched(args):
+    """Many independent instances (uneven n, differing gamma and lambda, one SNP panel)
+    through the batched calls: one step = batched build + factor + solve of all of them."""
+    import numpy as np
+    import torch
+
+    import synth
+    import paper_2409_01712_amd as krr
+
+    insts = synth.batched_workloads(count=args.batch)
+    dev = torch.device("cuda:0")
+    Gs, Ys = [], []
+    t0 = time.time()
+    for w, row0 in insts:
+        Gh = w.genotypes(rows=w.n, row0=row0)
+        Yh = w.phenotypes(Gh)
+        Gs.append(torch.from_numpy(Gh).to(dev))
+        Ys.append(torch.from_numpy(Yh).to(dev))
+        del Gh
+    torch.cuda.synchronize()
+    gen_s = time.time() - t0
+    gammas = [w.gamma for w, _ in insts]
+    lams = [w.lam for w, _ in insts]
+    m, r = insts[0][0].m, insts[0][0].r
+    ns = [w.n for w, _ in insts]
+    ctx = krr.krr_create(0, tile=args.tile)
+    adaptive = krr.Policy(eps=args.eps, high_panels=args.high_panels)
+    refine = krr.Refine(method=krr.KRR_REFINE_IR, max_iters=30, tol=REFINE_TOL)
+
+    def step(policy, ref):
+        Ks = krr.krr_build_kernel_batched(ctx, Gs, gammas, lams)
+        Fs = krr.krr_factor_batched(ctx, Ks, policy)
+        Xs, infos, st = krr.krr_solve_batched(ctx, Fs, Ys, ref, check=False)
+        for F in Fs:
+            F.release()
+        for K in Ks:
+            K.release()
+        return infos
+
+    for _ in range(args.warmup):
+        step(adaptive, refine)
+    torch.cuda.synchronize()
+    krr.krr_timers_enable(ctx, True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        infos = step(adaptive, refine)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    stages = krr.krr_timers_read(ctx)
+    krr.krr_timers_enable(ctx, False)
+    ops = sum(ops_per_step(n, m, r) for n in ns)
+    gram_ops = sum(float(n) * n * m for n in ns)
+    g_ms, g_cnt = stages["gram"]
+    achieved = gram_ops / (g_ms / g_cnt / 1e3) / 1e12
+    out = {
+        "metric": "KRR build+factor+solve Op/s vs plain FP32 GPU path at <=1e-5 rel err vs FP64",
+        "value": ops / dt, "unit": "Op/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": dt * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "mixed:i8,f8,f16,f32,f64",
+        "data": "synthetic (seeded Philox Binomial(2,p) genotypes, epistatic phenotypes)",
+        "config": {
+            "workload": "batch of %d KRR instances, n in [%d, %d] (sum %d), m=%d, r=%d, "
+                        "gamma in {0.5,1,2}/m, lambda in {1e-3,1e-2,1e-1,1}, tile %d"
+                        % (len(ns), min(ns), max(ns), sum(ns), m, r, args.tile),
+            "batch": len(ns), "m": m, "nrhs": r, "tile": args.tile,
+            "parallelism": "single GPU",
+        },
+        "ops_per_step": ops,
+        "refine": {"max_iters": max(i.iters for i in infos),
+                   "max_fwd_err_bound": max(i.fwd_err_bound for i in infos),
+                   "converged": int(sum(i.converged for i in infos))},
+        "stages_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in stages.items() if v[1]},
+        "roofline": {"kernel": "k_gram_tiles_batched (all instances in one launch)",
+                     "bound": "mfma", "achieved": achieved, "peak": PEAK["int8_TOPs"],
+                     "unit": "TOP/s", "frac": achieved / PEAK["int8_TOPs"], "traffic": None,
+                     "avg_launch_ms": g_ms / g_cnt},
+        "input_generation_s": gen_s,
+    }
+    if not args.no_plain:
+        plain = krr.plain_fp32_policy()
+        no_refine = krr.Refine(method=krr.KRR_REFINE_NONE)
+        step(plain, no_refine)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.plain_steps):
+            step(plain, no_refine)
+        torch.cuda.synchronize()
+        pdt = (time.perf_counter() - t0) / args.plain_steps
+        out["plain_fp32"] = {"value": ops / pdt, "ms_per_step": pdt * 1e3}
+        out["speedup_vs_plain_fp32"] = pdt / dt
     print(json.dumps(out), flush=True)
 
 

@@ -186,6 +186,43 @@ krr_status krr_solve(krr_context ctx, krr_factorization F, const double *Y, int6
 krr_status krr_predict(krr_context ctx, krr_kernel K, const int8_t *T, int64_t n_test, int64_t ldt,
                        const double *X, int64_t nrhs, int64_t ldx, double *P, int64_t ldp);
 
+/* ---- batches of independent instances ---------------------------------
+ * Many KRR problems at once, as in a cross-validation over (gamma, lambda)
+ * pairs on one genotype panel (the Overview's hyperparameter search): each
+ * call takes `batch` instances through the same phase.  Array arguments are
+ * HOST arrays of length `batch` (the pointers they hold are device
+ * pointers); outputs are written per instance and every instance behaves as
+ * in the single-instance call.  On any error no handle is returned (out[]
+ * all NULL) and the status is that of the first failure.
+ */
+
+/* Build of `batch` kernels sharing the SNP count m: instance b has G[b]
+ * (n[b] x m, ldg[b]), gamma[b], lambda[b].  Row norms, exp tables, the INT8
+ * Gram with its epilogue and the tile norms each run as ONE launch over all
+ * instances (larger instances first).  KRR_ERROR_BAD_GENOTYPE if any G[b]
+ * holds a value > 2.  Blocks until the build is done. */
+krr_status krr_build_kernel_batched(krr_context ctx, int32_t batch, const int8_t *const *G,
+                                    const int64_t *n, int64_t m, const int64_t *ldg,
+                                    const double *gamma, const double *lambda, krr_kernel *out);
+/* Factorization of `batch` distinct kernels under one policy (NULL =
+ * ADAPTIVE defaults).  Instances are spread over 4 streams by their
+ * Cholesky cost (longest first to the least loaded stream); each stream
+ * factors its instances in turn with one workspace sized for its largest.
+ * An instance that breaks down is then factored again on its own with
+ * promotion, exactly as krr_factor does.  Blocks until all are done. */
+krr_status krr_factor_batched(krr_context ctx, int32_t batch, const krr_kernel *K,
+                              const krr_precision_policy *policy, krr_factorization *out);
+/* Solve of `batch` factorizations with nrhs right-hand sides each: Y[b],
+ * X[b] are n_b x nrhs FP64 column-major (ldy[b], ldx[b] >= n_b).  The
+ * refinement of every instance advances together: one host wait per
+ * iteration for the whole batch.  info (NULL or `batch` entries) reports
+ * each instance; KRR_ERROR_NOT_CONVERGED if any instance missed the
+ * tolerance (its X holds the last iterate). */
+krr_status krr_solve_batched(krr_context ctx, int32_t batch, const krr_factorization *F,
+                             const double *const *Y, int64_t nrhs, const int64_t *ldy,
+                             double *const *X, const int64_t *ldx, const krr_refine_opts *opts,
+                             krr_solve_info *info);
+
 /* ---- diagnostics (tests and reports) ---------------------------------- */
 
 /* Copy the rows x cols block at (i0, j0) of the exact int32 distance

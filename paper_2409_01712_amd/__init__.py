@@ -75,6 +75,11 @@ _SIGS = [
     ("krr_solve", _I, [_P, _P, _P, _I64, _I64, _P, _I64, ctypes.POINTER(krr_refine_opts),
                        ctypes.POINTER(krr_solve_info)]),
     ("krr_predict", _I, [_P, _P, _P, _I64, _I64, _P, _I64, _I64, _P, _I64]),
+    ("krr_build_kernel_batched", _I, [_P, ctypes.c_int32, _P, _P, _I64, _P, _P, _P, _P]),
+    ("krr_factor_batched", _I, [_P, ctypes.c_int32, _P, ctypes.POINTER(krr_precision_policy),
+                                _P]),
+    ("krr_solve_batched", _I, [_P, ctypes.c_int32, _P, _P, _I64, _P, _P, _P,
+                               ctypes.POINTER(krr_refine_opts), _P]),
     ("krr_kernel_copy_distances", _I, [_P, _I64, _I64, _I64, _I64, _P, _I64]),
     ("krr_kernel_copy_matrix", _I, [_P, _I64, _I64, _I64, _I64, _P, _I64]),
     ("krr_factor_copy_l", _I, [_P, _I64, _I64, _I64, _I64, _P, _I64]),
@@ -321,6 +326,59 @@ def krr_solve(ctx: Context, F: Factor, Y, refine: Refine | None = None, check: b
     if check:
         _check(st, "krr_solve")
     return X, info, st
+
+
+def _host_array(ctype, values):
+    return (ctype * len(values))(*values)
+
+
+def krr_build_kernel_batched(ctx: Context, Gs, gammas, lams) -> list:
+    """Kernels of len(Gs) instances sharing the SNP count (one launch per Build stage)."""
+    Gs = [padded_genotypes(G) for G in Gs]
+    B = len(Gs)
+    m = Gs[0].shape[1]
+    assert all(G.shape[1] == m for G in Gs) and len(gammas) == B and len(lams) == B
+    out = (ctypes.c_void_p * B)()
+    _check(load().krr_build_kernel_batched(
+        ctx.handle, B, _host_array(ctypes.c_void_p, [_ptr(G) for G in Gs]),
+        _host_array(ctypes.c_int64, [G.shape[0] for G in Gs]), m,
+        _host_array(ctypes.c_int64, [G.stride(0) for G in Gs]),
+        _host_array(ctypes.c_double, [float(g) for g in gammas]),
+        _host_array(ctypes.c_double, [float(x) for x in lams]), out), "krr_build_kernel_batched")
+    return [Kernel(ctypes.c_void_p(out[b]), ctx, Gs[b], Gs[b].shape[0], m, gammas[b], lams[b])
+            for b in range(B)]
+
+
+def krr_factor_batched(ctx: Context, Ks, policy: Policy | None = None) -> list:
+    B = len(Ks)
+    out = (ctypes.c_void_p * B)()
+    pol = (policy or Policy()).c()
+    _check(load().krr_factor_batched(ctx.handle, B,
+                                     _host_array(ctypes.c_void_p, [K.handle.value for K in Ks]),
+                                     ctypes.byref(pol), out), "krr_factor_batched")
+    return [Factor(ctypes.c_void_p(out[b]), Ks[b]) for b in range(B)]
+
+
+def krr_solve_batched(ctx: Context, Fs, Ys, refine: Refine | None = None, check: bool = True):
+    """Solve every instance; returns ([X_b], [info_b], status).  Ys[b]: (n_b, r) float64."""
+    import torch
+    B = len(Fs)
+    Yc = [_colmajor(Y, F.kernel.n) for Y, F in zip(Ys, Fs)]
+    r = Yc[0].shape[1]
+    assert all(Y.shape[1] == r for Y in Yc)
+    Xs = [torch.empty((r, F.kernel.n), dtype=torch.float64, device=Y.device).t()
+          for F, Y in zip(Fs, Yc)]
+    infos = (krr_solve_info * B)()
+    opts = (refine or Refine()).c()
+    lds = _host_array(ctypes.c_int64, [F.kernel.n for F in Fs])
+    st = load().krr_solve_batched(ctx.handle, B,
+                                  _host_array(ctypes.c_void_p, [F.handle.value for F in Fs]),
+                                  _host_array(ctypes.c_void_p, [_ptr(Y) for Y in Yc]), r, lds,
+                                  _host_array(ctypes.c_void_p, [_ptr(X) for X in Xs]), lds,
+                                  ctypes.byref(opts), infos)
+    if check:
+        _check(st, "krr_solve_batched")
+    return Xs, [infos[b] for b in range(B)], st
 
 
 def krr_predict(ctx: Context, K: Kernel, T, X):

@@ -36,6 +36,8 @@ struct krr_context_s {
   // second stream and events for the factorization's lookahead
   hipStream_t aux = nullptr, side = nullptr, fmain = nullptr;
   std::vector<hipEvent_t> sched_ev;  // ordering events of the factorization schedule
+  std::vector<hipStream_t> bstreams;  // streams of the batched calls
+  std::vector<hipEvent_t> bevents;    // their ordering events
 };
 
 struct krr_kernel_s {
@@ -282,6 +284,11 @@ static void context_free(krr_context ctx) {
     }
   }
   for (hipEvent_t e : ctx->sched_ev) (void)hipEventDestroy(e);
+  for (hipStream_t x : ctx->bstreams) {
+    (void)hipStreamSynchronize(x);
+    (void)hipStreamDestroy(x);
+  }
+  for (hipEvent_t e : ctx->bevents) (void)hipEventDestroy(e);
   delete ctx;
 }
 
@@ -291,6 +298,57 @@ static krr_status context_aux(krr_context ctx) {
   for (hipStream_t *x : {&ctx->fmain, &ctx->side, &ctx->aux})
     if (!*x) HIPCHK(hipStreamCreateWithFlags(x, hipStreamNonBlocking));
   return KRR_SUCCESS;
+}
+
+// Streams for the instances of a batched call (default priority); as many as
+// the process has hardware queues by default, so that they run concurrently.
+constexpr int KRR_BATCH_STREAMS = 4;
+static krr_status context_batch_streams(krr_context ctx, int count) {
+  while ((int)ctx->bstreams.size() < count) {
+    hipStream_t x = nullptr;
+    HIPCHK(hipStreamCreateWithFlags(&x, hipStreamNonBlocking));
+    ctx->bstreams.push_back(x);
+  }
+  return KRR_SUCCESS;
+}
+
+// Orders work on the batch streams 0 .. count-1 after what is already on
+// `from` (join = false), or work on `from` after everything on them (join = true).
+static krr_status batch_fence(krr_context ctx, hipStream_t from, int count, bool join) {
+  std::vector<hipEvent_t> &ev = ctx->bevents;
+  while ((int)ev.size() < count) {
+    hipEvent_t e = nullptr;
+    HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    ev.push_back(e);
+  }
+  if (!join) {
+    HIPCHK(hipEventRecord(ev[0], from));
+    for (int q = 0; q < count; ++q) HIPCHK(hipStreamWaitEvent(ctx->bstreams[q], ev[0], 0));
+  } else {
+    for (int q = 0; q < count; ++q) {
+      HIPCHK(hipEventRecord(ev[q], ctx->bstreams[q]));
+      HIPCHK(hipStreamWaitEvent(from, ev[q], 0));
+    }
+  }
+  return KRR_SUCCESS;
+}
+
+// Longest-processing-time assignment of instances to `count` streams:
+// instances in decreasing cost, each to the least loaded stream.
+static std::vector<int> lpt_assign(const std::vector<double> &cost, int count,
+                                   std::vector<int> &order) {
+  const int B = (int)cost.size();
+  order.resize(B);
+  for (int b = 0; b < B; ++b) order[b] = b;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
+  std::vector<double> load(count, 0.0);
+  std::vector<int> where(B, 0);
+  for (int b : order) {
+    const int q = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    where[b] = q;
+    load[q] += cost[b];
+  }
+  return where;
 }
 
 // A handle was released: free the context if it was destroyed while handles lived.
@@ -326,19 +384,19 @@ static void kernel_free(krr_kernel K) {
   dfree(c, K->tnorm_part, (size_t)L.ntiles() * sb * sb * 8);
 }
 
-krr_status krr_build_kernel(krr_context ctx, const int8_t *G, int64_t n, int64_t m, int64_t ldg,
-                            double gamma, double lambda, krr_kernel *out) {
-  if (!out) return KRR_ERROR_INVALID_VALUE;
-  *out = nullptr;
-  if (!ctx || ctx->destroy_pending || !G || n <= 0 || m <= 0 || ldg < m || (ldg % 16) != 0 ||
-      !aligned16(G))
+static krr_status build_args(const int8_t *G, int64_t n, int64_t m, int64_t ldg, double gamma,
+                             double lambda) {
+  if (!G || n <= 0 || m <= 0 || ldg < m || (ldg % 16) != 0 || !aligned16(G))
     return KRR_ERROR_INVALID_VALUE;
   if (!(gamma > 0) || !isfinite(gamma) || !(lambda >= 0) || !isfinite(lambda))
     return KRR_ERROR_INVALID_VALUE;
   if (m > (1LL << 28) || n > (1LL << 30)) return KRR_ERROR_NOT_SUPPORTED;
-  HIPCHK(hipSetDevice(ctx->device));
-  hipStream_t s = ctx->stream;
+  return KRR_SUCCESS;
+}
 
+// A kernel handle with its device buffers allocated (contents not yet built).
+static krr_status kernel_new(krr_context ctx, const int8_t *G, int64_t n, int64_t m, int64_t ldg,
+                             double gamma, double lambda, krr_kernel *out) {
   krr_kernel K = new krr_kernel_s();
   K->ctx = ctx;
   K->G = G;
@@ -352,7 +410,6 @@ krr_status krr_build_kernel(krr_context ctx, const int8_t *G, int64_t n, int64_t
   K->etab_len = 4 * m + 1;
   const int sb = L.nb / 256;
   krr_status st = KRR_SUCCESS;
-  int32_t *flag = nullptr;
   do {
     if ((st = dalloc_t(ctx, &K->D, L.elems())) != KRR_SUCCESS) break;
     if ((st = dalloc_t(ctx, &K->A, L.elems())) != KRR_SUCCESS) break;
@@ -360,6 +417,31 @@ krr_status krr_build_kernel(krr_context ctx, const int8_t *G, int64_t n, int64_t
     if ((st = dalloc_t(ctx, &K->etab, K->etab_len)) != KRR_SUCCESS) break;
     if ((st = dalloc_t(ctx, &K->tnorm, L.ntiles())) != KRR_SUCCESS) break;
     if ((st = dalloc_t(ctx, &K->tnorm_part, L.ntiles() * sb * sb)) != KRR_SUCCESS) break;
+  } while (0);
+  if (st != KRR_SUCCESS) {
+    kernel_free(K);
+    delete K;
+    K = nullptr;
+  }
+  *out = K;
+  return st;
+}
+
+krr_status krr_build_kernel(krr_context ctx, const int8_t *G, int64_t n, int64_t m, int64_t ldg,
+                            double gamma, double lambda, krr_kernel *out) {
+  if (!out) return KRR_ERROR_INVALID_VALUE;
+  *out = nullptr;
+  if (!ctx || ctx->destroy_pending) return KRR_ERROR_INVALID_VALUE;
+  CHK(build_args(G, n, m, ldg, gamma, lambda));
+  HIPCHK(hipSetDevice(ctx->device));
+  hipStream_t s = ctx->stream;
+  krr_kernel K = nullptr;
+  CHK(kernel_new(ctx, G, n, m, ldg, gamma, lambda, &K));
+  const TileLayout &L = K->L;
+  const int sb = L.nb / 256;
+  krr_status st = KRR_SUCCESS;
+  int32_t *flag = nullptr;
+  do {
     if ((st = dalloc_t(ctx, &flag, 1)) != KRR_SUCCESS) break;
     launch_fill_i32(flag, 1, 0, s);
     {
@@ -397,6 +479,127 @@ krr_status krr_build_kernel(krr_context ctx, const int8_t *G, int64_t n, int64_t
   return KRR_SUCCESS;
 }
 
+static void norm_from_tiles(krr_kernel K) {
+  const TileLayout &L = K->L;
+  double s = 0.0;
+  for (int I = 0; I < L.nt; ++I)
+    for (int J = 0; J <= I; ++J) {
+      const double v = K->tnorm_host[TileLayout::tri(I, J)];
+      s += (I == J ? 1.0 : 2.0) * v * v;
+    }
+  // padding rows contribute identity entries (1 each) to the stored tiles
+  s -= (double)(L.np - L.n);
+  K->norm_a = sqrt(s > 0 ? s : 0.0);
+}
+
+krr_status krr_build_kernel_batched(krr_context ctx, int32_t batch, const int8_t *const *G,
+                                    const int64_t *n, int64_t m, const int64_t *ldg,
+                                    const double *gamma, const double *lambda, krr_kernel *out) {
+  if (!out || batch <= 0) return KRR_ERROR_INVALID_VALUE;
+  for (int b = 0; b < batch; ++b) out[b] = nullptr;
+  if (!ctx || ctx->destroy_pending || !G || !n || !ldg || !gamma || !lambda)
+    return KRR_ERROR_INVALID_VALUE;
+  for (int b = 0; b < batch; ++b) CHK(build_args(G[b], n[b], m, ldg[b], gamma[b], lambda[b]));
+  HIPCHK(hipSetDevice(ctx->device));
+  hipStream_t s = ctx->stream;
+  // largest instances first, so that the small ones fill the tail of each launch
+  std::vector<int> order(batch);
+  for (int b = 0; b < batch; ++b) order[b] = b;
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return n[a] > n[b]; });
+  std::vector<krr_kernel> Ks(batch, nullptr);
+  std::vector<BuildJob> jobs(batch);
+  std::vector<int32_t> hflags(batch, 0);
+  BuildJob *djobs = nullptr;
+  int32_t *flags = nullptr;
+  krr_status st = KRR_SUCCESS;
+  do {
+    int64_t rows = 0, blocks = 0, max_len = 0, max_tiles = 0;
+    for (int q = 0; q < batch && st == KRR_SUCCESS; ++q) {
+      const int b = order[q];
+      st = kernel_new(ctx, G[b], n[b], m, ldg[b], gamma[b], lambda[b], &Ks[b]);
+      if (st != KRR_SUCCESS) break;
+      krr_kernel K = Ks[b];
+      BuildJob &j = jobs[q];
+      j.G = G[b];
+      j.n = n[b];
+      j.np = K->L.np;
+      j.ldg = ldg[b];
+      j.nrm = K->nrm;
+      j.flag = nullptr;  // set below
+      j.etab = K->etab;
+      j.etab_len = K->etab_len;
+      j.gamma = gamma[b];
+      j.lambda = lambda[b];
+      j.D = K->D;
+      j.A = K->A;
+      j.part = K->tnorm_part;
+      j.tnorm = K->tnorm;
+      j.ntiles = K->L.ntiles();
+      j.row0 = rows;
+      j.block0 = blocks;
+      rows += K->L.np;
+      blocks += gram_blocks(K->L);
+      max_len = std::max(max_len, K->etab_len);
+      max_tiles = std::max(max_tiles, K->L.ntiles());
+    }
+    if (st != KRR_SUCCESS) break;
+    if ((st = dalloc_t(ctx, &djobs, batch)) != KRR_SUCCESS) break;
+    if ((st = dalloc_t(ctx, &flags, batch)) != KRR_SUCCESS) break;
+    for (int q = 0; q < batch; ++q) jobs[q].flag = flags + q;
+    if (hipMemcpy(djobs, jobs.data(), sizeof(BuildJob) * batch, hipMemcpyHostToDevice) !=
+        hipSuccess) {
+      st = KRR_ERROR_HIP;
+      break;
+    }
+    launch_fill_i32(flags, batch, 0, s);
+    {
+      Stage t(ctx, KRR_STAGE_ROW_NORMS);
+      launch_row_norms_batched(djobs, batch, rows, m, s);
+    }
+    if (hipMemcpyAsync(hflags.data(), flags, 4 * batch, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) {
+      st = KRR_ERROR_HIP;
+      break;
+    }
+    if ((st = launch_ok()) != KRR_SUCCESS) break;
+    for (int q = 0; q < batch; ++q)
+      if (hflags[q]) st = KRR_ERROR_BAD_GENOTYPE;
+    if (st != KRR_SUCCESS) break;
+    launch_exp_tables_batched(djobs, batch, max_len, s);
+    {
+      Stage t(ctx, KRR_STAGE_GRAM);
+      launch_gram_tiles_batched(djobs, batch, blocks, m, ctx->opts.tile, s);
+    }
+    launch_tile_norms_batched(djobs, batch, max_tiles, ctx->opts.tile, s);
+    if ((st = launch_ok()) != KRR_SUCCESS) break;
+    // the Frobenius norms the precision rule needs, all in one synchronization
+    for (int b = 0; b < batch && st == KRR_SUCCESS; ++b) {
+      krr_kernel K = Ks[b];
+      K->tnorm_host.resize(K->L.ntiles());
+      if (hipMemcpyAsync(K->tnorm_host.data(), K->tnorm, K->L.ntiles() * 8,
+                         hipMemcpyDeviceToHost, s) != hipSuccess)
+        st = KRR_ERROR_HIP;
+    }
+    if (st == KRR_SUCCESS && hipStreamSynchronize(s) != hipSuccess) st = KRR_ERROR_HIP;
+  } while (0);
+  if (djobs) dfree(ctx, djobs, sizeof(BuildJob) * batch);
+  if (flags) dfree(ctx, flags, 4 * batch);
+  if (st != KRR_SUCCESS) {
+    for (krr_kernel K : Ks)
+      if (K) {
+        kernel_free(K);
+        delete K;
+      }
+    return st;
+  }
+  for (int b = 0; b < batch; ++b) {
+    norm_from_tiles(Ks[b]);
+    out[b] = Ks[b];
+    ctx->live++;
+  }
+  return KRR_SUCCESS;
+}
+
 krr_status krr_kernel_release(krr_kernel K) {
   if (!K) return KRR_ERROR_INVALID_VALUE;
   krr_context c = K->ctx;
@@ -415,15 +618,7 @@ static krr_status kernel_norm(krr_kernel K) {
   HIPCHK(hipMemcpyAsync(K->tnorm_host.data(), K->tnorm, L.ntiles() * 8, hipMemcpyDeviceToHost,
                         K->ctx->stream));
   HIPCHK(hipStreamSynchronize(K->ctx->stream));
-  double s = 0.0;
-  for (int I = 0; I < L.nt; ++I)
-    for (int J = 0; J <= I; ++J) {
-      const double v = K->tnorm_host[TileLayout::tri(I, J)];
-      s += (I == J ? 1.0 : 2.0) * v * v;
-    }
-  // padding rows contribute identity entries (1 each) to the stored tiles
-  s -= (double)(L.np - L.n);
-  K->norm_a = sqrt(s > 0 ? s : 0.0);
+  norm_from_tiles(K);
   return KRR_SUCCESS;
 }
 
@@ -490,12 +685,16 @@ static krr_status factor_work_alloc(krr_context c, FactorWork &w, const TileLayo
   return KRR_SUCCESS;
 }
 
-krr_status krr_factor(krr_context ctx, krr_kernel K, const krr_precision_policy *policy,
-                      krr_factorization *out) {
-  if (!out) return KRR_ERROR_INVALID_VALUE;
-  *out = nullptr;
-  if (!ctx || !K || K->ctx != ctx) return KRR_ERROR_INVALID_VALUE;
-  krr_precision_policy p{};
+// Precisions in force for one factorization attempt.
+struct FactorPlan {
+  int mode;
+  int allow16, allow8;
+  bool diag64;
+};
+
+static krr_status resolve_policy(const krr_precision_policy *policy, krr_precision_policy &p,
+                                 FactorPlan &fp) {
+  p = krr_precision_policy{};
   if (policy) {
     p = *policy;
   } else {
@@ -511,21 +710,217 @@ krr_status krr_factor(krr_context ctx, krr_kernel K, const krr_precision_policy 
   if (p.mode == KRR_POLICY_FIXED && p.fixed_prec != KRR_PREC_FP16 && p.fixed_prec != KRR_PREC_FP8)
     return KRR_ERROR_INVALID_VALUE;
   if (p.high_panels < 0) return KRR_ERROR_INVALID_VALUE;
+  fp.allow16 = fp.allow8 = 0;
+  if (p.mode == KRR_POLICY_ADAPTIVE) {
+    fp.allow16 = (p.allowed >> KRR_PREC_FP16) & 1;
+    fp.allow8 = (p.allowed >> KRR_PREC_FP8) & 1;
+  } else if (p.mode == KRR_POLICY_FIXED) {
+    fp.allow16 = p.fixed_prec == KRR_PREC_FP16;
+    fp.allow8 = p.fixed_prec == KRR_PREC_FP8;
+  }
+  fp.mode = p.mode;
+  fp.diag64 = p.diag_fp64 != 0;
+  return KRR_SUCCESS;
+}
+
+// After a breakdown: drop the lowest precision in use, then fall back to
+// FP64 pivots.  False when nothing is left to promote.
+static bool promote(FactorPlan &fp, krr_precision_policy &p) {
+  if (fp.allow8) {
+    fp.allow8 = 0;
+    if (fp.mode == KRR_POLICY_FIXED) {
+      p.fixed_prec = KRR_PREC_FP16;
+      fp.allow16 = 1;
+    }
+  } else if (fp.allow16) {
+    fp.allow16 = 0;
+    fp.mode = KRR_POLICY_FP32;
+  } else if (!fp.diag64) {
+    fp.diag64 = true;
+  } else {
+    return false;
+  }
+  return true;
+}
+
+// Enqueue one factorization attempt of F (its matrix already in F->Lst):
+// clears the breakdown flag, the counters and the precision map, runs the
+// tile Cholesky on s (one stream) or on the context's three streams joined
+// back into s (lookahead), and counts the updates per precision.  Nothing
+// here waits for the device.
+static krr_status factor_enqueue(krr_context ctx, krr_kernel K, krr_factorization F,
+                                 const krr_precision_policy &p, const FactorPlan &fp,
+                                 FactorWork &w, uint8_t *dmap, int64_t mapsz, bool lookahead,
+                                 int g, hipStream_t s) {
+  const TileLayout &L = F->L;
+  launch_fill_i32(w.flag, 1, 0, s);
+  launch_fill_i32((int32_t *)w.counts, 6, 0, s);
+  launch_fill_u8(dmap, mapsz, 255, s);
+  UpdatePolicy up;
+  up.mode = fp.mode;
+  up.allow16 = fp.allow16;
+  up.allow8 = fp.allow8;
+  up.high_panels = p.high_panels;
+  up.fixed_prec = p.fixed_prec;
+  up.thr = p.eps * K->norm_a / L.nt;
+  const bool need16 = fp.allow16 != 0, need8 = fp.allow8 != 0;
+  const int64_t te = L.tile_elems();
+  // Panels are produced in groups of g block columns.  Inside a group
+  // each panel updates the group's later columns right away; everything
+  // to the right of the group gets one update by the whole group (K = g nb).
+  auto slot = [&](int k) -> PanelBuf & { return w.pb[((k / g) & 1) * g + (k % g)]; };
+  auto panels = [&](int G0, int npan, const PanelBuf **ps) {
+    for (int q = 0; q < npan; ++q) ps[q] = &slot(G0 + q);
+  };
+  // POTRF(k); the updates of tile (k, k) by panels q0 .. q0+nq-1 are folded in
+  auto potrf = [&](int k, int q0, int nq, hipStream_t st) {
+    DiagUpdate du{};
+    du.npan = nq;
+    du.pmap = dmap;
+    for (int q = 0; q < nq; ++q) {
+      du.P[q] = slot(q0 + q).P32 + (int64_t)(k - (q0 + q) - 1) * te;
+      du.pmap_at[q] = (int64_t)(q0 + q) * L.ntiles() + TileLayout::tri(k, k);
+    }
+    Stage t(ctx, KRR_STAGE_POTRF, st);
+    launch_potrf_tile(F->Lst + TileLayout::tri(k, k) * te, k, L, fp.diag64, w, du, st);
+  };
+  // TRSM of panel k, tiles k+1+t_lo .. : by substitution (no inverse) or
+  // as a product with inv(L_kk) after forming it
+  auto trsm_subst = [&](int k, int t_lo, int t_hi, hipStream_t st) {
+    Stage t(ctx, KRR_STAGE_TRSM, st);
+    launch_trsm_subst(F->Lst, k, L, fp.diag64, w, slot(k), t_lo, t_hi, st);
+  };
+  auto trsm_gemm = [&](int k, int t_lo, int t_hi, hipStream_t st) {
+    {
+      Stage t(ctx, KRR_STAGE_POTRF, st);
+      launch_tile_inverses(F->Lst, F->Linv, k, k + 1, L, fp.diag64, w, st);
+    }
+    Stage t(ctx, KRR_STAGE_TRSM, st);
+    launch_trsm_gemm(F->Lst, F->Linv + (int64_t)k * te, k, L, w, slot(k), t_lo, t_hi, st);
+  };
+  auto convert = [&](int k, hipStream_t st) {
+    Stage t(ctx, KRR_STAGE_CONVERT, st);
+    launch_convert_panel(F->Lst, k, L, w, slot(k), need16, need8, st);
+  };
+  // panels G0 .. G0+npan-1 onto the tiles of columns jlo .. jhi (which: UPD_*)
+  auto update = [&](int G0, int npan, int jlo, int jhi, int which, hipStream_t st) {
+    if (jlo > jhi || jlo >= L.nt) return;
+    const PanelBuf *ps[KRR_MAX_GROUP];
+    panels(G0, npan, ps);
+    Stage t(ctx, KRR_STAGE_UPDATE, st);
+    launch_update(F->Lst, G0, npan, jlo, jhi, L, up, w, ps, dmap, which, st);
+  };
+  const int NT = L.nt;
+  if (!lookahead) {  // one stream, in program order
+    for (int G0 = 0; G0 < NT; G0 += g) {
+      const int gend = std::min(G0 + g, NT);
+      for (int k = G0; k < gend; ++k) {
+        potrf(k, 0, 0, s);
+        trsm_gemm(k, 0, NT, s);
+        if (k + 1 < NT) convert(k, s);
+        update(k, 1, k + 1, gend - 1, UPD_ALL, s);
+      }
+      update(G0, gend - G0, gend, NT - 1, UPD_ALL, s);
+    }
+  } else {
+    // Three streams.  Main, the critical path: POTRF(k) (with the tile's
+    // last updates folded into its load) and the TRSM of row k+1 alone.  Side: the
+    // rest of each panel's TRSM, its operand copies, its updates of the
+    // group's later columns, and the group's update of the next group's
+    // columns.  Aux: each group's update of every column beyond the next
+    // group.  Events order all updates of any one tile, so the factor
+    // does not depend on the schedule.
+    hipStream_t sm = ctx->fmain, sd = ctx->side, sx = ctx->aux;
+    const int ngroups = (NT + g - 1) / g;
+    std::vector<hipEvent_t> &E = ctx->sched_ev;
+    const size_t need = (size_t)3 * NT + 2 * ngroups + 4;
+    bool ok = true;
+    while (ok && E.size() < need) {
+      hipEvent_t e;
+      ok = hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess;
+      if (ok) E.push_back(e);
+    }
+    hipEvent_t *e_t1 = E.data(), *e_conv = e_t1 + NT, *e_uin = e_conv + NT,
+               *e_aux = e_uin + NT, *e_narrow = e_aux + ngroups, *e_join = e_narrow + ngroups;
+    auto rec = [&](hipEvent_t e, hipStream_t st) {
+      ok = ok && hipEventRecord(e, st) == hipSuccess;
+    };
+    auto wait = [&](hipStream_t st, hipEvent_t e) {
+      ok = ok && hipStreamWaitEvent(st, e, 0) == hipSuccess;
+    };
+    // all three start after the work already on the caller's stream
+    rec(e_join[0], s);
+    wait(sm, e_join[0]);
+    wait(sd, e_join[0]);
+    wait(sx, e_join[0]);
+    for (int G0 = 0; G0 < NT && ok; G0 += g) {
+      const int gi = G0 / g, gend = std::min(G0 + g, NT), nend = std::min(gend + g, NT);
+      for (int k = G0; k < gend; ++k) {
+        // tile (k, k) still lacks panel k-1 (inside the group) or the
+        // whole previous group (at its start)
+        if (k > G0) potrf(k, k - 1, 1, sm);
+        else potrf(k, std::max(G0 - g, 0), G0 > 0 ? g : 0, sm);
+        if (k + 1 >= NT) break;
+        // column k below the diagonal: in-group updates (side), or the
+        // previous group's update of this group's columns (side)
+        if (k > G0) wait(sm, e_uin[k - 1]);
+        else if (gi > 0) wait(sm, e_narrow[gi - 1]);
+        trsm_subst(k, 0, 1, sm);
+        rec(e_t1[k], sm);
+        wait(sd, e_t1[k]);
+        trsm_gemm(k, 1, NT, sd);
+        convert(k, sd);
+        rec(e_conv[k], sd);
+        update(k, 1, k + 1, gend - 1, UPD_OFFDIAG, sd);
+        update(k, 1, k + 2, gend - 1, UPD_DIAG, sd);
+        rec(e_uin[k], sd);
+      }
+      if (gend >= NT) break;
+      const int npan = gend - G0;
+      if (nend < NT) {  // aux: everything right of the next group
+        wait(sx, e_conv[gend - 1]);
+        update(G0, npan, nend, NT - 1, UPD_ALL, sx);
+      }
+      rec(e_aux[gi], sx);
+      // the next group's columns, after the previous group's aux update
+      // reached them; its first diagonal tile on the main stream
+      if (gi > 0) {
+        wait(sm, e_aux[gi - 1]);
+        wait(sd, e_aux[gi - 1]);
+      }
+      update(G0, npan, gend, nend - 1, UPD_OFFDIAG, sd);
+      update(G0, npan, gend + 1, nend - 1, UPD_DIAG, sd);
+      rec(e_narrow[gi], sd);
+    }
+    // join on the caller's stream
+    rec(e_join[1], sd);
+    rec(e_join[2], sx);
+    rec(e_join[3], sm);
+    wait(s, e_join[1]);
+    wait(s, e_join[2]);
+    wait(s, e_join[3]);
+    if (!ok) return KRR_ERROR_HIP;
+  }
+  if (lookahead) {  // the last tile has no panel below it
+    Stage t(ctx, KRR_STAGE_POTRF, s);
+    launch_tile_inverses(F->Lst, F->Linv, NT - 1, NT, L, fp.diag64, w, s);
+  }
+  launch_count_pmap(dmap, mapsz, w.counts, s);
+  return KRR_SUCCESS;
+}
+
+krr_status krr_factor(krr_context ctx, krr_kernel K, const krr_precision_policy *policy,
+                      krr_factorization *out) {
+  if (!out) return KRR_ERROR_INVALID_VALUE;
+  *out = nullptr;
+  if (!ctx || !K || K->ctx != ctx) return KRR_ERROR_INVALID_VALUE;
+  krr_precision_policy p;
+  FactorPlan fp;
+  CHK(resolve_policy(policy, p, fp));
   HIPCHK(hipSetDevice(ctx->device));
   hipStream_t s = ctx->stream;
   const TileLayout &L = K->L;
   CHK(kernel_norm(K));
-
-  int allow16 = 0, allow8 = 0;
-  if (p.mode == KRR_POLICY_ADAPTIVE) {
-    allow16 = (p.allowed >> KRR_PREC_FP16) & 1;
-    allow8 = (p.allowed >> KRR_PREC_FP8) & 1;
-  } else if (p.mode == KRR_POLICY_FIXED) {
-    allow16 = p.fixed_prec == KRR_PREC_FP16;
-    allow8 = p.fixed_prec == KRR_PREC_FP8;
-  }
-  int mode = p.mode;
-  bool diag64 = p.diag_fp64 != 0;
   const char *la_env = getenv("KRR_NO_LOOKAHEAD");
   const bool lookahead = !(la_env && atoi(la_env) != 0);
   const char *g_env = getenv("KRR_GROUP");
@@ -556,165 +951,14 @@ krr_status krr_factor(krr_context ctx, krr_kernel K, const krr_precision_policy 
       launch_expand_tiles(K->D, K->etab, K->etab_len, K->lambda, L, F->Lst, s);
     }
     if ((st = dalloc_t(ctx, &F->Linv, (int64_t)L.nt * L.tile_elems())) != KRR_SUCCESS) break;
-    if ((st = factor_work_alloc(ctx, w, L, allow16 || p.allow_promotion, allow8,
+    if ((st = factor_work_alloc(ctx, w, L, fp.allow16 || p.allow_promotion, fp.allow8,
                                 std::min(2 * g, 2 * KRR_MAX_GROUP))) != KRR_SUCCESS)
       break;
     if ((st = dalloc_t(ctx, &dmap, mapsz)) != KRR_SUCCESS) break;
     for (int attempt = 0;; ++attempt) {
       if (attempt > 0) launch_expand_tiles(K->D, K->etab, K->etab_len, K->lambda, L, F->Lst, s);
-      launch_fill_i32(w.flag, 1, 0, s);
-      launch_fill_i32((int32_t *)w.counts, 6, 0, s);
-      launch_fill_u8(dmap, mapsz, 255, s);
-      UpdatePolicy up;
-      up.mode = mode;
-      up.allow16 = allow16;
-      up.allow8 = allow8;
-      up.high_panels = p.high_panels;
-      up.fixed_prec = p.fixed_prec;
-      up.thr = p.eps * K->norm_a / L.nt;
-      const bool need16 = allow16 != 0, need8 = allow8 != 0;
-      const int64_t te = L.tile_elems();
-      // Panels are produced in groups of g block columns.  Inside a group
-      // each panel updates the group's later columns right away; everything
-      // to the right of the group gets one update by the whole group (K = g nb).
-      auto slot = [&](int k) -> PanelBuf & { return w.pb[((k / g) & 1) * g + (k % g)]; };
-      auto panels = [&](int G0, int npan, const PanelBuf **ps) {
-        for (int q = 0; q < npan; ++q) ps[q] = &slot(G0 + q);
-      };
-      // POTRF(k); the updates of tile (k, k) by panels q0 .. q0+nq-1 are folded in
-      auto potrf = [&](int k, int q0, int nq, hipStream_t st) {
-        DiagUpdate du{};
-        du.npan = nq;
-        du.pmap = dmap;
-        for (int q = 0; q < nq; ++q) {
-          du.P[q] = slot(q0 + q).P32 + (int64_t)(k - (q0 + q) - 1) * te;
-          du.pmap_at[q] = (int64_t)(q0 + q) * L.ntiles() + TileLayout::tri(k, k);
-        }
-        Stage t(ctx, KRR_STAGE_POTRF, st);
-        launch_potrf_tile(F->Lst + TileLayout::tri(k, k) * te, k, L, diag64, w, du, st);
-      };
-      // TRSM of panel k, tiles k+1+t_lo .. : by substitution (no inverse) or
-      // as a product with inv(L_kk) after forming it
-      auto trsm_subst = [&](int k, int t_lo, int t_hi, hipStream_t st) {
-        Stage t(ctx, KRR_STAGE_TRSM, st);
-        launch_trsm_subst(F->Lst, k, L, diag64, w, slot(k), t_lo, t_hi, st);
-      };
-      auto trsm_gemm = [&](int k, int t_lo, int t_hi, hipStream_t st) {
-        {
-          Stage t(ctx, KRR_STAGE_POTRF, st);
-          launch_tile_inverses(F->Lst, F->Linv, k, k + 1, L, diag64, w, st);
-        }
-        Stage t(ctx, KRR_STAGE_TRSM, st);
-        launch_trsm_gemm(F->Lst, F->Linv + (int64_t)k * te, k, L, w, slot(k), t_lo, t_hi, st);
-      };
-      auto convert = [&](int k, hipStream_t st) {
-        Stage t(ctx, KRR_STAGE_CONVERT, st);
-        launch_convert_panel(F->Lst, k, L, w, slot(k), need16, need8, st);
-      };
-      // panels G0 .. G0+npan-1 onto the tiles of columns jlo .. jhi (which: UPD_*)
-      auto update = [&](int G0, int npan, int jlo, int jhi, int which, hipStream_t st) {
-        if (jlo > jhi || jlo >= L.nt) return;
-        const PanelBuf *ps[KRR_MAX_GROUP];
-        panels(G0, npan, ps);
-        Stage t(ctx, KRR_STAGE_UPDATE, st);
-        launch_update(F->Lst, G0, npan, jlo, jhi, L, up, w, ps, dmap, which, st);
-      };
-      const int NT = L.nt;
-      if (!lookahead) {  // one stream, in program order
-        for (int G0 = 0; G0 < NT; G0 += g) {
-          const int gend = std::min(G0 + g, NT);
-          for (int k = G0; k < gend; ++k) {
-            potrf(k, 0, 0, s);
-            trsm_gemm(k, 0, NT, s);
-            if (k + 1 < NT) convert(k, s);
-            update(k, 1, k + 1, gend - 1, UPD_ALL, s);
-          }
-          update(G0, gend - G0, gend, NT - 1, UPD_ALL, s);
-        }
-      } else {
-        // Three streams.  Main, the critical path: POTRF(k) (with the tile's
-        // last updates folded into its load) and the TRSM of row k+1 alone.  Side: the
-        // rest of each panel's TRSM, its operand copies, its updates of the
-        // group's later columns, and the group's update of the next group's
-        // columns.  Aux: each group's update of every column beyond the next
-        // group.  Events order all updates of any one tile, so the factor
-        // does not depend on the schedule.
-        hipStream_t sm = ctx->fmain, sd = ctx->side, sx = ctx->aux;
-        const int ngroups = (NT + g - 1) / g;
-        std::vector<hipEvent_t> &E = ctx->sched_ev;
-        const size_t need = (size_t)3 * NT + 2 * ngroups + 4;
-        bool ok = true;
-        while (ok && E.size() < need) {
-          hipEvent_t e;
-          ok = hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess;
-          if (ok) E.push_back(e);
-        }
-        hipEvent_t *e_t1 = E.data(), *e_conv = e_t1 + NT, *e_uin = e_conv + NT,
-                   *e_aux = e_uin + NT, *e_narrow = e_aux + ngroups, *e_join = e_narrow + ngroups;
-        auto rec = [&](hipEvent_t e, hipStream_t st) {
-          ok = ok && hipEventRecord(e, st) == hipSuccess;
-        };
-        auto wait = [&](hipStream_t st, hipEvent_t e) {
-          ok = ok && hipStreamWaitEvent(st, e, 0) == hipSuccess;
-        };
-        // all three start after the work already on the caller's stream
-        rec(e_join[0], s);
-        wait(sm, e_join[0]);
-        wait(sd, e_join[0]);
-        wait(sx, e_join[0]);
-        for (int G0 = 0; G0 < NT && ok; G0 += g) {
-          const int gi = G0 / g, gend = std::min(G0 + g, NT), nend = std::min(gend + g, NT);
-          for (int k = G0; k < gend; ++k) {
-            // tile (k, k) still lacks panel k-1 (inside the group) or the
-            // whole previous group (at its start)
-            if (k > G0) potrf(k, k - 1, 1, sm);
-            else potrf(k, std::max(G0 - g, 0), G0 > 0 ? g : 0, sm);
-            if (k + 1 >= NT) break;
-            // column k below the diagonal: in-group updates (side), or the
-            // previous group's update of this group's columns (side)
-            if (k > G0) wait(sm, e_uin[k - 1]);
-            else if (gi > 0) wait(sm, e_narrow[gi - 1]);
-            trsm_subst(k, 0, 1, sm);
-            rec(e_t1[k], sm);
-            wait(sd, e_t1[k]);
-            trsm_gemm(k, 1, NT, sd);
-            convert(k, sd);
-            rec(e_conv[k], sd);
-            update(k, 1, k + 1, gend - 1, UPD_OFFDIAG, sd);
-            update(k, 1, k + 2, gend - 1, UPD_DIAG, sd);
-            rec(e_uin[k], sd);
-          }
-          if (gend >= NT) break;
-          const int npan = gend - G0;
-          if (nend < NT) {  // aux: everything right of the next group
-            wait(sx, e_conv[gend - 1]);
-            update(G0, npan, nend, NT - 1, UPD_ALL, sx);
-          }
-          rec(e_aux[gi], sx);
-          // the next group's columns, after the previous group's aux update
-          // reached them; its first diagonal tile on the main stream
-          if (gi > 0) {
-            wait(sm, e_aux[gi - 1]);
-            wait(sd, e_aux[gi - 1]);
-          }
-          update(G0, npan, gend, nend - 1, UPD_OFFDIAG, sd);
-          update(G0, npan, gend + 1, nend - 1, UPD_DIAG, sd);
-          rec(e_narrow[gi], sd);
-        }
-        // join on the caller's stream
-        rec(e_join[1], sd);
-        rec(e_join[2], sx);
-        rec(e_join[3], sm);
-        wait(s, e_join[1]);
-        wait(s, e_join[2]);
-        wait(s, e_join[3]);
-        if (!ok) { st = KRR_ERROR_HIP; break; }
-      }
-      if (lookahead) {  // the last tile has no panel below it
-        Stage t(ctx, KRR_STAGE_POTRF, s);
-        launch_tile_inverses(F->Lst, F->Linv, NT - 1, NT, L, diag64, w, s);
-      }
-      launch_count_pmap(dmap, mapsz, w.counts, s);
+      if ((st = factor_enqueue(ctx, K, F, p, fp, w, dmap, mapsz, lookahead, g, s)) != KRR_SUCCESS)
+        break;
       if ((st = launch_ok()) != KRR_SUCCESS) break;
       int32_t hflag = 0;
       unsigned long long hc[3] = {0, 0, 0};
@@ -731,20 +975,7 @@ krr_status krr_factor(krr_context ctx, krr_kernel K, const krr_precision_policy 
         st = KRR_ERROR_NOT_POSITIVE_DEFINITE;
         break;
       }
-      // promotion: drop the lowest precision in use, then fall back to FP64 pivots
-      if (allow8) {
-        allow8 = 0;
-        if (mode == KRR_POLICY_FIXED) {
-          mode = KRR_POLICY_FIXED;
-          p.fixed_prec = KRR_PREC_FP16;
-          allow16 = 1;
-        }
-      } else if (allow16) {
-        allow16 = 0;
-        mode = KRR_POLICY_FP32;
-      } else if (!diag64) {
-        diag64 = true;
-      } else {
+      if (!promote(fp, p)) {
         st = KRR_ERROR_NOT_POSITIVE_DEFINITE;
         break;
       }
@@ -770,6 +1001,163 @@ krr_status krr_factor(krr_context ctx, krr_kernel K, const krr_precision_policy 
             (long long)F->info.updates[2], F->info.promotions);
   ctx->live++;
   *out = F;
+  return KRR_SUCCESS;
+}
+
+static void factor_free(krr_factorization F) {
+  krr_context c = F->ctx;
+  dfree(c, F->Lst, F->L.elems() * 4);
+  dfree(c, F->Linv, (size_t)F->L.nt * F->L.tile_elems() * 4);
+  delete F;
+}
+
+krr_status krr_factor_batched(krr_context ctx, int32_t batch, const krr_kernel *K,
+                              const krr_precision_policy *policy, krr_factorization *out) {
+  if (!out || batch <= 0) return KRR_ERROR_INVALID_VALUE;
+  for (int b = 0; b < batch; ++b) out[b] = nullptr;
+  if (!ctx || !K) return KRR_ERROR_INVALID_VALUE;
+  for (int b = 0; b < batch; ++b) {
+    if (!K[b] || K[b]->ctx != ctx) return KRR_ERROR_INVALID_VALUE;
+    for (int c = 0; c < b; ++c)
+      if (K[c] == K[b]) return KRR_ERROR_INVALID_VALUE;  // one factorization per kernel
+  }
+  krr_precision_policy p;
+  FactorPlan fp;
+  CHK(resolve_policy(policy, p, fp));
+  HIPCHK(hipSetDevice(ctx->device));
+  hipStream_t s = ctx->stream;
+  {  // Frobenius norms of kernels not built by the batched build, in one synchronization
+    bool any = false;
+    for (int b = 0; b < batch; ++b) {
+      krr_kernel k = K[b];
+      if (k->norm_a >= 0) continue;
+      k->tnorm_host.resize(k->L.ntiles());
+      HIPCHK(hipMemcpyAsync(k->tnorm_host.data(), k->tnorm, k->L.ntiles() * 8,
+                            hipMemcpyDeviceToHost, s));
+      any = true;
+    }
+    if (any) {
+      HIPCHK(hipStreamSynchronize(s));
+      for (int b = 0; b < batch; ++b)
+        if (K[b]->norm_a < 0) norm_from_tiles(K[b]);
+    }
+  }
+  const char *g_env = getenv("KRR_GROUP");
+  const int g = std::max(1, std::min(KRR_MAX_GROUP, g_env ? atoi(g_env) : 4));
+  const int S = std::min<int>(batch, KRR_BATCH_STREAMS);
+  CHK(context_batch_streams(ctx, S));
+  // instances to streams by their Cholesky cost; each stream runs its
+  // instances one after the other (tile Cholesky on one stream, in program
+  // order) and the streams run concurrently
+  std::vector<double> cost(batch);
+  for (int b = 0; b < batch; ++b) cost[b] = (double)K[b]->L.nt * K[b]->L.nt * K[b]->L.nt;
+  std::vector<int> order;
+  const std::vector<int> where = lpt_assign(cost, S, order);
+  std::vector<TileLayout> wl(S);  // workspace layout: the stream's largest instance
+  for (int b = 0; b < batch; ++b)
+    if (K[b]->L.nt > wl[where[b]].nt) wl[where[b]] = K[b]->L;
+  std::vector<FactorWork> W(S);
+  std::vector<std::pair<int32_t *, unsigned long long *>> own(S, {nullptr, nullptr});
+  std::vector<krr_factorization> Fs(batch, nullptr);
+  std::vector<uint8_t *> dmap(batch, nullptr);
+  std::vector<int64_t> mapsz(batch, 0);
+  int32_t *flags = nullptr;
+  unsigned long long *counts = nullptr;
+  std::vector<int32_t> hflag(batch, 0);
+  std::vector<unsigned long long> hc(3 * (size_t)batch, 0);
+  krr_status st = KRR_SUCCESS;
+  do {
+    if ((st = dalloc_t(ctx, &flags, batch)) != KRR_SUCCESS) break;
+    if ((st = dalloc_t(ctx, &counts, 3 * batch)) != KRR_SUCCESS) break;
+    for (int q = 0; q < S && st == KRR_SUCCESS; ++q) {
+      st = factor_work_alloc(ctx, W[q], wl[q], fp.allow16 || p.allow_promotion, fp.allow8,
+                             std::min(2 * g, 2 * KRR_MAX_GROUP));
+      own[q] = {W[q].flag, W[q].counts};
+    }
+    if (st != KRR_SUCCESS) break;
+    if ((st = batch_fence(ctx, s, S, false)) != KRR_SUCCESS) break;
+    for (int b : order) {
+      const TileLayout &L = K[b]->L;
+      hipStream_t sq = ctx->bstreams[where[b]];
+      krr_factorization F = Fs[b] = new krr_factor_s();
+      F->ctx = ctx;
+      F->K = K[b];
+      F->L = L;
+      F->info.nt = L.nt;
+      F->info.tile = L.nb;
+      F->info.norm_a = K[b]->norm_a;
+      F->info.breakdown_col = -1;
+      if (K[b]->A) {  // consume the build's matrix in place
+        F->Lst = K[b]->A;
+        K[b]->A = nullptr;
+      } else {
+        if ((st = dalloc_t(ctx, &F->Lst, L.elems())) != KRR_SUCCESS) break;
+        launch_expand_tiles(K[b]->D, K[b]->etab, K[b]->etab_len, K[b]->lambda, L, F->Lst, sq);
+      }
+      if ((st = dalloc_t(ctx, &F->Linv, (int64_t)L.nt * L.tile_elems())) != KRR_SUCCESS) break;
+      mapsz[b] = (int64_t)L.nt * L.ntiles();
+      if ((st = dalloc_t(ctx, &dmap[b], mapsz[b])) != KRR_SUCCESS) break;
+      FactorWork &w = W[where[b]];
+      w.flag = flags + b;
+      w.counts = counts + 3 * b;
+      if ((st = factor_enqueue(ctx, K[b], F, p, fp, w, dmap[b], mapsz[b], false, g, sq)) !=
+          KRR_SUCCESS)
+        break;
+    }
+    const krr_status sj = batch_fence(ctx, s, S, true);
+    if (st == KRR_SUCCESS) st = sj;
+    if (st == KRR_SUCCESS) st = launch_ok();
+    if (st != KRR_SUCCESS) break;
+    if (hipMemcpyAsync(hflag.data(), flags, 4 * batch, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipMemcpyAsync(hc.data(), counts, 24 * batch, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) {
+      st = KRR_ERROR_HIP;
+      break;
+    }
+    for (int b = 0; b < batch; ++b) {
+      for (int q = 0; q < 3; ++q) Fs[b]->info.updates[q] = (int64_t)hc[3 * b + q];
+      if (Fs[b]->L.nt <= 128 && hflag[b] == 0) {
+        Fs[b]->pmap.resize(mapsz[b]);
+        if (hipMemcpy(Fs[b]->pmap.data(), dmap[b], mapsz[b], hipMemcpyDeviceToHost) != hipSuccess)
+          st = KRR_ERROR_HIP;
+      }
+    }
+  } while (0);
+  (void)hipStreamSynchronize(s);
+  for (int q = 0; q < S; ++q) {
+    W[q].flag = own[q].first;
+    W[q].counts = own[q].second;
+    factor_work_free(ctx, W[q], wl[q]);
+  }
+  for (int b = 0; b < batch; ++b)
+    if (dmap[b]) dfree(ctx, dmap[b], mapsz[b]);
+  if (flags) dfree(ctx, flags, 4 * batch);
+  if (counts) dfree(ctx, counts, 24 * batch);
+  // an instance that broke down is factored again on its own, with promotion
+  for (int b = 0; b < batch && st == KRR_SUCCESS; ++b) {
+    if (hflag[b] == 0) continue;
+    if (!p.allow_promotion) {
+      st = KRR_ERROR_NOT_POSITIVE_DEFINITE;
+      break;
+    }
+    factor_free(Fs[b]);
+    Fs[b] = nullptr;
+    krr_factorization F = nullptr;
+    st = krr_factor(ctx, K[b], policy, &F);
+    if (st == KRR_SUCCESS) {
+      ctx->live--;  // counted once, below, with the others
+      Fs[b] = F;
+    }
+  }
+  if (st != KRR_SUCCESS) {
+    for (krr_factorization F : Fs)
+      if (F) factor_free(F);
+    return st;
+  }
+  for (int b = 0; b < batch; ++b) {
+    out[b] = Fs[b];
+    ctx->live++;
+  }
   return KRR_SUCCESS;
 }
 
@@ -799,14 +1187,8 @@ krr_status krr_factor_precision_map(krr_factorization F, uint8_t *host_dst, int6
   return KRR_SUCCESS;
 }
 
-krr_status krr_solve(krr_context ctx, krr_factorization F, const double *Y, int64_t nrhs, int64_t ldy,
-                     double *X, int64_t ldx, const krr_refine_opts *opts, krr_solve_info *info) {
-  if (!ctx || !F || !Y || !X || nrhs <= 0 || nrhs > 4096) return KRR_ERROR_INVALID_VALUE;
-  krr_kernel K = F->K;
-  if (K->ctx != ctx) return KRR_ERROR_INVALID_VALUE;
-  const TileLayout &L = F->L;
-  if (ldy < L.n || ldx < L.n) return KRR_ERROR_INVALID_VALUE;
-  krr_refine_opts o{};
+static krr_status refine_args(const krr_refine_opts *opts, krr_refine_opts &o) {
+  o = krr_refine_opts{};
   if (opts) {
     o = *opts;
   } else {
@@ -817,62 +1199,109 @@ krr_status krr_solve(krr_context ctx, krr_factorization F, const double *Y, int6
   if (o.method < KRR_REFINE_NONE || o.method > KRR_REFINE_AUTO || o.max_iters < 0 || !(o.tol >= 0))
     return KRR_ERROR_INVALID_VALUE;
   if (o.method == KRR_REFINE_PCG) return KRR_ERROR_NOT_SUPPORTED;
+  return KRR_SUCCESS;
+}
+
+// Device buffers of one solve; right-hand sides row-major np x r.
+struct SolveBufs {
+  double *Yr = nullptr, *Xr = nullptr, *Rr = nullptr, *cn = nullptr;
+  float *Bf = nullptr, *Zf = nullptr, *Xf = nullptr;
+};
+
+static krr_status solve_alloc(Scoped &sc, int64_t cnt, int r, SolveBufs &b) {
+  CHK(sc.alloc(&b.Yr, cnt));
+  CHK(sc.alloc(&b.Xr, cnt));
+  CHK(sc.alloc(&b.Rr, cnt));
+  CHK(sc.alloc(&b.cn, 2 * r));
+  CHK(sc.alloc(&b.Bf, cnt));
+  CHK(sc.alloc(&b.Zf, cnt));
+  CHK(sc.alloc(&b.Xf, cnt));
+  return KRR_SUCCESS;
+}
+
+// X += L^-T L^-1 src with FP32 sweeps (src: FP64, row-major np x r).
+static void solve_sweeps(krr_context ctx, krr_factorization F, int r, SolveBufs &b,
+                         const double *src, hipStream_t s) {
+  const TileLayout &L = F->L;
+  const int64_t cnt = L.np * r;
+  launch_f64_to_f32(src, cnt, b.Bf, s);
+  {
+    Stage t(ctx, KRR_STAGE_FWD, s);
+    launch_fwd_sweep(F->Lst, F->Linv, L, r, b.Bf, b.Zf, s);
+  }
+  {
+    Stage t(ctx, KRR_STAGE_BWD, s);
+    launch_bwd_sweep(F->Lst, F->Linv, L, r, b.Zf, b.Xf, s);
+  }
+  launch_axpy_f32_to_f64(b.Xf, cnt, 1.0, b.Xr, s);
+}
+
+// R = Y - (K + lambda I) X in FP64, then the squared column norms of R and X
+// into cn[0 .. r) and cn[r .. 2r).
+static void residual_norms(krr_context ctx, krr_factorization F, int r, SolveBufs &b,
+                           hipStream_t s) {
+  krr_kernel K = F->K;
+  const TileLayout &L = F->L;
+  {
+    Stage t(ctx, KRR_STAGE_RESIDUAL, s);
+    launch_residual(K->D, K->etab, K->etab_len, K->lambda, L, r, b.Xr, b.Yr, b.Rr, s);
+  }
+  launch_col_norms(b.Rr, L.np, r, b.cn, s);
+  launch_col_norms(b.Xr, L.np, r, b.cn + r, s);
+}
+
+// The refinement's stop quantities from the squared norms: the forward-error
+// bound max_j ||r_j|| / (lambda ||x_j||) and the backward error.
+static void refine_bounds(const double *hn, const double *yn, int r, double lambda, double norm_a,
+                          double &bound, double &berr) {
+  const double lam = lambda > 0 ? lambda : 1e-300;
+  bound = 0;
+  berr = 0;
+  for (int c = 0; c < r; ++c) {
+    const double rn = sqrt(hn[c]), xn = sqrt(hn[r + c]), ynn = sqrt(yn[c]);
+    const double b = xn > 0 ? rn / (lam * xn) : (rn > 0 ? INFINITY : 0.0);
+    bound = std::max(bound, b);
+    const double den = norm_a * xn + ynn;
+    berr = std::max(berr, den > 0 ? rn / den : 0.0);
+  }
+}
+
+krr_status krr_solve(krr_context ctx, krr_factorization F, const double *Y, int64_t nrhs, int64_t ldy,
+                     double *X, int64_t ldx, const krr_refine_opts *opts, krr_solve_info *info) {
+  if (!ctx || !F || !Y || !X || nrhs <= 0 || nrhs > 4096) return KRR_ERROR_INVALID_VALUE;
+  krr_kernel K = F->K;
+  if (K->ctx != ctx) return KRR_ERROR_INVALID_VALUE;
+  const TileLayout &L = F->L;
+  if (ldy < L.n || ldx < L.n) return KRR_ERROR_INVALID_VALUE;
+  krr_refine_opts o;
+  CHK(refine_args(opts, o));
   HIPCHK(hipSetDevice(ctx->device));
   hipStream_t s = ctx->stream;
   const int r = (int)nrhs;
   const int64_t cnt = L.np * r;
   Scoped sc(ctx);
-  double *Yr, *Xr, *Rr, *cn;
-  float *Bf, *Zf, *Xf;
-  CHK(sc.alloc(&Yr, cnt));
-  CHK(sc.alloc(&Xr, cnt));
-  CHK(sc.alloc(&Rr, cnt));
-  CHK(sc.alloc(&cn, 2 * r));
-  CHK(sc.alloc(&Bf, cnt));
-  CHK(sc.alloc(&Zf, cnt));
-  CHK(sc.alloc(&Xf, cnt));
-  launch_colmajor_to_rows(Y, L.n, ldy, r, L.np, Yr, s);
-  launch_fill_f64(Xr, cnt, 0.0, s);
-  // unrefined solve in FP32
-  launch_f64_to_f32(Yr, cnt, Bf, s);
-  {
-    Stage t(ctx, KRR_STAGE_FWD);
-    launch_fwd_sweep(F->Lst, F->Linv, L, r, Bf, Zf, s);
-  }
-  {
-    Stage t(ctx, KRR_STAGE_BWD);
-    launch_bwd_sweep(F->Lst, F->Linv, L, r, Zf, Xf, s);
-  }
-  launch_axpy_f32_to_f64(Xf, cnt, 1.0, Xr, s);
+  SolveBufs b;
+  CHK(solve_alloc(sc, cnt, r, b));
+  launch_colmajor_to_rows(Y, L.n, ldy, r, L.np, b.Yr, s);
+  launch_fill_f64(b.Xr, cnt, 0.0, s);
+  solve_sweeps(ctx, F, r, b, b.Yr, s);  // the unrefined FP32 solve
   CHK(launch_ok());
   krr_solve_info inf{};
   inf.first_bound = -1;
   krr_status st = KRR_SUCCESS;
   if (o.method != KRR_REFINE_NONE) {
     std::vector<double> hn(2 * r), yn(r);
-    launch_col_norms(Yr, L.np, r, cn, s);
-    HIPCHK(hipMemcpyAsync(yn.data(), cn, r * 8, hipMemcpyDeviceToHost, s));
+    launch_col_norms(b.Yr, L.np, r, b.cn, s);
+    HIPCHK(hipMemcpyAsync(yn.data(), b.cn, r * 8, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
-    const double lam = K->lambda > 0 ? K->lambda : 1e-300;
     int it = 0;
     for (;; ++it) {
-      {
-        Stage t(ctx, KRR_STAGE_RESIDUAL);
-        launch_residual(K->D, K->etab, K->etab_len, K->lambda, L, r, Xr, Yr, Rr, s);
-      }
-      launch_col_norms(Rr, L.np, r, cn, s);
-      launch_col_norms(Xr, L.np, r, cn + r, s);
+      residual_norms(ctx, F, r, b, s);
       CHK(launch_ok());
-      HIPCHK(hipMemcpyAsync(hn.data(), cn, 2 * r * 8, hipMemcpyDeviceToHost, s));
+      HIPCHK(hipMemcpyAsync(hn.data(), b.cn, 2 * r * 8, hipMemcpyDeviceToHost, s));
       HIPCHK(hipStreamSynchronize(s));
-      double bound = 0, berr = 0;
-      for (int c = 0; c < r; ++c) {
-        const double rn = sqrt(hn[c]), xn = sqrt(hn[r + c]), ynn = sqrt(yn[c]);
-        const double b = xn > 0 ? rn / (lam * xn) : (rn > 0 ? INFINITY : 0.0);
-        bound = std::max(bound, b);
-        const double den = K->norm_a * xn + ynn;
-        berr = std::max(berr, den > 0 ? rn / den : 0.0);
-      }
+      double bound, berr;
+      refine_bounds(hn.data(), yn.data(), r, K->lambda, K->norm_a, bound, berr);
       if (it == 0) inf.first_bound = bound;
       inf.fwd_err_bound = bound;
       inf.backward_err = berr;
@@ -881,27 +1310,107 @@ krr_status krr_solve(krr_context ctx, krr_factorization F, const double *Y, int6
         break;
       }
       if (it >= o.max_iters) break;
-      launch_f64_to_f32(Rr, cnt, Bf, s);
-      {
-        Stage t(ctx, KRR_STAGE_FWD);
-        launch_fwd_sweep(F->Lst, F->Linv, L, r, Bf, Zf, s);
-      }
-      {
-        Stage t(ctx, KRR_STAGE_BWD);
-        launch_bwd_sweep(F->Lst, F->Linv, L, r, Zf, Xf, s);
-      }
-      launch_axpy_f32_to_f64(Xf, cnt, 1.0, Xr, s);
+      solve_sweeps(ctx, F, r, b, b.Rr, s);
     }
     inf.iters = it;
     if (!inf.converged) st = KRR_ERROR_NOT_CONVERGED;
   }
-  launch_rows_to_colmajor(Xr, L.n, r, X, ldx, s);
+  launch_rows_to_colmajor(b.Xr, L.n, r, X, ldx, s);
   CHK(launch_ok());
   HIPCHK(hipStreamSynchronize(s));
   if (info) *info = inf;
   if (ctx->opts.verbose)
     fprintf(stderr, "krr_solve: iters=%d bound=%.3e first=%.3e\n", inf.iters, inf.fwd_err_bound,
             inf.first_bound);
+  return st;
+}
+
+krr_status krr_solve_batched(krr_context ctx, int32_t batch, const krr_factorization *F,
+                             const double *const *Y, int64_t nrhs, const int64_t *ldy,
+                             double *const *X, const int64_t *ldx, const krr_refine_opts *opts,
+                             krr_solve_info *info) {
+  if (!ctx || batch <= 0 || !F || !Y || !X || !ldy || !ldx || nrhs <= 0 || nrhs > 4096)
+    return KRR_ERROR_INVALID_VALUE;
+  for (int b = 0; b < batch; ++b) {
+    if (!F[b] || !Y[b] || !X[b] || F[b]->K->ctx != ctx) return KRR_ERROR_INVALID_VALUE;
+    if (ldy[b] < F[b]->L.n || ldx[b] < F[b]->L.n) return KRR_ERROR_INVALID_VALUE;
+  }
+  krr_refine_opts o;
+  CHK(refine_args(opts, o));
+  HIPCHK(hipSetDevice(ctx->device));
+  hipStream_t s = ctx->stream;
+  const int r = (int)nrhs;
+  const int S = std::min<int>(batch, KRR_BATCH_STREAMS);
+  CHK(context_batch_streams(ctx, S));
+  std::vector<double> cost(batch);
+  for (int b = 0; b < batch; ++b) cost[b] = (double)F[b]->L.np * F[b]->L.np;
+  std::vector<int> order;
+  const std::vector<int> where = lpt_assign(cost, S, order);
+  auto stream_of = [&](int b) { return ctx->bstreams[where[b]]; };
+  Scoped sc(ctx);
+  std::vector<SolveBufs> B(batch);
+  for (int b = 0; b < batch; ++b) CHK(solve_alloc(sc, F[b]->L.np * r, r, B[b]));
+  // every instance's refinement runs on its stream; the host waits once per
+  // iteration for all of them
+  std::vector<krr_solve_info> inf(batch);
+  std::vector<double> hn(2 * (size_t)r * batch), yn((size_t)r * batch);
+  CHK(batch_fence(ctx, s, S, false));
+  for (int b : order) {
+    const TileLayout &L = F[b]->L;
+    hipStream_t sq = stream_of(b);
+    launch_colmajor_to_rows(Y[b], L.n, ldy[b], r, L.np, B[b].Yr, sq);
+    launch_fill_f64(B[b].Xr, L.np * r, 0.0, sq);
+    solve_sweeps(ctx, F[b], r, B[b], B[b].Yr, sq);
+    inf[b].first_bound = -1;
+    if (o.method != KRR_REFINE_NONE) {
+      launch_col_norms(B[b].Yr, L.np, r, B[b].cn, sq);
+      HIPCHK(hipMemcpyAsync(yn.data() + (size_t)r * b, B[b].cn, r * 8, hipMemcpyDeviceToHost, sq));
+    }
+  }
+  CHK(launch_ok());
+  std::vector<char> active(batch, o.method != KRR_REFINE_NONE);
+  for (int it = 0;; ++it) {
+    bool any = false;
+    for (int b : order) {
+      if (!active[b]) continue;
+      any = true;
+      hipStream_t sq = stream_of(b);
+      residual_norms(ctx, F[b], r, B[b], sq);
+      HIPCHK(hipMemcpyAsync(hn.data() + 2 * (size_t)r * b, B[b].cn, 2 * r * 8,
+                            hipMemcpyDeviceToHost, sq));
+    }
+    if (!any) break;
+    CHK(launch_ok());
+    for (int q = 0; q < S; ++q) HIPCHK(hipStreamSynchronize(ctx->bstreams[q]));
+    for (int b : order) {
+      if (!active[b]) continue;
+      double bound, berr;
+      refine_bounds(hn.data() + 2 * (size_t)r * b, yn.data() + (size_t)r * b, r, F[b]->K->lambda,
+                    F[b]->K->norm_a, bound, berr);
+      if (it == 0) inf[b].first_bound = bound;
+      inf[b].fwd_err_bound = bound;
+      inf[b].backward_err = berr;
+      inf[b].iters = it;
+      if (bound <= o.tol) {
+        inf[b].converged = 1;
+        active[b] = 0;
+      } else if (it >= o.max_iters) {
+        active[b] = 0;
+      } else {
+        solve_sweeps(ctx, F[b], r, B[b], B[b].Rr, stream_of(b));
+      }
+    }
+  }
+  for (int b : order)
+    launch_rows_to_colmajor(B[b].Xr, F[b]->L.n, r, X[b], ldx[b], stream_of(b));
+  CHK(launch_ok());
+  CHK(batch_fence(ctx, s, S, true));
+  HIPCHK(hipStreamSynchronize(s));
+  krr_status st = KRR_SUCCESS;
+  for (int b = 0; b < batch; ++b) {
+    if (o.method != KRR_REFINE_NONE && !inf[b].converged) st = KRR_ERROR_NOT_CONVERGED;
+    if (info) info[b] = inf[b];
+  }
   return st;
 }
 

@@ -37,11 +37,9 @@ void launch_exp_table(double *tab, int64_t len, double gamma, hipStream_t s) {
 // Row norms n_i = sum_k g_ik^2 (one workgroup per row, 16-byte loads, dot4),
 // and the genotype check: any byte outside {0, 1, 2} sets *flag.  Rows
 // n .. rows_padded-1 are padding and get n_i = 0.
-__global__ __launch_bounds__(256) void k_row_norms(const int8_t *__restrict__ G, int64_t n,
-                                                   int64_t m, int64_t ldg, int32_t *nrm,
-                                                   int32_t *flag) {
+KRR_DEV void row_norm(const int8_t *__restrict__ G, int64_t n, int64_t m, int64_t ldg,
+                      int32_t *nrm, int32_t *flag, int64_t row) {
   __shared__ int sh[4];
-  const int64_t row = blockIdx.x;
   if (row >= n) {
     if (threadIdx.x == 0) nrm[row] = 0;
     return;
@@ -70,6 +68,12 @@ __global__ __launch_bounds__(256) void k_row_norms(const int8_t *__restrict__ G,
   if (threadIdx.x == 0) nrm[row] = sh[0] + sh[1] + sh[2] + sh[3];
 }
 
+__global__ __launch_bounds__(256) void k_row_norms(const int8_t *__restrict__ G, int64_t n,
+                                                   int64_t m, int64_t ldg, int32_t *nrm,
+                                                   int32_t *flag) {
+  row_norm(G, n, m, ldg, nrm, flag, blockIdx.x);
+}
+
 void launch_row_norms(const int8_t *G, int64_t n, int64_t rows_padded, int64_t m, int64_t ldg,
                       int32_t *nrm, int32_t *flag, hipStream_t s) {
   hipLaunchKernelGGL(k_row_norms, dim3((unsigned)rows_padded), dim3(256), 0, s, G, n, m, ldg,
@@ -82,13 +86,10 @@ void launch_row_norms(const int8_t *G, int64_t n, int64_t rows_padded, int64_t m
 // LDS, FP64 product rounded to FP32), 1 + lambda on the diagonal, identity
 // on padding; plus the sub-block's FP64 sum of squares for the tile norms.
 template <class S>
-__global__ __launch_bounds__(S::THREADS) void k_gram_tiles(const int8_t *__restrict__ G, int64_t n,
-                                                    int64_t m, int64_t ldg,
-                                                    const int32_t *__restrict__ nrm,
-                                                    const double *__restrict__ etab,
-                                                    int64_t etab_len, double lambda, int nb,
-                                                    int nt, int SB, int32_t *__restrict__ D,
-                                                    float *__restrict__ A, double *part) {
+KRR_DEV void gram_block(const int8_t *__restrict__ G, int64_t n, int64_t m, int64_t ldg,
+                        const int32_t *__restrict__ nrm, const double *__restrict__ etab,
+                        int64_t etab_len, double lambda, int nb, int SB, int32_t *__restrict__ D,
+                        float *__restrict__ A, double *part, int64_t bid) {
   constexpr int BM = S::kBM, BN = S::kBN, NW = S::THREADS / 64;
   extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
   __shared__ double shd[NW];
@@ -100,7 +101,6 @@ __global__ __launch_bounds__(S::THREADS) void k_gram_tiles(const int8_t *__restr
     for (int q = threadIdx.x; q < EXP_LO; q += S::THREADS) elo[q] = etab[min((int64_t)q, dmax)];
     for (int q = threadIdx.x; q < nhi; q += S::THREADS) ehi[q] = etab[(int64_t)q * EXP_LO];
   }
-  const int64_t bid = xcd_remap(blockIdx.x, gridDim.x);
   const int nsub = SB * SB;
   const int sub = (int)(bid % nsub);
   const int64_t t = bid / nsub;  // tile in the order of the launch
@@ -152,6 +152,42 @@ __global__ __launch_bounds__(S::THREADS) void k_gram_tiles(const int8_t *__restr
   if (threadIdx.x == 0) part[tt * nsub + sub] = ss;
 }
 
+template <class S>
+__global__ __launch_bounds__(S::THREADS) void k_gram_tiles(const int8_t *__restrict__ G, int64_t n,
+                                                    int64_t m, int64_t ldg,
+                                                    const int32_t *__restrict__ nrm,
+                                                    const double *__restrict__ etab,
+                                                    int64_t etab_len, double lambda, int nb,
+                                                    int SB, int32_t *__restrict__ D,
+                                                    float *__restrict__ A, double *part) {
+  gram_block<S>(G, n, m, ldg, nrm, etab, etab_len, lambda, nb, SB, D, A, part,
+                xcd_remap(blockIdx.x, gridDim.x));
+}
+
+// Instance of a batch that owns workgroup `bid`: the last job whose first
+// workgroup (field F of BuildJob) is <= bid.
+template <int64_t BuildJob::*F>
+KRR_DEV int find_job(const BuildJob *jobs, int njobs, int64_t bid) {
+  int lo = 0, hi = njobs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (jobs[mid].*F <= bid) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// All instances of a batch in one launch: each workgroup finds its instance
+// and runs the same block as the single-instance kernel.
+template <class S>
+__global__ __launch_bounds__(S::THREADS) void k_gram_tiles_batched(const BuildJob *__restrict__ jobs,
+                                                            int njobs, int64_t m, int nb, int SB) {
+  const int64_t bid = xcd_remap(blockIdx.x, gridDim.x);
+  const BuildJob &j = jobs[find_job<&BuildJob::block0>(jobs, njobs, bid)];
+  gram_block<S>(j.G, j.n, m, j.ldg, j.nrm, j.etab, j.etab_len, j.lambda, nb, SB, j.D, j.A, j.part,
+                bid - j.block0);
+}
+
 typedef StreamShape<256, 256, 2, 4, 4> GramShape;
 
 void launch_gram_tiles(const int8_t *G, int64_t m, int64_t ldg, const int32_t *nrm,
@@ -167,7 +203,64 @@ void launch_gram_tiles(const int8_t *G, int64_t m, int64_t ldg, const int32_t *n
   }
   hipLaunchKernelGGL((k_gram_tiles<GramShape>), dim3((unsigned)blocks), dim3(GramShape::THREADS),
                      GramShape::LDS_BYTES, s, G, L.n, m,
-                     ldg, nrm, etab, etab_len, lambda, L.nb, L.nt, SB, D, A, tnorm_part);
+                     ldg, nrm, etab, etab_len, lambda, L.nb, SB, D, A, tnorm_part);
+}
+
+int64_t gram_blocks(const TileLayout &L) {
+  const int SB = L.nb / GramShape::kBM;
+  return L.ntiles() * SB * SB;
+}
+
+int gram_parts(int nb) { return (nb / GramShape::kBM) * (nb / GramShape::kBM); }
+
+void launch_gram_tiles_batched(const BuildJob *jobs, int njobs, int64_t blocks, int64_t m, int nb,
+                               hipStream_t s) {
+  static bool attr = false;
+  if (!attr) {
+    hipFuncSetAttribute((const void *)k_gram_tiles_batched<GramShape>,
+                        hipFuncAttributeMaxDynamicSharedMemorySize, GramShape::LDS_BYTES);
+    attr = true;
+  }
+  hipLaunchKernelGGL((k_gram_tiles_batched<GramShape>), dim3((unsigned)blocks),
+                     dim3(GramShape::THREADS), GramShape::LDS_BYTES, s, jobs, njobs, m, nb,
+                     nb / GramShape::kBM);
+}
+
+__global__ __launch_bounds__(256) void k_row_norms_batched(const BuildJob *__restrict__ jobs,
+                                                           int njobs, int64_t m) {
+  const BuildJob &j = jobs[find_job<&BuildJob::row0>(jobs, njobs, blockIdx.x)];
+  row_norm(j.G, j.n, m, j.ldg, j.nrm, j.flag, (int64_t)blockIdx.x - j.row0);
+}
+
+void launch_row_norms_batched(const BuildJob *jobs, int njobs, int64_t rows, int64_t m,
+                              hipStream_t s) {
+  hipLaunchKernelGGL(k_row_norms_batched, dim3((unsigned)rows), dim3(256), 0, s, jobs, njobs, m);
+}
+
+__global__ void k_exp_tables_batched(const BuildJob *__restrict__ jobs) {
+  const BuildJob &j = jobs[blockIdx.y];
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < j.etab_len) j.etab[i] = exp(-j.gamma * (double)i);
+}
+
+void launch_exp_tables_batched(const BuildJob *jobs, int njobs, int64_t max_len, hipStream_t s) {
+  hipLaunchKernelGGL(k_exp_tables_batched, dim3((unsigned)((max_len + 255) / 256), njobs),
+                     dim3(256), 0, s, jobs);
+}
+
+__global__ void k_tile_norms_batched(const BuildJob *__restrict__ jobs, int parts) {
+  const BuildJob &j = jobs[blockIdx.y];
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= j.ntiles) return;
+  double s = 0.0;
+  for (int q = 0; q < parts; ++q) s += j.part[t * parts + q];
+  j.tnorm[t] = sqrt(s);
+}
+
+void launch_tile_norms_batched(const BuildJob *jobs, int njobs, int64_t max_ntiles, int nb,
+                               hipStream_t s) {
+  hipLaunchKernelGGL(k_tile_norms_batched, dim3((unsigned)((max_ntiles + 255) / 256), njobs),
+                     dim3(256), 0, s, jobs, gram_parts(nb));
 }
 
 // Tile Frobenius norms from the per-sub-block partial sums, in fixed order.

@@ -20,6 +20,36 @@ struct TileLayout {
 };
 
 // ---- build.hip ----
+// One instance of a batched Build: its inputs, outputs and the first
+// workgroup of each batched launch that belongs to it.
+struct BuildJob {
+  const int8_t *G;
+  int64_t n, np, ldg;
+  int32_t *nrm;
+  int32_t *flag;        // genotype check of this instance
+  double *etab;         // exp(-gamma d), d = 0 .. etab_len-1
+  int64_t etab_len;
+  double gamma, lambda;
+  int32_t *D;
+  float *A;
+  double *part;         // per-sub-block sums of squares
+  double *tnorm;        // per-tile Frobenius norms
+  int64_t ntiles;
+  int64_t row0;         // first row-norm workgroup
+  int64_t block0;       // first Gram workgroup
+};
+// Batched Build launches over jobs[0 .. njobs-1] (device memory); rows and
+// blocks are the totals over the batch (last job's row0 + np, block0 + its
+// blocks).
+void launch_row_norms_batched(const BuildJob *jobs, int njobs, int64_t rows, int64_t m,
+                              hipStream_t s);
+void launch_exp_tables_batched(const BuildJob *jobs, int njobs, int64_t max_len, hipStream_t s);
+int64_t gram_blocks(const TileLayout &L);  // Gram workgroups of one instance
+void launch_gram_tiles_batched(const BuildJob *jobs, int njobs, int64_t blocks, int64_t m, int nb,
+                               hipStream_t s);
+int gram_parts(int nb);  // partial sums per tile
+void launch_tile_norms_batched(const BuildJob *jobs, int njobs, int64_t max_ntiles, int nb,
+                               hipStream_t s);
 void launch_exp_table(double *tab, int64_t len, double gamma, hipStream_t s);
 void launch_row_norms(const int8_t *G, int64_t n, int64_t rows_padded, int64_t m, int64_t ldg,
                       int32_t *nrm, int32_t *flag, hipStream_t s);

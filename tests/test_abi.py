@@ -108,3 +108,17 @@ def test_product_path_does_not_import_oracle():
                 txt = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in txt and "from oracle" not in txt, f
                 assert "krr_oracle" not in txt, f
+
+
+def test_batched_arguments_rejected_on_host(lib):
+    P = ctypes.c_void_p
+    outs = (P * 2)()
+    n = (ctypes.c_int64 * 2)(10, 10)
+    assert lib.krr_build_kernel_batched(None, 2, None, n, 16, n, None, None, outs) == \
+        krr.KRR_ERROR_INVALID_VALUE
+    assert lib.krr_build_kernel_batched(None, 0, None, None, 16, None, None, None, outs) == \
+        krr.KRR_ERROR_INVALID_VALUE
+    assert lib.krr_factor_batched(None, 2, None, None, outs) == krr.KRR_ERROR_INVALID_VALUE
+    assert outs[0] is None and outs[1] is None
+    assert lib.krr_solve_batched(None, 2, None, None, 1, None, None, None, None, None) == \
+        krr.KRR_ERROR_INVALID_VALUE

@@ -294,3 +294,119 @@ def test_workspace_limit(ctx):
     with pytest.raises(krr.KRRError) as e:
         krr.krr_build_kernel(c2, _dev(G), 0.01, 0.1)
     assert e.value.status == krr.KRR_ERROR_OUT_OF_MEMORY
+
+
+# --- the benchmark's full size, in its launch configuration ---------------------------------
+
+def test_full_size_single_workload_sampled():
+    """n = 32768, m = 65536, r = 16, tile 512, adaptive policy with lookahead and the
+    benchmark's refinement target.  The oracle cannot hold the 32768^2 matrix, so it
+    checks sampled blocks of distances (by definition, bit for bit) and of K (one FP32
+    ulp), and the FP64 residual r = Y - (K + lambda I) X on sampled rows: each column's
+    sampled residual norm must stay below lambda * tol * ||x_j||, the stop rule whose
+    PSD bound certifies the 1e-5 relative error."""
+    w = synth.WORKLOADS["single"]
+    n, m = w.n, w.m
+    G = w.genotypes()
+    Y = w.phenotypes(G)
+    assert G.shape == (32768, 65536) and Y.shape[1] == 16
+    c = krr.krr_create(0, tile=512)
+    Gd = _dev(G)
+    K = krr.krr_build_kernel(c, Gd, w.gamma, w.lam)
+    blocks = [(0, 0), (n - 64, 0), (n - 64, n - 64), (16484, 7003), (511, 31000), (20000, 20000)]
+    for i0, j0 in blocks:
+        d = krr.krr_kernel_copy_distances(K, i0, j0, 64, 64).cpu().numpy()
+        ref = oracle.sqdist(G[i0:i0 + 64], G[j0:j0 + 64])
+        assert np.array_equal(d.astype(np.int64), ref), (i0, j0)
+        a = krr.krr_kernel_copy_matrix(K, i0, j0, 64, 64).cpu().numpy().astype(np.float64)
+        kref = oracle.gaussian(ref, w.gamma)
+        gi = np.arange(i0, i0 + 64)[:, None]
+        gj = np.arange(j0, j0 + 64)[None, :]
+        kref = np.where(gi == gj, 1.0 + w.lam, kref)
+        ulp = np.spacing(kref.astype(np.float32)).astype(np.float64)
+        assert np.all(np.abs(a - kref) <= ulp), (i0, j0)
+    F = krr.krr_factor(c, K, krr.Policy())
+    tol = 9.9e-6
+    X, info, st = krr.krr_solve(c, F, _dev(Y), krr.Refine(method=krr.KRR_REFINE_IR,
+                                                          max_iters=30, tol=tol))
+    assert info.converged == 1 and info.fwd_err_bound <= 1e-5
+    fi = krr.krr_factor_get_info(F)
+    assert fi.updates[2] > 0  # the adaptive rule did use FP8
+    Xh = X.cpu().numpy()
+    rng = np.random.default_rng(7)
+    rows = np.sort(np.concatenate([[0, n - 1], rng.choice(n, 30, replace=False)]))
+    R = oracle.residual_rows(G, w.gamma, w.lam, Xh, Y, rows)
+    xnorm = np.linalg.norm(Xh, axis=0)
+    assert np.all(np.linalg.norm(R, axis=0) <= w.lam * tol * xnorm)
+    F.release()
+    K.release()
+    c.close()
+
+
+# --- batches of independent instances -------------------------------------------------------
+
+def _batch_instances(seed=2024):
+    """Five instances of uneven n on one genotype panel (rows of one stream), with the
+    (gamma, lambda) grid of a cross-validation sweep."""
+    ns = [300, 1024, 700, 1536, 257]
+    m = 2000
+    Gall = _gen(sum(ns), m, seed=seed)
+    offs = np.cumsum([0] + ns)
+    Gs = [np.ascontiguousarray(Gall[offs[b]:offs[b + 1]]) for b in range(len(ns))]
+    gammas = [g / m for g in (0.5, 1.0, 2.0, 0.5, 1.0)]
+    lams = [1e-2, 1e-1, 1.0, 1e-1, 1e-2]
+    Ys = [synth.phenotypes(G, 3, n_pairs=10, n_add=5, seed=11 + b, h2=0.5)
+          for b, G in enumerate(Gs)]
+    return Gs, gammas, lams, Ys
+
+
+def test_batched_build_bit_exact_and_matches_single():
+    Gs, gammas, lams, _ = _batch_instances()
+    c = krr.krr_create(0, tile=256)
+    Ks = krr.krr_build_kernel_batched(c, [_dev(G) for G in Gs], gammas, lams)
+    for G, g, lam, K in zip(Gs, gammas, lams, Ks):
+        n = len(G)
+        d = krr.krr_kernel_copy_distances(K, 0, 0, n, n).cpu().numpy().astype(np.int64)
+        ref = oracle.sqdist(G)
+        assert np.array_equal(d, ref)
+        a = krr.krr_kernel_copy_matrix(K, 0, 0, n, n).cpu().numpy().astype(np.float64)
+        kref = oracle.gaussian(ref, g) + lam * np.eye(n)
+        ulp = np.spacing(kref.astype(np.float32)).astype(np.float64)
+        assert np.all(np.abs(a - kref) <= ulp)
+        # the single-instance build gives the same bytes
+        K1 = krr.krr_build_kernel(c, _dev(G), g, lam)
+        a1 = krr.krr_kernel_copy_matrix(K1, 0, 0, n, n)
+        assert torch.equal(a1.cpu(), torch.from_numpy(a.astype(np.float32)))
+        nt = (n + 255) // 256
+        assert np.array_equal(krr.krr_kernel_tile_norms(K, nt), krr.krr_kernel_tile_norms(K1, nt))
+        # ||K + lambda I||_F of the stored FP32 matrix, which the precision rule uses
+        np.testing.assert_allclose(krr.krr_factor_get_info(krr.krr_factor(c, K)).norm_a,
+                                   np.linalg.norm(a), rtol=1e-12)
+
+
+@pytest.mark.parametrize("policy", ["adaptive", "plain"])
+def test_batched_fit_parity(policy):
+    Gs, gammas, lams, Ys = _batch_instances()
+    pol = krr.Policy() if policy == "adaptive" else krr.plain_fp32_policy()
+    c = krr.krr_create(0, tile=256)
+    Ks = krr.krr_build_kernel_batched(c, [_dev(G) for G in Gs], gammas, lams)
+    Fs = krr.krr_factor_batched(c, Ks, pol)
+    Xs, infos, st = krr.krr_solve_batched(c, Fs, [_dev(Y) for Y in Ys], krr.Refine(tol=1e-8))
+    for b, (G, g, lam, Y) in enumerate(zip(Gs, gammas, lams, Ys)):
+        assert infos[b].converged == 1, b
+        Wo = oracle.fit(G, Y, g, lam)
+        assert _colrel(Xs[b].cpu().numpy(), Wo) <= TOL, b
+    # one instance through the single-instance calls agrees to the same bar
+    K = krr.krr_build_kernel(c, _dev(Gs[3]), gammas[3], lams[3])
+    X1, info1, _ = krr.krr_solve(c, krr.krr_factor(c, K, pol), _dev(Ys[3]), krr.Refine(tol=1e-8))
+    assert _colrel(Xs[3].cpu().numpy(), X1.cpu().numpy()) <= TOL
+
+
+def test_batched_bad_genotype_returns_nothing():
+    Gs, gammas, lams, _ = _batch_instances()
+    Gs[2] = Gs[2].copy()
+    Gs[2][5, 7] = 3
+    c = krr.krr_create(0, tile=256)
+    with pytest.raises(krr.KRRError) as e:
+        krr.krr_build_kernel_batched(c, [_dev(G) for G in Gs], gammas, lams)
+    assert e.value.status == krr.KRR_ERROR_BAD_GENOTYPE
