@@ -8,6 +8,8 @@
 #include <string.h>
 
 #include <algorithm>
+#include <map>
+#include <unordered_map>
 #include <vector>
 
 #include "internal.h"
@@ -23,7 +25,11 @@ struct krr_context_s {
   int device = 0;
   hipStream_t stream = nullptr;
   krr_options opts{};
-  int64_t allocated = 0;
+  int64_t allocated = 0;  // bytes of the blocks handed out
+  // device memory cache: freed blocks by size, and the size of every live block
+  std::multimap<size_t, void *> cache;
+  size_t cached = 0;
+  std::unordered_map<void *, size_t> live_sizes;
   // stage timers
   bool timing = false;
   std::vector<TimerRec> recs;
@@ -86,18 +92,48 @@ namespace {
     if (_s != KRR_SUCCESS) return _s; \
   } while (0)
 
+// Device memory goes through a per-context cache: a freed block is kept and
+// handed to a later request of about its size instead of going back to the
+// runtime (whose free synchronizes the device and whose large allocations map
+// pages, milliseconds per call).  Every free in this library happens after the
+// work that used the block has completed (the calls synchronize their stream
+// before releasing memory), so any later call may reuse a cached block.
+constexpr size_t KRR_CACHE_MAX = (size_t)64 << 30;  // larger caches return blocks to the runtime
+
+void cache_flush(krr_context ctx) {
+  for (auto &kv : ctx->cache) (void)hipFree(kv.second);
+  ctx->cache.clear();
+  ctx->cached = 0;
+}
+
 krr_status dalloc(krr_context ctx, void **p, size_t bytes) {
   *p = nullptr;
-  if (bytes == 0) bytes = 16;
+  bytes = (std::max<size_t>(bytes, 16) + 255) & ~(size_t)255;
   if (ctx->opts.workspace_limit > 0 && ctx->allocated + (int64_t)bytes > ctx->opts.workspace_limit)
     return KRR_ERROR_OUT_OF_MEMORY;
-  hipError_t e = hipMalloc(p, bytes);
-  if (e != hipSuccess) {
-    (void)hipGetLastError();
-    *p = nullptr;
-    return e == hipErrorOutOfMemory ? KRR_ERROR_OUT_OF_MEMORY : KRR_ERROR_HIP;
+  size_t size = bytes;
+  // the smallest cached block that fits, if it wastes at most a quarter
+  auto it = ctx->cache.lower_bound(bytes);
+  if (it != ctx->cache.end() && it->first <= bytes + bytes / 4) {
+    size = it->first;
+    *p = it->second;
+    ctx->cached -= size;
+    ctx->cache.erase(it);
+  } else {
+    hipError_t e = hipMalloc(p, bytes);
+    if (e == hipErrorOutOfMemory && !ctx->cache.empty()) {
+      (void)hipGetLastError();
+      cache_flush(ctx);
+      e = hipMalloc(p, bytes);
+    }
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      *p = nullptr;
+      return e == hipErrorOutOfMemory ? KRR_ERROR_OUT_OF_MEMORY : KRR_ERROR_HIP;
+    }
   }
-  ctx->allocated += (int64_t)bytes;
+  ctx->live_sizes[*p] = size;
+  ctx->allocated += (int64_t)size;
   return KRR_SUCCESS;
 }
 
@@ -106,10 +142,21 @@ krr_status dalloc_t(krr_context ctx, T **p, int64_t count) {
   return dalloc(ctx, (void **)p, (size_t)count * sizeof(T));
 }
 
-void dfree(krr_context ctx, void *p, size_t bytes) {
-  if (p) {
+void dfree(krr_context ctx, void *p, size_t /*bytes*/) {
+  if (!p) return;
+  auto it = ctx->live_sizes.find(p);
+  if (it == ctx->live_sizes.end()) {  // not from dalloc: nothing to account
     (void)hipFree(p);
-    ctx->allocated -= (int64_t)bytes;
+    return;
+  }
+  const size_t size = it->second;
+  ctx->live_sizes.erase(it);
+  ctx->allocated -= (int64_t)size;
+  if (ctx->cached + size <= KRR_CACHE_MAX) {
+    ctx->cache.emplace(size, p);
+    ctx->cached += size;
+  } else {
+    (void)hipFree(p);
   }
 }
 
@@ -145,6 +192,8 @@ struct Scoped {  // frees device buffers on scope exit unless released
   }
   void release() { bufs.clear(); }
   ~Scoped() {
+    // an early return may leave work in flight; the blocks go back to the cache
+    if (!bufs.empty()) (void)hipDeviceSynchronize();
     for (auto &b : bufs) dfree(ctx, b.first, b.second);
   }
 };
@@ -277,6 +326,7 @@ static void context_free(krr_context ctx) {
   (void)hipStreamSynchronize(ctx->stream);
   timers_drain(ctx);
   for (hipEvent_t e : ctx->pool) (void)hipEventDestroy(e);
+  cache_flush(ctx);
   for (hipStream_t x : {ctx->aux, ctx->side, ctx->fmain}) {
     if (x) {
       (void)hipStreamSynchronize(x);
@@ -987,6 +1037,9 @@ krr_status krr_factor(krr_context ctx, krr_kernel K, const krr_precision_policy 
         st = KRR_ERROR_HIP;
     }
   } while (0);
+  // on an error, work may still be in flight on the factorization's streams:
+  // let it finish before its memory goes back to the cache
+  if (st != KRR_SUCCESS) (void)hipDeviceSynchronize();
   if (dmap) dfree(ctx, dmap, mapsz);
   factor_work_free(ctx, w, L);
   if (st != KRR_SUCCESS) {
@@ -1123,6 +1176,7 @@ krr_status krr_factor_batched(krr_context ctx, int32_t batch, const krr_kernel *
       }
     }
   } while (0);
+  if (st != KRR_SUCCESS) (void)hipDeviceSynchronize();  // nothing left in flight
   (void)hipStreamSynchronize(s);
   for (int q = 0; q < S; ++q) {
     W[q].flag = own[q].first;
