@@ -1258,11 +1258,13 @@ static krr_status refine_args(const krr_refine_opts *opts, krr_refine_opts &o) {
 
 // Device buffers of one solve; right-hand sides row-major np x r.
 struct SolveBufs {
-  double *Yr = nullptr, *Xr = nullptr, *Rr = nullptr, *cn = nullptr;
+  double *Yr = nullptr, *Xr = nullptr, *Rr = nullptr, *cn = nullptr, *Pr = nullptr;
   float *Bf = nullptr, *Zf = nullptr, *Xf = nullptr;
 };
 
-static krr_status solve_alloc(Scoped &sc, int64_t cnt, int r, SolveBufs &b) {
+static krr_status solve_alloc(Scoped &sc, const TileLayout &L, int r, SolveBufs &b) {
+  const int64_t cnt = L.np * r;
+  CHK(sc.alloc(&b.Pr, cnt * residual_split(L)));
   CHK(sc.alloc(&b.Yr, cnt));
   CHK(sc.alloc(&b.Xr, cnt));
   CHK(sc.alloc(&b.Rr, cnt));
@@ -1298,7 +1300,8 @@ static void residual_norms(krr_context ctx, krr_factorization F, int r, SolveBuf
   const TileLayout &L = F->L;
   {
     Stage t(ctx, KRR_STAGE_RESIDUAL, s);
-    launch_residual(K->D, K->etab, K->etab_len, K->lambda, L, r, b.Xr, b.Yr, b.Rr, s);
+    launch_residual(K->D, K->etab, K->etab_len, K->gamma, K->lambda, L, r, b.Xr, b.Yr, b.Rr, b.Pr,
+                    s);
   }
   launch_col_norms(b.Rr, L.np, r, b.cn, s);
   launch_col_norms(b.Xr, L.np, r, b.cn + r, s);
@@ -1335,7 +1338,7 @@ krr_status krr_solve(krr_context ctx, krr_factorization F, const double *Y, int6
   const int64_t cnt = L.np * r;
   Scoped sc(ctx);
   SolveBufs b;
-  CHK(solve_alloc(sc, cnt, r, b));
+  CHK(solve_alloc(sc, L, r, b));
   launch_colmajor_to_rows(Y, L.n, ldy, r, L.np, b.Yr, s);
   launch_fill_f64(b.Xr, cnt, 0.0, s);
   solve_sweeps(ctx, F, r, b, b.Yr, s);  // the unrefined FP32 solve
@@ -1403,7 +1406,7 @@ krr_status krr_solve_batched(krr_context ctx, int32_t batch, const krr_factoriza
   auto stream_of = [&](int b) { return ctx->bstreams[where[b]]; };
   Scoped sc(ctx);
   std::vector<SolveBufs> B(batch);
-  for (int b = 0; b < batch; ++b) CHK(solve_alloc(sc, F[b]->L.np * r, r, B[b]));
+  for (int b = 0; b < batch; ++b) CHK(solve_alloc(sc, F[b]->L, r, B[b]));
   // every instance's refinement runs on its stream; the host waits once per
   // iteration for all of them
   std::vector<krr_solve_info> inf(batch);

@@ -15,15 +15,9 @@ namespace krr {
 
 // exp(-gamma * d) for every integer distance d in [0, len): the FP64 kernel
 // value of any entry is then a table lookup, bit-identical to evaluating exp.
-// The FP32 matrix handed to the factorization takes the value in two factors,
-// exp(-gamma d) = exp(-gamma 512 hi) exp(-gamma lo), d = 512 hi + lo: two
-// small tables that stay in LDS, the FP64 product rounded to FP32 (within one
+// The FP32 matrix handed to the factorization takes the value as the
+// two-level product of common.h (exp_two_level), rounded to FP32 (within one
 // FP32 ulp of the correctly rounded value).
-constexpr int EXP_LO = 512;         // entries of the low table
-constexpr int EXP_HI_MAX = 2048;    // largest high table kept in LDS
-KRR_DEV double exp_two_level(const double *hi, const double *lo, int32_t d) {
-  return hi[d / EXP_LO] * lo[d % EXP_LO];
-}
 __global__ void k_exp_table(double *tab, int64_t len, double gamma) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < len) tab[i] = exp(-gamma * (double)i);

@@ -15,6 +15,16 @@ typedef _Float16 v8h __attribute__((ext_vector_type(8)));
 // row-major block at tile index I (I + 1) / 2 + J.
 KRR_DEV int64_t tri_index(int64_t I, int64_t J) { return I * (I + 1) / 2 + J; }
 
+// exp(-gamma d) for an integer distance d as the product of two table
+// entries, exp(-gamma 512 hi) exp(-gamma lo) with d = 512 hi + lo: two small
+// FP64 tables that fit in LDS (4m + 1 <= 512 * EXP_HI_MAX).  The product of
+// the two correctly rounded factors is within two FP64 ulps of exp(-gamma d).
+constexpr int EXP_LO = 512;         // entries of the low table
+constexpr int EXP_HI_MAX = 2048;    // largest high table kept in LDS
+KRR_DEV double exp_two_level(const double *hi, const double *lo, int32_t d) {
+  return hi[d / EXP_LO] * lo[d % EXP_LO];
+}
+
 // Decode a linear index t over the lower triangle {(a, b): 0 <= b <= a}.
 KRR_DEV void tri_decode(int64_t t, int &a, int &b) {
   int64_t x = (int64_t)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);

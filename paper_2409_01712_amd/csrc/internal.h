@@ -144,9 +144,12 @@ void launch_fwd_sweep(const float *Astore, const float *Linv, const TileLayout &
                       float *B, float *Z, hipStream_t s);
 void launch_bwd_sweep(const float *Astore, const float *Linv, const TileLayout &L, int r,
                       float *Z, float *X, hipStream_t s);
-void launch_residual(const int32_t *D, const double *etab, int64_t etab_len, double lambda,
-                     const TileLayout &L, int r, const double *X, const double *Y, double *R,
-                     hipStream_t s);
+// R = Y - (K + lambda I) X in FP64; part: residual_split(L) * np * r doubles
+// of workspace for the partial products.
+int residual_split(const TileLayout &L);
+void launch_residual(const int32_t *D, const double *etab, int64_t etab_len, double gamma,
+                     double lambda, const TileLayout &L, int r, const double *X, const double *Y,
+                     double *R, double *part, hipStream_t s);
 void launch_colmajor_to_rows(const double *src, int64_t n, int64_t ld, int r, int64_t np,
                              double *dst, hipStream_t s);
 void launch_rows_to_colmajor(const double *src, int64_t n, int r, double *dst, int64_t ld,

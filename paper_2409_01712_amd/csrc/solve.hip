@@ -8,6 +8,8 @@
 // beside) is updated.  The FP64 residual r = Y - (K + lambda I) X recomputes
 // every kernel entry from the exact int32 distance through the FP64 table
 // exp(-gamma d).
+#include <algorithm>
+
 #include "common.h"
 #include "internal.h"
 
@@ -203,61 +205,203 @@ __device__ __forceinline__ void exp_mfma_block(const int32_t *__restrict__ D, in
   }
 }
 
+// exp(-gamma d) without a gather per entry: with d = h W - t, h = round(d / W)
+// and W a power of two, exp(-gamma d) = exp(-gamma h W) exp(gamma t), the first
+// factor from a small LDS table indexed by h (the distances of a wavefront
+// fall in a few neighbouring h, so the reads are broadcasts) and the second
+// by its Taylor polynomial of degree RES_DEG, |gamma t| <= gamma W / 2 <=
+// RES_XMAX (truncation below 2^-60 relative).  Within a few FP64 ulps of
+// the correctly rounded value.
+constexpr int RES_DEG = 7;
+constexpr double RES_XMAX = 0.02;  // 0.02^8 / 8! < 2^-60
+constexpr int RES_HI_MAX = 2048;   // entries of the LDS table
+
 // Residual R = Y - (K + lambda I) X over the packed lower tiles of int32
-// distances: 64 rows (4 waves x 16) of tile row I per workgroup; tiles
-// (I, J <= I) are read directly and tiles (J > I, I) transposed.
-template <int NCB>
+// distances, in FP64 (16 x 16 x 4 MFMA).  A workgroup owns 64 rows of tile
+// row I (wave w: rows 16w .. 16w+15) and 16 NCB columns, and walks all n
+// columns 64 at a time: tiles (I, J <= I) are read directly, tiles (J > I, I)
+// transposed.  Per 64-column step the 64 rows of X it multiplies are staged
+// once in LDS for the four waves (double-buffered), and the next step's
+// distances and X rows are in flight during the current step's MFMAs.
+// FACT: exp(-gamma d) factored with W = 2^wshift; otherwise the FP64 table in
+// memory (one gather per entry).
+template <int NCB, bool FACT>
 __global__ __launch_bounds__(256) void k_residual(const int32_t *__restrict__ D,
                                                   const double *__restrict__ etab,
-                                                  int64_t etab_len, double lambda, int64_t n,
-                                                  int nb, int NT, int r,
+                                                  int64_t etab_len, double gamma, int wshift,
+                                                  int64_t np, int nb, int NT, int r,
                                                   const double *__restrict__ X,
-                                                  const double *__restrict__ Y,
-                                                  double *__restrict__ R) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+                                                  double *__restrict__ part) {
+  constexpr int XC = 16 * NCB, XLD = XC + 2, XPT = XC / 4;  // X values per thread and step
+  __shared__ double ehi[RES_HI_MAX];
+  __shared__ double xs[2][64 * XLD];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, lg = lane >> 4;
-  const int64_t g0 = (int64_t)blockIdx.x * 64 + wave * 16;
-  const int I = (int)(g0 / nb), rloc = (int)(g0 % nb);
-  const int col0 = blockIdx.y * 16 * NCB;
+  const int64_t dmax = etab_len - 1;
+  if (FACT) {
+    const int nhi = (int)(dmax >> wshift) + 2;
+    for (int q = tid; q < nhi; q += 256) ehi[q] = exp(-gamma * (double)((int64_t)q << wshift));
+  }
+  const int64_t r0 = (int64_t)blockIdx.x * 64;  // first row of the workgroup
+  const int I = (int)(r0 / nb), rloc = (int)(r0 % nb) + wave * 16;
+  const int col0 = blockIdx.y * XC;
   const int64_t te = (int64_t)nb * nb;
+  // this workgroup's share of the columns: tiles J0 .. J1-1
+  const int J0 = (int)((int64_t)NT * blockIdx.z / gridDim.z);
+  const int J1 = (int)((int64_t)NT * (blockIdx.z + 1) / gridDim.z);
+  const int spt = nb / 64, st0 = J0 * spt, nsteps = J1 * spt;
+
+  // branch-free (both orientations issue the same sixteen loads), so the
+  // compiler can count them and leave the next step's loads in flight
+  auto fetch_d = [&](int st, int32_t (&d)[4][4]) {
+    const int J = st / spt, q = (st % spt) * 64;
+    const bool dir = J <= I;
+    const int64_t tb = tri_index(dir ? I : J, dir ? J : I) * te;
+    const int64_t sr = dir ? nb : 1, sc = dir ? 1 : nb;  // strides of row and k
+    const int32_t *b = D + tb + (int64_t)(rloc + li) * sr + (int64_t)(q + 4 * lg) * sc;
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) d[u][e] = b[(int64_t)(16 * u + e) * sc];
+  };
+  // element v of this thread: row (tid + 256 v) / XC, column (tid + 256 v) % XC
+  auto fetch_x = [&](int st, double (&x)[XPT]) {
+    const int64_t xr0 = (int64_t)(st / spt) * nb + (st % spt) * 64;
+#pragma unroll
+    for (int v = 0; v < XPT; ++v) {
+      const int e = tid + 256 * v, t = e / XC, c = col0 + e % XC;
+      const double val = X[(xr0 + t) * r + min(c, r - 1)];
+      x[v] = c < r ? val : 0.0;
+    }
+  };
+  auto store_x = [&](int buf, const double (&x)[XPT]) {
+#pragma unroll
+    for (int v = 0; v < XPT; ++v) {
+      const int e = tid + 256 * v;
+      xs[buf][(e / XC) * XLD + e % XC] = x[v];
+    }
+  };
+  const int32_t half = FACT ? (1 << wshift) >> 1 : 0;
+  auto kexp = [&](int32_t d) -> double {
+    const int32_t dd = (int32_t)min((int64_t)max(d, 0), dmax);
+    if (!FACT) return etab[dd];
+    const int32_t h = (dd + half) >> wshift;
+    const double x = gamma * (double)((h << wshift) - dd);
+    double p = 1.0 / 5040.0;  // 1 / RES_DEG!
+    p = fma(p, x, 1.0 / 720.0);
+    p = fma(p, x, 1.0 / 120.0);
+    p = fma(p, x, 1.0 / 24.0);
+    p = fma(p, x, 1.0 / 6.0);
+    p = fma(p, x, 0.5);
+    p = fma(p, x, 1.0);
+    p = fma(p, x, 1.0);
+    return ehi[h] * p;
+  };
+
   v4d acc[NCB];
 #pragma unroll
   for (int c = 0; c < NCB; ++c) acc[c] = (v4d){0.0, 0.0, 0.0, 0.0};
-  for (int J = 0; J < NT; ++J) {
-    if (J <= I)
-      exp_mfma_block<0, NCB>(D + ((int64_t)I * (I + 1) / 2 + J) * te, nb, rloc + li, 0, nb, etab,
-                             etab_len - 1, X, r, (int64_t)J * nb, col0, li, lg, acc);
-    else
-      exp_mfma_block<1, NCB>(D + ((int64_t)J * (J + 1) / 2 + I) * te, nb, rloc + li, 0, nb, etab,
-                             etab_len - 1, X, r, (int64_t)J * nb, col0, li, lg, acc);
+  // two register sets for the distances, used alternately (no copies between
+  // steps): step st computes with one while the other receives step st + 1
+  int32_t da[4][4], db[4][4];
+  double xv[XPT];
+  if (st0 < nsteps) {
+    fetch_d(st0, da);
+    fetch_x(st0, xv);
+    store_x(0, xv);
   }
+  __syncthreads();  // the table and the first X block
+  int cur = 0;
+  auto step = [&](int st, const int32_t (&dc)[4][4], int32_t (&dn)[4][4]) {
+    const bool more = st + 1 < nsteps;
+    if (more) {  // X first: storing it to LDS at the end of the step waits on it alone
+      fetch_x(st + 1, xv);
+      fetch_d(st + 1, dn);
+    }
+    double a[4][4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) a[u][e] = kexp(dc[u][e]);
+    const double *xb = xs[cur];
+#pragma unroll
+    for (int c = 0; c < NCB; ++c)
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(
+              a[u][e], xb[(16 * u + 4 * lg + e) * XLD + c * 16 + li], acc[c], 0, 0, 0);
+    // keep the store of the prefetched X block after this step's MFMAs (it
+    // waits for those loads)
+    __builtin_amdgcn_sched_barrier(0);
+    if (more) store_x(cur ^ 1, xv);  // its readers (step st - 1) passed the last barrier
+    // LDS reads and writes of this step done everywhere; the next step's
+    // distance loads stay in flight across the barrier
+    bar_nofence();
+    cur ^= 1;
+  };
+  for (int st = st0; st < nsteps; st += 2) {
+    step(st, da, db);
+    if (st + 1 < nsteps) step(st + 1, db, da);
+  }
+  const int64_t g0 = r0 + wave * 16;
+  double *P = part + (int64_t)blockIdx.z * np * r;
 #pragma unroll
   for (int c = 0; c < NCB; ++c) {
     const int col = col0 + c * 16 + li;
     if (col >= r) continue;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int64_t g = g0 + 4 * i + lg;
-      const int64_t off = g * r + col;
-      R[off] = (g < n) ? Y[off] - acc[c][i] - lambda * X[off] : 0.0;
-    }
+    for (int i = 0; i < 4; ++i) P[(g0 + 4 * i + lg) * r + col] = acc[c][i];
   }
 }
 
-void launch_residual(const int32_t *D, const double *etab, int64_t etab_len, double lambda,
-                     const TileLayout &L, int r, const double *X, const double *Y, double *R,
-                     hipStream_t s) {
+// R = Y - sum_z part[z] - lambda X, the partial products added in z order.
+__global__ void k_residual_sum(const double *__restrict__ part, int nsplit, int64_t np, int r,
+                               int64_t n, double lambda, const double *__restrict__ X,
+                               const double *__restrict__ Y, double *__restrict__ R) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= np * r) return;
+  double s = 0.0;
+  for (int z = 0; z < nsplit; ++z) s += part[(int64_t)z * np * r + e];
+  R[e] = (e / r < n) ? Y[e] - s - lambda * X[e] : 0.0;
+}
+
+// log2 of the largest W = 2^k with gamma W / 2 <= RES_XMAX whose table of
+// exp(-gamma h W), h <= dmax / W + 1, fits in LDS; -1 when none does.
+static int residual_wshift(double gamma, int64_t dmax) {
+  int k = 0;
+  while (k < 30 && gamma * (double)(1LL << (k + 1)) * 0.5 <= RES_XMAX) ++k;
+  if (gamma * (double)(1LL << k) * 0.5 > RES_XMAX) return -1;
+  if ((dmax >> k) + 2 > RES_HI_MAX) return -1;
+  return k;
+}
+
+int residual_split(const TileLayout &L) { return std::min(4, L.nt); }
+
+void launch_residual(const int32_t *D, const double *etab, int64_t etab_len, double gamma,
+                     double lambda, const TileLayout &L, int r, const double *X, const double *Y,
+                     double *R, double *part, hipStream_t s) {
   const unsigned rb = (unsigned)(L.np / 64);
-  const int ncb = (r + 15) / 16;
-  if (ncb <= 1)
-    hipLaunchKernelGGL(k_residual<1>, dim3(rb, 1), dim3(256), 0, s, D, etab, etab_len, lambda, L.n,
-                       L.nb, L.nt, r, X, Y, R);
-  else if (ncb <= 2)
-    hipLaunchKernelGGL(k_residual<2>, dim3(rb, 1), dim3(256), 0, s, D, etab, etab_len, lambda, L.n,
-                       L.nb, L.nt, r, X, Y, R);
-  else
-    hipLaunchKernelGGL(k_residual<4>, dim3(rb, (unsigned)((r + 63) / 64)), dim3(256), 0, s, D,
-                       etab, etab_len, lambda, L.n, L.nb, L.nt, r, X, Y, R);
+  const int ncb = (r + 15) / 16, z = residual_split(L);
+  const int ws = residual_wshift(gamma, etab_len - 1);
+  const dim3 grid(rb, ncb <= 2 ? 1u : (unsigned)((r + 63) / 64), z);
+#define KRR_RES(NCB, FACT)                                                                     \
+  hipLaunchKernelGGL((k_residual<NCB, FACT>), grid, dim3(256), 0, s, D, etab, etab_len, gamma, \
+                     ws, L.np, L.nb, L.nt, r, X, part)
+  if (ws >= 0) {
+    if (ncb <= 1) KRR_RES(1, true);
+    else if (ncb <= 2) KRR_RES(2, true);
+    else KRR_RES(4, true);
+  } else {
+    if (ncb <= 1) KRR_RES(1, false);
+    else if (ncb <= 2) KRR_RES(2, false);
+    else KRR_RES(4, false);
+  }
+#undef KRR_RES
+  const int64_t tot = L.np * r;
+  hipLaunchKernelGGL(k_residual_sum, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, part, z,
+                     L.np, r, L.n, lambda, X, Y, R);
 }
 
 // Predict: P[i, :] = sum_j exp(-gamma Dt[i, j]) X[j, :] in FP64 for a block of
