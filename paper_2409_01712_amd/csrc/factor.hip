@@ -572,13 +572,14 @@ __global__ __launch_bounds__(256) void k_trsm_panel(const float *__restrict__ As
     // B(kk, c) = L[c0 + c][kk] over kk < 64 s
     const T *Lrow = WLk + (int64_t)(c0 + li) * nb;
     v4 acc = {0, 0, 0, 0};
-#pragma unroll 2
-    for (int kk = 0; kk < BS * s; kk += 16) {
-      T bv[4];
+    // 64 columns of k per iteration, all sixteen loads (L_kk, in L2) issued
+    // before the MFMAs: this loop is bound by load latency
+    for (int k64 = 0; k64 < BS * s; k64 += BS) {
+      T bv[16];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) bv[u] = Lrow[kk + 4 * u + lg];
+      for (int u = 0; u < 16; ++u) bv[u] = Lrow[k64 + 4 * u + lg];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) acc = M16<T>::mma(Pr[li][kk + 4 * u + lg], bv[u], acc);
+      for (int u = 0; u < 16; ++u) acc = M16<T>::mma(Pr[li][k64 + 4 * u + lg], bv[u], acc);
     }
 #pragma unroll
     for (int r = 0; r < 4; ++r) {

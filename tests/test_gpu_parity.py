@@ -410,3 +410,23 @@ def test_batched_bad_genotype_returns_nothing():
     with pytest.raises(krr.KRRError) as e:
         krr.krr_build_kernel_batched(c, [_dev(G) for G in Gs], gammas, lams)
     assert e.value.status == krr.KRR_ERROR_BAD_GENOTYPE
+
+
+@pytest.mark.parametrize("gamma_scale", [1.0, 2000.0])
+def test_residual_bound_matches_oracle(ctx, gamma_scale):
+    """The FP64 residual behind the refinement's stop rule: the bound the library reports
+    for the unrefined X equals max_j ||Y_j - (K + lambda I) X_j|| / (lambda ||X_j||) with the
+    oracle's residual (exp by definition).  gamma_scale 2000 takes the kernel's table
+    path instead of the factored exponential."""
+    n, m, r = 1100, 300, 3
+    G = _gen(n, m, seed=21)
+    Y = synth.phenotypes(G, r, n_pairs=10, n_add=5, seed=8, h2=0.5)
+    gamma, lam = gamma_scale / m, 0.05
+    K = krr.krr_build_kernel(ctx, _dev(G), gamma, lam)
+    F = krr.krr_factor(ctx, K)
+    X, info, st = krr.krr_solve(ctx, F, _dev(Y), krr.Refine(max_iters=0, tol=0.0), check=False)
+    Xh = X.cpu().numpy()
+    R = oracle.residual_rows(G, gamma, lam, Xh, Y, np.arange(n))
+    bound = np.max(np.linalg.norm(R, axis=0) / (lam * np.linalg.norm(Xh, axis=0)))
+    assert info.first_bound > 0
+    np.testing.assert_allclose(info.fwd_err_bound, bound, rtol=1e-8)
