@@ -103,8 +103,9 @@ typedef struct krr_precision_policy {
 enum {
   KRR_REFINE_NONE = 0, /* one pair of FP32 triangular solves, no FP64 residual */
   KRR_REFINE_IR = 1,   /* iterative refinement with an FP64 residual */
-  KRR_REFINE_PCG = 2,  /* conjugate gradients preconditioned by the factor */
-  KRR_REFINE_AUTO = 3  /* IR, switching to PCG when IR contracts slower than 0.5 */
+  KRR_REFINE_PCG = 2,  /* conjugate gradients preconditioned by the factor: not built,
+                          krr_solve returns KRR_ERROR_NOT_SUPPORTED */
+  KRR_REFINE_AUTO = 3  /* the library's choice; currently IR */
 };
 
 typedef struct krr_refine_opts {
@@ -206,7 +207,10 @@ krr_status krr_build_kernel_batched(krr_context ctx, int32_t batch, const int8_t
                                     const double *gamma, const double *lambda, krr_kernel *out);
 /* Factorization of `batch` distinct kernels under one policy (NULL =
  * ADAPTIVE defaults).  Instances are spread over 4 streams by their
- * Cholesky cost (longest first to the least loaded stream); each stream
+ * Cholesky cost (longest first to the least loaded stream; the environment
+ * variable KRR_BATCH_STREAMS, 1 to 16, changes the count of 4 -- useful with
+ * GPU_MAX_HW_QUEUES raised to match, so that the streams run concurrently on
+ * separate hardware queues); each stream
  * factors its instances in turn with one workspace sized for its largest.
  * An instance that breaks down is then factored again on its own with
  * promotion, exactly as krr_factor does.  Blocks until all are done. */

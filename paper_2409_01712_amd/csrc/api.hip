@@ -350,9 +350,18 @@ static krr_status context_aux(krr_context ctx) {
   return KRR_SUCCESS;
 }
 
-// Streams for the instances of a batched call (default priority); as many as
-// the process has hardware queues by default, so that they run concurrently.
-constexpr int KRR_BATCH_STREAMS = 4;
+// Streams for the instances of a batched call (default priority): by default
+// as many as the HIP runtime gives a process hardware queues (4), so that they
+// run concurrently; KRR_BATCH_STREAMS (1 .. 16) sets another count, for a
+// process that raised GPU_MAX_HW_QUEUES to match.
+static int batch_stream_count() {
+  static const int n = [] {
+    const char *e = getenv("KRR_BATCH_STREAMS");
+    const int v = e ? atoi(e) : 4;
+    return std::max(1, std::min(16, v));
+  }();
+  return n;
+}
 static krr_status context_batch_streams(krr_context ctx, int count) {
   while ((int)ctx->bstreams.size() < count) {
     hipStream_t x = nullptr;
@@ -1097,7 +1106,7 @@ krr_status krr_factor_batched(krr_context ctx, int32_t batch, const krr_kernel *
   }
   const char *g_env = getenv("KRR_GROUP");
   const int g = std::max(1, std::min(KRR_MAX_GROUP, g_env ? atoi(g_env) : 4));
-  const int S = std::min<int>(batch, KRR_BATCH_STREAMS);
+  const int S = std::min<int>(batch, batch_stream_count());
   CHK(context_batch_streams(ctx, S));
   // instances to streams by their Cholesky cost; each stream runs its
   // instances one after the other (tile Cholesky on one stream, in program
@@ -1397,7 +1406,7 @@ krr_status krr_solve_batched(krr_context ctx, int32_t batch, const krr_factoriza
   HIPCHK(hipSetDevice(ctx->device));
   hipStream_t s = ctx->stream;
   const int r = (int)nrhs;
-  const int S = std::min<int>(batch, KRR_BATCH_STREAMS);
+  const int S = std::min<int>(batch, batch_stream_count());
   CHK(context_batch_streams(ctx, S));
   std::vector<double> cost(batch);
   for (int b = 0; b < batch; ++b) cost[b] = (double)F[b]->L.np * F[b]->L.np;
