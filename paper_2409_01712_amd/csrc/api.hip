@@ -870,17 +870,25 @@ static krr_status factor_enqueue(krr_context ctx, krr_kernel K, krr_factorizatio
     launch_update(F->Lst, G0, npan, jlo, jhi, L, up, w, ps, dmap, which, st);
   };
   const int NT = L.nt;
-  if (!lookahead) {  // one stream, in program order
+  if (!lookahead) {
+    // One stream, in program order, with few launches per tile (this path
+    // serves many small instances at once): the panel by substitution, and
+    // the tile inverses (needed only by the solves) at the end, a chunk of
+    // tiles per launch sequence.
     for (int G0 = 0; G0 < NT; G0 += g) {
       const int gend = std::min(G0 + g, NT);
       for (int k = G0; k < gend; ++k) {
         potrf(k, 0, 0, s);
-        trsm_gemm(k, 0, NT, s);
-        if (k + 1 < NT) convert(k, s);
+        if (k + 1 < NT) {
+          trsm_subst(k, 0, NT - 1 - k, s);
+          convert(k, s);
+        }
         update(k, 1, k + 1, gend - 1, UPD_ALL, s);
       }
       update(G0, gend - G0, gend, NT - 1, UPD_ALL, s);
     }
+    Stage t(ctx, KRR_STAGE_POTRF, s);
+    launch_tile_inverses(F->Lst, F->Linv, 0, NT, L, fp.diag64, w, s);
   } else {
     // Three streams.  Main, the critical path: POTRF(k) (with the tile's
     // last updates folded into its load) and the TRSM of row k+1 alone.  Side: the
@@ -1405,72 +1413,129 @@ krr_status krr_solve_batched(krr_context ctx, int32_t batch, const krr_factoriza
   CHK(refine_args(opts, o));
   HIPCHK(hipSetDevice(ctx->device));
   hipStream_t s = ctx->stream;
-  const int r = (int)nrhs;
-  const int S = std::min<int>(batch, batch_stream_count());
-  CHK(context_batch_streams(ctx, S));
-  std::vector<double> cost(batch);
-  for (int b = 0; b < batch; ++b) cost[b] = (double)F[b]->L.np * F[b]->L.np;
-  std::vector<int> order;
-  const std::vector<int> where = lpt_assign(cost, S, order);
-  auto stream_of = [&](int b) { return ctx->bstreams[where[b]]; };
+  const int r = (int)nrhs, nb = ctx->opts.tile;
   Scoped sc(ctx);
   std::vector<SolveBufs> B(batch);
   for (int b = 0; b < batch; ++b) CHK(solve_alloc(sc, F[b]->L, r, B[b]));
-  // every instance's refinement runs on its stream; the host waits once per
-  // iteration for all of them
-  std::vector<krr_solve_info> inf(batch);
-  std::vector<double> hn(2 * (size_t)r * batch), yn((size_t)r * batch);
-  CHK(batch_fence(ctx, s, S, false));
-  for (int b : order) {
+  SolveJob *djobs = nullptr;
+  CHK(sc.alloc(&djobs, batch));
+  // The table of the instances a batched launch covers; every instance's
+  // steps run in lockstep in one launch per step (sweeps) or per pass
+  // (residual), all on the context stream.
+  std::vector<SolveJob> all(batch);
+  std::vector<std::vector<SolveJob>> tables;  // every uploaded table lives until the return
+  for (int b = 0; b < batch; ++b) {
+    krr_kernel K = F[b]->K;
+    SolveJob &j = all[b];
+    j.Lst = F[b]->Lst;
+    j.Linv = F[b]->Linv;
+    j.B = B[b].Bf;
+    j.Z = B[b].Zf;
+    j.X = B[b].Xf;
+    j.nt = F[b]->L.nt;
+    j.D = K->D;
+    j.etab = K->etab;
+    j.etab_len = K->etab_len;
+    j.gamma = K->gamma;
+    j.wshift = residual_exp_shift(K->gamma, K->etab_len);
+    j.np = F[b]->L.np;
+    j.Xd = B[b].Xr;
+    j.part = B[b].Pr;
+    j.rb0 = 0;
+  }
+  // upload the table of the instances in `ids` (rb0 prefix over them); its
+  // host copy is kept until the call returns, past any asynchronous copy
+  auto upload = [&](const std::vector<int> &ids, int &ntmax, int64_t &rblocks,
+                    bool &fact) -> krr_status {
+    tables.emplace_back();
+    std::vector<SolveJob> &act = tables.back();
+    ntmax = 0;
+    rblocks = 0;
+    fact = true;
+    for (int b : ids) {
+      SolveJob j = all[b];
+      j.rb0 = rblocks;
+      rblocks += j.np / 64;
+      ntmax = std::max(ntmax, j.nt);
+      fact = fact && j.wshift >= 0;
+      act.push_back(j);
+    }
+    HIPCHK(hipMemcpyAsync(djobs, act.data(), sizeof(SolveJob) * act.size(), hipMemcpyHostToDevice,
+                          s));
+    return KRR_SUCCESS;
+  };
+  auto sweeps = [&](const std::vector<int> &ids, bool from_residual) -> krr_status {
+    for (int b : ids) {
+      const int64_t cnt = F[b]->L.np * r;
+      launch_f64_to_f32(from_residual ? B[b].Rr : B[b].Yr, cnt, B[b].Bf, s);
+    }
+    int ntmax;
+    int64_t rblocks;
+    bool fact;
+    CHK(upload(ids, ntmax, rblocks, fact));
+    {
+      Stage t(ctx, KRR_STAGE_FWD, s);
+      launch_sweeps_batched(djobs, (int)ids.size(), ntmax, nb, r, s);
+    }
+    for (int b : ids) launch_axpy_f32_to_f64(B[b].Xf, F[b]->L.np * r, 1.0, B[b].Xr, s);
+    return launch_ok();
+  };
+  std::vector<int> ids(batch);
+  for (int b = 0; b < batch; ++b) ids[b] = b;
+  for (int b = 0; b < batch; ++b) {
     const TileLayout &L = F[b]->L;
-    hipStream_t sq = stream_of(b);
-    launch_colmajor_to_rows(Y[b], L.n, ldy[b], r, L.np, B[b].Yr, sq);
-    launch_fill_f64(B[b].Xr, L.np * r, 0.0, sq);
-    solve_sweeps(ctx, F[b], r, B[b], B[b].Yr, sq);
-    inf[b].first_bound = -1;
-    if (o.method != KRR_REFINE_NONE) {
-      launch_col_norms(B[b].Yr, L.np, r, B[b].cn, sq);
-      HIPCHK(hipMemcpyAsync(yn.data() + (size_t)r * b, B[b].cn, r * 8, hipMemcpyDeviceToHost, sq));
-    }
+    launch_colmajor_to_rows(Y[b], L.n, ldy[b], r, L.np, B[b].Yr, s);
+    launch_fill_f64(B[b].Xr, L.np * r, 0.0, s);
   }
-  CHK(launch_ok());
-  std::vector<char> active(batch, o.method != KRR_REFINE_NONE);
-  for (int it = 0;; ++it) {
-    bool any = false;
-    for (int b : order) {
-      if (!active[b]) continue;
-      any = true;
-      hipStream_t sq = stream_of(b);
-      residual_norms(ctx, F[b], r, B[b], sq);
-      HIPCHK(hipMemcpyAsync(hn.data() + 2 * (size_t)r * b, B[b].cn, 2 * r * 8,
-                            hipMemcpyDeviceToHost, sq));
+  CHK(sweeps(ids, false));  // the unrefined FP32 solves
+  std::vector<krr_solve_info> inf(batch);
+  for (auto &x : inf) x.first_bound = -1;
+  std::vector<double> hn(2 * (size_t)r * batch), yn((size_t)r * batch);
+  if (o.method != KRR_REFINE_NONE) {
+    for (int b = 0; b < batch; ++b) {
+      launch_col_norms(B[b].Yr, F[b]->L.np, r, B[b].cn, s);
+      HIPCHK(hipMemcpyAsync(yn.data() + (size_t)r * b, B[b].cn, r * 8, hipMemcpyDeviceToHost, s));
     }
-    if (!any) break;
-    CHK(launch_ok());
-    for (int q = 0; q < S; ++q) HIPCHK(hipStreamSynchronize(ctx->bstreams[q]));
-    for (int b : order) {
-      if (!active[b]) continue;
-      double bound, berr;
-      refine_bounds(hn.data() + 2 * (size_t)r * b, yn.data() + (size_t)r * b, r, F[b]->K->lambda,
-                    F[b]->K->norm_a, bound, berr);
-      if (it == 0) inf[b].first_bound = bound;
-      inf[b].fwd_err_bound = bound;
-      inf[b].backward_err = berr;
-      inf[b].iters = it;
-      if (bound <= o.tol) {
-        inf[b].converged = 1;
-        active[b] = 0;
-      } else if (it >= o.max_iters) {
-        active[b] = 0;
-      } else {
-        solve_sweeps(ctx, F[b], r, B[b], B[b].Rr, stream_of(b));
+    HIPCHK(hipStreamSynchronize(s));
+    for (int it = 0; !ids.empty(); ++it) {
+      int ntmax;
+      int64_t rblocks;
+      bool fact;
+      CHK(upload(ids, ntmax, rblocks, fact));
+      {
+        Stage t(ctx, KRR_STAGE_RESIDUAL, s);
+        launch_residual_batched(djobs, (int)ids.size(), rblocks, fact, nb, r, s);
       }
+      for (int b : ids) {
+        const TileLayout &L = F[b]->L;
+        launch_residual_sum(B[b].Pr, residual_split(L), L, r, F[b]->K->lambda, B[b].Xr, B[b].Yr,
+                            B[b].Rr, s);
+        launch_col_norms(B[b].Rr, L.np, r, B[b].cn, s);
+        launch_col_norms(B[b].Xr, L.np, r, B[b].cn + r, s);
+        HIPCHK(hipMemcpyAsync(hn.data() + 2 * (size_t)r * b, B[b].cn, 2 * r * 8,
+                              hipMemcpyDeviceToHost, s));
+      }
+      CHK(launch_ok());
+      HIPCHK(hipStreamSynchronize(s));
+      std::vector<int> next;
+      for (int b : ids) {
+        double bound, berr;
+        refine_bounds(hn.data() + 2 * (size_t)r * b, yn.data() + (size_t)r * b, r,
+                      F[b]->K->lambda, F[b]->K->norm_a, bound, berr);
+        if (it == 0) inf[b].first_bound = bound;
+        inf[b].fwd_err_bound = bound;
+        inf[b].backward_err = berr;
+        inf[b].iters = it;
+        if (bound <= o.tol) inf[b].converged = 1;
+        else if (it < o.max_iters) next.push_back(b);
+      }
+      ids.swap(next);
+      if (!ids.empty()) CHK(sweeps(ids, true));
     }
   }
-  for (int b : order)
-    launch_rows_to_colmajor(B[b].Xr, F[b]->L.n, r, X[b], ldx[b], stream_of(b));
+  for (int b = 0; b < batch; ++b)
+    launch_rows_to_colmajor(B[b].Xr, F[b]->L.n, r, X[b], ldx[b], s);
   CHK(launch_ok());
-  CHK(batch_fence(ctx, s, S, true));
   HIPCHK(hipStreamSynchronize(s));
   krr_status st = KRR_SUCCESS;
   for (int b = 0; b < batch; ++b) {

@@ -19,6 +19,24 @@ struct TileLayout {
   static int64_t tri(int64_t I, int64_t J) { return I * (I + 1) / 2 + J; }
 };
 
+// One instance of a batched solve (device table): the factor, the FP32
+// right-hand sides of the sweeps (row-major np x r), and what the FP64
+// residual reads and writes.
+struct SolveJob {
+  const float *Lst, *Linv;
+  float *B, *Z, *X;
+  int nt;
+  const int32_t *D;
+  const double *etab;
+  int64_t etab_len;
+  double gamma;
+  int wshift;           // residual_exp_shift(gamma, etab_len)
+  int64_t np;
+  const double *Xd;     // FP64 iterate
+  double *part;         // residual_split * np * r partial products
+  int64_t rb0;          // first residual row block of this instance
+};
+
 // ---- build.hip ----
 // One instance of a batched Build: its inputs, outputs and the first
 // workgroup of each batched launch that belongs to it.
@@ -150,6 +168,19 @@ int residual_split(const TileLayout &L);
 void launch_residual(const int32_t *D, const double *etab, int64_t etab_len, double gamma,
                      double lambda, const TileLayout &L, int r, const double *X, const double *Y,
                      double *R, double *part, hipStream_t s);
+// Batched (lockstep over a table of instances, tile counts up to ntmax):
+// both sweeps, L Z = B then L^T X = Z.
+void launch_sweeps_batched(const SolveJob *jobs, int njobs, int ntmax, int nb, int r,
+                           hipStream_t s);
+// log2 of the residual's exp factoring width for (gamma, 4m + 1), or -1
+int residual_exp_shift(double gamma, int64_t etab_len);
+// partial products of every instance (rblocks = total np / 64; fact when every
+// instance has wshift >= 0), then per instance R = Y - sum part - lambda X
+void launch_residual_batched(const SolveJob *jobs, int njobs, int64_t rblocks, bool fact, int nb,
+                             int r, hipStream_t s);
+void launch_residual_sum(const double *part, int nsplit, const TileLayout &L, int r,
+                         double lambda, const double *X, const double *Y, double *R,
+                         hipStream_t s);
 void launch_colmajor_to_rows(const double *src, int64_t n, int64_t ld, int r, int64_t np,
                              double *dst, hipStream_t s);
 void launch_rows_to_colmajor(const double *src, int64_t n, int r, double *dst, int64_t ld,

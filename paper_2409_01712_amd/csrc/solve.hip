@@ -85,12 +85,11 @@ __device__ __forceinline__ v4f job_product(const float *__restrict__ M, const fl
 //   forward  Z_k = inv(L_kk) B_k     (rows of the inverse need k <= row)
 //   backward X_k = inv(L_kk)^T Z_k   (its transpose, k >= row)
 template <bool FWD>
-__global__ __launch_bounds__(256) void k_sweep_diag(const float *__restrict__ Linv_k,
-                                                    const float *In_k, float *Out_k, int nb,
-                                                    int r) {
+__device__ __forceinline__ void sweep_diag_body(const float *__restrict__ Linv_k, const float *In_k,
+                                                float *Out_k, int nb, int r, int bid) {
   __shared__ v4f red[4][64];
   const int CJ = (r + 15) / 16;
-  const int rj = blockIdx.x / CJ, cj = blockIdx.x % CJ;
+  const int rj = bid / CJ, cj = bid % CJ;
   const int row0 = rj * 16, col0 = cj * 16;
   const v4f acc = job_product<!FWD>(Linv_k, In_k, nb, r, row0, col0, FWD ? 0 : row0,
                                     FWD ? row0 + 16 : nb, red);
@@ -101,17 +100,23 @@ __global__ __launch_bounds__(256) void k_sweep_diag(const float *__restrict__ Li
   }
 }
 
+template <bool FWD>
+__global__ __launch_bounds__(256) void k_sweep_diag(const float *__restrict__ Linv_k,
+                                                    const float *In_k, float *Out_k, int nb,
+                                                    int r) {
+  sweep_diag_body<FWD>(Linv_k, In_k, Out_k, nb, r, blockIdx.x);
+}
+
 // Sweep step k, update part (one job per workgroup):
 //   forward  B_i -= L_ik Z_k,   i > k
 //   backward Z_j -= L_kj^T X_k, j < k
 template <bool FWD>
-__global__ __launch_bounds__(256) void k_sweep_panel(const float *__restrict__ Lst,
-                                                     const float *V_k, float *In, int k, int nb,
-                                                     int r) {
+__device__ __forceinline__ void sweep_panel_body(const float *__restrict__ Lst, const float *V_k,
+                                                 float *In, int k, int nb, int r, int64_t bid) {
   __shared__ v4f red[4][64];
   const int CJ = (r + 15) / 16, per = (nb / 16) * CJ;
-  const int64_t t = blockIdx.x / per;
-  const int rem = (int)(blockIdx.x % per), rj = rem / CJ, cj = rem % CJ;
+  const int64_t t = bid / per;
+  const int rem = (int)(bid % per), rj = rem / CJ, cj = rem % CJ;
   const int64_t i = FWD ? k + 1 + t : t;
   const int64_t te = (int64_t)nb * nb;
   const float *M = Lst + (FWD ? i * (i + 1) / 2 + k : (int64_t)k * (k + 1) / 2 + i) * te;
@@ -122,6 +127,54 @@ __global__ __launch_bounds__(256) void k_sweep_panel(const float *__restrict__ L
     float *o = In + i * (int64_t)nb * r;
 #pragma unroll
     for (int e = 0; e < 4; ++e) o[(int64_t)(row0 + 4 * (lane >> 4) + e) * r + col] -= acc[e];
+  }
+}
+
+template <bool FWD>
+__global__ __launch_bounds__(256) void k_sweep_panel(const float *__restrict__ Lst,
+                                                     const float *V_k, float *In, int k, int nb,
+                                                     int r) {
+  sweep_panel_body<FWD>(Lst, V_k, In, k, nb, r, blockIdx.x);
+}
+
+// The same steps for a batch of instances in lockstep (blockIdx.y = instance):
+// step k of instance j runs when k < its tile count; forward B -> Z, backward
+// Z -> X.  Workgroups without work return before any barrier.
+template <bool FWD>
+__global__ __launch_bounds__(256) void k_sweep_diag_b(const SolveJob *__restrict__ jobs, int k,
+                                                      int nb, int r) {
+  const SolveJob &j = jobs[blockIdx.y];
+  if (k >= j.nt) return;
+  const int64_t te = (int64_t)nb * nb, vb = (int64_t)nb * r;
+  sweep_diag_body<FWD>(j.Linv + k * te, (FWD ? j.B : j.Z) + k * vb, (FWD ? j.Z : j.X) + k * vb, nb,
+                       r, blockIdx.x);
+}
+
+template <bool FWD>
+__global__ __launch_bounds__(256) void k_sweep_panel_b(const SolveJob *__restrict__ jobs, int k,
+                                                       int nb, int r) {
+  const SolveJob &j = jobs[blockIdx.y];
+  const int per = (nb / 16) * ((r + 15) / 16);
+  const int t = (int)(blockIdx.x / per);
+  if (k >= j.nt || (FWD ? k + 1 + t >= j.nt : t >= k)) return;
+  const int64_t vb = (int64_t)nb * r;
+  sweep_panel_body<FWD>(j.Lst, (FWD ? j.Z : j.X) + k * vb, FWD ? j.B : j.Z, k, nb, r, blockIdx.x);
+}
+
+void launch_sweeps_batched(const SolveJob *jobs, int njobs, int ntmax, int nb, int r,
+                           hipStream_t s) {
+  const int per = (nb / 16) * ((r + 15) / 16);
+  for (int k = 0; k < ntmax; ++k) {
+    hipLaunchKernelGGL(k_sweep_diag_b<true>, dim3(per, njobs), dim3(256), 0, s, jobs, k, nb, r);
+    if (ntmax - 1 - k > 0)
+      hipLaunchKernelGGL(k_sweep_panel_b<true>, dim3((unsigned)((ntmax - 1 - k) * per), njobs),
+                         dim3(256), 0, s, jobs, k, nb, r);
+  }
+  for (int k = ntmax - 1; k >= 0; --k) {
+    hipLaunchKernelGGL(k_sweep_diag_b<false>, dim3(per, njobs), dim3(256), 0, s, jobs, k, nb, r);
+    if (k > 0)
+      hipLaunchKernelGGL(k_sweep_panel_b<false>, dim3((unsigned)(k * per), njobs), dim3(256), 0, s,
+                         jobs, k, nb, r);
   }
 }
 
@@ -226,12 +279,12 @@ constexpr int RES_HI_MAX = 2048;   // entries of the LDS table
 // FACT: exp(-gamma d) factored with W = 2^wshift; otherwise the FP64 table in
 // memory (one gather per entry).
 template <int NCB, bool FACT>
-__global__ __launch_bounds__(256) void k_residual(const int32_t *__restrict__ D,
-                                                  const double *__restrict__ etab,
-                                                  int64_t etab_len, double gamma, int wshift,
-                                                  int64_t np, int nb, int NT, int r,
-                                                  const double *__restrict__ X,
-                                                  double *__restrict__ part) {
+__device__ __forceinline__ void residual_body(const int32_t *__restrict__ D,
+                                              const double *__restrict__ etab, int64_t etab_len,
+                                              double gamma, int wshift, int64_t np, int nb, int NT,
+                                              int r, const double *__restrict__ X,
+                                              double *__restrict__ part, int64_t bx, int by,
+                                              int bz, int nz) {
   constexpr int XC = 16 * NCB, XLD = XC + 2, XPT = XC / 4;  // X values per thread and step
   __shared__ double ehi[RES_HI_MAX];
   __shared__ double xs[2][64 * XLD];
@@ -242,13 +295,13 @@ __global__ __launch_bounds__(256) void k_residual(const int32_t *__restrict__ D,
     const int nhi = (int)(dmax >> wshift) + 2;
     for (int q = tid; q < nhi; q += 256) ehi[q] = exp(-gamma * (double)((int64_t)q << wshift));
   }
-  const int64_t r0 = (int64_t)blockIdx.x * 64;  // first row of the workgroup
+  const int64_t r0 = bx * 64;  // first row of the workgroup
   const int I = (int)(r0 / nb), rloc = (int)(r0 % nb) + wave * 16;
-  const int col0 = blockIdx.y * XC;
+  const int col0 = by * XC;
   const int64_t te = (int64_t)nb * nb;
   // this workgroup's share of the columns: tiles J0 .. J1-1
-  const int J0 = (int)((int64_t)NT * blockIdx.z / gridDim.z);
-  const int J1 = (int)((int64_t)NT * (blockIdx.z + 1) / gridDim.z);
+  const int J0 = (int)((int64_t)NT * bz / nz);
+  const int J1 = (int)((int64_t)NT * (bz + 1) / nz);
   const int spt = nb / 64, st0 = J0 * spt, nsteps = J1 * spt;
 
   // branch-free (both orientations issue the same sixteen loads), so the
@@ -346,7 +399,7 @@ __global__ __launch_bounds__(256) void k_residual(const int32_t *__restrict__ D,
     if (st + 1 < nsteps) step(st + 1, db, da);
   }
   const int64_t g0 = r0 + wave * 16;
-  double *P = part + (int64_t)blockIdx.z * np * r;
+  double *P = part + (int64_t)bz * np * r;
 #pragma unroll
   for (int c = 0; c < NCB; ++c) {
     const int col = col0 + c * 16 + li;
@@ -354,6 +407,36 @@ __global__ __launch_bounds__(256) void k_residual(const int32_t *__restrict__ D,
 #pragma unroll
     for (int i = 0; i < 4; ++i) P[(g0 + 4 * i + lg) * r + col] = acc[c][i];
   }
+}
+
+template <int NCB, bool FACT>
+__global__ __launch_bounds__(256) void k_residual(const int32_t *__restrict__ D,
+                                                  const double *__restrict__ etab,
+                                                  int64_t etab_len, double gamma, int wshift,
+                                                  int64_t np, int nb, int NT, int r,
+                                                  const double *__restrict__ X,
+                                                  double *__restrict__ part) {
+  residual_body<NCB, FACT>(D, etab, etab_len, gamma, wshift, np, nb, NT, r, X, part, blockIdx.x,
+                           blockIdx.y, blockIdx.z, gridDim.z);
+}
+
+// All instances of a batch in one launch: blockIdx.x runs over the row
+// blocks of every instance (the job owning it found by its first block),
+// blockIdx.z over the column split, cut to the instance's own split.
+template <int NCB, bool FACT>
+__global__ __launch_bounds__(256) void k_residual_b(const SolveJob *__restrict__ jobs, int njobs,
+                                                    int nb, int r) {
+  int lo = 0, hi = njobs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (jobs[mid].rb0 <= (int64_t)blockIdx.x) lo = mid;
+    else hi = mid - 1;
+  }
+  const SolveJob &j = jobs[lo];
+  const int nz = j.nt < 4 ? j.nt : 4;
+  if ((int)blockIdx.z >= nz) return;
+  residual_body<NCB, FACT>(j.D, j.etab, j.etab_len, j.gamma, j.wshift, j.np, nb, j.nt, r, j.Xd,
+                           j.part, (int64_t)blockIdx.x - j.rb0, blockIdx.y, blockIdx.z, nz);
 }
 
 // R = Y - sum_z part[z] - lambda X, the partial products added in z order.
@@ -378,6 +461,35 @@ static int residual_wshift(double gamma, int64_t dmax) {
 }
 
 int residual_split(const TileLayout &L) { return std::min(4, L.nt); }
+int residual_exp_shift(double gamma, int64_t etab_len) {
+  return residual_wshift(gamma, etab_len - 1);
+}
+
+void launch_residual_batched(const SolveJob *jobs, int njobs, int64_t rblocks, bool fact, int nb,
+                             int r, hipStream_t s) {
+  const int ncb = (r + 15) / 16;
+  const dim3 grid((unsigned)rblocks, ncb <= 2 ? 1u : (unsigned)((r + 63) / 64), 4);
+#define KRR_RESB(NCB, FACT)                                                                    \
+  hipLaunchKernelGGL((k_residual_b<NCB, FACT>), grid, dim3(256), 0, s, jobs, njobs, nb, r)
+  if (fact) {
+    if (ncb <= 1) KRR_RESB(1, true);
+    else if (ncb <= 2) KRR_RESB(2, true);
+    else KRR_RESB(4, true);
+  } else {
+    if (ncb <= 1) KRR_RESB(1, false);
+    else if (ncb <= 2) KRR_RESB(2, false);
+    else KRR_RESB(4, false);
+  }
+#undef KRR_RESB
+}
+
+void launch_residual_sum(const double *part, int nsplit, const TileLayout &L, int r,
+                         double lambda, const double *X, const double *Y, double *R,
+                         hipStream_t s) {
+  const int64_t tot = L.np * r;
+  hipLaunchKernelGGL(k_residual_sum, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, part,
+                     nsplit, L.np, r, L.n, lambda, X, Y, R);
+}
 
 void launch_residual(const int32_t *D, const double *etab, int64_t etab_len, double gamma,
                      double lambda, const TileLayout &L, int r, const double *X, const double *Y,
