@@ -87,7 +87,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="single", choices=["single", "small", "batched"])
     ap.add_argument("--batch", type=int, default=48, help="instances of the batched workload")
-    ap.add_argument("--batch-streams", type=int, default=16,
+    ap.add_argument("--batch-streams", type=int, default=4,
                     help="streams (and hardware queues) of the batched workload")
     ap.add_argument("--n", type=int, default=0, help="override the number of patients")
     ap.add_argument("--plain-steps", type=int, default=1)

@@ -1114,41 +1114,21 @@ krr_status krr_factor_batched(krr_context ctx, int32_t batch, const krr_kernel *
   }
   const char *g_env = getenv("KRR_GROUP");
   const int g = std::max(1, std::min(KRR_MAX_GROUP, g_env ? atoi(g_env) : 4));
-  const int S = std::min<int>(batch, batch_stream_count());
-  CHK(context_batch_streams(ctx, S));
-  // instances to streams by their Cholesky cost; each stream runs its
-  // instances one after the other (tile Cholesky on one stream, in program
-  // order) and the streams run concurrently
-  std::vector<double> cost(batch);
-  for (int b = 0; b < batch; ++b) cost[b] = (double)K[b]->L.nt * K[b]->L.nt * K[b]->L.nt;
-  std::vector<int> order;
-  const std::vector<int> where = lpt_assign(cost, S, order);
-  std::vector<TileLayout> wl(S);  // workspace layout: the stream's largest instance
-  for (int b = 0; b < batch; ++b)
-    if (K[b]->L.nt > wl[where[b]].nt) wl[where[b]] = K[b]->L;
-  std::vector<FactorWork> W(S);
-  std::vector<std::pair<int32_t *, unsigned long long *>> own(S, {nullptr, nullptr});
+  const bool need16 = fp.allow16 || p.allow_promotion;
+  std::vector<FactorWork> W(batch);
   std::vector<krr_factorization> Fs(batch, nullptr);
   std::vector<uint8_t *> dmap(batch, nullptr);
   std::vector<int64_t> mapsz(batch, 0);
-  int32_t *flags = nullptr;
-  unsigned long long *counts = nullptr;
+  std::vector<int> nts(batch);
+  std::vector<FactorJob> jobs(batch);
+  FactorJob *djobs = nullptr;
   std::vector<int32_t> hflag(batch, 0);
   std::vector<unsigned long long> hc(3 * (size_t)batch, 0);
   krr_status st = KRR_SUCCESS;
   do {
-    if ((st = dalloc_t(ctx, &flags, batch)) != KRR_SUCCESS) break;
-    if ((st = dalloc_t(ctx, &counts, 3 * batch)) != KRR_SUCCESS) break;
-    for (int q = 0; q < S && st == KRR_SUCCESS; ++q) {
-      st = factor_work_alloc(ctx, W[q], wl[q], fp.allow16 || p.allow_promotion, fp.allow8,
-                             std::min(2 * g, 2 * KRR_MAX_GROUP));
-      own[q] = {W[q].flag, W[q].counts};
-    }
-    if (st != KRR_SUCCESS) break;
-    if ((st = batch_fence(ctx, s, S, false)) != KRR_SUCCESS) break;
-    for (int b : order) {
+    // memory: each instance its own factor storage, workspace and map
+    for (int b = 0; b < batch && st == KRR_SUCCESS; ++b) {
       const TileLayout &L = K[b]->L;
-      hipStream_t sq = ctx->bstreams[where[b]];
       krr_factorization F = Fs[b] = new krr_factor_s();
       F->ctx = ctx;
       F->K = K[b];
@@ -1162,25 +1142,70 @@ krr_status krr_factor_batched(krr_context ctx, int32_t batch, const krr_kernel *
         K[b]->A = nullptr;
       } else {
         if ((st = dalloc_t(ctx, &F->Lst, L.elems())) != KRR_SUCCESS) break;
-        launch_expand_tiles(K[b]->D, K[b]->etab, K[b]->etab_len, K[b]->lambda, L, F->Lst, sq);
+        launch_expand_tiles(K[b]->D, K[b]->etab, K[b]->etab_len, K[b]->lambda, L, F->Lst, s);
       }
       if ((st = dalloc_t(ctx, &F->Linv, (int64_t)L.nt * L.tile_elems())) != KRR_SUCCESS) break;
       mapsz[b] = (int64_t)L.nt * L.ntiles();
       if ((st = dalloc_t(ctx, &dmap[b], mapsz[b])) != KRR_SUCCESS) break;
-      FactorWork &w = W[where[b]];
-      w.flag = flags + b;
-      w.counts = counts + 3 * b;
-      if ((st = factor_enqueue(ctx, K[b], F, p, fp, w, dmap[b], mapsz[b], false, g, sq)) !=
-          KRR_SUCCESS)
+      if ((st = factor_work_alloc(ctx, W[b], L, need16, fp.allow8,
+                                  std::min(2 * g, KRR_SLOTS))) != KRR_SUCCESS)
         break;
+      nts[b] = L.nt;
+      launch_fill_i32(W[b].flag, 1, 0, s);
+      launch_fill_i32((int32_t *)W[b].counts, 6, 0, s);
+      launch_fill_u8(dmap[b], mapsz[b], 255, s);
+      FactorJob &j = jobs[b];
+      j = FactorJob{};
+      j.Lst = F->Lst;
+      j.Linv = F->Linv;
+      j.W = W[b].W64;
+      j.WL = W[b].WL64;
+      j.Dinv = W[b].Dinv64;
+      j.Winv = W[b].Winv64;
+      j.Tmp = W[b].Tmp64;
+      for (int q = 0; q < KRR_SLOTS; ++q) {
+        j.P32[q] = W[b].pb[q].P32;
+        j.P16[q] = W[b].pb[q].P16;
+        j.P8[q] = W[b].pb[q].P8;
+        j.pnorm[q] = W[b].pb[q].pnorm;
+        j.pexp8[q] = W[b].pb[q].pexp8;
+      }
+      j.pnorm_part = W[b].pnorm_part;
+      j.pmax_part = W[b].pmax_part;
+      j.flag = W[b].flag;
+      j.pmap = dmap[b];
+      j.ntiles = L.ntiles();
+      j.thr = p.eps * K[b]->norm_a / L.nt;
+      j.nt = L.nt;
     }
-    const krr_status sj = batch_fence(ctx, s, S, true);
-    if (st == KRR_SUCCESS) st = sj;
+    if (st != KRR_SUCCESS) break;
+    if ((st = dalloc_t(ctx, &djobs, batch)) != KRR_SUCCESS) break;
+    if (hipMemcpyAsync(djobs, jobs.data(), sizeof(FactorJob) * batch, hipMemcpyHostToDevice, s) !=
+        hipSuccess) {
+      st = KRR_ERROR_HIP;
+      break;
+    }
+    UpdatePolicy up;
+    up.mode = fp.mode;
+    up.allow16 = fp.allow16;
+    up.allow8 = fp.allow8;
+    up.high_panels = p.high_panels;
+    up.fixed_prec = p.fixed_prec;
+    up.thr = 0;  // per instance, from the table
+    {
+      Stage t(ctx, KRR_STAGE_POTRF, s);
+      launch_factor_lockstep(djobs, nts.data(), batch, ctx->opts.tile, g, up, fp.diag64,
+                             fp.allow16 != 0, fp.allow8 != 0, s);
+    }
+    for (int b = 0; b < batch; ++b) {
+      launch_count_pmap(dmap[b], mapsz[b], W[b].counts, s);
+      if (hipMemcpyAsync(&hflag[b], W[b].flag, 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+          hipMemcpyAsync(&hc[3 * b], W[b].counts, 24, hipMemcpyDeviceToHost, s) != hipSuccess)
+        st = KRR_ERROR_HIP;
+    }
     if (st == KRR_SUCCESS) st = launch_ok();
     if (st != KRR_SUCCESS) break;
-    if (hipMemcpyAsync(hflag.data(), flags, 4 * batch, hipMemcpyDeviceToHost, s) != hipSuccess ||
-        hipMemcpyAsync(hc.data(), counts, 24 * batch, hipMemcpyDeviceToHost, s) != hipSuccess ||
-        hipStreamSynchronize(s) != hipSuccess) {
+    if (hipStreamSynchronize(s) != hipSuccess) {
       st = KRR_ERROR_HIP;
       break;
     }
@@ -1194,16 +1219,11 @@ krr_status krr_factor_batched(krr_context ctx, int32_t batch, const krr_kernel *
     }
   } while (0);
   if (st != KRR_SUCCESS) (void)hipDeviceSynchronize();  // nothing left in flight
-  (void)hipStreamSynchronize(s);
-  for (int q = 0; q < S; ++q) {
-    W[q].flag = own[q].first;
-    W[q].counts = own[q].second;
-    factor_work_free(ctx, W[q], wl[q]);
-  }
-  for (int b = 0; b < batch; ++b)
+  for (int b = 0; b < batch; ++b) {
+    factor_work_free(ctx, W[b], K[b]->L);
     if (dmap[b]) dfree(ctx, dmap[b], mapsz[b]);
-  if (flags) dfree(ctx, flags, 4 * batch);
-  if (counts) dfree(ctx, counts, 24 * batch);
+  }
+  if (djobs) dfree(ctx, djobs, sizeof(FactorJob) * batch);
   // an instance that broke down is factored again on its own, with promotion
   for (int b = 0; b < batch && st == KRR_SUCCESS; ++b) {
     if (hflag[b] == 0) continue;

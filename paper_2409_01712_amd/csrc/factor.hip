@@ -219,9 +219,8 @@ __device__ __forceinline__ void diag64_store(const T (*S)[BS + 1], const T (*X)[
 
 // First diagonal block of the tile: W_00 -> L_00 (in WL) and inv(L_00).
 template <typename T>
-__global__ __launch_bounds__(256) void k_potrf_diag64(const T *__restrict__ W, T *__restrict__ WL,
-                                                      int nb, T *__restrict__ Dinv, int32_t *flag,
-                                                      int64_t colbase) {
+KRR_DEV void potrf_diag64_first(const T *__restrict__ W, T *__restrict__ WL, int nb,
+                                T *__restrict__ Dinv, int32_t *flag, int64_t colbase) {
   __shared__ T S[BS][BS + 1];  // the block, overwritten by L
   __shared__ T X[BS][BS + 1];  // inv(L)
   __shared__ T colv[16];       // current column of a 16 x 16 factor
@@ -241,6 +240,13 @@ __global__ __launch_bounds__(256) void k_potrf_diag64(const T *__restrict__ W, T
   __syncthreads();
   diag64_body<T>(S, X, colv, flag, colbase);
   diag64_store<T>(S, X, WL, nb, Dinv);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_potrf_diag64(const T *__restrict__ W, T *__restrict__ WL,
+                                                      int nb, T *__restrict__ Dinv, int32_t *flag,
+                                                      int64_t colbase) {
+  potrf_diag64_first<T>(W, WL, nb, Dinv, flag, colbase);
 }
 
 template <typename T, bool BT>
@@ -316,14 +322,13 @@ __device__ __forceinline__ void store_lds64(T (*dst)[BS + 1], const typename M16
 // diagonal step -- without writing it back.  Block column s of W is only
 // read in this step (the factor goes to WL), so the pairs need no ordering.
 template <typename T>
-__global__ __launch_bounds__(256) void k_potrf_step(T *__restrict__ W, T *__restrict__ WL, int nb,
-                                                    int s, T *__restrict__ Dinv, int32_t *flag,
-                                                    int64_t colbase) {
+KRR_DEV void potrf_step_body(T *__restrict__ W, T *__restrict__ WL, int nb, int s,
+                             T *__restrict__ Dinv, int32_t *flag, int64_t colbase, int bid) {
   typedef typename M16<T>::v4 v4;
   __shared__ T buf[3][BS][BS + 1];
   __shared__ T colv[16];
   int a, b;
-  tri_decode(blockIdx.x, a, b);
+  tri_decode(bid, a, b);
   a += s + 1;
   b += s + 1;
   T(*Xa)[BS + 1] = buf[0];
@@ -369,6 +374,13 @@ __global__ __launch_bounds__(256) void k_potrf_step(T *__restrict__ W, T *__rest
   }
 }
 
+template <typename T>
+__global__ __launch_bounds__(256) void k_potrf_step(T *__restrict__ W, T *__restrict__ WL, int nb,
+                                                    int s, T *__restrict__ Dinv, int32_t *flag,
+                                                    int64_t colbase) {
+  potrf_step_body<T>(W, WL, nb, s, Dinv, flag, colbase, blockIdx.x);
+}
+
 // Inverses of the diagonal tiles k0 .. k0+C-1 (tile c = blockIdx.y or
 // blockIdx.z / pairs) by recursive doubling: with the inverses of the
 // diagonal blocks of size b known,
@@ -391,15 +403,11 @@ __global__ void k_trtri_init(const T *__restrict__ Dinv, T *__restrict__ Winv, i
 // step 0: Tmp_p = L[(2p+1)b.., 2pb..] * Winv[2pb.., 2pb..]
 // step 1: Winv[(2p+1)b.., 2pb..] = -Winv[(2p+1)b.., (2p+1)b..] * Tmp_p
 template <typename T>
-__global__ __launch_bounds__(256) void k_trtri_level(const T *__restrict__ WLall,
-                                                     T *__restrict__ Winvc, T *__restrict__ Tmpc,
-                                                     int nb, int b, int step, int k0, int pairs) {
+KRR_DEV void trtri_level_body(const T *__restrict__ WL, T *__restrict__ Winv, T *__restrict__ Tmp,
+                              int nb, int b, int step, int64_t p, int rb, int cb) {
   __shared__ T As[BS][BS + 1];
   __shared__ T Bs[BS][BS + 1];
-  const int c = blockIdx.z / pairs;
-  const int64_t p = blockIdx.z % pairs, o = 2 * p * b, te = (int64_t)nb * nb;
-  const T *WL = WLall + (int64_t)(k0 + c) * te;
-  T *Winv = Winvc + (int64_t)c * te, *Tmp = Tmpc + (int64_t)c * (te / 2);
+  const int64_t o = 2 * p * b;
   const T *A;
   const T *B;
   T *C;
@@ -416,7 +424,6 @@ __global__ __launch_bounds__(256) void k_trtri_level(const T *__restrict__ WLall
     C = Winv + (o + b) * nb + o;     ldc = nb;
     alpha = (T)-1;
   }
-  const int rb = blockIdx.y, cb = blockIdx.x;
   typename M16<T>::v4 acc[4];
   zero4<T>(acc);
   for (int kk = 0; kk < b; kk += BS) {
@@ -427,6 +434,17 @@ __global__ __launch_bounds__(256) void k_trtri_level(const T *__restrict__ WLall
     __syncthreads();
   }
   store64<T, false>(C + (int64_t)(rb * BS) * ldc + cb * BS, ldc, acc, alpha);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_trtri_level(const T *__restrict__ WLall,
+                                                     T *__restrict__ Winvc, T *__restrict__ Tmpc,
+                                                     int nb, int b, int step, int k0, int pairs) {
+  const int c = blockIdx.z / pairs;
+  const int64_t te = (int64_t)nb * nb;
+  trtri_level_body<T>(WLall + (int64_t)(k0 + c) * te, Winvc + (int64_t)c * te,
+                      Tmpc + (int64_t)c * (te / 2), nb, b, step, blockIdx.z % pairs, blockIdx.y,
+                      blockIdx.x);
 }
 
 // Write L_kk (lower, zero above) into the factor storage and inv(L_kk), FP32.
@@ -481,19 +499,19 @@ void launch_tile_inverses(float *Lst, float *Linv, int k_lo, int k_hi, const Til
 typedef GemmShape<64, 64, 2, 2> DiagUpdShape;
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_potrf_load(const float *__restrict__ Akk, T *__restrict__ W,
-                                                    int nb, DiagUpdate du) {
+KRR_DEV void potrf_load_body(const float *__restrict__ Akk, T *__restrict__ W, int nb,
+                             const DiagUpdate &du, int bid) {
   typedef DiagUpdShape S;
   __shared__ __attribute__((aligned(16))) uint8_t lds[S::LDS_BYTES];
   int bi, bj;
-  tri_decode(blockIdx.x, bi, bj);
+  tri_decode(bid, bi, bj);
   OpF32::acc_t acc[S::WTM][S::WTN];
   zero_acc(acc);
   for (int q = 0; q < du.npan; ++q)
     gemm_nt_core<OpF32, S>(OpF32{}, (const uint8_t *)(du.P[q] + (int64_t)bi * 64 * nb),
                            (int64_t)nb * 4, 64, (const uint8_t *)(du.P[q] + (int64_t)bj * 64 * nb),
                            (int64_t)nb * 4, 64, (int64_t)nb * 4, acc, lds);
-  if (blockIdx.x == 0 && threadIdx.x < du.npan && du.pmap)
+  if (bid == 0 && threadIdx.x < du.npan && du.pmap)
     du.pmap[du.pmap_at[threadIdx.x]] = (uint8_t)KRR_PREC_FP32;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
@@ -506,6 +524,12 @@ __global__ __launch_bounds__(256) void k_potrf_load(const float *__restrict__ Ak
         const int64_t o = (int64_t)r * nb + c;
         W[o] = (c <= r) ? (T)Akk[o] - (T)acc[tm][tn][e] : (T)0;
       }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_potrf_load(const float *__restrict__ Akk, T *__restrict__ W,
+                                                    int nb, DiagUpdate du) {
+  potrf_load_body<T>(Akk, W, nb, du, blockIdx.x);
 }
 
 template <typename T>
@@ -547,20 +571,18 @@ void launch_potrf_tile(float *Akk, int k, const TileLayout &L, bool fp64, Factor
 constexpr int TRSM_ROWS = 16;
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_trsm_panel(const float *__restrict__ Astore,
-                                                    const T *__restrict__ WLk,
-                                                    const T *__restrict__ Dinvk, int k, int t_lo,
-                                                    int nb, int parts, float *__restrict__ P32,
-                                                    double *__restrict__ pnorm_part,
-                                                    float *__restrict__ pmax_part) {
+KRR_DEV void trsm_panel_body(const float *__restrict__ Astore, const T *__restrict__ WLk,
+                             const T *__restrict__ Dinvk, int k, int t_lo, int nb, int parts,
+                             float *__restrict__ P32, double *__restrict__ pnorm_part,
+                             float *__restrict__ pmax_part, int bid) {
   typedef typename M16<T>::v4 v4;
   __shared__ T Pr[TRSM_ROWS][512 + 1];
   __shared__ T Tb[TRSM_ROWS][BS + 1];
   __shared__ double shd[4];
   __shared__ float shf[4];
   const int RS = nb / TRSM_ROWS;
-  const int64_t t = t_lo + blockIdx.x / RS;
-  const int r0 = (blockIdx.x % RS) * TRSM_ROWS;
+  const int64_t t = t_lo + bid / RS;
+  const int r0 = (bid % RS) * TRSM_ROWS;
   const int64_t i = k + 1 + t, te = (int64_t)nb * nb;
   const float *A = Astore + (i * (i + 1) / 2 + k) * te + (int64_t)r0 * nb;
   float *Pout = P32 + t * te + (int64_t)r0 * nb;
@@ -612,14 +634,25 @@ __global__ __launch_bounds__(256) void k_trsm_panel(const float *__restrict__ As
   ss = block_sum<4>(ss, shd);
   mx = block_max<4>(mx, shf);
   if (threadIdx.x == 0) {
-    pnorm_part[t * parts + blockIdx.x % RS] = ss;
-    pmax_part[t * parts + blockIdx.x % RS] = mx;
+    pnorm_part[t * parts + bid % RS] = ss;
+    pmax_part[t * parts + bid % RS] = mx;
   }
   // a tile has `parts` slots; the ones past RS stay empty here
-  if (blockIdx.x % RS == 0 && threadIdx.x >= RS && threadIdx.x < parts) {
+  if (bid % RS == 0 && threadIdx.x >= RS && threadIdx.x < parts) {
     pnorm_part[t * parts + threadIdx.x] = 0.0;
     pmax_part[t * parts + threadIdx.x] = 0.0f;
   }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_trsm_panel(const float *__restrict__ Astore,
+                                                    const T *__restrict__ WLk,
+                                                    const T *__restrict__ Dinvk, int k, int t_lo,
+                                                    int nb, int parts, float *__restrict__ P32,
+                                                    double *__restrict__ pnorm_part,
+                                                    float *__restrict__ pmax_part) {
+  trsm_panel_body<T>(Astore, WLk, Dinvk, k, t_lo, nb, parts, P32, pnorm_part, pmax_part,
+                     blockIdx.x);
 }
 
 // Partial-norm slots per tile: the substitution TRSM fills nb/16 of them, the
@@ -651,18 +684,16 @@ void launch_trsm_subst(const float *Astore, int k, const TileLayout &L, bool fp6
 // each leaving its FP64 sum of squares and max |entry|.
 typedef GemmShape<64, 64, 2, 2> TrsmShape;
 
-__global__ __launch_bounds__(256) void k_trsm_gemm(const float *__restrict__ Astore,
-                                                   const float *__restrict__ Linv, int k, int t_lo,
-                                                   int nb, int parts, float *__restrict__ P32,
-                                                   double *__restrict__ pnorm_part,
-                                                   float *__restrict__ pmax_part) {
+KRR_DEV void trsm_gemm_body(const float *__restrict__ Astore, const float *__restrict__ Linv,
+                           int k, int t_lo, int nb, int parts, float *__restrict__ P32,
+                           double *__restrict__ pnorm_part, float *__restrict__ pmax_part,
+                           int64_t bid) {
   typedef TrsmShape S;
   constexpr int B = S::kBM;
   __shared__ __attribute__((aligned(16))) uint8_t lds[S::LDS_BYTES];
   __shared__ double shd[4];
   __shared__ float shf[4];
   const int SB = nb / B, nsub = SB * SB;
-  const int64_t bid = xcd_remap(blockIdx.x, gridDim.x);
   const int sub = (int)(bid % nsub);
   const int64_t t = t_lo + bid / nsub;
   const int64_t i = k + 1 + t;
@@ -704,6 +735,15 @@ __global__ __launch_bounds__(256) void k_trsm_gemm(const float *__restrict__ Ast
   }
 }
 
+__global__ __launch_bounds__(256) void k_trsm_gemm(const float *__restrict__ Astore,
+                                                   const float *__restrict__ Linv, int k, int t_lo,
+                                                   int nb, int parts, float *__restrict__ P32,
+                                                   double *__restrict__ pnorm_part,
+                                                   float *__restrict__ pmax_part) {
+  trsm_gemm_body(Astore, Linv, k, t_lo, nb, parts, P32, pnorm_part, pmax_part,
+                 xcd_remap(blockIdx.x, gridDim.x));
+}
+
 void launch_trsm_gemm(const float *Astore, const float *Linv_k, int k, const TileLayout &L,
                       FactorWork &w, const PanelBuf &pb, int t_lo, int t_hi, hipStream_t s) {
   t_hi = std::min(t_hi, L.nt - 1 - k);
@@ -719,13 +759,14 @@ void launch_trsm_gemm(const float *Astore, const float *Linv_k, int k, const Til
 // write the FP16 copy (unscaled) and the scaled FP8 E4M3 copy.
 constexpr int CONV_CHUNK = 4096;  // elements per workgroup
 
-__global__ __launch_bounds__(256) void k_convert_panel(
-    const float *__restrict__ P32, float *__restrict__ Astore, _Float16 *__restrict__ P16,
-    uint8_t *__restrict__ P8, const double *__restrict__ pnorm_part,
-    const float *__restrict__ pmax_part, int parts, float *__restrict__ pnorm,
-    int *__restrict__ pexp8, int k, int nb, int chunks, int need16, int need8) {
-  const int64_t t = blockIdx.x / chunks;
-  const int ch = blockIdx.x % chunks;
+KRR_DEV void convert_panel_body(const float *__restrict__ P32, float *__restrict__ Astore,
+                                _Float16 *__restrict__ P16, uint8_t *__restrict__ P8,
+                                const double *__restrict__ pnorm_part,
+                                const float *__restrict__ pmax_part, int parts,
+                                float *__restrict__ pnorm, int *__restrict__ pexp8, int k, int nb,
+                                int chunks, int need16, int need8, int64_t bid) {
+  const int64_t t = bid / chunks;
+  const int ch = (int)(bid % chunks);
   const int64_t i = k + 1 + t;
   double ss = 0.0;
   float mx = 0.0f;
@@ -757,6 +798,15 @@ __global__ __launch_bounds__(256) void k_convert_panel(
     pnorm[t] = (float)sqrt(ss);
     pexp8[t] = ilogbf(s8);  // s8 = 2^pexp8
   }
+}
+
+__global__ __launch_bounds__(256) void k_convert_panel(
+    const float *__restrict__ P32, float *__restrict__ Astore, _Float16 *__restrict__ P16,
+    uint8_t *__restrict__ P8, const double *__restrict__ pnorm_part,
+    const float *__restrict__ pmax_part, int parts, float *__restrict__ pnorm,
+    int *__restrict__ pexp8, int k, int nb, int chunks, int need16, int need8) {
+  convert_panel_body(P32, Astore, P16, P8, pnorm_part, pmax_part, parts, pnorm, pexp8, k, nb,
+                     chunks, need16, need8, blockIdx.x);
 }
 
 void launch_convert_panel(float *Astore, int k, const TileLayout &L, FactorWork &w,
@@ -838,10 +888,10 @@ struct SegSrc {
 // (lower sub-blocks only).  Otherwise the off-diagonal tiles, remapped so that
 // the sub-blocks of one tile share an XCD.
 template <class S, bool DIAG>
-__global__ __launch_bounds__(S::THREADS) void k_update(
-    float *__restrict__ Astore, PanelSet ps, int k0, int npan, int jlo, int jhi, int NT, int nb,
-    int SB, int mode, int allow16, int allow8, int high_panels, int fixed_prec, double thr,
-    uint8_t *__restrict__ pmap, int64_t ntiles_all) {
+KRR_DEV void update_body(float *__restrict__ Astore, const PanelSet &ps, int k0, int npan, int jlo,
+                         int jhi, int NT, int nb, int SB, int mode, int allow16, int allow8,
+                         int high_panels, int fixed_prec, double thr, uint8_t *__restrict__ pmap,
+                         int64_t ntiles_all, int64_t blk, int64_t nblk) {
   constexpr int BM = S::kBM;
   extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
   __shared__ SegTable tab;
@@ -849,11 +899,11 @@ __global__ __launch_bounds__(S::THREADS) void k_update(
   int si, sj;
   if constexpr (DIAG) {
     const int nsd = SB * (SB + 1) / 2;
-    i = j = jlo + blockIdx.x / nsd;
-    tri_decode(blockIdx.x % nsd, si, sj);
+    i = j = jlo + blk / nsd;
+    tri_decode(blk % nsd, si, sj);
   } else {
     const int nsub = SB * SB;
-    const int64_t bid = xcd_remap(blockIdx.x, gridDim.x);
+    const int64_t bid = xcd_remap(blk, nblk);
     const int sub = (int)(bid % nsub);
     int64_t tt = bid / nsub;
     si = sub / SB;
@@ -962,6 +1012,15 @@ __global__ __launch_bounds__(S::THREADS) void k_update(
       }
 }
 
+template <class S, bool DIAG>
+__global__ __launch_bounds__(S::THREADS) void k_update(
+    float *__restrict__ Astore, PanelSet ps, int k0, int npan, int jlo, int jhi, int NT, int nb,
+    int SB, int mode, int allow16, int allow8, int high_panels, int fixed_prec, double thr,
+    uint8_t *__restrict__ pmap, int64_t ntiles_all) {
+  update_body<S, DIAG>(Astore, ps, k0, npan, jlo, jhi, NT, nb, SB, mode, allow16, allow8,
+                       high_panels, fixed_prec, thr, pmap, ntiles_all, blockIdx.x, gridDim.x);
+}
+
 void launch_update(float *Astore, int k0, int npan, int jlo, int jhi, const TileLayout &L,
                    const UpdatePolicy &pol, FactorWork &w, const PanelBuf *const *pbs,
                    uint8_t *pmap, int which, hipStream_t s) {
@@ -1019,6 +1078,255 @@ void launch_update(float *Astore, int k0, int npan, int jlo, int jhi, const Tile
                        pol.mode, pol.allow16, pol.allow8, pol.high_panels, pol.fixed_prec, pol.thr,
                        pmap, L.ntiles());
   }
+}
+
+// ---------------------------------------------------------------------------
+// Lockstep batch: the kernels above behind a table of instances
+// (blockIdx.y = instance).  A workgroup with nothing to do for its instance
+// at this step returns before any barrier.
+KRR_DEV int slot_of(int k, int g) { return ((k / g) & 1) * g + k % g; }
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_potrf_load_b(const FactorJob *__restrict__ jobs, int k,
+                                                      int nb) {
+  const FactorJob &j = jobs[blockIdx.y];
+  if (k >= j.nt) return;
+  DiagUpdate du;
+  du.npan = 0;
+  du.pmap = nullptr;
+  potrf_load_body<T>(j.Lst + tri_index(k, k) * nb * nb, (T *)j.W, nb, du, blockIdx.x);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_potrf_diag64_b(const FactorJob *__restrict__ jobs, int k,
+                                                        int nb) {
+  const FactorJob &j = jobs[blockIdx.y];
+  if (k >= j.nt) return;
+  const int64_t te = (int64_t)nb * nb, db = (int64_t)(nb / BS) * BS * BS;
+  potrf_diag64_first<T>((const T *)j.W, (T *)j.WL + k * te, nb, (T *)j.Dinv + k * db, j.flag,
+                        (int64_t)k * nb);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_potrf_step_b(const FactorJob *__restrict__ jobs, int k,
+                                                      int st, int nb) {
+  const FactorJob &j = jobs[blockIdx.y];
+  if (k >= j.nt) return;
+  const int64_t te = (int64_t)nb * nb, db = (int64_t)(nb / BS) * BS * BS;
+  potrf_step_body<T>((T *)j.W, (T *)j.WL + k * te, nb, st, (T *)j.Dinv + k * db, j.flag,
+                     (int64_t)k * nb, blockIdx.x);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_trsm_panel_b(const FactorJob *__restrict__ jobs, int k,
+                                                      int nb, int parts, int g) {
+  const FactorJob &j = jobs[blockIdx.y];
+  const int RS = nb / TRSM_ROWS;
+  if (k + 1 >= j.nt || (int)(blockIdx.x / RS) >= j.nt - 1 - k) return;
+  const int64_t te = (int64_t)nb * nb, db = (int64_t)(nb / BS) * BS * BS;
+  trsm_panel_body<T>(j.Lst, (const T *)j.WL + k * te, (const T *)j.Dinv + k * db, k, 0, nb, parts,
+                     j.P32[slot_of(k, g)], j.pnorm_part, j.pmax_part, blockIdx.x);
+}
+
+__global__ __launch_bounds__(256) void k_convert_panel_b(const FactorJob *__restrict__ jobs, int k,
+                                                         int nb, int chunks, int parts, int need16,
+                                                         int need8, int g) {
+  const FactorJob &j = jobs[blockIdx.y];
+  if (k + 1 >= j.nt || (int64_t)(blockIdx.x / chunks) >= j.nt - 1 - k) return;
+  const int sl = slot_of(k, g);
+  convert_panel_body(j.P32[sl], j.Lst, j.P16[sl], j.P8[sl], j.pnorm_part, j.pmax_part, parts,
+                     j.pnorm[sl], j.pexp8[sl], k, nb, chunks, need16, need8, blockIdx.x);
+}
+
+// Tile inverse of diagonal tile k (and L_kk, inv(L_kk) into the factor
+// storage), then the panel as a product with it.
+template <typename T>
+__global__ void k_trtri_init_b(const FactorJob *__restrict__ jobs, int k, int nb) {
+  const FactorJob &j = jobs[blockIdx.y];
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= j.nt || e >= (int64_t)nb * nb) return;
+  const int NB = nb / BS;
+  const T *D = (const T *)j.Dinv + (int64_t)k * NB * BS * BS;
+  const int r = (int)(e / nb), q = (int)(e % nb);
+  ((T *)j.Winv)[e] = (r / BS == q / BS) ? D[(int64_t)(r / BS) * BS * BS + (r % BS) * BS + q % BS]
+                                        : (T)0;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_trtri_level_b(const FactorJob *__restrict__ jobs, int k,
+                                                       int nb, int b, int step, int pairs) {
+  const FactorJob &j = jobs[blockIdx.z / pairs];
+  if (k >= j.nt) return;
+  const int64_t te = (int64_t)nb * nb;
+  trtri_level_body<T>((const T *)j.WL + k * te, (T *)j.Winv, (T *)j.Tmp, nb, b, step,
+                      blockIdx.z % pairs, blockIdx.y, blockIdx.x);
+}
+
+template <typename T>
+__global__ void k_potrf_store_b(const FactorJob *__restrict__ jobs, int k, int nb) {
+  const FactorJob &j = jobs[blockIdx.y];
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= j.nt || e >= (int64_t)nb * nb) return;
+  const int64_t te = (int64_t)nb * nb;
+  const int r = (int)(e / nb), q = (int)(e % nb);
+  j.Lst[((int64_t)k * (k + 1) / 2 + k) * te + e] = (q <= r) ? (float)((const T *)j.WL)[k * te + e] : 0.0f;
+  j.Linv[k * te + e] = (q <= r) ? (float)((const T *)j.Winv)[e] : 0.0f;
+}
+
+__global__ __launch_bounds__(256) void k_trsm_gemm_b(const FactorJob *__restrict__ jobs, int k,
+                                                     int nb, int parts, int g) {
+  const FactorJob &j = jobs[blockIdx.y];
+  const int SB = nb / TrsmShape::kBM;
+  const int64_t nblk = (int64_t)(j.nt - 1 - k) * SB * SB;
+  if (k + 1 >= j.nt || (int64_t)blockIdx.x >= nblk) return;
+  trsm_gemm_body(j.Lst, j.Linv + (int64_t)k * nb * nb, k, 0, nb, parts, j.P32[slot_of(k, g)],
+                 j.pnorm_part, j.pmax_part, xcd_remap(blockIdx.x, nblk));
+}
+
+// The update of one instance: in-group (panel k0 onto the group's later
+// columns) or the group's update (panels G0 = k0 .. onto every column right
+// of the group), clipped to the instance's tile count.  Returns its block
+// count (0 when it has none) and its arguments.
+__host__ __device__ inline int64_t update_extent(int nt, int k0, bool group, int g, int SB, bool diag,
+                                          int &npan, int &jlo, int &jhi) {
+  if (!group) {
+    const int G0 = (k0 / g) * g;
+    npan = 1;
+    jlo = k0 + 1;
+    jhi = min(G0 + g, nt) - 1;
+    if (k0 >= nt) return 0;
+  } else {
+    npan = min(g, nt - k0);
+    jlo = min(k0 + g, nt);
+    jhi = nt - 1;
+    if (npan < 1) return 0;
+  }
+  if (jlo > jhi) return 0;
+  if (diag) return (int64_t)(jhi - jlo + 1) * SB * (SB + 1) / 2;
+  int64_t off = 0;
+  if (jhi == nt - 1) {
+    const int64_t T = nt - jlo;
+    off = T * (T - 1) / 2;
+  } else {
+    for (int jj = jlo; jj <= jhi; ++jj) off += nt - 1 - jj;
+  }
+  return off * SB * SB;
+}
+
+template <class S, bool DIAG>
+__global__ __launch_bounds__(S::THREADS) void k_update_b(const FactorJob *__restrict__ jobs, int k0,
+                                                         int group, int g, int nb, int SB,
+                                                         int mode, int allow16, int allow8,
+                                                         int high_panels, int fixed_prec) {
+  const FactorJob &j = jobs[blockIdx.y];
+  int npan, jlo, jhi;
+  const int64_t nblk = update_extent(j.nt, k0, group != 0, g, SB, DIAG, npan, jlo, jhi);
+  if ((int64_t)blockIdx.x >= nblk) return;
+  PanelSet ps;
+  for (int q = 0; q < npan; ++q) {
+    const int sl = slot_of(k0 + q, g);
+    ps.P32[q] = j.P32[sl];
+    ps.P16[q] = j.P16[sl];
+    ps.P8[q] = j.P8[sl];
+    ps.pnorm[q] = j.pnorm[sl];
+    ps.pexp8[q] = j.pexp8[sl];
+  }
+  update_body<S, DIAG>(j.Lst, ps, k0, npan, jlo, jhi, j.nt, nb, SB, mode, allow16, allow8,
+                       high_panels, fixed_prec, j.thr, j.pmap, j.ntiles, blockIdx.x, nblk);
+}
+
+template <typename T>
+static void factor_lockstep_t(const FactorJob *jobs, const int *nts, int nj, int nb, int g,
+                              const UpdatePolicy &pol, bool need16, bool need8, hipStream_t s) {
+  const int NB = nb / BS, parts = trsm_parts(nb);
+  const int chunks = (int)((int64_t)nb * nb / CONV_CHUNK);
+  int ntmax = 0;
+  for (int b = 0; b < nj; ++b) ntmax = std::max(ntmax, nts[b]);
+  static bool attr = false;
+  if (!attr) {
+    hipFuncSetAttribute((const void *)k_update_b<UpdStream, false>,
+                        hipFuncAttributeMaxDynamicSharedMemorySize, UpdStream::LDS_BYTES);
+    hipFuncSetAttribute((const void *)k_update_b<UpdDiagStream, true>,
+                        hipFuncAttributeMaxDynamicSharedMemorySize, UpdDiagStream::LDS_BYTES);
+    hipFuncSetAttribute((const void *)k_update_b<UpdDiagStream, false>,
+                        hipFuncAttributeMaxDynamicSharedMemorySize, UpdDiagStream::LDS_BYTES);
+    attr = true;
+  }
+  // updates as launch_update does them: diagonal tiles (128 x 128 blocks),
+  // then the off-diagonal ones, small blocks when the batch has few tiles
+  // in all (grids sized for the instance with the most)
+  auto update = [&](int k0, bool group) {
+    const int SBd = nb / UpdDiagStream::kBM, SBo = nb / UpdStream::kBM;
+    int64_t md = 0, mo = 0, so = 0, mo_small = 0;
+    int npan, jlo, jhi;
+    for (int b = 0; b < nj; ++b) {
+      md = std::max(md, update_extent(nts[b], k0, group, g, SBd, true, npan, jlo, jhi));
+      const int64_t off = update_extent(nts[b], k0, group, g, 1, false, npan, jlo, jhi);
+      mo = std::max(mo, off);
+      so += off;
+    }
+    if (md > 0)
+      hipLaunchKernelGGL((k_update_b<UpdDiagStream, true>), dim3((unsigned)md, nj),
+                         dim3(UpdDiagStream::THREADS), UpdDiagStream::LDS_BYTES, s, jobs, k0,
+                         group ? 1 : 0, g, nb, SBd, pol.mode, pol.allow16, pol.allow8,
+                         pol.high_panels, pol.fixed_prec);
+    if (mo <= 0) return;
+    if (so * 4 < 8 * 256) {
+      mo_small = mo * SBd * SBd;
+      hipLaunchKernelGGL((k_update_b<UpdDiagStream, false>), dim3((unsigned)mo_small, nj),
+                         dim3(UpdDiagStream::THREADS), UpdDiagStream::LDS_BYTES, s, jobs, k0,
+                         group ? 1 : 0, g, nb, SBd, pol.mode, pol.allow16, pol.allow8,
+                         pol.high_panels, pol.fixed_prec);
+    } else {
+      hipLaunchKernelGGL((k_update_b<UpdStream, false>), dim3((unsigned)(mo * SBo * SBo), nj),
+                         dim3(UpdStream::THREADS), UpdStream::LDS_BYTES, s, jobs, k0,
+                         group ? 1 : 0, g, nb, SBo, pol.mode, pol.allow16, pol.allow8,
+                         pol.high_panels, pol.fixed_prec);
+    }
+  };
+  for (int G0 = 0; G0 < ntmax; G0 += g) {
+    const int gend = std::min(G0 + g, ntmax);
+    for (int k = G0; k < gend; ++k) {
+      hipLaunchKernelGGL(k_potrf_load_b<T>, dim3(NB * (NB + 1) / 2, nj), dim3(256), 0, s, jobs, k,
+                         nb);
+      hipLaunchKernelGGL(k_potrf_diag64_b<T>, dim3(1, nj), dim3(256), 0, s, jobs, k, nb);
+      for (int st = 0; st + 1 < NB; ++st) {
+        const int rest = NB - 1 - st;
+        hipLaunchKernelGGL(k_potrf_step_b<T>, dim3(rest * (rest + 1) / 2, nj), dim3(256), 0, s,
+                           jobs, k, st, nb);
+      }
+      // inv(L_kk), then the panel as a product with it
+      const unsigned eb = (unsigned)(((int64_t)nb * nb + 255) / 256);
+      hipLaunchKernelGGL(k_trtri_init_b<T>, dim3(eb, nj), dim3(256), 0, s, jobs, k, nb);
+      for (int b = BS; b < nb; b *= 2) {
+        const unsigned nbk = (unsigned)(b / BS);
+        const int pairs = nb / (2 * b);
+        for (int step = 0; step < 2; ++step)
+          hipLaunchKernelGGL(k_trtri_level_b<T>, dim3(nbk, nbk, pairs * nj), dim3(256), 0, s, jobs,
+                             k, nb, b, step, pairs);
+      }
+      hipLaunchKernelGGL(k_potrf_store_b<T>, dim3(eb, nj), dim3(256), 0, s, jobs, k, nb);
+      if (k + 1 < ntmax) {
+        const int SBt = nb / TrsmShape::kBM;
+        hipLaunchKernelGGL(k_trsm_gemm_b, dim3((unsigned)((ntmax - 1 - k) * SBt * SBt), nj),
+                           dim3(256), 0, s, jobs, k, nb, parts, g);
+        hipLaunchKernelGGL(k_convert_panel_b, dim3((unsigned)((int64_t)(ntmax - 1 - k) * chunks), nj),
+                           dim3(256), 0, s, jobs, k, nb, chunks, parts, need16 ? 1 : 0,
+                           need8 ? 1 : 0, g);
+      }
+      update(k, false);
+    }
+    update(G0, true);
+  }
+}
+
+void launch_factor_lockstep(const FactorJob *jobs, const int *nts, int njobs, int nb, int g,
+                            const UpdatePolicy &pol, bool fp64, bool need16, bool need8,
+                            hipStream_t s) {
+  if (fp64)
+    factor_lockstep_t<double>(jobs, nts, njobs, nb, g, pol, need16, need8, s);
+  else
+    factor_lockstep_t<float>(jobs, nts, njobs, nb, g, pol, need16, need8, s);
 }
 
 // Updates per operand precision, from the precision map (255 = no update).

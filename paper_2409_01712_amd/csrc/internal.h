@@ -127,6 +127,36 @@ struct DiagUpdate {
   uint8_t *pmap;
   int npan;
 };
+constexpr int KRR_SLOTS = 2 * KRR_MAX_GROUP;  // panel buffers of a workspace
+// One instance of a lockstep batched factorization (device table): its
+// factor storage, its workspace (diagonal tiles in the factorization's
+// type, FP64 or FP32) and panel buffers, and its precision threshold.
+struct FactorJob {
+  float *Lst, *Linv;
+  void *W, *WL, *Dinv, *Winv, *Tmp;
+  float *P32[KRR_SLOTS];
+  _Float16 *P16[KRR_SLOTS];
+  uint8_t *P8[KRR_SLOTS];
+  float *pnorm[KRR_SLOTS];
+  int *pexp8[KRR_SLOTS];
+  double *pnorm_part;
+  float *pmax_part;
+  int32_t *flag;
+  uint8_t *pmap;
+  int64_t ntiles;
+  double thr;  // eps * ||A||_F / nt
+  int nt;
+};
+// The single-stream tile Cholesky (substitution TRSM, grouped updates of g
+// panels, panel k in buffer ((k / g) % 2) g + k % g) of njobs instances in
+// lockstep: every POTRF step, TRSM, conversion and update is one launch for
+// all instances that have that step; the panel is solved as a product with
+// the tile inverse, formed right after the tile's factor (L_kk and its
+// inverse stored as krr_factor stores them).  nts: host copy of the tile
+// counts; pol.thr is taken per instance from the table.
+void launch_factor_lockstep(const FactorJob *jobs, const int *nts, int njobs, int nb, int g,
+                            const UpdatePolicy &pol, bool fp64, bool need16, bool need8,
+                            hipStream_t s);
 // Diagonal tile k: L_kk = chol(A_kk - sum_q P_q P_q^T) into the work's
 // factor store (tile k), with the inverses of its 64 x 64 diagonal blocks.
 void launch_potrf_tile(float *Akk, int k, const TileLayout &L, bool fp64, FactorWork &w,
