@@ -87,8 +87,6 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="single", choices=["single", "small", "batched"])
     ap.add_argument("--batch", type=int, default=48, help="instances of the batched workload")
-    ap.add_argument("--batch-streams", type=int, default=4,
-                    help="streams (and hardware queues) of the batched workload")
     ap.add_argument("--n", type=int, default=0, help="override the number of patients")
     ap.add_argument("--plain-steps", type=int, default=1)
     ap.add_argument("--no-plain", action="store_true")
@@ -109,9 +107,6 @@ def main():
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
-    if args.workload == "batched":  # before anything starts the HIP runtime
-        os.environ["GPU_MAX_HW_QUEUES"] = str(max(4, args.batch_streams))
-        os.environ["KRR_BATCH_STREAMS"] = str(args.batch_streams)
 
     import numpy as np
     import torch
@@ -267,9 +262,8 @@ def main():
 
 def main_batched(args):
     """Many independent instances (uneven n, differing gamma and lambda, one SNP panel)
-    through the batched calls: one step = batched build + factor + solve of all of them.
-    The instances' factorizations and solves run on --batch-streams streams, each on a
-    hardware queue of its own (GPU_MAX_HW_QUEUES is raised to match before HIP starts)."""
+    through the batched calls: one step = batched build + factor + solve of all of them,
+    each stage one launch per step for all instances."""
     import numpy as np
     import torch
 

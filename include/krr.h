@@ -206,20 +206,21 @@ krr_status krr_build_kernel_batched(krr_context ctx, int32_t batch, const int8_t
                                     const int64_t *n, int64_t m, const int64_t *ldg,
                                     const double *gamma, const double *lambda, krr_kernel *out);
 /* Factorization of `batch` distinct kernels under one policy (NULL =
- * ADAPTIVE defaults).  Instances are spread over 4 streams by their
- * Cholesky cost (longest first to the least loaded stream; the environment
- * variable KRR_BATCH_STREAMS, 1 to 16, changes the count of 4 -- useful with
- * GPU_MAX_HW_QUEUES raised to match, so that the streams run concurrently on
- * separate hardware queues); each stream
- * factors its instances in turn with one workspace sized for its largest.
+ * ADAPTIVE defaults), in lockstep on the context stream: every POTRF step,
+ * tile-inverse level, TRSM, operand conversion and trailing update is one
+ * launch for all instances that have it (instances differ in tile count; the
+ * schedule is the single-stream one of krr_factor, with the panel solved as
+ * a product with the tile inverse).  Each instance gets its own workspace.
  * An instance that breaks down is then factored again on its own with
  * promotion, exactly as krr_factor does.  Blocks until all are done. */
 krr_status krr_factor_batched(krr_context ctx, int32_t batch, const krr_kernel *K,
                               const krr_precision_policy *policy, krr_factorization *out);
 /* Solve of `batch` factorizations with nrhs right-hand sides each: Y[b],
- * X[b] are n_b x nrhs FP64 column-major (ldy[b], ldx[b] >= n_b).  The
- * refinement of every instance advances together: one host wait per
- * iteration for the whole batch.  info (NULL or `batch` entries) reports
+ * X[b] are n_b x nrhs FP64 column-major (ldy[b], ldx[b] >= n_b).  In
+ * lockstep on the context stream: each sweep step is one launch for all
+ * instances, each refinement pass one FP64 residual launch for the
+ * instances not yet converged, and one host wait per pass for the whole
+ * batch.  info (NULL or `batch` entries) reports
  * each instance; KRR_ERROR_NOT_CONVERGED if any instance missed the
  * tolerance (its X holds the last iterate). */
 krr_status krr_solve_batched(krr_context ctx, int32_t batch, const krr_factorization *F,

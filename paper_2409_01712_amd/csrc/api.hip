@@ -42,8 +42,6 @@ struct krr_context_s {
   // second stream and events for the factorization's lookahead
   hipStream_t aux = nullptr, side = nullptr, fmain = nullptr;
   std::vector<hipEvent_t> sched_ev;  // ordering events of the factorization schedule
-  std::vector<hipStream_t> bstreams;  // streams of the batched calls
-  std::vector<hipEvent_t> bevents;    // their ordering events
 };
 
 struct krr_kernel_s {
@@ -334,11 +332,6 @@ static void context_free(krr_context ctx) {
     }
   }
   for (hipEvent_t e : ctx->sched_ev) (void)hipEventDestroy(e);
-  for (hipStream_t x : ctx->bstreams) {
-    (void)hipStreamSynchronize(x);
-    (void)hipStreamDestroy(x);
-  }
-  for (hipEvent_t e : ctx->bevents) (void)hipEventDestroy(e);
   delete ctx;
 }
 
@@ -348,66 +341,6 @@ static krr_status context_aux(krr_context ctx) {
   for (hipStream_t *x : {&ctx->fmain, &ctx->side, &ctx->aux})
     if (!*x) HIPCHK(hipStreamCreateWithFlags(x, hipStreamNonBlocking));
   return KRR_SUCCESS;
-}
-
-// Streams for the instances of a batched call (default priority): by default
-// as many as the HIP runtime gives a process hardware queues (4), so that they
-// run concurrently; KRR_BATCH_STREAMS (1 .. 16) sets another count, for a
-// process that raised GPU_MAX_HW_QUEUES to match.
-static int batch_stream_count() {
-  static const int n = [] {
-    const char *e = getenv("KRR_BATCH_STREAMS");
-    const int v = e ? atoi(e) : 4;
-    return std::max(1, std::min(16, v));
-  }();
-  return n;
-}
-static krr_status context_batch_streams(krr_context ctx, int count) {
-  while ((int)ctx->bstreams.size() < count) {
-    hipStream_t x = nullptr;
-    HIPCHK(hipStreamCreateWithFlags(&x, hipStreamNonBlocking));
-    ctx->bstreams.push_back(x);
-  }
-  return KRR_SUCCESS;
-}
-
-// Orders work on the batch streams 0 .. count-1 after what is already on
-// `from` (join = false), or work on `from` after everything on them (join = true).
-static krr_status batch_fence(krr_context ctx, hipStream_t from, int count, bool join) {
-  std::vector<hipEvent_t> &ev = ctx->bevents;
-  while ((int)ev.size() < count) {
-    hipEvent_t e = nullptr;
-    HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-    ev.push_back(e);
-  }
-  if (!join) {
-    HIPCHK(hipEventRecord(ev[0], from));
-    for (int q = 0; q < count; ++q) HIPCHK(hipStreamWaitEvent(ctx->bstreams[q], ev[0], 0));
-  } else {
-    for (int q = 0; q < count; ++q) {
-      HIPCHK(hipEventRecord(ev[q], ctx->bstreams[q]));
-      HIPCHK(hipStreamWaitEvent(from, ev[q], 0));
-    }
-  }
-  return KRR_SUCCESS;
-}
-
-// Longest-processing-time assignment of instances to `count` streams:
-// instances in decreasing cost, each to the least loaded stream.
-static std::vector<int> lpt_assign(const std::vector<double> &cost, int count,
-                                   std::vector<int> &order) {
-  const int B = (int)cost.size();
-  order.resize(B);
-  for (int b = 0; b < B; ++b) order[b] = b;
-  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cost[a] > cost[b]; });
-  std::vector<double> load(count, 0.0);
-  std::vector<int> where(B, 0);
-  for (int b : order) {
-    const int q = (int)(std::min_element(load.begin(), load.end()) - load.begin());
-    where[b] = q;
-    load[q] += cost[b];
-  }
-  return where;
 }
 
 // A handle was released: free the context if it was destroyed while handles lived.
