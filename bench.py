@@ -217,7 +217,21 @@ def main():
         "avg_launch_ms": gram_avg_s * 1e3,
     }
     u_ms, u_cnt = stages["update"]
-    out["update_stage"] = {"ms_per_step": u_ms / args.steps, "launches_per_step": u_cnt / args.steps}
+    # trailing-update MFMA utilisation: algorithmic flops per precision (off-diagonal tile
+    # update 2 nb^3; a diagonal tile's lower triangle nb^2 (nb + 1), always FP32) against the
+    # time at each precision's dense peak, over the update kernels' summed time
+    nb = args.tile
+    NT = (n + nb - 1) // nb
+    ndiag = NT * (NT - 1) // 2
+    f_off, f_diag = 2.0 * nb ** 3, float(nb) * nb * (nb + 1)
+    u32, u16, u8 = (int(finfo.updates[q]) for q in range(3))
+    fl = {"fp32": (u32 - ndiag) * f_off + ndiag * f_diag, "fp16": u16 * f_off, "fp8": u8 * f_off}
+    ideal_s = (fl["fp32"] / (PEAK["fp32_TFLOPs"] * 1e12) + fl["fp16"] / (PEAK["fp16_TFLOPs"] * 1e12)
+               + fl["fp8"] / (PEAK["fp8_TFLOPs"] * 1e12))
+    u_s = u_ms / args.steps / 1e3
+    out["update_stage"] = {"ms_per_step": u_ms / args.steps, "launches_per_step": u_cnt / args.steps,
+                           "flops": fl, "achieved_TFLOPs": sum(fl.values()) / u_s / 1e12,
+                           "time_at_peak_ms": ideal_s * 1e3, "mfma_frac": ideal_s / u_s}
 
     if not args.no_plain:
         for i in range(args.warmup):
