@@ -430,3 +430,58 @@ def test_residual_bound_matches_oracle(ctx, gamma_scale):
     bound = np.max(np.linalg.norm(R, axis=0) / (lam * np.linalg.norm(Xh, axis=0)))
     assert info.first_bound > 0
     np.testing.assert_allclose(info.fwd_err_bound, bound, rtol=1e-8)
+
+
+def test_batched_edge_sizes():
+    """A batch of one, a one-patient instance, and sizes either side of a tile."""
+    m = 200
+    ns = [1, 255, 256, 257, 513]
+    Gall = _gen(sum(ns), m, seed=31)
+    offs = np.cumsum([0] + ns)
+    Gs = [np.ascontiguousarray(Gall[offs[b]:offs[b + 1]]) for b in range(len(ns))]
+    gammas = [1.0 / m] * len(ns)
+    lams = [0.1] * len(ns)
+    Ys = [synth.phenotypes(G, 2, n_pairs=5, n_add=2, seed=40 + b, h2=0.5) if len(G) > 1
+          else np.array([[0.7, -0.3]]) for b, G in enumerate(Gs)]
+    c = krr.krr_create(0, tile=256)
+    for sel in ([3], list(range(len(ns)))):
+        Ks = krr.krr_build_kernel_batched(c, [_dev(Gs[b]) for b in sel], [gammas[b] for b in sel],
+                                          [lams[b] for b in sel])
+        Fs = krr.krr_factor_batched(c, Ks)
+        Xs, infos, st = krr.krr_solve_batched(c, Fs, [_dev(Ys[b]) for b in sel],
+                                              krr.Refine(tol=1e-8))
+        for q, b in enumerate(sel):
+            n = ns[b]
+            d = krr.krr_kernel_copy_distances(Ks[q], 0, 0, n, n).cpu().numpy().astype(np.int64)
+            assert np.array_equal(d, oracle.sqdist(Gs[b]))
+            assert infos[q].converged == 1
+            Wo = oracle.fit(Gs[b], Ys[b], gammas[b], lams[b])
+            assert _colrel(Xs[q].cpu().numpy(), Wo) <= TOL, (b, n)
+
+
+def test_batched_singular_instance_fails_the_batch():
+    """Identical rows and lambda = 0 in one instance: the factorization breaks down, promotion
+    cannot cure it, and the batched call returns no handles."""
+    Gs, gammas, lams, _ = _batch_instances()
+    Gs[1] = np.ones((300, Gs[0].shape[1]), np.int8)
+    lams[1] = 0.0
+    c = krr.krr_create(0, tile=256)
+    Ks = krr.krr_build_kernel_batched(c, [_dev(G) for G in Gs], gammas, lams)
+    with pytest.raises(krr.KRRError) as e:
+        krr.krr_factor_batched(c, Ks)
+    assert e.value.status == krr.KRR_ERROR_NOT_POSITIVE_DEFINITE
+
+
+def test_single_stream_factorization(monkeypatch):
+    """The factorization without lookahead (one stream, substitution TRSM, tile inverses at the
+    end) reaches the same refined X."""
+    monkeypatch.setenv("KRR_NO_LOOKAHEAD", "1")
+    w = synth.WORKLOADS["small"]
+    G = w.genotypes(rows=1300)
+    Y = w.phenotypes(G)
+    Wo = oracle.fit(G, Y, w.gamma, w.lam)
+    c = krr.krr_create(0, tile=256)
+    K = krr.krr_build_kernel(c, _dev(G), w.gamma, w.lam)
+    X, info, st = krr.krr_solve(c, krr.krr_factor(c, K), _dev(Y), krr.Refine(tol=1e-8))
+    assert info.converged == 1
+    assert _colrel(X.cpu().numpy(), Wo) <= TOL
