@@ -833,7 +833,7 @@ static krr_status factor_enqueue(krr_context ctx, krr_kernel K, krr_factorizatio
     hipStream_t sm = ctx->fmain, sd = ctx->side, sx = ctx->aux;
     const int ngroups = (NT + g - 1) / g;
     std::vector<hipEvent_t> &E = ctx->sched_ev;
-    const size_t need = (size_t)3 * NT + 2 * ngroups + 4;
+    const size_t need = (size_t)4 * NT + 2 * ngroups + 4;
     bool ok = true;
     while (ok && E.size() < need) {
       hipEvent_t e;
@@ -841,7 +841,8 @@ static krr_status factor_enqueue(krr_context ctx, krr_kernel K, krr_factorizatio
       if (ok) E.push_back(e);
     }
     hipEvent_t *e_t1 = E.data(), *e_conv = e_t1 + NT, *e_uin = e_conv + NT,
-               *e_aux = e_uin + NT, *e_narrow = e_aux + ngroups, *e_join = e_narrow + ngroups;
+               *e_udiag = e_uin + NT, *e_aux = e_udiag + NT, *e_narrow = e_aux + ngroups,
+               *e_join = e_narrow + ngroups;
     auto rec = [&](hipEvent_t e, hipStream_t st) {
       ok = ok && hipEventRecord(e, st) == hipSuccess;
     };
@@ -857,7 +858,9 @@ static krr_status factor_enqueue(krr_context ctx, krr_kernel K, krr_factorizatio
       const int gi = G0 / g, gend = std::min(G0 + g, NT), nend = std::min(gend + g, NT);
       for (int k = G0; k < gend; ++k) {
         // tile (k, k) still lacks panel k-1 (inside the group) or the
-        // whole previous group (at its start)
+        // whole previous group (at its start); the earlier panels of the
+        // group reached it through the side stream's diagonal updates
+        if (k >= G0 + 2) wait(sm, e_udiag[k - 2]);
         if (k > G0) potrf(k, k - 1, 1, sm);
         else potrf(k, std::max(G0 - g, 0), G0 > 0 ? g : 0, sm);
         if (k + 1 >= NT) break;
@@ -871,9 +874,13 @@ static krr_status factor_enqueue(krr_context ctx, krr_kernel K, krr_factorizatio
         trsm_gemm(k, 1, NT, sd);
         convert(k, sd);
         rec(e_conv[k], sd);
-        update(k, 1, k + 1, gend - 1, UPD_OFFDIAG, sd);
-        update(k, 1, k + 2, gend - 1, UPD_DIAG, sd);
+        // column k+1 below the diagonal gets every panel of the group so far
+        // in one product (the later columns wait for their turn), which is
+        // all the next TRSM needs; then the diagonal tiles further right
+        if (k + 1 < gend) update(G0, k - G0 + 1, k + 1, k + 1, UPD_OFFDIAG, sd);
         rec(e_uin[k], sd);
+        update(k, 1, k + 2, gend - 1, UPD_DIAG, sd);
+        rec(e_udiag[k], sd);
       }
       if (gend >= NT) break;
       const int npan = gend - G0;
