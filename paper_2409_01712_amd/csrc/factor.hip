@@ -3,9 +3,12 @@
 // "Deploying a Four-Precision Cholesky-Based Solver").
 //
 // Right-looking over panels k = 0 .. NT-1:
-//   POTRF   L_kk = chol(A_kk) in FP64 (or FP32 on the plain path), with
-//           L_kk^{-1} formed alongside;
-//   TRSM    L_ik = A_ik L_kk^{-T} as an FP32 MFMA product with L_kk^{-1};
+//   POTRF   L_kk = chol(A_kk) in FP64 (or FP32 on the plain path) by 64-column
+//           steps, with the inverses of its 64 x 64 diagonal blocks, and
+//           L_kk^{-1} formed from them;
+//   TRSM    L_ik = A_ik L_kk^{-T}: by block substitution with L_kk (the row
+//           tile on the critical path) or as an FP32 MFMA product with
+//           L_kk^{-1} (the rest);
 //   convert L_ik to FP16 / FP8 E4M3 copies with a per-tile power-of-two
 //           scale (produced once per panel, consumed by every update);
 //   update  A_ij -= L_ik L_jk^T for k < j <= i: FP32 on diagonal tiles and
@@ -822,10 +825,11 @@ void launch_convert_panel(float *Astore, int k, const TileLayout &L, FactorWork 
 
 // Trailing update by a group of consecutive panels k0 .. k0+npan-1:
 //   A_ij -= sum_k L_ik L_jk^T   for the tiles (i, j), jlo <= j <= jhi, j <= i < NT,
-// one 128 x 128 block per workgroup, FP32 accumulation over all panels of
-// the group (the FP32 block of C is read and written once per group).  The
-// operand precision is chosen per (tile, panel), uniform across the
-// workgroup:
+// one 256 x 256 (off-diagonal) or 128 x 128 (diagonal tiles, short column
+// ranges) block per workgroup, FP32 accumulation over all panels of the
+// group, added into C with one atomic FP32 add per element (so C is not read
+// by the workgroup, and each element gets one add per launch).  The operand
+// precision is chosen per (tile, panel), uniform across the workgroup:
 //   FP32 on diagonal tiles, on panels k < high_panels and under the FP32 policy;
 //   FIXED: fixed_prec; ADAPTIVE: lowest allowed p with
 //   u_p ||L_ik||_F ||L_jk||_F <= thr (= eps ||A||_F / NT).
