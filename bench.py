@@ -91,7 +91,7 @@ def parse():
     ap.add_argument("--plain-steps", type=int, default=1)
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=2048, help="patients in the oracle sample")
+    ap.add_argument("--cpu-sample", type=int, default=3072, help="patients in the oracle sample")
     ap.add_argument("--eps", type=float, default=1.0)
     ap.add_argument("--high-panels", type=int, default=1)
     ap.add_argument("--tile", type=int, default=512)
