@@ -6,6 +6,8 @@ error of the weights X and predictions P per phenotype column, after FP64
 refinement; the FP32 kernel matrix within 1 FP32 ulp of the FP64 value; the
 FP32 Cholesky factor within FP32 backward error.
 """
+import os
+
 import numpy as np
 import pytest
 
@@ -523,3 +525,51 @@ def test_full_size_batched_workload_sampled():
         rows = np.sort(rng.choice(ns[b], 8, replace=False))
         R = oracle.residual_rows(Gs[b], gammas[b], lams[b], Xh, Ys[b], rows)
         assert np.all(np.linalg.norm(R, axis=0) <= lams[b] * tol * np.linalg.norm(Xh, axis=0)), b
+
+
+# --- the two largest workloads (opt-in: minutes of host-side input generation) -------------
+
+_LARGE = pytest.mark.skipif(os.environ.get("KRR_LARGE_TESTS") != "1",
+                            reason="largest workloads: set KRR_LARGE_TESTS=1 (tens of GB of "
+                                   "generated input, minutes of host time)")
+
+
+def _large_check(name, predict=False):
+    w = synth.WORKLOADS[name]
+    G = w.genotypes()
+    Y = w.phenotypes(G)
+    n = w.n
+    c = krr.krr_create(0, tile=512)
+    K = krr.krr_build_kernel(c, _dev(G), w.gamma, w.lam)
+    rng = np.random.default_rng(5)
+    for _ in range(3):
+        i0, j0 = int(rng.integers(0, n - 64)), int(rng.integers(0, n - 64))
+        d = krr.krr_kernel_copy_distances(K, i0, j0, 64, 64).cpu().numpy().astype(np.int64)
+        assert np.array_equal(d, oracle.sqdist(G[i0:i0 + 64], G[j0:j0 + 64]))
+    F = krr.krr_factor(c, K)
+    tol = 9.9e-6
+    X, info, st = krr.krr_solve(c, F, _dev(Y), krr.Refine(max_iters=30, tol=tol))
+    assert info.converged == 1 and info.fwd_err_bound <= 1e-5
+    Xh = X.cpu().numpy()
+    rows = np.sort(rng.choice(n, 8, replace=False))
+    R = oracle.residual_rows(G, w.gamma, w.lam, Xh, Y, rows)
+    assert np.all(np.linalg.norm(R, axis=0) <= w.lam * tol * np.linalg.norm(Xh, axis=0))
+    if predict:
+        T = w.test_genotypes()
+        P = krr.krr_predict(c, K, _dev(T), X).cpu().numpy()
+        trows = np.sort(rng.choice(len(T), 8, replace=False))
+        Po = oracle.predict(G, T[trows], Xh, w.gamma)
+        assert _colrel(P[trows], Po) <= 1e-12
+
+
+@_LARGE
+def test_large_workload_sampled():
+    """n = 131072, m = 262144 (5% of SNPs in linkage blocks), r = 64, lambda = 0.05."""
+    _large_check("large")
+
+
+@_LARGE
+def test_trainpredict_workload_sampled():
+    """n = 200000, m = 100000 (MAF ~ Beta(0.5, 2)), r = 128, then Predict for 20000 test
+    patients: sampled predictions with the library's weights against the oracle's."""
+    _large_check("trainpredict", predict=True)
