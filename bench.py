@@ -8,7 +8,11 @@ and FP64 iterative refinement until a rigorous bound guarantees 1e-5
 relative error against the exact solution.
 
 Op count per step (the paper's complexity figures for Build and the
-Cholesky, plus the solves): n^2 m + n^3 / 3 + 2 n^2 r.
+Cholesky, plus the solves): n^2 m + n^3 / 3 + 2 n^2 r; a train+predict
+workload adds Predict for its test patients, 2 n_test n (m + r).
+
+--workload selects the input: single (the default benchmark), small,
+large, trainpredict, or batched (48 instances through the batched calls).
 
 Prints ONE JSON line (rank 0).  The same ops are timed on the plain FP32 GPU
 path (FP32 diagonal POTRF and updates, FP32 solves, no refinement) for the
@@ -85,7 +89,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="single", choices=["single", "small", "batched"])
+    ap.add_argument("--workload", default="single",
+                    choices=["single", "small", "batched", "large", "trainpredict"])
     ap.add_argument("--batch", type=int, default=48, help="instances of the batched workload")
     ap.add_argument("--n", type=int, default=0, help="override the number of patients")
     ap.add_argument("--plain-steps", type=int, default=1)
@@ -135,6 +140,9 @@ def main():
     dev = torch.device("cuda:0")
     G = torch.from_numpy(Gh).to(dev)
     Y = torch.from_numpy(Yh).to(dev)
+    # a train+predict workload also predicts for its test patients in every step
+    n_test = w.n_test if not args.n else 0
+    T = torch.from_numpy(w.test_genotypes()).to(dev) if n_test else None
     torch.cuda.synchronize()
     log = (lambda *a: print(*a, file=sys.stderr, flush=True)) if args.verbose else (lambda *a: None)
     log("inputs: n=%d m=%d r=%d generated in %.1fs" % (n, m, r, gen_s))
@@ -153,6 +161,8 @@ def main():
         K = krr.krr_build_kernel(ctx, G, w.gamma, w.lam)
         F = krr.krr_factor(ctx, K, policy)
         X, info, st = krr.krr_solve(ctx, F, Y, ref, check=False)
+        if T is not None:
+            krr.krr_predict(ctx, K, T, X)
         finfo = krr.krr_factor_get_info(F)
         F.release()
         K.release()
@@ -174,7 +184,8 @@ def main():
     stages = krr.krr_timers_read(ctx)
     krr.krr_timers_enable(ctx, False)
 
-    ops = ops_per_step(n, m, r)
+    # predict: the INT8 cross Gram (2 n_test n m) and K_test X (2 n_test n r)
+    ops = ops_per_step(n, m, r) + 2.0 * n_test * n * (m + r)
     value = ops / dt
     out = {
         "metric": "KRR build+factor+solve Op/s vs plain FP32 GPU path at <=1e-5 rel err vs FP64",
