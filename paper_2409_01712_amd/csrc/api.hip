@@ -824,7 +824,10 @@ static krr_status factor_enqueue(krr_context ctx, krr_kernel K, krr_factorizatio
           trsm_subst(k, 0, NT - 1 - k, s);
           convert(k, s);
         }
-        update(k, 1, k + 1, gend - 1, UPD_ALL, s);
+        // panel k onto the group's later diagonal tiles; column k+1 below the
+        // diagonal gets the group's panels G0 .. k in one product
+        update(k, 1, k + 1, gend - 1, UPD_DIAG, s);
+        if (k + 1 < gend) update(G0, k - G0 + 1, k + 1, k + 1, UPD_OFFDIAG, s);
       }
       update(G0, gend - G0, gend, NT - 1, UPD_ALL, s);
     }

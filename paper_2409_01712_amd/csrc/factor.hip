@@ -1191,14 +1191,22 @@ __global__ __launch_bounds__(256) void k_trsm_gemm_b(const FactorJob *__restrict
 // columns) or the group's update (panels G0 = k0 .. onto every column right
 // of the group), clipped to the instance's tile count.  Returns its block
 // count (0 when it has none) and its arguments.
-__host__ __device__ inline int64_t update_extent(int nt, int k0, bool group, int g, int SB, bool diag,
-                                          int &npan, int &jlo, int &jhi) {
+__host__ __device__ inline int64_t update_extent(int nt, int k, bool group, int g, int SB, bool diag,
+                                          int &k0, int &npan, int &jlo, int &jhi) {
+  k0 = k;
   if (!group) {
-    const int G0 = (k0 / g) * g;
-    npan = 1;
-    jlo = k0 + 1;
-    jhi = min(G0 + g, nt) - 1;
-    if (k0 >= nt) return 0;
+    const int G0 = (k / g) * g;
+    if (k >= nt) return 0;
+    if (diag) {  // panel k onto the group's later diagonal tiles
+      npan = 1;
+      jlo = k + 1;
+      jhi = min(G0 + g, nt) - 1;
+    } else {  // left-looking: column k+1 gets the group's panels G0 .. k at once
+      k0 = G0;
+      npan = k - G0 + 1;
+      jlo = jhi = k + 1;
+      if (k + 1 >= min(G0 + g, nt)) return 0;
+    }
   } else {
     npan = min(g, nt - k0);
     jlo = min(k0 + g, nt);
@@ -1223,19 +1231,19 @@ __global__ __launch_bounds__(S::THREADS) void k_update_b(const FactorJob *__rest
                                                          int mode, int allow16, int allow8,
                                                          int high_panels, int fixed_prec) {
   const FactorJob &j = jobs[blockIdx.y];
-  int npan, jlo, jhi;
-  const int64_t nblk = update_extent(j.nt, k0, group != 0, g, SB, DIAG, npan, jlo, jhi);
+  int kf, npan, jlo, jhi;
+  const int64_t nblk = update_extent(j.nt, k0, group != 0, g, SB, DIAG, kf, npan, jlo, jhi);
   if ((int64_t)blockIdx.x >= nblk) return;
   PanelSet ps;
   for (int q = 0; q < npan; ++q) {
-    const int sl = slot_of(k0 + q, g);
+    const int sl = slot_of(kf + q, g);
     ps.P32[q] = j.P32[sl];
     ps.P16[q] = j.P16[sl];
     ps.P8[q] = j.P8[sl];
     ps.pnorm[q] = j.pnorm[sl];
     ps.pexp8[q] = j.pexp8[sl];
   }
-  update_body<S, DIAG>(j.Lst, ps, k0, npan, jlo, jhi, j.nt, nb, SB, mode, allow16, allow8,
+  update_body<S, DIAG>(j.Lst, ps, kf, npan, jlo, jhi, j.nt, nb, SB, mode, allow16, allow8,
                        high_panels, fixed_prec, j.thr, j.pmap, j.ntiles, blockIdx.x, nblk);
 }
 
@@ -1262,10 +1270,10 @@ static void factor_lockstep_t(const FactorJob *jobs, const int *nts, int nj, int
   auto update = [&](int k0, bool group) {
     const int SBd = nb / UpdDiagStream::kBM, SBo = nb / UpdStream::kBM;
     int64_t md = 0, mo = 0, so = 0, mo_small = 0;
-    int npan, jlo, jhi;
+    int kf, npan, jlo, jhi;
     for (int b = 0; b < nj; ++b) {
-      md = std::max(md, update_extent(nts[b], k0, group, g, SBd, true, npan, jlo, jhi));
-      const int64_t off = update_extent(nts[b], k0, group, g, 1, false, npan, jlo, jhi);
+      md = std::max(md, update_extent(nts[b], k0, group, g, SBd, true, kf, npan, jlo, jhi));
+      const int64_t off = update_extent(nts[b], k0, group, g, 1, false, kf, npan, jlo, jhi);
       mo = std::max(mo, off);
       so += off;
     }
