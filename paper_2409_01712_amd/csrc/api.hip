@@ -740,7 +740,8 @@ static bool promote(FactorPlan &fp, krr_precision_policy &p) {
 // launches pay -- and 4 for FP32 updates, whose groups are long enough
 // already and whose updates overlap the factorization better in smaller
 // pieces (measured at n = 32768: FP8 88.3 ms with 8 against 89.5 with 4,
-// FP32 142 ms with 4 against 148 with 8).
+// FP32 142 ms with 4 against 148 with 8; 48 instances in lockstep: FP8
+// 215 ms with 8 against 218 with 4, FP32 272 ms with 4 against 279 with 8).
 static int panel_group(const FactorPlan &fp) { return (fp.allow8 || fp.allow16) ? 8 : 4; }
 
 // Enqueue one factorization attempt of F (its matrix already in F->Lst):
@@ -1064,9 +1065,7 @@ krr_status krr_factor_batched(krr_context ctx, int32_t batch, const krr_kernel *
     }
   }
   const char *g_env = getenv("KRR_GROUP");
-  // small instances in lockstep: groups of 4 (measured: 48 instances 223 ms
-  // per step against 229 with 8)
-  const int g = std::max(1, std::min(KRR_MAX_GROUP, g_env ? atoi(g_env) : 4));
+  const int g = std::max(1, std::min(KRR_MAX_GROUP, g_env ? atoi(g_env) : panel_group(fp)));
   const bool need16 = fp.allow16 || p.allow_promotion;
   std::vector<FactorWork> W(batch);
   std::vector<krr_factorization> Fs(batch, nullptr);
