@@ -103,9 +103,12 @@ typedef struct krr_precision_policy {
 enum {
   KRR_REFINE_NONE = 0, /* one pair of FP32 triangular solves, no FP64 residual */
   KRR_REFINE_IR = 1,   /* iterative refinement with an FP64 residual */
-  KRR_REFINE_PCG = 2,  /* conjugate gradients preconditioned by the factor: not built,
-                          krr_solve returns KRR_ERROR_NOT_SUPPORTED */
-  KRR_REFINE_AUTO = 3  /* the library's choice; currently IR */
+  KRR_REFINE_PCG = 2,  /* conjugate gradients on K + lambda I preconditioned by the factor
+                          (A p from the FP64 residual kernel); iters counts CG steps.
+                          krr_solve only: krr_solve_batched returns
+                          KRR_ERROR_NOT_SUPPORTED */
+  KRR_REFINE_AUTO = 3  /* IR while each iteration at least halves the bound, then PCG
+                          from the current X (krr_solve_batched: IR) */
 };
 
 typedef struct krr_refine_opts {
@@ -170,7 +173,9 @@ krr_status krr_factor_get_info(krr_factorization F, krr_factor_info *info);
 /*
  * Solve (Algorithm 3, second half): X = (K + lambda*I)^{-1} Y for nrhs
  * phenotype columns, by FP32 forward/back substitution with the factor and
- * refinement against an FP64 residual recomputed from the exact distances.
+ * refinement against an FP64 residual recomputed from the exact distances
+ * (classical refinement or preconditioned conjugate gradients, opts->method).
+ * Convergence is always judged on a freshly computed residual of the final X.
  * Y, X: n x nrhs FP64 column-major on the device.  opts/info may be NULL.
  * Returns KRR_ERROR_NOT_CONVERGED if the tolerance is not met within
  * max_iters (X holds the last iterate).  Blocks once per iteration.

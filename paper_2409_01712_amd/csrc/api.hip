@@ -1230,7 +1230,9 @@ krr_status krr_factor_precision_map(krr_factorization F, uint8_t *host_dst, int6
   return KRR_SUCCESS;
 }
 
-static krr_status refine_args(const krr_refine_opts *opts, krr_refine_opts &o) {
+// pcg_ok: the call implements KRR_REFINE_PCG (krr_solve); elsewhere it is
+// NOT_SUPPORTED and AUTO means IR.
+static krr_status refine_args(const krr_refine_opts *opts, bool pcg_ok, krr_refine_opts &o) {
   o = krr_refine_opts{};
   if (opts) {
     o = *opts;
@@ -1241,7 +1243,8 @@ static krr_status refine_args(const krr_refine_opts *opts, krr_refine_opts &o) {
   }
   if (o.method < KRR_REFINE_NONE || o.method > KRR_REFINE_AUTO || o.max_iters < 0 || !(o.tol >= 0))
     return KRR_ERROR_INVALID_VALUE;
-  if (o.method == KRR_REFINE_PCG) return KRR_ERROR_NOT_SUPPORTED;
+  if (o.method == KRR_REFINE_PCG && !pcg_ok) return KRR_ERROR_NOT_SUPPORTED;
+  if (o.method == KRR_REFINE_AUTO && !pcg_ok) o.method = KRR_REFINE_IR;
   return KRR_SUCCESS;
 }
 
@@ -1264,9 +1267,9 @@ static krr_status solve_alloc(Scoped &sc, const TileLayout &L, int r, SolveBufs 
   return KRR_SUCCESS;
 }
 
-// X += L^-T L^-1 src with FP32 sweeps (src: FP64, row-major np x r).
+// dst += L^-T L^-1 src with FP32 sweeps (src, dst: FP64, row-major np x r).
 static void solve_sweeps(krr_context ctx, krr_factorization F, int r, SolveBufs &b,
-                         const double *src, hipStream_t s) {
+                         const double *src, double *dst, hipStream_t s) {
   const TileLayout &L = F->L;
   const int64_t cnt = L.np * r;
   launch_f64_to_f32(src, cnt, b.Bf, s);
@@ -1278,7 +1281,7 @@ static void solve_sweeps(krr_context ctx, krr_factorization F, int r, SolveBufs 
     Stage t(ctx, KRR_STAGE_BWD, s);
     launch_bwd_sweep(F->Lst, F->Linv, L, r, b.Zf, b.Xf, s);
   }
-  launch_axpy_f32_to_f64(b.Xf, cnt, 1.0, b.Xr, s);
+  launch_axpy_f32_to_f64(b.Xf, cnt, 1.0, dst, s);
 }
 
 // R = Y - (K + lambda I) X in FP64, then the squared column norms of R and X
@@ -1312,6 +1315,69 @@ static void refine_bounds(const double *hn, const double *yn, int r, double lamb
   }
 }
 
+// Conjugate-gradient state: z (preconditioned residual), p (direction),
+// nq = -A p, a zero right-hand side for the residual kernel, and per-column
+// scalars p . nq, rho and the next rho.
+struct PcgBufs {
+  double *Z = nullptr, *P = nullptr, *Nq = nullptr, *Y0 = nullptr, *dots = nullptr;
+};
+
+static krr_status pcg_alloc(Scoped &sc, const TileLayout &L, int r, PcgBufs &pb) {
+  const int64_t cnt = L.np * r;
+  CHK(sc.alloc(&pb.Z, cnt));
+  CHK(sc.alloc(&pb.P, cnt));
+  CHK(sc.alloc(&pb.Nq, cnt));
+  CHK(sc.alloc(&pb.Y0, cnt));
+  CHK(sc.alloc(&pb.dots, 3 * r));
+  launch_fill_f64(pb.Y0, cnt, 0.0, sc.ctx->stream);
+  return KRR_SUCCESS;
+}
+
+// Conjugate gradients on (K + lambda I) X = Y, column by column, preconditioned
+// by the factor (z = L^-T L^-1 r with the FP32 sweeps), from the current X and
+// its true residual in b.Rr.  A p comes from the FP64 residual kernel with a
+// zero right-hand side.  Runs until the updated residual meets the stop rule
+// or `it` reaches the budget; the caller then recomputes the true residual,
+// which alone decides convergence, and restarts from it if it falls short.
+static krr_status pcg_run(krr_context ctx, krr_factorization F, int r, SolveBufs &b, PcgBufs &pb,
+                          const std::vector<double> &yn, const krr_refine_opts &o, int &it,
+                          hipStream_t s) {
+  krr_kernel K = F->K;
+  const TileLayout &L = F->L;
+  const int64_t cnt = L.np * r;
+  double *pnq = pb.dots, *rho = pb.dots + r, *rho_next = pb.dots + 2 * r;
+  launch_fill_f64(pb.Z, cnt, 0.0, s);
+  solve_sweeps(ctx, F, r, b, b.Rr, pb.Z, s);
+  launch_pcg_dir(pb.P, pb.Z, nullptr, nullptr, cnt, r, s);
+  launch_col_dots(b.Rr, pb.Z, L.np, r, rho, s);
+  std::vector<double> hn(2 * r);
+  while (it < o.max_iters) {
+    {
+      Stage t(ctx, KRR_STAGE_RESIDUAL, s);
+      launch_residual(K->D, K->etab, K->etab_len, K->gamma, K->lambda, L, r, pb.P, pb.Y0, pb.Nq,
+                      b.Pr, s);
+    }
+    launch_col_dots(pb.P, pb.Nq, L.np, r, pnq, s);
+    launch_pcg_step(b.Xr, b.Rr, pb.P, pb.Nq, rho, pnq, cnt, r, s);
+    ++it;
+    launch_col_norms(b.Rr, L.np, r, b.cn, s);
+    launch_col_norms(b.Xr, L.np, r, b.cn + r, s);
+    CHK(launch_ok());
+    HIPCHK(hipMemcpyAsync(hn.data(), b.cn, 2 * r * 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    double bound, berr;
+    refine_bounds(hn.data(), yn.data(), r, K->lambda, K->norm_a, bound, berr);
+    if (ctx->opts.verbose) fprintf(stderr, "krr_solve: pcg it=%d updated bound=%.3e\n", it, bound);
+    if (bound <= o.tol) break;
+    launch_fill_f64(pb.Z, cnt, 0.0, s);
+    solve_sweeps(ctx, F, r, b, b.Rr, pb.Z, s);
+    launch_col_dots(b.Rr, pb.Z, L.np, r, rho_next, s);
+    launch_pcg_dir(pb.P, pb.Z, rho_next, rho, cnt, r, s);
+    std::swap(rho, rho_next);
+  }
+  return KRR_SUCCESS;
+}
+
 krr_status krr_solve(krr_context ctx, krr_factorization F, const double *Y, int64_t nrhs, int64_t ldy,
                      double *X, int64_t ldx, const krr_refine_opts *opts, krr_solve_info *info) {
   if (!ctx || !F || !Y || !X || nrhs <= 0 || nrhs > 4096) return KRR_ERROR_INVALID_VALUE;
@@ -1320,7 +1386,7 @@ krr_status krr_solve(krr_context ctx, krr_factorization F, const double *Y, int6
   const TileLayout &L = F->L;
   if (ldy < L.n || ldx < L.n) return KRR_ERROR_INVALID_VALUE;
   krr_refine_opts o;
-  CHK(refine_args(opts, o));
+  CHK(refine_args(opts, true, o));
   HIPCHK(hipSetDevice(ctx->device));
   hipStream_t s = ctx->stream;
   const int r = (int)nrhs;
@@ -1330,7 +1396,7 @@ krr_status krr_solve(krr_context ctx, krr_factorization F, const double *Y, int6
   CHK(solve_alloc(sc, L, r, b));
   launch_colmajor_to_rows(Y, L.n, ldy, r, L.np, b.Yr, s);
   launch_fill_f64(b.Xr, cnt, 0.0, s);
-  solve_sweeps(ctx, F, r, b, b.Yr, s);  // the unrefined FP32 solve
+  solve_sweeps(ctx, F, r, b, b.Yr, b.Xr, s);  // the unrefined FP32 solve
   CHK(launch_ok());
   krr_solve_info inf{};
   inf.first_bound = -1;
@@ -1340,9 +1406,13 @@ krr_status krr_solve(krr_context ctx, krr_factorization F, const double *Y, int6
     launch_col_norms(b.Yr, L.np, r, b.cn, s);
     HIPCHK(hipMemcpyAsync(yn.data(), b.cn, r * 8, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
+    PcgBufs pb;
+    if (o.method == KRR_REFINE_PCG || o.method == KRR_REFINE_AUTO) CHK(pcg_alloc(sc, L, r, pb));
+    bool pcg = o.method == KRR_REFINE_PCG;
+    double prev = 0;
     int it = 0;
-    for (;; ++it) {
-      residual_norms(ctx, F, r, b, s);
+    for (;;) {
+      residual_norms(ctx, F, r, b, s);  // the true residual of the current X
       CHK(launch_ok());
       HIPCHK(hipMemcpyAsync(hn.data(), b.cn, 2 * r * 8, hipMemcpyDeviceToHost, s));
       HIPCHK(hipStreamSynchronize(s));
@@ -1356,7 +1426,15 @@ krr_status krr_solve(krr_context ctx, krr_factorization F, const double *Y, int6
         break;
       }
       if (it >= o.max_iters) break;
-      solve_sweeps(ctx, F, r, b, b.Rr, s);
+      // AUTO: refinement while each iteration at least halves the bound, then CG
+      if (o.method == KRR_REFINE_AUTO && it > 0 && bound > 0.5 * prev) pcg = true;
+      prev = bound;
+      if (pcg) {
+        CHK(pcg_run(ctx, F, r, b, pb, yn, o, it, s));
+      } else {
+        solve_sweeps(ctx, F, r, b, b.Rr, b.Xr, s);
+        ++it;
+      }
     }
     inf.iters = it;
     if (!inf.converged) st = KRR_ERROR_NOT_CONVERGED;
@@ -1382,7 +1460,7 @@ krr_status krr_solve_batched(krr_context ctx, int32_t batch, const krr_factoriza
     if (ldy[b] < F[b]->L.n || ldx[b] < F[b]->L.n) return KRR_ERROR_INVALID_VALUE;
   }
   krr_refine_opts o;
-  CHK(refine_args(opts, o));
+  CHK(refine_args(opts, false, o));
   HIPCHK(hipSetDevice(ctx->device));
   hipStream_t s = ctx->stream;
   const int r = (int)nrhs, nb = ctx->opts.tile;

@@ -219,6 +219,15 @@ void launch_f64_to_f32(const double *src, int64_t count, float *dst, hipStream_t
 void launch_axpy_f32_to_f64(const float *src, int64_t count, double alpha, double *dst,
                             hipStream_t s);
 void launch_col_norms(const double *A, int64_t n, int r, double *out, hipStream_t s);
+void launch_col_dots(const double *A, const double *B, int64_t n, int r, double *out,
+                     hipStream_t s);
+// Preconditioned conjugate gradients on the columns of row-major count / r x r
+// matrices: x += alpha p, res -= alpha A p from nq = -A p, alpha = rho / (p . A p)
+// with pnq = p . nq; then p = z + (rho_new / rho_old) p (p = z when rho_old is null).
+void launch_pcg_step(double *x, double *res, const double *p, const double *nq, const double *rho,
+                     const double *pnq, int64_t count, int r, hipStream_t s);
+void launch_pcg_dir(double *p, const double *z, const double *rho_new, const double *rho_old,
+                    int64_t count, int r, hipStream_t s);
 void launch_predict_apply(const int32_t *Dt, int64_t rows, int64_t cols, int64_t ldd,
                           const double *etab, int64_t etab_len, const double *X, int r, double *P,
                           int64_t ldp, hipStream_t s);

@@ -621,22 +621,68 @@ void launch_axpy_f32_to_f64(const float *src, int64_t count, double alpha, doubl
                      src, count, alpha, dst);
 }
 
-// Squared column norms of a row-major n x r FP64 matrix, fixed order.
-__global__ __launch_bounds__(256) void k_col_norms(const double *__restrict__ A, int64_t n, int r,
-                                                   double *__restrict__ out) {
+// Column dot products sum_i A_ic B_ic of two row-major n x r FP64 matrices,
+// fixed order (squared column norms when B = A).
+__global__ __launch_bounds__(256) void k_col_dots(const double *__restrict__ A,
+                                                  const double *__restrict__ B, int64_t n, int r,
+                                                  double *__restrict__ out) {
   __shared__ double sh[4];
   const int c = blockIdx.x;
   double s = 0.0;
-  for (int64_t i = threadIdx.x; i < n; i += 256) {
-    const double v = A[i * r + c];
-    s += v * v;
-  }
+  for (int64_t i = threadIdx.x; i < n; i += 256) s += A[i * r + c] * B[i * r + c];
   s = block_sum<4>(s, sh);
   if (threadIdx.x == 0) out[c] = s;
 }
 
+void launch_col_dots(const double *A, const double *B, int64_t n, int r, double *out,
+                     hipStream_t s) {
+  hipLaunchKernelGGL(k_col_dots, dim3(r), dim3(256), 0, s, A, B, n, r, out);
+}
+
 void launch_col_norms(const double *A, int64_t n, int r, double *out, hipStream_t s) {
-  hipLaunchKernelGGL(k_col_norms, dim3(r), dim3(256), 0, s, A, n, r, out);
+  launch_col_dots(A, A, n, r, out, s);
+}
+
+// One step of conjugate gradients on every column c of row-major n x r
+// matrices, given nq = -A p (the residual kernel with a zero right-hand side):
+//   alpha_c = rho_c / (p_c . A p_c),  x_c += alpha_c p_c,  r_c -= alpha_c A p_c.
+// A zero curvature (only when p_c = 0) gives alpha_c = 0.
+__global__ void k_pcg_step(double *__restrict__ x, double *__restrict__ res,
+                           const double *__restrict__ p, const double *__restrict__ nq,
+                           const double *__restrict__ rho, const double *__restrict__ pnq,
+                           int64_t count, int r) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= count) return;
+  const int c = (int)(e % r);
+  const double den = -pnq[c];
+  const double alpha = den != 0.0 ? rho[c] / den : 0.0;
+  x[e] += alpha * p[e];
+  res[e] += alpha * nq[e];
+}
+
+void launch_pcg_step(double *x, double *res, const double *p, const double *nq, const double *rho,
+                     const double *pnq, int64_t count, int r, hipStream_t s) {
+  hipLaunchKernelGGL(k_pcg_step, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, x, res, p,
+                     nq, rho, pnq, count, r);
+}
+
+// New search directions p_c = z_c + beta_c p_c, beta_c = rho_new_c / rho_old_c
+// (0 when rho_old_c is 0); start: rho_old = nullptr gives p = z.
+__global__ void k_pcg_dir(double *__restrict__ p, const double *__restrict__ z,
+                          const double *__restrict__ rho_new, const double *__restrict__ rho_old,
+                          int64_t count, int r) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= count) return;
+  const int c = (int)(e % r);
+  double beta = 0.0;
+  if (rho_old && rho_old[c] != 0.0) beta = rho_new[c] / rho_old[c];
+  p[e] = z[e] + beta * p[e];
+}
+
+void launch_pcg_dir(double *p, const double *z, const double *rho_new, const double *rho_old,
+                    int64_t count, int r, hipStream_t s) {
+  hipLaunchKernelGGL(k_pcg_dir, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, p, z,
+                     rho_new, rho_old, count, r);
 }
 
 __global__ void k_fill_f64(double *p, int64_t count, double v) {

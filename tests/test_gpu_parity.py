@@ -220,6 +220,67 @@ def test_solve_parity_ragged_many_rhs(ctx):
     assert _colrel(X.cpu().numpy(), Wo) <= TOL
 
 
+@pytest.mark.parametrize("method", ["pcg", "auto"])
+@pytest.mark.parametrize("policy", ["adaptive", "fixed_fp8"])
+def test_pcg_parity(method, policy):
+    """Conjugate gradients preconditioned by the mixed-precision factor (and AUTO,
+    which starts with refinement) reach the oracle's FP64 solution at lambda = 1e-3,
+    where refinement contracts slowest, with a ragged n (1500 at tile 256) and one
+    all-zero right-hand side, whose solution is exactly zero."""
+    n, m, r = 1500, 2000, 6
+    G = _gen(n, m, seed=41)
+    Y = synth.phenotypes(G, r, n_pairs=10, n_add=5, seed=5, h2=0.5)
+    Y[:, 2] = 0.0
+    gamma, lam, tol = 0.5 / m, 1e-3, 1e-8
+    Wo = oracle.fit(G, Y, gamma, lam)
+    c = krr.krr_create(0, tile=256)
+    K = krr.krr_build_kernel(c, _dev(G), gamma, lam)
+    F = krr.krr_factor(c, K, POLICIES[policy])
+    meth = {"pcg": krr.KRR_REFINE_PCG, "auto": krr.KRR_REFINE_AUTO}[method]
+    X, info, st = krr.krr_solve(c, F, _dev(Y), krr.Refine(method=meth, max_iters=60, tol=tol))
+    X_ir, info_ir, _ = krr.krr_solve(c, F, _dev(Y), krr.Refine(max_iters=60, tol=tol), check=False)
+    print(f"{method}/{policy}: iters {info.iters} (IR {info_ir.iters}), "
+          f"first bound {info.first_bound:.2e}, final {info.fwd_err_bound:.2e}")
+    assert st == krr.KRR_SUCCESS and info.converged == 1 and info.fwd_err_bound <= tol
+    assert info.first_bound > tol and info.iters >= 1
+    Xh = X.cpu().numpy()
+    assert np.all(Xh[:, 2] == 0.0)
+    keep = [0, 1, 3, 4, 5]
+    assert _colrel(Xh[:, keep], Wo[:, keep]) <= TOL
+    # the stop rule is certified on the oracle's own FP64 residual of the returned X
+    R = oracle.residual_rows(G, gamma, lam, Xh, Y, np.arange(n))
+    xn = np.linalg.norm(Xh, axis=0)
+    assert np.all(np.linalg.norm(R, axis=0) <= lam * tol * xn * 1.01 + 1e-300)
+    F.release()
+    K.release()
+    c.close()
+
+
+def test_pcg_budget_and_batched_rejection():
+    """PCG with no iteration budget reports NOT_CONVERGED with the first solve in X;
+    the batched solve implements refinement only and rejects PCG."""
+    w = synth.WORKLOADS["small"]
+    G = w.genotypes(rows=600)
+    Y = w.phenotypes(G)
+    c = krr.krr_create(0, tile=256)
+    K = krr.krr_build_kernel(c, _dev(G), w.gamma, w.lam)
+    F = krr.krr_factor(c, K)
+    X0, info0, st0 = krr.krr_solve(c, F, _dev(Y), krr.Refine(method=krr.KRR_REFINE_NONE))
+    X, info, st = krr.krr_solve(c, F, _dev(Y), krr.Refine(method=krr.KRR_REFINE_PCG, max_iters=0,
+                                                          tol=1e-300), check=False)
+    assert st == krr.KRR_ERROR_NOT_CONVERGED and info.iters == 0 and info.converged == 0
+    assert torch.equal(X, X0)
+    Ks = krr.krr_build_kernel_batched(c, [_dev(G)], [w.gamma], [w.lam])
+    Fs = krr.krr_factor_batched(c, Ks)
+    _, _, stb = krr.krr_solve_batched(c, Fs, [_dev(Y)], krr.Refine(method=krr.KRR_REFINE_PCG),
+                                      check=False)
+    assert stb == krr.KRR_ERROR_NOT_SUPPORTED
+    Xa, infa, sta = krr.krr_solve_batched(c, Fs, [_dev(Y)],
+                                          krr.Refine(method=krr.KRR_REFINE_AUTO, tol=1e-8))
+    assert sta == krr.KRR_SUCCESS and infa[0].converged == 1
+    c.close()
+
+
 def test_refactor_from_distances(ctx):
     """A second factorization of one kernel re-expands K from the stored distances."""
     w = synth.WORKLOADS["small"]
