@@ -98,6 +98,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=3072, help="patients in the oracle sample")
     ap.add_argument("--eps", type=float, default=1.0)
+    ap.add_argument("--refine", choices=["ir", "pcg", "auto"], default="ir",
+                    help="refinement method of the adaptive path")
     ap.add_argument("--high-panels", type=int, default=1)
     ap.add_argument("--tile", type=int, default=512)
     ap.add_argument("--verbose", action="store_true")
@@ -154,7 +156,9 @@ def main():
     # solution, enforced through the rigorous bound ||x - x*|| <= ||r|| / lambda
     # (K + lambda I has smallest eigenvalue >= lambda): stopping at
     # ||r_j|| / (lambda ||x_j||) <= tol gives ||x_j - x*_j|| / ||x*_j|| <= tol / (1 - tol).
-    refine = krr.Refine(method=krr.KRR_REFINE_IR, max_iters=30, tol=REFINE_TOL)
+    method = {"ir": krr.KRR_REFINE_IR, "pcg": krr.KRR_REFINE_PCG,
+              "auto": krr.KRR_REFINE_AUTO}[args.refine]
+    refine = krr.Refine(method=method, max_iters=30, tol=REFINE_TOL)
     no_refine = krr.Refine(method=krr.KRR_REFINE_NONE)
 
     def step(policy, ref):
@@ -209,7 +213,7 @@ def main():
             "parallelism": "single GPU",
         },
         "ops_per_step": ops,
-        "refine": {"iters": info.iters, "fwd_err_bound": info.fwd_err_bound,
+        "refine": {"method": args.refine, "iters": info.iters, "fwd_err_bound": info.fwd_err_bound,
                    "first_bound": info.first_bound, "converged": bool(info.converged)},
         "updates": {"fp32": int(finfo.updates[0]), "fp16": int(finfo.updates[1]),
                     "fp8": int(finfo.updates[2]), "promotions": int(finfo.promotions)},
@@ -313,7 +317,8 @@ def main_batched(args):
     ns = [w.n for w, _ in insts]
     ctx = krr.krr_create(0, tile=args.tile)
     adaptive = krr.Policy(eps=args.eps, high_panels=args.high_panels)
-    refine = krr.Refine(method=krr.KRR_REFINE_IR, max_iters=30, tol=REFINE_TOL)
+    refine = krr.Refine(method=krr.KRR_REFINE_IR if args.refine == "ir" else krr.KRR_REFINE_AUTO,
+                        max_iters=30, tol=REFINE_TOL)
 
     def step(policy, ref):
         Ks = krr.krr_build_kernel_batched(ctx, Gs, gammas, lams)

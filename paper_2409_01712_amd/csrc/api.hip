@@ -67,6 +67,7 @@ struct krr_factor_s {
   TileLayout L;
   float *Lst = nullptr;   // FP32 factor, packed lower tiles
   float *Linv = nullptr;  // inverses of the diagonal tiles, nt x nb x nb
+  float *Cpair = nullptr; // coupling tiles of the paired sweeps, nt / 2 (first solve)
   krr_factor_info info{};
   std::vector<uint8_t> pmap;
 };
@@ -1030,6 +1031,7 @@ static void factor_free(krr_factorization F) {
   krr_context c = F->ctx;
   dfree(c, F->Lst, F->L.elems() * 4);
   dfree(c, F->Linv, (size_t)F->L.nt * F->L.tile_elems() * 4);
+  if (F->Cpair) dfree(c, F->Cpair, (size_t)(F->L.nt / 2) * F->L.tile_elems() * 4);
   delete F;
 }
 
@@ -1252,7 +1254,27 @@ static krr_status refine_args(const krr_refine_opts *opts, bool pcg_ok, krr_refi
 struct SolveBufs {
   double *Yr = nullptr, *Xr = nullptr, *Rr = nullptr, *cn = nullptr, *Pr = nullptr;
   float *Bf = nullptr, *Zf = nullptr, *Xf = nullptr;
+  const float *C = nullptr;  // coupling tiles of the paired sweeps, or null
 };
+
+// The coupling tiles of the paired sweeps, formed on the first solve with a
+// factor and kept with it; KRR_SWEEP_PAIRS=0 sweeps one tile per step.
+static krr_status sweep_coupling(krr_context ctx, krr_factorization F, Scoped &sc, SolveBufs &b,
+                                 hipStream_t s) {
+  b.C = nullptr;
+  const char *e = getenv("KRR_SWEEP_PAIRS");
+  const TileLayout &L = F->L;
+  const int64_t npair = L.nt / 2;
+  if ((e && atoi(e) == 0) || npair == 0) return KRR_SUCCESS;
+  if (!F->Cpair) {
+    float *tmp = nullptr;
+    CHK(sc.alloc(&tmp, npair * L.tile_elems()));
+    CHK(dalloc_t(ctx, &F->Cpair, npair * L.tile_elems()));
+    launch_sweep_coupling(F->Lst, F->Linv, L, tmp, F->Cpair, s);
+  }
+  b.C = F->Cpair;
+  return KRR_SUCCESS;
+}
 
 static krr_status solve_alloc(Scoped &sc, const TileLayout &L, int r, SolveBufs &b) {
   const int64_t cnt = L.np * r;
@@ -1275,11 +1297,11 @@ static void solve_sweeps(krr_context ctx, krr_factorization F, int r, SolveBufs 
   launch_f64_to_f32(src, cnt, b.Bf, s);
   {
     Stage t(ctx, KRR_STAGE_FWD, s);
-    launch_fwd_sweep(F->Lst, F->Linv, L, r, b.Bf, b.Zf, s);
+    launch_fwd_sweep(F->Lst, F->Linv, b.C, L, r, b.Bf, b.Zf, s);
   }
   {
     Stage t(ctx, KRR_STAGE_BWD, s);
-    launch_bwd_sweep(F->Lst, F->Linv, L, r, b.Zf, b.Xf, s);
+    launch_bwd_sweep(F->Lst, F->Linv, b.C, L, r, b.Zf, b.Xf, s);
   }
   launch_axpy_f32_to_f64(b.Xf, cnt, 1.0, dst, s);
 }
@@ -1394,6 +1416,7 @@ krr_status krr_solve(krr_context ctx, krr_factorization F, const double *Y, int6
   Scoped sc(ctx);
   SolveBufs b;
   CHK(solve_alloc(sc, L, r, b));
+  CHK(sweep_coupling(ctx, F, sc, b, s));
   launch_colmajor_to_rows(Y, L.n, ldy, r, L.np, b.Yr, s);
   launch_fill_f64(b.Xr, cnt, 0.0, s);
   solve_sweeps(ctx, F, r, b, b.Yr, b.Xr, s);  // the unrefined FP32 solve

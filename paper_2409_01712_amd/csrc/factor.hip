@@ -450,6 +450,45 @@ __global__ __launch_bounds__(256) void k_trtri_level(const T *__restrict__ WLall
                       blockIdx.x);
 }
 
+// Coupling tiles of the paired triangular sweeps, FP32: for the tile pair
+// (k, k+1) = (2p, 2p+1) of block lower-triangular L,
+//   inv([L_kk 0; L_k+1,k L_k+1,k+1]) = [inv(L_kk) 0; -C_p inv(L_k+1,k+1)],
+//   C_p = inv(L_k+1,k+1) L_k+1,k inv(L_kk),
+// in two products (step 0: Tmp_p = L_k+1,k inv(L_kk); step 1: C_p =
+// inv(L_k+1,k+1) Tmp_p).  Output block (blockIdx.y, blockIdx.x) of 64 x 64 of
+// pair blockIdx.z.
+__global__ __launch_bounds__(256) void k_sweep_coupling(const float *__restrict__ Lst,
+                                                        const float *__restrict__ Linv,
+                                                        float *__restrict__ Tmp,
+                                                        float *__restrict__ C, int nb, int step) {
+  __shared__ float As[BS][BS + 1];
+  __shared__ float Bs[BS][BS + 1];
+  const int64_t p = blockIdx.z, te = (int64_t)nb * nb, k = 2 * p;
+  const int rb = blockIdx.y, cb = blockIdx.x;
+  const float *A = step == 0 ? Lst + tri_index(k + 1, k) * te : Linv + (k + 1) * te;
+  const float *B = step == 0 ? Linv + k * te : Tmp + p * te;
+  float *Out = (step == 0 ? Tmp : C) + p * te;
+  typename M16<float>::v4 acc[4];
+  zero4<float>(acc);
+  for (int kk = 0; kk < nb; kk += BS) {
+    load64(As, A + (int64_t)(rb * BS) * nb + kk, nb);
+    load64(Bs, B + (int64_t)kk * nb + cb * BS, nb);
+    __syncthreads();
+    mm64<float, false>(As, Bs, acc);
+    __syncthreads();
+  }
+  store64<float, false>(Out + (int64_t)(rb * BS) * nb + cb * BS, nb, acc, 1.0f);
+}
+
+void launch_sweep_coupling(const float *Lst, const float *Linv, const TileLayout &L, float *Tmp,
+                           float *C, hipStream_t s) {
+  const int npair = L.nt / 2, nbk = L.nb / BS;
+  if (npair == 0) return;
+  for (int step = 0; step < 2; ++step)
+    hipLaunchKernelGGL(k_sweep_coupling, dim3(nbk, nbk, npair), dim3(256), 0, s, Lst, Linv, Tmp, C,
+                       L.nb, step);
+}
+
 // Write L_kk (lower, zero above) into the factor storage and inv(L_kk), FP32.
 template <typename T>
 __global__ void k_potrf_store(const T *__restrict__ WLall, const T *__restrict__ Winvc,

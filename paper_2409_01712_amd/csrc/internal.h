@@ -165,6 +165,10 @@ void launch_potrf_tile(float *Akk, int k, const TileLayout &L, bool fp64, Factor
 // k_lo .. k_hi-1 (factored before).
 void launch_tile_inverses(float *Lst, float *Linv, int k_lo, int k_hi, const TileLayout &L,
                           bool fp64, FactorWork &w, hipStream_t s);
+// Coupling tiles C_p = inv(L_k+1,k+1) L_k+1,k inv(L_kk) of the tile pairs
+// (k, k+1) = (2p, 2p+1), p < nt / 2, for the paired sweeps; Tmp, C: nt / 2 tiles.
+void launch_sweep_coupling(const float *Lst, const float *Linv, const TileLayout &L, float *Tmp,
+                           float *C, hipStream_t s);
 // P_i = A_ik inv(L_kk)^T for the tiles i = k+1+t, t_lo <= t < t_hi: by
 // substitution with the factor of tile k (no inverse needed), or as a product
 // with inv(L_kk) (launch_tile_inverses first).
@@ -188,10 +192,12 @@ void launch_encode_fp8(const float *x, int64_t n, uint8_t *out, hipStream_t s);
 
 // ---- solve.hip ----
 // Internal right-hand sides are row-major np x r.
-void launch_fwd_sweep(const float *Astore, const float *Linv, const TileLayout &L, int r,
-                      float *B, float *Z, hipStream_t s);
-void launch_bwd_sweep(const float *Astore, const float *Linv, const TileLayout &L, int r,
-                      float *Z, float *X, hipStream_t s);
+// C: the coupling tiles of launch_sweep_coupling (tiles taken in pairs), or
+// null (one tile per step).
+void launch_fwd_sweep(const float *Astore, const float *Linv, const float *C, const TileLayout &L,
+                      int r, float *B, float *Z, hipStream_t s);
+void launch_bwd_sweep(const float *Astore, const float *Linv, const float *C, const TileLayout &L,
+                      int r, float *Z, float *X, hipStream_t s);
 // R = Y - (K + lambda I) X in FP64; part: residual_split(L) * np * r doubles
 // of workspace for the partial products.
 int residual_split(const TileLayout &L);

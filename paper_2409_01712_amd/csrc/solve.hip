@@ -81,6 +81,62 @@ __device__ __forceinline__ v4f job_product(const float *__restrict__ M, const fl
   return sum;
 }
 
+// The sum of two such products, M1 V1 + sign2 M2 V2 (k ranges [klo1, khi1)
+// and [klo2, khi2), multiples of 16, each at most nb <= 512 wide): the
+// 16-wide k blocks of both are dealt round robin to the four waves, at most
+// sixteen per wave, all loads of a wave in flight before its MFMAs.
+template <bool TRANS>
+__device__ __forceinline__ v4f job_product2(const float *__restrict__ M1, const float *V1,
+                                            int klo1, int khi1, const float *__restrict__ M2,
+                                            const float *V2, int klo2, int khi2, float sign2,
+                                            int nb, int r, int row0, int col0, v4f (*red)[64]) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, lg = lane >> 4;
+  const int R = row0 + li, col = col0 + li;
+  const int cc = min(col, r - 1);
+  const bool cv = col < r;
+  const int n1 = (khi1 - klo1) / 16, n2 = (khi2 - klo2) / 16;
+  float a[16][4], b[16][4];
+#pragma unroll
+  for (int u = 0; u < 16; ++u) {
+    const int g = wave + 4 * u;
+    const bool first = g < n1;
+    if (g < n1 + n2) {
+      const float *M = first ? M1 : M2;
+      const float *V = first ? V1 : V2;
+      const int kk = (first ? klo1 + 16 * g : klo2 + 16 * (g - n1)) + 4 * lg;
+      const float sg = first ? 1.0f : sign2;
+      if (!TRANS) {
+        const float4 v = *(const float4 *)(M + (int64_t)R * nb + kk);
+        a[u][0] = v.x; a[u][1] = v.y; a[u][2] = v.z; a[u][3] = v.w;
+      } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) a[u][e] = M[(int64_t)(kk + e) * nb + R];
+      }
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const float v = V[(int64_t)(kk + e) * r + cc];
+        b[u][e] = cv ? sg * v : 0.f;
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) a[u][e] = b[u][e] = 0.f;
+    }
+  }
+  v4f acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int u = 0; u < 16; ++u)
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u][e], b[u][e], acc, 0, 0, 0);
+  red[wave][lane] = acc;
+  __syncthreads();
+  v4f sum = red[0][lane];
+#pragma unroll
+  for (int q = 1; q < 4; ++q) sum += red[q][lane];
+  return sum;
+}
+
 // Sweep step k, diagonal part:
 //   forward  Z_k = inv(L_kk) B_k     (rows of the inverse need k <= row)
 //   backward X_k = inv(L_kk)^T Z_k   (its transpose, k >= row)
@@ -137,6 +193,72 @@ __global__ __launch_bounds__(256) void k_sweep_panel(const float *__restrict__ L
   sweep_panel_body<FWD>(Lst, V_k, In, k, nb, r, blockIdx.x);
 }
 
+// Paired sweep steps over the tiles (k, k+1) = (2p, 2p+1), with the coupling
+// tile C_p = inv(L_k+1,k+1) L_k+1,k inv(L_kk) standing in for the step between
+// them, so that one launch covers both diagonal tiles and one the panels of both:
+//   forward  Z_k = inv(L_kk) B_k,  Z_k+1 = inv(L_k+1,k+1) B_k+1 - C_p B_k,
+//            B_i -= L_ik Z_k + L_i,k+1 Z_k+1,  i > k+1;
+//   backward X_k+1 = inv(L_k+1,k+1)^T Z_k+1,  X_k = inv(L_kk)^T Z_k - C_p^T Z_k+1,
+//            Z_j -= L_kj^T X_k + L_k+1,j^T X_k+1,  j < k.
+// Diagonal launch: 2 x per workgroups, the first per for tile k's rows.
+template <bool FWD>
+__global__ __launch_bounds__(256) void k_sweep_diag2(const float *__restrict__ Linv,
+                                                     const float *__restrict__ Cp, const float *In,
+                                                     float *Out, int k, int nb, int r) {
+  __shared__ v4f red[4][64];
+  const int CJ = (r + 15) / 16, per = (nb / 16) * CJ;
+  const int half = blockIdx.x / per, rem = blockIdx.x % per;
+  const int rj = rem / CJ, cj = rem % CJ;
+  const int row0 = rj * 16, col0 = cj * 16;
+  const int64_t te = (int64_t)nb * nb, vb = (int64_t)nb * r;
+  const float *Li0 = Linv + (int64_t)k * te, *Li1 = Linv + (int64_t)(k + 1) * te;
+  const float *In0 = In + (int64_t)k * vb, *In1 = In + (int64_t)(k + 1) * vb;
+  v4f acc;
+  if (FWD) {
+    if (half == 0)
+      acc = job_product2<false>(Li0, In0, 0, row0 + 16, Cp, In0, 0, 0, 0.f, nb, r, row0, col0, red);
+    else
+      acc = job_product2<false>(Li1, In1, 0, row0 + 16, Cp, In0, 0, nb, -1.f, nb, r, row0, col0,
+                                red);
+  } else {
+    if (half == 1)
+      acc = job_product2<true>(Li1, In1, row0, nb, Cp, In1, 0, 0, 0.f, nb, r, row0, col0, red);
+    else
+      acc = job_product2<true>(Li0, In0, row0, nb, Cp, In1, 0, nb, -1.f, nb, r, row0, col0, red);
+  }
+  const int lane = threadIdx.x & 63, col = col0 + (lane & 15);
+  if (threadIdx.x < 64 && col < r) {
+    float *o = Out + (int64_t)(k + half) * vb;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) o[(int64_t)(row0 + 4 * (lane >> 4) + e) * r + col] = acc[e];
+  }
+}
+
+// Panel launch of a pair: one job per workgroup, tile t of the panel rows
+// (forward i = k+2+t; backward j = t < k).
+template <bool FWD>
+__global__ __launch_bounds__(256) void k_sweep_panel2(const float *__restrict__ Lst,
+                                                      const float *V, float *In, int k, int nb,
+                                                      int r) {
+  __shared__ v4f red[4][64];
+  const int CJ = (r + 15) / 16, per = (nb / 16) * CJ;
+  const int64_t t = blockIdx.x / per;
+  const int rem = (int)(blockIdx.x % per), rj = rem / CJ, cj = rem % CJ;
+  const int64_t te = (int64_t)nb * nb, vb = (int64_t)nb * r;
+  const int64_t i = FWD ? k + 2 + t : t;
+  const float *M1 = Lst + (FWD ? tri_index(i, k) : tri_index(k, i)) * te;
+  const float *M2 = Lst + (FWD ? tri_index(i, k + 1) : tri_index(k + 1, i)) * te;
+  const int row0 = rj * 16, col0 = cj * 16;
+  const v4f acc = job_product2<!FWD>(M1, V + (int64_t)k * vb, 0, nb, M2, V + (int64_t)(k + 1) * vb,
+                                     0, nb, 1.f, nb, r, row0, col0, red);
+  const int lane = threadIdx.x & 63, col = col0 + (lane & 15);
+  if (threadIdx.x < 64 && col < r) {
+    float *o = In + i * vb;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) o[(int64_t)(row0 + 4 * (lane >> 4) + e) * r + col] -= acc[e];
+  }
+}
+
 // The same steps for a batch of instances in lockstep (blockIdx.y = instance):
 // step k of instance j runs when k < its tile count; forward B -> Z, backward
 // Z -> X.  Workgroups without work return before any barrier.
@@ -178,31 +300,54 @@ void launch_sweeps_batched(const SolveJob *jobs, int njobs, int ntmax, int nb, i
   }
 }
 
-// L Z = B (B is overwritten).
-void launch_fwd_sweep(const float *Astore, const float *Linv, const TileLayout &L, int r, float *B,
-                      float *Z, hipStream_t s) {
+// L Z = B (B is overwritten).  With the coupling tiles C (nt / 2 of them, or
+// null) the tiles go in pairs (0, 1), (2, 3), ..., the last one alone when nt
+// is odd.
+void launch_fwd_sweep(const float *Astore, const float *Linv, const float *C, const TileLayout &L,
+                      int r, float *B, float *Z, hipStream_t s) {
   const int nb = L.nb, NT = L.nt, CJ = (r + 15) / 16, per = (nb / 16) * CJ;
   const int64_t te = (int64_t)nb * nb, vb = (int64_t)nb * r;
-  for (int k = 0; k < NT; ++k) {
+  for (int k = 0; k < NT;) {
+    if (C && k + 1 < NT) {
+      hipLaunchKernelGGL(k_sweep_diag2<true>, dim3(2 * per), dim3(256), 0, s, Linv,
+                         C + (int64_t)(k / 2) * te, B, Z, k, nb, r);
+      if (NT - 2 - k > 0)
+        hipLaunchKernelGGL(k_sweep_panel2<true>, dim3((unsigned)((NT - 2 - k) * per)), dim3(256),
+                           0, s, Astore, Z, B, k, nb, r);
+      k += 2;
+      continue;
+    }
     hipLaunchKernelGGL(k_sweep_diag<true>, dim3(per), dim3(256), 0, s, Linv + k * te, B + k * vb,
                        Z + k * vb, nb, r);
     if (NT - 1 - k > 0)
       hipLaunchKernelGGL(k_sweep_panel<true>, dim3((unsigned)((NT - 1 - k) * per)), dim3(256), 0,
                          s, Astore, Z + k * vb, B, k, nb, r);
+    ++k;
   }
 }
 
-// L^T X = Z (Z is overwritten).
-void launch_bwd_sweep(const float *Astore, const float *Linv, const TileLayout &L, int r, float *Z,
-                      float *X, hipStream_t s) {
+// L^T X = Z (Z is overwritten); the pairs of the forward sweep, last first.
+void launch_bwd_sweep(const float *Astore, const float *Linv, const float *C, const TileLayout &L,
+                      int r, float *Z, float *X, hipStream_t s) {
   const int nb = L.nb, NT = L.nt, CJ = (r + 15) / 16, per = (nb / 16) * CJ;
   const int64_t te = (int64_t)nb * nb, vb = (int64_t)nb * r;
-  for (int k = NT - 1; k >= 0; --k) {
+  for (int k = NT - 1; k >= 0;) {
+    if (C && k % 2 == 1) {  // the pair (k-1, k)
+      const int k0 = k - 1;
+      hipLaunchKernelGGL(k_sweep_diag2<false>, dim3(2 * per), dim3(256), 0, s, Linv,
+                         C + (int64_t)(k0 / 2) * te, Z, X, k0, nb, r);
+      if (k0 > 0)
+        hipLaunchKernelGGL(k_sweep_panel2<false>, dim3((unsigned)(k0 * per)), dim3(256), 0, s,
+                           Astore, X, Z, k0, nb, r);
+      k -= 2;
+      continue;
+    }
     hipLaunchKernelGGL(k_sweep_diag<false>, dim3(per), dim3(256), 0, s, Linv + k * te, Z + k * vb,
                        X + k * vb, nb, r);
     if (k > 0)
       hipLaunchKernelGGL(k_sweep_panel<false>, dim3((unsigned)(k * per)), dim3(256), 0, s, Astore,
                          X + k * vb, Z, k, nb, r);
+    --k;
   }
 }
 

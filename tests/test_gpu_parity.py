@@ -220,6 +220,35 @@ def test_solve_parity_ragged_many_rhs(ctx):
     assert _colrel(X.cpu().numpy(), Wo) <= TOL
 
 
+@pytest.mark.parametrize("n", [200, 700, 1200, 1500])
+def test_paired_sweeps_match_single_steps(monkeypatch, n):
+    """Triangular sweeps that take the tiles in pairs (a coupling tile standing in
+    for the step between the two) agree with one-tile-per-step sweeps to FP32
+    rounding, at tile counts 1, 3, 5 and 6 (tile 256); the refined result matches
+    the oracle."""
+    m, r = 900, 5
+    G = _gen(n, m, seed=n)
+    Y = synth.phenotypes(G, r, n_pairs=5, n_add=3, seed=n + 1, h2=0.5)
+    gamma, lam = 1.0 / m, 0.1
+    c = krr.krr_create(0, tile=256)
+    K = krr.krr_build_kernel(c, _dev(G), gamma, lam)
+    F = krr.krr_factor(c, K, krr.plain_fp32_policy())
+    none = krr.Refine(method=krr.KRR_REFINE_NONE)
+    X2, _, _ = krr.krr_solve(c, F, _dev(Y), none)
+    monkeypatch.setenv("KRR_SWEEP_PAIRS", "0")
+    X1, _, _ = krr.krr_solve(c, F, _dev(Y), none)
+    monkeypatch.delenv("KRR_SWEEP_PAIRS")
+    # both carry the FP32 factor's error; a wrong coupling or a missed panel
+    # term would move X by O(1)
+    assert _colrel(X2.cpu().numpy(), X1.cpu().numpy()) <= 2e-3
+    X, info, st = krr.krr_solve(c, F, _dev(Y), krr.Refine(tol=1e-8))
+    assert info.converged == 1
+    assert _colrel(X.cpu().numpy(), oracle.fit(G, Y, gamma, lam)) <= TOL
+    F.release()
+    K.release()
+    c.close()
+
+
 @pytest.mark.parametrize("method", ["pcg", "auto"])
 @pytest.mark.parametrize("policy", ["adaptive", "fixed_fp8"])
 def test_pcg_parity(method, policy):
