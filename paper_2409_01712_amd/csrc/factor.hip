@@ -887,7 +887,11 @@ struct PanelSet {
 // form one streamed K range (one segment per panel), so a sub-block runs at
 // most three products (FP32, FP16, FP8 operands) into one FP32 accumulator.
 typedef StreamShape<256, 256, 2, 4, 4> UpdStream;   // off-diagonal tiles
-typedef StreamShape<128, 128, 2, 2, 4> UpdDiagStream;  // diagonal tiles
+typedef StreamShape<128, 128, 2, 2, 4> UpdDiagStream;  // few off-diagonal tiles
+// Diagonal tiles: always FP32 and with up to a whole group of
+// panels (K = 8 nb), so each block's serial K loop is long; 64 x 64 blocks
+// cut it four times over and give four times the workgroups.
+typedef StreamShape<64, 64, 2, 2, 4> UpdDiag64;
 
 // Segment table in LDS: per precision, the row-0 addresses of the A and B
 // operand blocks of each selected panel (and the FP8 scale codes).
@@ -1089,17 +1093,17 @@ void launch_update(float *Astore, int k0, int npan, int jlo, int jhi, const Tile
   if (!attr) {
     hipFuncSetAttribute((const void *)k_update<UpdStream, false>,
                         hipFuncAttributeMaxDynamicSharedMemorySize, UpdStream::LDS_BYTES);
-    hipFuncSetAttribute((const void *)k_update<UpdDiagStream, true>,
-                        hipFuncAttributeMaxDynamicSharedMemorySize, UpdDiagStream::LDS_BYTES);
+    hipFuncSetAttribute((const void *)k_update<UpdDiag64, true>,
+                        hipFuncAttributeMaxDynamicSharedMemorySize, UpdDiag64::LDS_BYTES);
     hipFuncSetAttribute((const void *)k_update<UpdDiagStream, false>,
                         hipFuncAttributeMaxDynamicSharedMemorySize, UpdDiagStream::LDS_BYTES);
     attr = true;
   }
   if (which != UPD_OFFDIAG) {  // diagonal tiles first: they are the longest per block
-    const int SB = L.nb / UpdDiagStream::kBM;
+    const int SB = L.nb / UpdDiag64::kBM;
     const int64_t blocks = (int64_t)(jhi - jlo + 1) * SB * (SB + 1) / 2;
-    hipLaunchKernelGGL((k_update<UpdDiagStream, true>), dim3((unsigned)blocks),
-                       dim3(UpdDiagStream::THREADS), UpdDiagStream::LDS_BYTES, s, Astore, ps, k0,
+    hipLaunchKernelGGL((k_update<UpdDiag64, true>), dim3((unsigned)blocks),
+                       dim3(UpdDiag64::THREADS), UpdDiag64::LDS_BYTES, s, Astore, ps, k0,
                        npan, jlo, jhi, NT, L.nb, SB, pol.mode, pol.allow16, pol.allow8,
                        pol.high_panels, pol.fixed_prec, pol.thr, pmap, L.ntiles());
   }
@@ -1297,29 +1301,29 @@ static void factor_lockstep_t(const FactorJob *jobs, const int *nts, int nj, int
   if (!attr) {
     hipFuncSetAttribute((const void *)k_update_b<UpdStream, false>,
                         hipFuncAttributeMaxDynamicSharedMemorySize, UpdStream::LDS_BYTES);
-    hipFuncSetAttribute((const void *)k_update_b<UpdDiagStream, true>,
-                        hipFuncAttributeMaxDynamicSharedMemorySize, UpdDiagStream::LDS_BYTES);
+    hipFuncSetAttribute((const void *)k_update_b<UpdDiag64, true>,
+                        hipFuncAttributeMaxDynamicSharedMemorySize, UpdDiag64::LDS_BYTES);
     hipFuncSetAttribute((const void *)k_update_b<UpdDiagStream, false>,
                         hipFuncAttributeMaxDynamicSharedMemorySize, UpdDiagStream::LDS_BYTES);
     attr = true;
   }
-  // updates as launch_update does them: diagonal tiles (128 x 128 blocks),
+  // updates as launch_update does them: diagonal tiles (64 x 64 blocks),
   // then the off-diagonal ones, small blocks when the batch has few tiles
   // in all (grids sized for the instance with the most)
   auto update = [&](int k0, bool group) {
-    const int SBd = nb / UpdDiagStream::kBM, SBo = nb / UpdStream::kBM;
+    const int SBd = nb / UpdDiagStream::kBM, SBo = nb / UpdStream::kBM, SB64 = nb / UpdDiag64::kBM;
     int64_t md = 0, mo = 0, so = 0, mo_small = 0;
     int kf, npan, jlo, jhi;
     for (int b = 0; b < nj; ++b) {
-      md = std::max(md, update_extent(nts[b], k0, group, g, SBd, true, kf, npan, jlo, jhi));
+      md = std::max(md, update_extent(nts[b], k0, group, g, SB64, true, kf, npan, jlo, jhi));
       const int64_t off = update_extent(nts[b], k0, group, g, 1, false, kf, npan, jlo, jhi);
       mo = std::max(mo, off);
       so += off;
     }
     if (md > 0)
-      hipLaunchKernelGGL((k_update_b<UpdDiagStream, true>), dim3((unsigned)md, nj),
-                         dim3(UpdDiagStream::THREADS), UpdDiagStream::LDS_BYTES, s, jobs, k0,
-                         group ? 1 : 0, g, nb, SBd, pol.mode, pol.allow16, pol.allow8,
+      hipLaunchKernelGGL((k_update_b<UpdDiag64, true>), dim3((unsigned)md, nj),
+                         dim3(UpdDiag64::THREADS), UpdDiag64::LDS_BYTES, s, jobs, k0,
+                         group ? 1 : 0, g, nb, SB64, pol.mode, pol.allow16, pol.allow8,
                          pol.high_panels, pol.fixed_prec);
     if (mo <= 0) return;
     if (so * 4 < 8 * 256) {
