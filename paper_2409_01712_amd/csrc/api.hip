@@ -837,12 +837,13 @@ static krr_status factor_enqueue(krr_context ctx, krr_kernel K, krr_factorizatio
     launch_tile_inverses(F->Lst, F->Linv, 0, NT, L, fp.diag64, w, s);
   } else {
     // Three streams.  Main, the critical path: POTRF(k) (with the tile's
-    // last updates folded into its load) and the TRSM of row k+1 alone.  Side: the
-    // rest of each panel's TRSM, its operand copies, its updates of the
-    // group's later columns, and the group's update of the next group's
-    // columns.  Aux: each group's update of every column beyond the next
-    // group.  Events order all updates of any one tile, so the factor
-    // does not depend on the schedule.
+    // last updates folded into its load) and the TRSM of row k+1 alone.
+    // Side: the rest of each panel's TRSM, its operand copies, its updates
+    // of the group's later columns, and the group's update of the next
+    // group's columns.  Aux: each group's update of every column beyond the
+    // next group, started after the update of the next group's columns.
+    // Events order all updates of any one tile, so the factor does not
+    // depend on the schedule.
     hipStream_t sm = ctx->fmain, sd = ctx->side, sx = ctx->aux;
     const int ngroups = (NT + g - 1) / g;
     std::vector<hipEvent_t> &E = ctx->sched_ev;
@@ -897,11 +898,6 @@ static krr_status factor_enqueue(krr_context ctx, krr_kernel K, krr_factorizatio
       }
       if (gend >= NT) break;
       const int npan = gend - G0;
-      if (nend < NT) {  // aux: everything right of the next group
-        wait(sx, e_conv[gend - 1]);
-        update(G0, npan, nend, NT - 1, UPD_ALL, sx);
-      }
-      rec(e_aux[gi], sx);
       // the next group's columns, after the previous group's aux update
       // reached them; its first diagonal tile on the main stream
       if (gi > 0) {
@@ -911,6 +907,14 @@ static krr_status factor_enqueue(krr_context ctx, krr_kernel K, krr_factorizatio
       update(G0, npan, gend, nend - 1, UPD_OFFDIAG, sd);
       update(G0, npan, gend + 1, nend - 1, UPD_DIAG, sd);
       rec(e_narrow[gi], sd);
+      // aux: everything right of the next group, once the next group's
+      // columns are done, so that the update the main stream waits for does
+      // not share the chip with this much larger one
+      if (nend < NT) {
+        wait(sx, e_narrow[gi]);
+        update(G0, npan, nend, NT - 1, UPD_ALL, sx);
+      }
+      rec(e_aux[gi], sx);
     }
     // join on the caller's stream
     rec(e_join[1], sd);
