@@ -847,7 +847,7 @@ static krr_status factor_enqueue(krr_context ctx, krr_kernel K, krr_factorizatio
     hipStream_t sm = ctx->fmain, sd = ctx->side, sx = ctx->aux;
     const int ngroups = (NT + g - 1) / g;
     std::vector<hipEvent_t> &E = ctx->sched_ev;
-    const size_t need = (size_t)4 * NT + 2 * ngroups + 4;
+    const size_t need = (size_t)4 * NT + 2 * ngroups + 5;
     bool ok = true;
     while (ok && E.size() < need) {
       hipEvent_t e;
@@ -856,7 +856,12 @@ static krr_status factor_enqueue(krr_context ctx, krr_kernel K, krr_factorizatio
     }
     hipEvent_t *e_t1 = E.data(), *e_conv = e_t1 + NT, *e_uin = e_conv + NT,
                *e_udiag = e_uin + NT, *e_aux = e_udiag + NT, *e_narrow = e_aux + ngroups,
-               *e_join = e_narrow + ngroups;
+               *e_join = e_narrow + ngroups, e_early = e_join[4];
+    // Panel 0 (FP32 under the adaptive policies, so its updates are the
+    // costliest) goes to every column beyond the first group as soon as it
+    // exists, on aux while the first group is factored; the first group's
+    // boundary updates then carry panels 1 .. g-1 only.
+    const bool early0 = NT > g && g > 1;
     auto rec = [&](hipEvent_t e, hipStream_t st) {
       ok = ok && hipEventRecord(e, st) == hipSuccess;
     };
@@ -875,8 +880,14 @@ static krr_status factor_enqueue(krr_context ctx, krr_kernel K, krr_factorizatio
         // whole previous group (at its start); the earlier panels of the
         // group reached it through the side stream's diagonal updates
         if (k >= G0 + 2) wait(sm, e_udiag[k - 2]);
-        if (k > G0) potrf(k, k - 1, 1, sm);
-        else potrf(k, std::max(G0 - g, 0), G0 > 0 ? g : 0, sm);
+        if (k > G0) {
+          potrf(k, k - 1, 1, sm);
+        } else if (early0 && gi == 1) {  // panel 0 reached it through aux
+          wait(sm, e_early);
+          potrf(k, 1, g - 1, sm);
+        } else {
+          potrf(k, std::max(G0 - g, 0), G0 > 0 ? g : 0, sm);
+        }
         if (k + 1 >= NT) break;
         // column k below the diagonal: in-group updates (side), or the
         // previous group's update of this group's columns (side)
@@ -888,6 +899,11 @@ static krr_status factor_enqueue(krr_context ctx, krr_kernel K, krr_factorizatio
         trsm_gemm(k, 1, NT, sd);
         convert(k, sd);
         rec(e_conv[k], sd);
+        if (early0 && k == 0) {
+          wait(sx, e_conv[0]);
+          update(0, 1, gend, NT - 1, UPD_ALL, sx);
+          rec(e_early, sx);
+        }
         // column k+1 below the diagonal gets every panel of the group so far
         // in one product (the later columns wait for their turn), which is
         // all the next TRSM needs; then the diagonal tiles further right
@@ -897,22 +913,24 @@ static krr_status factor_enqueue(krr_context ctx, krr_kernel K, krr_factorizatio
         rec(e_udiag[k], sd);
       }
       if (gend >= NT) break;
-      const int npan = gend - G0;
+      const int p0 = (early0 && gi == 0) ? 1 : 0;  // panel 0 already applied beyond
+      const int q0 = G0 + p0, npan = gend - q0;
       // the next group's columns, after the previous group's aux update
       // reached them; its first diagonal tile on the main stream
       if (gi > 0) {
         wait(sm, e_aux[gi - 1]);
         wait(sd, e_aux[gi - 1]);
       }
-      update(G0, npan, gend, nend - 1, UPD_OFFDIAG, sd);
-      update(G0, npan, gend + 1, nend - 1, UPD_DIAG, sd);
+      if (p0) wait(sd, e_early);
+      update(q0, npan, gend, nend - 1, UPD_OFFDIAG, sd);
+      update(q0, npan, gend + 1, nend - 1, UPD_DIAG, sd);
       rec(e_narrow[gi], sd);
       // aux: everything right of the next group, once the next group's
       // columns are done, so that the update the main stream waits for does
       // not share the chip with this much larger one
       if (nend < NT) {
         wait(sx, e_narrow[gi]);
-        update(G0, npan, nend, NT - 1, UPD_ALL, sx);
+        update(q0, npan, nend, NT - 1, UPD_ALL, sx);
       }
       rec(e_aux[gi], sx);
     }
