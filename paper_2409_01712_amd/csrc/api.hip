@@ -1311,12 +1311,12 @@ static krr_status solve_alloc(Scoped &sc, const TileLayout &L, int r, SolveBufs 
   return KRR_SUCCESS;
 }
 
-// dst += L^-T L^-1 src with FP32 sweeps (src, dst: FP64, row-major np x r).
+// dst += L^-T L^-1 src with FP32 sweeps (src, dst: FP64, row-major np x r;
+// the sweeps work on column-major FP32 copies).
 static void solve_sweeps(krr_context ctx, krr_factorization F, int r, SolveBufs &b,
                          const double *src, double *dst, hipStream_t s) {
   const TileLayout &L = F->L;
-  const int64_t cnt = L.np * r;
-  launch_f64_to_f32(src, cnt, b.Bf, s);
+  launch_rows_f64_to_cols_f32(src, L.np, r, b.Bf, s);
   {
     Stage t(ctx, KRR_STAGE_FWD, s);
     launch_fwd_sweep(F->Lst, F->Linv, b.C, L, r, b.Bf, b.Zf, s);
@@ -1325,7 +1325,7 @@ static void solve_sweeps(krr_context ctx, krr_factorization F, int r, SolveBufs 
     Stage t(ctx, KRR_STAGE_BWD, s);
     launch_bwd_sweep(F->Lst, F->Linv, b.C, L, r, b.Zf, b.Xf, s);
   }
-  launch_axpy_f32_to_f64(b.Xf, cnt, 1.0, dst, s);
+  launch_cols_f32_axpy_rows_f64(b.Xf, L.np, r, 1.0, dst, s);
 }
 
 // R = Y - (K + lambda I) X in FP64, then the squared column norms of R and X

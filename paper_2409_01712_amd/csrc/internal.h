@@ -192,8 +192,9 @@ void launch_encode_fp8(const float *x, int64_t n, uint8_t *out, hipStream_t s);
 
 // ---- solve.hip ----
 // Internal right-hand sides are row-major np x r.
-// C: the coupling tiles of launch_sweep_coupling (tiles taken in pairs), or
-// null (one tile per step).
+// Right-hand sides of these two: FP32 column-major np x r (column stride
+// np).  C: the coupling tiles of launch_sweep_coupling (tiles taken in
+// pairs), or null (one tile per step).
 void launch_fwd_sweep(const float *Astore, const float *Linv, const float *C, const TileLayout &L,
                       int r, float *B, float *Z, hipStream_t s);
 void launch_bwd_sweep(const float *Astore, const float *Linv, const float *C, const TileLayout &L,
@@ -222,6 +223,11 @@ void launch_colmajor_to_rows(const double *src, int64_t n, int64_t ld, int r, in
 void launch_rows_to_colmajor(const double *src, int64_t n, int r, double *dst, int64_t ld,
                              hipStream_t s);
 void launch_f64_to_f32(const double *src, int64_t count, float *dst, hipStream_t s);
+// row-major FP64 np x r -> column-major FP32, and dst += alpha src back
+void launch_rows_f64_to_cols_f32(const double *src, int64_t np, int r, float *dst,
+                                 hipStream_t s);
+void launch_cols_f32_axpy_rows_f64(const float *src, int64_t np, int r, double alpha, double *dst,
+                                   hipStream_t s);
 void launch_axpy_f32_to_f64(const float *src, int64_t count, double alpha, double *dst,
                             hipStream_t s);
 void launch_col_norms(const double *A, int64_t n, int r, double *out, hipStream_t s);

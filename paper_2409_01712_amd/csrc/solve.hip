@@ -31,14 +31,62 @@ typedef double v4d __attribute__((ext_vector_type(4)));
 
 // One 16 x 16 output job per workgroup: out = M[row0 .. row0+15, klo .. khi)
 // V[klo .. khi, col0 .. col0+15] for an nb x nb FP32 tile M (row-major; with
-// TRANS read transposed, M(row, k) = Mt[k][row]) and an nb x r row-major
-// block V; klo, khi multiples of 16.  The four waves take the 16-wide k
+// TRANS read transposed, M(row, k) = Mt[k][row]) and an nb-row block V of r
+// columns, row-major (V(k, c) = V[k r + c]) or, with CM, column-major with
+// column stride ldv (V(k, c) = V[c ldv + k], four k per lane in one 16-byte
+// load); klo, khi multiples of 16.  The four waves take the 16-wide k
 // blocks round robin, each with all its loads in flight at once (at most
 // eight blocks: nb <= 512), and the partial sums are added in wave order.
-template <bool TRANS>
+// Four consecutive k of column cc of V into b (zeros when the column is past r).
+template <bool CM>
+__device__ __forceinline__ void load_v4(const float *V, int r, int64_t ldv, int kk, int cc,
+                                        bool cv, float sg, float (&b)[4]) {
+  if (CM) {
+    const float4 v = *(const float4 *)(V + (int64_t)cc * ldv + kk);
+    b[0] = cv ? sg * v.x : 0.f;
+    b[1] = cv ? sg * v.y : 0.f;
+    b[2] = cv ? sg * v.z : 0.f;
+    b[3] = cv ? sg * v.w : 0.f;
+  } else {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const float v = V[(int64_t)(kk + e) * r + cc];
+      b[e] = cv ? sg * v : 0.f;
+    }
+  }
+}
+
+// The 16 x 16 result of a job (rows row0 + 4 (lane / 16) + e, column col) into
+// o, or subtracted from it, in V's layout; lanes 0 .. 63 of the first wave.
+template <bool CM, bool SUB>
+__device__ __forceinline__ void store_job(float *o, int r, int64_t ldv, int row0, int col,
+                                          const v4f &acc) {
+  const int lane = threadIdx.x & 63;
+  if (threadIdx.x >= 64 || col >= r) return;
+  const int rb = row0 + 4 * (lane >> 4);
+  if (CM) {
+    float4 *q = (float4 *)(o + (int64_t)col * ldv + rb);
+    if (SUB) {
+      float4 v = *q;
+      v.x -= acc[0]; v.y -= acc[1]; v.z -= acc[2]; v.w -= acc[3];
+      *q = v;
+    } else {
+      *q = make_float4(acc[0], acc[1], acc[2], acc[3]);
+    }
+  } else {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      float *q = o + (int64_t)(rb + e) * r + col;
+      if (SUB) *q -= acc[e];
+      else *q = acc[e];
+    }
+  }
+}
+
+template <bool TRANS, bool CM>
 __device__ __forceinline__ v4f job_product(const float *__restrict__ M, const float *V, int nb,
-                                           int r, int row0, int col0, int klo, int khi,
-                                           v4f (*red)[64]) {
+                                           int r, int64_t ldv, int row0, int col0, int klo,
+                                           int khi, v4f (*red)[64]) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int li = lane & 15, lg = lane >> 4;
   const int R = row0 + li, col = col0 + li;
@@ -57,11 +105,7 @@ __device__ __forceinline__ v4f job_product(const float *__restrict__ M, const fl
 #pragma unroll
         for (int e = 0; e < 4; ++e) a[u][e] = M[(int64_t)(kk + e) * nb + R];
       }
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const float v = V[(int64_t)(kk + e) * r + cc];
-        b[u][e] = cv ? v : 0.f;
-      }
+      load_v4<CM>(V, r, ldv, kk, cc, cv, 1.f, b[u]);
     } else {
 #pragma unroll
       for (int e = 0; e < 4; ++e) a[u][e] = b[u][e] = 0.f;
@@ -85,11 +129,12 @@ __device__ __forceinline__ v4f job_product(const float *__restrict__ M, const fl
 // and [klo2, khi2), multiples of 16, each at most nb <= 512 wide): the
 // 16-wide k blocks of both are dealt round robin to the four waves, at most
 // sixteen per wave, all loads of a wave in flight before its MFMAs.
-template <bool TRANS>
+template <bool TRANS, bool CM>
 __device__ __forceinline__ v4f job_product2(const float *__restrict__ M1, const float *V1,
                                             int klo1, int khi1, const float *__restrict__ M2,
                                             const float *V2, int klo2, int khi2, float sign2,
-                                            int nb, int r, int row0, int col0, v4f (*red)[64]) {
+                                            int nb, int r, int64_t ldv, int row0, int col0,
+                                            v4f (*red)[64]) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int li = lane & 15, lg = lane >> 4;
   const int R = row0 + li, col = col0 + li;
@@ -113,11 +158,7 @@ __device__ __forceinline__ v4f job_product2(const float *__restrict__ M1, const 
 #pragma unroll
         for (int e = 0; e < 4; ++e) a[u][e] = M[(int64_t)(kk + e) * nb + R];
       }
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const float v = V[(int64_t)(kk + e) * r + cc];
-        b[u][e] = cv ? sg * v : 0.f;
-      }
+      load_v4<CM>(V, r, ldv, kk, cc, cv, sg, b[u]);
     } else {
 #pragma unroll
       for (int e = 0; e < 4; ++e) a[u][e] = b[u][e] = 0.f;
@@ -137,38 +178,43 @@ __device__ __forceinline__ v4f job_product2(const float *__restrict__ M1, const 
   return sum;
 }
 
+// Right-hand-side blocks of the sweeps: rows of tile t start at t nb r
+// (row-major) or t nb (CM: column-major, column stride ldv = np).
+template <bool CM>
+KRR_DEV int64_t tile_off(int64_t t, int nb, int r) {
+  return CM ? t * nb : t * nb * (int64_t)r;
+}
+
 // Sweep step k, diagonal part:
 //   forward  Z_k = inv(L_kk) B_k     (rows of the inverse need k <= row)
 //   backward X_k = inv(L_kk)^T Z_k   (its transpose, k >= row)
-template <bool FWD>
+template <bool FWD, bool CM>
 __device__ __forceinline__ void sweep_diag_body(const float *__restrict__ Linv_k, const float *In_k,
-                                                float *Out_k, int nb, int r, int bid) {
+                                                float *Out_k, int nb, int r, int64_t ldv,
+                                                int bid) {
   __shared__ v4f red[4][64];
   const int CJ = (r + 15) / 16;
   const int rj = bid / CJ, cj = bid % CJ;
   const int row0 = rj * 16, col0 = cj * 16;
-  const v4f acc = job_product<!FWD>(Linv_k, In_k, nb, r, row0, col0, FWD ? 0 : row0,
-                                    FWD ? row0 + 16 : nb, red);
-  const int lane = threadIdx.x & 63, col = col0 + (lane & 15);
-  if (threadIdx.x < 64 && col < r) {
-#pragma unroll
-    for (int e = 0; e < 4; ++e) Out_k[(int64_t)(row0 + 4 * (lane >> 4) + e) * r + col] = acc[e];
-  }
+  const v4f acc = job_product<!FWD, CM>(Linv_k, In_k, nb, r, ldv, row0, col0, FWD ? 0 : row0,
+                                        FWD ? row0 + 16 : nb, red);
+  store_job<CM, false>(Out_k, r, ldv, row0, col0 + (threadIdx.x & 15), acc);
 }
 
 template <bool FWD>
 __global__ __launch_bounds__(256) void k_sweep_diag(const float *__restrict__ Linv_k,
                                                     const float *In_k, float *Out_k, int nb,
-                                                    int r) {
-  sweep_diag_body<FWD>(Linv_k, In_k, Out_k, nb, r, blockIdx.x);
+                                                    int r, int64_t ldv) {
+  sweep_diag_body<FWD, true>(Linv_k, In_k, Out_k, nb, r, ldv, blockIdx.x);
 }
 
 // Sweep step k, update part (one job per workgroup):
 //   forward  B_i -= L_ik Z_k,   i > k
 //   backward Z_j -= L_kj^T X_k, j < k
-template <bool FWD>
+template <bool FWD, bool CM>
 __device__ __forceinline__ void sweep_panel_body(const float *__restrict__ Lst, const float *V_k,
-                                                 float *In, int k, int nb, int r, int64_t bid) {
+                                                 float *In, int k, int nb, int r, int64_t ldv,
+                                                 int64_t bid) {
   __shared__ v4f red[4][64];
   const int CJ = (r + 15) / 16, per = (nb / 16) * CJ;
   const int64_t t = bid / per;
@@ -177,20 +223,15 @@ __device__ __forceinline__ void sweep_panel_body(const float *__restrict__ Lst, 
   const int64_t te = (int64_t)nb * nb;
   const float *M = Lst + (FWD ? i * (i + 1) / 2 + k : (int64_t)k * (k + 1) / 2 + i) * te;
   const int row0 = rj * 16, col0 = cj * 16;
-  const v4f acc = job_product<!FWD>(M, V_k, nb, r, row0, col0, 0, nb, red);
-  const int lane = threadIdx.x & 63, col = col0 + (lane & 15);
-  if (threadIdx.x < 64 && col < r) {
-    float *o = In + i * (int64_t)nb * r;
-#pragma unroll
-    for (int e = 0; e < 4; ++e) o[(int64_t)(row0 + 4 * (lane >> 4) + e) * r + col] -= acc[e];
-  }
+  const v4f acc = job_product<!FWD, CM>(M, V_k, nb, r, ldv, row0, col0, 0, nb, red);
+  store_job<CM, true>(In + tile_off<CM>(i, nb, r), r, ldv, row0, col0 + (threadIdx.x & 15), acc);
 }
 
 template <bool FWD>
 __global__ __launch_bounds__(256) void k_sweep_panel(const float *__restrict__ Lst,
                                                      const float *V_k, float *In, int k, int nb,
-                                                     int r) {
-  sweep_panel_body<FWD>(Lst, V_k, In, k, nb, r, blockIdx.x);
+                                                     int r, int64_t ldv) {
+  sweep_panel_body<FWD, true>(Lst, V_k, In, k, nb, r, ldv, blockIdx.x);
 }
 
 // Paired sweep steps over the tiles (k, k+1) = (2p, 2p+1), with the coupling
@@ -200,38 +241,39 @@ __global__ __launch_bounds__(256) void k_sweep_panel(const float *__restrict__ L
 //            B_i -= L_ik Z_k + L_i,k+1 Z_k+1,  i > k+1;
 //   backward X_k+1 = inv(L_k+1,k+1)^T Z_k+1,  X_k = inv(L_kk)^T Z_k - C_p^T Z_k+1,
 //            Z_j -= L_kj^T X_k + L_k+1,j^T X_k+1,  j < k.
-// Diagonal launch: 2 x per workgroups, the first per for tile k's rows.
+// Right-hand sides column-major (column stride ldv).  Diagonal launch:
+// 2 x per workgroups, the first per for tile k's rows.
 template <bool FWD>
 __global__ __launch_bounds__(256) void k_sweep_diag2(const float *__restrict__ Linv,
                                                      const float *__restrict__ Cp, const float *In,
-                                                     float *Out, int k, int nb, int r) {
+                                                     float *Out, int k, int nb, int r,
+                                                     int64_t ldv) {
   __shared__ v4f red[4][64];
   const int CJ = (r + 15) / 16, per = (nb / 16) * CJ;
   const int half = blockIdx.x / per, rem = blockIdx.x % per;
   const int rj = rem / CJ, cj = rem % CJ;
   const int row0 = rj * 16, col0 = cj * 16;
-  const int64_t te = (int64_t)nb * nb, vb = (int64_t)nb * r;
+  const int64_t te = (int64_t)nb * nb;
   const float *Li0 = Linv + (int64_t)k * te, *Li1 = Linv + (int64_t)(k + 1) * te;
-  const float *In0 = In + (int64_t)k * vb, *In1 = In + (int64_t)(k + 1) * vb;
+  const float *In0 = In + tile_off<true>(k, nb, r), *In1 = In + tile_off<true>(k + 1, nb, r);
   v4f acc;
   if (FWD) {
     if (half == 0)
-      acc = job_product2<false>(Li0, In0, 0, row0 + 16, Cp, In0, 0, 0, 0.f, nb, r, row0, col0, red);
+      acc = job_product2<false, true>(Li0, In0, 0, row0 + 16, Cp, In0, 0, 0, 0.f, nb, r, ldv,
+                                      row0, col0, red);
     else
-      acc = job_product2<false>(Li1, In1, 0, row0 + 16, Cp, In0, 0, nb, -1.f, nb, r, row0, col0,
-                                red);
+      acc = job_product2<false, true>(Li1, In1, 0, row0 + 16, Cp, In0, 0, nb, -1.f, nb, r, ldv,
+                                      row0, col0, red);
   } else {
     if (half == 1)
-      acc = job_product2<true>(Li1, In1, row0, nb, Cp, In1, 0, 0, 0.f, nb, r, row0, col0, red);
+      acc = job_product2<true, true>(Li1, In1, row0, nb, Cp, In1, 0, 0, 0.f, nb, r, ldv, row0,
+                                     col0, red);
     else
-      acc = job_product2<true>(Li0, In0, row0, nb, Cp, In1, 0, nb, -1.f, nb, r, row0, col0, red);
+      acc = job_product2<true, true>(Li0, In0, row0, nb, Cp, In1, 0, nb, -1.f, nb, r, ldv, row0,
+                                     col0, red);
   }
-  const int lane = threadIdx.x & 63, col = col0 + (lane & 15);
-  if (threadIdx.x < 64 && col < r) {
-    float *o = Out + (int64_t)(k + half) * vb;
-#pragma unroll
-    for (int e = 0; e < 4; ++e) o[(int64_t)(row0 + 4 * (lane >> 4) + e) * r + col] = acc[e];
-  }
+  store_job<true, false>(Out + tile_off<true>(k + half, nb, r), r, ldv, row0,
+                         col0 + (threadIdx.x & 15), acc);
 }
 
 // Panel launch of a pair: one job per workgroup, tile t of the panel rows
@@ -239,24 +281,21 @@ __global__ __launch_bounds__(256) void k_sweep_diag2(const float *__restrict__ L
 template <bool FWD>
 __global__ __launch_bounds__(256) void k_sweep_panel2(const float *__restrict__ Lst,
                                                       const float *V, float *In, int k, int nb,
-                                                      int r) {
+                                                      int r, int64_t ldv) {
   __shared__ v4f red[4][64];
   const int CJ = (r + 15) / 16, per = (nb / 16) * CJ;
   const int64_t t = blockIdx.x / per;
   const int rem = (int)(blockIdx.x % per), rj = rem / CJ, cj = rem % CJ;
-  const int64_t te = (int64_t)nb * nb, vb = (int64_t)nb * r;
+  const int64_t te = (int64_t)nb * nb;
   const int64_t i = FWD ? k + 2 + t : t;
   const float *M1 = Lst + (FWD ? tri_index(i, k) : tri_index(k, i)) * te;
   const float *M2 = Lst + (FWD ? tri_index(i, k + 1) : tri_index(k + 1, i)) * te;
   const int row0 = rj * 16, col0 = cj * 16;
-  const v4f acc = job_product2<!FWD>(M1, V + (int64_t)k * vb, 0, nb, M2, V + (int64_t)(k + 1) * vb,
-                                     0, nb, 1.f, nb, r, row0, col0, red);
-  const int lane = threadIdx.x & 63, col = col0 + (lane & 15);
-  if (threadIdx.x < 64 && col < r) {
-    float *o = In + i * vb;
-#pragma unroll
-    for (int e = 0; e < 4; ++e) o[(int64_t)(row0 + 4 * (lane >> 4) + e) * r + col] -= acc[e];
-  }
+  const v4f acc = job_product2<!FWD, true>(M1, V + tile_off<true>(k, nb, r), 0, nb, M2,
+                                           V + tile_off<true>(k + 1, nb, r), 0, nb, 1.f, nb, r,
+                                           ldv, row0, col0, red);
+  store_job<true, true>(In + tile_off<true>(i, nb, r), r, ldv, row0, col0 + (threadIdx.x & 15),
+                        acc);
 }
 
 // The same steps for a batch of instances in lockstep (blockIdx.y = instance):
@@ -268,8 +307,8 @@ __global__ __launch_bounds__(256) void k_sweep_diag_b(const SolveJob *__restrict
   const SolveJob &j = jobs[blockIdx.y];
   if (k >= j.nt) return;
   const int64_t te = (int64_t)nb * nb, vb = (int64_t)nb * r;
-  sweep_diag_body<FWD>(j.Linv + k * te, (FWD ? j.B : j.Z) + k * vb, (FWD ? j.Z : j.X) + k * vb, nb,
-                       r, blockIdx.x);
+  sweep_diag_body<FWD, false>(j.Linv + k * te, (FWD ? j.B : j.Z) + k * vb,
+                              (FWD ? j.Z : j.X) + k * vb, nb, r, 0, blockIdx.x);
 }
 
 template <bool FWD>
@@ -280,7 +319,8 @@ __global__ __launch_bounds__(256) void k_sweep_panel_b(const SolveJob *__restric
   const int t = (int)(blockIdx.x / per);
   if (k >= j.nt || (FWD ? k + 1 + t >= j.nt : t >= k)) return;
   const int64_t vb = (int64_t)nb * r;
-  sweep_panel_body<FWD>(j.Lst, (FWD ? j.Z : j.X) + k * vb, FWD ? j.B : j.Z, k, nb, r, blockIdx.x);
+  sweep_panel_body<FWD, false>(j.Lst, (FWD ? j.Z : j.X) + k * vb, FWD ? j.B : j.Z, k, nb, r, 0,
+                               blockIdx.x);
 }
 
 void launch_sweeps_batched(const SolveJob *jobs, int njobs, int ntmax, int nb, int r,
@@ -300,28 +340,28 @@ void launch_sweeps_batched(const SolveJob *jobs, int njobs, int ntmax, int nb, i
   }
 }
 
-// L Z = B (B is overwritten).  With the coupling tiles C (nt / 2 of them, or
-// null) the tiles go in pairs (0, 1), (2, 3), ..., the last one alone when nt
-// is odd.
+// L Z = B (B is overwritten), right-hand sides column-major np x r (column
+// stride np).  With the coupling tiles C (nt / 2 of them, or null) the tiles
+// go in pairs (0, 1), (2, 3), ..., the last one alone when nt is odd.
 void launch_fwd_sweep(const float *Astore, const float *Linv, const float *C, const TileLayout &L,
                       int r, float *B, float *Z, hipStream_t s) {
   const int nb = L.nb, NT = L.nt, CJ = (r + 15) / 16, per = (nb / 16) * CJ;
-  const int64_t te = (int64_t)nb * nb, vb = (int64_t)nb * r;
+  const int64_t te = (int64_t)nb * nb, ldv = L.np;
   for (int k = 0; k < NT;) {
     if (C && k + 1 < NT) {
       hipLaunchKernelGGL(k_sweep_diag2<true>, dim3(2 * per), dim3(256), 0, s, Linv,
-                         C + (int64_t)(k / 2) * te, B, Z, k, nb, r);
+                         C + (int64_t)(k / 2) * te, B, Z, k, nb, r, ldv);
       if (NT - 2 - k > 0)
         hipLaunchKernelGGL(k_sweep_panel2<true>, dim3((unsigned)((NT - 2 - k) * per)), dim3(256),
-                           0, s, Astore, Z, B, k, nb, r);
+                           0, s, Astore, Z, B, k, nb, r, ldv);
       k += 2;
       continue;
     }
-    hipLaunchKernelGGL(k_sweep_diag<true>, dim3(per), dim3(256), 0, s, Linv + k * te, B + k * vb,
-                       Z + k * vb, nb, r);
+    hipLaunchKernelGGL(k_sweep_diag<true>, dim3(per), dim3(256), 0, s, Linv + k * te,
+                       B + (int64_t)k * nb, Z + (int64_t)k * nb, nb, r, ldv);
     if (NT - 1 - k > 0)
       hipLaunchKernelGGL(k_sweep_panel<true>, dim3((unsigned)((NT - 1 - k) * per)), dim3(256), 0,
-                         s, Astore, Z + k * vb, B, k, nb, r);
+                         s, Astore, Z + (int64_t)k * nb, B, k, nb, r, ldv);
     ++k;
   }
 }
@@ -330,25 +370,57 @@ void launch_fwd_sweep(const float *Astore, const float *Linv, const float *C, co
 void launch_bwd_sweep(const float *Astore, const float *Linv, const float *C, const TileLayout &L,
                       int r, float *Z, float *X, hipStream_t s) {
   const int nb = L.nb, NT = L.nt, CJ = (r + 15) / 16, per = (nb / 16) * CJ;
-  const int64_t te = (int64_t)nb * nb, vb = (int64_t)nb * r;
+  const int64_t te = (int64_t)nb * nb, ldv = L.np;
   for (int k = NT - 1; k >= 0;) {
     if (C && k % 2 == 1) {  // the pair (k-1, k)
       const int k0 = k - 1;
       hipLaunchKernelGGL(k_sweep_diag2<false>, dim3(2 * per), dim3(256), 0, s, Linv,
-                         C + (int64_t)(k0 / 2) * te, Z, X, k0, nb, r);
+                         C + (int64_t)(k0 / 2) * te, Z, X, k0, nb, r, ldv);
       if (k0 > 0)
         hipLaunchKernelGGL(k_sweep_panel2<false>, dim3((unsigned)(k0 * per)), dim3(256), 0, s,
-                           Astore, X, Z, k0, nb, r);
+                           Astore, X, Z, k0, nb, r, ldv);
       k -= 2;
       continue;
     }
-    hipLaunchKernelGGL(k_sweep_diag<false>, dim3(per), dim3(256), 0, s, Linv + k * te, Z + k * vb,
-                       X + k * vb, nb, r);
+    hipLaunchKernelGGL(k_sweep_diag<false>, dim3(per), dim3(256), 0, s, Linv + k * te,
+                       Z + (int64_t)k * nb, X + (int64_t)k * nb, nb, r, ldv);
     if (k > 0)
       hipLaunchKernelGGL(k_sweep_panel<false>, dim3((unsigned)(k * per)), dim3(256), 0, s, Astore,
-                         X + k * vb, Z, k, nb, r);
+                         X + (int64_t)k * nb, Z, k, nb, r, ldv);
     --k;
   }
+}
+
+// Row-major FP64 np x r into column-major FP32 (column stride np), and back
+// as dst += alpha src: the layout changes of the sweeps' right-hand sides.
+__global__ void k_rows_f64_to_cols_f32(const double *__restrict__ src, int64_t np, int r,
+                                       float *__restrict__ dst) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= np * r) return;
+  const int64_t c = e / np, i = e % np;
+  dst[e] = (float)src[i * r + c];
+}
+
+__global__ void k_cols_f32_axpy_rows_f64(const float *__restrict__ src, int64_t np, int r,
+                                         double alpha, double *__restrict__ dst) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= np * r) return;
+  const int64_t c = e / np, i = e % np;
+  dst[i * r + c] += alpha * (double)src[e];
+}
+
+void launch_rows_f64_to_cols_f32(const double *src, int64_t np, int r, float *dst,
+                                 hipStream_t s) {
+  const int64_t cnt = np * r;
+  hipLaunchKernelGGL(k_rows_f64_to_cols_f32, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s,
+                     src, np, r, dst);
+}
+
+void launch_cols_f32_axpy_rows_f64(const float *src, int64_t np, int r, double alpha, double *dst,
+                                   hipStream_t s) {
+  const int64_t cnt = np * r;
+  hipLaunchKernelGGL(k_cols_f32_axpy_rows_f64, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0,
+                     s, src, np, r, alpha, dst);
 }
 
 // ---------------------------------------------------------------------------
