@@ -1603,8 +1603,8 @@ krr_status krr_solve_batched(krr_context ctx, int32_t batch, const krr_factoriza
       }
       for (int b : ids) {
         const TileLayout &L = F[b]->L;
-        launch_residual_sum(B[b].Pr, residual_split(L), L, r, F[b]->K->lambda, B[b].Xr, B[b].Yr,
-                            B[b].Rr, s);
+        launch_residual_sum(B[b].Pr, residual_split_batched(L), L, r, F[b]->K->lambda, B[b].Xr,
+                            B[b].Yr, B[b].Rr, s);
         launch_col_norms(B[b].Rr, L.np, r, B[b].cn, s);
         launch_col_norms(B[b].Xr, L.np, r, B[b].cn + r, s);
         HIPCHK(hipMemcpyAsync(hn.data() + 2 * (size_t)r * b, B[b].cn, 2 * r * 8,

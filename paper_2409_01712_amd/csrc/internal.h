@@ -202,6 +202,8 @@ void launch_bwd_sweep(const float *Astore, const float *Linv, const float *C, co
 // R = Y - (K + lambda I) X in FP64; part: residual_split(L) * np * r doubles
 // of workspace for the partial products.
 int residual_split(const TileLayout &L);
+// the same for the lockstep batch (at most residual_split)
+int residual_split_batched(const TileLayout &L);
 void launch_residual(const int32_t *D, const double *etab, int64_t etab_len, double gamma,
                      double lambda, const TileLayout &L, int r, const double *X, const double *Y,
                      double *R, double *part, hipStream_t s);
