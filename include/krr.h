@@ -175,7 +175,7 @@ krr_status krr_factor_get_info(krr_factorization F, krr_factor_info *info);
  * phenotype columns, by FP32 forward/back substitution with the factor and
  * refinement against an FP64 residual recomputed from the exact distances
  * (classical refinement or preconditioned conjugate gradients, opts->method).
- * Convergence is always judged on a freshly computed residual of the final X.
+ * Convergence is always decided on a freshly computed residual of the final X.
  * Y, X: n x nrhs FP64 column-major on the device.  opts/info may be NULL.
  * Returns KRR_ERROR_NOT_CONVERGED if the tolerance is not met within
  * max_iters (X holds the last iterate).  Blocks once per iteration.
