@@ -141,35 +141,41 @@ __device__ __forceinline__ v4f job_product2(const float *__restrict__ M1, const 
   const int cc = min(col, r - 1);
   const bool cv = col < r;
   const int n1 = (khi1 - klo1) / 16, n2 = (khi2 - klo2) / 16;
-  float a[16][4], b[16][4];
-#pragma unroll
-  for (int u = 0; u < 16; ++u) {
-    const int g = wave + 4 * u;
-    const bool first = g < n1;
-    if (g < n1 + n2) {
-      const float *M = first ? M1 : M2;
-      const float *V = first ? V1 : V2;
-      const int kk = (first ? klo1 + 16 * g : klo2 + 16 * (g - n1)) + 4 * lg;
-      const float sg = first ? 1.0f : sign2;
-      if (!TRANS) {
-        const float4 v = *(const float4 *)(M + (int64_t)R * nb + kk);
-        a[u][0] = v.x; a[u][1] = v.y; a[u][2] = v.z; a[u][3] = v.w;
-      } else {
-#pragma unroll
-        for (int e = 0; e < 4; ++e) a[u][e] = M[(int64_t)(kk + e) * nb + R];
-      }
-      load_v4<CM>(V, r, ldv, kk, cc, cv, sg, b[u]);
-    } else {
-#pragma unroll
-      for (int e = 0; e < 4; ++e) a[u][e] = b[u][e] = 0.f;
-    }
-  }
+  // two phases of eight blocks: half the registers of one phase of sixteen,
+  // so more workgroups stay resident; the sum order over u is unchanged
   v4f acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-  for (int u = 0; u < 16; ++u)
+  for (int ph = 0; ph < 2; ++ph) {
+    float a[8][4], b[8][4];
 #pragma unroll
-    for (int e = 0; e < 4; ++e)
-      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u][e], b[u][e], acc, 0, 0, 0);
+    for (int uu = 0; uu < 8; ++uu) {
+      const int g = wave + 4 * (8 * ph + uu);
+      const bool first = g < n1;
+      if (g < n1 + n2) {
+        const float *M = first ? M1 : M2;
+        const float *V = first ? V1 : V2;
+        const int kk = (first ? klo1 + 16 * g : klo2 + 16 * (g - n1)) + 4 * lg;
+        const float sg = first ? 1.0f : sign2;
+        if (!TRANS) {
+          const float4 v = *(const float4 *)(M + (int64_t)R * nb + kk);
+          a[uu][0] = v.x; a[uu][1] = v.y; a[uu][2] = v.z; a[uu][3] = v.w;
+        } else {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) a[uu][e] = M[(int64_t)(kk + e) * nb + R];
+        }
+        load_v4<CM>(V, r, ldv, kk, cc, cv, sg, b[uu]);
+      } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) a[uu][e] = b[uu][e] = 0.f;
+      }
+    }
+#pragma unroll
+    for (int uu = 0; uu < 8; ++uu)
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[uu][e], b[uu][e], acc, 0, 0, 0);
+    __builtin_amdgcn_sched_barrier(0);
+  }
   red[wave][lane] = acc;
   __syncthreads();
   v4f sum = red[0][lane];
