@@ -5,7 +5,9 @@
 // substitution ... in the full FP32 precision", subsection on Ridge
 // Regression) for all phenotype columns at once: per tile step, the
 // diagonal block is applied through its inverse and the panel below (or
-// beside) is updated.  The FP64 residual r = Y - (K + lambda I) X recomputes
+// beside) is updated; one instance takes the tiles in pairs, with a
+// coupling tile standing in for the step between the two.  Refinement runs
+// classical iterations or conjugate gradients preconditioned by the factor.  The FP64 residual r = Y - (K + lambda I) X recomputes
 // every kernel entry from the exact int32 distance through the FP64 table
 // exp(-gamma d).
 #include <algorithm>
