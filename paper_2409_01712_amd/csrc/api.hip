@@ -1277,6 +1277,7 @@ struct SolveBufs {
   double *Yr = nullptr, *Xr = nullptr, *Rr = nullptr, *cn = nullptr, *Pr = nullptr;
   float *Bf = nullptr, *Zf = nullptr, *Xf = nullptr;
   const float *C = nullptr;  // coupling tiles of the paired sweeps, or null
+  double *cw = nullptr;      // workspace of the column reductions
 };
 
 // The coupling tiles of the paired sweeps, formed on the first solve with a
@@ -1305,6 +1306,7 @@ static krr_status solve_alloc(Scoped &sc, const TileLayout &L, int r, SolveBufs 
   CHK(sc.alloc(&b.Xr, cnt));
   CHK(sc.alloc(&b.Rr, cnt));
   CHK(sc.alloc(&b.cn, 2 * r));
+  CHK(sc.alloc(&b.cw, col_dots_workspace(r)));
   CHK(sc.alloc(&b.Bf, cnt));
   CHK(sc.alloc(&b.Zf, cnt));
   CHK(sc.alloc(&b.Xf, cnt));
@@ -1339,8 +1341,8 @@ static void residual_norms(krr_context ctx, krr_factorization F, int r, SolveBuf
     launch_residual(K->D, K->etab, K->etab_len, K->gamma, K->lambda, L, r, b.Xr, b.Yr, b.Rr, b.Pr,
                     s);
   }
-  launch_col_norms(b.Rr, L.np, r, b.cn, s);
-  launch_col_norms(b.Xr, L.np, r, b.cn + r, s);
+  launch_col_norms(b.Rr, L.np, r, b.cn, b.cw, s);
+  launch_col_norms(b.Xr, L.np, r, b.cn + r, b.cw, s);
 }
 
 // The refinement's stop quantities from the squared norms: the forward-error
@@ -1393,7 +1395,7 @@ static krr_status pcg_run(krr_context ctx, krr_factorization F, int r, SolveBufs
   launch_fill_f64(pb.Z, cnt, 0.0, s);
   solve_sweeps(ctx, F, r, b, b.Rr, pb.Z, s);
   launch_pcg_dir(pb.P, pb.Z, nullptr, nullptr, cnt, r, s);
-  launch_col_dots(b.Rr, pb.Z, L.np, r, rho, s);
+  launch_col_dots(b.Rr, pb.Z, L.np, r, rho, b.cw, s);
   std::vector<double> hn(2 * r);
   while (it < o.max_iters) {
     {
@@ -1401,11 +1403,11 @@ static krr_status pcg_run(krr_context ctx, krr_factorization F, int r, SolveBufs
       launch_residual(K->D, K->etab, K->etab_len, K->gamma, K->lambda, L, r, pb.P, pb.Y0, pb.Nq,
                       b.Pr, s);
     }
-    launch_col_dots(pb.P, pb.Nq, L.np, r, pnq, s);
+    launch_col_dots(pb.P, pb.Nq, L.np, r, pnq, b.cw, s);
     launch_pcg_step(b.Xr, b.Rr, pb.P, pb.Nq, rho, pnq, cnt, r, s);
     ++it;
-    launch_col_norms(b.Rr, L.np, r, b.cn, s);
-    launch_col_norms(b.Xr, L.np, r, b.cn + r, s);
+    launch_col_norms(b.Rr, L.np, r, b.cn, b.cw, s);
+    launch_col_norms(b.Xr, L.np, r, b.cn + r, b.cw, s);
     CHK(launch_ok());
     HIPCHK(hipMemcpyAsync(hn.data(), b.cn, 2 * r * 8, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
@@ -1415,7 +1417,7 @@ static krr_status pcg_run(krr_context ctx, krr_factorization F, int r, SolveBufs
     if (bound <= o.tol) break;
     launch_fill_f64(pb.Z, cnt, 0.0, s);
     solve_sweeps(ctx, F, r, b, b.Rr, pb.Z, s);
-    launch_col_dots(b.Rr, pb.Z, L.np, r, rho_next, s);
+    launch_col_dots(b.Rr, pb.Z, L.np, r, rho_next, b.cw, s);
     launch_pcg_dir(pb.P, pb.Z, rho_next, rho, cnt, r, s);
     std::swap(rho, rho_next);
   }
@@ -1448,7 +1450,7 @@ krr_status krr_solve(krr_context ctx, krr_factorization F, const double *Y, int6
   krr_status st = KRR_SUCCESS;
   if (o.method != KRR_REFINE_NONE) {
     std::vector<double> hn(2 * r), yn(r);
-    launch_col_norms(b.Yr, L.np, r, b.cn, s);
+    launch_col_norms(b.Yr, L.np, r, b.cn, b.cw, s);
     HIPCHK(hipMemcpyAsync(yn.data(), b.cn, r * 8, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     PcgBufs pb;
@@ -1588,7 +1590,7 @@ krr_status krr_solve_batched(krr_context ctx, int32_t batch, const krr_factoriza
   std::vector<double> hn(2 * (size_t)r * batch), yn((size_t)r * batch);
   if (o.method != KRR_REFINE_NONE) {
     for (int b = 0; b < batch; ++b) {
-      launch_col_norms(B[b].Yr, F[b]->L.np, r, B[b].cn, s);
+      launch_col_norms(B[b].Yr, F[b]->L.np, r, B[b].cn, B[b].cw, s);
       HIPCHK(hipMemcpyAsync(yn.data() + (size_t)r * b, B[b].cn, r * 8, hipMemcpyDeviceToHost, s));
     }
     HIPCHK(hipStreamSynchronize(s));
@@ -1605,8 +1607,8 @@ krr_status krr_solve_batched(krr_context ctx, int32_t batch, const krr_factoriza
         const TileLayout &L = F[b]->L;
         launch_residual_sum(B[b].Pr, residual_split_batched(L), L, r, F[b]->K->lambda, B[b].Xr,
                             B[b].Yr, B[b].Rr, s);
-        launch_col_norms(B[b].Rr, L.np, r, B[b].cn, s);
-        launch_col_norms(B[b].Xr, L.np, r, B[b].cn + r, s);
+        launch_col_norms(B[b].Rr, L.np, r, B[b].cn, B[b].cw, s);
+        launch_col_norms(B[b].Xr, L.np, r, B[b].cn + r, B[b].cw, s);
         HIPCHK(hipMemcpyAsync(hn.data() + 2 * (size_t)r * b, B[b].cn, 2 * r * 8,
                               hipMemcpyDeviceToHost, s));
       }

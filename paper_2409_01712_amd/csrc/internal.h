@@ -232,8 +232,11 @@ void launch_cols_f32_axpy_rows_f64(const float *src, int64_t np, int r, double a
                                    hipStream_t s);
 void launch_axpy_f32_to_f64(const float *src, int64_t count, double alpha, double *dst,
                             hipStream_t s);
-void launch_col_norms(const double *A, int64_t n, int r, double *out, hipStream_t s);
-void launch_col_dots(const double *A, const double *B, int64_t n, int r, double *out,
+// Column dot products / squared norms of row-major n x r FP64 matrices into
+// out[0 .. r); ws: col_dots_workspace(r) doubles.
+int col_dots_workspace(int r);
+void launch_col_norms(const double *A, int64_t n, int r, double *out, double *ws, hipStream_t s);
+void launch_col_dots(const double *A, const double *B, int64_t n, int r, double *out, double *ws,
                      hipStream_t s);
 // Preconditioned conjugate gradients on the columns of row-major count / r x r
 // matrices: x += alpha p, res -= alpha A p from nq = -A p, alpha = rho / (p . A p)

@@ -850,26 +850,42 @@ void launch_axpy_f32_to_f64(const float *src, int64_t count, double alpha, doubl
                      src, count, alpha, dst);
 }
 
-// Column dot products sum_i A_ic B_ic of two row-major n x r FP64 matrices,
-// fixed order (squared column norms when B = A).
-__global__ __launch_bounds__(256) void k_col_dots(const double *__restrict__ A,
-                                                  const double *__restrict__ B, int64_t n, int r,
-                                                  double *__restrict__ out) {
+// Column dot products sum_i A_ic B_ic of two row-major n x r FP64 matrices
+// (squared column norms when B = A), in a fixed order: COL_SPLIT slices of
+// rows summed per column by one workgroup each into ws, then the slices
+// added in slice order.
+constexpr int COL_SPLIT = 32;
+
+__global__ __launch_bounds__(256) void k_col_dots_part(const double *__restrict__ A,
+                                                       const double *__restrict__ B, int64_t n,
+                                                       int r, double *__restrict__ ws) {
   __shared__ double sh[4];
-  const int c = blockIdx.x;
+  const int c = blockIdx.x, sl = blockIdx.y;
+  const int64_t i0 = n * sl / COL_SPLIT, i1 = n * (sl + 1) / COL_SPLIT;
   double s = 0.0;
-  for (int64_t i = threadIdx.x; i < n; i += 256) s += A[i * r + c] * B[i * r + c];
+  for (int64_t i = i0 + threadIdx.x; i < i1; i += 256) s += A[i * r + c] * B[i * r + c];
   s = block_sum<4>(s, sh);
-  if (threadIdx.x == 0) out[c] = s;
+  if (threadIdx.x == 0) ws[(int64_t)sl * r + c] = s;
 }
 
-void launch_col_dots(const double *A, const double *B, int64_t n, int r, double *out,
+__global__ void k_col_dots_sum(const double *__restrict__ ws, int r, double *__restrict__ out) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= r) return;
+  double s = 0.0;
+  for (int sl = 0; sl < COL_SPLIT; ++sl) s += ws[(int64_t)sl * r + c];
+  out[c] = s;
+}
+
+int col_dots_workspace(int r) { return COL_SPLIT * r; }
+
+void launch_col_dots(const double *A, const double *B, int64_t n, int r, double *out, double *ws,
                      hipStream_t s) {
-  hipLaunchKernelGGL(k_col_dots, dim3(r), dim3(256), 0, s, A, B, n, r, out);
+  hipLaunchKernelGGL(k_col_dots_part, dim3(r, COL_SPLIT), dim3(256), 0, s, A, B, n, r, ws);
+  hipLaunchKernelGGL(k_col_dots_sum, dim3((r + 255) / 256), dim3(256), 0, s, ws, r, out);
 }
 
-void launch_col_norms(const double *A, int64_t n, int r, double *out, hipStream_t s) {
-  launch_col_dots(A, A, n, r, out, s);
+void launch_col_norms(const double *A, int64_t n, int r, double *out, double *ws, hipStream_t s) {
+  launch_col_dots(A, A, n, r, out, ws, s);
 }
 
 // One step of conjugate gradients on every column c of row-major n x r
