@@ -799,7 +799,10 @@ void launch_trsm_gemm(const float *Astore, const float *Linv_k, int k, const Til
 // Panel conversion: reduce each tile's partial norms (fixed order), pick the
 // FP8 power-of-two scale, copy the FP32 L_ik into the factor storage and
 // write the FP16 copy (unscaled) and the scaled FP8 E4M3 copy.
-constexpr int CONV_CHUNK = 4096;  // elements per workgroup
+// elements per workgroup (nb^2 is a multiple of both): one instance's panels
+// run beside other work and want many small workgroups; the lockstep batch
+// has many instances per launch and wants fewer, longer ones
+constexpr int CONV_CHUNK = 4096, CONV_CHUNK_B = 16384;
 
 KRR_DEV void convert_panel_body(const float *__restrict__ P32, float *__restrict__ Astore,
                                 _Float16 *__restrict__ P16, uint8_t *__restrict__ P8,
@@ -810,18 +813,26 @@ KRR_DEV void convert_panel_body(const float *__restrict__ P32, float *__restrict
   const int64_t t = bid / chunks;
   const int ch = (int)(bid % chunks);
   const int64_t i = k + 1 + t;
-  double ss = 0.0;
-  float mx = 0.0f;
-  for (int q = 0; q < parts; ++q) {
-    ss += pnorm_part[t * parts + q];
-    mx = fmaxf(mx, pmax_part[t * parts + q]);
+  // the tile's largest magnitude from its partial maxima, one per thread
+  // (a max is exact in any order)
+  __shared__ float smx[256];
+  {
+    float m = 0.0f;
+    for (int q = threadIdx.x; q < parts; q += 256) m = fmaxf(m, pmax_part[t * parts + q]);
+    smx[threadIdx.x] = m;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if ((int)threadIdx.x < w) smx[threadIdx.x] = fmaxf(smx[threadIdx.x], smx[threadIdx.x + w]);
+      __syncthreads();
+    }
   }
+  const float mx = smx[0];
   const float s8 = pow2_scale(mx, 448.0f);
   const int64_t te = (int64_t)nb * nb;
   const float *src = P32 + t * te;
   float *dstL = Astore + (i * (i + 1) / 2 + k) * te;
-  const int64_t e0 = (int64_t)ch * CONV_CHUNK;
-  for (int64_t e = e0 + threadIdx.x * 4; e < e0 + CONV_CHUNK; e += 256 * 4) {
+  const int64_t csz = te / chunks, e0 = (int64_t)ch * csz;
+  for (int64_t e = e0 + threadIdx.x * 4; e < e0 + csz; e += 256 * 4) {
     const float4 v = *(const float4 *)(src + e);
     *(float4 *)(dstL + e) = v;
     if (need16) {
@@ -837,6 +848,8 @@ KRR_DEV void convert_panel_body(const float *__restrict__ P32, float *__restrict
     }
   }
   if (ch == 0 && threadIdx.x == 0) {
+    double ss = 0.0;  // the tile norm, partial sums added in a fixed order
+    for (int q = 0; q < parts; ++q) ss += pnorm_part[t * parts + q];
     pnorm[t] = (float)sqrt(ss);
     pexp8[t] = ilogbf(s8);  // s8 = 2^pexp8
   }
@@ -1294,7 +1307,7 @@ template <typename T>
 static void factor_lockstep_t(const FactorJob *jobs, const int *nts, int nj, int nb, int g,
                               const UpdatePolicy &pol, bool need16, bool need8, hipStream_t s) {
   const int NB = nb / BS, parts = trsm_parts(nb);
-  const int chunks = (int)((int64_t)nb * nb / CONV_CHUNK);
+  const int chunks = (int)((int64_t)nb * nb / CONV_CHUNK_B);
   int ntmax = 0;
   for (int b = 0; b < nj; ++b) ntmax = std::max(ntmax, nts[b]);
   static bool attr = false;
