@@ -90,6 +90,46 @@ def test_gaussian_matches_library_exp():
     assert np.array_equal(K, K.T)
 
 
+def _golden_gaussian_cases(golden_dir):
+    spec = json.load(open(os.path.join(golden_dir, "gaussian_values.json")))
+    for case in spec["cases"]:
+        pts = case["patients"]
+        G = np.array([pts["a"], pts["b"], pts["c"]], np.int8)
+        g = np.log(2.0) if case["gamma"] == "ln2" else float(case["gamma"])
+        want = np.array([[float(v) for v in row] for row in case["K"]])
+        yield G, g, want
+
+
+def _golden_ok(gauss, golden_dir):
+    """Every hand-worked entry within 4 FP64 ulps (gamma = ln 2 carries one rounding)."""
+    for G, g, want in _golden_gaussian_cases(golden_dir):
+        K = gauss(oracle.sqdist(G), g)
+        if not np.all(np.abs(K - want) <= 4 * np.spacing(want)):
+            return False
+    return True
+
+
+def test_gaussian_golden_values(golden_dir):
+    """Algorithm 5's Gaussian on the paper's three-patient example, against values worked
+    out by hand: 2^-d at gamma = ln 2 and e^-(d/4) at gamma = 1/4."""
+    assert _golden_ok(oracle.gaussian, golden_dir)
+    for G, g, want in _golden_gaussian_cases(golden_dir):
+        assert np.all(np.abs(oracle.build_kernel(G, g) - want) <= 4 * np.spacing(want))
+
+
+def test_gaussian_planted_mistakes_are_caught(golden_dir):
+    """Plausible slips in the kernel formula -- gamma halved, the distance square-rooted,
+    the minus sign dropped, gamma doubled -- each fail the hand-worked values."""
+    mutants = {
+        "half_gamma": lambda D, g: oracle.gaussian(D, g / 2),
+        "double_gamma": lambda D, g: oracle.gaussian(D, 2 * g),
+        "sqrt_distance": lambda D, g: np.exp(-g * np.sqrt(D.astype(np.float64))),
+        "no_minus": lambda D, g: np.exp(g * D.astype(np.float64)),
+    }
+    for name, f in mutants.items():
+        assert not _golden_ok(f, golden_dir), name
+
+
 def test_kernel_is_psd():
     """The Gaussian kernel matrix is positive semi-definite (so lambda_min(K + lambda I) >= lambda)."""
     G = synth.WORKLOADS["small"].genotypes(rows=300)
