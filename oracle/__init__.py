@@ -9,6 +9,10 @@ glue below.
 Paper passages followed (arXiv 2409.01712):
   * Algorithm 1 (KRR driver): Build, then Associate, then Predict.
   * Algorithm 2 (Build) and Algorithm 5 (Gaussian kernel): K_ij = exp(-gamma ||g_i - g_j||^2).
+  * Algorithm 5, IBS branch (the SKAT kernel described in "Current State of the
+    Art"): the alleles two patients share identical by state, summed over SNPs,
+    over the total number of alleles 2 m (the reading of the text; the
+    algorithm's listing divides by m).
   * Subsection "Engaging INT8 Tensor Cores for Distance Calculations": the
     squared distance d_ij = sum_k (g_ik - g_jk)^2 between patient rows.
   * Algorithm 3 (Associate): factorize K + lambda I (the paper names the
@@ -47,14 +51,15 @@ def _load():
         P, I = ctypes.c_void_p, ctypes.c_int64
         D = ctypes.c_double
         lib.oracle_sqdist.argtypes = [P, I, I, P, I, I, I, P, I]
+        lib.oracle_ibs_counts.argtypes = [P, I, I, P, I, I, I, P, I]
         lib.oracle_gaussian.argtypes = [P, I, I, I, D, P, I]
         lib.oracle_cholesky.argtypes = [P, I, I]
         lib.oracle_cholesky.restype = I
         lib.oracle_forward.argtypes = [P, I, I, P, I, I]
         lib.oracle_backward.argtypes = [P, I, I, P, I, I]
         lib.oracle_matmul.argtypes = [P, I, I, I, P, I, I, P, I]
-        lib.oracle_residual_rows.argtypes = [P, I, I, I, D, D, P, I, P, I, P, I, I, P, I]
-        for f in ("oracle_sqdist", "oracle_gaussian", "oracle_forward", "oracle_backward",
+        lib.oracle_residual_rows.argtypes = [P, I, I, I, D, D, P, I, P, I, P, I, I, P, I, I]
+        for f in ("oracle_sqdist", "oracle_ibs_counts", "oracle_gaussian", "oracle_forward", "oracle_backward",
                   "oracle_matmul", "oracle_residual_rows"):
             getattr(lib, f).restype = None
         _lib = lib
@@ -88,6 +93,24 @@ def sqdist(G1: np.ndarray, G2: np.ndarray | None = None) -> np.ndarray:
     return D
 
 
+def ibs_counts(G1: np.ndarray, G2: np.ndarray | None = None) -> np.ndarray:
+    """Alleles shared identical by state, by definition (int64):
+    s_ij = sum_k (2 - |G1[i,k] - G2[j,k]|) (Algorithm 5, IBS branch)."""
+    G1 = _rows(G1, np.int8)
+    G2 = G1 if G2 is None else _rows(G2, np.int8)
+    assert G1.shape[1] == G2.shape[1]
+    n1, m = G1.shape
+    n2 = G2.shape[0]
+    S = np.empty((n1, n2), np.int64)
+    _load().oracle_ibs_counts(G1.ctypes.data, n1, m, G2.ctypes.data, n2, m, m, S.ctypes.data, n2)
+    return S
+
+
+def ibs(S: np.ndarray, m: int) -> np.ndarray:
+    """IBS kernel: shared-allele counts over the total number of alleles, s / (2 m), FP64."""
+    return np.asarray(S, np.int64).astype(np.float64) / float(2 * m)
+
+
 def gaussian(D: np.ndarray, gamma: float) -> np.ndarray:
     """Gaussian kernel of Algorithm 5 on squared distances: exp(-gamma d), FP64."""
     D = _rows(D, np.int64)
@@ -97,9 +120,15 @@ def gaussian(D: np.ndarray, gamma: float) -> np.ndarray:
     return K
 
 
-def build_kernel(G: np.ndarray, gamma: float, T: np.ndarray | None = None) -> np.ndarray:
-    """Algorithm 2 Build(gamma, G1, G2, K) with the Gaussian kernel."""
-    return gaussian(sqdist(G if T is None else T, G), gamma)
+def build_kernel(G: np.ndarray, gamma: float, T: np.ndarray | None = None,
+                 kind: str = "gaussian") -> np.ndarray:
+    """Algorithm 2 Build(gamma, G1, G2, K) with the Gaussian or the IBS kernel of
+    Algorithm 5 (gamma unused by IBS)."""
+    A = G if T is None else T
+    if kind == "ibs":
+        return ibs(ibs_counts(A, G), G.shape[1])
+    assert kind == "gaussian", kind
+    return gaussian(sqdist(A, G), gamma)
 
 
 def cholesky(A: np.ndarray) -> np.ndarray:
@@ -155,18 +184,20 @@ def associate(K: np.ndarray, Y: np.ndarray, lam: float) -> tuple[np.ndarray, np.
     return W, L
 
 
-def fit(G: np.ndarray, Y: np.ndarray, gamma: float, lam: float) -> np.ndarray:
+def fit(G: np.ndarray, Y: np.ndarray, gamma: float, lam: float,
+        kind: str = "gaussian") -> np.ndarray:
     """Algorithm 1 phases 1-2: Build then Associate; returns the weights W (n x r)."""
-    return associate(build_kernel(G, gamma), Y, lam)[0]
+    return associate(build_kernel(G, gamma, kind=kind), Y, lam)[0]
 
 
-def predict(G: np.ndarray, T: np.ndarray, W: np.ndarray, gamma: float) -> np.ndarray:
+def predict(G: np.ndarray, T: np.ndarray, W: np.ndarray, gamma: float,
+            kind: str = "gaussian") -> np.ndarray:
     """Algorithm 4: K_test = Build(gamma, T, G) (n_test x n), P = K_test W."""
-    return matmul(build_kernel(G, gamma, T), W)
+    return matmul(build_kernel(G, gamma, T, kind=kind), W)
 
 
 def residual_rows(G: np.ndarray, gamma: float, lam: float, X: np.ndarray, Y: np.ndarray,
-                  rows) -> np.ndarray:
+                  rows, kind: str = "gaussian") -> np.ndarray:
     """r = Y - (K + lambda I) X on the given rows, K recomputed from G by definition."""
     G = _rows(G, np.int8)
     X = _rows(X, np.float64)
@@ -179,5 +210,6 @@ def residual_rows(G: np.ndarray, gamma: float, lam: float, X: np.ndarray, Y: np.
     R = np.empty((len(rows), r), np.float64)
     _load().oracle_residual_rows(G.ctypes.data, n, m, m, float(gamma), float(lam),
                                  rows.ctypes.data, len(rows), X.ctypes.data, r,
-                                 Y.ctypes.data, r, r, R.ctypes.data, r)
+                                 Y.ctypes.data, r, r, R.ctypes.data, r,
+                                 1 if kind == "ibs" else 0)
     return R

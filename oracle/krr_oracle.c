@@ -14,6 +14,10 @@
  *              definition of the "Engaging INT8 Tensor Cores" subsection):
  *             d_ij = sum_k (g_ik - g_jk)^2 exactly in integers,
  *             K_ij = exp(-gamma * d_ij) in FP64.
+ *             IBS case of Algorithm 5 (identical-by-state, the SKAT kernel
+ *             of the "Current State of the Art" section): s_ij = sum_k
+ *             (alleles shared at SNP k) = sum_k (2 - |g_ik - g_jk|) exactly,
+ *             K_ij = s_ij / (2 m), the count over the total number of alleles.
  *   Associate (Algorithm 3): A = K + lambda*I, A = L L^T (Cholesky),
  *             then L Z = Y and L^T W = Z (forward / back substitution).
  *   Predict   (Algorithm 4): K_test = Build(gamma, T, G), P = K_test W.
@@ -41,6 +45,26 @@ void oracle_sqdist(const int8_t *G1, int64_t n1, int64_t ld1, const int8_t *G2,
         s += t * t;
       }
       D[i * ldd + j] = s;
+    }
+  }
+}
+
+/* Identical-by-state allele counts (Algorithm 5, IBS branch), by definition:
+ * a genotype counts minor alleles, so two patients share 2 - |g1 - g2| alleles
+ * at a SNP.  S[i*ldd + j] = sum_k (2 - |G1[i,k] - G2[j,k]|). */
+void oracle_ibs_counts(const int8_t *G1, int64_t n1, int64_t ld1, const int8_t *G2,
+                       int64_t n2, int64_t ld2, int64_t m, int64_t *S, int64_t ldd) {
+#pragma omp parallel for schedule(dynamic, 4)
+  for (int64_t i = 0; i < n1; ++i) {
+    const int8_t *a = G1 + i * ld1;
+    for (int64_t j = 0; j < n2; ++j) {
+      const int8_t *b = G2 + j * ld2;
+      int64_t s = 0;
+      for (int64_t k = 0; k < m; ++k) {
+        const int64_t t = (int64_t)a[k] - (int64_t)b[k];
+        s += 2 - (t < 0 ? -t : t);
+      }
+      S[i * ldd + j] = s;
     }
   }
 }
@@ -125,11 +149,12 @@ void oracle_matmul(const double *K, int64_t n1, int64_t n2, int64_t ldk,
  * recomputed from the genotypes by definition (no stored matrix):
  *   R[t, c] = Y[rows[t], c] - sum_j (K_{rows[t], j} + lambda*[rows[t] == j]) X[j, c].
  * Used where the n x n matrix does not fit in host memory. */
+/* kind 0: Gaussian exp(-gamma d); kind 1: IBS s / (2 m). */
 void oracle_residual_rows(const int8_t *G, int64_t n, int64_t m, int64_t ldg,
                           double gamma, double lambda, const int64_t *rows,
                           int64_t nrows, const double *X, int64_t ldx,
                           const double *Y, int64_t ldy, int64_t r, double *R,
-                          int64_t ldr) {
+                          int64_t ldr, int64_t kind) {
 #pragma omp parallel for schedule(dynamic, 1)
   for (int64_t t = 0; t < nrows; ++t) {
     const int64_t i = rows[t];
@@ -140,9 +165,9 @@ void oracle_residual_rows(const int8_t *G, int64_t n, int64_t m, int64_t ldg,
       int64_t s = 0;
       for (int64_t k = 0; k < m; ++k) {
         const int64_t u = (int64_t)a[k] - (int64_t)b[k];
-        s += u * u;
+        s += kind == 1 ? 2 - (u < 0 ? -u : u) : u * u;
       }
-      double kij = exp(-gamma * (double)s);
+      double kij = kind == 1 ? (double)s / (double)(2 * m) : exp(-gamma * (double)s);
       if (j == i) kij += lambda;
       for (int64_t c = 0; c < r; ++c) acc[c] += kij * X[j * ldx + c];
     }

@@ -130,6 +130,75 @@ def test_gaussian_planted_mistakes_are_caught(golden_dir):
         assert not _golden_ok(f, golden_dir), name
 
 
+# --- IBS kernel (Algorithm 5, IBS branch) ------------------------------------------------
+
+def _shared_alleles_brute(a, b):
+    """Alleles shared identical by state at one SNP, from the allele multisets: genotype g
+    carries g minor and 2 - g major alleles; the shared count is the multiset overlap."""
+    return min(a, b) + min(2 - a, 2 - b)
+
+
+def test_ibs_golden_values(golden_dir):
+    spec = json.load(open(os.path.join(golden_dir, "ibs_values.json")))
+    for case in spec["cases"]:
+        pts = case["patients"]
+        G = np.array([pts["a"], pts["b"], pts["c"]], np.int8)
+        assert oracle.ibs_counts(G).tolist() == case["shared"]
+        want = np.array([[float(v) for v in row] for row in case["K"]])
+        assert np.array_equal(oracle.build_kernel(G, 0.0, kind="ibs"), want)
+
+
+def test_ibs_planted_mistakes_are_caught(golden_dir):
+    """Dividing by m (the listing's literal N_S) or counting squared differences
+    instead of absolute ones fails the hand-worked values."""
+    spec = json.load(open(os.path.join(golden_dir, "ibs_values.json")))
+    G = np.array([spec["cases"][0]["patients"][k] for k in "abc"], np.int8)
+    want = np.array([[float(v) for v in row] for row in spec["cases"][0]["K"]])
+    m = G.shape[1]
+    by_m = oracle.ibs_counts(G) / m
+    sq = (2 * m - oracle.sqdist(G)) / (2 * m)
+    assert not np.array_equal(by_m, want) and not np.array_equal(sq, want)
+
+
+def test_ibs_brute_force_and_identity():
+    """Counts against the allele-multiset overlap on tiny inputs, and the identity behind
+    the GPU's INT8 form: s = 2m - d + 2 (C02 + C20), C02 counting SNPs with g_i = 0 and
+    g_j = 2 (one-hot products)."""
+    G = _tiny_genotypes(7, 11, 21)
+    T = _tiny_genotypes(5, 11, 22)
+    S = oracle.ibs_counts(T, G)
+    for i in range(5):
+        for j in range(7):
+            assert S[i, j] == sum(_shared_alleles_brute(int(T[i, k]), int(G[j, k]))
+                                  for k in range(11))
+    G = _tiny_genotypes(40, 300, 23).astype(np.int64)
+    z, t = (G == 0).astype(np.int64), (G == 2).astype(np.int64)
+    want = 2 * 300 - oracle.sqdist(G.astype(np.int8)) + 2 * (z @ t.T + t @ z.T)
+    assert np.array_equal(oracle.ibs_counts(G.astype(np.int8)), want)
+
+
+def test_ibs_kernel_properties():
+    """Unit diagonal, symmetric, entries in [0, 1], positive semi-definite (a sum over
+    SNPs of inner products of allele indicators)."""
+    G = synth.WORKLOADS["small"].genotypes(rows=300)
+    K = oracle.build_kernel(G, 0.0, kind="ibs")
+    assert np.all(np.diag(K) == 1.0) and np.array_equal(K, K.T)
+    assert K.min() >= 0.0 and K.max() <= 1.0
+    assert np.linalg.eigvalsh(K).min() > -1e-10
+
+
+def test_ibs_fit_dense_inverse_and_residual():
+    w = synth.WORKLOADS["small"]
+    G = w.genotypes(rows=200)
+    Y = w.phenotypes(G)
+    W = oracle.fit(G, Y, 0.0, w.lam, kind="ibs")
+    A = oracle.build_kernel(G, 0.0, kind="ibs") + w.lam * np.eye(200)
+    want = np.linalg.inv(A) @ Y
+    assert np.max(np.abs(W - want)) <= 1e-10 * np.max(np.abs(want))
+    R = oracle.residual_rows(G, 0.0, w.lam, W, Y, [0, 5, 199], kind="ibs")
+    assert np.max(np.abs(R)) <= 1e-9
+
+
 def test_kernel_is_psd():
     """The Gaussian kernel matrix is positive semi-definite (so lambda_min(K + lambda I) >= lambda)."""
     G = synth.WORKLOADS["small"].genotypes(rows=300)
