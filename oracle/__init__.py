@@ -9,6 +9,9 @@ glue below.
 Paper passages followed (arXiv 2409.01712):
   * Algorithm 1 (KRR driver): Build, then Associate, then Predict.
   * Algorithm 2 (Build) and Algorithm 5 (Gaussian kernel): K_ij = exp(-gamma ||g_i - g_j||^2).
+  * Confounders ("Engaging INT8 Tensor Cores" subsection): real covariates
+    whose squared distances are added to the integer genotype distances before
+    the exponential of the Gaussian kernel.
   * Algorithm 5, IBS branch (the SKAT kernel described in "Current State of the
     Art"): the alleles two patients share identical by state, summed over SNPs,
     over the total number of alleles 2 m (the reading of the text; the
@@ -52,14 +55,17 @@ def _load():
         D = ctypes.c_double
         lib.oracle_sqdist.argtypes = [P, I, I, P, I, I, I, P, I]
         lib.oracle_ibs_counts.argtypes = [P, I, I, P, I, I, I, P, I]
+        lib.oracle_conf_sqdist.argtypes = [P, I, I, P, I, I, I, P, I]
         lib.oracle_gaussian.argtypes = [P, I, I, I, D, P, I]
+        lib.oracle_gaussian_real.argtypes = [P, I, I, I, D, P, I]
         lib.oracle_cholesky.argtypes = [P, I, I]
         lib.oracle_cholesky.restype = I
         lib.oracle_forward.argtypes = [P, I, I, P, I, I]
         lib.oracle_backward.argtypes = [P, I, I, P, I, I]
         lib.oracle_matmul.argtypes = [P, I, I, I, P, I, I, P, I]
-        lib.oracle_residual_rows.argtypes = [P, I, I, I, D, D, P, I, P, I, P, I, I, P, I, I]
-        for f in ("oracle_sqdist", "oracle_ibs_counts", "oracle_gaussian", "oracle_forward", "oracle_backward",
+        lib.oracle_residual_rows.argtypes = [P, I, I, I, D, D, P, I, P, I, P, I, I, P, I, I, P, I]
+        for f in ("oracle_sqdist", "oracle_ibs_counts", "oracle_conf_sqdist", "oracle_gaussian",
+                  "oracle_gaussian_real", "oracle_forward", "oracle_backward",
                   "oracle_matmul", "oracle_residual_rows"):
             getattr(lib, f).restype = None
         _lib = lib
@@ -106,6 +112,21 @@ def ibs_counts(G1: np.ndarray, G2: np.ndarray | None = None) -> np.ndarray:
     return S
 
 
+def conf_sqdist(C1: np.ndarray, C2: np.ndarray | None = None) -> np.ndarray:
+    """Squared Euclidean distances between confounder rows, by definition (FP64)."""
+    C1 = _rows(C1, np.float64)
+    C2 = C1 if C2 is None else _rows(C2, np.float64)
+    if C1.ndim == 1:
+        C1 = C1[:, None]
+    if C2.ndim == 1:
+        C2 = C2[:, None]
+    n1, q = C1.shape
+    n2 = C2.shape[0]
+    Dc = np.empty((n1, n2), np.float64)
+    _load().oracle_conf_sqdist(C1.ctypes.data, n1, q, C2.ctypes.data, n2, q, q, Dc.ctypes.data, n2)
+    return Dc
+
+
 def ibs(S: np.ndarray, m: int) -> np.ndarray:
     """IBS kernel: shared-allele counts over the total number of alleles, s / (2 m), FP64."""
     return np.asarray(S, np.int64).astype(np.float64) / float(2 * m)
@@ -121,14 +142,22 @@ def gaussian(D: np.ndarray, gamma: float) -> np.ndarray:
 
 
 def build_kernel(G: np.ndarray, gamma: float, T: np.ndarray | None = None,
-                 kind: str = "gaussian") -> np.ndarray:
+                 kind: str = "gaussian", C: np.ndarray | None = None,
+                 Ct: np.ndarray | None = None) -> np.ndarray:
     """Algorithm 2 Build(gamma, G1, G2, K) with the Gaussian or the IBS kernel of
-    Algorithm 5 (gamma unused by IBS)."""
+    Algorithm 5 (gamma unused by IBS).  C (n x q) / Ct (rows of T): confounders of the
+    Gaussian kernel, exp(-gamma (d_genotypes + d_confounders))."""
     A = G if T is None else T
     if kind == "ibs":
         return ibs(ibs_counts(A, G), G.shape[1])
     assert kind == "gaussian", kind
-    return gaussian(sqdist(A, G), gamma)
+    if C is None:
+        return gaussian(sqdist(A, G), gamma)
+    D = sqdist(A, G).astype(np.float64) + conf_sqdist(C if T is None else Ct, C)
+    n1, n2 = D.shape
+    K = np.empty((n1, n2), np.float64)
+    _load().oracle_gaussian_real(D.ctypes.data, n1, n2, n2, float(gamma), K.ctypes.data, n2)
+    return K
 
 
 def cholesky(A: np.ndarray) -> np.ndarray:
@@ -185,19 +214,20 @@ def associate(K: np.ndarray, Y: np.ndarray, lam: float) -> tuple[np.ndarray, np.
 
 
 def fit(G: np.ndarray, Y: np.ndarray, gamma: float, lam: float,
-        kind: str = "gaussian") -> np.ndarray:
+        kind: str = "gaussian", C: np.ndarray | None = None) -> np.ndarray:
     """Algorithm 1 phases 1-2: Build then Associate; returns the weights W (n x r)."""
-    return associate(build_kernel(G, gamma, kind=kind), Y, lam)[0]
+    return associate(build_kernel(G, gamma, kind=kind, C=C), Y, lam)[0]
 
 
 def predict(G: np.ndarray, T: np.ndarray, W: np.ndarray, gamma: float,
-            kind: str = "gaussian") -> np.ndarray:
+            kind: str = "gaussian", C: np.ndarray | None = None,
+            Ct: np.ndarray | None = None) -> np.ndarray:
     """Algorithm 4: K_test = Build(gamma, T, G) (n_test x n), P = K_test W."""
-    return matmul(build_kernel(G, gamma, T, kind=kind), W)
+    return matmul(build_kernel(G, gamma, T, kind=kind, C=C, Ct=Ct), W)
 
 
 def residual_rows(G: np.ndarray, gamma: float, lam: float, X: np.ndarray, Y: np.ndarray,
-                  rows, kind: str = "gaussian") -> np.ndarray:
+                  rows, kind: str = "gaussian", C: np.ndarray | None = None) -> np.ndarray:
     """r = Y - (K + lambda I) X on the given rows, K recomputed from G by definition."""
     G = _rows(G, np.int8)
     X = _rows(X, np.float64)
@@ -206,10 +236,15 @@ def residual_rows(G: np.ndarray, gamma: float, lam: float, X: np.ndarray, Y: np.
         X, Y = X[:, None], Y[:, None]
     rows = np.ascontiguousarray(rows, dtype=np.int64)
     n, m = G.shape
+    Cc, q = None, 0
+    if C is not None:
+        Cc = _rows(C, np.float64).reshape(n, -1)
+        q = Cc.shape[1]
     r = X.shape[1]
     R = np.empty((len(rows), r), np.float64)
     _load().oracle_residual_rows(G.ctypes.data, n, m, m, float(gamma), float(lam),
                                  rows.ctypes.data, len(rows), X.ctypes.data, r,
                                  Y.ctypes.data, r, r, R.ctypes.data, r,
-                                 1 if kind == "ibs" else 0)
+                                 1 if kind == "ibs" else 0,
+                                 Cc.ctypes.data if Cc is not None else None, q)
     return R

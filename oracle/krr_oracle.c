@@ -18,6 +18,11 @@
  *             of the "Current State of the Art" section): s_ij = sum_k
  *             (alleles shared at SNP k) = sum_k (2 - |g_ik - g_jk|) exactly,
  *             K_ij = s_ij / (2 m), the count over the total number of alleles.
+ *             Confounders (subsection "Engaging INT8 Tensor Cores": real
+ *             covariates whose squared distances are added to the integer
+ *             genotype distances before the exponential): with q real
+ *             covariates c_i per patient, d_ij = sum_k (g_ik - g_jk)^2 +
+ *             sum_l (c_il - c_jl)^2 and K_ij = exp(-gamma * d_ij).
  *   Associate (Algorithm 3): A = K + lambda*I, A = L L^T (Cholesky),
  *             then L Z = Y and L^T W = Z (forward / back substitution).
  *   Predict   (Algorithm 4): K_test = Build(gamma, T, G), P = K_test W.
@@ -69,6 +74,22 @@ void oracle_ibs_counts(const int8_t *G1, int64_t n1, int64_t ld1, const int8_t *
   }
 }
 
+/* Squared distances between confounder rows, by definition, FP64:
+ * Dc[i*ldd + j] = sum_l (C1[i,l] - C2[j,l])^2. */
+void oracle_conf_sqdist(const double *C1, int64_t n1, int64_t ld1, const double *C2,
+                        int64_t n2, int64_t ld2, int64_t q, double *Dc, int64_t ldd) {
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n1; ++i)
+    for (int64_t j = 0; j < n2; ++j) {
+      double s = 0.0;
+      for (int64_t l = 0; l < q; ++l) {
+        const double t = C1[i * ld1 + l] - C2[j * ld2 + l];
+        s += t * t;
+      }
+      Dc[i * ldd + j] = s;
+    }
+}
+
 /* Gaussian kernel (Algorithm 5): K_ij = exp(-gamma * d_ij), FP64. */
 void oracle_gaussian(const int64_t *D, int64_t n1, int64_t n2, int64_t ldd,
                      double gamma, double *K, int64_t ldk) {
@@ -76,6 +97,16 @@ void oracle_gaussian(const int64_t *D, int64_t n1, int64_t n2, int64_t ldd,
   for (int64_t i = 0; i < n1; ++i)
     for (int64_t j = 0; j < n2; ++j)
       K[i * ldk + j] = exp(-gamma * (double)D[i * ldd + j]);
+}
+
+/* The Gaussian kernel on real squared distances (genotype plus confounder
+ * distances): K_ij = exp(-gamma * d_ij), FP64. */
+void oracle_gaussian_real(const double *D, int64_t n1, int64_t n2, int64_t ldd,
+                          double gamma, double *K, int64_t ldk) {
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n1; ++i)
+    for (int64_t j = 0; j < n2; ++j)
+      K[i * ldk + j] = exp(-gamma * D[i * ldd + j]);
 }
 
 /* Cholesky A = L L^T of a symmetric positive definite matrix, in place on the
@@ -149,12 +180,13 @@ void oracle_matmul(const double *K, int64_t n1, int64_t n2, int64_t ldk,
  * recomputed from the genotypes by definition (no stored matrix):
  *   R[t, c] = Y[rows[t], c] - sum_j (K_{rows[t], j} + lambda*[rows[t] == j]) X[j, c].
  * Used where the n x n matrix does not fit in host memory. */
-/* kind 0: Gaussian exp(-gamma d); kind 1: IBS s / (2 m). */
+/* kind 0: Gaussian exp(-gamma d); kind 1: IBS s / (2 m).  C (n x q, may be
+ * NULL with q = 0): confounders, their squared distance added to d (Gaussian). */
 void oracle_residual_rows(const int8_t *G, int64_t n, int64_t m, int64_t ldg,
                           double gamma, double lambda, const int64_t *rows,
                           int64_t nrows, const double *X, int64_t ldx,
                           const double *Y, int64_t ldy, int64_t r, double *R,
-                          int64_t ldr, int64_t kind) {
+                          int64_t ldr, int64_t kind, const double *C, int64_t q) {
 #pragma omp parallel for schedule(dynamic, 1)
   for (int64_t t = 0; t < nrows; ++t) {
     const int64_t i = rows[t];
@@ -167,7 +199,12 @@ void oracle_residual_rows(const int8_t *G, int64_t n, int64_t m, int64_t ldg,
         const int64_t u = (int64_t)a[k] - (int64_t)b[k];
         s += kind == 1 ? 2 - (u < 0 ? -u : u) : u * u;
       }
-      double kij = kind == 1 ? (double)s / (double)(2 * m) : exp(-gamma * (double)s);
+      double dc = 0.0;
+      for (int64_t l = 0; l < q; ++l) {
+        const double t = C[i * q + l] - C[j * q + l];
+        dc += t * t;
+      }
+      double kij = kind == 1 ? (double)s / (double)(2 * m) : exp(-gamma * ((double)s + dc));
       if (j == i) kij += lambda;
       for (int64_t c = 0; c < r; ++c) acc[c] += kij * X[j * ldx + c];
     }

@@ -130,6 +130,71 @@ def test_gaussian_planted_mistakes_are_caught(golden_dir):
         assert not _golden_ok(f, golden_dir), name
 
 
+# --- confounders ("Engaging INT8 Tensor Cores" subsection) ----------------------------
+
+def _golden_conf(golden_dir):
+    spec = json.load(open(os.path.join(golden_dir, "confounder_values.json")))
+    G = np.array([spec["patients"][k] for k in "abc"], np.int8)
+    C = np.array([spec["confounders"][k] for k in "abc"], np.float64)
+    want = np.array([[float(v) for v in row] for row in spec["K_ln2"]])
+    return spec, G, C, want
+
+
+def test_confounder_golden_values(golden_dir):
+    spec, G, C, want = _golden_conf(golden_dir)
+    assert oracle.conf_sqdist(C).tolist() == spec["conf_sqdist"]
+    K = oracle.build_kernel(G, np.log(2.0), C=C)
+    assert np.all(np.abs(K - want) <= 4 * np.spacing(want))
+
+
+def test_confounder_planted_mistakes_are_caught(golden_dir):
+    """Leaving the confounder term out, or adding its distance unsquared, fails the
+    hand-worked values."""
+    spec, G, C, want = _golden_conf(golden_dir)
+    g = np.log(2.0)
+    without = oracle.build_kernel(G, g)
+    unsquared = np.exp(-g * (oracle.sqdist(G) + np.sqrt(oracle.conf_sqdist(C))))
+    for bad in (without, unsquared):
+        assert not np.all(np.abs(bad - want) <= 4 * np.spacing(want))
+
+
+def test_confounder_distances_brute_force_and_syrk_form():
+    """By definition against a Python loop, and the SYRK form the GPU uses,
+    ||c_i||^2 + ||c_j||^2 - 2 c_i . c_j, through numpy's product."""
+    rng = np.random.default_rng(31)
+    C1, C2 = rng.standard_normal((6, 5)), rng.standard_normal((4, 5))
+    Dc = oracle.conf_sqdist(C2, C1)
+    for i in range(4):
+        for j in range(6):
+            assert abs(Dc[i, j] - sum((C2[i, l] - C1[j, l]) ** 2 for l in range(5))) <= 1e-13
+    C = rng.standard_normal((50, 12))
+    nrm = (C * C).sum(1)
+    syrk = nrm[:, None] + nrm[None, :] - 2 * (C @ C.T)
+    assert np.max(np.abs(oracle.conf_sqdist(C) - syrk)) <= 1e-12 * np.max(syrk)
+
+
+def test_confounder_kernel_reductions():
+    """Zero confounders reduce to the genotype kernel; identical genotypes leave only the
+    confounder kernel; the full kernel stays PSD; the fit with confounders matches a
+    dense inverse and its residual rows vanish."""
+    w = synth.WORKLOADS["small"]
+    G = w.genotypes(rows=200)
+    Y = w.phenotypes(G)
+    C = np.random.default_rng(32).standard_normal((200, 3)) * 10.0
+    assert np.array_equal(oracle.build_kernel(G, w.gamma, C=np.zeros((200, 3))),
+                          oracle.build_kernel(G, w.gamma))
+    Gsame = np.repeat(G[:1], 200, axis=0)
+    Kc = oracle.build_kernel(Gsame, 0.01, C=C)
+    assert np.max(np.abs(Kc - np.exp(-0.01 * oracle.conf_sqdist(C)))) <= 1e-15
+    K = oracle.build_kernel(G, w.gamma, C=C)
+    assert np.linalg.eigvalsh(K).min() > -1e-12
+    W = oracle.fit(G, Y, w.gamma, w.lam, C=C)
+    want = np.linalg.inv(K + w.lam * np.eye(200)) @ Y
+    assert np.max(np.abs(W - want)) <= 1e-10 * np.max(np.abs(want))
+    R = oracle.residual_rows(G, w.gamma, w.lam, W, Y, [0, 77, 199], C=C)
+    assert np.max(np.abs(R)) <= 1e-9
+
+
 # --- IBS kernel (Algorithm 5, IBS branch) ------------------------------------------------
 
 def _shared_alleles_brute(a, b):
