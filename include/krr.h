@@ -256,7 +256,7 @@ krr_status krr_debug_encode_fp8(krr_context ctx, const float *x, int64_t n, uint
 krr_status krr_kernel_tile_norms(krr_kernel K, double *host_dst, int64_t count);
 /* Precision chosen for each update: host array of NT * NT(NT+1)/2 bytes,
  * entry [k * NT(NT+1)/2 + I(I+1)/2 + J] for the update of tile (I, J) by
- * panel k (255 where no update happens).  Only recorded when NT <= 128. */
+ * panel k (255 where no update happens), recorded at every NT. */
 krr_status krr_factor_precision_map(krr_factorization F, uint8_t *host_dst, int64_t count);
 
 /* ---- per-stage timers (HIP events on the context stream) -------------- */

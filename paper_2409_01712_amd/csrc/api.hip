@@ -980,10 +980,9 @@ krr_status krr_factor(krr_context ctx, krr_kernel K, const krr_precision_policy 
   FactorWork w;
   krr_status st = KRR_SUCCESS;
   uint8_t *dmap = nullptr;
-  // precision of every (panel, tile) update; copied to the host (for the
-  // diagnostics accessor) when it is small
+  // precision of every (panel, tile) update; copied to the host for the
+  // diagnostics accessor (NT^2 (NT+1) / 2 bytes: 30 MB at NT = 391)
   const int64_t mapsz = (int64_t)L.nt * L.ntiles();
-  const bool keep_map = L.nt <= 128;
   do {
     if (K->A) {  // consume the build's matrix in place
       F->Lst = K->A;
@@ -1023,7 +1022,7 @@ krr_status krr_factor(krr_context ctx, krr_kernel K, const krr_precision_policy 
       }
       F->info.promotions++;
     }
-    if (st == KRR_SUCCESS && keep_map) {
+    if (st == KRR_SUCCESS) {
       F->pmap.resize(mapsz);
       if (hipMemcpy(F->pmap.data(), dmap, mapsz, hipMemcpyDeviceToHost) != hipSuccess)
         st = KRR_ERROR_HIP;
@@ -1187,7 +1186,7 @@ krr_status krr_factor_batched(krr_context ctx, int32_t batch, const krr_kernel *
     }
     for (int b = 0; b < batch; ++b) {
       for (int q = 0; q < 3; ++q) Fs[b]->info.updates[q] = (int64_t)hc[3 * b + q];
-      if (Fs[b]->L.nt <= 128 && hflag[b] == 0) {
+      if (hflag[b] == 0) {
         Fs[b]->pmap.resize(mapsz[b]);
         if (hipMemcpy(Fs[b]->pmap.data(), dmap[b], mapsz[b], hipMemcpyDeviceToHost) != hipSuccess)
           st = KRR_ERROR_HIP;
@@ -1233,9 +1232,7 @@ krr_status krr_factor_release(krr_factorization F) {
   krr_context c = F->ctx;
   (void)hipSetDevice(c->device);
   (void)hipStreamSynchronize(c->stream);
-  dfree(c, F->Lst, F->L.elems() * 4);
-  dfree(c, F->Linv, (size_t)F->L.nt * F->L.tile_elems() * 4);
-  delete F;
+  factor_free(F);  // the factor, the tile inverses and the sweeps' coupling tiles
   context_unref(c);
   return KRR_SUCCESS;
 }

@@ -1,9 +1,9 @@
 // Associate phase, second half (arXiv 2409.01712, Algorithm 3: Solve for W)
 // and the FP64 pieces of refinement and Predict (Algorithm 4: P = K_test W).
 //
-// Triangular solves run in FP32 on the tile factor ("forward and backward
-// substitution ... in the full FP32 precision", subsection on Ridge
-// Regression) for all phenotype columns at once: per tile step, the
+// Triangular solves run in FP32 on the tile factor (the Ridge Regression
+// subsection keeps both substitutions in single precision; Algorithm 3's
+// Solve) for all phenotype columns at once: per tile step, the
 // diagonal block is applied through its inverse and the panel below (or
 // beside) is updated; one instance takes the tiles in pairs, with a
 // coupling tile standing in for the step between the two.  Refinement runs
