@@ -54,7 +54,8 @@ typedef enum krr_status {
   KRR_ERROR_NOT_POSITIVE_DEFINITE = 4, /* Cholesky breakdown that promotion could not cure */
   KRR_ERROR_NOT_CONVERGED = 5,         /* refinement hit max_iters; X still written, info filled */
   KRR_ERROR_HIP = 6,                   /* a HIP runtime call failed */
-  KRR_ERROR_NOT_SUPPORTED = 7          /* option combination not implemented */
+  KRR_ERROR_NOT_SUPPORTED = 7,         /* option combination not implemented */
+  KRR_ERROR_SCRATCH_TOO_SMALL = 8      /* krr_predict_noalloc: input larger than its fixed scratch */
 } krr_status;
 
 typedef struct krr_context_s *krr_context;
@@ -191,6 +192,37 @@ krr_status krr_solve(krr_context ctx, krr_factorization F, const double *Y, int6
  */
 krr_status krr_predict(krr_context ctx, krr_kernel K, const int8_t *T, int64_t n_test, int64_t ldt,
                        const double *X, int64_t nrhs, int64_t ldx, double *P, int64_t ldp);
+
+/*
+ * Predict without any device allocation, for callers that cannot allocate:
+ * code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same arguments, results and errors as krr_predict (the same
+ * kernels, so P is bit-identical), but the working buffers (genotype-check
+ * flag, test-row norms, the row-major copy of X, the cross distances of a
+ * chunk of test rows) live in a fixed device scratch of
+ * KRR_NOALLOC_SCRATCH_BYTES that each device holds from krr_create until the
+ * process ends.  Calls no hipMalloc/hipFree and no allocating library routine.
+ * Limit: 256 + 4*n_test + 8*np*nrhs + 4*64*np bytes (rounded up to 256 each;
+ * np = n rounded up to the tile size) must fit, else
+ * KRR_ERROR_SCRATCH_TOO_SMALL before any work (krr_noalloc_limits answers
+ * the question in advance).  Every call on one device shares that device's
+ * scratch and leaves its contents behind: calls that overlap on one device
+ * (two host threads, or two streams in flight) race and must be serialised
+ * by the caller.  Blocks for the genotype check and at the end, like
+ * krr_predict.
+ */
+#define KRR_NOALLOC_SCRATCH_BYTES ((int64_t)64 << 20)
+krr_status krr_predict_noalloc(krr_context ctx, krr_kernel K, const int8_t *T, int64_t n_test,
+                               int64_t ldt, const double *X, int64_t nrhs, int64_t ldx, double *P,
+                               int64_t ldp);
+/* Host-only check: *fits = 1 if krr_predict_noalloc accepts n training
+ * patients (tile size `tile`, 0 = 512), n_test test patients and nrhs
+ * columns; *scratch_bytes = KRR_NOALLOC_SCRATCH_BYTES.  No GPU work. */
+krr_status krr_noalloc_limits(int64_t n, int64_t n_test, int64_t nrhs, int32_t tile,
+                              int64_t *scratch_bytes, int32_t *fits);
+/* Bytes of device memory the context currently holds for live buffers and
+ * in its block cache (host values; no GPU work). */
+krr_status krr_context_memory(krr_context ctx, int64_t *allocated, int64_t *cached);
 
 /* ---- batches of independent instances ---------------------------------
  * Many KRR problems at once, as in a cross-validation over (gamma, lambda)

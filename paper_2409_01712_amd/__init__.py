@@ -26,6 +26,8 @@ KRR_ERROR_NOT_POSITIVE_DEFINITE = 4
 KRR_ERROR_NOT_CONVERGED = 5
 KRR_ERROR_HIP = 6
 KRR_ERROR_NOT_SUPPORTED = 7
+KRR_ERROR_SCRATCH_TOO_SMALL = 8
+KRR_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 KRR_PREC_FP32, KRR_PREC_FP16, KRR_PREC_FP8 = 0, 1, 2
 KRR_POLICY_FP32, KRR_POLICY_ADAPTIVE, KRR_POLICY_FIXED = 0, 1, 2
@@ -75,6 +77,10 @@ _SIGS = [
     ("krr_solve", _I, [_P, _P, _P, _I64, _I64, _P, _I64, ctypes.POINTER(krr_refine_opts),
                        ctypes.POINTER(krr_solve_info)]),
     ("krr_predict", _I, [_P, _P, _P, _I64, _I64, _P, _I64, _I64, _P, _I64]),
+    ("krr_predict_noalloc", _I, [_P, _P, _P, _I64, _I64, _P, _I64, _I64, _P, _I64]),
+    ("krr_noalloc_limits", _I, [_I64, _I64, _I64, ctypes.c_int32, ctypes.POINTER(_I64),
+                                ctypes.POINTER(ctypes.c_int32)]),
+    ("krr_context_memory", _I, [_P, ctypes.POINTER(_I64), ctypes.POINTER(_I64)]),
     ("krr_build_kernel_batched", _I, [_P, ctypes.c_int32, _P, _P, _I64, _P, _P, _P, _P]),
     ("krr_factor_batched", _I, [_P, ctypes.c_int32, _P, ctypes.POINTER(krr_precision_policy),
                                 _P]),
@@ -393,6 +399,40 @@ def krr_predict(ctx: Context, K: Kernel, T, X):
     _check(load().krr_predict(ctx.handle, K.handle, _ptr(T), nt, T.stride(0), _ptr(Xc), r, K.n,
                               _ptr(P), nt), "krr_predict")
     return P
+
+
+def krr_predict_noalloc(ctx: Context, K: Kernel, T, X, P=None):
+    """krr_predict through the no-allocation entry point: the library allocates
+    nothing; P (n_test x r, float64, column-major) may be passed in by the caller."""
+    import torch
+    T = padded_genotypes(T)
+    nt, m = T.shape
+    assert m == K.m
+    Xc = _colmajor(X, K.n)
+    r = Xc.shape[1]
+    if P is None:
+        P = torch.empty((r, nt), dtype=torch.float64, device=Xc.device).t()
+    assert P.shape == (nt, r) and P.stride(0) == 1 and P.dtype == torch.float64
+    _check(load().krr_predict_noalloc(ctx.handle, K.handle, _ptr(T), nt, T.stride(0), _ptr(Xc), r,
+                                      K.n, _ptr(P), P.stride(1)), "krr_predict_noalloc")
+    return P
+
+
+def krr_noalloc_limits(n: int, n_test: int, nrhs: int, tile: int = 512):
+    """(scratch bytes, whether krr_predict_noalloc accepts these sizes); host only."""
+    b = ctypes.c_int64()
+    f = ctypes.c_int32()
+    _check(load().krr_noalloc_limits(n, n_test, nrhs, tile, ctypes.byref(b), ctypes.byref(f)),
+           "krr_noalloc_limits")
+    return int(b.value), bool(f.value)
+
+
+def krr_context_memory(ctx: Context):
+    """(bytes in live library buffers, bytes in the context's block cache)."""
+    a, c = ctypes.c_int64(), ctypes.c_int64()
+    _check(load().krr_context_memory(ctx.handle, ctypes.byref(a), ctypes.byref(c)),
+           "krr_context_memory")
+    return int(a.value), int(c.value)
 
 
 def krr_debug_encode_fp8(ctx: Context, x):

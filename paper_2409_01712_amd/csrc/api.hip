@@ -9,6 +9,7 @@
 
 #include <algorithm>
 #include <map>
+#include <mutex>
 #include <unordered_map>
 #include <vector>
 
@@ -293,9 +294,44 @@ const char *krr_status_string(krr_status s) {
     case KRR_ERROR_NOT_CONVERGED: return "refinement did not converge";
     case KRR_ERROR_HIP: return "HIP runtime error";
     case KRR_ERROR_NOT_SUPPORTED: return "not supported";
+    case KRR_ERROR_SCRATCH_TOO_SMALL:
+      return "input needs more than the fixed scratch of the no-allocation entry point";
   }
   return "unknown status";
 }
+
+// Fixed device scratch of the no-allocation entry point (krr_predict_noalloc).
+// Each device the library runs on holds its own copy of this array until the
+// process ends.  In host code its name is a host-side stand-in: kernels and
+// copies get the device address taken once per device (scratch_init, called by
+// krr_create with that device current), never the name itself.
+static __device__ __align__(256) uint8_t scratch[KRR_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int KRR_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[KRR_MAX_DEVICES] = {};
+
+// The calling thread's current device must be `device`.
+krr_status scratch_init(int device) {
+  if (device < 0 || device >= KRR_MAX_DEVICES) return KRR_ERROR_NOT_SUPPORTED;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr[device]) return KRR_SUCCESS;
+  void *p = nullptr;
+  const hipError_t e = hipGetSymbolAddress((void **)&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !p) {
+    (void)hipGetLastError();
+    return KRR_ERROR_HIP;
+  }
+  g_scratch_ptr[device] = p;
+  return KRR_SUCCESS;
+}
+
+void *scratch_ptr(int device) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return (device >= 0 && device < KRR_MAX_DEVICES) ? g_scratch_ptr[device] : nullptr;
+}
+}  // namespace
 
 krr_status krr_create(krr_context *out, int device, void *stream, const krr_options *opts) {
   if (!out) return KRR_ERROR_INVALID_VALUE;
@@ -312,6 +348,7 @@ krr_status krr_create(krr_context *out, int device, void *stream, const krr_opti
   }
   if (device < 0 || device >= count) return KRR_ERROR_INVALID_VALUE;
   HIPCHK(hipSetDevice(device));
+  CHK(scratch_init(device));
   krr_context c = new krr_context_s();
   c->device = device;
   c->stream = (hipStream_t)stream;
@@ -1639,27 +1676,26 @@ krr_status krr_solve_batched(krr_context ctx, int32_t batch, const krr_factoriza
   return st;
 }
 
-krr_status krr_predict(krr_context ctx, krr_kernel K, const int8_t *T, int64_t n_test, int64_t ldt,
-                       const double *X, int64_t nrhs, int64_t ldx, double *P, int64_t ldp) {
+static krr_status predict_args(krr_context ctx, krr_kernel K, const int8_t *T, int64_t n_test,
+                               int64_t ldt, const double *X, int64_t nrhs, int64_t ldx,
+                               const double *P, int64_t ldp) {
   if (!ctx || !K || !T || !X || !P || n_test <= 0 || nrhs <= 0 || nrhs > 4096)
     return KRR_ERROR_INVALID_VALUE;
   if (K->ctx != ctx) return KRR_ERROR_INVALID_VALUE;
   if (ldt < K->m || (ldt % 16) != 0 || !aligned16(T) || ldx < K->n || ldp < n_test)
     return KRR_ERROR_INVALID_VALUE;
-  HIPCHK(hipSetDevice(ctx->device));
+  return KRR_SUCCESS;
+}
+
+// Predict with caller-placed buffers: nrm_t (n_test), flag (1), Dt (chunk x
+// np int32), Xr (np x r FP64).  Checks T's genotypes (one wait), then runs the
+// cross Gram and the FP64 product chunk by chunk of test rows.
+static krr_status predict_run(krr_context ctx, krr_kernel K, const int8_t *T, int64_t n_test,
+                              int64_t ldt, const double *X, int r, int64_t ldx, double *P,
+                              int64_t ldp, int32_t *nrm_t, int32_t *flag, int32_t *Dt,
+                              int64_t chunk, double *Xr) {
   hipStream_t s = ctx->stream;
   const TileLayout &L = K->L;
-  const int r = (int)nrhs;
-  // test rows per pass, so the int32 cross-distance block stays within ~2 GiB
-  int64_t chunk = std::max<int64_t>(256, ((int64_t)1 << 29) / L.np / 256 * 256);
-  chunk = std::min<int64_t>(chunk, (n_test + 255) / 256 * 256);
-  Scoped sc(ctx);
-  int32_t *nrm_t, *flag, *Dt;
-  double *Xr;
-  CHK(sc.alloc(&nrm_t, (n_test + 255) / 256 * 256));
-  CHK(sc.alloc(&flag, 1));
-  CHK(sc.alloc(&Dt, chunk * L.np));
-  CHK(sc.alloc(&Xr, L.np * r));
   launch_fill_i32(flag, 1, 0, s);
   launch_row_norms(T, n_test, n_test, K->m, ldt, nrm_t, flag, s);
   int32_t hflag = 0;
@@ -1680,6 +1716,79 @@ krr_status krr_predict(krr_context ctx, krr_kernel K, const int8_t *T, int64_t n
   }
   CHK(launch_ok());
   HIPCHK(hipStreamSynchronize(s));
+  return KRR_SUCCESS;
+}
+
+krr_status krr_predict(krr_context ctx, krr_kernel K, const int8_t *T, int64_t n_test, int64_t ldt,
+                       const double *X, int64_t nrhs, int64_t ldx, double *P, int64_t ldp) {
+  CHK(predict_args(ctx, K, T, n_test, ldt, X, nrhs, ldx, P, ldp));
+  HIPCHK(hipSetDevice(ctx->device));
+  const TileLayout &L = K->L;
+  const int r = (int)nrhs;
+  // test rows per pass, so the int32 cross-distance block stays within ~2 GiB
+  int64_t chunk = std::max<int64_t>(256, ((int64_t)1 << 29) / L.np / 256 * 256);
+  chunk = std::min<int64_t>(chunk, (n_test + 255) / 256 * 256);
+  Scoped sc(ctx);
+  int32_t *nrm_t, *flag, *Dt;
+  double *Xr;
+  CHK(sc.alloc(&nrm_t, (n_test + 255) / 256 * 256));
+  CHK(sc.alloc(&flag, 1));
+  CHK(sc.alloc(&Dt, chunk * L.np));
+  CHK(sc.alloc(&Xr, L.np * r));
+  return predict_run(ctx, K, T, n_test, ldt, X, r, ldx, P, ldp, nrm_t, flag, Dt, chunk, Xr);
+}
+
+// Layout of the fixed scratch for one no-allocation Predict: flag, test-row
+// norms, the row-major copy of X, then the cross distances of `chunk` test
+// rows.  Returns false when even a 64-row chunk does not fit.
+static bool noalloc_layout(int64_t n_test, int64_t np, int r, int64_t *off_nrm, int64_t *off_x,
+                           int64_t *off_dt, int64_t *chunk) {
+  auto up = [](int64_t b) { return (b + 255) / 256 * 256; };
+  *off_nrm = 256;
+  *off_x = *off_nrm + up(n_test * 4);
+  *off_dt = *off_x + up(np * (int64_t)r * 8);
+  const int64_t room = (int64_t)KRR_NOALLOC_SCRATCH_BYTES - *off_dt;
+  if (room <= 0) return false;
+  int64_t c = room / (np * 4) / 64 * 64;  // rows of cross distances that fit
+  c = std::min<int64_t>(c, (n_test + 63) / 64 * 64);
+  if (c < 64) return false;
+  *chunk = c;
+  return true;
+}
+
+krr_status krr_predict_noalloc(krr_context ctx, krr_kernel K, const int8_t *T, int64_t n_test,
+                               int64_t ldt, const double *X, int64_t nrhs, int64_t ldx, double *P,
+                               int64_t ldp) {
+  CHK(predict_args(ctx, K, T, n_test, ldt, X, nrhs, ldx, P, ldp));
+  const int r = (int)nrhs;
+  int64_t off_nrm, off_x, off_dt, chunk;
+  if (!noalloc_layout(n_test, K->L.np, r, &off_nrm, &off_x, &off_dt, &chunk))
+    return KRR_ERROR_SCRATCH_TOO_SMALL;
+  HIPCHK(hipSetDevice(ctx->device));
+  uint8_t *base = (uint8_t *)scratch_ptr(ctx->device);  // set up by krr_create
+  if (!base) return KRR_ERROR_HIP;
+  return predict_run(ctx, K, T, n_test, ldt, X, r, ldx, P, ldp, (int32_t *)(base + off_nrm),
+                     (int32_t *)base, (int32_t *)(base + off_dt), chunk,
+                     (double *)(base + off_x));
+}
+
+krr_status krr_noalloc_limits(int64_t n, int64_t n_test, int64_t nrhs, int32_t tile,
+                              int64_t *scratch_bytes, int32_t *fits) {
+  if (!scratch_bytes || !fits || n <= 0 || n_test <= 0 || nrhs <= 0) return KRR_ERROR_INVALID_VALUE;
+  if (tile == 0) tile = 512;
+  if (tile != 256 && tile != 512) return KRR_ERROR_INVALID_VALUE;
+  *scratch_bytes = (int64_t)KRR_NOALLOC_SCRATCH_BYTES;
+  int64_t a, b, c, d;
+  *fits = (nrhs <= 4096 && noalloc_layout(n_test, make_layout(n, tile).np, (int)nrhs, &a, &b, &c, &d))
+              ? 1
+              : 0;
+  return KRR_SUCCESS;
+}
+
+krr_status krr_context_memory(krr_context ctx, int64_t *allocated, int64_t *cached) {
+  if (!ctx) return KRR_ERROR_INVALID_VALUE;
+  if (allocated) *allocated = ctx->allocated;
+  if (cached) *cached = (int64_t)ctx->cached;
   return KRR_SUCCESS;
 }
 

@@ -44,8 +44,9 @@ def test_every_declared_symbol_is_exported(lib):
 
 
 def test_status_strings(lib):
-    for s in range(8):
+    for s in range(9):
         assert lib.krr_status_string(s)
+        assert lib.krr_status_string(s) != b"unknown status"
     assert b"genotype" in lib.krr_status_string(krr.KRR_ERROR_BAD_GENOTYPE)
 
 
@@ -121,4 +122,18 @@ def test_batched_arguments_rejected_on_host(lib):
     assert lib.krr_factor_batched(None, 2, None, None, outs) == krr.KRR_ERROR_INVALID_VALUE
     assert outs[0] is None and outs[1] is None
     assert lib.krr_solve_batched(None, 2, None, None, 1, None, None, None, None, None) == \
+        krr.KRR_ERROR_INVALID_VALUE
+
+
+def test_noalloc_limits_on_host(lib):
+    """The no-allocation Predict's size check needs no GPU."""
+    b, fits = krr.krr_noalloc_limits(32768, 20000, 16)
+    assert b == krr.KRR_NOALLOC_SCRATCH_BYTES == 64 << 20 and fits
+    assert not krr.krr_noalloc_limits(200000, 20000, 128)[1]  # X alone is 205 MB
+    assert not krr.krr_noalloc_limits(1000, 20_000_000, 1)[1]  # test-row norms 80 MB
+    assert not krr.krr_noalloc_limits(1000, 10, 5000)[1]  # more columns than Predict takes
+    b, f = ctypes.c_int64(), ctypes.c_int32()
+    assert lib.krr_noalloc_limits(0, 1, 1, 512, ctypes.byref(b), ctypes.byref(f)) == \
+        krr.KRR_ERROR_INVALID_VALUE
+    assert lib.krr_predict_noalloc(None, None, None, 1, 16, None, 1, 1, None, 1) == \
         krr.KRR_ERROR_INVALID_VALUE
