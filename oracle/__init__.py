@@ -21,6 +21,9 @@ Paper passages followed (arXiv 2409.01712):
   * Algorithm 3 (Associate): factorize K + lambda I (the paper names the
     regularisation alpha), then solve for the weights W.
   * Algorithm 4 (Predict): K_test = Build(gamma, T, G), P = K_test W.
+  * Ridge Regression subsection, Eq. 1-2: beta = (X^T X + lambda I)^-1 X^T Y, the
+    minimiser of ||Y - X beta||^2 + lambda ||beta||^2, with X^T X and X^T Y by their
+    definitions; predictions T beta.  The linear kernel K = G1 G2^T.
 
 Every function here has a pin in tests/test_oracle.py.
 """
@@ -64,9 +67,13 @@ def _load():
         lib.oracle_backward.argtypes = [P, I, I, P, I, I]
         lib.oracle_matmul.argtypes = [P, I, I, I, P, I, I, P, I]
         lib.oracle_residual_rows.argtypes = [P, I, I, I, D, D, P, I, P, I, P, I, I, P, I, I, P, I]
+        lib.oracle_dot.argtypes = [P, I, I, P, I, I, I, P, I]
+        lib.oracle_xtx.argtypes = [P, I, I, I, P]
+        lib.oracle_xty.argtypes = [P, I, I, I, P, I, I, P, I]
         for f in ("oracle_sqdist", "oracle_ibs_counts", "oracle_conf_sqdist", "oracle_gaussian",
                   "oracle_gaussian_real", "oracle_forward", "oracle_backward",
-                  "oracle_matmul", "oracle_residual_rows"):
+                  "oracle_matmul", "oracle_residual_rows", "oracle_dot", "oracle_xtx",
+                  "oracle_xty"):
             getattr(lib, f).restype = None
         _lib = lib
     return _lib
@@ -248,3 +255,51 @@ def residual_rows(G: np.ndarray, gamma: float, lam: float, X: np.ndarray, Y: np.
                                  1 if kind == "ibs" else 0,
                                  Cc.ctypes.data if Cc is not None else None, q)
     return R
+
+
+def dot(G1: np.ndarray, G2: np.ndarray | None = None) -> np.ndarray:
+    """Linear kernel between genotype rows, by definition: S_ij = sum_k G1[i,k] G2[j,k] (int64)."""
+    G1 = _rows(G1, np.int8)
+    G2 = G1 if G2 is None else _rows(G2, np.int8)
+    assert G1.shape[1] == G2.shape[1]
+    n1, m = G1.shape
+    n2 = G2.shape[0]
+    S = np.empty((n1, n2), np.int64)
+    _load().oracle_dot(G1.ctypes.data, n1, m, G2.ctypes.data, n2, m, m, S.ctypes.data, n2)
+    return S
+
+
+def xtx(G: np.ndarray) -> np.ndarray:
+    """X^T X of the genotype matrix (m x m, int64), a sum over patients (Eq. 2)."""
+    G = _rows(G, np.int8)
+    n, m = G.shape
+    S = np.empty((m, m), np.int64)
+    _load().oracle_xtx(G.ctypes.data, n, m, m, S.ctypes.data)
+    return S
+
+
+def xty(G: np.ndarray, Y: np.ndarray) -> np.ndarray:
+    """X^T Y (m x r, FP64), a sum over patients (Eq. 2)."""
+    G = _rows(G, np.int8)
+    Y = _rows(Y, np.float64)
+    if Y.ndim == 1:
+        Y = Y[:, None]
+    n, m = G.shape
+    r = Y.shape[1]
+    B = np.empty((m, r), np.float64)
+    _load().oracle_xty(G.ctypes.data, n, m, m, Y.ctypes.data, r, r, B.ctypes.data, r)
+    return B
+
+
+def rr_fit(G: np.ndarray, Y: np.ndarray, lam: float) -> np.ndarray:
+    """Ridge Regression, Eq. 2: beta = (X^T X + lambda I)^-1 X^T Y through the Cholesky
+    factor of X^T X + lambda I and two substitutions (m x r, FP64)."""
+    A = xtx(G).astype(np.float64)
+    A[np.diag_indices_from(A)] += lam
+    L = cholesky(A)
+    return backward(L, forward(L, xty(G, Y)))
+
+
+def rr_predict(T: np.ndarray, beta: np.ndarray) -> np.ndarray:
+    """Predictions of the linear model, T beta (FP64)."""
+    return matmul(np.asarray(T, np.float64), beta)

@@ -26,6 +26,10 @@
  *   Associate (Algorithm 3): A = K + lambda*I, A = L L^T (Cholesky),
  *             then L Z = Y and L^T W = Z (forward / back substitution).
  *   Predict   (Algorithm 4): K_test = Build(gamma, T, G), P = K_test W.
+ *   Ridge Regression (RR subsection, Eq. 1-2): beta = (X^T X + lambda I)^-1 X^T Y
+ *             with X the n x m genotype matrix; X^T X and X^T Y by their
+ *             definitions (sums over patients), then the same Cholesky and
+ *             substitutions.  The linear kernel K_ij = sum_k g_ik g_jk.
  *
  * Matrices are row-major; Y, W, P are row-major n x r here (the Python
  * wrapper converts).
@@ -211,4 +215,44 @@ void oracle_residual_rows(const int8_t *G, int64_t n, int64_t m, int64_t ldg,
     for (int64_t c = 0; c < r; ++c) R[t * ldr + c] = Y[i * ldy + c] - acc[c];
     free(acc);
   }
+}
+
+/* Linear kernel (inner products of genotype rows), by definition:
+ * S[i*ldd + j] = sum_k G1[i,k] * G2[j,k]. */
+void oracle_dot(const int8_t *G1, int64_t n1, int64_t ld1, const int8_t *G2, int64_t n2,
+                int64_t ld2, int64_t m, int64_t *S, int64_t ldd) {
+#pragma omp parallel for schedule(dynamic, 4)
+  for (int64_t i = 0; i < n1; ++i) {
+    const int8_t *a = G1 + i * ld1;
+    for (int64_t j = 0; j < n2; ++j) {
+      const int8_t *b = G2 + j * ld2;
+      int64_t s = 0;
+      for (int64_t k = 0; k < m; ++k) s += (int64_t)a[k] * (int64_t)b[k];
+      S[i * ldd + j] = s;
+    }
+  }
+}
+
+/* X^T X of the n x m genotype matrix, by definition (a sum over patients):
+ * S[a*m + b] = sum_i G[i,a] * G[i,b]  (RR subsection, Eq. 2). */
+void oracle_xtx(const int8_t *G, int64_t n, int64_t m, int64_t ldg, int64_t *S) {
+#pragma omp parallel for schedule(dynamic, 4)
+  for (int64_t a = 0; a < m; ++a)
+    for (int64_t b = 0; b < m; ++b) {
+      int64_t s = 0;
+      for (int64_t i = 0; i < n; ++i) s += (int64_t)G[i * ldg + a] * (int64_t)G[i * ldg + b];
+      S[a * m + b] = s;
+    }
+}
+
+/* X^T Y, by definition: B[a*ldb + c] = sum_i G[i,a] * Y[i*ldy + c]  (Eq. 2). */
+void oracle_xty(const int8_t *G, int64_t n, int64_t m, int64_t ldg, const double *Y, int64_t r,
+                int64_t ldy, double *B, int64_t ldb) {
+#pragma omp parallel for schedule(static)
+  for (int64_t a = 0; a < m; ++a)
+    for (int64_t c = 0; c < r; ++c) {
+      double s = 0.0;
+      for (int64_t i = 0; i < n; ++i) s += (double)G[i * ldg + a] * Y[i * ldy + c];
+      B[a * ldb + c] = s;
+    }
 }

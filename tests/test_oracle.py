@@ -439,3 +439,73 @@ def test_ld_blocks():
     f = founders[0]
     same = (G[:, f + 1:f + length] == G[:, f:f + 1]).mean()
     assert 0.85 < same < 0.99  # ~10% resampled, some of those equal by chance
+
+
+# --- Ridge Regression (RR subsection, Eq. 1-2) -----------------------------------------
+
+def _rr_golden(golden_dir):
+    spec = json.load(open(os.path.join(golden_dir, "ridge_regression.json")))
+    X = np.array(spec["X"], np.int8)
+    Y = np.array(spec["Y"], np.float64)[:, None]
+    return spec, X, Y
+
+
+def test_rr_golden_values(golden_dir):
+    spec, X, Y = _rr_golden(golden_dir)
+    assert oracle.xtx(X).tolist() == spec["XtX"]
+    assert oracle.xty(X, Y)[:, 0].tolist() == spec["XtY"]
+    beta = oracle.rr_fit(X, Y, spec["lambda"])[:, 0]
+    want = np.array([float(v) for v in spec["beta"]])
+    assert np.all(np.abs(beta - want) <= 4 * np.spacing(np.abs(want)))
+    P = oracle.rr_predict(np.array(spec["T"], np.int8), beta[:, None])[:, 0]
+    assert abs(P[0] - float(spec["P"][0])) <= 4 * np.spacing(0.625)
+
+
+def test_rr_planted_mistakes_are_caught(golden_dir):
+    """The regulariser subtracted instead of added, X X^T in place of X^T X, and a
+    transposed X^T Y each fail the hand-worked solution or its dimensions."""
+    spec, X, Y = _rr_golden(golden_dir)
+    want = np.array([float(v) for v in spec["beta"]])[:, None]
+    lam = spec["lambda"]
+    A = oracle.xtx(X).astype(np.float64)
+    minus = np.linalg.solve(A - lam * np.eye(2), oracle.xty(X, Y))
+    assert not np.allclose(minus, want, rtol=1e-12, atol=0)
+    wrong_gram = oracle.dot(X).astype(np.float64) + lam * np.eye(3)  # n x n, not m x m
+    assert wrong_gram.shape != A.shape
+    swapped = np.linalg.solve(A + lam * np.eye(2), oracle.xty(X[:, ::-1], Y))
+    assert not np.allclose(swapped, want, rtol=1e-12, atol=0)
+
+
+@pytest.mark.parametrize("n,m", [(60, 40), (30, 80)])
+def test_rr_is_the_penalised_least_squares_minimiser(n, m):
+    """Eq. 2's beta minimises Eq. 1: it equals the least-squares solution of the
+    augmented system [X; sqrt(lambda) I] beta = [Y; 0] (LAPACK's SVD-based lstsq), and
+    it satisfies the stationarity condition X^T (Y - X beta) = lambda beta -- with more
+    patients than SNPs and with fewer (N_P << N_S, where the regulariser is needed)."""
+    rng = np.random.default_rng(n * m)
+    G = synth.genotypes(n, m, synth.maf_uniform(m, 0.05, 0.5, 7), 7)
+    Y = rng.standard_normal((n, 3))
+    lam = 0.7
+    beta = oracle.rr_fit(G, Y, lam)
+    X = G.astype(np.float64)
+    aug = np.vstack([X, np.sqrt(lam) * np.eye(m)])
+    ref = np.linalg.lstsq(aug, np.vstack([Y, np.zeros((m, 3))]), rcond=None)[0]
+    assert np.max(np.abs(beta - ref)) <= 1e-10 * np.max(np.abs(ref))
+    grad = X.T @ (Y - X @ beta) - lam * beta
+    assert np.max(np.abs(grad)) <= 1e-9 * np.max(np.abs(X.T @ Y))
+
+
+def test_rr_products_by_definition():
+    """X^T X and X^T Y against brute force over patients; the linear kernel is the
+    inner product of rows, and X^T X is the linear kernel of the SNP columns."""
+    G = synth.genotypes(37, 23, synth.maf_uniform(23, 0.05, 0.5, 3), 3)
+    Y = np.random.default_rng(1).standard_normal((37, 2))
+    S = oracle.xtx(G)
+    for a in range(23):
+        for b in range(23):
+            assert S[a, b] == sum(int(G[i, a]) * int(G[i, b]) for i in range(37))
+    B = oracle.xty(G, Y)
+    for a in (0, 11, 22):
+        assert abs(B[a, 1] - sum(float(G[i, a]) * Y[i, 1] for i in range(37))) <= 1e-12
+    assert np.array_equal(oracle.dot(np.ascontiguousarray(G.T)), S)
+    assert np.array_equal(oracle.dot(G), G.astype(np.int64) @ G.T.astype(np.int64))
