@@ -6,6 +6,7 @@ call although the scratch keeps the previous call's contents, and reject
 inputs larger than its scratch before doing any work.
 """
 import ctypes
+import gc
 
 import numpy as np
 import pytest
@@ -40,13 +41,21 @@ def _noalloc(ctx, K, T, X):
     nor torch allocated device memory during the call."""
     P = torch.full((X.shape[1], T.shape[0]), np.nan, dtype=torch.float64, device=DEV).t()
     torch.cuda.synchronize()
-    before_lib = krr.krr_context_memory(ctx)
-    before_torch = torch.cuda.memory_allocated()
-    out = krr.krr_predict_noalloc(ctx, K, T, X, P)
-    torch.cuda.synchronize()
+    # no collection of earlier tests' garbage may free torch memory during the call
+    gc.collect()
+    gc.disable()
+    try:
+        before_lib = krr.krr_context_memory(ctx)
+        before_torch = torch.cuda.memory_allocated()
+        out = krr.krr_predict_noalloc(ctx, K, T, X, P)
+        torch.cuda.synchronize()
+        after_lib = krr.krr_context_memory(ctx)
+        after_torch = torch.cuda.memory_allocated()
+    finally:
+        gc.enable()
     assert out.data_ptr() == P.data_ptr()
-    assert krr.krr_context_memory(ctx) == before_lib
-    assert torch.cuda.memory_allocated() == before_torch
+    assert after_lib == before_lib
+    assert after_torch == before_torch
     return out.cpu().numpy()
 
 
