@@ -102,7 +102,12 @@ def parse():
     ap.add_argument("--refine", choices=["ir", "pcg", "auto"], default="ir",
                     help="refinement method of the adaptive path")
     ap.add_argument("--high-panels", type=int, default=1)
-    ap.add_argument("--tile", type=int, default=512)
+    ap.add_argument("--tile", type=int, default=512,
+                    help="tile size when the autotuner is off (--no-tune)")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="skip the autotuner: library defaults with --tile")
+    ap.add_argument("--tune-cache", default=os.environ.get("KRR_TUNE_CACHE"),
+                    help="autotuner cache file (JSON); default none, i.e. search every run")
     ap.add_argument("--verbose", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="only copy this many bytes device to device (calibrates HBM counters)")
@@ -155,6 +160,7 @@ def main():
     ctx = krr.krr_create(0, tile=args.tile)
     adaptive = krr.Policy(eps=args.eps, high_panels=args.high_panels)
     plain = krr.plain_fp32_policy()
+    ctx_plain = krr.krr_create(0, tile=args.tile)
     # The metric's accuracy target, 1e-5 relative error against the exact
     # solution, enforced through the rigorous bound ||x - x*|| <= ||r|| / lambda
     # (K + lambda I has smallest eigenvalue >= lambda): stopping at
@@ -164,16 +170,30 @@ def main():
     refine = krr.Refine(method=method, max_iters=30, tol=REFINE_TOL)
     no_refine = krr.Refine(method=krr.KRR_REFINE_NONE)
 
-    def step(policy, ref):
-        K = krr.krr_build_kernel(ctx, G, w.gamma, w.lam)
-        F = krr.krr_factor(ctx, K, policy)
-        X, info, st = krr.krr_solve(ctx, F, Y, ref, check=False)
+    def step(policy, ref, c=None):
+        c = c or ctx
+        K = krr.krr_build_kernel(c, G, w.gamma, w.lam)
+        F = krr.krr_factor(c, K, policy)
+        X, info, st = krr.krr_solve(c, F, Y, ref, check=False)
         if T is not None:
-            krr.krr_predict(ctx, K, T, X)
+            krr.krr_predict(c, K, T, X)
         finfo = krr.krr_factor_get_info(F)
         F.release()
         K.release()
         return X, info, st, finfo
+
+    # the same autotuner picks each path's schedule (tile, panel group, residual
+    # split, sweep pairing) on these inputs, outside the timed region
+    tuning = {}
+    if not args.no_tune:
+        t0 = time.time()
+        tuning["adaptive"], _ = krr.krr_autotune(ctx, G, Y, w.gamma, w.lam, adaptive, refine,
+                                                 args.tune_cache)
+        if not args.no_plain:
+            tuning["plain_fp32"], _ = krr.krr_autotune(ctx_plain, G, Y, w.gamma, w.lam, plain,
+                                                       no_refine, args.tune_cache)
+        log("autotuned in %.1fs: %s" % (time.time() - t0, tuning))
+    nb = krr.krr_get_tuning(ctx)["tile"]
 
     for i in range(args.warmup):
         step(adaptive, refine)
@@ -213,8 +233,8 @@ def main():
         "config": {
             "workload": "single KRR instance n=%d patients, m=%d SNPs, r=%d phenotypes, "
                         "gamma=1/m, lambda=%g, tile %d, adaptive FP32/FP16/FP8 updates + FP64 "
-                        "diagonal + FP64 refinement" % (n, m, r, w.lam, args.tile),
-            "n": n, "m": m, "nrhs": r, "gamma": w.gamma, "lambda": w.lam, "tile": args.tile,
+                        "diagonal + FP64 refinement" % (n, m, r, w.lam, nb),
+            "n": n, "m": m, "nrhs": r, "gamma": w.gamma, "lambda": w.lam, "tile": nb,
             "eps": args.eps, "high_panels": args.high_panels,
             "parallelism": "single GPU",
         },
@@ -227,6 +247,7 @@ def main():
         "updates": {"fp32": int(finfo.updates[0]), "fp16": int(finfo.updates[1]),
                     "fp8": int(finfo.updates[2]), "promotions": int(finfo.promotions)},
         "stages_ms_per_step": {k: round(v[0] / args.steps, 4) for k, v in stages.items() if v[1]},
+        "tuning": tuning or {"adaptive": krr.krr_get_tuning(ctx)},
     }
 
     # dominant kernel: the INT8 Gram (one launch per step)
@@ -244,7 +265,6 @@ def main():
     # trailing-update MFMA utilisation: algorithmic flops per precision (off-diagonal tile
     # update 2 nb^3; a diagonal tile's lower triangle nb^2 (nb + 1), always FP32) against the
     # time at each precision's dense peak, over the update kernels' summed time
-    nb = args.tile
     NT = (n + nb - 1) // nb
     ndiag = NT * (NT - 1) // 2
     f_off, f_diag = 2.0 * nb ** 3, float(nb) * nb * (nb + 1)
@@ -259,20 +279,20 @@ def main():
 
     if not args.no_plain:
         for i in range(args.warmup):
-            step(plain, no_refine)
+            step(plain, no_refine, ctx_plain)
         torch.cuda.synchronize()
-        krr.krr_timers_enable(ctx, True)
+        krr.krr_timers_enable(ctx_plain, True)
         t0 = time.perf_counter()
         for i in range(args.plain_steps):
-            Xp, pinfo, _, _ = step(plain, no_refine)
+            Xp, pinfo, _, _ = step(plain, no_refine, ctx_plain)
         torch.cuda.synchronize()
         pdt = (time.perf_counter() - t0) / args.plain_steps
-        pstages = krr.krr_timers_read(ctx)
-        krr.krr_timers_enable(ctx, False)
+        pstages = krr.krr_timers_read(ctx_plain)
+        krr.krr_timers_enable(ctx_plain, False)
         # accuracy of the plain path, measured by the FP64 residual bound
-        K = krr.krr_build_kernel(ctx, G, w.gamma, w.lam)
-        F = krr.krr_factor(ctx, K, plain)
-        _, pin, _ = krr.krr_solve(ctx, F, Y, krr.Refine(max_iters=0, tol=0.0), check=False)
+        K = krr.krr_build_kernel(ctx_plain, G, w.gamma, w.lam)
+        F = krr.krr_factor(ctx_plain, K, plain)
+        _, pin, _ = krr.krr_solve(ctx_plain, F, Y, krr.Refine(max_iters=0, tol=0.0), check=False)
         F.release()
         K.release()
         out["plain_fp32"] = {"value": ops / pdt, "ms_per_step": pdt * 1e3,

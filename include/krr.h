@@ -62,11 +62,23 @@ typedef struct krr_context_s *krr_context;
 typedef struct krr_kernel_s *krr_kernel;
 typedef struct krr_factor_s *krr_factorization;
 
+/* Device allocator a caller may supply (both functions or neither): alloc
+ * returns device memory of at least `bytes` on the context's device (NULL on
+ * failure, reported as KRR_ERROR_OUT_OF_MEMORY); free gets back exactly what
+ * alloc returned, with the same size.  The library keeps freed blocks in its
+ * per-context cache and returns them through free when the cache is flushed
+ * (krr_destroy, or an allocation failure). */
+typedef void *(*krr_alloc_fn)(uint64_t bytes, void *user);
+typedef void (*krr_free_fn)(void *ptr, uint64_t bytes, void *user);
+
 /* Context options. */
 typedef struct krr_options {
   int32_t tile;             /* Cholesky tile size nb: 256 or 512 (0 = 512) */
   int32_t verbose;          /* 0 = silent; 1 = per-call summary on stderr */
   int64_t workspace_limit;  /* max bytes the library may allocate (0 = no cap) */
+  krr_alloc_fn device_alloc;/* NULL: hipMalloc */
+  krr_free_fn device_free;  /* NULL: hipFree */
+  void *alloc_user;         /* passed to both */
 } krr_options;
 
 /* Operand precisions of a trailing-matrix update. */
@@ -74,9 +86,17 @@ enum { KRR_PREC_FP32 = 0, KRR_PREC_FP16 = 1, KRR_PREC_FP8 = 2 };
 
 /* Factorization precision policies. */
 enum {
-  KRR_POLICY_FP32 = 0,     /* every update in FP32 (the plain single-precision path) */
-  KRR_POLICY_ADAPTIVE = 1, /* per-update precision from operand tile norms */
-  KRR_POLICY_FIXED = 2     /* every off-diagonal update of panels >= high_panels in fixed_prec */
+  KRR_POLICY_FP32 = 0,      /* every update in FP32 (the plain single-precision path) */
+  KRR_POLICY_ADAPTIVE = 1,  /* per-update precision from operand (or tile) norms */
+  KRR_POLICY_FIXED = 2,     /* every off-diagonal update of panels >= high_panels in fixed_prec */
+  KRR_POLICY_FIXED_MAP = 3  /* the caller's map gives every off-diagonal update's precision */
+};
+
+/* ADAPTIVE precision rules (krr_precision_policy.rule). */
+enum {
+  KRR_RULE_OPERAND = 0, /* u_p ||L_IK||_F ||L_JK||_F <= eps ||A||_F / NT (default) */
+  KRR_RULE_TILE = 1,    /* u_p ||A_IJ||_F <= eps ||A||_F / NT, ||A_IJ|| from the build */
+  KRR_RULE_BOTH = 2     /* both must hold: the tile rule is a ceiling on the operand rule */
 };
 
 /*
@@ -86,9 +106,23 @@ enum {
  *
  * ADAPTIVE: the update A_IJ -= L_IK L_JK^T (I > J > K) uses the lowest
  * allowed precision p with  u_p * ||L_IK||_F * ||L_JK||_F <= eps * ||A||_F / NT,
- * u_FP8 = 2^-4, u_FP16 = 2^-11; otherwise FP32.  Updates of diagonal tiles
- * and of panels K < high_panels are always FP32.  Low-precision operands
- * carry a per-tile power-of-two scale; accumulation is FP32.
+ * u_FP8 = 2^-4, u_FP16 = 2^-11; otherwise FP32 (rule KRR_RULE_OPERAND; see
+ * KRR_RULE_* for the tile-norm variants).  Updates of diagonal tiles and of
+ * panels K < high_panels are always FP32.  FP8 operands carry a per-tile
+ * power-of-two scale (unless no_fp8_scale); accumulation is FP32.
+ *
+ * FIXED_MAP: fixed_map (HOST memory, fixed_map_count = NT * NT(NT+1)/2
+ * bytes in the layout krr_factor_precision_map returns, NT = ceil(n / tile))
+ * gives KRR_PREC_* for the update of tile (I, J) by panel K; entries of
+ * diagonal tiles and values > KRR_PREC_FP8 mean FP32.  Replaying a map that
+ * krr_factor_precision_map exported reproduces that factor bit for bit.
+ *
+ * Promotion (allow_promotion): after a non-positive pivot in tile row B,
+ * every panel K < B may use one precision level less than before (FP8 ->
+ * FP16 -> FP32) and the factorization is redone from the stored distances;
+ * when all those panels are FP32 already, the diagonal POTRF moves to FP64;
+ * when that is done too, KRR_ERROR_NOT_POSITIVE_DEFINITE.
+ * A zero-initialised struct with mode and eps set is a valid policy.
  */
 typedef struct krr_precision_policy {
   int32_t mode;            /* KRR_POLICY_* */
@@ -96,8 +130,12 @@ typedef struct krr_precision_policy {
   double eps;              /* ADAPTIVE threshold (default 1.0) */
   int32_t high_panels;     /* panels K < high_panels update in FP32 (default 1) */
   int32_t fixed_prec;      /* FIXED mode: KRR_PREC_FP16 or KRR_PREC_FP8 */
-  int32_t allow_promotion; /* on breakdown, drop the lowest precision and refactor */
+  int32_t allow_promotion; /* on breakdown, promote the panels before it and refactor */
   int32_t diag_fp64;       /* 1: diagonal-tile POTRF in FP64; 0: in FP32 */
+  int32_t rule;            /* ADAPTIVE: KRR_RULE_* (0 = operand norms) */
+  int32_t no_fp8_scale;    /* 1: FP8 operands without the per-tile power-of-two scale */
+  const uint8_t *fixed_map;/* FIXED_MAP only (host), else NULL */
+  int64_t fixed_map_count; /* bytes at fixed_map */
 } krr_precision_policy;
 
 /* Refinement methods for krr_solve. */
@@ -157,6 +195,52 @@ krr_status krr_build_kernel(krr_context ctx, const int8_t *G, int64_t n, int64_t
                             double gamma, double lambda, krr_kernel *out);
 krr_status krr_kernel_release(krr_kernel K);
 
+/* Kernel types of Algorithm 5. */
+enum {
+  KRR_KERNEL_GAUSSIAN = 0, /* K_ij = exp(-gamma (d_ij + dc_ij)), dc from the confounders (if any) */
+  KRR_KERNEL_IBS = 1,      /* K_ij = (alleles shared identical by state) / (2m); gamma unused */
+  KRR_KERNEL_LINEAR = 2    /* K_ij = g_i . g_j (exact int32; FP32 exact below 2^24); gamma
+                              unused.  krr_kernel_copy_distances returns the inner products */
+};
+
+/*
+ * Optional description of the kernel for krr_build_kernel_ex.
+ *
+ * IBS (Algorithm 5, IBS branch; the SKAT kernel of the state-of-the-art
+ * survey): for genotypes a, b in {0, 1, 2} the alleles shared identical by
+ * state are 2 - |a - b|; summed over the m SNPs and divided by the 2m
+ * alleles of a patient (the text's normalisation; the algorithm's listing
+ * divides by m).  Computed exactly as 1 - d/(2m) with d = sum_k |g_ik - g_jk|,
+ * the squared distance of thermometer-encoded rows ([g >= 1], [g >= 2])
+ * through the same INT8 Gram.  The library keeps the encoded copy (n x
+ * 2 round_up(m, 16) bytes); krr_kernel_copy_distances returns d.
+ *
+ * Confounders (subsection "Engaging INT8 Tensor Cores for Distance
+ * Calculations": real-valued covariates whose squared distances are added to
+ * the integer genotype distances before the exponential): C is n x q FP64
+ * row-major (one patient per row, leading dimension ldc >= q, q <= 32), a
+ * DEVICE array copied at build time.  dc_ij = sum_k (c_ik - c_jk)^2 in FP64;
+ * the library keeps exp(-gamma dc_ij) in FP64 (8 bytes per stored entry) for
+ * the FP64 residual and multiplies it into the FP32 matrix.  Gaussian only;
+ * Predict then needs the test rows' confounders (krr_predict_ex); the
+ * batched solve and predict return KRR_ERROR_NOT_SUPPORTED for such kernels.
+ */
+typedef struct krr_kernel_desc {
+  int32_t kind;     /* KRR_KERNEL_* */
+  int32_t reserved; /* 0 */
+  const double *C;  /* confounders (device), or NULL */
+  int64_t q;        /* confounders per patient */
+  int64_t ldc;      /* row pitch of C in elements */
+} krr_kernel_desc;
+
+/* Build with a kernel description (NULL = Gaussian without confounders, the
+ * same as krr_build_kernel).  Errors as krr_build_kernel, plus
+ * KRR_ERROR_INVALID_VALUE for an unknown kind or bad confounder sizes and
+ * KRR_ERROR_NOT_SUPPORTED for q > 32. */
+krr_status krr_build_kernel_ex(krr_context ctx, const int8_t *G, int64_t n, int64_t m, int64_t ldg,
+                               double gamma, double lambda, const krr_kernel_desc *desc,
+                               krr_kernel *out);
+
 /*
  * Factorize (Algorithm 3, first half): L L^T = K + lambda*I under the
  * precision policy (NULL = ADAPTIVE defaults).  The first factorization of
@@ -192,6 +276,13 @@ krr_status krr_solve(krr_context ctx, krr_factorization F, const double *Y, int6
  */
 krr_status krr_predict(krr_context ctx, krr_kernel K, const int8_t *T, int64_t n_test, int64_t ldt,
                        const double *X, int64_t nrhs, int64_t ldx, double *P, int64_t ldp);
+/* Predict for any kernel of krr_build_kernel_ex: the IBS kernel compares the
+ * encoded test rows; with confounders Ct (n_test x q FP64 row-major, ldct >=
+ * q, device) holds the test rows' covariates (NULL otherwise).  krr_predict
+ * returns KRR_ERROR_INVALID_VALUE for a kernel with confounders. */
+krr_status krr_predict_ex(krr_context ctx, krr_kernel K, const int8_t *T, int64_t n_test,
+                          int64_t ldt, const double *Ct, int64_t ldct, const double *X,
+                          int64_t nrhs, int64_t ldx, double *P, int64_t ldp);
 
 /*
  * Predict without any device allocation, for callers that cannot allocate:
@@ -202,7 +293,8 @@ krr_status krr_predict(krr_context ctx, krr_kernel K, const int8_t *T, int64_t n
  * chunk of test rows) live in a fixed device scratch of
  * KRR_NOALLOC_SCRATCH_BYTES that each device holds from krr_create until the
  * process ends.  Calls no hipMalloc/hipFree and no allocating library routine.
- * Limit: 256 + 4*n_test + 8*np*nrhs + 4*64*np bytes (rounded up to 256 each;
+ * Gaussian kernels without confounders only (KRR_ERROR_NOT_SUPPORTED
+ * otherwise).  Limit: 256 + 4*n_test + 8*np*nrhs + 4*64*np bytes (rounded up to 256 each;
  * np = n rounded up to the tile size) must fit, else
  * KRR_ERROR_SCRATCH_TOO_SMALL before any work (krr_noalloc_limits answers
  * the question in advance).  Every call on one device shares that device's
@@ -265,6 +357,38 @@ krr_status krr_solve_batched(krr_context ctx, int32_t batch, const krr_factoriza
                              double *const *X, const int64_t *ldx, const krr_refine_opts *opts,
                              krr_solve_info *info);
 
+/* Predict (Algorithm 4) for `batch` kernels: P[b] = K_test,b X[b] with
+ * K_test,b built from T[b] (n_test[b] x m_b, ldt[b]) and kernel K[b]'s G.
+ * X[b]: n_b x nrhs (ldx[b]), P[b]: n_test[b] x nrhs (ldp[b]), FP64
+ * column-major device arrays.  Every instance's genotype check runs first
+ * (one wait; KRR_ERROR_BAD_GENOTYPE and no output if any fails), then the
+ * instances' cross Grams and products in order on the context stream, in
+ * one cross-distance buffer sized for the largest.  Blocks until done. */
+krr_status krr_predict_batched(krr_context ctx, int32_t batch, const krr_kernel *K,
+                               const int8_t *const *T, const int64_t *n_test, const int64_t *ldt,
+                               const double *const *X, int64_t nrhs, const int64_t *ldx,
+                               double *const *P, const int64_t *ldp);
+
+/* ---- Ridge Regression ---------------------------------------------------
+ * The RR subsection (Eq. 1-2): beta = (X^T X + lambda I)^-1 X^T Y minimises
+ * ||Y - X beta||^2 + lambda ||beta||^2, X = G the n x m genotype matrix
+ * (int8 {0,1,2}, row-major, ldg as for krr_build_kernel).  X^T X (m x m) is
+ * the linear kernel of the SNP columns, formed by the INT8 Gram on X^T
+ * (exact int32, n <= 2^22 so that its entries stay exact in FP32); X^T Y in
+ * FP64; then krr_factor under `policy` and krr_solve with `refine` (FP64
+ * refinement against the exact X^T X).  Y: n x nrhs, beta: m x nrhs, FP64
+ * column-major device arrays.  Errors as krr_build_kernel / krr_factor /
+ * krr_solve (KRR_ERROR_NOT_CONVERGED with beta written).  Blocks. */
+krr_status krr_rr_fit(krr_context ctx, const int8_t *G, int64_t n, int64_t m, int64_t ldg,
+                      const double *Y, int64_t nrhs, int64_t ldy, double lambda,
+                      const krr_precision_policy *policy, const krr_refine_opts *refine,
+                      double *beta, int64_t ldb, krr_solve_info *info);
+/* Predictions of the fitted model, P = T beta (n_test x nrhs, FP64
+ * column-major; T int8 n_test x m row-major, ldt >= m).  Blocks. */
+krr_status krr_rr_predict(krr_context ctx, const int8_t *T, int64_t n_test, int64_t m,
+                          int64_t ldt, const double *beta, int64_t nrhs, int64_t ldb, double *P,
+                          int64_t ldp);
+
 /* ---- diagnostics (tests and reports) ---------------------------------- */
 
 /* Copy the rows x cols block at (i0, j0) of the exact int32 distance
@@ -290,6 +414,60 @@ krr_status krr_kernel_tile_norms(krr_kernel K, double *host_dst, int64_t count);
  * entry [k * NT(NT+1)/2 + I(I+1)/2 + J] for the update of tile (I, J) by
  * panel k (255 where no update happens), recorded at every NT. */
 krr_status krr_factor_precision_map(krr_factorization F, uint8_t *host_dst, int64_t count);
+
+/* ---- schedule tuning and the autotuner ---------------------------------- */
+
+/* Schedule choices of a context (0 or -1: the library's default). */
+typedef struct krr_tuning {
+  int32_t tile;           /* Cholesky tile nb: 256 or 512 */
+  int32_t panel_group;    /* panels per grouped trailing update, 1 .. 8 (0: 8 for FP16/FP8
+                             updates, 4 for FP32) */
+  int32_t residual_split; /* column ranges of the FP64 residual, 1 .. 16 (0: min(8, NT)) */
+  int32_t sweep_pairs;    /* 1: triangular sweeps over tile pairs, 0: one tile per step (-1: 1) */
+  int32_t lookahead;      /* 1: three-stream factorization schedule, 0: one stream (-1: 1) */
+} krr_tuning;
+
+/* Set or read the context's tuning.  Changing the tile needs a context with
+ * no live kernel or factor handles (KRR_ERROR_INVALID_VALUE otherwise). */
+krr_status krr_set_tuning(krr_context ctx, const krr_tuning *t);
+krr_status krr_get_tuning(krr_context ctx, krr_tuning *t);
+
+/*
+ * Autotuner: chooses the context's tuning for one problem shape by timing
+ * whole build + factor + solve steps (HIP events on the context stream) on
+ * the caller's data, searching one choice at a time: the tile (256, 512,
+ * each after an untimed warm-up), then the panel group (4, 6, 8), the
+ * residual split (4, 8, 16) and the sweep pairing, each at the best choices
+ * so far.  The result is kept in the context (krr_get_tuning) and written to
+ * *out and *best_ms.  With cache_path (a host path, may be NULL) the choice
+ * is looked up first under the key of krr_tuning_key, and stored there after
+ * a search; a cached choice is applied without running anything.  The
+ * context must have no live handles (the tile may change).  Candidates that
+ * fail (for instance NOT_CONVERGED) are skipped; KRR_ERROR_NOT_CONVERGED if
+ * all do.  Arguments as krr_build_kernel / krr_factor / krr_solve.
+ */
+krr_status krr_autotune(krr_context ctx, const int8_t *G, int64_t n, int64_t m, int64_t ldg,
+                        double gamma, double lambda, const double *Y, int64_t nrhs, int64_t ldy,
+                        const krr_precision_policy *policy, const krr_refine_opts *refine,
+                        const char *cache_path, krr_tuning *out, double *best_ms);
+
+/* The autotuner's cache key for a problem on `device` (host only; no GPU
+ * work beyond reading the device's properties): architecture, compute-unit
+ * count, n, m, nrhs, the policy's mode and diagonal precision, the
+ * refinement method.  Written NUL-terminated into key (cap bytes). */
+krr_status krr_tuning_key(int device, int64_t n, int64_t m, int64_t nrhs,
+                          const krr_precision_policy *policy, const krr_refine_opts *refine,
+                          char *key, int32_t cap);
+/* The cache file (host only, no GPU): a JSON object with one entry per key,
+ * {"key": {"tile": .., "panel_group": .., "residual_split": .., "sweep_pairs": ..,
+ * "lookahead": .., "ms": ..}, ...}.  store adds or replaces one entry (the
+ * file is rewritten whole, through a temporary file and a rename); load sets
+ * *found to 0 when the file or the key is absent, KRR_ERROR_INVALID_VALUE on
+ * a malformed entry for the key. */
+krr_status krr_tuning_cache_store(const char *path, const char *key, const krr_tuning *t,
+                                  double ms);
+krr_status krr_tuning_cache_load(const char *path, const char *key, krr_tuning *t, double *ms,
+                                 int32_t *found);
 
 /* ---- per-stage timers (HIP events on the context stream) -------------- */
 

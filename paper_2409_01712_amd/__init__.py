@@ -30,19 +30,42 @@ KRR_ERROR_SCRATCH_TOO_SMALL = 8
 KRR_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 KRR_PREC_FP32, KRR_PREC_FP16, KRR_PREC_FP8 = 0, 1, 2
-KRR_POLICY_FP32, KRR_POLICY_ADAPTIVE, KRR_POLICY_FIXED = 0, 1, 2
+KRR_POLICY_FP32, KRR_POLICY_ADAPTIVE, KRR_POLICY_FIXED, KRR_POLICY_FIXED_MAP = 0, 1, 2, 3
+KRR_RULE_OPERAND, KRR_RULE_TILE, KRR_RULE_BOTH = 0, 1, 2
+KRR_KERNEL_GAUSSIAN, KRR_KERNEL_IBS, KRR_KERNEL_LINEAR = 0, 1, 2
 KRR_REFINE_NONE, KRR_REFINE_IR, KRR_REFINE_PCG, KRR_REFINE_AUTO = 0, 1, 2, 3
+
+
+KRR_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p)
+KRR_FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p)
 
 
 class krr_options(ctypes.Structure):
     _fields_ = [("tile", ctypes.c_int32), ("verbose", ctypes.c_int32),
-                ("workspace_limit", ctypes.c_int64)]
+                ("workspace_limit", ctypes.c_int64), ("device_alloc", KRR_ALLOC_FN),
+                ("device_free", KRR_FREE_FN), ("alloc_user", ctypes.c_void_p)]
 
 
 class krr_precision_policy(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("allowed", ctypes.c_int32), ("eps", ctypes.c_double),
                 ("high_panels", ctypes.c_int32), ("fixed_prec", ctypes.c_int32),
-                ("allow_promotion", ctypes.c_int32), ("diag_fp64", ctypes.c_int32)]
+                ("allow_promotion", ctypes.c_int32), ("diag_fp64", ctypes.c_int32),
+                ("rule", ctypes.c_int32), ("no_fp8_scale", ctypes.c_int32),
+                ("fixed_map", ctypes.c_void_p), ("fixed_map_count", ctypes.c_int64)]
+
+
+class krr_kernel_desc(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("reserved", ctypes.c_int32), ("C", ctypes.c_void_p),
+                ("q", ctypes.c_int64), ("ldc", ctypes.c_int64)]
+
+
+class krr_tuning(ctypes.Structure):
+    _fields_ = [("tile", ctypes.c_int32), ("panel_group", ctypes.c_int32),
+                ("residual_split", ctypes.c_int32), ("sweep_pairs", ctypes.c_int32),
+                ("lookahead", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {f: int(getattr(self, f)) for f, _ in self._fields_}
 
 
 class krr_refine_opts(ctypes.Structure):
@@ -70,6 +93,8 @@ _SIGS = [
     ("krr_destroy", _I, [_P]),
     ("krr_set_stream", _I, [_P, _P]),
     ("krr_build_kernel", _I, [_P, _P, _I64, _I64, _I64, _D, _D, ctypes.POINTER(_P)]),
+    ("krr_build_kernel_ex", _I, [_P, _P, _I64, _I64, _I64, _D, _D,
+                                 ctypes.POINTER(krr_kernel_desc), ctypes.POINTER(_P)]),
     ("krr_kernel_release", _I, [_P]),
     ("krr_factor", _I, [_P, _P, ctypes.POINTER(krr_precision_policy), ctypes.POINTER(_P)]),
     ("krr_factor_release", _I, [_P]),
@@ -77,6 +102,8 @@ _SIGS = [
     ("krr_solve", _I, [_P, _P, _P, _I64, _I64, _P, _I64, ctypes.POINTER(krr_refine_opts),
                        ctypes.POINTER(krr_solve_info)]),
     ("krr_predict", _I, [_P, _P, _P, _I64, _I64, _P, _I64, _I64, _P, _I64]),
+    ("krr_predict_ex", _I, [_P, _P, _P, _I64, _I64, _P, _I64, _P, _I64, _I64, _P, _I64]),
+    ("krr_predict_batched", _I, [_P, ctypes.c_int32, _P, _P, _P, _P, _P, _I64, _P, _P, _P]),
     ("krr_predict_noalloc", _I, [_P, _P, _P, _I64, _I64, _P, _I64, _I64, _P, _I64]),
     ("krr_noalloc_limits", _I, [_I64, _I64, _I64, ctypes.c_int32, ctypes.POINTER(_I64),
                                 ctypes.POINTER(ctypes.c_int32)]),
@@ -86,12 +113,27 @@ _SIGS = [
                                 _P]),
     ("krr_solve_batched", _I, [_P, ctypes.c_int32, _P, _P, _I64, _P, _P, _P,
                                ctypes.POINTER(krr_refine_opts), _P]),
+    ("krr_rr_fit", _I, [_P, _P, _I64, _I64, _I64, _P, _I64, _I64, _D,
+                        ctypes.POINTER(krr_precision_policy), ctypes.POINTER(krr_refine_opts), _P,
+                        _I64, ctypes.POINTER(krr_solve_info)]),
+    ("krr_rr_predict", _I, [_P, _P, _I64, _I64, _I64, _P, _I64, _I64, _P, _I64]),
     ("krr_kernel_copy_distances", _I, [_P, _I64, _I64, _I64, _I64, _P, _I64]),
     ("krr_kernel_copy_matrix", _I, [_P, _I64, _I64, _I64, _I64, _P, _I64]),
     ("krr_factor_copy_l", _I, [_P, _I64, _I64, _I64, _I64, _P, _I64]),
     ("krr_kernel_tile_norms", _I, [_P, _P, _I64]),
     ("krr_factor_precision_map", _I, [_P, _P, _I64]),
     ("krr_debug_encode_fp8", _I, [_P, _P, _I64, _P]),
+    ("krr_set_tuning", _I, [_P, ctypes.POINTER(krr_tuning)]),
+    ("krr_get_tuning", _I, [_P, ctypes.POINTER(krr_tuning)]),
+    ("krr_autotune", _I, [_P, _P, _I64, _I64, _I64, _D, _D, _P, _I64, _I64,
+                          ctypes.POINTER(krr_precision_policy), ctypes.POINTER(krr_refine_opts),
+                          ctypes.c_char_p, ctypes.POINTER(krr_tuning), ctypes.POINTER(_D)]),
+    ("krr_tuning_key", _I, [_I, _I64, _I64, _I64, ctypes.POINTER(krr_precision_policy),
+                            ctypes.POINTER(krr_refine_opts), ctypes.c_char_p, ctypes.c_int32]),
+    ("krr_tuning_cache_store", _I, [ctypes.c_char_p, ctypes.c_char_p, ctypes.POINTER(krr_tuning),
+                                    _D]),
+    ("krr_tuning_cache_load", _I, [ctypes.c_char_p, ctypes.c_char_p, ctypes.POINTER(krr_tuning),
+                                   ctypes.POINTER(_D), ctypes.POINTER(ctypes.c_int32)]),
     ("krr_timers_enable", _I, [_P, ctypes.c_int32]),
     ("krr_timers_read", _I, [_P, _P, _P, ctypes.c_int32]),
     ("krr_stage_name", ctypes.c_char_p, [ctypes.c_int32]),
@@ -222,10 +264,21 @@ class Policy:
     fixed_prec: int = KRR_PREC_FP16
     allow_promotion: int = 1
     diag_fp64: int = 1
+    rule: int = KRR_RULE_OPERAND
+    no_fp8_scale: int = 0
+    fixed_map: object = None  # numpy uint8 array (FIXED_MAP)
 
     def c(self):
-        return krr_precision_policy(self.mode, self.allowed, self.eps, self.high_panels,
-                                    self.fixed_prec, self.allow_promotion, self.diag_fp64)
+        pol = krr_precision_policy(self.mode, self.allowed, self.eps, self.high_panels,
+                                   self.fixed_prec, self.allow_promotion, self.diag_fp64,
+                                   self.rule, self.no_fp8_scale, None, 0)
+        if self.fixed_map is not None:
+            import numpy as np
+            fm = np.ascontiguousarray(self.fixed_map, dtype=np.uint8)
+            pol.fixed_map = fm.ctypes.data
+            pol.fixed_map_count = fm.size
+            pol._keep = fm  # the array outlives the call through the struct
+        return pol
 
 
 def plain_fp32_policy() -> Policy:
@@ -244,13 +297,23 @@ class Refine:
 
 
 def krr_create(device: int = 0, stream=None, tile: int = 512, verbose: int = 0,
-               workspace_limit: int = 0) -> Context:
+               workspace_limit: int = 0, allocator=None) -> Context:
+    """allocator: optional (alloc(bytes) -> int device pointer, free(ptr, bytes)) pair of
+    Python callables the library uses instead of hipMalloc/hipFree."""
     lib = load()
     h = ctypes.c_void_p()
     opts = krr_options(tile, verbose, workspace_limit)
+    keep = None
+    if allocator is not None:
+        alloc, free = allocator
+        keep = (KRR_ALLOC_FN(lambda b, u: alloc(int(b)) or None),
+                KRR_FREE_FN(lambda p, b, u: free(int(p), int(b))))
+        opts.device_alloc, opts.device_free = keep
     _check(lib.krr_create(ctypes.byref(h), device, _stream_handle(stream), ctypes.byref(opts)),
            "krr_create")
-    return Context(h, device)
+    c = Context(h, device)
+    c._alloc_fns = keep  # the callbacks live as long as the context
+    return c
 
 
 def krr_set_stream(ctx: Context, stream=None):
@@ -268,6 +331,53 @@ def padded_genotypes(G):
     buf = torch.zeros((n, pitch), dtype=torch.int8, device=G.device)
     buf[:, :m] = G
     return buf[:, :m]
+
+
+def krr_set_tuning(ctx: Context, tile=512, panel_group=0, residual_split=0, sweep_pairs=-1,
+                   lookahead=-1):
+    t = krr_tuning(tile, panel_group, residual_split, sweep_pairs, lookahead)
+    _check(load().krr_set_tuning(ctx.handle, ctypes.byref(t)), "krr_set_tuning")
+
+
+def krr_get_tuning(ctx: Context) -> dict:
+    t = krr_tuning()
+    _check(load().krr_get_tuning(ctx.handle, ctypes.byref(t)), "krr_get_tuning")
+    return t.as_dict()
+
+
+def krr_autotune(ctx: Context, G, Y, gamma: float, lam: float, policy: Policy | None = None,
+                 refine: Refine | None = None, cache_path: str | None = None):
+    """Search the context's schedule choices on this problem (see include/krr.h);
+    returns (tuning dict, best step time in ms)."""
+    G = padded_genotypes(G)
+    n, m = G.shape
+    Yc = _colmajor(Y, n)
+    t = krr_tuning()
+    ms = ctypes.c_double()
+    pol = (policy or Policy()).c()
+    ref = (refine or Refine()).c()
+    _check(load().krr_autotune(ctx.handle, _ptr(G), n, m, G.stride(0), float(gamma), float(lam),
+                               _ptr(Yc), Yc.shape[1], n, ctypes.byref(pol), ctypes.byref(ref),
+                               cache_path.encode() if cache_path else None, ctypes.byref(t),
+                               ctypes.byref(ms)), "krr_autotune")
+    return t.as_dict(), float(ms.value)
+
+
+def krr_tuning_cache_store(path: str, key: str, tuning: dict, ms: float):
+    t = krr_tuning(*(int(tuning[f]) for f, _ in krr_tuning._fields_))
+    _check(load().krr_tuning_cache_store(path.encode(), key.encode(), ctypes.byref(t), ms),
+           "krr_tuning_cache_store")
+
+
+def krr_tuning_cache_load(path: str, key: str):
+    """(tuning dict, ms), or None when the key is not in the file."""
+    t = krr_tuning()
+    ms = ctypes.c_double()
+    found = ctypes.c_int32()
+    _check(load().krr_tuning_cache_load(path.encode(), key.encode(), ctypes.byref(t),
+                                        ctypes.byref(ms), ctypes.byref(found)),
+           "krr_tuning_cache_load")
+    return (t.as_dict(), float(ms.value)) if found.value else None
 
 
 def krr_timers_enable(ctx: Context, enable: bool = True):
@@ -293,6 +403,31 @@ def krr_build_kernel(ctx: Context, G, gamma: float, lam: float) -> Kernel:
     _check(load().krr_build_kernel(ctx.handle, _ptr(G), n, m, G.stride(0), float(gamma),
                                    float(lam), ctypes.byref(h)), "krr_build_kernel")
     return Kernel(h, ctx, G, n, m, gamma, lam)
+
+
+def krr_build_kernel_ex(ctx: Context, G, gamma: float, lam: float, kind: int = KRR_KERNEL_GAUSSIAN,
+                        C=None) -> Kernel:
+    """Build with a kernel type of Algorithm 5 (KRR_KERNEL_GAUSSIAN / KRR_KERNEL_IBS) and,
+    for the Gaussian kernel, optional confounders C (n x q float64 on the GPU)."""
+    import torch
+    G = padded_genotypes(G)
+    n, m = G.shape
+    desc = krr_kernel_desc(kind, 0, None, 0, 0)
+    Cd = None
+    if C is not None:
+        Cd = C.to(torch.float64)
+        if Cd.dim() == 1:
+            Cd = Cd[:, None]
+        Cd = Cd.contiguous()
+        assert Cd.shape[0] == n
+        desc.C, desc.q, desc.ldc = Cd.data_ptr(), Cd.shape[1], Cd.shape[1]
+    h = ctypes.c_void_p()
+    _check(load().krr_build_kernel_ex(ctx.handle, _ptr(G), n, m, G.stride(0), float(gamma),
+                                      float(lam), ctypes.byref(desc), ctypes.byref(h)),
+           "krr_build_kernel_ex")
+    K = Kernel(h, ctx, G, n, m, gamma, lam)
+    K.kind, K.q = kind, (0 if Cd is None else Cd.shape[1])
+    return K
 
 
 def krr_factor(ctx: Context, K: Kernel, policy: Policy | None = None) -> Factor:
@@ -401,6 +536,49 @@ def krr_predict(ctx: Context, K: Kernel, T, X):
     return P
 
 
+def krr_predict_ex(ctx: Context, K: Kernel, T, X, Ct=None):
+    """P = K_test X for any kernel of krr_build_kernel_ex; Ct: the test rows' confounders."""
+    import torch
+    T = padded_genotypes(T)
+    nt, m = T.shape
+    assert m == K.m
+    Xc = _colmajor(X, K.n)
+    r = Xc.shape[1]
+    P = torch.empty((r, nt), dtype=torch.float64, device=Xc.device).t()
+    Ctd, ldct = None, 0
+    if Ct is not None:
+        Ctd = Ct.to(torch.float64)
+        if Ctd.dim() == 1:
+            Ctd = Ctd[:, None]
+        Ctd = Ctd.contiguous()
+        ldct = Ctd.shape[1]
+    _check(load().krr_predict_ex(ctx.handle, K.handle, _ptr(T), nt, T.stride(0),
+                                 _ptr(Ctd) if Ctd is not None else None, ldct, _ptr(Xc), r, K.n,
+                                 _ptr(P), nt), "krr_predict_ex")
+    return P
+
+
+def krr_predict_batched(ctx: Context, Ks, Ts, Xs) -> list:
+    """[P_b] = [K_test,b X_b] for every instance (test genotypes Ts[b], weights Xs[b])."""
+    import torch
+    B = len(Ks)
+    Ts = [padded_genotypes(T) for T in Ts]
+    Xc = [_colmajor(X, K.n) for X, K in zip(Xs, Ks)]
+    r = Xc[0].shape[1]
+    assert all(X.shape[1] == r for X in Xc) and len(Ts) == B
+    Ps = [torch.empty((r, T.shape[0]), dtype=torch.float64, device=T.device).t() for T in Ts]
+    _check(load().krr_predict_batched(
+        ctx.handle, B, _host_array(ctypes.c_void_p, [K.handle.value for K in Ks]),
+        _host_array(ctypes.c_void_p, [_ptr(T) for T in Ts]),
+        _host_array(ctypes.c_int64, [T.shape[0] for T in Ts]),
+        _host_array(ctypes.c_int64, [T.stride(0) for T in Ts]),
+        _host_array(ctypes.c_void_p, [_ptr(X) for X in Xc]), r,
+        _host_array(ctypes.c_int64, [K.n for K in Ks]),
+        _host_array(ctypes.c_void_p, [_ptr(P) for P in Ps]),
+        _host_array(ctypes.c_int64, [T.shape[0] for T in Ts])), "krr_predict_batched")
+    return Ps
+
+
 def krr_predict_noalloc(ctx: Context, K: Kernel, T, X, P=None):
     """krr_predict through the no-allocation entry point: the library allocates
     nothing; P (n_test x r, float64, column-major) may be passed in by the caller."""
@@ -433,6 +611,40 @@ def krr_context_memory(ctx: Context):
     _check(load().krr_context_memory(ctx.handle, ctypes.byref(a), ctypes.byref(c)),
            "krr_context_memory")
     return int(a.value), int(c.value)
+
+
+def krr_rr_fit(ctx: Context, G, Y, lam: float, policy: Policy | None = None,
+               refine: Refine | None = None, check: bool = True):
+    """Ridge Regression (Eq. 2): beta = (X^T X + lambda I)^-1 X^T Y with X = G (n x m int8
+    on the GPU); returns (beta (m x r float64), info, status)."""
+    import torch
+    G = padded_genotypes(G)
+    n, m = G.shape
+    Yc = _colmajor(Y, n)
+    r = Yc.shape[1]
+    beta = torch.empty((r, m), dtype=torch.float64, device=Yc.device).t()
+    info = krr_solve_info()
+    pol = (policy or Policy()).c()
+    ref = (refine or Refine()).c()
+    st = load().krr_rr_fit(ctx.handle, _ptr(G), n, m, G.stride(0), _ptr(Yc), r, n, float(lam),
+                           ctypes.byref(pol), ctypes.byref(ref), _ptr(beta), m,
+                           ctypes.byref(info))
+    if check:
+        _check(st, "krr_rr_fit")
+    return beta, info, st
+
+
+def krr_rr_predict(ctx: Context, T, beta):
+    """P = T beta for test genotypes T (n_test x m int8 on the GPU)."""
+    import torch
+    T = padded_genotypes(T)
+    nt, m = T.shape
+    B = _colmajor(beta, m)
+    r = B.shape[1]
+    P = torch.empty((r, nt), dtype=torch.float64, device=B.device).t()
+    _check(load().krr_rr_predict(ctx.handle, _ptr(T), nt, m, T.stride(0), _ptr(B), r, m, _ptr(P),
+                                 nt), "krr_rr_predict")
+    return P
 
 
 def krr_debug_encode_fp8(ctx: Context, x):

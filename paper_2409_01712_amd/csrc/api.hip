@@ -10,6 +10,7 @@
 #include <algorithm>
 #include <map>
 #include <mutex>
+#include <string>
 #include <unordered_map>
 #include <vector>
 
@@ -40,6 +41,8 @@ struct krr_context_s {
   // live kernel/factor handles; krr_destroy defers the free until they are released
   int64_t live = 0;
   bool destroy_pending = false;
+  // schedule choices (krr_set_tuning / krr_autotune); 0 / -1 fields: the defaults
+  krr_tuning tune{};
   // second stream and events for the factorization's lookahead
   hipStream_t aux = nullptr, side = nullptr, fmain = nullptr;
   std::vector<hipEvent_t> sched_ev;  // ordering events of the factorization schedule
@@ -50,6 +53,21 @@ struct krr_kernel_s {
   const int8_t *G = nullptr;
   int64_t n = 0, m = 0, ldg = 0;
   double gamma = 0, lambda = 0;
+  int kind = KRR_KERNEL_GAUSSIAN;
+  // IBS: the thermometer-encoded genotypes (n x ldh, mh = ldh columns), owned
+  int8_t *H = nullptr;
+  int64_t ldh = 0;
+  // confounders: their FP64 copy (n x q) and the factors exp(-gamma dc) (packed tiles)
+  double *Cc = nullptr;
+  double *Ec = nullptr;
+  int64_t q = 0;
+  // what the Gram reads: G, or H for the IBS kernel
+  const int8_t *gram_src() const { return H ? H : G; }
+  int64_t gram_m() const { return H ? ldh : m; }
+  int64_t gram_ld() const { return H ? ldh : ldg; }
+  int vmode() const {
+    return kind == KRR_KERNEL_IBS ? VAL_TABLE : kind == KRR_KERNEL_LINEAR ? VAL_LINEAR : VAL_EXP;
+  }
   TileLayout L;
   int32_t *D = nullptr;  // exact distances, packed lower tiles
   float *A = nullptr;    // K + lambda I, FP32, packed lower tiles (null once consumed)
@@ -100,8 +118,20 @@ namespace {
 // before releasing memory), so any later call may reuse a cached block.
 constexpr size_t KRR_CACHE_MAX = (size_t)64 << 30;  // larger caches return blocks to the runtime
 
+// Device memory from the caller's allocator when the context has one.
+void raw_free(krr_context ctx, void *p, size_t size) {
+  if (ctx->opts.device_free) ctx->opts.device_free(p, size, ctx->opts.alloc_user);
+  else (void)hipFree(p);
+}
+
+hipError_t raw_alloc(krr_context ctx, void **p, size_t bytes) {
+  if (!ctx->opts.device_alloc) return hipMalloc(p, bytes);
+  *p = ctx->opts.device_alloc(bytes, ctx->opts.alloc_user);
+  return *p ? hipSuccess : hipErrorOutOfMemory;
+}
+
 void cache_flush(krr_context ctx) {
-  for (auto &kv : ctx->cache) (void)hipFree(kv.second);
+  for (auto &kv : ctx->cache) raw_free(ctx, kv.second, kv.first);
   ctx->cache.clear();
   ctx->cached = 0;
 }
@@ -120,11 +150,11 @@ krr_status dalloc(krr_context ctx, void **p, size_t bytes) {
     ctx->cached -= size;
     ctx->cache.erase(it);
   } else {
-    hipError_t e = hipMalloc(p, bytes);
+    hipError_t e = raw_alloc(ctx, p, bytes);
     if (e == hipErrorOutOfMemory && !ctx->cache.empty()) {
       (void)hipGetLastError();
       cache_flush(ctx);
-      e = hipMalloc(p, bytes);
+      e = raw_alloc(ctx, p, bytes);
     }
     if (e != hipSuccess) {
       (void)hipGetLastError();
@@ -145,10 +175,7 @@ krr_status dalloc_t(krr_context ctx, T **p, int64_t count) {
 void dfree(krr_context ctx, void *p, size_t /*bytes*/) {
   if (!p) return;
   auto it = ctx->live_sizes.find(p);
-  if (it == ctx->live_sizes.end()) {  // not from dalloc: nothing to account
-    (void)hipFree(p);
-    return;
-  }
+  if (it == ctx->live_sizes.end()) return;  // not from dalloc: not ours to free
   const size_t size = it->second;
   ctx->live_sizes.erase(it);
   ctx->allocated -= (int64_t)size;
@@ -156,7 +183,7 @@ void dfree(krr_context ctx, void *p, size_t /*bytes*/) {
     ctx->cache.emplace(size, p);
     ctx->cached += size;
   } else {
-    (void)hipFree(p);
+    raw_free(ctx, p, size);
   }
 }
 
@@ -341,6 +368,7 @@ krr_status krr_create(krr_context *out, int device, void *stream, const krr_opti
   if (o.tile == 0) o.tile = 512;
   if (o.tile != 256 && o.tile != 512) return KRR_ERROR_INVALID_VALUE;
   if (o.workspace_limit < 0) return KRR_ERROR_INVALID_VALUE;
+  if (!o.device_alloc != !o.device_free) return KRR_ERROR_INVALID_VALUE;
   int count = 0;
   if (hipGetDeviceCount(&count) != hipSuccess) {
     (void)hipGetLastError();
@@ -353,6 +381,7 @@ krr_status krr_create(krr_context *out, int device, void *stream, const krr_opti
   c->device = device;
   c->stream = (hipStream_t)stream;
   c->opts = o;
+  c->tune = krr_tuning{o.tile, 0, 0, -1, -1};
   *out = c;
   return KRR_SUCCESS;
 }
@@ -409,6 +438,9 @@ static void kernel_free(krr_kernel K) {
   dfree(c, K->A, (size_t)L.elems() * 4);
   dfree(c, K->nrm, (size_t)L.np * 4);
   dfree(c, K->etab, (size_t)K->etab_len * 8);
+  dfree(c, K->H, (size_t)K->n * K->ldh);
+  dfree(c, K->Cc, (size_t)K->n * K->q * 8);
+  dfree(c, K->Ec, (size_t)L.elems() * 8);
   dfree(c, K->tnorm, (size_t)L.ntiles() * 8);
   const int sb = L.nb / 256;
   dfree(c, K->tnorm_part, (size_t)L.ntiles() * sb * sb * 8);
@@ -459,24 +491,64 @@ static krr_status kernel_new(krr_context ctx, const int8_t *G, int64_t n, int64_
 
 krr_status krr_build_kernel(krr_context ctx, const int8_t *G, int64_t n, int64_t m, int64_t ldg,
                             double gamma, double lambda, krr_kernel *out) {
+  return krr_build_kernel_ex(ctx, G, n, m, ldg, gamma, lambda, nullptr, out);
+}
+
+krr_status krr_build_kernel_ex(krr_context ctx, const int8_t *G, int64_t n, int64_t m, int64_t ldg,
+                               double gamma, double lambda, const krr_kernel_desc *desc,
+                               krr_kernel *out) {
   if (!out) return KRR_ERROR_INVALID_VALUE;
   *out = nullptr;
   if (!ctx || ctx->destroy_pending) return KRR_ERROR_INVALID_VALUE;
   CHK(build_args(G, n, m, ldg, gamma, lambda));
+  krr_kernel_desc dsc{};
+  if (desc) dsc = *desc;
+  if (dsc.kind != KRR_KERNEL_GAUSSIAN && dsc.kind != KRR_KERNEL_IBS &&
+      dsc.kind != KRR_KERNEL_LINEAR)
+    return KRR_ERROR_INVALID_VALUE;
+  if (dsc.C) {
+    if (dsc.kind != KRR_KERNEL_GAUSSIAN || dsc.q <= 0 || dsc.ldc < dsc.q) return KRR_ERROR_INVALID_VALUE;
+    if (dsc.q > KRR_CONF_QMAX) return KRR_ERROR_NOT_SUPPORTED;
+  }
   HIPCHK(hipSetDevice(ctx->device));
   hipStream_t s = ctx->stream;
   krr_kernel K = nullptr;
   CHK(kernel_new(ctx, G, n, m, ldg, gamma, lambda, &K));
+  K->kind = dsc.kind;
   const TileLayout &L = K->L;
   const int sb = L.nb / 256;
   krr_status st = KRR_SUCCESS;
   int32_t *flag = nullptr;
   do {
     if ((st = dalloc_t(ctx, &flag, 1)) != KRR_SUCCESS) break;
+    if (K->kind == KRR_KERNEL_IBS) {
+      // encoded rows: [g >= 1] then [g >= 2], each half padded to 16 bytes; the
+      // squared distance of two encoded rows is sum_k |g_ik - g_jk| <= 2m
+      K->ldh = 2 * ((m + 15) / 16 * 16);
+      if ((st = dalloc_t(ctx, &K->H, n * K->ldh)) != KRR_SUCCESS) break;
+      dfree(ctx, K->etab, (size_t)K->etab_len * 8);
+      K->etab = nullptr;
+      K->etab_len = 2 * m + 1;
+      if ((st = dalloc_t(ctx, &K->etab, K->etab_len)) != KRR_SUCCESS) break;
+    }
+    if (dsc.C) {
+      K->q = dsc.q;
+      if ((st = dalloc_t(ctx, &K->Cc, n * dsc.q)) != KRR_SUCCESS) break;
+      if ((st = dalloc_t(ctx, &K->Ec, L.elems())) != KRR_SUCCESS) break;
+      if (hipMemcpy2DAsync(K->Cc, dsc.q * 8, dsc.C, dsc.ldc * 8, dsc.q * 8, n,
+                           hipMemcpyDeviceToDevice, s) != hipSuccess) {
+        st = KRR_ERROR_HIP;
+        break;
+      }
+    }
     launch_fill_i32(flag, 1, 0, s);
     {
       Stage t(ctx, KRR_STAGE_ROW_NORMS);
-      launch_row_norms(G, n, L.np, m, ldg, K->nrm, flag, s);
+      launch_row_norms(G, n, L.np, m, ldg, K->nrm, flag, s);  // and the genotype check
+      if (K->H) {
+        launch_ibs_encode(G, n, m, ldg, K->H, K->ldh, s);
+        launch_row_norms(K->H, n, L.np, K->ldh, K->ldh, K->nrm, flag, s);
+      }
     }
     int32_t hflag = 0;
     if (hipMemcpyAsync(&hflag, flag, 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
@@ -489,11 +561,13 @@ krr_status krr_build_kernel(krr_context ctx, const int8_t *G, int64_t n, int64_t
       st = KRR_ERROR_BAD_GENOTYPE;
       break;
     }
-    launch_exp_table(K->etab, K->etab_len, gamma, s);
+    if (K->kind == KRR_KERNEL_IBS) launch_ibs_table(K->etab, K->etab_len, m, s);
+    else if (K->kind == KRR_KERNEL_GAUSSIAN) launch_exp_table(K->etab, K->etab_len, gamma, s);
+    if (K->Ec) launch_conf_factor(K->Cc, n, K->q, K->q, gamma, L, K->Ec, s);
     {
       Stage t(ctx, KRR_STAGE_GRAM);
-      launch_gram_tiles(G, m, ldg, K->nrm, K->etab, K->etab_len, lambda, L, K->D, K->A,
-                        K->tnorm_part, s);
+      launch_gram_tiles(K->gram_src(), K->gram_m(), K->gram_ld(), K->nrm, K->etab, K->etab_len,
+                        lambda, L, K->D, K->A, K->tnorm_part, K->vmode(), K->Ec, s);
     }
     launch_tile_norms(K->tnorm_part, sb * sb, L.ntiles(), K->tnorm, s);
     st = launch_ok();
@@ -735,9 +809,13 @@ static krr_status resolve_policy(const krr_precision_policy *policy, krr_precisi
     p.allow_promotion = 1;
     p.diag_fp64 = 1;
   }
-  if (p.mode < KRR_POLICY_FP32 || p.mode > KRR_POLICY_FIXED) return KRR_ERROR_INVALID_VALUE;
+  if (p.mode < KRR_POLICY_FP32 || p.mode > KRR_POLICY_FIXED_MAP) return KRR_ERROR_INVALID_VALUE;
   if (p.mode == KRR_POLICY_ADAPTIVE && !(p.eps > 0)) return KRR_ERROR_INVALID_VALUE;
+  if (p.mode == KRR_POLICY_ADAPTIVE && (p.rule < KRR_RULE_OPERAND || p.rule > KRR_RULE_BOTH))
+    return KRR_ERROR_INVALID_VALUE;
   if (p.mode == KRR_POLICY_FIXED && p.fixed_prec != KRR_PREC_FP16 && p.fixed_prec != KRR_PREC_FP8)
+    return KRR_ERROR_INVALID_VALUE;
+  if (p.mode == KRR_POLICY_FIXED_MAP && (!p.fixed_map || p.fixed_map_count <= 0))
     return KRR_ERROR_INVALID_VALUE;
   if (p.high_panels < 0) return KRR_ERROR_INVALID_VALUE;
   fp.allow16 = fp.allow8 = 0;
@@ -747,30 +825,34 @@ static krr_status resolve_policy(const krr_precision_policy *policy, krr_precisi
   } else if (p.mode == KRR_POLICY_FIXED) {
     fp.allow16 = p.fixed_prec == KRR_PREC_FP16;
     fp.allow8 = p.fixed_prec == KRR_PREC_FP8;
+  } else if (p.mode == KRR_POLICY_FIXED_MAP) {
+    for (int64_t e = 0; e < p.fixed_map_count; ++e) {
+      fp.allow16 |= p.fixed_map[e] == KRR_PREC_FP16;
+      fp.allow8 |= p.fixed_map[e] == KRR_PREC_FP8;
+    }
   }
   fp.mode = p.mode;
   fp.diag64 = p.diag_fp64 != 0;
   return KRR_SUCCESS;
 }
 
-// After a breakdown: drop the lowest precision in use, then fall back to
-// FP64 pivots.  False when nothing is left to promote.
-static bool promote(FactorPlan &fp, krr_precision_policy &p) {
-  if (fp.allow8) {
-    fp.allow8 = 0;
-    if (fp.mode == KRR_POLICY_FIXED) {
-      p.fixed_prec = KRR_PREC_FP16;
-      fp.allow16 = 1;
+// After a breakdown in tile row `brow`: every panel before it may use one
+// precision level less than before (cap: the lowest precision a panel may
+// use); when all of them are FP32 already, FP64 pivots.  False when nothing
+// is left to promote.
+static bool promote_panels(std::vector<uint8_t> &cap, int brow, FactorPlan &fp) {
+  bool changed = false;
+  for (int k = 0; k < brow && k < (int)cap.size(); ++k)
+    if (cap[k] > KRR_PREC_FP32) {
+      cap[k]--;
+      changed = true;
     }
-  } else if (fp.allow16) {
-    fp.allow16 = 0;
-    fp.mode = KRR_POLICY_FP32;
-  } else if (!fp.diag64) {
+  if (changed) return true;
+  if (!fp.diag64) {
     fp.diag64 = true;
-  } else {
-    return false;
+    return true;
   }
-  return true;
+  return false;
 }
 
 // Panels per grouped trailing update (KRR_GROUP overrides): 8 when updates
@@ -782,6 +864,15 @@ static bool promote(FactorPlan &fp, krr_precision_policy &p) {
 // 215 ms with 8 against 218 with 4, FP32 272 ms with 4 against 279 with 8).
 static int panel_group(const FactorPlan &fp) { return (fp.allow8 || fp.allow16) ? 8 : 4; }
 
+// The group size in force: KRR_GROUP (debugging), else the context's tuning,
+// else the default above.
+static int group_size(krr_context ctx, const FactorPlan &fp) {
+  const char *g_env = getenv("KRR_GROUP");
+  const int g = g_env ? atoi(g_env)
+                      : (ctx->tune.panel_group > 0 ? ctx->tune.panel_group : panel_group(fp));
+  return std::max(1, std::min(KRR_MAX_GROUP, g));
+}
+
 // Enqueue one factorization attempt of F (its matrix already in F->Lst):
 // clears the breakdown flag, the counters and the precision map, runs the
 // tile Cholesky on s (one stream) or on the context's three streams joined
@@ -789,7 +880,8 @@ static int panel_group(const FactorPlan &fp) { return (fp.allow8 || fp.allow16) 
 // here waits for the device.
 static krr_status factor_enqueue(krr_context ctx, krr_kernel K, krr_factorization F,
                                  const krr_precision_policy &p, const FactorPlan &fp,
-                                 FactorWork &w, uint8_t *dmap, int64_t mapsz, bool lookahead,
+                                 FactorWork &w, uint8_t *dmap, int64_t mapsz,
+                                 const uint8_t *fmap, const uint8_t *pcap, bool lookahead,
                                  int g, hipStream_t s) {
   const TileLayout &L = F->L;
   launch_fill_i32(w.flag, 1, 0, s);
@@ -801,8 +893,13 @@ static krr_status factor_enqueue(krr_context ctx, krr_kernel K, krr_factorizatio
   up.allow8 = fp.allow8;
   up.high_panels = p.high_panels;
   up.fixed_prec = p.fixed_prec;
+  up.rule = p.rule;
   up.thr = p.eps * K->norm_a / L.nt;
+  up.fmap = fmap;
+  up.pcap = pcap;
+  up.tnorm = K->tnorm;
   const bool need16 = fp.allow16 != 0, need8 = fp.allow8 != 0;
+  const bool scale8 = p.no_fp8_scale == 0;
   const int64_t te = L.tile_elems();
   // Panels are produced in groups of g block columns.  Inside a group
   // each panel updates the group's later columns right away; everything
@@ -839,7 +936,7 @@ static krr_status factor_enqueue(krr_context ctx, krr_kernel K, krr_factorizatio
   };
   auto convert = [&](int k, hipStream_t st) {
     Stage t(ctx, KRR_STAGE_CONVERT, st);
-    launch_convert_panel(F->Lst, k, L, w, slot(k), need16, need8, st);
+    launch_convert_panel(F->Lst, k, L, w, scale8, slot(k), need16, need8, st);
   };
   // panels G0 .. G0+npan-1 onto the tiles of columns jlo .. jhi (which: UPD_*)
   auto update = [&](int G0, int npan, int jlo, int jhi, int which, hipStream_t st) {
@@ -1001,9 +1098,8 @@ krr_status krr_factor(krr_context ctx, krr_kernel K, const krr_precision_policy 
   const TileLayout &L = K->L;
   CHK(kernel_norm(K));
   const char *la_env = getenv("KRR_NO_LOOKAHEAD");
-  const bool lookahead = !(la_env && atoi(la_env) != 0);
-  const char *g_env = getenv("KRR_GROUP");
-  const int g = std::max(1, std::min(KRR_MAX_GROUP, g_env ? atoi(g_env) : panel_group(fp)));
+  const bool lookahead = la_env ? atoi(la_env) == 0 : ctx->tune.lookahead != 0;
+  const int g = group_size(ctx, fp);
   if (lookahead) CHK(context_aux(ctx));
 
   krr_factorization F = new krr_factor_s();
@@ -1016,26 +1112,48 @@ krr_status krr_factor(krr_context ctx, krr_kernel K, const krr_precision_policy 
   F->info.breakdown_col = -1;
   FactorWork w;
   krr_status st = KRR_SUCCESS;
-  uint8_t *dmap = nullptr;
+  uint8_t *dmap = nullptr, *fmap = nullptr, *pcap = nullptr;
   // precision of every (panel, tile) update; copied to the host for the
   // diagnostics accessor (NT^2 (NT+1) / 2 bytes: 30 MB at NT = 391)
   const int64_t mapsz = (int64_t)L.nt * L.ntiles();
+  if (p.mode == KRR_POLICY_FIXED_MAP && p.fixed_map_count != mapsz) {
+    delete F;
+    return KRR_ERROR_INVALID_VALUE;
+  }
+  // lowest precision each panel may use; lowered panel by panel on breakdown
+  std::vector<uint8_t> cap(L.nt, (uint8_t)KRR_PREC_FP8);
   do {
     if (K->A) {  // consume the build's matrix in place
       F->Lst = K->A;
       K->A = nullptr;
     } else {
       if ((st = dalloc_t(ctx, &F->Lst, L.elems())) != KRR_SUCCESS) break;
-      launch_expand_tiles(K->D, K->etab, K->etab_len, K->lambda, L, F->Lst, s);
+      launch_expand_tiles(K->D, K->etab, K->etab_len, K->lambda, K->vmode(), K->Ec, L,
+                          F->Lst, s);
     }
     if ((st = dalloc_t(ctx, &F->Linv, (int64_t)L.nt * L.tile_elems())) != KRR_SUCCESS) break;
     if ((st = factor_work_alloc(ctx, w, L, fp.allow16 || p.allow_promotion, fp.allow8,
                                 std::min(2 * g, 2 * KRR_MAX_GROUP))) != KRR_SUCCESS)
       break;
     if ((st = dalloc_t(ctx, &dmap, mapsz)) != KRR_SUCCESS) break;
+    if ((st = dalloc_t(ctx, &pcap, L.nt)) != KRR_SUCCESS) break;
+    if (p.mode == KRR_POLICY_FIXED_MAP) {
+      if ((st = dalloc_t(ctx, &fmap, mapsz)) != KRR_SUCCESS) break;
+      if (hipMemcpyAsync(fmap, p.fixed_map, mapsz, hipMemcpyHostToDevice, s) != hipSuccess) {
+        st = KRR_ERROR_HIP;
+        break;
+      }
+    }
     for (int attempt = 0;; ++attempt) {
-      if (attempt > 0) launch_expand_tiles(K->D, K->etab, K->etab_len, K->lambda, L, F->Lst, s);
-      if ((st = factor_enqueue(ctx, K, F, p, fp, w, dmap, mapsz, lookahead, g, s)) != KRR_SUCCESS)
+      if (attempt > 0) launch_expand_tiles(K->D, K->etab, K->etab_len, K->lambda, K->vmode(), K->Ec, L,
+                          F->Lst, s);
+      // the caps (host memory, pageable): the copy completes before the call returns
+      if (hipMemcpyAsync(pcap, cap.data(), L.nt, hipMemcpyHostToDevice, s) != hipSuccess) {
+        st = KRR_ERROR_HIP;
+        break;
+      }
+      if ((st = factor_enqueue(ctx, K, F, p, fp, w, dmap, mapsz, fmap, pcap, lookahead, g, s)) !=
+          KRR_SUCCESS)
         break;
       if ((st = launch_ok()) != KRR_SUCCESS) break;
       int32_t hflag = 0;
@@ -1053,7 +1171,7 @@ krr_status krr_factor(krr_context ctx, krr_kernel K, const krr_precision_policy 
         st = KRR_ERROR_NOT_POSITIVE_DEFINITE;
         break;
       }
-      if (!promote(fp, p)) {
+      if (!promote_panels(cap, (int)((hflag - 1) / L.nb), fp)) {
         st = KRR_ERROR_NOT_POSITIVE_DEFINITE;
         break;
       }
@@ -1069,6 +1187,8 @@ krr_status krr_factor(krr_context ctx, krr_kernel K, const krr_precision_policy 
   // let it finish before its memory goes back to the cache
   if (st != KRR_SUCCESS) (void)hipDeviceSynchronize();
   if (dmap) dfree(ctx, dmap, mapsz);
+  if (fmap) dfree(ctx, fmap, mapsz);
+  if (pcap) dfree(ctx, pcap, L.nt);
   factor_work_free(ctx, w, L);
   if (st != KRR_SUCCESS) {
     dfree(ctx, F->Lst, L.elems() * 4);
@@ -1106,6 +1226,7 @@ krr_status krr_factor_batched(krr_context ctx, int32_t batch, const krr_kernel *
   krr_precision_policy p;
   FactorPlan fp;
   CHK(resolve_policy(policy, p, fp));
+  if (p.mode == KRR_POLICY_FIXED_MAP) return KRR_ERROR_NOT_SUPPORTED;  // one map per instance
   HIPCHK(hipSetDevice(ctx->device));
   hipStream_t s = ctx->stream;
   {  // Frobenius norms of kernels not built by the batched build, in one synchronization
@@ -1124,8 +1245,7 @@ krr_status krr_factor_batched(krr_context ctx, int32_t batch, const krr_kernel *
         if (K[b]->norm_a < 0) norm_from_tiles(K[b]);
     }
   }
-  const char *g_env = getenv("KRR_GROUP");
-  const int g = std::max(1, std::min(KRR_MAX_GROUP, g_env ? atoi(g_env) : panel_group(fp)));
+  const int g = group_size(ctx, fp);
   const bool need16 = fp.allow16 || p.allow_promotion;
   std::vector<FactorWork> W(batch);
   std::vector<krr_factorization> Fs(batch, nullptr);
@@ -1154,7 +1274,8 @@ krr_status krr_factor_batched(krr_context ctx, int32_t batch, const krr_kernel *
         K[b]->A = nullptr;
       } else {
         if ((st = dalloc_t(ctx, &F->Lst, L.elems())) != KRR_SUCCESS) break;
-        launch_expand_tiles(K[b]->D, K[b]->etab, K[b]->etab_len, K[b]->lambda, L, F->Lst, s);
+        launch_expand_tiles(K[b]->D, K[b]->etab, K[b]->etab_len, K[b]->lambda, K[b]->vmode(),
+                            K[b]->Ec, L, F->Lst, s);
       }
       if ((st = dalloc_t(ctx, &F->Linv, (int64_t)L.nt * L.tile_elems())) != KRR_SUCCESS) break;
       mapsz[b] = (int64_t)L.nt * L.ntiles();
@@ -1188,6 +1309,7 @@ krr_status krr_factor_batched(krr_context ctx, int32_t batch, const krr_kernel *
       j.pmap = dmap[b];
       j.ntiles = L.ntiles();
       j.thr = p.eps * K[b]->norm_a / L.nt;
+      j.tnorm = K[b]->tnorm;
       j.nt = L.nt;
     }
     if (st != KRR_SUCCESS) break;
@@ -1203,11 +1325,12 @@ krr_status krr_factor_batched(krr_context ctx, int32_t batch, const krr_kernel *
     up.allow8 = fp.allow8;
     up.high_panels = p.high_panels;
     up.fixed_prec = p.fixed_prec;
-    up.thr = 0;  // per instance, from the table
+    up.rule = p.rule;
+    up.thr = 0;  // per instance, from the table (with the tile norms)
     {
       Stage t(ctx, KRR_STAGE_POTRF, s);
       launch_factor_lockstep(djobs, nts.data(), batch, ctx->opts.tile, g, up, fp.diag64,
-                             fp.allow16 != 0, fp.allow8 != 0, s);
+                             fp.allow16 != 0, fp.allow8 != 0, p.no_fp8_scale == 0, s);
     }
     for (int b = 0; b < batch; ++b) {
       launch_count_pmap(dmap[b], mapsz[b], W[b].counts, s);
@@ -1312,6 +1435,7 @@ struct SolveBufs {
   float *Bf = nullptr, *Zf = nullptr, *Xf = nullptr;
   const float *C = nullptr;  // coupling tiles of the paired sweeps, or null
   double *cw = nullptr;      // workspace of the column reductions
+  int z = 1;                 // column ranges of the residual (Pr holds z np r)
 };
 
 // The coupling tiles of the paired sweeps, formed on the first solve with a
@@ -1322,7 +1446,8 @@ static krr_status sweep_coupling(krr_context ctx, krr_factorization F, Scoped &s
   const char *e = getenv("KRR_SWEEP_PAIRS");
   const TileLayout &L = F->L;
   const int64_t npair = L.nt / 2;
-  if ((e && atoi(e) == 0) || npair == 0) return KRR_SUCCESS;
+  const bool pairs = e ? atoi(e) != 0 : ctx->tune.sweep_pairs != 0;
+  if (!pairs || npair == 0) return KRR_SUCCESS;
   if (!F->Cpair) {
     float *tmp = nullptr;
     CHK(sc.alloc(&tmp, npair * L.tile_elems()));
@@ -1333,9 +1458,10 @@ static krr_status sweep_coupling(krr_context ctx, krr_factorization F, Scoped &s
   return KRR_SUCCESS;
 }
 
-static krr_status solve_alloc(Scoped &sc, const TileLayout &L, int r, SolveBufs &b) {
+static krr_status solve_alloc(Scoped &sc, const TileLayout &L, int r, SolveBufs &b, int z) {
   const int64_t cnt = L.np * r;
-  CHK(sc.alloc(&b.Pr, cnt * residual_split(L)));
+  b.z = std::max(1, std::min(z, L.nt));
+  CHK(sc.alloc(&b.Pr, cnt * b.z));
   CHK(sc.alloc(&b.Yr, cnt));
   CHK(sc.alloc(&b.Xr, cnt));
   CHK(sc.alloc(&b.Rr, cnt));
@@ -1372,8 +1498,8 @@ static void residual_norms(krr_context ctx, krr_factorization F, int r, SolveBuf
   const TileLayout &L = F->L;
   {
     Stage t(ctx, KRR_STAGE_RESIDUAL, s);
-    launch_residual(K->D, K->etab, K->etab_len, K->gamma, K->lambda, L, r, b.Xr, b.Yr, b.Rr, b.Pr,
-                    s);
+    launch_residual(K->D, K->etab, K->etab_len, K->gamma, K->vmode(), K->Ec, K->lambda, L, r,
+                    b.Xr, b.Yr, b.Rr, b.Pr, b.z, s);
   }
   launch_col_norms(b.Rr, L.np, r, b.cn, b.cw, s);
   launch_col_norms(b.Xr, L.np, r, b.cn + r, b.cw, s);
@@ -1434,8 +1560,8 @@ static krr_status pcg_run(krr_context ctx, krr_factorization F, int r, SolveBufs
   while (it < o.max_iters) {
     {
       Stage t(ctx, KRR_STAGE_RESIDUAL, s);
-      launch_residual(K->D, K->etab, K->etab_len, K->gamma, K->lambda, L, r, pb.P, pb.Y0, pb.Nq,
-                      b.Pr, s);
+      launch_residual(K->D, K->etab, K->etab_len, K->gamma, K->vmode(), K->Ec, K->lambda, L,
+                      r, pb.P, pb.Y0, pb.Nq, b.Pr, b.z, s);
     }
     launch_col_dots(pb.P, pb.Nq, L.np, r, pnq, b.cw, s);
     launch_pcg_step(b.Xr, b.Rr, pb.P, pb.Nq, rho, pnq, cnt, r, s);
@@ -1473,7 +1599,8 @@ krr_status krr_solve(krr_context ctx, krr_factorization F, const double *Y, int6
   const int64_t cnt = L.np * r;
   Scoped sc(ctx);
   SolveBufs b;
-  CHK(solve_alloc(sc, L, r, b));
+  CHK(solve_alloc(sc, L, r, b,
+                  ctx->tune.residual_split > 0 ? ctx->tune.residual_split : residual_split(L)));
   CHK(sweep_coupling(ctx, F, sc, b, s));
   launch_colmajor_to_rows(Y, L.n, ldy, r, L.np, b.Yr, s);
   launch_fill_f64(b.Xr, cnt, 0.0, s);
@@ -1539,6 +1666,8 @@ krr_status krr_solve_batched(krr_context ctx, int32_t batch, const krr_factoriza
   for (int b = 0; b < batch; ++b) {
     if (!F[b] || !Y[b] || !X[b] || F[b]->K->ctx != ctx) return KRR_ERROR_INVALID_VALUE;
     if (ldy[b] < F[b]->L.n || ldx[b] < F[b]->L.n) return KRR_ERROR_INVALID_VALUE;
+    // the lockstep residual has no confounders and no linear kernel
+    if (F[b]->K->Ec || F[b]->K->kind == KRR_KERNEL_LINEAR) return KRR_ERROR_NOT_SUPPORTED;
   }
   krr_refine_opts o;
   CHK(refine_args(opts, false, o));
@@ -1547,7 +1676,8 @@ krr_status krr_solve_batched(krr_context ctx, int32_t batch, const krr_factoriza
   const int r = (int)nrhs, nb = ctx->opts.tile;
   Scoped sc(ctx);
   std::vector<SolveBufs> B(batch);
-  for (int b = 0; b < batch; ++b) CHK(solve_alloc(sc, F[b]->L, r, B[b]));
+  for (int b = 0; b < batch; ++b)
+    CHK(solve_alloc(sc, F[b]->L, r, B[b], residual_split_batched(F[b]->L)));
   SolveJob *djobs = nullptr;
   CHK(sc.alloc(&djobs, batch));
   // The table of the instances a batched launch covers; every instance's
@@ -1568,7 +1698,7 @@ krr_status krr_solve_batched(krr_context ctx, int32_t batch, const krr_factoriza
     j.etab = K->etab;
     j.etab_len = K->etab_len;
     j.gamma = K->gamma;
-    j.wshift = residual_exp_shift(K->gamma, K->etab_len);
+    j.wshift = K->vmode() != VAL_EXP ? -1 : residual_exp_shift(K->gamma, K->etab_len);
     j.np = F[b]->L.np;
     j.Xd = B[b].Xr;
     j.part = B[b].Pr;
@@ -1687,55 +1817,160 @@ static krr_status predict_args(krr_context ctx, krr_kernel K, const int8_t *T, i
   return KRR_SUCCESS;
 }
 
-// Predict with caller-placed buffers: nrm_t (n_test), flag (1), Dt (chunk x
-// np int32), Xr (np x r FP64).  Checks T's genotypes (one wait), then runs the
-// cross Gram and the FP64 product chunk by chunk of test rows.
+// Working buffers of one Predict: nrm_t (n_test), flag (1), Dt (chunk x np
+// int32), Xr (np x r FP64); for the IBS kernel Tenc (n_test x ldh, the
+// encoded test rows); with confounders Et (chunk x np FP64).
+struct PredictBufs {
+  int32_t *nrm_t = nullptr, *flag = nullptr, *Dt = nullptr;
+  double *Xr = nullptr, *Et = nullptr;
+  int8_t *Tenc = nullptr;
+  int64_t chunk = 0;
+};
+
+// Test rows per pass, so the cross-distance block (and the confounder
+// factors) stay within ~2 GiB.
+static int64_t predict_chunk(krr_kernel K, int64_t n_test) {
+  const int64_t per = K->L.np * (K->Ec ? 12 : 4);
+  int64_t chunk = std::max<int64_t>(256, ((int64_t)1 << 31) / per / 256 * 256);
+  return std::min<int64_t>(chunk, (n_test + 255) / 256 * 256);
+}
+
+static krr_status predict_alloc(Scoped &sc, krr_kernel K, int64_t n_test, int r, PredictBufs &b) {
+  const TileLayout &L = K->L;
+  b.chunk = predict_chunk(K, n_test);
+  CHK(sc.alloc(&b.nrm_t, (n_test + 255) / 256 * 256));
+  CHK(sc.alloc(&b.flag, 1));
+  CHK(sc.alloc(&b.Dt, b.chunk * L.np));
+  CHK(sc.alloc(&b.Xr, L.np * r));
+  if (K->H) CHK(sc.alloc(&b.Tenc, n_test * K->ldh));
+  if (K->Ec) CHK(sc.alloc(&b.Et, b.chunk * L.np));
+  return KRR_SUCCESS;
+}
+
+// Checks T's genotypes (one wait), then runs the cross Gram and the FP64
+// product chunk by chunk of test rows.  Ct: the test rows' confounders when
+// the kernel has them (n_test x q, ldct).
 static krr_status predict_run(krr_context ctx, krr_kernel K, const int8_t *T, int64_t n_test,
-                              int64_t ldt, const double *X, int r, int64_t ldx, double *P,
-                              int64_t ldp, int32_t *nrm_t, int32_t *flag, int32_t *Dt,
-                              int64_t chunk, double *Xr) {
+                              int64_t ldt, const double *Ct, int64_t ldct, const double *X, int r,
+                              int64_t ldx, double *P, int64_t ldp, const PredictBufs &b) {
   hipStream_t s = ctx->stream;
   const TileLayout &L = K->L;
-  launch_fill_i32(flag, 1, 0, s);
-  launch_row_norms(T, n_test, n_test, K->m, ldt, nrm_t, flag, s);
+  launch_fill_i32(b.flag, 1, 0, s);
+  launch_row_norms(T, n_test, n_test, K->m, ldt, b.nrm_t, b.flag, s);
   int32_t hflag = 0;
-  HIPCHK(hipMemcpyAsync(&hflag, flag, 4, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(&hflag, b.flag, 4, hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
   CHK(launch_ok());
   if (hflag) return KRR_ERROR_BAD_GENOTYPE;
-  launch_colmajor_to_rows(X, K->n, ldx, r, L.np, Xr, s);
-  for (int64_t r0 = 0; r0 < n_test; r0 += chunk) {
-    const int64_t rows = std::min(chunk, n_test - r0);
+  const int8_t *Tsrc = T;
+  int64_t ldsrc = ldt;
+  if (K->H) {  // the IBS kernel compares encoded rows
+    launch_ibs_encode(T, n_test, K->m, ldt, b.Tenc, K->ldh, s);
+    launch_row_norms(b.Tenc, n_test, n_test, K->ldh, K->ldh, b.nrm_t, b.flag, s);
+    Tsrc = b.Tenc;
+    ldsrc = K->ldh;
+  }
+  launch_colmajor_to_rows(X, K->n, ldx, r, L.np, b.Xr, s);
+  for (int64_t r0 = 0; r0 < n_test; r0 += b.chunk) {
+    const int64_t rows = std::min(b.chunk, n_test - r0);
     {
       Stage t(ctx, KRR_STAGE_CROSS_GRAM);
-      launch_cross_gram(T + r0 * ldt, rows, nrm_t + r0, K->G, K->n, K->m, ldt, K->ldg, K->nrm,
-                        L.np, Dt, L.np, s);
+      launch_cross_gram(Tsrc + r0 * ldsrc, rows, b.nrm_t + r0, K->gram_src(), K->n, K->gram_m(),
+                        ldsrc, K->gram_ld(), K->nrm, L.np, b.Dt, L.np,
+                        K->vmode() == VAL_LINEAR, s);
+      if (K->Ec)
+        launch_conf_factor_cross(Ct + r0 * ldct, rows, ldct, K->Cc, K->n, K->q, K->q, K->gamma,
+                                 L.np, b.Et, L.np, s);
     }
     Stage t(ctx, KRR_STAGE_PREDICT);
-    launch_predict_apply(Dt, rows, L.np, L.np, K->etab, K->etab_len, Xr, r, P + r0, ldp, s);
+    launch_predict_apply(b.Dt, rows, L.np, L.np, K->etab, K->etab_len, b.Xr, r, P + r0, ldp,
+                         K->Ec ? b.Et : nullptr, K->vmode() == VAL_LINEAR, s);
   }
   CHK(launch_ok());
   HIPCHK(hipStreamSynchronize(s));
   return KRR_SUCCESS;
 }
 
+krr_status krr_predict_ex(krr_context ctx, krr_kernel K, const int8_t *T, int64_t n_test,
+                          int64_t ldt, const double *Ct, int64_t ldct, const double *X,
+                          int64_t nrhs, int64_t ldx, double *P, int64_t ldp) {
+  CHK(predict_args(ctx, K, T, n_test, ldt, X, nrhs, ldx, P, ldp));
+  if (K->Ec && (!Ct || ldct < K->q)) return KRR_ERROR_INVALID_VALUE;
+  HIPCHK(hipSetDevice(ctx->device));
+  Scoped sc(ctx);
+  PredictBufs b;
+  CHK(predict_alloc(sc, K, n_test, (int)nrhs, b));
+  return predict_run(ctx, K, T, n_test, ldt, Ct, ldct, X, (int)nrhs, ldx, P, ldp, b);
+}
+
 krr_status krr_predict(krr_context ctx, krr_kernel K, const int8_t *T, int64_t n_test, int64_t ldt,
                        const double *X, int64_t nrhs, int64_t ldx, double *P, int64_t ldp) {
-  CHK(predict_args(ctx, K, T, n_test, ldt, X, nrhs, ldx, P, ldp));
+  if (K && K->Ec) return KRR_ERROR_INVALID_VALUE;  // needs the test rows' confounders
+  return krr_predict_ex(ctx, K, T, n_test, ldt, nullptr, 0, X, nrhs, ldx, P, ldp);
+}
+
+krr_status krr_predict_batched(krr_context ctx, int32_t batch, const krr_kernel *K,
+                               const int8_t *const *T, const int64_t *n_test, const int64_t *ldt,
+                               const double *const *X, int64_t nrhs, const int64_t *ldx,
+                               double *const *P, const int64_t *ldp) {
+  if (!ctx || batch <= 0 || !K || !T || !n_test || !ldt || !X || !ldx || !P || !ldp)
+    return KRR_ERROR_INVALID_VALUE;
+  for (int b = 0; b < batch; ++b) {
+    CHK(predict_args(ctx, K[b], T[b], n_test[b], ldt[b], X[b], nrhs, ldx[b], P[b], ldp[b]));
+    if (K[b]->kind != KRR_KERNEL_GAUSSIAN || K[b]->Ec)
+      return KRR_ERROR_NOT_SUPPORTED;  // krr_predict_ex per instance
+  }
   HIPCHK(hipSetDevice(ctx->device));
-  const TileLayout &L = K->L;
+  hipStream_t s = ctx->stream;
   const int r = (int)nrhs;
-  // test rows per pass, so the int32 cross-distance block stays within ~2 GiB
-  int64_t chunk = std::max<int64_t>(256, ((int64_t)1 << 29) / L.np / 256 * 256);
-  chunk = std::min<int64_t>(chunk, (n_test + 255) / 256 * 256);
+  // one cross-distance and one X buffer, sized for the largest instance
+  int64_t dt_elems = 0, x_elems = 0, nrm_elems = 0;
+  std::vector<int64_t> chunk(batch), nrm_off(batch);
+  for (int b = 0; b < batch; ++b) {
+    const int64_t np = K[b]->L.np;
+    chunk[b] = std::max<int64_t>(256, ((int64_t)1 << 29) / np / 256 * 256);
+    chunk[b] = std::min<int64_t>(chunk[b], (n_test[b] + 255) / 256 * 256);
+    dt_elems = std::max(dt_elems, chunk[b] * np);
+    x_elems = std::max(x_elems, np * r);
+    nrm_off[b] = nrm_elems;
+    nrm_elems += (n_test[b] + 255) / 256 * 256;
+  }
   Scoped sc(ctx);
   int32_t *nrm_t, *flag, *Dt;
   double *Xr;
-  CHK(sc.alloc(&nrm_t, (n_test + 255) / 256 * 256));
-  CHK(sc.alloc(&flag, 1));
-  CHK(sc.alloc(&Dt, chunk * L.np));
-  CHK(sc.alloc(&Xr, L.np * r));
-  return predict_run(ctx, K, T, n_test, ldt, X, r, ldx, P, ldp, nrm_t, flag, Dt, chunk, Xr);
+  CHK(sc.alloc(&nrm_t, nrm_elems));
+  CHK(sc.alloc(&flag, batch));
+  CHK(sc.alloc(&Dt, dt_elems));
+  CHK(sc.alloc(&Xr, x_elems));
+  // every instance's genotype check, then one wait
+  launch_fill_i32(flag, batch, 0, s);
+  for (int b = 0; b < batch; ++b)
+    launch_row_norms(T[b], n_test[b], n_test[b], K[b]->m, ldt[b], nrm_t + nrm_off[b], flag + b, s);
+  std::vector<int32_t> hflag(batch, 0);
+  HIPCHK(hipMemcpyAsync(hflag.data(), flag, 4 * (size_t)batch, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  CHK(launch_ok());
+  for (int b = 0; b < batch; ++b)
+    if (hflag[b]) return KRR_ERROR_BAD_GENOTYPE;
+  for (int b = 0; b < batch; ++b) {
+    const krr_kernel k = K[b];
+    const TileLayout &L = k->L;
+    launch_colmajor_to_rows(X[b], k->n, ldx[b], r, L.np, Xr, s);
+    for (int64_t r0 = 0; r0 < n_test[b]; r0 += chunk[b]) {
+      const int64_t rows = std::min(chunk[b], n_test[b] - r0);
+      {
+        Stage t(ctx, KRR_STAGE_CROSS_GRAM);
+        launch_cross_gram(T[b] + r0 * ldt[b], rows, nrm_t + nrm_off[b] + r0, k->G, k->n, k->m,
+                          ldt[b], k->ldg, k->nrm, L.np, Dt, L.np, false, s);
+      }
+      Stage t(ctx, KRR_STAGE_PREDICT);
+      launch_predict_apply(Dt, rows, L.np, L.np, k->etab, k->etab_len, Xr, r, P[b] + r0, ldp[b],
+                           nullptr, false, s);
+    }
+  }
+  CHK(launch_ok());
+  HIPCHK(hipStreamSynchronize(s));
+  return KRR_SUCCESS;
 }
 
 // Layout of the fixed scratch for one no-allocation Predict: flag, test-row
@@ -1760,6 +1995,8 @@ krr_status krr_predict_noalloc(krr_context ctx, krr_kernel K, const int8_t *T, i
                                int64_t ldt, const double *X, int64_t nrhs, int64_t ldx, double *P,
                                int64_t ldp) {
   CHK(predict_args(ctx, K, T, n_test, ldt, X, nrhs, ldx, P, ldp));
+  if (K->kind != KRR_KERNEL_GAUSSIAN || K->Ec)
+    return KRR_ERROR_NOT_SUPPORTED;  // the Gaussian kernel without confounders
   const int r = (int)nrhs;
   int64_t off_nrm, off_x, off_dt, chunk;
   if (!noalloc_layout(n_test, K->L.np, r, &off_nrm, &off_x, &off_dt, &chunk))
@@ -1767,9 +2004,13 @@ krr_status krr_predict_noalloc(krr_context ctx, krr_kernel K, const int8_t *T, i
   HIPCHK(hipSetDevice(ctx->device));
   uint8_t *base = (uint8_t *)scratch_ptr(ctx->device);  // set up by krr_create
   if (!base) return KRR_ERROR_HIP;
-  return predict_run(ctx, K, T, n_test, ldt, X, r, ldx, P, ldp, (int32_t *)(base + off_nrm),
-                     (int32_t *)base, (int32_t *)(base + off_dt), chunk,
-                     (double *)(base + off_x));
+  PredictBufs b;
+  b.flag = (int32_t *)base;
+  b.nrm_t = (int32_t *)(base + off_nrm);
+  b.Xr = (double *)(base + off_x);
+  b.Dt = (int32_t *)(base + off_dt);
+  b.chunk = chunk;
+  return predict_run(ctx, K, T, n_test, ldt, nullptr, 0, X, r, ldx, P, ldp, b);
 }
 
 krr_status krr_noalloc_limits(int64_t n, int64_t n_test, int64_t nrhs, int32_t tile,
@@ -1839,3 +2080,287 @@ krr_status krr_factor_copy_l(krr_factorization F, int64_t i0, int64_t j0, int64_
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Schedule tuning and the autotuner.
+
+static bool tuning_valid(const krr_tuning &t) {
+  return (t.tile == 256 || t.tile == 512) && t.panel_group >= 0 && t.panel_group <= KRR_MAX_GROUP &&
+         t.residual_split >= 0 && t.residual_split <= 16 && t.sweep_pairs >= -1 &&
+         t.sweep_pairs <= 1 && t.lookahead >= -1 && t.lookahead <= 1;
+}
+
+krr_status krr_set_tuning(krr_context ctx, const krr_tuning *t) {
+  if (!ctx || !t || !tuning_valid(*t)) return KRR_ERROR_INVALID_VALUE;
+  if (t->tile != ctx->opts.tile && ctx->live > 0) return KRR_ERROR_INVALID_VALUE;
+  ctx->tune = *t;
+  ctx->opts.tile = t->tile;
+  return KRR_SUCCESS;
+}
+
+krr_status krr_get_tuning(krr_context ctx, krr_tuning *t) {
+  if (!ctx || !t) return KRR_ERROR_INVALID_VALUE;
+  *t = ctx->tune;
+  t->tile = ctx->opts.tile;
+  return KRR_SUCCESS;
+}
+
+krr_status krr_tuning_key(int device, int64_t n, int64_t m, int64_t nrhs,
+                          const krr_precision_policy *policy, const krr_refine_opts *refine,
+                          char *key, int32_t cap) {
+  if (!key || cap <= 0 || n <= 0 || m <= 0 || nrhs <= 0) return KRR_ERROR_INVALID_VALUE;
+  krr_precision_policy p;
+  FactorPlan fp;
+  CHK(resolve_policy(policy, p, fp));
+  const int method = refine ? refine->method : KRR_REFINE_IR;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) != hipSuccess) {
+    (void)hipGetLastError();
+    return KRR_ERROR_HIP;
+  }
+  char arch[sizeof(prop.gcnArchName) + 1];
+  memcpy(arch, prop.gcnArchName, sizeof(prop.gcnArchName));
+  arch[sizeof(prop.gcnArchName)] = 0;
+  for (char *c = arch; *c; ++c)
+    if (*c == '"' || *c == '\\' || *c == ' ') *c = '_';
+  const int w = snprintf(key, (size_t)cap, "%s|cu%d|n%lld|m%lld|r%lld|mode%d|d64%d|ref%d", arch,
+                         prop.multiProcessorCount, (long long)n, (long long)m, (long long)nrhs,
+                         p.mode, p.diag_fp64 ? 1 : 0, method);
+  return (w > 0 && w < cap) ? KRR_SUCCESS : KRR_ERROR_INVALID_VALUE;
+}
+
+// One line of the cache file: "key": {fields}
+static bool cache_parse_line(const char *line, std::string &key, krr_tuning &t, double &ms,
+                             bool &well_formed) {
+  const char *q0 = strchr(line, '"');
+  if (!q0) return false;
+  const char *q1 = strchr(q0 + 1, '"');
+  if (!q1) return false;
+  key.assign(q0 + 1, q1 - q0 - 1);
+  int tile, g, z, pr, la;
+  well_formed = sscanf(q1 + 1,
+                       " : {\"tile\": %d, \"panel_group\": %d, \"residual_split\": %d, "
+                       "\"sweep_pairs\": %d, \"lookahead\": %d, \"ms\": %lf}",
+                       &tile, &g, &z, &pr, &la, &ms) == 6;
+  if (well_formed) {
+    t = krr_tuning{tile, g, z, pr, la};
+    well_formed = tuning_valid(t);
+  }
+  return true;
+}
+
+static std::map<std::string, std::string> cache_read(const char *path) {
+  std::map<std::string, std::string> lines;
+  FILE *f = fopen(path, "r");
+  if (!f) return lines;
+  char buf[1024];
+  while (fgets(buf, sizeof buf, f)) {
+    std::string key;
+    krr_tuning t;
+    double ms;
+    bool ok;
+    size_t len = strlen(buf);
+    while (len && (buf[len - 1] == '\n' || buf[len - 1] == '\r' || buf[len - 1] == ',')) buf[--len] = 0;
+    if (cache_parse_line(buf, key, t, ms, ok)) lines[key] = buf;
+  }
+  fclose(f);
+  return lines;
+}
+
+krr_status krr_tuning_cache_load(const char *path, const char *key, krr_tuning *t, double *ms,
+                                 int32_t *found) {
+  if (!path || !key || !t || !found) return KRR_ERROR_INVALID_VALUE;
+  *found = 0;
+  auto lines = cache_read(path);
+  auto it = lines.find(key);
+  if (it == lines.end()) return KRR_SUCCESS;
+  std::string k;
+  krr_tuning v;
+  double m = 0;
+  bool ok = false;
+  cache_parse_line(it->second.c_str(), k, v, m, ok);
+  if (!ok) return KRR_ERROR_INVALID_VALUE;
+  *t = v;
+  if (ms) *ms = m;
+  *found = 1;
+  return KRR_SUCCESS;
+}
+
+krr_status krr_tuning_cache_store(const char *path, const char *key, const krr_tuning *t,
+                                  double ms) {
+  if (!path || !key || !t || !tuning_valid(*t) || strchr(key, '"') || strchr(key, '\n'))
+    return KRR_ERROR_INVALID_VALUE;
+  auto lines = cache_read(path);
+  char buf[1024];
+  snprintf(buf, sizeof buf,
+           "\"%s\": {\"tile\": %d, \"panel_group\": %d, \"residual_split\": %d, "
+           "\"sweep_pairs\": %d, \"lookahead\": %d, \"ms\": %.6f}",
+           key, t->tile, t->panel_group, t->residual_split, t->sweep_pairs, t->lookahead, ms);
+  lines[key] = buf;
+  std::string tmp = std::string(path) + ".tmp";
+  FILE *f = fopen(tmp.c_str(), "w");
+  if (!f) return KRR_ERROR_INVALID_VALUE;
+  fprintf(f, "{\n");
+  size_t i = 0;
+  for (auto &kv : lines) fprintf(f, "%s%s\n", kv.second.c_str(), ++i < lines.size() ? "," : "");
+  fprintf(f, "}\n");
+  const bool ok = fclose(f) == 0 && rename(tmp.c_str(), path) == 0;
+  return ok ? KRR_SUCCESS : KRR_ERROR_INVALID_VALUE;
+}
+
+krr_status krr_autotune(krr_context ctx, const int8_t *G, int64_t n, int64_t m, int64_t ldg,
+                        double gamma, double lambda, const double *Y, int64_t nrhs, int64_t ldy,
+                        const krr_precision_policy *policy, const krr_refine_opts *refine,
+                        const char *cache_path, krr_tuning *out, double *best_ms) {
+  if (!ctx || !out || !Y || nrhs <= 0 || ldy < n || ctx->destroy_pending)
+    return KRR_ERROR_INVALID_VALUE;
+  CHK(build_args(G, n, m, ldg, gamma, lambda));
+  if (ctx->live > 0) return KRR_ERROR_INVALID_VALUE;
+  char key[512];
+  CHK(krr_tuning_key(ctx->device, n, m, nrhs, policy, refine, key, sizeof key));
+  if (cache_path) {
+    krr_tuning t;
+    double ms = 0;
+    int32_t found = 0;
+    if (krr_tuning_cache_load(cache_path, key, &t, &ms, &found) == KRR_SUCCESS && found) {
+      CHK(krr_set_tuning(ctx, &t));
+      *out = t;
+      if (best_ms) *best_ms = ms;
+      return KRR_SUCCESS;
+    }
+  }
+  HIPCHK(hipSetDevice(ctx->device));
+  hipStream_t s = ctx->stream;
+  double *X = nullptr;
+  CHK(dalloc_t(ctx, &X, n * nrhs));
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    dfree(ctx, X, (size_t)n * nrhs * 8);
+    return KRR_ERROR_HIP;
+  }
+  const krr_tuning saved = ctx->tune;
+  const int saved_tile = ctx->opts.tile;
+  // one whole step under tuning t; its time in ms, or a negative value on failure
+  auto run = [&](const krr_tuning &t) -> double {
+    ctx->tune = t;
+    ctx->opts.tile = t.tile;
+    if (hipEventRecord(e0, s) != hipSuccess) return -1;
+    krr_kernel K = nullptr;
+    krr_factorization F = nullptr;
+    krr_status st = krr_build_kernel(ctx, G, n, m, ldg, gamma, lambda, &K);
+    if (st == KRR_SUCCESS) st = krr_factor(ctx, K, policy, &F);
+    if (st == KRR_SUCCESS) st = krr_solve(ctx, F, Y, nrhs, ldy, X, n, refine, nullptr);
+    if (F) krr_factor_release(F);
+    if (K) krr_kernel_release(K);
+    float ms = -1;
+    if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+        hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+      return -1;
+    return st == KRR_SUCCESS ? (double)ms : -1;
+  };
+  krr_tuning best{saved_tile, 0, 0, -1, -1};
+  double best_t = -1;
+  auto consider = [&](const krr_tuning &t, bool warm) {
+    if (warm) run(t);
+    const double ms = run(t);
+    if (ms >= 0 && (best_t < 0 || ms < best_t)) {
+      best_t = ms;
+      best = t;
+    }
+  };
+  for (int tile : {512, 256}) {
+    krr_tuning t{tile, 0, 0, -1, -1};
+    consider(t, true);
+  }
+  if (best_t >= 0) {
+    const krr_tuning b0 = best;
+    for (int g : {4, 6, 8}) {
+      krr_tuning t = b0;
+      t.panel_group = g;
+      consider(t, false);
+    }
+    const krr_tuning b1 = best;
+    for (int z : {4, 8, 16}) {
+      krr_tuning t = b1;
+      t.residual_split = z;
+      consider(t, false);
+    }
+    const krr_tuning b2 = best;
+    for (int pr : {1, 0}) {
+      krr_tuning t = b2;
+      t.sweep_pairs = pr;
+      consider(t, false);
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  dfree(ctx, X, (size_t)n * nrhs * 8);
+  if (best_t < 0) {
+    ctx->tune = saved;
+    ctx->opts.tile = saved_tile;
+    return KRR_ERROR_NOT_CONVERGED;
+  }
+  ctx->tune = best;
+  ctx->opts.tile = best.tile;
+  *out = best;
+  if (best_ms) *best_ms = best_t;
+  if (cache_path) (void)krr_tuning_cache_store(cache_path, key, &best, best_t);
+  return KRR_SUCCESS;
+}
+
+// ---------------------------------------------------------------------------
+// Ridge Regression (the RR subsection, Eq. 1-2): beta = (X^T X + lambda I)^-1
+// X^T Y.  X^T X is the linear kernel of the SNP columns (the rows of X^T),
+// through the same INT8 Gram with exact int32 accumulation; the factorization,
+// solves and FP64 refinement are the KRR ones.
+
+krr_status krr_rr_fit(krr_context ctx, const int8_t *G, int64_t n, int64_t m, int64_t ldg,
+                      const double *Y, int64_t nrhs, int64_t ldy, double lambda,
+                      const krr_precision_policy *policy, const krr_refine_opts *refine,
+                      double *beta, int64_t ldb, krr_solve_info *info) {
+  if (!ctx || !Y || !beta || nrhs <= 0 || nrhs > 4096 || ldy < n || ldb < m)
+    return KRR_ERROR_INVALID_VALUE;
+  CHK(build_args(G, n, m, ldg, 1.0, lambda));
+  if (n > (1LL << 22)) return KRR_ERROR_NOT_SUPPORTED;  // X^T X entries <= 4n stay exact in FP32
+  HIPCHK(hipSetDevice(ctx->device));
+  hipStream_t s = ctx->stream;
+  const int64_t ldgt = (n + 15) / 16 * 16;
+  Scoped sc(ctx);
+  int8_t *Gt = nullptr;
+  double *B = nullptr;
+  CHK(sc.alloc(&Gt, m * ldgt));
+  CHK(sc.alloc(&B, m * nrhs));
+  launch_transpose_i8(G, n, m, ldg, Gt, ldgt, s);                      // X^T: SNPs as rows
+  launch_int8_t_times_f64(G, n, m, ldg, Y, (int)nrhs, ldy, B, m, s);   // X^T Y
+  CHK(launch_ok());
+  krr_kernel_desc d{};
+  d.kind = KRR_KERNEL_LINEAR;
+  krr_kernel K = nullptr;
+  krr_factorization F = nullptr;
+  krr_status st = krr_build_kernel_ex(ctx, Gt, m, n, ldgt, 1.0, lambda, &d, &K);
+  if (st == KRR_SUCCESS) st = krr_factor(ctx, K, policy, &F);
+  if (st == KRR_SUCCESS) st = krr_solve(ctx, F, B, nrhs, m, beta, ldb, refine, info);
+  if (F) krr_factor_release(F);
+  if (K) krr_kernel_release(K);
+  return st;
+}
+
+krr_status krr_rr_predict(krr_context ctx, const int8_t *T, int64_t n_test, int64_t m,
+                          int64_t ldt, const double *beta, int64_t nrhs, int64_t ldb, double *P,
+                          int64_t ldp) {
+  if (!ctx || !T || !beta || !P || n_test <= 0 || m <= 0 || nrhs <= 0 || ldt < m ||
+      ldb < m || ldp < n_test)
+    return KRR_ERROR_INVALID_VALUE;
+  HIPCHK(hipSetDevice(ctx->device));
+  hipStream_t s = ctx->stream;
+  const int64_t ldtt = (n_test + 15) / 16 * 16;
+  Scoped sc(ctx);
+  int8_t *Tt = nullptr;
+  CHK(sc.alloc(&Tt, m * ldtt));
+  launch_transpose_i8(T, n_test, m, ldt, Tt, ldtt, s);
+  // P = T beta = (T^T)^T beta, the same int8-transposed product as X^T Y
+  launch_int8_t_times_f64(Tt, m, n_test, ldtt, beta, (int)nrhs, ldb, P, ldp, s);
+  CHK(launch_ok());
+  HIPCHK(hipStreamSynchronize(s));
+  return KRR_SUCCESS;
+}

@@ -79,18 +79,24 @@ void launch_row_norms(const int8_t *G, int64_t n, int64_t rows_padded, int64_t m
 // entry: d = n_i + n_j - 2 S (int32), A = exp(-gamma d) (two-level table in
 // LDS, FP64 product rounded to FP32), 1 + lambda on the diagonal, identity
 // on padding; plus the sub-block's FP64 sum of squares for the tile norms.
+// vmode (VAL_*): VAL_EXP the Gaussian through the exponential tables;
+// VAL_TABLE another kernel of the distance held in the table (IBS), a plain
+// lookup per entry; VAL_LINEAR the linear kernel: the Gram entry itself is
+// stored and is the value.  Ec (or null): FP64 confounder factors
+// exp(-gamma dc_ij) in the packed tile layout, multiplied in.
 template <class S>
 KRR_DEV void gram_block(const int8_t *__restrict__ G, int64_t n, int64_t m, int64_t ldg,
                         const int32_t *__restrict__ nrm, const double *__restrict__ etab,
                         int64_t etab_len, double lambda, int nb, int SB, int32_t *__restrict__ D,
-                        float *__restrict__ A, double *part, int64_t bid) {
+                        float *__restrict__ A, double *part, int64_t bid, int vmode,
+                        const double *__restrict__ Ec) {
   constexpr int BM = S::kBM, BN = S::kBN, NW = S::THREADS / 64;
   extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
   __shared__ double shd[NW];
   __shared__ double ehi[EXP_HI_MAX], elo[EXP_LO];
   const int64_t dmax = etab_len - 1;
   const int nhi = (int)(dmax / EXP_LO) + 1;
-  const bool two_level = nhi <= EXP_HI_MAX;
+  const bool two_level = vmode == VAL_EXP && nhi <= EXP_HI_MAX;
   if (two_level) {  // visible to the epilogue through the GEMM's barriers
     for (int q = threadIdx.x; q < EXP_LO; q += S::THREADS) elo[q] = etab[min((int64_t)q, dmax)];
     for (int q = threadIdx.x; q < nhi; q += S::THREADS) ehi[q] = etab[(int64_t)q * EXP_LO];
@@ -128,16 +134,20 @@ KRR_DEV void gram_block(const int8_t *__restrict__ G, int64_t n, int64_t m, int6
         const int64_t gi = row0 + r, gj = col0 + c;
         int32_t d;
         float a;
-        if (gi < n && gj < n) {
+        const int64_t off = tbase + (int64_t)(si * BM + r) * nb + sj * BN + c;
+        if (gi < n && gj < n && vmode == VAL_LINEAR) {
+          d = acc[tm][tn][i];  // the inner product is the value (exact in FP32 below 2^24)
+          a = (float)((double)d + (gi == gj ? lambda : 0.0));
+        } else if (gi < n && gj < n) {
           d = nrm[gi] + nrm[gj] - 2 * acc[tm][tn][i];
           const int32_t dc = (int32_t)min((int64_t)max(d, 0), dmax);
-          const double e = two_level ? exp_two_level(ehi, elo, dc) : etab[dc];
+          double e = two_level ? exp_two_level(ehi, elo, dc) : etab[dc];
+          if (Ec) e *= Ec[off];
           a = (gi == gj) ? (float)(1.0 + lambda) : (float)e;
         } else {
           d = 0;
           a = (gi == gj) ? 1.0f : 0.0f;
         }
-        const int64_t off = tbase + (int64_t)(si * BM + r) * nb + sj * BN + c;
         D[off] = d;
         A[off] = a;
         ss += (double)a * (double)a;
@@ -153,9 +163,11 @@ __global__ __launch_bounds__(S::THREADS) void k_gram_tiles(const int8_t *__restr
                                                     const double *__restrict__ etab,
                                                     int64_t etab_len, double lambda, int nb,
                                                     int SB, int32_t *__restrict__ D,
-                                                    float *__restrict__ A, double *part) {
+                                                    float *__restrict__ A, double *part,
+                                                    int vmode,
+                                                    const double *__restrict__ Ec) {
   gram_block<S>(G, n, m, ldg, nrm, etab, etab_len, lambda, nb, SB, D, A, part,
-                xcd_remap(blockIdx.x, gridDim.x));
+                xcd_remap(blockIdx.x, gridDim.x), vmode, Ec);
 }
 
 // Instance of a batch that owns workgroup `bid`: the last job whose first
@@ -179,14 +191,15 @@ __global__ __launch_bounds__(S::THREADS) void k_gram_tiles_batched(const BuildJo
   const int64_t bid = xcd_remap(blockIdx.x, gridDim.x);
   const BuildJob &j = jobs[find_job<&BuildJob::block0>(jobs, njobs, bid)];
   gram_block<S>(j.G, j.n, m, j.ldg, j.nrm, j.etab, j.etab_len, j.lambda, nb, SB, j.D, j.A, j.part,
-                bid - j.block0);
+                bid - j.block0, VAL_EXP, nullptr);
 }
 
 typedef StreamShape<256, 256, 2, 4, 4> GramShape;
 
 void launch_gram_tiles(const int8_t *G, int64_t m, int64_t ldg, const int32_t *nrm,
                        const double *etab, int64_t etab_len, double lambda, const TileLayout &L,
-                       int32_t *D, float *A, double *tnorm_part, hipStream_t s) {
+                       int32_t *D, float *A, double *tnorm_part, int vmode,
+                       const double *Ec, hipStream_t s) {
   const int SB = L.nb / GramShape::kBM;
   const int64_t blocks = L.ntiles() * SB * SB;
   static bool attr = false;
@@ -197,7 +210,7 @@ void launch_gram_tiles(const int8_t *G, int64_t m, int64_t ldg, const int32_t *n
   }
   hipLaunchKernelGGL((k_gram_tiles<GramShape>), dim3((unsigned)blocks), dim3(GramShape::THREADS),
                      GramShape::LDS_BYTES, s, G, L.n, m,
-                     ldg, nrm, etab, etab_len, lambda, L.nb, SB, D, A, tnorm_part);
+                     ldg, nrm, etab, etab_len, lambda, L.nb, SB, D, A, tnorm_part, vmode, Ec);
 }
 
 int64_t gram_blocks(const TileLayout &L) {
@@ -276,6 +289,7 @@ void launch_tile_norms(const double *part, int parts, int64_t ntiles, double *tn
 // epilogue wrote), for a second factorization of one kernel.
 __global__ void k_expand_tiles(const int32_t *__restrict__ D, const double *__restrict__ etab,
                                int64_t etab_len, double lambda, int64_t n, int nb, int64_t total,
+                               int vmode, const double *__restrict__ Ec,
                                float *__restrict__ A) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= total) return;
@@ -285,12 +299,15 @@ __global__ void k_expand_tiles(const int32_t *__restrict__ D, const double *__re
   tri_decode(t, I, J);
   const int64_t gi = (int64_t)I * nb + w / nb, gj = (int64_t)J * nb + w % nb;
   float a;
-  if (gi < n && gj < n) {  // the same value as the Gram epilogue
+  if (gi < n && gj < n && vmode == VAL_LINEAR) {
+    a = (float)((double)D[e] + (gi == gj ? lambda : 0.0));
+  } else if (gi < n && gj < n) {  // the same value as the Gram epilogue
     const int64_t dmax = etab_len - 1;
     const int32_t dc = (int32_t)min((int64_t)max(D[e], 0), dmax);
-    const double ev = (dmax / EXP_LO + 1 <= EXP_HI_MAX)
-                          ? etab[(int64_t)(dc / EXP_LO) * EXP_LO] * etab[dc % EXP_LO]
-                          : etab[dc];
+    double ev = (vmode == VAL_EXP && dmax / EXP_LO + 1 <= EXP_HI_MAX)
+                    ? etab[(int64_t)(dc / EXP_LO) * EXP_LO] * etab[dc % EXP_LO]
+                    : etab[dc];
+    if (Ec) ev *= Ec[e];
     a = (gi == gj) ? (float)(1.0 + lambda) : (float)ev;
   } else {
     a = (gi == gj) ? 1.0f : 0.0f;
@@ -299,15 +316,160 @@ __global__ void k_expand_tiles(const int32_t *__restrict__ D, const double *__re
 }
 
 void launch_expand_tiles(const int32_t *D, const double *etab, int64_t etab_len, double lambda,
-                         const TileLayout &L, float *A, hipStream_t s) {
+                         int vmode, const double *Ec, const TileLayout &L, float *A,
+                         hipStream_t s) {
   const int64_t total = L.elems();
   hipLaunchKernelGGL(k_expand_tiles, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, D,
-                     etab, etab_len, lambda, L.n, L.nb, total, A);
+                     etab, etab_len, lambda, L.n, L.nb, total, vmode, Ec, A);
+}
+
+// IBS kernel (Algorithm 5, IBS branch): the alleles two patients share
+// identical by state, over the 2m alleles of a patient.  With the
+// thermometer encoding h(g) = ([g >= 1], [g >= 2]) of each genotype,
+// ||h(a) - h(b)||^2 = |a - b| for a, b in {0, 1, 2}, so the squared distance
+// of the encoded rows is d = sum_k |g_ik - g_jk| (exact, through the same
+// INT8 Gram), the shared alleles are 2m - d, and K_ij = (2m - d) / (2m):
+// tab[d] for d = 0 .. 2m (larger d cannot occur; they read 0).
+__global__ void k_ibs_table(double *tab, int64_t len, int64_t m) {
+  const int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (d < len) tab[d] = d <= 2 * m ? (double)(2 * m - d) / (double)(2 * m) : 0.0;
+}
+
+void launch_ibs_table(double *tab, int64_t len, int64_t m, hipStream_t s) {
+  hipLaunchKernelGGL(k_ibs_table, dim3((unsigned)((len + 255) / 256)), dim3(256), 0, s, tab, len,
+                     m);
+}
+
+// Thermometer encoding of genotype rows: H[i, c] = [g_ic >= 1] for c < m and
+// H[i, half + c] = [g_ic >= 2], half = m rounded up to 16; the columns
+// m .. half-1 and half+m .. 2 half-1 are zero.  16 genotypes per thread.
+__global__ void k_ibs_encode(const int8_t *__restrict__ G, int64_t rows, int64_t m, int64_t ldg,
+                             int8_t *__restrict__ H, int64_t ldh, int64_t half) {
+  const int64_t per_row = half / 16;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= rows * per_row) return;
+  const int64_t i = e / per_row, c0 = (e % per_row) * 16;
+  const uint8_t *g = (const uint8_t *)G + i * ldg + c0;
+  uint32_t w[4];
+  *(v4i *)w = *(const v4i *)g;  // in bounds: ldg is a multiple of 16 and >= m
+  uint32_t h1[4], h2[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int64_t valid = m - c0 - 4 * q;
+    uint32_t x = w[q];
+    if (valid <= 0) x = 0;
+    else if (valid < 4) x &= (1u << (8 * valid)) - 1u;
+    // per byte b in {0, 1, 2}: [b >= 1] = (b | b >> 1) & 1, [b >= 2] = (b >> 1) & 1
+    h1[q] = (x | (x >> 1)) & 0x01010101u;
+    h2[q] = (x >> 1) & 0x01010101u;
+  }
+  int8_t *o = H + i * ldh + c0;
+  *(v4i *)o = *(const v4i *)h1;
+  *(v4i *)(o + half) = *(const v4i *)h2;
+}
+
+void launch_ibs_encode(const int8_t *G, int64_t rows, int64_t m, int64_t ldg, int8_t *H,
+                       int64_t ldh, hipStream_t s) {
+  const int64_t half = (m + 15) / 16 * 16;
+  const int64_t tot = rows * (half / 16);
+  if (tot <= 0) return;
+  hipLaunchKernelGGL(k_ibs_encode, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, G, rows,
+                     m, ldg, H, ldh, half);
+}
+
+// Confounder factors of the Gaussian kernel (the Build subsection adds the
+// squared distances of real-valued covariates to the genotype distances
+// before the exponential): Ec_ij = exp(-gamma dc_ij), dc_ij = sum_k (c_ik -
+// c_jk)^2 by its definition in FP64, over the packed lower tiles (1 on
+// padding rows and columns).  One 64 x 64 block per workgroup, the 64 + 64
+// confounder rows it needs staged in LDS.
+constexpr int CONF_QMAX = 32;
+
+__global__ __launch_bounds__(256) void k_conf_factor(const double *__restrict__ C, int64_t n,
+                                                     int64_t q, int64_t ldc, double gamma, int nb,
+                                                     double *__restrict__ Ec) {
+  __shared__ double ci[64][CONF_QMAX + 1], cj[64][CONF_QMAX + 1];
+  const int sb = nb / 64, nsub = sb * sb;
+  const int64_t t = blockIdx.x / nsub;
+  const int sub = (int)(blockIdx.x % nsub), si = sub / sb, sj = sub % sb;
+  int I, J;
+  tri_decode(t, I, J);
+  const int64_t i0 = (int64_t)I * nb + si * 64, j0 = (int64_t)J * nb + sj * 64;
+  for (int e = threadIdx.x; e < 64 * (int)q; e += 256) {
+    const int r = e / (int)q, k = e % (int)q;
+    ci[r][k] = (i0 + r < n) ? C[(i0 + r) * ldc + k] : 0.0;
+    cj[r][k] = (j0 + r < n) ? C[(j0 + r) * ldc + k] : 0.0;
+  }
+  __syncthreads();
+  double *out = Ec + t * (int64_t)nb * nb + (int64_t)(si * 64) * nb + sj * 64;
+  for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+    const int r = e / 64, c = e % 64;
+    double v = 1.0;
+    if (i0 + r < n && j0 + c < n) {
+      double dc = 0.0;
+      for (int k = 0; k < (int)q; ++k) {
+        const double x = ci[r][k] - cj[c][k];
+        dc = fma(x, x, dc);
+      }
+      v = exp(-gamma * dc);
+    }
+    out[(int64_t)r * nb + c] = v;
+  }
+}
+
+void launch_conf_factor(const double *C, int64_t n, int64_t q, int64_t ldc, double gamma,
+                        const TileLayout &L, double *Ec, hipStream_t s) {
+  const int sb = L.nb / 64;
+  hipLaunchKernelGGL(k_conf_factor, dim3((unsigned)(L.ntiles() * sb * sb)), dim3(256), 0, s, C, L.n,
+                     q, ldc, gamma, L.nb, Ec);
+}
+
+// The same factors between test rows (Ct, rows x q) and training rows (C):
+// Et[i, j] = exp(-gamma sum_k (ct_ik - c_jk)^2) for j < n, 1 for the padding
+// columns n .. cols-1; row-major with leading dimension lde.
+__global__ __launch_bounds__(256) void k_conf_factor_cross(const double *__restrict__ Ct,
+                                                           int64_t rows, int64_t ldct,
+                                                           const double *__restrict__ C, int64_t n,
+                                                           int64_t q, int64_t ldc, double gamma,
+                                                           int64_t cols, double *__restrict__ Et,
+                                                           int64_t lde) {
+  __shared__ double ci[64][CONF_QMAX + 1], cj[64][CONF_QMAX + 1];
+  const int64_t ncb = (cols + 63) / 64;
+  const int64_t i0 = (int64_t)(blockIdx.x / ncb) * 64, j0 = (int64_t)(blockIdx.x % ncb) * 64;
+  for (int e = threadIdx.x; e < 64 * (int)q; e += 256) {
+    const int r = e / (int)q, k = e % (int)q;
+    ci[r][k] = (i0 + r < rows) ? Ct[(i0 + r) * ldct + k] : 0.0;
+    cj[r][k] = (j0 + r < n) ? C[(j0 + r) * ldc + k] : 0.0;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+    const int r = e / 64, c = e % 64;
+    if (i0 + r >= rows || j0 + c >= cols) continue;
+    double v = 1.0;
+    if (j0 + c < n) {
+      double dc = 0.0;
+      for (int k = 0; k < (int)q; ++k) {
+        const double x = ci[r][k] - cj[c][k];
+        dc = fma(x, x, dc);
+      }
+      v = exp(-gamma * dc);
+    }
+    Et[(i0 + r) * lde + j0 + c] = v;
+  }
+}
+
+void launch_conf_factor_cross(const double *Ct, int64_t rows, int64_t ldct, const double *C,
+                              int64_t n, int64_t q, int64_t ldc, double gamma, int64_t cols,
+                              double *Et, int64_t lde, hipStream_t s) {
+  const int64_t blocks = ((rows + 63) / 64) * ((cols + 63) / 64);
+  hipLaunchKernelGGL(k_conf_factor_cross, dim3((unsigned)blocks), dim3(256), 0, s, Ct, rows, ldct,
+                     C, n, q, ldc, gamma, cols, Et, lde);
 }
 
 // Cross distances for Predict (Algorithm 4's Build(gamma, T, G)):
 // Dt[i, j] = n^T_i + n^G_j - 2 <t_i, g_j> for i < rows, j < cols_padded
-// (0 for the padding columns j >= n).  Row-major with leading dimension ldd.
+// (0 for the padding columns j >= n), or the inner product <t_i, g_j>
+// itself for the linear kernel.  Row-major with leading dimension ldd.
 template <class S>
 __global__ __launch_bounds__(S::THREADS) void k_cross_gram(const int8_t *__restrict__ T, int64_t rows,
                                                     const int32_t *__restrict__ nrm_t,
@@ -315,7 +477,8 @@ __global__ __launch_bounds__(S::THREADS) void k_cross_gram(const int8_t *__restr
                                                     int64_t m, int64_t ldt, int64_t ldg,
                                                     const int32_t *__restrict__ nrm_g,
                                                     int64_t cols, int64_t nbc,
-                                                    int32_t *__restrict__ Dt, int64_t ldd) {
+                                                    int32_t *__restrict__ Dt, int64_t ldd,
+                                                    int linear) {
   constexpr int BM = S::kBM, BN = S::kBN;
   extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
   const int64_t bid = xcd_remap(blockIdx.x, gridDim.x);
@@ -339,13 +502,16 @@ __global__ __launch_bounds__(S::THREADS) void k_cross_gram(const int8_t *__restr
         const int64_t gi = row0 + S::row(wave, tm, i, lane);
         const int64_t gj = col0 + S::col(wave, tn, lane);
         if (gi < rows && gj < cols)
-          Dt[gi * ldd + gj] = (gj < n) ? nrm_t[gi] + nrm_g[gj] - 2 * acc[tm][tn][i] : 0;
+          Dt[gi * ldd + gj] = (gj >= n)  ? 0
+                              : linear   ? acc[tm][tn][i]
+                                         : nrm_t[gi] + nrm_g[gj] - 2 * acc[tm][tn][i];
       }
 }
 
 void launch_cross_gram(const int8_t *T, int64_t nt_rows, const int32_t *nrm_t, const int8_t *G,
                        int64_t n, int64_t m, int64_t ldt, int64_t ldg, const int32_t *nrm_g,
-                       int64_t cols_padded, int32_t *Dt, int64_t ldd, hipStream_t s) {
+                       int64_t cols_padded, int32_t *Dt, int64_t ldd, bool linear,
+                       hipStream_t s) {
   constexpr int BM = GramShape::kBM, BN = GramShape::kBN;
   const int64_t nbr = (nt_rows + BM - 1) / BM, nbc = (cols_padded + BN - 1) / BN;
   static bool attr = false;
@@ -356,7 +522,8 @@ void launch_cross_gram(const int8_t *T, int64_t nt_rows, const int32_t *nrm_t, c
   }
   hipLaunchKernelGGL((k_cross_gram<GramShape>), dim3((unsigned)(nbr * nbc)),
                      dim3(GramShape::THREADS), GramShape::LDS_BYTES, s, T,
-                     nt_rows, nrm_t, G, n, m, ldt, ldg, nrm_g, cols_padded, nbc, Dt, ldd);
+                     nt_rows, nrm_t, G, n, m, ldt, ldg, nrm_g, cols_padded, nbc, Dt, ldd,
+                     linear ? 1 : 0);
 }
 
 // Diagnostics: gather a rectangular block of a tile-packed symmetric matrix.
@@ -396,6 +563,82 @@ void launch_copy_tiles_f32(const float *A, const TileLayout &L, int64_t i0, int6
   const int64_t tot = rows * cols;
   hipLaunchKernelGGL(k_copy_tiles<float>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, A,
                      L.nb, i0, j0, rows, cols, lower_only ? 1 : 0, dst, ld);
+}
+
+}  // namespace krr
+
+namespace krr {
+
+// Transpose of an int8 matrix: At[c, i] = A[i, c] for i < rows, c < cols, and
+// zeros in the padding columns rows .. ldt-1 of At.  64 x 64 blocks through LDS.
+__global__ __launch_bounds__(256) void k_transpose_i8(const int8_t *__restrict__ A, int64_t rows,
+                                                      int64_t cols, int64_t lda,
+                                                      int8_t *__restrict__ At, int64_t ldt) {
+  __shared__ int8_t t[64][65];
+  const int64_t r0 = (int64_t)blockIdx.y * 64, c0 = (int64_t)blockIdx.x * 64;
+  for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+    const int r = e / 64, c = e % 64;
+    t[r][c] = (r0 + r < rows && c0 + c < cols) ? A[(r0 + r) * lda + c0 + c] : (int8_t)0;
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+    const int c = e / 64, r = e % 64;  // output row c0 + c, column r0 + r
+    if (c0 + c < cols && r0 + r < ldt) At[(c0 + c) * ldt + r0 + r] = t[r][c];
+  }
+}
+
+void launch_transpose_i8(const int8_t *A, int64_t rows, int64_t cols, int64_t lda, int8_t *At,
+                         int64_t ldt, hipStream_t s) {
+  const dim3 grid((unsigned)((cols + 63) / 64), (unsigned)((ldt + 63) / 64));
+  hipLaunchKernelGGL(k_transpose_i8, grid, dim3(256), 0, s, A, rows, cols, lda, At, ldt);
+}
+
+// B = A^T Y for an int8 matrix A (rows x cols, row-major) and FP64 Y (rows x
+// r, column-major, ldy): B[a, c] = sum_i A[i, a] Y[i, c] in FP64 with the sum
+// over i in order; B column-major (ldb).  A workgroup owns 64 columns a and
+// 16 columns c (four per thread); the rows are staged 64 at a time (the A
+// block and the Y block in LDS).  The products of small integers with FP64
+// values are exact, so only the additions round.
+__global__ __launch_bounds__(256) void k_int8_t_times_f64(const int8_t *__restrict__ A,
+                                                          int64_t rows, int64_t cols, int64_t lda,
+                                                          const double *__restrict__ Y, int r,
+                                                          int64_t ldy, double *__restrict__ B,
+                                                          int64_t ldb) {
+  __shared__ int8_t as[64][64 + 4];
+  __shared__ double ys[64][17];
+  const int64_t a0 = (int64_t)blockIdx.x * 64;
+  const int c0 = blockIdx.y * 16;
+  const int al = threadIdx.x % 64, cg = threadIdx.x / 64;  // column a0 + al, c0 + 4 cg .. +3
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int64_t i0 = 0; i0 < rows; i0 += 64) {
+    for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+      const int ii = e / 64, aa = e % 64;
+      as[ii][aa] = (i0 + ii < rows && a0 + aa < cols) ? A[(i0 + ii) * lda + a0 + aa] : (int8_t)0;
+    }
+    for (int e = threadIdx.x; e < 64 * 16; e += 256) {
+      const int cc = e / 64, ii = e % 64;
+      ys[ii][cc] = (i0 + ii < rows && c0 + cc < r) ? Y[(int64_t)(c0 + cc) * ldy + i0 + ii] : 0.0;
+    }
+    __syncthreads();
+    for (int ii = 0; ii < 64; ++ii) {
+      const double g = (double)as[ii][al];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc[q] = fma(g, ys[ii][4 * cg + q], acc[q]);
+    }
+    __syncthreads();
+  }
+  if (a0 + al < cols)
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (c0 + 4 * cg + q < r) B[(int64_t)(c0 + 4 * cg + q) * ldb + a0 + al] = acc[q];
+}
+
+void launch_int8_t_times_f64(const int8_t *A, int64_t rows, int64_t cols, int64_t lda,
+                             const double *Y, int r, int64_t ldy, double *B, int64_t ldb,
+                             hipStream_t s) {
+  const dim3 grid((unsigned)((cols + 63) / 64), (unsigned)((r + 15) / 16));
+  hipLaunchKernelGGL(k_int8_t_times_f64, grid, dim3(256), 0, s, A, rows, cols, lda, Y, r, ldy, B,
+                     ldb);
 }
 
 }  // namespace krr

@@ -809,7 +809,7 @@ KRR_DEV void convert_panel_body(const float *__restrict__ P32, float *__restrict
                                 const double *__restrict__ pnorm_part,
                                 const float *__restrict__ pmax_part, int parts,
                                 float *__restrict__ pnorm, int *__restrict__ pexp8, int k, int nb,
-                                int chunks, int need16, int need8, int64_t bid) {
+                                int chunks, int need16, int need8, int scale8, int64_t bid) {
   const int64_t t = bid / chunks;
   const int ch = (int)(bid % chunks);
   const int64_t i = k + 1 + t;
@@ -827,7 +827,7 @@ KRR_DEV void convert_panel_body(const float *__restrict__ P32, float *__restrict
     }
   }
   const float mx = smx[0];
-  const float s8 = pow2_scale(mx, 448.0f);
+  const float s8 = scale8 ? pow2_scale(mx, 448.0f) : 1.0f;
   const int64_t te = (int64_t)nb * nb;
   const float *src = P32 + t * te;
   float *dstL = Astore + (i * (i + 1) / 2 + k) * te;
@@ -859,12 +859,12 @@ __global__ __launch_bounds__(256) void k_convert_panel(
     const float *__restrict__ P32, float *__restrict__ Astore, _Float16 *__restrict__ P16,
     uint8_t *__restrict__ P8, const double *__restrict__ pnorm_part,
     const float *__restrict__ pmax_part, int parts, float *__restrict__ pnorm,
-    int *__restrict__ pexp8, int k, int nb, int chunks, int need16, int need8) {
+    int *__restrict__ pexp8, int k, int nb, int chunks, int need16, int need8, int scale8) {
   convert_panel_body(P32, Astore, P16, P8, pnorm_part, pmax_part, parts, pnorm, pexp8, k, nb,
-                     chunks, need16, need8, blockIdx.x);
+                     chunks, need16, need8, scale8, blockIdx.x);
 }
 
-void launch_convert_panel(float *Astore, int k, const TileLayout &L, FactorWork &w,
+void launch_convert_panel(float *Astore, int k, const TileLayout &L, FactorWork &w, bool scale8,
                           const PanelBuf &pb, bool need16, bool need8, hipStream_t s) {
   const int64_t tiles = L.nt - 1 - k;
   if (tiles <= 0) return;
@@ -872,7 +872,7 @@ void launch_convert_panel(float *Astore, int k, const TileLayout &L, FactorWork 
   hipLaunchKernelGGL(k_convert_panel, dim3((unsigned)(tiles * chunks)), dim3(256), 0, s, pb.P32,
                      Astore, pb.P16, pb.P8, w.pnorm_part, w.pmax_part, trsm_parts(L.nb), pb.pnorm,
                      pb.pexp8,
-                     k, L.nb, chunks, need16 ? 1 : 0, need8 ? 1 : 0);
+                     k, L.nb, chunks, need16 ? 1 : 0, need8 ? 1 : 0, scale8 ? 1 : 0);
 }
 
 // Trailing update by a group of consecutive panels k0 .. k0+npan-1:
@@ -949,9 +949,9 @@ struct SegSrc {
 // the sub-blocks of one tile share an XCD.
 template <class S, bool DIAG>
 KRR_DEV void update_body(float *__restrict__ Astore, const PanelSet &ps, int k0, int npan, int jlo,
-                         int jhi, int NT, int nb, int SB, int mode, int allow16, int allow8,
-                         int high_panels, int fixed_prec, double thr, uint8_t *__restrict__ pmap,
-                         int64_t ntiles_all, int64_t blk, int64_t nblk) {
+                         int jhi, int NT, int nb, int SB, const UpdatePolicy &pol,
+                         uint8_t *__restrict__ pmap, int64_t ntiles_all, int64_t blk,
+                         int64_t nblk) {
   constexpr int BM = S::kBM;
   extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
   __shared__ SegTable tab;
@@ -993,17 +993,28 @@ KRR_DEV void update_body(float *__restrict__ Astore, const PanelSet &ps, int k0,
     const int q = threadIdx.x, k = k0 + q;
     const int64_t a = i - k - 1, b = j - k - 1;
     int prec = KRR_PREC_FP32;
-    if (i != j && k >= high_panels) {
-      if (mode == KRR_POLICY_FIXED) {
-        prec = fixed_prec;
-      } else if (mode == KRR_POLICY_ADAPTIVE) {
-        const double prod = (double)ps.pnorm[q][a] * (double)ps.pnorm[q][b];
-        if (allow8 && 0.0625 * prod <= thr)
+    if (i != j && pol.mode == KRR_POLICY_FIXED_MAP) {
+      prec = pol.fmap[(int64_t)k * ntiles_all + i * (i + 1) / 2 + j];
+      prec = prec > KRR_PREC_FP8 ? KRR_PREC_FP32 : prec;
+    } else if (i != j && k >= pol.high_panels) {
+      if (pol.mode == KRR_POLICY_FIXED) {
+        prec = pol.fixed_prec;
+      } else if (pol.mode == KRR_POLICY_ADAPTIVE) {
+        // operand rule u_p ||L_ik|| ||L_jk|| <= thr, tile rule u_p ||A_ij|| <= thr,
+        // or the lower precision of the two (the tile rule as a ceiling)
+        double prod = (double)ps.pnorm[q][a] * (double)ps.pnorm[q][b];
+        if (pol.rule == KRR_RULE_TILE) prod = pol.tnorm[i * (i + 1) / 2 + j];
+        else if (pol.rule == KRR_RULE_BOTH) prod = fmax(prod, pol.tnorm[i * (i + 1) / 2 + j]);
+        if (pol.allow8 && 0.0625 * prod <= pol.thr)
           prec = KRR_PREC_FP8;
-        else if (allow16 && 0.00048828125 * prod <= thr)
+        else if (pol.allow16 && 0.00048828125 * prod <= pol.thr)
           prec = KRR_PREC_FP16;
       }
     }
+    // precisions the attempt still allows (promotion): globally, then per panel
+    if (prec == KRR_PREC_FP8 && !pol.allow8) prec = KRR_PREC_FP16;
+    if (prec == KRR_PREC_FP16 && !pol.allow16) prec = KRR_PREC_FP32;
+    if (pol.pcap && prec > (int)pol.pcap[k]) prec = pol.pcap[k];
     const int64_t ra = a * te + (int64_t)si * BM * nb, rb = b * te + (int64_t)sj * BM * nb;
     if (prec == KRR_PREC_FP32) {
       qa[q] = (uint64_t)(ps.P32[q] + ra);
@@ -1075,10 +1086,9 @@ KRR_DEV void update_body(float *__restrict__ Astore, const PanelSet &ps, int k0,
 template <class S, bool DIAG>
 __global__ __launch_bounds__(S::THREADS) void k_update(
     float *__restrict__ Astore, PanelSet ps, int k0, int npan, int jlo, int jhi, int NT, int nb,
-    int SB, int mode, int allow16, int allow8, int high_panels, int fixed_prec, double thr,
-    uint8_t *__restrict__ pmap, int64_t ntiles_all) {
-  update_body<S, DIAG>(Astore, ps, k0, npan, jlo, jhi, NT, nb, SB, mode, allow16, allow8,
-                       high_panels, fixed_prec, thr, pmap, ntiles_all, blockIdx.x, gridDim.x);
+    int SB, UpdatePolicy pol, uint8_t *__restrict__ pmap, int64_t ntiles_all) {
+  update_body<S, DIAG>(Astore, ps, k0, npan, jlo, jhi, NT, nb, SB, pol, pmap, ntiles_all,
+                       blockIdx.x, gridDim.x);
 }
 
 void launch_update(float *Astore, int k0, int npan, int jlo, int jhi, const TileLayout &L,
@@ -1117,8 +1127,7 @@ void launch_update(float *Astore, int k0, int npan, int jlo, int jhi, const Tile
     const int64_t blocks = (int64_t)(jhi - jlo + 1) * SB * (SB + 1) / 2;
     hipLaunchKernelGGL((k_update<UpdDiag64, true>), dim3((unsigned)blocks),
                        dim3(UpdDiag64::THREADS), UpdDiag64::LDS_BYTES, s, Astore, ps, k0,
-                       npan, jlo, jhi, NT, L.nb, SB, pol.mode, pol.allow16, pol.allow8,
-                       pol.high_panels, pol.fixed_prec, pol.thr, pmap, L.ntiles());
+                       npan, jlo, jhi, NT, L.nb, SB, pol, pmap, L.ntiles());
   }
   if (which == UPD_DIAG) return;
   if (offdiag > 0 && offdiag * 4 < 8 * 256) {
@@ -1128,15 +1137,13 @@ void launch_update(float *Astore, int k0, int npan, int jlo, int jhi, const Tile
     const int64_t blocks = offdiag * SB * SB;
     hipLaunchKernelGGL((k_update<UpdDiagStream, false>), dim3((unsigned)blocks),
                        dim3(UpdDiagStream::THREADS), UpdDiagStream::LDS_BYTES, s, Astore, ps, k0,
-                       npan, jlo, jhi, NT, L.nb, SB, pol.mode, pol.allow16, pol.allow8,
-                       pol.high_panels, pol.fixed_prec, pol.thr, pmap, L.ntiles());
+                       npan, jlo, jhi, NT, L.nb, SB, pol, pmap, L.ntiles());
   } else if (offdiag > 0) {
     const int SB = L.nb / UpdStream::kBM;
     const int64_t blocks = offdiag * SB * SB;
     hipLaunchKernelGGL((k_update<UpdStream, false>), dim3((unsigned)blocks), dim3(UpdStream::THREADS),
                        UpdStream::LDS_BYTES, s, Astore, ps, k0, npan, jlo, jhi, NT, L.nb, SB,
-                       pol.mode, pol.allow16, pol.allow8, pol.high_panels, pol.fixed_prec, pol.thr,
-                       pmap, L.ntiles());
+                       pol, pmap, L.ntiles());
   }
 }
 
@@ -1190,12 +1197,12 @@ __global__ __launch_bounds__(256) void k_trsm_panel_b(const FactorJob *__restric
 
 __global__ __launch_bounds__(256) void k_convert_panel_b(const FactorJob *__restrict__ jobs, int k,
                                                          int nb, int chunks, int parts, int need16,
-                                                         int need8, int g) {
+                                                         int need8, int scale8, int g) {
   const FactorJob &j = jobs[blockIdx.y];
   if (k + 1 >= j.nt || (int64_t)(blockIdx.x / chunks) >= j.nt - 1 - k) return;
   const int sl = slot_of(k, g);
   convert_panel_body(j.P32[sl], j.Lst, j.P16[sl], j.P8[sl], j.pnorm_part, j.pmax_part, parts,
-                     j.pnorm[sl], j.pexp8[sl], k, nb, chunks, need16, need8, blockIdx.x);
+                     j.pnorm[sl], j.pexp8[sl], k, nb, chunks, need16, need8, scale8, blockIdx.x);
 }
 
 // Tile inverse of diagonal tile k (and L_kk, inv(L_kk) into the factor
@@ -1284,8 +1291,7 @@ __host__ __device__ inline int64_t update_extent(int nt, int k, bool group, int 
 template <class S, bool DIAG>
 __global__ __launch_bounds__(S::THREADS) void k_update_b(const FactorJob *__restrict__ jobs, int k0,
                                                          int group, int g, int nb, int SB,
-                                                         int mode, int allow16, int allow8,
-                                                         int high_panels, int fixed_prec) {
+                                                         UpdatePolicy pol) {
   const FactorJob &j = jobs[blockIdx.y];
   int kf, npan, jlo, jhi;
   const int64_t nblk = update_extent(j.nt, k0, group != 0, g, SB, DIAG, kf, npan, jlo, jhi);
@@ -1299,13 +1305,16 @@ __global__ __launch_bounds__(S::THREADS) void k_update_b(const FactorJob *__rest
     ps.pnorm[q] = j.pnorm[sl];
     ps.pexp8[q] = j.pexp8[sl];
   }
-  update_body<S, DIAG>(j.Lst, ps, kf, npan, jlo, jhi, j.nt, nb, SB, mode, allow16, allow8,
-                       high_panels, fixed_prec, j.thr, j.pmap, j.ntiles, blockIdx.x, nblk);
+  pol.thr = j.thr;
+  pol.tnorm = j.tnorm;
+  update_body<S, DIAG>(j.Lst, ps, kf, npan, jlo, jhi, j.nt, nb, SB, pol, j.pmap, j.ntiles,
+                       blockIdx.x, nblk);
 }
 
 template <typename T>
 static void factor_lockstep_t(const FactorJob *jobs, const int *nts, int nj, int nb, int g,
-                              const UpdatePolicy &pol, bool need16, bool need8, hipStream_t s) {
+                              const UpdatePolicy &pol, bool need16, bool need8, bool scale8,
+                              hipStream_t s) {
   const int NB = nb / BS, parts = trsm_parts(nb);
   const int chunks = (int)((int64_t)nb * nb / CONV_CHUNK_B);
   int ntmax = 0;
@@ -1336,20 +1345,17 @@ static void factor_lockstep_t(const FactorJob *jobs, const int *nts, int nj, int
     if (md > 0)
       hipLaunchKernelGGL((k_update_b<UpdDiag64, true>), dim3((unsigned)md, nj),
                          dim3(UpdDiag64::THREADS), UpdDiag64::LDS_BYTES, s, jobs, k0,
-                         group ? 1 : 0, g, nb, SB64, pol.mode, pol.allow16, pol.allow8,
-                         pol.high_panels, pol.fixed_prec);
+                         group ? 1 : 0, g, nb, SB64, pol);
     if (mo <= 0) return;
     if (so * 4 < 8 * 256) {
       mo_small = mo * SBd * SBd;
       hipLaunchKernelGGL((k_update_b<UpdDiagStream, false>), dim3((unsigned)mo_small, nj),
                          dim3(UpdDiagStream::THREADS), UpdDiagStream::LDS_BYTES, s, jobs, k0,
-                         group ? 1 : 0, g, nb, SBd, pol.mode, pol.allow16, pol.allow8,
-                         pol.high_panels, pol.fixed_prec);
+                         group ? 1 : 0, g, nb, SBd, pol);
     } else {
       hipLaunchKernelGGL((k_update_b<UpdStream, false>), dim3((unsigned)(mo * SBo * SBo), nj),
                          dim3(UpdStream::THREADS), UpdStream::LDS_BYTES, s, jobs, k0,
-                         group ? 1 : 0, g, nb, SBo, pol.mode, pol.allow16, pol.allow8,
-                         pol.high_panels, pol.fixed_prec);
+                         group ? 1 : 0, g, nb, SBo, pol);
     }
   };
   for (int G0 = 0; G0 < ntmax; G0 += g) {
@@ -1380,7 +1386,7 @@ static void factor_lockstep_t(const FactorJob *jobs, const int *nts, int nj, int
                            dim3(256), 0, s, jobs, k, nb, parts, g);
         hipLaunchKernelGGL(k_convert_panel_b, dim3((unsigned)((int64_t)(ntmax - 1 - k) * chunks), nj),
                            dim3(256), 0, s, jobs, k, nb, chunks, parts, need16 ? 1 : 0,
-                           need8 ? 1 : 0, g);
+                           need8 ? 1 : 0, scale8 ? 1 : 0, g);
       }
       update(k, false);
     }
@@ -1390,11 +1396,11 @@ static void factor_lockstep_t(const FactorJob *jobs, const int *nts, int nj, int
 
 void launch_factor_lockstep(const FactorJob *jobs, const int *nts, int njobs, int nb, int g,
                             const UpdatePolicy &pol, bool fp64, bool need16, bool need8,
-                            hipStream_t s) {
+                            bool scale8, hipStream_t s) {
   if (fp64)
-    factor_lockstep_t<double>(jobs, nts, njobs, nb, g, pol, need16, need8, s);
+    factor_lockstep_t<double>(jobs, nts, njobs, nb, g, pol, need16, need8, scale8, s);
   else
-    factor_lockstep_t<float>(jobs, nts, njobs, nb, g, pol, need16, need8, s);
+    factor_lockstep_t<float>(jobs, nts, njobs, nb, g, pol, need16, need8, scale8, s);
 }
 
 // Updates per operand precision, from the precision map (255 = no update).

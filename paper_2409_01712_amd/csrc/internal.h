@@ -71,15 +71,43 @@ void launch_tile_norms_batched(const BuildJob *jobs, int njobs, int64_t max_ntil
 void launch_exp_table(double *tab, int64_t len, double gamma, hipStream_t s);
 void launch_row_norms(const int8_t *G, int64_t n, int64_t rows_padded, int64_t m, int64_t ldg,
                       int32_t *nrm, int32_t *flag, hipStream_t s);
+// How a stored integer becomes the kernel value: the exponential of the
+// distance (Gaussian), a table of the distance (IBS), the integer itself
+// (linear kernel: the stored integer is the inner product, not a distance).
+enum { VAL_EXP = 0, VAL_TABLE = 1, VAL_LINEAR = 2 };
+// vmode: VAL_*; Ec: FP64 confounder factors in the packed tile layout, or null.
 void launch_gram_tiles(const int8_t *G, int64_t m, int64_t ldg, const int32_t *nrm,
                        const double *etab, int64_t etab_len, double lambda, const TileLayout &L,
-                       int32_t *D, float *A, double *tnorm_part, hipStream_t s);
+                       int32_t *D, float *A, double *tnorm_part, int vmode,
+                       const double *Ec, hipStream_t s);
 void launch_tile_norms(const double *part, int parts, int64_t ntiles, double *tnorm, hipStream_t s);
 void launch_expand_tiles(const int32_t *D, const double *etab, int64_t etab_len, double lambda,
-                         const TileLayout &L, float *A, hipStream_t s);
+                         int vmode, const double *Ec, const TileLayout &L, float *A,
+                         hipStream_t s);
+// At (cols x ldt) = A^T with zero padding columns; B = A^T Y in FP64 (A int8
+// rows x cols row-major, Y and B column-major).
+void launch_transpose_i8(const int8_t *A, int64_t rows, int64_t cols, int64_t lda, int8_t *At,
+                         int64_t ldt, hipStream_t s);
+void launch_int8_t_times_f64(const int8_t *A, int64_t rows, int64_t cols, int64_t lda,
+                             const double *Y, int r, int64_t ldy, double *B, int64_t ldb,
+                             hipStream_t s);
+// IBS kernel: table (2m - d) / (2m), and the thermometer encoding of genotype
+// rows (H: rows x ldh int8, ldh >= 2 * round_up(m, 16), a multiple of 16).
+void launch_ibs_table(double *tab, int64_t len, int64_t m, hipStream_t s);
+void launch_ibs_encode(const int8_t *G, int64_t rows, int64_t m, int64_t ldg, int8_t *H,
+                       int64_t ldh, hipStream_t s);
+// Confounder factors exp(-gamma ||c_i - c_j||^2) (FP64, q <= 32): packed lower
+// tiles of the training set, and test rows x training columns.
+constexpr int KRR_CONF_QMAX = 32;
+void launch_conf_factor(const double *C, int64_t n, int64_t q, int64_t ldc, double gamma,
+                        const TileLayout &L, double *Ec, hipStream_t s);
+void launch_conf_factor_cross(const double *Ct, int64_t rows, int64_t ldct, const double *C,
+                              int64_t n, int64_t q, int64_t ldc, double gamma, int64_t cols,
+                              double *Et, int64_t lde, hipStream_t s);
 void launch_cross_gram(const int8_t *T, int64_t nt_rows, const int32_t *nrm_t, const int8_t *G,
                        int64_t n, int64_t m, int64_t ldt, int64_t ldg, const int32_t *nrm_g,
-                       int64_t cols_padded, int32_t *Dt, int64_t ldd, hipStream_t s);
+                       int64_t cols_padded, int32_t *Dt, int64_t ldd, bool linear,
+                       hipStream_t s);
 void launch_copy_tiles_i32(const int32_t *D, const TileLayout &L, int64_t i0, int64_t j0,
                            int64_t rows, int64_t cols, int32_t *dst, int64_t ld, hipStream_t s);
 void launch_copy_tiles_f32(const float *A, const TileLayout &L, int64_t i0, int64_t j0,
@@ -92,7 +120,11 @@ struct UpdatePolicy {
   int allow16, allow8;
   int high_panels;
   int fixed_prec;
+  int rule;          // KRR_RULE_* (ADAPTIVE)
   double thr;        // eps * ||A||_F / NT
+  const uint8_t *fmap = nullptr;  // FIXED_MAP: precision per (panel, tile), device
+  const uint8_t *pcap = nullptr;  // lowest precision allowed per panel (promotion), or null
+  const double *tnorm = nullptr;  // per-tile ||A_IJ||_F of the build (KRR_RULE_TILE / BOTH)
 };
 // Operand copies of one panel (tiles k+1 .. nt-1 of block column k).  Two
 // are kept so that panel k+1 can be produced while panel k is still read.
@@ -145,6 +177,7 @@ struct FactorJob {
   uint8_t *pmap;
   int64_t ntiles;
   double thr;  // eps * ||A||_F / nt
+  const double *tnorm;  // the build's tile norms (tile precision rule)
   int nt;
 };
 // The single-stream tile Cholesky (substitution TRSM, grouped updates of g
@@ -156,7 +189,7 @@ struct FactorJob {
 // counts; pol.thr is taken per instance from the table.
 void launch_factor_lockstep(const FactorJob *jobs, const int *nts, int njobs, int nb, int g,
                             const UpdatePolicy &pol, bool fp64, bool need16, bool need8,
-                            hipStream_t s);
+                            bool scale8, hipStream_t s);
 // Diagonal tile k: L_kk = chol(A_kk - sum_q P_q P_q^T) into the work's
 // factor store (tile k), with the inverses of its 64 x 64 diagonal blocks.
 void launch_potrf_tile(float *Akk, int k, const TileLayout &L, bool fp64, FactorWork &w,
@@ -176,7 +209,7 @@ void launch_trsm_subst(const float *Astore, int k, const TileLayout &L, bool fp6
                        const PanelBuf &pb, int t_lo, int t_hi, hipStream_t s);
 void launch_trsm_gemm(const float *Astore, const float *Linv_k, int k, const TileLayout &L,
                       FactorWork &w, const PanelBuf &pb, int t_lo, int t_hi, hipStream_t s);
-void launch_convert_panel(float *Astore, int k, const TileLayout &L, FactorWork &w,
+void launch_convert_panel(float *Astore, int k, const TileLayout &L, FactorWork &w, bool scale8,
                           const PanelBuf &pb, bool need16, bool need8, hipStream_t s);
 // Trailing update of the tiles (i, j), jlo <= j <= jhi, j <= i, by the npan
 // consecutive panels k0 .. k0+npan-1 whose operand copies are *pbs[q].
@@ -204,9 +237,14 @@ void launch_bwd_sweep(const float *Astore, const float *Linv, const float *C, co
 int residual_split(const TileLayout &L);
 // the same for the lockstep batch (at most residual_split)
 int residual_split_batched(const TileLayout &L);
+// vmode: VAL_* (VAL_EXP factors the exponential when gamma allows); Ec: FP64
+// confounder factors (packed like D) multiplied into every entry, or null.
+// nsplit: tile-column ranges summed in fixed order (clamped to 1 .. nt); part
+// holds nsplit * np * r doubles.
 void launch_residual(const int32_t *D, const double *etab, int64_t etab_len, double gamma,
-                     double lambda, const TileLayout &L, int r, const double *X, const double *Y,
-                     double *R, double *part, hipStream_t s);
+                     int vmode, const double *Ec, double lambda, const TileLayout &L, int r,
+                     const double *X, const double *Y, double *R, double *part, int nsplit,
+                     hipStream_t s);
 // Batched (lockstep over a table of instances, tile counts up to ntmax):
 // both sweeps, L Z = B then L^T X = Z.
 void launch_sweeps_batched(const SolveJob *jobs, int njobs, int ntmax, int nb, int r,
@@ -245,9 +283,11 @@ void launch_pcg_step(double *x, double *res, const double *p, const double *nq, 
                      const double *pnq, int64_t count, int r, hipStream_t s);
 void launch_pcg_dir(double *p, const double *z, const double *rho_new, const double *rho_old,
                     int64_t count, int r, hipStream_t s);
+// Et (or null): factors multiplied into the entries, row-major like Dt;
+// linear: Dt holds inner products, which are the values.
 void launch_predict_apply(const int32_t *Dt, int64_t rows, int64_t cols, int64_t ldd,
                           const double *etab, int64_t etab_len, const double *X, int r, double *P,
-                          int64_t ldp, hipStream_t s);
+                          int64_t ldp, const double *Et, bool linear, hipStream_t s);
 void launch_fill_f64(double *p, int64_t count, double v, hipStream_t s);
 void launch_fill_i32(int32_t *p, int64_t count, int32_t v, hipStream_t s);
 void launch_fill_u8(uint8_t *p, int64_t count, uint8_t v, hipStream_t s);

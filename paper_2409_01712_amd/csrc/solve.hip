@@ -436,12 +436,15 @@ void launch_cols_f32_axpy_rows_f64(const float *src, int64_t np, int r, double a
 // acc[16 rows x 16 NCB cols] += sum_j exp(-gamma d(row, j)) X[j, cols].
 // DMODE 0: d(row, j) = D[row * ldd + j] (row-major block)
 // DMODE 1: d(row, j) = D[j * ldd + row] (transposed block)
-template <int DMODE, int NCB>
+// E (or null): factors multiplied into the kernel entries, laid out as D
+// (DMODE 0 only).
+template <int DMODE, int NCB, bool LIN = false>
 __device__ __forceinline__ void exp_mfma_block(const int32_t *__restrict__ D, int64_t ldd, int row,
                                                int64_t j0, int64_t jn, const double *__restrict__ etab,
                                                int64_t emax, const double *__restrict__ X, int r,
                                                int64_t xrow0, int col0, int li, int lg,
-                                               v4d (&acc)[NCB]) {
+                                               v4d (&acc)[NCB],
+                                               const double *__restrict__ E = nullptr) {
   // j advances 64 at a time (the ranges are multiples of 64): the distance
   // loads and table lookups of four 16-wide steps are issued before their MFMAs.
   for (int64_t q = j0; q < jn; q += 64) {
@@ -461,7 +464,18 @@ __device__ __forceinline__ void exp_mfma_block(const int32_t *__restrict__ D, in
 #pragma unroll
     for (int u = 0; u < 4; ++u)
 #pragma unroll
-      for (int e = 0; e < 4; ++e) a[u][e] = etab[min((int64_t)max(d[u][e], 0), emax)];
+      for (int e = 0; e < 4; ++e)
+        a[u][e] = LIN ? (double)d[u][e] : etab[min((int64_t)max(d[u][e], 0), emax)];
+    if (DMODE == 0 && E) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const double4 f = *(const double4 *)(E + (int64_t)row * ldd + q + 16 * u + 4 * lg);
+        a[u][0] *= f.x;
+        a[u][1] *= f.y;
+        a[u][2] *= f.z;
+        a[u][3] *= f.w;
+      }
+    }
 #pragma unroll
     for (int c = 0; c < NCB; ++c) {
       const int col = col0 + c * 16 + li;
@@ -501,22 +515,27 @@ constexpr int RES_HI_MAX = 2048;   // entries of the LDS table
 // transposed.  Per 64-column step the 64 rows of X it multiplies are staged
 // once in LDS for the four waves (double-buffered), and the next step's
 // distances and X rows are in flight during the current step's MFMAs.
-// FACT: exp(-gamma d) factored with W = 2^wshift; otherwise the FP64 table in
-// memory (one gather per entry).
-template <int NCB, bool FACT>
+// The exponential is factored with W = 2^wshift (VM 1), or read from the FP64
+// table in memory (VM 0, one gather per entry).
+// VM: how a stored integer becomes the FP64 kernel value -- 0 the table
+// etab[d], 1 the factored exponential above, 2 the integer itself (linear
+// kernel).  CONF: every kernel entry times its FP64 confounder factor Ec (the
+// same packed layout as D), loaded beside the distance.
+template <int NCB, int VM, bool CONF = false>
 __device__ __forceinline__ void residual_body(const int32_t *__restrict__ D,
                                               const double *__restrict__ etab, int64_t etab_len,
                                               double gamma, int wshift, int64_t np, int nb, int NT,
                                               int r, const double *__restrict__ X,
                                               double *__restrict__ part, int64_t bx, int by,
-                                              int bz, int nz) {
+                                              int bz, int nz,
+                                              const double *__restrict__ Ec = nullptr) {
   constexpr int XC = 16 * NCB, XLD = XC + 2, XPT = XC / 4;  // X values per thread and step
   __shared__ double ehi[RES_HI_MAX];
   __shared__ double xs[2][64 * XLD];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, lg = lane >> 4;
   const int64_t dmax = etab_len - 1;
-  if (FACT) {
+  if (VM == 1) {
     const int nhi = (int)(dmax >> wshift) + 2;
     for (int q = tid; q < nhi; q += 256) ehi[q] = exp(-gamma * (double)((int64_t)q << wshift));
   }
@@ -542,6 +561,18 @@ __device__ __forceinline__ void residual_body(const int32_t *__restrict__ D,
 #pragma unroll
       for (int e = 0; e < 4; ++e) d[u][e] = b[(int64_t)(16 * u + e) * sc];
   };
+  // the confounder factors of the same entries
+  auto fetch_e = [&](int st, double (&f)[4][4]) {
+    const int J = st / spt, q = (st % spt) * 64;
+    const bool dir = J <= I;
+    const int64_t tb = tri_index(dir ? I : J, dir ? J : I) * te;
+    const int64_t sr = dir ? nb : 1, sc = dir ? 1 : nb;
+    const double *b = Ec + tb + (int64_t)(rloc + li) * sr + (int64_t)(q + 4 * lg) * sc;
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) f[u][e] = b[(int64_t)(16 * u + e) * sc];
+  };
   // element v of this thread: row (tid + 256 v) / XC, column (tid + 256 v) % XC
   auto fetch_x = [&](int st, double (&x)[XPT]) {
     const int64_t xr0 = (int64_t)(st / spt) * nb + (st % spt) * 64;
@@ -559,10 +590,11 @@ __device__ __forceinline__ void residual_body(const int32_t *__restrict__ D,
       xs[buf][(e / XC) * XLD + e % XC] = x[v];
     }
   };
-  const int32_t half = FACT ? (1 << wshift) >> 1 : 0;
+  const int32_t half = VM == 1 ? (1 << wshift) >> 1 : 0;
   auto kexp = [&](int32_t d) -> double {
+    if (VM == 2) return (double)d;
     const int32_t dd = (int32_t)min((int64_t)max(d, 0), dmax);
-    if (!FACT) return etab[dd];
+    if (VM == 0) return etab[dd];
     const int32_t h = (dd + half) >> wshift;
     const double x = gamma * (double)((h << wshift) - dd);
     double p = 1.0 / 5040.0;  // 1 / RES_DEG!
@@ -582,25 +614,32 @@ __device__ __forceinline__ void residual_body(const int32_t *__restrict__ D,
   // two register sets for the distances, used alternately (no copies between
   // steps): step st computes with one while the other receives step st + 1
   int32_t da[4][4], db[4][4];
+  double ea[CONF ? 4 : 1][4], eb[CONF ? 4 : 1][4];
   double xv[XPT];
   if (st0 < nsteps) {
     fetch_d(st0, da);
+    if constexpr (CONF) fetch_e(st0, ea);
     fetch_x(st0, xv);
     store_x(0, xv);
   }
   __syncthreads();  // the table and the first X block
   int cur = 0;
-  auto step = [&](int st, const int32_t (&dc)[4][4], int32_t (&dn)[4][4]) {
+  auto step = [&](int st, const int32_t (&dc)[4][4], int32_t (&dn)[4][4],
+                  const double (&ec)[CONF ? 4 : 1][4], double (&en)[CONF ? 4 : 1][4]) {
     const bool more = st + 1 < nsteps;
     if (more) {  // X first: storing it to LDS at the end of the step waits on it alone
       fetch_x(st + 1, xv);
       fetch_d(st + 1, dn);
+      if constexpr (CONF) fetch_e(st + 1, en);
     }
     double a[4][4];
 #pragma unroll
     for (int u = 0; u < 4; ++u)
 #pragma unroll
-      for (int e = 0; e < 4; ++e) a[u][e] = kexp(dc[u][e]);
+      for (int e = 0; e < 4; ++e) {
+        a[u][e] = kexp(dc[u][e]);
+        if constexpr (CONF) a[u][e] *= ec[u][e];
+      }
     const double *xb = xs[cur];
 #pragma unroll
     for (int c = 0; c < NCB; ++c)
@@ -620,8 +659,8 @@ __device__ __forceinline__ void residual_body(const int32_t *__restrict__ D,
     cur ^= 1;
   };
   for (int st = st0; st < nsteps; st += 2) {
-    step(st, da, db);
-    if (st + 1 < nsteps) step(st + 1, db, da);
+    step(st, da, db, ea, eb);
+    if (st + 1 < nsteps) step(st + 1, db, da, eb, ea);
   }
   const int64_t g0 = r0 + wave * 16;
   double *P = part + (int64_t)bz * np * r;
@@ -634,21 +673,22 @@ __device__ __forceinline__ void residual_body(const int32_t *__restrict__ D,
   }
 }
 
-template <int NCB, bool FACT>
+template <int NCB, int VM, bool CONF>
 __global__ __launch_bounds__(256) void k_residual(const int32_t *__restrict__ D,
                                                   const double *__restrict__ etab,
                                                   int64_t etab_len, double gamma, int wshift,
                                                   int64_t np, int nb, int NT, int r,
                                                   const double *__restrict__ X,
-                                                  double *__restrict__ part) {
-  residual_body<NCB, FACT>(D, etab, etab_len, gamma, wshift, np, nb, NT, r, X, part, blockIdx.x,
-                           blockIdx.y, blockIdx.z, gridDim.z);
+                                                  double *__restrict__ part,
+                                                  const double *__restrict__ Ec) {
+  residual_body<NCB, VM, CONF>(D, etab, etab_len, gamma, wshift, np, nb, NT, r, X, part,
+                                 blockIdx.x, blockIdx.y, blockIdx.z, gridDim.z, Ec);
 }
 
 // All instances of a batch in one launch: blockIdx.x runs over the row
 // blocks of every instance (the job owning it found by its first block),
 // blockIdx.z over the column split, cut to the instance's own split.
-template <int NCB, bool FACT>
+template <int NCB, int VM>
 __global__ __launch_bounds__(256) void k_residual_b(const SolveJob *__restrict__ jobs, int njobs,
                                                     int nb, int r) {
   int lo = 0, hi = njobs - 1;
@@ -660,7 +700,7 @@ __global__ __launch_bounds__(256) void k_residual_b(const SolveJob *__restrict__
   const SolveJob &j = jobs[lo];
   const int nz = j.nt < 4 ? j.nt : 4;  // residual_split_batched
   if ((int)blockIdx.z >= nz) return;
-  residual_body<NCB, FACT>(j.D, j.etab, j.etab_len, j.gamma, j.wshift, j.np, nb, j.nt, r, j.Xd,
+  residual_body<NCB, VM>(j.D, j.etab, j.etab_len, j.gamma, j.wshift, j.np, nb, j.nt, r, j.Xd,
                            j.part, (int64_t)blockIdx.x - j.rb0, blockIdx.y, blockIdx.z, nz);
 }
 
@@ -698,16 +738,16 @@ void launch_residual_batched(const SolveJob *jobs, int njobs, int64_t rblocks, b
                              int r, hipStream_t s) {
   const int ncb = (r + 15) / 16;
   const dim3 grid((unsigned)rblocks, ncb <= 2 ? 1u : (unsigned)((r + 63) / 64), 4);
-#define KRR_RESB(NCB, FACT)                                                                    \
-  hipLaunchKernelGGL((k_residual_b<NCB, FACT>), grid, dim3(256), 0, s, jobs, njobs, nb, r)
+#define KRR_RESB(NCB, VM)                                                                    \
+  hipLaunchKernelGGL((k_residual_b<NCB, VM>), grid, dim3(256), 0, s, jobs, njobs, nb, r)
   if (fact) {
-    if (ncb <= 1) KRR_RESB(1, true);
-    else if (ncb <= 2) KRR_RESB(2, true);
-    else KRR_RESB(4, true);
+    if (ncb <= 1) KRR_RESB(1, 1);
+    else if (ncb <= 2) KRR_RESB(2, 1);
+    else KRR_RESB(4, 1);
   } else {
-    if (ncb <= 1) KRR_RESB(1, false);
-    else if (ncb <= 2) KRR_RESB(2, false);
-    else KRR_RESB(4, false);
+    if (ncb <= 1) KRR_RESB(1, 0);
+    else if (ncb <= 2) KRR_RESB(2, 0);
+    else KRR_RESB(4, 0);
   }
 #undef KRR_RESB
 }
@@ -721,24 +761,32 @@ void launch_residual_sum(const double *part, int nsplit, const TileLayout &L, in
 }
 
 void launch_residual(const int32_t *D, const double *etab, int64_t etab_len, double gamma,
-                     double lambda, const TileLayout &L, int r, const double *X, const double *Y,
-                     double *R, double *part, hipStream_t s) {
+                     int vmode, const double *Ec, double lambda, const TileLayout &L, int r,
+                     const double *X, const double *Y, double *R, double *part, int nsplit,
+                     hipStream_t s) {
   const unsigned rb = (unsigned)(L.np / 64);
-  const int ncb = (r + 15) / 16, z = residual_split(L);
-  const int ws = residual_wshift(gamma, etab_len - 1);
+  const int ncb = (r + 15) / 16, z = std::max(1, std::min(nsplit, L.nt));
+  const int ws = vmode == VAL_EXP ? residual_wshift(gamma, etab_len - 1) : -1;
   const dim3 grid(rb, ncb <= 2 ? 1u : (unsigned)((r + 63) / 64), z);
-#define KRR_RES(NCB, FACT)                                                                     \
-  hipLaunchKernelGGL((k_residual<NCB, FACT>), grid, dim3(256), 0, s, D, etab, etab_len, gamma, \
-                     ws, L.np, L.nb, L.nt, r, X, part)
-  if (ws >= 0) {
-    if (ncb <= 1) KRR_RES(1, true);
-    else if (ncb <= 2) KRR_RES(2, true);
-    else KRR_RES(4, true);
+#define KRR_RES(NCB, VM, CONF)                                                      \
+  hipLaunchKernelGGL((k_residual<NCB, VM, CONF>), grid, dim3(256), 0, s, D, etab, etab_len, \
+                     gamma, ws, L.np, L.nb, L.nt, r, X, part, Ec)
+#define KRR_RES2(VM, CONF)              \
+  do {                                     \
+    if (ncb <= 1) KRR_RES(1, VM, CONF);  \
+    else if (ncb <= 2) KRR_RES(2, VM, CONF); \
+    else KRR_RES(4, VM, CONF);           \
+  } while (0)
+  if (vmode == VAL_LINEAR) {
+    KRR_RES2(2, false);
+  } else if (Ec) {
+    if (ws >= 0) KRR_RES2(1, true);
+    else KRR_RES2(0, true);
   } else {
-    if (ncb <= 1) KRR_RES(1, false);
-    else if (ncb <= 2) KRR_RES(2, false);
-    else KRR_RES(4, false);
+    if (ws >= 0) KRR_RES2(1, false);
+    else KRR_RES2(0, false);
   }
+#undef KRR_RES2
 #undef KRR_RES
   const int64_t tot = L.np * r;
   hipLaunchKernelGGL(k_residual_sum, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, part, z,
@@ -748,13 +796,14 @@ void launch_residual(const int32_t *D, const double *etab, int64_t etab_len, dou
 // Predict: P[i, :] = sum_j exp(-gamma Dt[i, j]) X[j, :] in FP64 for a block of
 // test rows (Dt row-major rows x cols, cols a multiple of 16; X row-major
 // cols x r).  Output written column-major into P (leading dimension ldp).
-template <int NCB>
+template <int NCB, bool LIN>
 __global__ __launch_bounds__(256) void k_predict_apply(const int32_t *__restrict__ Dt, int64_t rows,
                                                        int64_t cols, int64_t ldd,
                                                        const double *__restrict__ etab,
                                                        int64_t etab_len,
                                                        const double *__restrict__ X, int r,
-                                                       double *__restrict__ P, int64_t ldp) {
+                                                       double *__restrict__ P, int64_t ldp,
+                                                       const double *__restrict__ Et) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int li = lane & 15, lg = lane >> 4;
   const int64_t g0 = (int64_t)blockIdx.x * 64 + wave * 16;
@@ -764,8 +813,8 @@ __global__ __launch_bounds__(256) void k_predict_apply(const int32_t *__restrict
   for (int c = 0; c < NCB; ++c) acc[c] = (v4d){0.0, 0.0, 0.0, 0.0};
   // rows past the end read row rows-1 (valid memory); their outputs are dropped
   const int64_t arow = min(g0 + li, rows - 1);
-  exp_mfma_block<0, NCB>(Dt + arow * ldd, ldd, 0, 0, cols, etab, etab_len - 1, X, r, 0, col0, li,
-                         lg, acc);
+  exp_mfma_block<0, NCB, LIN>(Dt + arow * ldd, ldd, 0, 0, cols, etab, etab_len - 1, X, r, 0, col0,
+                              li, lg, acc, Et ? Et + arow * ldd : nullptr);
 #pragma unroll
   for (int c = 0; c < NCB; ++c) {
     const int col = col0 + c * 16 + li;
@@ -780,18 +829,23 @@ __global__ __launch_bounds__(256) void k_predict_apply(const int32_t *__restrict
 
 void launch_predict_apply(const int32_t *Dt, int64_t rows, int64_t cols, int64_t ldd,
                           const double *etab, int64_t etab_len, const double *X, int r, double *P,
-                          int64_t ldp, hipStream_t s) {
+                          int64_t ldp, const double *Et, bool linear, hipStream_t s) {
   const unsigned rb = (unsigned)((rows + 63) / 64);
   const int ncb = (r + 15) / 16;
-  if (ncb <= 1)
-    hipLaunchKernelGGL(k_predict_apply<1>, dim3(rb, 1), dim3(256), 0, s, Dt, rows, cols, ldd, etab,
-                       etab_len, X, r, P, ldp);
-  else if (ncb <= 2)
-    hipLaunchKernelGGL(k_predict_apply<2>, dim3(rb, 1), dim3(256), 0, s, Dt, rows, cols, ldd, etab,
-                       etab_len, X, r, P, ldp);
-  else
-    hipLaunchKernelGGL(k_predict_apply<4>, dim3(rb, (unsigned)((r + 63) / 64)), dim3(256), 0, s,
-                       Dt, rows, cols, ldd, etab, etab_len, X, r, P, ldp);
+#define KRR_PA(NCB, LIN, GY)                                                                      \
+  hipLaunchKernelGGL((k_predict_apply<NCB, LIN>), dim3(rb, GY), dim3(256), 0, s, Dt, rows, cols, \
+                     ldd, etab, etab_len, X, r, P, ldp, Et)
+  const unsigned gy = (unsigned)((r + 63) / 64);
+  if (linear) {
+    if (ncb <= 1) KRR_PA(1, true, 1);
+    else if (ncb <= 2) KRR_PA(2, true, 1);
+    else KRR_PA(4, true, gy);
+  } else {
+    if (ncb <= 1) KRR_PA(1, false, 1);
+    else if (ncb <= 2) KRR_PA(2, false, 1);
+    else KRR_PA(4, false, gy);
+  }
+#undef KRR_PA
 }
 
 // ---------------------------------------------------------------------------

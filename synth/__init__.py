@@ -112,6 +112,20 @@ def ld_founders(m: int, frac: float, length: int, seed: int) -> np.ndarray:
     return np.sort(rng.choice(slots, size=nblocks, replace=False)) * length
 
 
+def confounders(n: int, q: int, seed: int, sd: float, row0: int = 0) -> np.ndarray:
+    """Real-valued covariates (n x q, float64, row-major) standing in for the
+    confounders of a cohort (principal components, age, sex and the like):
+    column 0 a binary indicator, the others N(0, sd^2), one seeded stream
+    per row so that any row block can be regenerated."""
+    out = np.empty((n, q), np.float64)
+    for i in range(n):
+        rng = np.random.default_rng([seed, 4, row0 + i])
+        v = rng.standard_normal(q) * sd
+        v[0] = sd * float(rng.integers(0, 2))
+        out[i] = v
+    return out
+
+
 def phenotypes(G: np.ndarray, r: int, n_pairs: int, n_add: int, seed: int,
                h2: float | None = None, noise_sd: float | None = None) -> np.ndarray:
     """Phenotype matrix Y (n x r, float64, column-major) with epistatic signal.

@@ -71,6 +71,11 @@ def test_invalid_arguments_rejected_on_host(lib):
     opts = krr.krr_options(300, 0, 0)
     assert lib.krr_create(ctypes.byref(h), 0, None, ctypes.byref(opts)) == \
         krr.KRR_ERROR_INVALID_VALUE
+    # an allocator without its free function (or the reverse) is rejected
+    opts = krr.krr_options(512, 0, 0)
+    opts.device_alloc = krr.KRR_ALLOC_FN(lambda b, u: None)
+    assert lib.krr_create(ctypes.byref(h), 0, None, ctypes.byref(opts)) == \
+        krr.KRR_ERROR_INVALID_VALUE
 
 
 def test_struct_layouts_match_header(tmp_path):
@@ -81,6 +86,8 @@ def test_struct_layouts_match_header(tmp_path):
         "krr_refine_opts": krr.krr_refine_opts,
         "krr_solve_info": krr.krr_solve_info,
         "krr_factor_info": krr.krr_factor_info,
+        "krr_kernel_desc": krr.krr_kernel_desc,
+        "krr_tuning": krr.krr_tuning,
     }
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "krr.h"', "int main(void){"]
     for name, cls in structs.items():
@@ -137,3 +144,36 @@ def test_noalloc_limits_on_host(lib):
         krr.KRR_ERROR_INVALID_VALUE
     assert lib.krr_predict_noalloc(None, None, None, 1, 16, None, 1, 1, None, 1) == \
         krr.KRR_ERROR_INVALID_VALUE
+
+
+def test_tuning_cache_round_trip(lib, tmp_path):
+    """The autotuner's cache file (host code, no GPU): entries are added and
+    replaced by key, survive a re-read, absent keys and files read as not found,
+    and malformed entries or invalid tunings are rejected."""
+    path = str(tmp_path / "tune.json")
+    assert krr.krr_tuning_cache_load(path, "k1") is None  # no file yet
+    a = {"tile": 512, "panel_group": 8, "residual_split": 8, "sweep_pairs": 1, "lookahead": 1}
+    b = {"tile": 256, "panel_group": 4, "residual_split": 16, "sweep_pairs": 0, "lookahead": -1}
+    krr.krr_tuning_cache_store(path, "gfx950|cu256|n32768|m65536|r16|mode1|d641|ref1", a, 85.25)
+    krr.krr_tuning_cache_store(path, "k2", b, 12.5)
+    assert krr.krr_tuning_cache_load(path, "gfx950|cu256|n32768|m65536|r16|mode1|d641|ref1") == \
+        (a, 85.25)
+    assert krr.krr_tuning_cache_load(path, "k2") == (b, 12.5)
+    krr.krr_tuning_cache_store(path, "k2", a, 10.0)  # replaced, the other kept
+    assert krr.krr_tuning_cache_load(path, "k2") == (a, 10.0)
+    assert krr.krr_tuning_cache_load(path, "k3") is None
+    import json
+    doc = json.load(open(path))  # the file is plain JSON
+    assert set(doc) == {"gfx950|cu256|n32768|m65536|r16|mode1|d641|ref1", "k2"}
+    assert doc["k2"]["ms"] == 10.0
+    bad = dict(a, tile=300)
+    with pytest.raises(krr.KRRError):
+        krr.krr_tuning_cache_store(path, "k4", bad, 1.0)
+    with open(path, "a") as f:
+        f.write('"k5": {"tile": 512, "panel_group": oops}\n')
+    with pytest.raises(krr.KRRError):
+        krr.krr_tuning_cache_load(path, "k5")
+    assert krr.krr_tuning_cache_load(path, "k2") == (a, 10.0)
+    # a tuning is validated before it reaches a context
+    t = krr.krr_tuning(300, 0, 0, -1, -1)
+    assert lib.krr_set_tuning(None, ctypes.byref(t)) == krr.KRR_ERROR_INVALID_VALUE
