@@ -62,7 +62,7 @@ class krr_kernel_desc(ctypes.Structure):
 class krr_tuning(ctypes.Structure):
     _fields_ = [("tile", ctypes.c_int32), ("panel_group", ctypes.c_int32),
                 ("residual_split", ctypes.c_int32), ("sweep_pairs", ctypes.c_int32),
-                ("lookahead", ctypes.c_int32)]
+                ("lookahead", ctypes.c_int32), ("aux_cu_quarters", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: int(getattr(self, f)) for f, _ in self._fields_}
@@ -108,6 +108,7 @@ _SIGS = [
     ("krr_noalloc_limits", _I, [_I64, _I64, _I64, ctypes.c_int32, ctypes.POINTER(_I64),
                                 ctypes.POINTER(ctypes.c_int32)]),
     ("krr_context_memory", _I, [_P, ctypes.POINTER(_I64), ctypes.POINTER(_I64)]),
+    ("krr_context_graphs", _I, [_P, ctypes.POINTER(_I64), ctypes.POINTER(_I64)]),
     ("krr_build_kernel_batched", _I, [_P, ctypes.c_int32, _P, _P, _I64, _P, _P, _P, _P]),
     ("krr_factor_batched", _I, [_P, ctypes.c_int32, _P, ctypes.POINTER(krr_precision_policy),
                                 _P]),
@@ -334,8 +335,8 @@ def padded_genotypes(G):
 
 
 def krr_set_tuning(ctx: Context, tile=512, panel_group=0, residual_split=0, sweep_pairs=-1,
-                   lookahead=-1):
-    t = krr_tuning(tile, panel_group, residual_split, sweep_pairs, lookahead)
+                   lookahead=-1, aux_cu_quarters=0):
+    t = krr_tuning(tile, panel_group, residual_split, sweep_pairs, lookahead, aux_cu_quarters)
     _check(load().krr_set_tuning(ctx.handle, ctypes.byref(t)), "krr_set_tuning")
 
 
@@ -645,6 +646,14 @@ def krr_rr_predict(ctx: Context, T, beta):
     _check(load().krr_rr_predict(ctx.handle, _ptr(T), nt, m, T.stride(0), _ptr(B), r, m, _ptr(P),
                                  nt), "krr_rr_predict")
     return P
+
+
+def krr_context_graphs(ctx: Context):
+    """(graphs the context keeps instantiated, graph launches so far)."""
+    a, b = ctypes.c_int64(), ctypes.c_int64()
+    _check(load().krr_context_graphs(ctx.handle, ctypes.byref(a), ctypes.byref(b)),
+           "krr_context_graphs")
+    return int(a.value), int(b.value)
 
 
 def krr_debug_encode_fp8(ctx: Context, x):

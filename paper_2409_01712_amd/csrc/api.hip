@@ -8,6 +8,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <functional>
 #include <map>
 #include <mutex>
 #include <string>
@@ -43,8 +44,17 @@ struct krr_context_s {
   bool destroy_pending = false;
   // schedule choices (krr_set_tuning / krr_autotune); 0 / -1 fields: the defaults
   krr_tuning tune{};
+  // instantiated graphs of the batched calls' launch sequences, by launch shape
+  std::map<std::string, hipGraphExec_t> graphs;
+  int64_t graph_replays = 0;
+  // device job tables of the batched factorization and solve, kept at stable
+  // addresses so that their graphs can be replayed (grown, never shrunk)
+  void *jobtab[2] = {nullptr, nullptr};
+  size_t jobtab_bytes[2] = {0, 0};
   // second stream and events for the factorization's lookahead
   hipStream_t aux = nullptr, side = nullptr, fmain = nullptr;
+  hipStream_t cap = nullptr;  // graph capture
+  int aux_q = 4;              // quarters of the CUs the aux stream uses
   std::vector<hipEvent_t> sched_ev;  // ordering events of the factorization schedule
 };
 
@@ -381,18 +391,25 @@ krr_status krr_create(krr_context *out, int device, void *stream, const krr_opti
   c->device = device;
   c->stream = (hipStream_t)stream;
   c->opts = o;
-  c->tune = krr_tuning{o.tile, 0, 0, -1, -1};
+  c->tune = krr_tuning{o.tile, 0, 0, -1, -1, 0};
   *out = c;
   return KRR_SUCCESS;
+}
+
+static void graphs_clear(krr_context ctx) {
+  for (auto &kv : ctx->graphs) (void)hipGraphExecDestroy(kv.second);
+  ctx->graphs.clear();
 }
 
 static void context_free(krr_context ctx) {
   (void)hipSetDevice(ctx->device);
   (void)hipStreamSynchronize(ctx->stream);
+  graphs_clear(ctx);
+  for (int q = 0; q < 2; ++q) dfree(ctx, ctx->jobtab[q], ctx->jobtab_bytes[q]);
   timers_drain(ctx);
   for (hipEvent_t e : ctx->pool) (void)hipEventDestroy(e);
   cache_flush(ctx);
-  for (hipStream_t x : {ctx->aux, ctx->side, ctx->fmain}) {
+  for (hipStream_t x : {ctx->aux, ctx->side, ctx->fmain, ctx->cap}) {
     if (x) {
       (void)hipStreamSynchronize(x);
       (void)hipStreamDestroy(x);
@@ -404,9 +421,40 @@ static void context_free(krr_context ctx) {
 
 // The factorization's three streams (default priority): its own main stream
 // (the critical path), a side stream and an aux stream.
+// The aux stream (the wide trailing updates, off the critical path) may be
+// limited to q quarters of the compute units, so that the main and side
+// streams find free ones: CU i is enabled when (i / 8) % 4 < q, which leaves
+// every XCD the same share whether the mask's bits run XCD by XCD or
+// interleave the XCDs.  KRR_AUX_CU_QUARTERS overrides the tuning.
 static krr_status context_aux(krr_context ctx) {
-  for (hipStream_t *x : {&ctx->fmain, &ctx->side, &ctx->aux})
+  for (hipStream_t *x : {&ctx->fmain, &ctx->side})
     if (!*x) HIPCHK(hipStreamCreateWithFlags(x, hipStreamNonBlocking));
+  const char *e = getenv("KRR_AUX_CU_QUARTERS");
+  int q = e ? atoi(e) : ctx->tune.aux_cu_quarters;
+  if (q <= 0 || q > 4) q = 4;
+  if (ctx->aux && ctx->aux_q != q) {
+    HIPCHK(hipStreamSynchronize(ctx->aux));
+    HIPCHK(hipStreamDestroy(ctx->aux));
+    ctx->aux = nullptr;
+  }
+  if (!ctx->aux) {
+    int ncu = 0;
+    HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, ctx->device));
+    bool masked = false;
+    if (q < 4 && ncu > 0) {
+      std::vector<uint32_t> mask((ncu + 31) / 32, 0u);
+      for (int i = 0; i < ncu; ++i)
+        if (((i >> 3) & 3) < q) mask[i / 32] |= 1u << (i % 32);
+      masked = hipExtStreamCreateWithCUMask(&ctx->aux, (uint32_t)mask.size(), mask.data()) ==
+               hipSuccess;
+      if (!masked) {
+        (void)hipGetLastError();
+        ctx->aux = nullptr;
+      }
+    }
+    if (!masked) HIPCHK(hipStreamCreateWithFlags(&ctx->aux, hipStreamNonBlocking));
+    ctx->aux_q = masked ? q : 4;
+  }
   return KRR_SUCCESS;
 }
 
@@ -747,7 +795,7 @@ static void factor_work_free(krr_context c, FactorWork &w, const TileLayout &L) 
     dfree(c, pb.P32, pt * te * 4);
     dfree(c, pb.P16, pt * te * 2);
     dfree(c, pb.P8, pt * te);
-    dfree(c, pb.pnorm, pt * 4);
+    dfree(c, pb.pnorm, (pt + 2) * 4);
     dfree(c, pb.pexp8, pt * 4);
   }
   dfree(c, w.pnorm_part, pt * parts * 8);
@@ -778,7 +826,7 @@ static krr_status factor_work_alloc(krr_context c, FactorWork &w, const TileLayo
     WA(pb.P32, pt * te * 4);
     WA(pb.P16, need16 ? pt * te * 2 : 16);
     WA(pb.P8, need8 ? pt * te : 16);
-    WA(pb.pnorm, pt * 4);
+    WA(pb.pnorm, (pt + 2) * 4);  // + the norms' extremes
     WA(pb.pexp8, pt * 4);
   }
   WA(w.pnorm_part, pt * parts * 8);
@@ -898,7 +946,9 @@ static krr_status factor_enqueue(krr_context ctx, krr_kernel K, krr_factorizatio
   up.fmap = fmap;
   up.pcap = pcap;
   up.tnorm = K->tnorm;
-  const bool need16 = fp.allow16 != 0, need8 = fp.allow8 != 0;
+  // FP16 operands: chosen by the rule, or FP8 ones promoted a level after a breakdown
+  up.have16 = fp.allow16 || (fp.allow8 && p.allow_promotion);
+  const bool need16 = up.have16 != 0, need8 = fp.allow8 != 0;
   const bool scale8 = p.no_fp8_scale == 0;
   const int64_t te = L.tile_elems();
   // Panels are produced in groups of g block columns.  Inside a group
@@ -936,7 +986,7 @@ static krr_status factor_enqueue(krr_context ctx, krr_kernel K, krr_factorizatio
   };
   auto convert = [&](int k, hipStream_t st) {
     Stage t(ctx, KRR_STAGE_CONVERT, st);
-    launch_convert_panel(F->Lst, k, L, w, scale8, slot(k), need16, need8, st);
+    launch_convert_panel(F->Lst, k, L, w, scale8, slot(k), need16, need8, &up, st);
   };
   // panels G0 .. G0+npan-1 onto the tiles of columns jlo .. jhi (which: UPD_*)
   auto update = [&](int G0, int npan, int jlo, int jhi, int which, hipStream_t st) {
@@ -1213,6 +1263,78 @@ static void factor_free(krr_factorization F) {
   delete F;
 }
 
+// Run a fixed launch sequence through a HIP graph: captured from `enqueue`
+// on the first call with a given key (the launch shape, including the device
+// addresses the kernels are given), instantiated, kept in the context and
+// replayed on later calls.  The sequence must hold kernel launches only.
+// KRR_NO_GRAPH=1 enqueues directly.
+constexpr size_t KRR_GRAPH_CACHE_MAX = 64;
+
+// Job table `which` (0 factorization, 1 solve) of at least `bytes`, at the
+// same address from call to call while it is large enough.  Only used on the
+// context stream by calls that synchronize before returning.
+static krr_status job_table(krr_context ctx, int which, size_t bytes, void **out) {
+  if (ctx->jobtab_bytes[which] < bytes) {
+    if (ctx->jobtab[which]) {
+      HIPCHK(hipStreamSynchronize(ctx->stream));
+      dfree(ctx, ctx->jobtab[which], ctx->jobtab_bytes[which]);
+      ctx->jobtab[which] = nullptr;
+      ctx->jobtab_bytes[which] = 0;
+    }
+    const size_t cap = std::max<size_t>(bytes, 4096);
+    CHK(dalloc(ctx, &ctx->jobtab[which], cap));
+    ctx->jobtab_bytes[which] = cap;
+  }
+  *out = ctx->jobtab[which];
+  return KRR_SUCCESS;
+}
+
+static krr_status graph_run(krr_context ctx, const std::string &key, hipStream_t s,
+                            const std::function<void(hipStream_t)> &enqueue) {
+  const char *e = getenv("KRR_NO_GRAPH");
+  if (e && atoi(e) != 0) {
+    enqueue(s);
+    return launch_ok();
+  }
+  auto it = ctx->graphs.find(key);
+  if (it == ctx->graphs.end()) {
+    if (ctx->graphs.size() >= KRR_GRAPH_CACHE_MAX) {
+      HIPCHK(hipStreamSynchronize(s));  // no replay of an evicted graph is in flight
+      graphs_clear(ctx);
+    }
+    // captured on a stream of the context's own (the caller's stream may be
+    // the null stream, which cannot be captured); nothing runs while capturing
+    if (!ctx->cap) HIPCHK(hipStreamCreateWithFlags(&ctx->cap, hipStreamNonBlocking));
+    hipGraph_t g = nullptr;
+    HIPCHK(hipStreamBeginCapture(ctx->cap, hipStreamCaptureModeThreadLocal));
+    enqueue(ctx->cap);
+    const hipError_t ce = hipStreamEndCapture(ctx->cap, &g);
+    if (ce != hipSuccess || !g) {
+      (void)hipGetLastError();
+      if (g) (void)hipGraphDestroy(g);
+      return KRR_ERROR_HIP;
+    }
+    hipGraphExec_t x = nullptr;
+    const hipError_t ie = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ie != hipSuccess) {
+      (void)hipGetLastError();
+      return KRR_ERROR_HIP;
+    }
+    it = ctx->graphs.emplace(key, x).first;
+  }
+  HIPCHK(hipGraphLaunch(it->second, s));
+  ctx->graph_replays++;
+  return launch_ok();
+}
+
+krr_status krr_context_graphs(krr_context ctx, int64_t *cached, int64_t *launches) {
+  if (!ctx) return KRR_ERROR_INVALID_VALUE;
+  if (cached) *cached = (int64_t)ctx->graphs.size();
+  if (launches) *launches = ctx->graph_replays;
+  return KRR_SUCCESS;
+}
+
 krr_status krr_factor_batched(krr_context ctx, int32_t batch, const krr_kernel *K,
                               const krr_precision_policy *policy, krr_factorization *out) {
   if (!out || batch <= 0) return KRR_ERROR_INVALID_VALUE;
@@ -1313,7 +1435,8 @@ krr_status krr_factor_batched(krr_context ctx, int32_t batch, const krr_kernel *
       j.nt = L.nt;
     }
     if (st != KRR_SUCCESS) break;
-    if ((st = dalloc_t(ctx, &djobs, batch)) != KRR_SUCCESS) break;
+    if ((st = job_table(ctx, 0, sizeof(FactorJob) * batch, (void **)&djobs)) != KRR_SUCCESS)
+      break;
     if (hipMemcpyAsync(djobs, jobs.data(), sizeof(FactorJob) * batch, hipMemcpyHostToDevice, s) !=
         hipSuccess) {
       st = KRR_ERROR_HIP;
@@ -1326,11 +1449,24 @@ krr_status krr_factor_batched(krr_context ctx, int32_t batch, const krr_kernel *
     up.high_panels = p.high_panels;
     up.fixed_prec = p.fixed_prec;
     up.rule = p.rule;
+    up.have16 = fp.allow16;  // no promotion caps in the lockstep: FP16 only if the rule has it
     up.thr = 0;  // per instance, from the table (with the tile norms)
     {
+      // every lockstep launch of the factorization in one graph, replayed for
+      // batches of the same shape (the instances' pointers come from the table)
+      char kb[256];
+      snprintf(kb, sizeof kb, "factor|%p|%d|%d|%d|%d|%d|%d|%d|%d|%d|%d|%d|%d", (void *)djobs,
+               batch, ctx->opts.tile, g, fp.diag64 ? 1 : 0, fp.allow16, fp.allow8,
+               p.no_fp8_scale, up.mode, up.high_panels, up.fixed_prec, up.rule,
+               (int)sizeof(FactorJob));
+      std::string key = kb;
+      for (int b = 0; b < batch; ++b) key += "|" + std::to_string(nts[b]);
       Stage t(ctx, KRR_STAGE_POTRF, s);
-      launch_factor_lockstep(djobs, nts.data(), batch, ctx->opts.tile, g, up, fp.diag64,
-                             fp.allow16 != 0, fp.allow8 != 0, p.no_fp8_scale == 0, s);
+      st = graph_run(ctx, key, s, [&](hipStream_t cs) {
+        launch_factor_lockstep(djobs, nts.data(), batch, ctx->opts.tile, g, up, fp.diag64,
+                               fp.allow16 != 0, fp.allow8 != 0, p.no_fp8_scale == 0, cs);
+      });
+      if (st != KRR_SUCCESS) break;
     }
     for (int b = 0; b < batch; ++b) {
       launch_count_pmap(dmap[b], mapsz[b], W[b].counts, s);
@@ -1358,7 +1494,7 @@ krr_status krr_factor_batched(krr_context ctx, int32_t batch, const krr_kernel *
     factor_work_free(ctx, W[b], K[b]->L);
     if (dmap[b]) dfree(ctx, dmap[b], mapsz[b]);
   }
-  if (djobs) dfree(ctx, djobs, sizeof(FactorJob) * batch);
+
   // an instance that broke down is factored again on its own, with promotion
   for (int b = 0; b < batch && st == KRR_SUCCESS; ++b) {
     if (hflag[b] == 0) continue;
@@ -1679,7 +1815,7 @@ krr_status krr_solve_batched(krr_context ctx, int32_t batch, const krr_factoriza
   for (int b = 0; b < batch; ++b)
     CHK(solve_alloc(sc, F[b]->L, r, B[b], residual_split_batched(F[b]->L)));
   SolveJob *djobs = nullptr;
-  CHK(sc.alloc(&djobs, batch));
+  CHK(job_table(ctx, 1, sizeof(SolveJob) * batch, (void **)&djobs));
   // The table of the instances a batched launch covers; every instance's
   // steps run in lockstep in one launch per step (sweeps) or per pass
   // (residual), all on the context stream.
@@ -1735,8 +1871,13 @@ krr_status krr_solve_batched(krr_context ctx, int32_t batch, const krr_factoriza
     bool fact;
     CHK(upload(ids, ntmax, rblocks, fact));
     {
+      char kb[128];
+      snprintf(kb, sizeof kb, "sweeps|%p|%d|%d|%d|%d", (void *)djobs, (int)ids.size(), ntmax, nb,
+               r);
       Stage t(ctx, KRR_STAGE_FWD, s);
-      launch_sweeps_batched(djobs, (int)ids.size(), ntmax, nb, r, s);
+      CHK(graph_run(ctx, kb, s, [&](hipStream_t cs) {
+        launch_sweeps_batched(djobs, (int)ids.size(), ntmax, nb, r, cs);
+      }));
     }
     for (int b : ids) launch_axpy_f32_to_f64(B[b].Xf, F[b]->L.np * r, 1.0, B[b].Xr, s);
     return launch_ok();
@@ -2087,7 +2228,8 @@ krr_status krr_factor_copy_l(krr_factorization F, int64_t i0, int64_t j0, int64_
 static bool tuning_valid(const krr_tuning &t) {
   return (t.tile == 256 || t.tile == 512) && t.panel_group >= 0 && t.panel_group <= KRR_MAX_GROUP &&
          t.residual_split >= 0 && t.residual_split <= 16 && t.sweep_pairs >= -1 &&
-         t.sweep_pairs <= 1 && t.lookahead >= -1 && t.lookahead <= 1;
+         t.sweep_pairs <= 1 && t.lookahead >= -1 && t.lookahead <= 1 && t.aux_cu_quarters >= 0 &&
+         t.aux_cu_quarters <= 4;
 }
 
 krr_status krr_set_tuning(krr_context ctx, const krr_tuning *t) {
@@ -2137,13 +2279,14 @@ static bool cache_parse_line(const char *line, std::string &key, krr_tuning &t, 
   const char *q1 = strchr(q0 + 1, '"');
   if (!q1) return false;
   key.assign(q0 + 1, q1 - q0 - 1);
-  int tile, g, z, pr, la;
+  int tile, g, z, pr, la, aq;
   well_formed = sscanf(q1 + 1,
                        " : {\"tile\": %d, \"panel_group\": %d, \"residual_split\": %d, "
-                       "\"sweep_pairs\": %d, \"lookahead\": %d, \"ms\": %lf}",
-                       &tile, &g, &z, &pr, &la, &ms) == 6;
+                       "\"sweep_pairs\": %d, \"lookahead\": %d, \"aux_cu_quarters\": %d, "
+                       "\"ms\": %lf}",
+                       &tile, &g, &z, &pr, &la, &aq, &ms) == 7;
   if (well_formed) {
-    t = krr_tuning{tile, g, z, pr, la};
+    t = krr_tuning{tile, g, z, pr, la, aq};
     well_formed = tuning_valid(t);
   }
   return true;
@@ -2194,8 +2337,9 @@ krr_status krr_tuning_cache_store(const char *path, const char *key, const krr_t
   char buf[1024];
   snprintf(buf, sizeof buf,
            "\"%s\": {\"tile\": %d, \"panel_group\": %d, \"residual_split\": %d, "
-           "\"sweep_pairs\": %d, \"lookahead\": %d, \"ms\": %.6f}",
-           key, t->tile, t->panel_group, t->residual_split, t->sweep_pairs, t->lookahead, ms);
+           "\"sweep_pairs\": %d, \"lookahead\": %d, \"aux_cu_quarters\": %d, \"ms\": %.6f}",
+           key, t->tile, t->panel_group, t->residual_split, t->sweep_pairs, t->lookahead,
+           t->aux_cu_quarters, ms);
   lines[key] = buf;
   std::string tmp = std::string(path) + ".tmp";
   FILE *f = fopen(tmp.c_str(), "w");
@@ -2258,7 +2402,7 @@ krr_status krr_autotune(krr_context ctx, const int8_t *G, int64_t n, int64_t m, 
       return -1;
     return st == KRR_SUCCESS ? (double)ms : -1;
   };
-  krr_tuning best{saved_tile, 0, 0, -1, -1};
+  krr_tuning best{saved_tile, 0, 0, -1, -1, 0};
   double best_t = -1;
   auto consider = [&](const krr_tuning &t, bool warm) {
     if (warm) run(t);
@@ -2269,7 +2413,7 @@ krr_status krr_autotune(krr_context ctx, const int8_t *G, int64_t n, int64_t m, 
     }
   };
   for (int tile : {512, 256}) {
-    krr_tuning t{tile, 0, 0, -1, -1};
+    krr_tuning t{tile, 0, 0, -1, -1, 0};
     consider(t, true);
   }
   if (best_t >= 0) {
@@ -2290,6 +2434,12 @@ krr_status krr_autotune(krr_context ctx, const int8_t *G, int64_t n, int64_t m, 
       krr_tuning t = b2;
       t.sweep_pairs = pr;
       consider(t, false);
+    }
+    const krr_tuning b3 = best;
+    for (int aq : {3, 2}) {
+      krr_tuning t = b3;
+      t.aux_cu_quarters = aq;
+      consider(t, true);  // a new aux stream: warm it first
     }
   }
   (void)hipEventDestroy(e0);

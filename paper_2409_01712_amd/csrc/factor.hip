@@ -804,15 +804,93 @@ void launch_trsm_gemm(const float *Astore, const float *Linv_k, int k, const Til
 // has many instances per launch and wants fewer, longer ones
 constexpr int CONV_CHUNK = 4096, CONV_CHUNK_B = 16384;
 
+// The precision the rule chooses for an operand-norm product, before the
+// precisions the attempt allows and the panel caps are applied.
+KRR_DEV int rule_prec(const UpdatePolicy &pol, double prod) {
+  if (pol.allow8 && 0.0625 * prod <= pol.thr) return KRR_PREC_FP8;
+  if (pol.allow16 && 0.00048828125 * prod <= pol.thr) return KRR_PREC_FP16;
+  return KRR_PREC_FP32;
+}
+
+// The precision an update reads its operands in: the choice c capped by the
+// panel's promotion level, FP16 only where FP16 operands are reachable.
+KRR_DEV int effective_prec(const UpdatePolicy &pol, int k, int c) {
+  if (pol.pcap && c > (int)pol.pcap[k]) c = pol.pcap[k];
+  if (c == KRR_PREC_FP8 && !pol.allow8) c = KRR_PREC_FP16;
+  if (c == KRR_PREC_FP16 && !pol.have16) c = KRR_PREC_FP32;
+  return c;
+}
+
+// Which copies of panel k's tile with norm pn some update will read (its
+// partners' norms lie in [mn, mx]): the effective precisions of the choices
+// between those of pn mx and pn mn under the operand rule, the fixed
+// precision under FIXED, every allowed one under the map or the tile rules.
+KRR_DEV void copies_needed(const UpdatePolicy &pol, int k, float pn, float mn, float mx, int &n16,
+                           int &n8) {
+  int lo = KRR_PREC_FP32, hi = KRR_PREC_FP32;
+  if (pol.mode == KRR_POLICY_FIXED_MAP ||
+      (pol.mode == KRR_POLICY_ADAPTIVE && pol.rule != KRR_RULE_OPERAND && k >= pol.high_panels)) {
+    hi = KRR_PREC_FP8;
+  } else if (k >= pol.high_panels && pol.mode == KRR_POLICY_FIXED) {
+    lo = hi = pol.fixed_prec;
+  } else if (k >= pol.high_panels && pol.mode == KRR_POLICY_ADAPTIVE) {
+    lo = rule_prec(pol, (double)pn * (double)mx);
+    hi = rule_prec(pol, (double)pn * (double)mn);
+  }
+  n16 = n8 = 0;
+  for (int c = lo; c <= hi; ++c) {
+    const int e = effective_prec(pol, k, c);
+    n16 |= e == KRR_PREC_FP16;
+    n8 |= e == KRR_PREC_FP8;
+  }
+}
+
+// Panel k's tile norms (each tile's partial sums added in a fixed order, as
+// FP32) and, at pnorm[mm_at] and pnorm[mm_at + 1], their smallest and largest.
+__global__ __launch_bounds__(256) void k_panel_norms(const double *__restrict__ pnorm_part,
+                                                     int parts, int tiles,
+                                                     float *__restrict__ pnorm, int mm_at) {
+  __shared__ float smn[256], smx[256];
+  float mn = INFINITY, mx = 0.0f;
+  for (int t = threadIdx.x; t < tiles; t += 256) {
+    double ss = 0.0;
+    for (int q = 0; q < parts; ++q) ss += pnorm_part[(int64_t)t * parts + q];
+    const float v = (float)sqrt(ss);
+    pnorm[t] = v;
+    mn = fminf(mn, v);
+    mx = fmaxf(mx, v);
+  }
+  smn[threadIdx.x] = mn;
+  smx[threadIdx.x] = mx;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      smn[threadIdx.x] = fminf(smn[threadIdx.x], smn[threadIdx.x + w]);
+      smx[threadIdx.x] = fmaxf(smx[threadIdx.x], smx[threadIdx.x + w]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    pnorm[mm_at] = smn[0];
+    pnorm[mm_at + 1] = smx[0];
+  }
+}
+
+// select: the tile norms and their extremes are in pnorm already (from
+// k_panel_norms) and only the copies pol lets some update read are written;
+// otherwise the norms are formed here and need16 / need8 decide.
 KRR_DEV void convert_panel_body(const float *__restrict__ P32, float *__restrict__ Astore,
                                 _Float16 *__restrict__ P16, uint8_t *__restrict__ P8,
                                 const double *__restrict__ pnorm_part,
                                 const float *__restrict__ pmax_part, int parts,
                                 float *__restrict__ pnorm, int *__restrict__ pexp8, int k, int nb,
-                                int chunks, int need16, int need8, int scale8, int64_t bid) {
+                                int chunks, int need16, int need8, int scale8, int64_t bid,
+                                int select = 0, const UpdatePolicy *pol = nullptr,
+                                int mm_at = 0) {
   const int64_t t = bid / chunks;
   const int ch = (int)(bid % chunks);
   const int64_t i = k + 1 + t;
+  if (select) copies_needed(*pol, k, pnorm[t], pnorm[mm_at], pnorm[mm_at + 1], need16, need8);
   // the tile's largest magnitude from its partial maxima, one per thread
   // (a max is exact in any order)
   __shared__ float smx[256];
@@ -848,9 +926,11 @@ KRR_DEV void convert_panel_body(const float *__restrict__ P32, float *__restrict
     }
   }
   if (ch == 0 && threadIdx.x == 0) {
-    double ss = 0.0;  // the tile norm, partial sums added in a fixed order
-    for (int q = 0; q < parts; ++q) ss += pnorm_part[t * parts + q];
-    pnorm[t] = (float)sqrt(ss);
+    if (!select) {
+      double ss = 0.0;  // the tile norm, partial sums added in a fixed order
+      for (int q = 0; q < parts; ++q) ss += pnorm_part[t * parts + q];
+      pnorm[t] = (float)sqrt(ss);
+    }
     pexp8[t] = ilogbf(s8);  // s8 = 2^pexp8
   }
 }
@@ -859,20 +939,27 @@ __global__ __launch_bounds__(256) void k_convert_panel(
     const float *__restrict__ P32, float *__restrict__ Astore, _Float16 *__restrict__ P16,
     uint8_t *__restrict__ P8, const double *__restrict__ pnorm_part,
     const float *__restrict__ pmax_part, int parts, float *__restrict__ pnorm,
-    int *__restrict__ pexp8, int k, int nb, int chunks, int need16, int need8, int scale8) {
+    int *__restrict__ pexp8, int k, int nb, int chunks, int need16, int need8, int scale8,
+    int select, UpdatePolicy pol, int mm_at) {
   convert_panel_body(P32, Astore, P16, P8, pnorm_part, pmax_part, parts, pnorm, pexp8, k, nb,
-                     chunks, need16, need8, scale8, blockIdx.x);
+                     chunks, need16, need8, scale8, blockIdx.x, select, &pol, mm_at);
 }
 
 void launch_convert_panel(float *Astore, int k, const TileLayout &L, FactorWork &w, bool scale8,
-                          const PanelBuf &pb, bool need16, bool need8, hipStream_t s) {
+                          const PanelBuf &pb, bool need16, bool need8, const UpdatePolicy *pol,
+                          hipStream_t s) {
   const int64_t tiles = L.nt - 1 - k;
   if (tiles <= 0) return;
   const int chunks = (int)((int64_t)L.nb * L.nb / CONV_CHUNK);
+  const int mm_at = std::max(L.nt - 1, 1);  // the norms' extremes after the largest panel
+  const int parts = trsm_parts(L.nb);
+  if (pol)
+    hipLaunchKernelGGL(k_panel_norms, dim3(1), dim3(256), 0, s, w.pnorm_part, parts, (int)tiles,
+                       pb.pnorm, mm_at);
   hipLaunchKernelGGL(k_convert_panel, dim3((unsigned)(tiles * chunks)), dim3(256), 0, s, pb.P32,
-                     Astore, pb.P16, pb.P8, w.pnorm_part, w.pmax_part, trsm_parts(L.nb), pb.pnorm,
-                     pb.pexp8,
-                     k, L.nb, chunks, need16 ? 1 : 0, need8 ? 1 : 0, scale8 ? 1 : 0);
+                     Astore, pb.P16, pb.P8, w.pnorm_part, w.pmax_part, parts, pb.pnorm,
+                     pb.pexp8, k, L.nb, chunks, need16 ? 1 : 0, need8 ? 1 : 0, scale8 ? 1 : 0,
+                     pol ? 1 : 0, pol ? *pol : UpdatePolicy{}, mm_at);
 }
 
 // Trailing update by a group of consecutive panels k0 .. k0+npan-1:
@@ -1005,16 +1092,11 @@ KRR_DEV void update_body(float *__restrict__ Astore, const PanelSet &ps, int k0,
         double prod = (double)ps.pnorm[q][a] * (double)ps.pnorm[q][b];
         if (pol.rule == KRR_RULE_TILE) prod = pol.tnorm[i * (i + 1) / 2 + j];
         else if (pol.rule == KRR_RULE_BOTH) prod = fmax(prod, pol.tnorm[i * (i + 1) / 2 + j]);
-        if (pol.allow8 && 0.0625 * prod <= pol.thr)
-          prec = KRR_PREC_FP8;
-        else if (pol.allow16 && 0.00048828125 * prod <= pol.thr)
-          prec = KRR_PREC_FP16;
+        prec = rule_prec(pol, prod);
       }
     }
-    // precisions the attempt still allows (promotion): globally, then per panel
-    if (prec == KRR_PREC_FP8 && !pol.allow8) prec = KRR_PREC_FP16;
-    if (prec == KRR_PREC_FP16 && !pol.allow16) prec = KRR_PREC_FP32;
-    if (pol.pcap && prec > (int)pol.pcap[k]) prec = pol.pcap[k];
+    // the panel's promotion cap and the precisions the attempt makes available
+    prec = effective_prec(pol, k, prec);
     const int64_t ra = a * te + (int64_t)si * BM * nb, rb = b * te + (int64_t)sj * BM * nb;
     if (prec == KRR_PREC_FP32) {
       qa[q] = (uint64_t)(ps.P32[q] + ra);

@@ -117,7 +117,8 @@ void launch_copy_tiles_f32(const float *A, const TileLayout &L, int64_t i0, int6
 // ---- factor.hip ----
 struct UpdatePolicy {
   int mode;          // KRR_POLICY_*
-  int allow16, allow8;
+  int allow16, allow8;  // precisions the rule may choose
+  int have16 = 0;       // FP16 operands reachable (the rule, or FP8 promoted one level)
   int high_panels;
   int fixed_prec;
   int rule;          // KRR_RULE_* (ADAPTIVE)
@@ -209,8 +210,12 @@ void launch_trsm_subst(const float *Astore, int k, const TileLayout &L, bool fp6
                        const PanelBuf &pb, int t_lo, int t_hi, hipStream_t s);
 void launch_trsm_gemm(const float *Astore, const float *Linv_k, int k, const TileLayout &L,
                       FactorWork &w, const PanelBuf &pb, int t_lo, int t_hi, hipStream_t s);
+// pol (or null): write only the operand copies some update of each tile will
+// read under this policy (the tile norms, their extremes and the rule);
+// otherwise every copy need16 / need8 asks for.
 void launch_convert_panel(float *Astore, int k, const TileLayout &L, FactorWork &w, bool scale8,
-                          const PanelBuf &pb, bool need16, bool need8, hipStream_t s);
+                          const PanelBuf &pb, bool need16, bool need8, const UpdatePolicy *pol,
+                          hipStream_t s);
 // Trailing update of the tiles (i, j), jlo <= j <= jhi, j <= i, by the npan
 // consecutive panels k0 .. k0+npan-1 whose operand copies are *pbs[q].
 void launch_update(float *Astore, int k0, int npan, int jlo, int jhi, const TileLayout &L,

@@ -152,8 +152,10 @@ def test_tuning_cache_round_trip(lib, tmp_path):
     and malformed entries or invalid tunings are rejected."""
     path = str(tmp_path / "tune.json")
     assert krr.krr_tuning_cache_load(path, "k1") is None  # no file yet
-    a = {"tile": 512, "panel_group": 8, "residual_split": 8, "sweep_pairs": 1, "lookahead": 1}
-    b = {"tile": 256, "panel_group": 4, "residual_split": 16, "sweep_pairs": 0, "lookahead": -1}
+    a = {"tile": 512, "panel_group": 8, "residual_split": 8, "sweep_pairs": 1, "lookahead": 1,
+         "aux_cu_quarters": 3}
+    b = {"tile": 256, "panel_group": 4, "residual_split": 16, "sweep_pairs": 0, "lookahead": -1,
+         "aux_cu_quarters": 0}
     krr.krr_tuning_cache_store(path, "gfx950|cu256|n32768|m65536|r16|mode1|d641|ref1", a, 85.25)
     krr.krr_tuning_cache_store(path, "k2", b, 12.5)
     assert krr.krr_tuning_cache_load(path, "gfx950|cu256|n32768|m65536|r16|mode1|d641|ref1") == \
@@ -175,5 +177,5 @@ def test_tuning_cache_round_trip(lib, tmp_path):
         krr.krr_tuning_cache_load(path, "k5")
     assert krr.krr_tuning_cache_load(path, "k2") == (a, 10.0)
     # a tuning is validated before it reaches a context
-    t = krr.krr_tuning(300, 0, 0, -1, -1)
+    t = krr.krr_tuning(300, 0, 0, -1, -1, 0)
     assert lib.krr_set_tuning(None, ctypes.byref(t)) == krr.KRR_ERROR_INVALID_VALUE
