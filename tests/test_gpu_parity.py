@@ -249,6 +249,41 @@ def test_paired_sweeps_match_single_steps(monkeypatch, n):
     c.close()
 
 
+@pytest.mark.skip(reason="persistent one-launch sweeps are switched off (KRR_SWEEP_PAIRS=2 "
+                  "returns KRR_ERROR_NOT_SUPPORTED): the first GPU runs hung at n=200 (one "
+                  "tile), also with time-bounded waits, and the cause is not known")
+@pytest.mark.parametrize("n,r", [(200, 5), (700, 40), (1500, 5), (3000, 17)])
+def test_persistent_sweeps_match_single_steps(monkeypatch, n, r):
+    """Sweeps as one persistent launch each (work items from an atomic ticket, waits on
+    per-tile counters) agree with one-tile-per-step sweeps to FP32 rounding, at tile
+    counts 1, 3, 6 and 12 (tile 256) and 1 to 3 blocks of 16 right-hand sides; the
+    refined result matches the oracle."""
+    m = 900
+    G = _gen(n, m, seed=n + r)
+    Y = synth.phenotypes(G, r, n_pairs=5, n_add=3, seed=n + 2, h2=0.5)
+    gamma, lam = 1.0 / m, 0.1
+    c = krr.krr_create(0, tile=256)
+    K = krr.krr_build_kernel(c, _dev(G), gamma, lam)
+    F = krr.krr_factor(c, K, krr.plain_fp32_policy())
+    none = krr.Refine(method=krr.KRR_REFINE_NONE)
+    monkeypatch.setenv("KRR_SWEEP_PAIRS", "0")
+    X1, _, _ = krr.krr_solve(c, F, _dev(Y), none)
+    monkeypatch.setenv("KRR_SWEEP_PAIRS", "2")
+    Xp, _, st = krr.krr_solve(c, F, _dev(Y), none)
+    assert st == krr.KRR_SUCCESS
+    assert _colrel(Xp.cpu().numpy(), X1.cpu().numpy()) <= 2e-3
+    X, info, st = krr.krr_solve(c, F, _dev(Y), krr.Refine(tol=1e-8))
+    assert st == krr.KRR_SUCCESS and info.converged == 1
+    assert _colrel(X.cpu().numpy(), oracle.fit(G, Y, gamma, lam)) <= TOL
+    # the adaptive factor through the same sweeps, refined to the oracle
+    F2 = krr.krr_factor(c, K)
+    X2, info2, _ = krr.krr_solve(c, F2, _dev(Y), krr.Refine(tol=1e-8))
+    assert info2.converged == 1
+    assert _colrel(X2.cpu().numpy(), oracle.fit(G, Y, gamma, lam)) <= TOL
+    monkeypatch.delenv("KRR_SWEEP_PAIRS")
+    c.close()
+
+
 @pytest.mark.parametrize("method", ["pcg", "auto"])
 @pytest.mark.parametrize("policy", ["adaptive", "fixed_fp8"])
 def test_pcg_parity(method, policy):
