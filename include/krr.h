@@ -431,9 +431,9 @@ typedef struct krr_tuning {
   int32_t residual_split; /* column ranges of the FP64 residual, 1 .. 16 (0: min(8, NT)) */
   int32_t sweep_pairs;    /* 1: triangular sweeps over tile pairs, 0: one tile per step (-1: 1) */
   int32_t lookahead;      /* 1: three-stream factorization schedule, 0: one stream (-1: 1) */
-  int32_t aux_cu_quarters;/* quarters of the compute units the stream of the wide trailing
-                             updates may use, 1 .. 4 (0: all); the rest stay free for the
-                             critical path (a CU mask spread evenly over the XCDs) */
+  int32_t aux_cu_eighths; /* eighths of the compute units the stream of the wide trailing
+                             updates may use, 1 .. 8 (0: 7); the rest stay free for the
+                             critical path (a CU mask over groups of eight CUs) */
 } krr_tuning;
 
 /* Set or read the context's tuning.  Changing the tile needs a context with
@@ -447,7 +447,8 @@ krr_status krr_get_tuning(krr_context ctx, krr_tuning *t);
  * the caller's data, searching one choice at a time: the tile (256, 512,
  * each after an untimed warm-up), then the panel group (4, 6, 8), the
  * residual split (4, 8, 16), the sweep pairing and the compute units of the
- * wide-update stream (4, 3, 2 quarters), each at the best choices so far.  The result is kept in the context (krr_get_tuning) and written to
+ * wide-update stream (7, 8, 6 eighths), each at the best choices so far.
+ * The result is kept in the context (krr_get_tuning) and written to
  * *out and *best_ms.  With cache_path (a host path, may be NULL) the choice
  * is looked up first under the key of krr_tuning_key, and stored there after
  * a search; a cached choice is applied without running anything.  The
@@ -469,7 +470,7 @@ krr_status krr_tuning_key(int device, int64_t n, int64_t m, int64_t nrhs,
                           char *key, int32_t cap);
 /* The cache file (host only, no GPU): a JSON object with one entry per key,
  * {"key": {"tile": .., "panel_group": .., "residual_split": .., "sweep_pairs": ..,
- * "lookahead": .., "aux_cu_quarters": .., "ms": ..}, ...}.  store adds or replaces one entry (the
+ * "lookahead": .., "aux_cu_eighths": .., "ms": ..}, ...}.  store adds or replaces one entry (the
  * file is rewritten whole, through a temporary file and a rename); load sets
  * *found to 0 when the file or the key is absent, KRR_ERROR_INVALID_VALUE on
  * a malformed entry for the key. */

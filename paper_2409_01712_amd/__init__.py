@@ -62,7 +62,7 @@ class krr_kernel_desc(ctypes.Structure):
 class krr_tuning(ctypes.Structure):
     _fields_ = [("tile", ctypes.c_int32), ("panel_group", ctypes.c_int32),
                 ("residual_split", ctypes.c_int32), ("sweep_pairs", ctypes.c_int32),
-                ("lookahead", ctypes.c_int32), ("aux_cu_quarters", ctypes.c_int32)]
+                ("lookahead", ctypes.c_int32), ("aux_cu_eighths", ctypes.c_int32)]
 
     def as_dict(self):
         return {f: int(getattr(self, f)) for f, _ in self._fields_}
@@ -335,8 +335,8 @@ def padded_genotypes(G):
 
 
 def krr_set_tuning(ctx: Context, tile=512, panel_group=0, residual_split=0, sweep_pairs=-1,
-                   lookahead=-1, aux_cu_quarters=0):
-    t = krr_tuning(tile, panel_group, residual_split, sweep_pairs, lookahead, aux_cu_quarters)
+                   lookahead=-1, aux_cu_eighths=0):
+    t = krr_tuning(tile, panel_group, residual_split, sweep_pairs, lookahead, aux_cu_eighths)
     _check(load().krr_set_tuning(ctx.handle, ctypes.byref(t)), "krr_set_tuning")
 
 

@@ -54,7 +54,7 @@ struct krr_context_s {
   // second stream and events for the factorization's lookahead
   hipStream_t aux = nullptr, side = nullptr, fmain = nullptr;
   hipStream_t cap = nullptr;  // graph capture
-  int aux_q = 4;              // quarters of the CUs the aux stream uses
+  int aux_e = 8;              // eighths of the CUs the aux stream uses
   std::vector<hipEvent_t> sched_ev;  // ordering events of the factorization schedule
 };
 
@@ -422,17 +422,17 @@ static void context_free(krr_context ctx) {
 // The factorization's three streams (default priority): its own main stream
 // (the critical path), a side stream and an aux stream.
 // The aux stream (the wide trailing updates, off the critical path) may be
-// limited to q quarters of the compute units, so that the main and side
-// streams find free ones: CU i is enabled when (i / 8) % 4 < q, which leaves
-// every XCD the same share whether the mask's bits run XCD by XCD or
-// interleave the XCDs.  KRR_AUX_CU_QUARTERS overrides the tuning.
+// limited to q eighths of the compute units, so that the main and side
+// streams find free ones: CU i is enabled when (i / 8) % 8 < q.  (Quarters
+// spread the same way, (i / 8) % 4 < q, measured slower at the benchmark
+// size.)  KRR_AUX_CU_EIGHTHS overrides the tuning.
 static krr_status context_aux(krr_context ctx) {
   for (hipStream_t *x : {&ctx->fmain, &ctx->side})
     if (!*x) HIPCHK(hipStreamCreateWithFlags(x, hipStreamNonBlocking));
-  const char *e = getenv("KRR_AUX_CU_QUARTERS");
-  int q = e ? atoi(e) : ctx->tune.aux_cu_quarters;
-  if (q <= 0 || q > 4) q = 4;
-  if (ctx->aux && ctx->aux_q != q) {
+  const char *e = getenv("KRR_AUX_CU_EIGHTHS");
+  int q = e ? atoi(e) : ctx->tune.aux_cu_eighths;
+  if (q <= 0 || q > 8) q = q == 0 ? 7 : 8;  // 0: seven eighths (measured best at n = 32768)
+  if (ctx->aux && ctx->aux_e != q) {
     HIPCHK(hipStreamSynchronize(ctx->aux));
     HIPCHK(hipStreamDestroy(ctx->aux));
     ctx->aux = nullptr;
@@ -441,10 +441,10 @@ static krr_status context_aux(krr_context ctx) {
     int ncu = 0;
     HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, ctx->device));
     bool masked = false;
-    if (q < 4 && ncu > 0) {
+    if (q < 8 && ncu > 0) {
       std::vector<uint32_t> mask((ncu + 31) / 32, 0u);
       for (int i = 0; i < ncu; ++i)
-        if (((i >> 3) & 3) < q) mask[i / 32] |= 1u << (i % 32);
+        if (((i >> 3) & 7) < q) mask[i / 32] |= 1u << (i % 32);
       masked = hipExtStreamCreateWithCUMask(&ctx->aux, (uint32_t)mask.size(), mask.data()) ==
                hipSuccess;
       if (!masked) {
@@ -453,7 +453,7 @@ static krr_status context_aux(krr_context ctx) {
       }
     }
     if (!masked) HIPCHK(hipStreamCreateWithFlags(&ctx->aux, hipStreamNonBlocking));
-    ctx->aux_q = masked ? q : 4;
+    ctx->aux_e = masked ? q : 8;
   }
   return KRR_SUCCESS;
 }
@@ -2231,8 +2231,8 @@ krr_status krr_factor_copy_l(krr_factorization F, int64_t i0, int64_t j0, int64_
 static bool tuning_valid(const krr_tuning &t) {
   return (t.tile == 256 || t.tile == 512) && t.panel_group >= 0 && t.panel_group <= KRR_MAX_GROUP &&
          t.residual_split >= 0 && t.residual_split <= 16 && t.sweep_pairs >= -1 &&
-         t.sweep_pairs <= 1 && t.lookahead >= -1 && t.lookahead <= 1 && t.aux_cu_quarters >= 0 &&
-         t.aux_cu_quarters <= 4;
+         t.sweep_pairs <= 1 && t.lookahead >= -1 && t.lookahead <= 1 && t.aux_cu_eighths >= 0 &&
+         t.aux_cu_eighths <= 8;
 }
 
 krr_status krr_set_tuning(krr_context ctx, const krr_tuning *t) {
@@ -2285,7 +2285,7 @@ static bool cache_parse_line(const char *line, std::string &key, krr_tuning &t, 
   int tile, g, z, pr, la, aq;
   well_formed = sscanf(q1 + 1,
                        " : {\"tile\": %d, \"panel_group\": %d, \"residual_split\": %d, "
-                       "\"sweep_pairs\": %d, \"lookahead\": %d, \"aux_cu_quarters\": %d, "
+                       "\"sweep_pairs\": %d, \"lookahead\": %d, \"aux_cu_eighths\": %d, "
                        "\"ms\": %lf}",
                        &tile, &g, &z, &pr, &la, &aq, &ms) == 7;
   if (well_formed) {
@@ -2340,9 +2340,9 @@ krr_status krr_tuning_cache_store(const char *path, const char *key, const krr_t
   char buf[1024];
   snprintf(buf, sizeof buf,
            "\"%s\": {\"tile\": %d, \"panel_group\": %d, \"residual_split\": %d, "
-           "\"sweep_pairs\": %d, \"lookahead\": %d, \"aux_cu_quarters\": %d, \"ms\": %.6f}",
+           "\"sweep_pairs\": %d, \"lookahead\": %d, \"aux_cu_eighths\": %d, \"ms\": %.6f}",
            key, t->tile, t->panel_group, t->residual_split, t->sweep_pairs, t->lookahead,
-           t->aux_cu_quarters, ms);
+           t->aux_cu_eighths, ms);
   lines[key] = buf;
   std::string tmp = std::string(path) + ".tmp";
   FILE *f = fopen(tmp.c_str(), "w");
@@ -2439,9 +2439,9 @@ krr_status krr_autotune(krr_context ctx, const int8_t *G, int64_t n, int64_t m, 
       consider(t, false);
     }
     const krr_tuning b3 = best;
-    for (int aq : {3, 2}) {
+    for (int aq : {8, 6}) {
       krr_tuning t = b3;
-      t.aux_cu_quarters = aq;
+      t.aux_cu_eighths = aq;
       consider(t, true);  // a new aux stream: warm it first
     }
   }

@@ -81,75 +81,158 @@ KRR_DEV void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Factor sub-block (s, s) of the tile and invert it, one workgroup of four
-// waves, blocked by 16 columns (block kb = 0..3):
-//   wave 0 factors the 16 x 16 diagonal block in registers (lane i holds row
-//   i; pivots and columns move between lanes by readlane, no barriers) and
-//   forms its inverse by column-oriented forward substitution (lane c holds
-//   column c);
-//   panel   L_ib,kb = A_ib,kb inv(L_kb,kb)^T     (16 x 16 x 4 MFMA, one wave per block)
-//   update  A_ib,jb -= L_ib,kb L_jb,kb^T, kb < jb <= ib  (MFMA, blocks spread over waves)
-// The inverse of the 64 x 64 factor is then completed block column by block
-// column (wave jb owns column jb):
-//   X_ib,jb = -inv(L_ib,ib) sum_{kb=jb}^{ib-1} L_ib,kb X_kb,jb.
+// 16 x 16 Cholesky factor of the diagonal block at (b, b) of S, in place
+// (one wave; lane li holds row li, lanes 16..63 mirror lanes 0..15), by
+// 4-column blocks c = 0, 4, 8, 12:
+//   columns c .. c+3 of every row in registers, factored column by column:
+//   the pivot of lane c+j broadcast, l = column c+j of L, and the updates of
+//   the block's later columns with l_k broadcast from lane k; the next pivot
+//   is lane c+j+1's own updated diagonal, so the chain from one pivot to the
+//   next is one FMA and one broadcast;
+//   then the rank-4 update of the trailing rows and columns by one
+//   16 x 16 x 4 MFMA (the rest of the block is left as it is).
+// L goes to the lower triangle of the block (zeros above it); rv[j] =
+// 1 / L_jj; badj: first column with a non-positive pivot (replaced by 1
+// there), or -1.
 template <typename T>
-KRR_DEV void diag64_body(T (*S)[BS + 1], T (*X)[BS + 1], T *colv, int32_t *flag,
-                            int64_t col0) {
+KRR_DEV void chol16(T (*S)[BS + 1], int b, T (&rv)[16], int &badj) {
+  typedef typename M16<T>::v4 v4;
+  const int lane = threadIdx.x & 63, li = lane & 15, lg = lane >> 4;
+  badj = -1;
+#pragma unroll
+  for (int c = 0; c < 16; c += 4) {
+    T d[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) d[q] = S[b + li][b + c + q];
+    T pivn = bcast(d[0], c);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      T piv = pivn;
+      const bool bad = !(piv > (T)0);
+      badj = (bad && badj < 0) ? c + j : badj;
+      piv = bad ? (T)1 : piv;
+      const T r = rsqrt_nr(piv);
+      rv[c + j] = r;
+      const T l = (li == c + j) ? piv * r : d[j] * r;
+      d[j] = l;
+      if (j < 3) {
+        pivn = bcast(d[j + 1] - l * l, c + j + 1);
+#pragma unroll
+        for (int k = j + 1; k < 4; ++k) d[k] -= l * bcast(l, c + k);
+      }
+    }
+    if (lane < 16) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) S[b + li][b + c + q] = (c + q <= li) ? d[q] : (T)0;
+    }
+    if (c < 12) {
+      wave_lds_sync();
+      // S_ij -= sum_t L_i,c+t L_j,c+t for i, j >= c + 4
+      const T lv = S[b + li][b + c + lg];
+      v4 acc;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[r] = S[b + M16<T>::row(r, lane)][b + li];
+      acc = M16<T>::mma(-lv, lv, acc);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = M16<T>::row(r, lane);
+        if (row >= c + 4 && li >= c + 4) S[b + row][b + li] = acc[r];
+      }
+      wave_lds_sync();
+    }
+  }
+}
+
+// Factor the 16 x 16 diagonal block b of S (one wave, all lanes): L into S
+// (zero above the diagonal), its inverse into X (lane li computes column li
+// by forward substitution with the L entries read back from LDS).
+template <typename T>
+KRR_DEV void diag16(T (*S)[BS + 1], T (*X)[BS + 1], int b, int32_t *flag, int64_t col0) {
+  const int lane = threadIdx.x & 63, li = lane & 15;
+  T rv[16];
+  int badj;
+  chol16<T>(S, b, rv, badj);
+  if (badj >= 0 && lane == 0) atomicCAS(flag, 0, (int32_t)(col0 + b + badj + 1));
+  wave_lds_sync();
+  // column li of inv(L_bb): x_q = (e_li - sum_{p<q} L_qp x_p)_q / L_qq
+  T x[16];
+#pragma unroll
+  for (int q = 0; q < 16; ++q) x[q] = (q == li) ? (T)1 : (T)0;
+#pragma unroll
+  for (int q = 0; q < 16; ++q) {
+    x[q] *= rv[q];
+#pragma unroll
+    for (int p = q + 1; p < 16; ++p) x[p] -= S[b + p][b + q] * x[q];
+  }
+  if (lane < 16) {
+#pragma unroll
+    for (int q = 0; q < 16; ++q) X[b + q][b + li] = x[q];
+  }
+}
+
+// S_ib,jb -= L_ib,kb L_jb,kb^T (16 x 16 blocks of S, one wave).
+template <typename T>
+KRR_DEV void upd16(T (*S)[BS + 1], int ib, int jb, int kb) {
+  typedef typename M16<T>::v4 v4;
+  const int lane = threadIdx.x & 63, li = lane & 15, lg = lane >> 4, b = 16 * kb;
+  v4 acc;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) acc[r] = S[16 * ib + M16<T>::row(r, lane)][16 * jb + li];
+#pragma unroll
+  for (int k0 = 0; k0 < 16; k0 += 4)
+    acc = M16<T>::mma(-S[16 * ib + li][b + k0 + lg], S[16 * jb + li][b + k0 + lg], acc);
+#pragma unroll
+  for (int r = 0; r < 4; ++r) S[16 * ib + M16<T>::row(r, lane)][16 * jb + li] = acc[r];
+}
+
+// X_ib,jb = -inv(L_ib,ib) sum_{kb=jb}^{ib-1} L_ib,kb X_kb,jb (one wave), the
+// sum staged in the output block.
+template <typename T>
+KRR_DEV void inv16(const T (*S)[BS + 1], T (*X)[BS + 1], int ib, int jb) {
+  typedef typename M16<T>::v4 v4;
+  const int lane = threadIdx.x & 63, li = lane & 15, lg = lane >> 4;
+  v4 acc = {0, 0, 0, 0};
+  for (int kb = jb; kb < ib; ++kb)
+#pragma unroll
+    for (int k0 = 0; k0 < 16; k0 += 4)
+      acc = M16<T>::mma(S[16 * ib + li][16 * kb + k0 + lg], X[16 * kb + k0 + lg][16 * jb + li], acc);
+#pragma unroll
+  for (int r = 0; r < 4; ++r) X[16 * ib + M16<T>::row(r, lane)][16 * jb + li] = acc[r];
+  wave_lds_sync();
+  T bv[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) bv[r] = X[16 * ib + 4 * r + lg][16 * jb + li];
+  v4 out = {0, 0, 0, 0};
+#pragma unroll
+  for (int r = 0; r < 4; ++r) out = M16<T>::mma(-X[16 * ib + li][16 * ib + 4 * r + lg], bv[r], out);
+  wave_lds_sync();
+#pragma unroll
+  for (int r = 0; r < 4; ++r) X[16 * ib + M16<T>::row(r, lane)][16 * jb + li] = out[r];
+}
+
+// Factor sub-block (s, s) of the tile and invert it, one workgroup of four
+// waves, blocked by 16 columns (blocks kb = 0..3).  Wave 0 carries the
+// chain from one diagonal block to the next:
+//   panel   L_ib,kb = A_ib,kb inv(L_kb,kb)^T      (wave ib-kb-1, one per block)
+//   --- barrier ---
+//   wave 0: A_kb+1,kb+1 -= L L^T, then the 16 x 16 factor and inverse of it;
+//   waves 1..3 meanwhile: the other updates A_ib,jb -= L_ib,kb L_jb,kb^T
+//   (kb < jb <= ib) and the completed inverse blocks of row kb,
+//   X_kb,jb = -inv(L_kb,kb) sum_{p=jb}^{kb-1} L_kb,p X_p,jb
+//   --- barrier ---
+// so each 16-column step takes two barriers and the next diagonal factor
+// overlaps the rest of the step.  Every block gets the same products in the
+// same order as in the plain blocked algorithm.
+template <typename T>
+KRR_DEV void diag64_body(T (*S)[BS + 1], T (*X)[BS + 1], int32_t *flag, int64_t col0) {
   typedef typename M16<T>::v4 v4;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, lg = lane >> 4;
+  if (wave == 0) diag16<T>(S, X, 0, flag, col0);
+  __syncthreads();
   for (int kb = 0; kb < 4; ++kb) {
     const int b = 16 * kb;
-    if (wave == 0) {
-      // lane li holds row li of the block (lanes 16..63 mirror lanes 0..15)
-      T d[16], rv[16];
-#pragma unroll
-      for (int q = 0; q < 16; ++q) d[q] = S[b + li][b + q];
-      int badj = -1;
-#pragma unroll
-      for (int j = 0; j < 16; ++j) {
-        T piv = bcast(d[j], j);
-        const bool bad = !(piv > (T)0);
-        badj = (bad && badj < 0) ? j : badj;
-        piv = bad ? (T)1 : piv;
-        const T r = rsqrt_nr(piv);
-        rv[j] = r;
-        const T l = (li == j) ? piv * r : d[j] * r;
-        d[j] = l;
-        if (j < 15) {
-          // column j of L: the next pivot row's entry straight from lane j+1,
-          // the rest through LDS (broadcast reads)
-          if (lane < 16) colv[li] = l;
-          wave_lds_sync();
-          d[j + 1] -= l * bcast(l, j + 1);
-#pragma unroll
-          for (int k = j + 2; k < 16; ++k) d[k] -= l * colv[k];
-        }
-      }
-      if (badj >= 0 && lane == 0) atomicCAS(flag, 0, (int32_t)(col0 + b + badj + 1));
-      if (lane < 16) {
-#pragma unroll
-        for (int q = 0; q < 16; ++q) S[b + li][b + q] = (q <= li) ? d[q] : (T)0;
-      }
-      wave_lds_sync();
-      // column li of inv(L_kb,kb): x_q = (e_li - sum_{p<q} L_qp x_p)_q / L_qq
-      T x[16];
-#pragma unroll
-      for (int q = 0; q < 16; ++q) x[q] = (q == li) ? (T)1 : (T)0;
-#pragma unroll
-      for (int q = 0; q < 16; ++q) {
-        x[q] *= rv[q];
-#pragma unroll
-        for (int p = q + 1; p < 16; ++p) x[p] -= S[b + p][b + q] * x[q];
-      }
-      if (lane < 16) {
-#pragma unroll
-        for (int q = 0; q < 16; ++q) X[b + q][b + li] = x[q];
-      }
-    }
-    __syncthreads();
-    if (kb == 3) break;
-    {
+    if (kb < 3) {
       const int ib = kb + 1 + wave;
       if (ib < 4) {
         v4 acc = {0, 0, 0, 0};
@@ -159,53 +242,28 @@ KRR_DEV void diag64_body(T (*S)[BS + 1], T (*X)[BS + 1], T *colv, int32_t *flag,
 #pragma unroll
         for (int r = 0; r < 4; ++r) S[16 * ib + M16<T>::row(r, lane)][b + li] = acc[r];
       }
+      __syncthreads();
     }
-    __syncthreads();
-    {
-      const int rem = 3 - kb, npair = rem * (rem + 1) / 2;
-      for (int pi = wave; pi < npair; pi += 4) {
-        int jb = kb + 1, ib = 0, t = pi;
-        while (t >= 4 - jb) { t -= 4 - jb; ++jb; }
-        ib = jb + t;
-        v4 acc;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) acc[r] = S[16 * ib + M16<T>::row(r, lane)][16 * jb + li];
-#pragma unroll
-        for (int k0 = 0; k0 < 16; k0 += 4)
-          acc = M16<T>::mma(-S[16 * ib + li][b + k0 + lg], S[16 * jb + li][b + k0 + lg], acc);
-#pragma unroll
-        for (int r = 0; r < 4; ++r) S[16 * ib + M16<T>::row(r, lane)][16 * jb + li] = acc[r];
+    if (wave == 0) {
+      if (kb < 3) {
+        upd16<T>(S, kb + 1, kb + 1, kb);
+        wave_lds_sync();
+        diag16<T>(S, X, 16 * (kb + 1), flag, col0);
       }
+    } else {
+      // pairs (ib, jb), kb < jb <= ib < 4, other than (kb+1, kb+1), then
+      // the inverse blocks (kb, jb), jb < kb, dealt over waves 1..3
+      int item = 0;
+      for (int jb = kb + 1; jb < 4; ++jb)
+        for (int ib = jb; ib < 4; ++ib) {
+          if (ib == kb + 1 && jb == kb + 1) continue;
+          if (item++ % 3 == wave - 1) upd16<T>(S, ib, jb, kb);
+        }
+      for (int jb = 0; jb < kb; ++jb)
+        if (item++ % 3 == wave - 1) inv16<T>(S, X, kb, jb);
     }
     __syncthreads();
   }
-  if (wave < 3) {
-    const int jb = wave;
-    for (int ib = jb + 1; ib < 4; ++ib) {
-      v4 acc = {0, 0, 0, 0};
-      for (int kb = jb; kb < ib; ++kb)
-#pragma unroll
-        for (int k0 = 0; k0 < 16; k0 += 4)
-          acc = M16<T>::mma(S[16 * ib + li][16 * kb + k0 + lg], X[16 * kb + k0 + lg][16 * jb + li],
-                            acc);
-      // stage the sum in the output block, then X_ib,jb = -inv(L_ib,ib) * sum
-#pragma unroll
-      for (int r = 0; r < 4; ++r) X[16 * ib + M16<T>::row(r, lane)][16 * jb + li] = acc[r];
-      wave_lds_sync();
-      T bv[4];
-#pragma unroll
-      for (int r = 0; r < 4; ++r) bv[r] = X[16 * ib + 4 * r + lg][16 * jb + li];
-      v4 out = {0, 0, 0, 0};
-#pragma unroll
-      for (int r = 0; r < 4; ++r)
-        out = M16<T>::mma(-X[16 * ib + li][16 * ib + 4 * r + lg], bv[r], out);
-      wave_lds_sync();
-#pragma unroll
-      for (int r = 0; r < 4; ++r) X[16 * ib + M16<T>::row(r, lane)][16 * jb + li] = out[r];
-      wave_lds_sync();
-    }
-  }
-  __syncthreads();
 }
 
 // Write L (zero above the diagonal) and inv(L) of a factored 64 x 64 block.
@@ -226,7 +284,6 @@ KRR_DEV void potrf_diag64_first(const T *__restrict__ W, T *__restrict__ WL, int
                                 T *__restrict__ Dinv, int32_t *flag, int64_t colbase) {
   __shared__ T S[BS][BS + 1];  // the block, overwritten by L
   __shared__ T X[BS][BS + 1];  // inv(L)
-  __shared__ T colv[16];       // current column of a 16 x 16 factor
   {
     T v[16];
 #pragma unroll
@@ -241,7 +298,7 @@ KRR_DEV void potrf_diag64_first(const T *__restrict__ W, T *__restrict__ WL, int
     }
   }
   __syncthreads();
-  diag64_body<T>(S, X, colv, flag, colbase);
+  diag64_body<T>(S, X, flag, colbase);
   diag64_store<T>(S, X, WL, nb, Dinv);
 }
 
@@ -329,7 +386,6 @@ KRR_DEV void potrf_step_body(T *__restrict__ W, T *__restrict__ WL, int nb, int 
                              T *__restrict__ Dinv, int32_t *flag, int64_t colbase, int bid) {
   typedef typename M16<T>::v4 v4;
   __shared__ T buf[3][BS][BS + 1];
-  __shared__ T colv[16];
   int a, b;
   tri_decode(bid, a, b);
   a += s + 1;
@@ -337,6 +393,21 @@ KRR_DEV void potrf_step_body(T *__restrict__ W, T *__restrict__ WL, int nb, int 
   T(*Xa)[BS + 1] = buf[0];
   T(*Xb)[BS + 1] = buf[1];
   T(*Li)[BS + 1] = buf[2];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  T *Wab = W + (int64_t)(a * BS) * nb + b * BS;
+  const bool diag = a == s + 1 && b == s + 1;
+  // the next diagonal block's entries, loaded with the operands so that
+  // their latency is not on the path to its factorization
+  T wv[4][4];
+  if (diag) {
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = 16 * wave + M16<T>::row(r, lane), col = 16 * ct + (lane & 15);
+        wv[ct][r] = (col <= row) ? Wab[(int64_t)row * nb + col] : (T)0;
+      }
+  }
   load64(Xa, W + (int64_t)(a * BS) * nb + s * BS, nb);
   load64(Li, Dinv + (int64_t)s * BS * BS, BS);
   if (a != b) load64(Xb, W + (int64_t)(b * BS) * nb + s * BS, nb);
@@ -356,21 +427,19 @@ KRR_DEV void potrf_step_body(T *__restrict__ W, T *__restrict__ WL, int nb, int 
   v4 acc[4];
   zero4<T>(acc);
   mm64<T, true>(Xa, a == b ? Xa : Xb, acc);
-  T *Wab = W + (int64_t)(a * BS) * nb + b * BS;
-  if (a == s + 1 && b == s + 1) {
+  if (diag) {
     // buf[2] (inv(L_ss)) and buf[1] (unused: a == b) take the next block
     T(*S)[BS + 1] = buf[2];
     T(*X)[BS + 1] = buf[1];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
     for (int ct = 0; ct < 4; ++ct)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int row = 16 * wave + M16<T>::row(r, lane), col = 16 * ct + (lane & 15);
-        S[row][col] = (col <= row) ? Wab[(int64_t)row * nb + col] - acc[ct][r] : (T)0;
+        S[row][col] = (col <= row) ? wv[ct][r] - acc[ct][r] : (T)0;
       }
     __syncthreads();
-    diag64_body<T>(S, X, colv, flag, colbase + (int64_t)a * BS);
+    diag64_body<T>(S, X, flag, colbase + (int64_t)a * BS);
     diag64_store<T>(S, X, WL + (int64_t)(a * BS) * nb + a * BS, nb, Dinv + (int64_t)a * BS * BS);
   } else {
     store64<T, true>(Wab, nb, acc, (T)-1);
@@ -633,35 +702,53 @@ KRR_DEV void trsm_panel_body(const float *__restrict__ Astore, const T *__restri
   float mx = 0.0f;
   for (int s = 0; s < nb / BS; ++s) {
     const int c0 = BS * s + 16 * wave;  // this wave's 16 output columns
-    // B(kk, c) = L[c0 + c][kk] over kk < 64 s
+    // this step's A entries and inv(L_ss) row, loaded before the sum so that
+    // their latency overlaps it
+    float av[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) av[r] = A[(int64_t)M16<T>::row(r, lane) * nb + c0 + li];
+    const T *Drow = Dinvk + (int64_t)s * BS * BS + (16 * wave + li) * BS;
+    T dv[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) dv[u] = Drow[4 * u + lg];
+    // B(kk, c) = L[c0 + c][kk] over kk < 64 s, 64 columns of k per chunk;
+    // the loads of chunk c+1 are issued before the MFMAs of chunk c
     const T *Lrow = WLk + (int64_t)(c0 + li) * nb;
     v4 acc = {0, 0, 0, 0};
-    // 64 columns of k per iteration, all sixteen loads (L_kk, in L2) issued
-    // before the MFMAs: this loop is bound by load latency
-    for (int k64 = 0; k64 < BS * s; k64 += BS) {
-      T bv[16];
+    const int nch = s;
+    if (nch > 0) {
+      T b0[16], b1[16];
 #pragma unroll
-      for (int u = 0; u < 16; ++u) bv[u] = Lrow[k64 + 4 * u + lg];
+      for (int u = 0; u < 16; ++u) b0[u] = Lrow[4 * u + lg];
+      for (int ch = 0; ch < nch; ch += 2) {
+        const int k0 = BS * ch;
+        if (ch + 1 < nch) {
 #pragma unroll
-      for (int u = 0; u < 16; ++u) acc = M16<T>::mma(Pr[li][k64 + 4 * u + lg], bv[u], acc);
+          for (int u = 0; u < 16; ++u) b1[u] = Lrow[k0 + BS + 4 * u + lg];
+        }
+#pragma unroll
+        for (int u = 0; u < 16; ++u) acc = M16<T>::mma(Pr[li][k0 + 4 * u + lg], b0[u], acc);
+        if (ch + 1 < nch) {
+          if (ch + 2 < nch) {
+#pragma unroll
+            for (int u = 0; u < 16; ++u) b0[u] = Lrow[k0 + 2 * BS + 4 * u + lg];
+          }
+#pragma unroll
+          for (int u = 0; u < 16; ++u)
+            acc = M16<T>::mma(Pr[li][k0 + BS + 4 * u + lg], b1[u], acc);
+        }
+      }
     }
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int row = M16<T>::row(r, lane);
-      Tb[row][16 * wave + li] = (T)A[(int64_t)row * nb + c0 + li] - acc[r];
+      Tb[row][16 * wave + li] = (T)av[r] - acc[r];
     }
     __syncthreads();
     // P[:, c0 ..] = Tb inv(L_ss)^T: B(j, c) = inv(L_ss)[16 w + c][j]
-    const T *Drow = Dinvk + (int64_t)s * BS * BS + (16 * wave + li) * BS;
     v4 acc2 = {0, 0, 0, 0};
 #pragma unroll
-    for (int j = 0; j < BS; j += 16) {
-      T bv[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) bv[u] = Drow[j + 4 * u + lg];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) acc2 = M16<T>::mma(Tb[li][j + 4 * u + lg], bv[u], acc2);
-    }
+    for (int u = 0; u < 16; ++u) acc2 = M16<T>::mma(Tb[li][4 * u + lg], dv[u], acc2);
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int row = M16<T>::row(r, lane);

@@ -153,9 +153,9 @@ def test_tuning_cache_round_trip(lib, tmp_path):
     path = str(tmp_path / "tune.json")
     assert krr.krr_tuning_cache_load(path, "k1") is None  # no file yet
     a = {"tile": 512, "panel_group": 8, "residual_split": 8, "sweep_pairs": 1, "lookahead": 1,
-         "aux_cu_quarters": 3}
+         "aux_cu_eighths": 7}
     b = {"tile": 256, "panel_group": 4, "residual_split": 16, "sweep_pairs": 0, "lookahead": -1,
-         "aux_cu_quarters": 0}
+         "aux_cu_eighths": 0}
     krr.krr_tuning_cache_store(path, "gfx950|cu256|n32768|m65536|r16|mode1|d641|ref1", a, 85.25)
     krr.krr_tuning_cache_store(path, "k2", b, 12.5)
     assert krr.krr_tuning_cache_load(path, "gfx950|cu256|n32768|m65536|r16|mode1|d641|ref1") == \
