@@ -428,12 +428,16 @@ typedef struct krr_tuning {
   int32_t tile;           /* Cholesky tile nb: 256 or 512 */
   int32_t panel_group;    /* panels per grouped trailing update, 1 .. 8 (0: 8 for FP16/FP8
                              updates, 4 for FP32) */
-  int32_t residual_split; /* column ranges of the FP64 residual, 1 .. 16 (0: min(8, NT)) */
+  int32_t residual_split; /* column ranges of the FP64 residual, 1 .. 16, each stored tile
+                             read twice (0: min(8, NT)); -1: each stored tile read once, its
+                             two products in slots of their own (NT np nrhs doubles of
+                             workspace, used up to 1 GiB, else the default) */
   int32_t sweep_pairs;    /* 1: triangular sweeps over tile pairs, 0: one tile per step (-1: 1) */
   int32_t lookahead;      /* 1: three-stream factorization schedule, 0: one stream (-1: 1) */
   int32_t aux_cu_eighths; /* eighths of the compute units the stream of the wide trailing
-                             updates may use, 1 .. 8 (0: 7); the rest stay free for the
-                             critical path (a CU mask over groups of eight CUs) */
+                             updates may use, 1 .. 8 (0: all); the rest stay free for the
+                             critical path (a CU mask over groups of eight CUs; not searched
+                             by krr_autotune) */
 } krr_tuning;
 
 /* Set or read the context's tuning.  Changing the tile needs a context with
@@ -446,8 +450,8 @@ krr_status krr_get_tuning(krr_context ctx, krr_tuning *t);
  * whole build + factor + solve steps (HIP events on the context stream) on
  * the caller's data, searching one choice at a time: the tile (256, 512,
  * each after an untimed warm-up), then the panel group (4, 6, 8), the
- * residual split (4, 8, 16), the sweep pairing and the compute units of the
- * wide-update stream (7, 8, 6 eighths), each at the best choices so far.
+ * residual form (8, 4 or 16 column ranges with each stored tile read twice,
+ * or each read once) and the sweep pairing, each at the best choices so far.
  * The result is kept in the context (krr_get_tuning) and written to
  * *out and *best_ms.  With cache_path (a host path, may be NULL) the choice
  * is looked up first under the key of krr_tuning_key, and stored there after
@@ -500,6 +504,12 @@ enum {
  * accumulated totals.  While enabled, every stage launch is bracketed by a
  * pair of HIP events recorded on the context stream. */
 krr_status krr_timers_enable(krr_context ctx, int32_t enable);
+/* Time only the stages whose bit (1 << KRR_STAGE_*) is set in stage_mask (0:
+ * none), clearing the totals.  Each timed stage launch records two events;
+ * between dependent launches of the factorization they cost a few
+ * microseconds each, so a timed run of every stage is slower than an
+ * untimed one (about 2 ms per step at n = 32768). */
+krr_status krr_timers_enable_stages(krr_context ctx, uint32_t stage_mask);
 /* Wait for the stream, then return per-stage accumulated GPU time (ms) and
  * the number of timed intervals, for the first `count` stages (host arrays;
  * either may be NULL). */

@@ -136,6 +136,7 @@ _SIGS = [
     ("krr_tuning_cache_load", _I, [ctypes.c_char_p, ctypes.c_char_p, ctypes.POINTER(krr_tuning),
                                    ctypes.POINTER(_D), ctypes.POINTER(ctypes.c_int32)]),
     ("krr_timers_enable", _I, [_P, ctypes.c_int32]),
+    ("krr_timers_enable_stages", _I, [_P, ctypes.c_uint32]),
     ("krr_timers_read", _I, [_P, _P, _P, ctypes.c_int32]),
     ("krr_stage_name", ctypes.c_char_p, [ctypes.c_int32]),
     ("krr_status_string", ctypes.c_char_p, [_I]),
@@ -383,6 +384,16 @@ def krr_tuning_cache_load(path: str, key: str):
 
 def krr_timers_enable(ctx: Context, enable: bool = True):
     _check(load().krr_timers_enable(ctx.handle, 1 if enable else 0), "krr_timers_enable")
+
+
+def krr_timers_enable_stages(ctx: Context, stages):
+    """Time only the named stages (names as krr_timers_read returns them)."""
+    lib = load()
+    names = {lib.krr_stage_name(i).decode(): i for i in range(KRR_STAGE_COUNT)}
+    mask = 0
+    for s in stages:
+        mask |= 1 << names[s]
+    _check(lib.krr_timers_enable_stages(ctx.handle, mask), "krr_timers_enable_stages")
 
 
 def krr_timers_read(ctx: Context) -> dict:

@@ -34,7 +34,7 @@ struct krr_context_s {
   size_t cached = 0;
   std::unordered_map<void *, size_t> live_sizes;
   // stage timers
-  bool timing = false;
+  uint32_t timing = 0;  // bit s: stage s is timed
   std::vector<TimerRec> recs;
   std::vector<hipEvent_t> pool;
   double total_ms[KRR_STAGE_COUNT] = {};
@@ -256,7 +256,7 @@ struct Stage {
   int64_t idx = -1;
   Stage(krr_context ctx, int stage, hipStream_t stream = nullptr) : c(ctx) {
     st = stream ? stream : c->stream;
-    if (!c->timing) return;
+    if (!((c->timing >> stage) & 1u)) return;
     TimerRec r{stage, take_event(c), take_event(c)};
     if (!r.a || !r.b) return;
     if (hipEventRecord(r.a, st) != hipSuccess) return;
@@ -298,6 +298,10 @@ const char *krr_stage_name(int32_t stage) {
 }
 
 krr_status krr_timers_enable(krr_context ctx, int32_t enable) {
+  return krr_timers_enable_stages(ctx, enable ? (1u << KRR_STAGE_COUNT) - 1u : 0u);
+}
+
+krr_status krr_timers_enable_stages(krr_context ctx, uint32_t stage_mask) {
   if (!ctx) return KRR_ERROR_INVALID_VALUE;
   HIPCHK(hipSetDevice(ctx->device));
   timers_drain(ctx);
@@ -305,7 +309,7 @@ krr_status krr_timers_enable(krr_context ctx, int32_t enable) {
     ctx->total_ms[i] = 0;
     ctx->intervals[i] = 0;
   }
-  ctx->timing = enable != 0;
+  ctx->timing = stage_mask & ((1u << KRR_STAGE_COUNT) - 1u);
   return KRR_SUCCESS;
 }
 
@@ -423,15 +427,17 @@ static void context_free(krr_context ctx) {
 // (the critical path), a side stream and an aux stream.
 // The aux stream (the wide trailing updates, off the critical path) may be
 // limited to q eighths of the compute units, so that the main and side
-// streams find free ones: CU i is enabled when (i / 8) % 8 < q.  (Quarters
-// spread the same way, (i / 8) % 4 < q, measured slower at the benchmark
-// size.)  KRR_AUX_CU_EIGHTHS overrides the tuning.
+// streams find free ones: CU i is enabled when (i / 8) % 8 < q.  Not the
+// default and not searched by the autotuner: seven eighths took the adaptive
+// path at n = 32768 from 82 to 81 ms per step, but the plain FP32 path (whose
+// wide updates are most of its work) from 138 to 207 ms, and a masked stream
+// is a hardware queue of its own.  KRR_AUX_CU_EIGHTHS overrides the tuning.
 static krr_status context_aux(krr_context ctx) {
   for (hipStream_t *x : {&ctx->fmain, &ctx->side})
     if (!*x) HIPCHK(hipStreamCreateWithFlags(x, hipStreamNonBlocking));
   const char *e = getenv("KRR_AUX_CU_EIGHTHS");
   int q = e ? atoi(e) : ctx->tune.aux_cu_eighths;
-  if (q <= 0 || q > 8) q = q == 0 ? 7 : 8;  // 0: seven eighths (measured best at n = 32768)
+  if (q <= 0 || q > 8) q = 8;
   if (ctx->aux && ctx->aux_e != q) {
     HIPCHK(hipStreamSynchronize(ctx->aux));
     HIPCHK(hipStreamDestroy(ctx->aux));
@@ -1572,6 +1578,7 @@ struct SolveBufs {
   const float *C = nullptr;  // coupling tiles of the paired sweeps, or null
   double *cw = nullptr;      // workspace of the column reductions
   int z = 1;                 // column ranges of the residual (Pr holds z np r)
+  bool once = false;         // residual with each stored tile read once (z = NT slots)
 };
 
 // The coupling tiles of the paired sweeps, formed on the first solve with a
@@ -1597,9 +1604,14 @@ static krr_status sweep_coupling(krr_context ctx, krr_factorization F, Scoped &s
   return KRR_SUCCESS;
 }
 
+// z: column ranges of the residual with each stored tile read twice (0:
+// min(8, NT)); z = -1: each stored tile read once (one slot per partner
+// tile) when its slots take at most 1 GiB, else the default.
 static krr_status solve_alloc(Scoped &sc, const TileLayout &L, int r, SolveBufs &b, int z) {
   const int64_t cnt = L.np * r;
-  b.z = std::max(1, std::min(z, L.nt));
+  b.once = z == -1 && residual_once_bytes(L, r) <= ((int64_t)1 << 30);
+  if (z <= 0 && !b.once) z = residual_split(L);
+  b.z = b.once ? L.nt : std::max(1, std::min(z, L.nt));
   CHK(sc.alloc(&b.Pr, cnt * b.z));
   CHK(sc.alloc(&b.Yr, cnt));
   CHK(sc.alloc(&b.Xr, cnt));
@@ -1637,8 +1649,12 @@ static void residual_norms(krr_context ctx, krr_factorization F, int r, SolveBuf
   const TileLayout &L = F->L;
   {
     Stage t(ctx, KRR_STAGE_RESIDUAL, s);
-    launch_residual(K->D, K->etab, K->etab_len, K->gamma, K->vmode(), K->Ec, K->lambda, L, r,
-                    b.Xr, b.Yr, b.Rr, b.Pr, b.z, s);
+    if (b.once)
+      launch_residual_once(K->D, K->etab, K->etab_len, K->gamma, K->vmode(), K->Ec, K->lambda, L,
+                           r, b.Xr, b.Yr, b.Rr, b.Pr, s);
+    else
+      launch_residual(K->D, K->etab, K->etab_len, K->gamma, K->vmode(), K->Ec, K->lambda, L, r,
+                      b.Xr, b.Yr, b.Rr, b.Pr, b.z, s);
   }
   launch_col_norms(b.Rr, L.np, r, b.cn, b.cw, s);
   launch_col_norms(b.Xr, L.np, r, b.cn + r, b.cw, s);
@@ -1699,8 +1715,12 @@ static krr_status pcg_run(krr_context ctx, krr_factorization F, int r, SolveBufs
   while (it < o.max_iters) {
     {
       Stage t(ctx, KRR_STAGE_RESIDUAL, s);
-      launch_residual(K->D, K->etab, K->etab_len, K->gamma, K->vmode(), K->Ec, K->lambda, L,
-                      r, pb.P, pb.Y0, pb.Nq, b.Pr, b.z, s);
+      if (b.once)
+        launch_residual_once(K->D, K->etab, K->etab_len, K->gamma, K->vmode(), K->Ec, K->lambda,
+                             L, r, pb.P, pb.Y0, pb.Nq, b.Pr, s);
+      else
+        launch_residual(K->D, K->etab, K->etab_len, K->gamma, K->vmode(), K->Ec, K->lambda, L,
+                        r, pb.P, pb.Y0, pb.Nq, b.Pr, b.z, s);
     }
     launch_col_dots(pb.P, pb.Nq, L.np, r, pnq, b.cw, s);
     launch_pcg_step(b.Xr, b.Rr, pb.P, pb.Nq, rho, pnq, cnt, r, s);
@@ -1739,7 +1759,7 @@ krr_status krr_solve(krr_context ctx, krr_factorization F, const double *Y, int6
   Scoped sc(ctx);
   SolveBufs b;
   CHK(solve_alloc(sc, L, r, b,
-                  ctx->tune.residual_split > 0 ? ctx->tune.residual_split : residual_split(L)));
+                  ctx->tune.residual_split));
   CHK(sweep_coupling(ctx, F, sc, b, s));
   launch_colmajor_to_rows(Y, L.n, ldy, r, L.np, b.Yr, s);
   launch_fill_f64(b.Xr, cnt, 0.0, s);
@@ -2230,7 +2250,7 @@ krr_status krr_factor_copy_l(krr_factorization F, int64_t i0, int64_t j0, int64_
 
 static bool tuning_valid(const krr_tuning &t) {
   return (t.tile == 256 || t.tile == 512) && t.panel_group >= 0 && t.panel_group <= KRR_MAX_GROUP &&
-         t.residual_split >= 0 && t.residual_split <= 16 && t.sweep_pairs >= -1 &&
+         t.residual_split >= -1 && t.residual_split <= 16 && t.sweep_pairs >= -1 &&
          t.sweep_pairs <= 1 && t.lookahead >= -1 && t.lookahead <= 1 && t.aux_cu_eighths >= 0 &&
          t.aux_cu_eighths <= 8;
 }
@@ -2427,7 +2447,7 @@ krr_status krr_autotune(krr_context ctx, const int8_t *G, int64_t n, int64_t m, 
       consider(t, false);
     }
     const krr_tuning b1 = best;
-    for (int z : {4, 8, 16}) {
+    for (int z : {-1, 4, 16}) {
       krr_tuning t = b1;
       t.residual_split = z;
       consider(t, false);
@@ -2437,12 +2457,6 @@ krr_status krr_autotune(krr_context ctx, const int8_t *G, int64_t n, int64_t m, 
       krr_tuning t = b2;
       t.sweep_pairs = pr;
       consider(t, false);
-    }
-    const krr_tuning b3 = best;
-    for (int aq : {8, 6}) {
-      krr_tuning t = b3;
-      t.aux_cu_eighths = aq;
-      consider(t, true);  // a new aux stream: warm it first
     }
   }
   (void)hipEventDestroy(e0);

@@ -154,15 +154,15 @@ KRR_DEV void diag16(T (*S)[BS + 1], T (*X)[BS + 1], int b, int32_t *flag, int64_
   chol16<T>(S, b, rv, badj);
   if (badj >= 0 && lane == 0) atomicCAS(flag, 0, (int32_t)(col0 + b + badj + 1));
   wave_lds_sync();
-  // column li of inv(L_bb): x_q = (e_li - sum_{p<q} L_qp x_p)_q / L_qq
+  // column li of inv(L_bb): x_q = (e_li - sum_{p<q} L_qp x_p)_q / L_qq,
+  // row q of L read as a contiguous (broadcast) run, the sum in p order
   T x[16];
 #pragma unroll
-  for (int q = 0; q < 16; ++q) x[q] = (q == li) ? (T)1 : (T)0;
-#pragma unroll
   for (int q = 0; q < 16; ++q) {
-    x[q] *= rv[q];
+    T acc = (q == li) ? (T)1 : (T)0;
 #pragma unroll
-    for (int p = q + 1; p < 16; ++p) x[p] -= S[b + p][b + q] * x[q];
+    for (int p = 0; p < q; ++p) acc -= S[b + q][b + p] * x[p];
+    x[q] = acc * rv[q];
   }
   if (lane < 16) {
 #pragma unroll

@@ -250,6 +250,14 @@ void launch_residual(const int32_t *D, const double *etab, int64_t etab_len, dou
                      int vmode, const double *Ec, double lambda, const TileLayout &L, int r,
                      const double *X, const double *Y, double *R, double *part, int nsplit,
                      hipStream_t s);
+// The same residual with every stored tile of D read once (each tile's two
+// products into slots of their own, summed in fixed order): part holds
+// residual_once_bytes(L, r) bytes (NT * np * r doubles).
+int64_t residual_once_bytes(const TileLayout &L, int r);
+void launch_residual_once(const int32_t *D, const double *etab, int64_t etab_len, double gamma,
+                          int vmode, const double *Ec, double lambda, const TileLayout &L, int r,
+                          const double *X, const double *Y, double *R, double *part,
+                          hipStream_t s);
 // Batched (lockstep over a table of instances, tile counts up to ntmax):
 // both sweeps, L Z = B then L^T X = Z.
 void launch_sweeps_batched(const SolveJob *jobs, int njobs, int ntmax, int nb, int r,

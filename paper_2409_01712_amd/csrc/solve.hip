@@ -508,6 +508,15 @@ constexpr int RES_DEG = 7;
 constexpr double RES_XMAX = 0.02;  // 0.02^8 / 8! < 2^-60
 constexpr int RES_HI_MAX = 2048;   // entries of the LDS table
 
+// The two tables of VM 3 from etab: ehi[h] = etab[512 h], elo[l] = etab[l]
+// (EXP_LO = 512 entries), written by the whole workgroup (visible after its
+// next barrier).
+KRR_DEV void res_tables(const double *__restrict__ etab, int64_t dmax, double *ehi, double *elo) {
+  const int nhi = (int)(dmax / EXP_LO) + 1;
+  for (int q = threadIdx.x; q < EXP_LO; q += blockDim.x) elo[q] = etab[min((int64_t)q, dmax)];
+  for (int q = threadIdx.x; q < nhi; q += blockDim.x) ehi[q] = etab[(int64_t)q * EXP_LO];
+}
+
 // Residual R = Y - (K + lambda I) X over the packed lower tiles of int32
 // distances, in FP64 (16 x 16 x 4 MFMA).  A workgroup owns 64 rows of tile
 // row I (wave w: rows 16w .. 16w+15) and 16 NCB columns, and walks all n
@@ -519,7 +528,9 @@ constexpr int RES_HI_MAX = 2048;   // entries of the LDS table
 // table in memory (VM 0, one gather per entry).
 // VM: how a stored integer becomes the FP64 kernel value -- 0 the table
 // etab[d], 1 the factored exponential above, 2 the integer itself (linear
-// kernel).  CONF: every kernel entry times its FP64 confounder factor Ec (the
+// kernel), 3 the two-level product of LDS tables, exp(-gamma 512 h)
+// exp(-gamma l) for d = 512 h + l, both factors entries of etab (the same
+// values the build uses).  CONF: every kernel entry times its FP64 confounder factor Ec (the
 // same packed layout as D), loaded beside the distance.
 template <int NCB, int VM, bool CONF = false>
 __device__ __forceinline__ void residual_body(const int32_t *__restrict__ D,
@@ -530,7 +541,7 @@ __device__ __forceinline__ void residual_body(const int32_t *__restrict__ D,
                                               int bz, int nz,
                                               const double *__restrict__ Ec = nullptr) {
   constexpr int XC = 16 * NCB, XLD = XC + 2, XPT = XC / 4;  // X values per thread and step
-  __shared__ double ehi[RES_HI_MAX];
+  __shared__ double ehi[RES_HI_MAX], elo[VM == 3 ? EXP_LO : 1];
   __shared__ double xs[2][64 * XLD];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, lg = lane >> 4;
@@ -539,6 +550,7 @@ __device__ __forceinline__ void residual_body(const int32_t *__restrict__ D,
     const int nhi = (int)(dmax >> wshift) + 2;
     for (int q = tid; q < nhi; q += 256) ehi[q] = exp(-gamma * (double)((int64_t)q << wshift));
   }
+  if (VM == 3) res_tables(etab, dmax, ehi, elo);
   const int64_t r0 = bx * 64;  // first row of the workgroup
   const int I = (int)(r0 / nb), rloc = (int)(r0 % nb) + wave * 16;
   const int col0 = by * XC;
@@ -595,6 +607,7 @@ __device__ __forceinline__ void residual_body(const int32_t *__restrict__ D,
     if (VM == 2) return (double)d;
     const int32_t dd = (int32_t)min((int64_t)max(d, 0), dmax);
     if (VM == 0) return etab[dd];
+    if (VM == 3) return exp_two_level(ehi, elo, dd);
     const int32_t h = (dd + half) >> wshift;
     const double x = gamma * (double)((h << wshift) - dd);
     double p = 1.0 / 5040.0;  // 1 / RES_DEG!
@@ -673,6 +686,222 @@ __device__ __forceinline__ void residual_body(const int32_t *__restrict__ D,
   }
 }
 
+// The kernel value of an integer distance (VM as in residual_body): the
+// table, the factored exponential with its LDS table ehi, or the integer.
+template <int VM>
+KRR_DEV double res_kexp(int32_t d, const double *__restrict__ etab, int64_t dmax, double gamma,
+                        int wshift, const double *ehi, const double *elo) {
+  if (VM == 2) return (double)d;
+  const int32_t dd = (int32_t)min((int64_t)max(d, 0), dmax);
+  if (VM == 0) return etab[dd];
+  if (VM == 3) return exp_two_level(ehi, elo, dd);
+  const int32_t half = (1 << wshift) >> 1;
+  const int32_t h = (dd + half) >> wshift;
+  const double x = gamma * (double)((h << wshift) - dd);
+  double p = 1.0 / 5040.0;  // 1 / RES_DEG!
+  p = fma(p, x, 1.0 / 720.0);
+  p = fma(p, x, 1.0 / 120.0);
+  p = fma(p, x, 1.0 / 24.0);
+  p = fma(p, x, 1.0 / 6.0);
+  p = fma(p, x, 0.5);
+  p = fma(p, x, 1.0);
+  p = fma(p, x, 1.0);
+  return ehi[h] * p;
+}
+
+// Residual products with every stored tile read once.  A workgroup owns the
+// stored tile (I, J), I >= J (blockIdx.x in packed order), and 16 NCB columns
+// of X (blockIdx.y); it walks the tile in 64 x 64 blocks (row strip a, column
+// block c), turns each block's distances into FP64 kernel values once (in
+// LDS), and applies them both ways with 16 x 16 x 4 FP64 MFMA:
+//   R_I[strip a] += K_IJ[a, c] X_J[c]      (wave w: rows 16w ..; summed over c)
+//   R_J[c]       += K_IJ[a, c]^T X_I[a]    (wave w: columns 16w .. of each c;
+//                                           summed over a; I > J only)
+// Each sum goes to a slot of its own, part[partner][row][col] with the other
+// tile index as the partner: tile (I, J) writes slot J of the rows of I and
+// slot I of the rows of J, so every (row block, partner) pair is written
+// exactly once and k_residual_sum adds a row's NT slots in partner order.
+// The next block's distances and X rows are loaded during the current
+// block's products, and its kernel values evaluated before the barrier that
+// hands the LDS block over.
+template <int NCB, int VM, bool CONF>
+__global__ __launch_bounds__(256) void k_residual_once(const int32_t *__restrict__ D,
+                                                       const double *__restrict__ etab,
+                                                       int64_t etab_len, double gamma,
+                                                       int wshift, int64_t np, int nb, int r,
+                                                       const double *__restrict__ X,
+                                                       double *__restrict__ part,
+                                                       const double *__restrict__ Ec) {
+  constexpr int XC = 16 * NCB, XLD = XC + 2, XPT = XC / 4, KLD = 64 + 1;
+  __shared__ double ehi[RES_HI_MAX], elo[VM == 3 ? EXP_LO : 1];
+  __shared__ double ks[64 * KLD];
+  __shared__ double xj[64 * XLD], xi[64 * XLD];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 15, lg = lane >> 4;
+  const int64_t dmax = etab_len - 1;
+  if (VM == 1) {
+    const int nhi = (int)(dmax >> wshift) + 2;
+    for (int q = tid; q < nhi; q += 256) ehi[q] = exp(-gamma * (double)((int64_t)q << wshift));
+  }
+  if (VM == 3) res_tables(etab, dmax, ehi, elo);
+  int I, J;
+  tri_decode(blockIdx.x, I, J);
+  const bool both = I != J;
+  const int col0 = blockIdx.y * XC;
+  const int nblk = nb / 64;
+  const int64_t te = (int64_t)nb * nb;
+  const int32_t *Dt = D + tri_index(I, J) * te;
+  const double *Et = CONF ? Ec + tri_index(I, J) * te : nullptr;
+  // this thread's 16 entries of a 64 x 64 block: row tid / 4, columns 16 (tid % 4) ..
+  const int er = tid >> 2, ec = (tid & 3) * 16;
+  auto fetch_d = [&](int a, int c, int32_t (&d)[16], double (&f)[CONF ? 16 : 1]) {
+    const int64_t o = (int64_t)(64 * a + er) * nb + 64 * c + ec;
+    const int4 *q = (const int4 *)(Dt + o);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int4 v = q[u];
+      d[4 * u] = v.x; d[4 * u + 1] = v.y; d[4 * u + 2] = v.z; d[4 * u + 3] = v.w;
+    }
+    if constexpr (CONF) {
+      const double2 *fq = (const double2 *)(Et + o);
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const double2 v = fq[u];
+        f[2 * u] = v.x; f[2 * u + 1] = v.y;
+      }
+    }
+  };
+  // X rows row0 .. row0 + 63, columns col0 .. col0 + XC - 1 (zero past r)
+  auto fetch_x = [&](int64_t row0, double (&x)[XPT]) {
+#pragma unroll
+    for (int v = 0; v < XPT; ++v) {
+      const int e = tid + 256 * v, t = e / XC, c = col0 + e % XC;
+      const double val = X[(row0 + t) * r + min(c, r - 1)];
+      x[v] = c < r ? val : 0.0;
+    }
+  };
+  auto store_x = [&](double *xs, const double (&x)[XPT]) {
+#pragma unroll
+    for (int v = 0; v < XPT; ++v) {
+      const int e = tid + 256 * v;
+      xs[(e / XC) * XLD + e % XC] = x[v];
+    }
+  };
+  auto kvals = [&](const int32_t (&d)[16], const double (&f)[CONF ? 16 : 1], double (&kv)[16]) {
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      kv[q] = res_kexp<VM>(d[q], etab, dmax, gamma, wshift, ehi, elo);
+      if constexpr (CONF) kv[q] *= f[q];
+    }
+  };
+  auto store_k = [&](const double (&kv)[16]) {
+#pragma unroll
+    for (int q = 0; q < 16; ++q) ks[er * KLD + ec + q] = kv[q];
+  };
+
+  v4d acc_t[8][NCB];
+#pragma unroll
+  for (int c = 0; c < 8; ++c)
+#pragma unroll
+    for (int b = 0; b < NCB; ++b) acc_t[c][b] = (v4d){0.0, 0.0, 0.0, 0.0};
+  int32_t dn[16];
+  double fn[CONF ? 16 : 1], kv[16], xn[XPT], xin[XPT];
+  __syncthreads();  // the exponential table
+  // block (0, 0) into LDS
+  fetch_d(0, 0, dn, fn);
+  fetch_x((int64_t)J * nb, xn);
+  fetch_x((int64_t)I * nb, xin);
+  kvals(dn, fn, kv);
+  store_k(kv);
+  store_x(xj, xn);
+  store_x(xi, xin);
+  __syncthreads();
+  for (int a = 0; a < nblk; ++a) {
+    v4d acc_d[NCB], acc_e[NCB];
+#pragma unroll
+    for (int b = 0; b < NCB; ++b) acc_d[b] = acc_e[b] = (v4d){0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      if (c >= nblk) break;
+      // the next block: (a, c + 1), or the next strip's first block
+      const int na = c + 1 < nblk ? a : a + 1, nc = c + 1 < nblk ? c + 1 : 0;
+      const bool more = na < nblk;
+      if (more) {
+        fetch_x((int64_t)J * nb + 64 * nc, xn);
+        if (nc == 0) fetch_x((int64_t)I * nb + 64 * na, xin);
+        fetch_d(na, nc, dn, fn);
+      }
+      // R_I[strip a] += K[a, c] X_J[c] and R_J[c] += K[a, c]^T X_I[a], the
+      // MFMAs of the two sums interleaved (independent accumulators, so each
+      // chain's latency is hidden behind the other); the diagonal tile splits
+      // its direct sum over two accumulators (even and odd k) instead
+      if (both) {
+#pragma unroll
+        for (int b = 0; b < NCB; ++b)
+#pragma unroll
+          for (int k0 = 0; k0 < 64; k0 += 4) {
+            acc_d[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(
+                ks[(16 * wave + li) * KLD + k0 + lg], xj[(k0 + lg) * XLD + 16 * b + li],
+                acc_d[b], 0, 0, 0);
+            acc_t[c][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(
+                ks[(k0 + lg) * KLD + 16 * wave + li], xi[(k0 + lg) * XLD + 16 * b + li],
+                acc_t[c][b], 0, 0, 0);
+          }
+      } else {
+#pragma unroll
+        for (int b = 0; b < NCB; ++b)
+#pragma unroll
+          for (int k0 = 0; k0 < 64; k0 += 8) {
+            acc_d[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(
+                ks[(16 * wave + li) * KLD + k0 + lg], xj[(k0 + lg) * XLD + 16 * b + li],
+                acc_d[b], 0, 0, 0);
+            acc_e[b] = __builtin_amdgcn_mfma_f64_16x16x4f64(
+                ks[(16 * wave + li) * KLD + k0 + 4 + lg], xj[(k0 + 4 + lg) * XLD + 16 * b + li],
+                acc_e[b], 0, 0, 0);
+          }
+      }
+      if (more) kvals(dn, fn, kv);
+      __syncthreads();  // every wave is done with this block's LDS
+      if (more) {
+        store_k(kv);
+        store_x(xj, xn);
+        if (nc == 0) store_x(xi, xin);
+      }
+      __syncthreads();
+    }
+    // the direct sum of strip a: slot J of rows I nb + 64 a + 16 wave ..
+    if (!both) {
+#pragma unroll
+      for (int b = 0; b < NCB; ++b) acc_d[b] += acc_e[b];
+    }
+    double *P = part + (int64_t)J * np * r;
+    const int64_t g0 = (int64_t)I * nb + 64 * a + 16 * wave;
+#pragma unroll
+    for (int b = 0; b < NCB; ++b) {
+      const int col = col0 + 16 * b + li;
+      if (col >= r) continue;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) P[(g0 + 4 * i + lg) * r + col] = acc_d[b][i];
+    }
+  }
+  if (both) {
+    // the transposed sums: slot I of rows J nb + 64 c + 16 wave ..
+    double *P = part + (int64_t)I * np * r;
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      if (c >= nblk) break;
+      const int64_t g0 = (int64_t)J * nb + 64 * c + 16 * wave;
+#pragma unroll
+      for (int b = 0; b < NCB; ++b) {
+        const int col = col0 + 16 * b + li;
+        if (col >= r) continue;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) P[(g0 + 4 * i + lg) * r + col] = acc_t[c][b][i];
+      }
+    }
+  }
+}
+
 template <int NCB, int VM, bool CONF>
 __global__ __launch_bounds__(256) void k_residual(const int32_t *__restrict__ D,
                                                   const double *__restrict__ etab,
@@ -734,6 +963,16 @@ int residual_exp_shift(double gamma, int64_t etab_len) {
   return residual_wshift(gamma, etab_len - 1);
 }
 
+// The two-level tables (VM 3) fit in LDS, and are not switched off
+// (KRR_RES_EXP=taylor keeps the factored exponential of VM 1).
+static bool residual_two_level(int64_t etab_len) {
+  static const bool taylor = [] {
+    const char *e = getenv("KRR_RES_EXP");
+    return e && e[0] == 't';
+  }();
+  return !taylor && (etab_len - 1) / EXP_LO + 1 <= RES_HI_MAX;
+}
+
 void launch_residual_batched(const SolveJob *jobs, int njobs, int64_t rblocks, bool fact, int nb,
                              int r, hipStream_t s) {
   const int ncb = (r + 15) / 16;
@@ -767,6 +1006,7 @@ void launch_residual(const int32_t *D, const double *etab, int64_t etab_len, dou
   const unsigned rb = (unsigned)(L.np / 64);
   const int ncb = (r + 15) / 16, z = std::max(1, std::min(nsplit, L.nt));
   const int ws = vmode == VAL_EXP ? residual_wshift(gamma, etab_len - 1) : -1;
+  const bool two = vmode == VAL_EXP && residual_two_level(etab_len);
   const dim3 grid(rb, ncb <= 2 ? 1u : (unsigned)((r + 63) / 64), z);
 #define KRR_RES(NCB, VM, CONF)                                                      \
   hipLaunchKernelGGL((k_residual<NCB, VM, CONF>), grid, dim3(256), 0, s, D, etab, etab_len, \
@@ -780,10 +1020,12 @@ void launch_residual(const int32_t *D, const double *etab, int64_t etab_len, dou
   if (vmode == VAL_LINEAR) {
     KRR_RES2(2, false);
   } else if (Ec) {
-    if (ws >= 0) KRR_RES2(1, true);
+    if (two) KRR_RES2(3, true);
+    else if (ws >= 0) KRR_RES2(1, true);
     else KRR_RES2(0, true);
   } else {
-    if (ws >= 0) KRR_RES2(1, false);
+    if (two) KRR_RES2(3, false);
+    else if (ws >= 0) KRR_RES2(1, false);
     else KRR_RES2(0, false);
   }
 #undef KRR_RES2
@@ -791,6 +1033,43 @@ void launch_residual(const int32_t *D, const double *etab, int64_t etab_len, dou
   const int64_t tot = L.np * r;
   hipLaunchKernelGGL(k_residual_sum, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, part, z,
                      L.np, r, L.n, lambda, X, Y, R);
+}
+
+// Bytes of the slots of the read-once residual (NT partners per row block).
+int64_t residual_once_bytes(const TileLayout &L, int r) { return (int64_t)L.nt * L.np * r * 8; }
+
+void launch_residual_once(const int32_t *D, const double *etab, int64_t etab_len, double gamma,
+                          int vmode, const double *Ec, double lambda, const TileLayout &L, int r,
+                          const double *X, const double *Y, double *R, double *part,
+                          hipStream_t s) {
+  const int ncb = r <= 16 ? 1 : 2, xc = 16 * ncb;
+  const int ws = vmode == VAL_EXP ? residual_wshift(gamma, etab_len - 1) : -1;
+  const bool two = vmode == VAL_EXP && residual_two_level(etab_len);
+  const dim3 grid((unsigned)L.ntiles(), (unsigned)((r + xc - 1) / xc));
+#define KRR_RO(NCB, VM, CONF)                                                                 \
+  hipLaunchKernelGGL((k_residual_once<NCB, VM, CONF>), grid, dim3(256), 0, s, D, etab,         \
+                     etab_len, gamma, ws, L.np, L.nb, r, X, part, Ec)
+#define KRR_RO2(VM, CONF)              \
+  do {                                  \
+    if (ncb == 1) KRR_RO(1, VM, CONF);  \
+    else KRR_RO(2, VM, CONF);           \
+  } while (0)
+  if (vmode == VAL_LINEAR) {
+    KRR_RO2(2, false);
+  } else if (Ec) {
+    if (two) KRR_RO2(3, true);
+    else if (ws >= 0) KRR_RO2(1, true);
+    else KRR_RO2(0, true);
+  } else {
+    if (two) KRR_RO2(3, false);
+    else if (ws >= 0) KRR_RO2(1, false);
+    else KRR_RO2(0, false);
+  }
+#undef KRR_RO2
+#undef KRR_RO
+  const int64_t tot = L.np * r;
+  hipLaunchKernelGGL(k_residual_sum, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, part,
+                     L.nt, L.np, r, L.n, lambda, X, Y, R);
 }
 
 // Predict: P[i, :] = sum_j exp(-gamma Dt[i, j]) X[j, :] in FP64 for a block of

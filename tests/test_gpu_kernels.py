@@ -186,3 +186,49 @@ def test_ridge_regression_parity(n, m):
     P = krr.krr_rr_predict(ctx, _dev(T), _dev(bo)).cpu().numpy()
     assert _colrel(P, oracle.rr_predict(T, bo)) <= 1e-12
     ctx.close()
+
+
+@pytest.mark.parametrize("kind", ["gauss", "gauss_table", "linear", "confounders"])
+@pytest.mark.parametrize("r", [3, 40])
+def test_residual_read_once_matches_oracle(kind, r):
+    """The residual with every stored distance tile read once (residual_split = -1: each
+    tile's direct and transposed products into slots of their own, summed in fixed
+    order) gives the oracle's FP64 residual for the unrefined X, as the two-read form
+    does, for every way a stored integer becomes a kernel value (two-level exponential
+    tables, the plain table at a large gamma, the linear kernel, confounder factors),
+    with 1 and 3 blocks of 16 right-hand sides and a ragged n (3 tiles of 256)."""
+    n, m, lam = 700, 500, 0.05
+    G = _gen(n, m, seed=41 + r)
+    Y = synth.phenotypes(G, r, n_pairs=8, n_add=4, seed=42, h2=0.5)
+    C = None
+    if kind == "linear":
+        gamma = 0.0
+    elif kind == "gauss_table":
+        gamma = 2000.0 / m
+    elif kind == "confounders":
+        G, _, C, _, gamma = _conf_case(n, 0, m, 4, seed=43)
+        Y = synth.phenotypes(G, r, n_pairs=8, n_add=4, seed=42, h2=0.5)
+    else:
+        gamma = 1.0 / m
+    for split in (8, -1):
+        c = krr.krr_create(0, tile=256)
+        krr.krr_set_tuning(c, tile=256, residual_split=split)
+        if kind == "linear":
+            K = krr.krr_build_kernel_ex(c, _dev(G), 1.0, lam, kind=krr.KRR_KERNEL_LINEAR)
+        elif C is not None:
+            K = krr.krr_build_kernel_ex(c, _dev(G), gamma, lam, C=_dev(C))
+        else:
+            K = krr.krr_build_kernel(c, _dev(G), gamma, lam)
+        F = krr.krr_factor(c, K, krr.plain_fp32_policy())
+        X, info, _ = krr.krr_solve(c, F, _dev(Y), krr.Refine(max_iters=0, tol=0.0), check=False)
+        Xh = X.cpu().numpy()
+        if kind == "linear":
+            Kf = oracle.dot(G).astype(np.float64) + lam * np.eye(n)
+            R = Y - Kf @ Xh
+        else:
+            R = oracle.residual_rows(G, gamma, lam, Xh, Y, np.arange(n), C=C)
+        want = np.max(np.linalg.norm(R, axis=0) / (lam * np.linalg.norm(Xh, axis=0)))
+        np.testing.assert_allclose(info.fwd_err_bound, want, rtol=1e-8)
+        F.release()
+        K.release()
+        c.close()

@@ -340,3 +340,33 @@ def test_autotuner_searches_caches_and_applies(tmp_path):
     K.release()
     ctx.close()
     ctx2.close()
+
+
+def test_stage_timer_mask_times_only_the_chosen_stages():
+    """krr_timers_enable_stages: with only the Gram selected, a build + factor +
+    solve records one Gram interval and nothing for the other stages; enabling
+    every stage records the factorization's stages too."""
+    n, m = 1100, 700
+    G = synth.genotypes(n, m, synth.maf_uniform(m, 0.05, 0.5, 3), 3)
+    Y = synth.phenotypes(G, 2, n_pairs=5, n_add=3, seed=4, h2=0.5)
+    c = krr.krr_create(0, tile=256)
+    Gd, Yd = _dev(G), _dev(Y)
+
+    def run():
+        K = krr.krr_build_kernel(c, Gd, 1.0 / m, 0.1)
+        F = krr.krr_factor(c, K)
+        krr.krr_solve(c, F, Yd)
+        F.release()
+        K.release()
+
+    krr.krr_timers_enable_stages(c, ["gram"])
+    run()
+    st = krr.krr_timers_read(c)
+    assert st["gram"][1] == 1 and st["gram"][0] > 0
+    assert all(v[1] == 0 for k, v in st.items() if k != "gram")
+    krr.krr_timers_enable(c, True)
+    run()
+    st = krr.krr_timers_read(c)
+    assert st["gram"][1] == 1 and st["potrf"][1] > 0 and st["fwd_sweep"][1] > 0
+    krr.krr_timers_enable(c, False)
+    c.close()
