@@ -974,7 +974,10 @@ static krr_status factor_enqueue(krr_context ctx, krr_kernel K, krr_factorizatio
       du.pmap_at[q] = (int64_t)(q0 + q) * L.ntiles() + TileLayout::tri(k, k);
     }
     Stage t(ctx, KRR_STAGE_POTRF, st);
-    launch_potrf_tile(F->Lst + TileLayout::tri(k, k) * te, k, L, fp.diag64, w, du, st);
+    // with the lookahead schedule the steps also form the FP32 factor tile and
+    // the tile inverse but for its last block row (off the side stream)
+    launch_potrf_tile(F->Lst + TileLayout::tri(k, k) * te, k, L, fp.diag64, w, du,
+                      lookahead ? F->Linv + (int64_t)k * te : nullptr, st);
   };
   // TRSM of panel k, tiles k+1+t_lo .. : by substitution (no inverse) or
   // as a product with inv(L_kk) after forming it
@@ -985,7 +988,7 @@ static krr_status factor_enqueue(krr_context ctx, krr_kernel K, krr_factorizatio
   auto trsm_gemm = [&](int k, int t_lo, int t_hi, hipStream_t st) {
     {
       Stage t(ctx, KRR_STAGE_POTRF, st);
-      launch_tile_inverses(F->Lst, F->Linv, k, k + 1, L, fp.diag64, w, st);
+      launch_tile_inverse_last_row(F->Linv + (int64_t)k * te, k, L, fp.diag64, w, st);
     }
     Stage t(ctx, KRR_STAGE_TRSM, st);
     launch_trsm_gemm(F->Lst, F->Linv + (int64_t)k * te, k, L, w, slot(k), t_lo, t_hi, st);
@@ -1135,7 +1138,7 @@ static krr_status factor_enqueue(krr_context ctx, krr_kernel K, krr_factorizatio
   }
   if (lookahead) {  // the last tile has no panel below it
     Stage t(ctx, KRR_STAGE_POTRF, s);
-    launch_tile_inverses(F->Lst, F->Linv, NT - 1, NT, L, fp.diag64, w, s);
+    launch_tile_inverse_last_row(F->Linv + (int64_t)(NT - 1) * te, NT - 1, L, fp.diag64, w, s);
   }
   launch_count_pmap(dmap, mapsz, w.counts, s);
   return KRR_SUCCESS;

@@ -266,22 +266,29 @@ KRR_DEV void diag64_body(T (*S)[BS + 1], T (*X)[BS + 1], int32_t *flag, int64_t 
   }
 }
 
-// Write L (zero above the diagonal) and inv(L) of a factored 64 x 64 block.
+// Write L (zero above the diagonal) and inv(L) of a factored 64 x 64 block;
+// Lf, If (or null): FP32 copies of both at the block's place in FP32 tiles
+// (leading dimension ld).
 template <typename T>
 __device__ __forceinline__ void diag64_store(const T (*S)[BS + 1], const T (*X)[BS + 1], T *Lblk,
-                                             int64_t ld, T *Dblk) {
+                                             int64_t ld, T *Dblk, float *Lf = nullptr,
+                                             float *If = nullptr) {
 #pragma unroll
   for (int q = 0; q < 16; ++q) {
     const int e = threadIdx.x + 256 * q, r = e / BS, c = e % BS;
-    Lblk[(int64_t)r * ld + c] = (c <= r) ? S[r][c] : (T)0;
-    Dblk[e] = (c <= r) ? X[r][c] : (T)0;
+    const T l = (c <= r) ? S[r][c] : (T)0, x = (c <= r) ? X[r][c] : (T)0;
+    Lblk[(int64_t)r * ld + c] = l;
+    Dblk[e] = x;
+    if (Lf) Lf[(int64_t)r * ld + c] = (float)l;
+    if (If) If[(int64_t)r * ld + c] = (float)x;
   }
 }
 
 // First diagonal block of the tile: W_00 -> L_00 (in WL) and inv(L_00).
 template <typename T>
 KRR_DEV void potrf_diag64_first(const T *__restrict__ W, T *__restrict__ WL, int nb,
-                                T *__restrict__ Dinv, int32_t *flag, int64_t colbase) {
+                                T *__restrict__ Dinv, int32_t *flag, int64_t colbase,
+                                float *Lf = nullptr, float *If = nullptr) {
   __shared__ T S[BS][BS + 1];  // the block, overwritten by L
   __shared__ T X[BS][BS + 1];  // inv(L)
   {
@@ -299,14 +306,14 @@ KRR_DEV void potrf_diag64_first(const T *__restrict__ W, T *__restrict__ WL, int
   }
   __syncthreads();
   diag64_body<T>(S, X, flag, colbase);
-  diag64_store<T>(S, X, WL, nb, Dinv);
+  diag64_store<T>(S, X, WL, nb, Dinv, Lf, If);
 }
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_potrf_diag64(const T *__restrict__ W, T *__restrict__ WL,
                                                       int nb, T *__restrict__ Dinv, int32_t *flag,
-                                                      int64_t colbase) {
-  potrf_diag64_first<T>(W, WL, nb, Dinv, flag, colbase);
+                                                      int64_t colbase, float *Lf, float *If) {
+  potrf_diag64_first<T>(W, WL, nb, Dinv, flag, colbase, Lf, If);
 }
 
 template <typename T, bool BT>
@@ -346,6 +353,19 @@ __device__ __forceinline__ void store64(T *dst, int64_t ld, const typename M16<T
     }
 }
 
+// dst (ld, FP32) = alpha * acc
+template <typename T>
+__device__ __forceinline__ void store64f(float *dst, int64_t ld, const typename M16<T>::v4 (&acc)[4],
+                                         T alpha) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int ct = 0; ct < 4; ++ct)
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      dst[(int64_t)(16 * wave + M16<T>::row(r, lane)) * ld + 16 * ct + (lane & 15)] =
+          (float)(alpha * acc[ct][r]);
+}
+
 // Stage a 64 x 64 block into LDS: all 16 loads of a thread are issued before
 // any LDS store, so their latencies overlap.
 template <typename T>
@@ -381,11 +401,46 @@ __device__ __forceinline__ void store_lds64(T (*dst)[BS + 1], const typename M16
 // and the pair (s+1, s+1) goes on to factor its updated block -- the next
 // diagonal step -- without writing it back.  Block column s of W is only
 // read in this step (the factor goes to WL), so the pairs need no ordering.
+//
+// With Winv (the tile's FP64 inverse, leading dimension nb), workgroups
+// bid >= npairs form block row s of inv(L_kk), whose L row and earlier
+// inverse rows are final by now:
+//   X_st = -inv(L_ss) sum_{p=t}^{s-1} L_sp X_pt,  t = bid - npairs < s
+// (X_tt = inv(L_tt) from Dinv), into Winv and, with If, the FP32 inverse
+// tile.  Lf (or null): the FP32 factor tile gets the panel blocks and the
+// next diagonal block as they are written.
 template <typename T>
 KRR_DEV void potrf_step_body(T *__restrict__ W, T *__restrict__ WL, int nb, int s,
-                             T *__restrict__ Dinv, int32_t *flag, int64_t colbase, int bid) {
+                             T *__restrict__ Dinv, int32_t *flag, int64_t colbase, int bid,
+                             int npairs = 1 << 30, T *__restrict__ Winv = nullptr,
+                             float *Lf = nullptr, float *If = nullptr) {
   typedef typename M16<T>::v4 v4;
   __shared__ T buf[3][BS][BS + 1];
+  if (bid >= npairs) {
+    const int t = bid - npairs;
+    T(*Ab)[BS + 1] = buf[0];
+    T(*Bb)[BS + 1] = buf[1];
+    T(*Cb)[BS + 1] = buf[2];
+    v4 acc[4];
+    zero4<T>(acc);
+    for (int p = t; p < s; ++p) {
+      load64(Ab, WL + (int64_t)(s * BS) * nb + p * BS, nb);
+      if (p == t) load64(Bb, Dinv + (int64_t)t * BS * BS, BS);
+      else load64(Bb, Winv + (int64_t)(p * BS) * nb + t * BS, nb);
+      __syncthreads();
+      mm64<T, false>(Ab, Bb, acc);
+      __syncthreads();
+    }
+    store_lds64<T>(Cb, acc);
+    load64(Ab, Dinv + (int64_t)s * BS * BS, BS);
+    __syncthreads();
+    v4 out[4];
+    zero4<T>(out);
+    mm64<T, false>(Ab, Cb, out);
+    store64<T, false>(Winv + (int64_t)(s * BS) * nb + t * BS, nb, out, (T)-1);
+    if (If) store64f<T>(If + (int64_t)(s * BS) * nb + t * BS, nb, out, (T)-1);
+    return;
+  }
   int a, b;
   tri_decode(bid, a, b);
   a += s + 1;
@@ -422,7 +477,10 @@ KRR_DEV void potrf_step_body(T *__restrict__ W, T *__restrict__ WL, int nb, int 
   __syncthreads();
   store_lds64<T>(Xa, pa);
   if (a != b) store_lds64<T>(Xb, pb);
-  else store64<T, false>(WL + (int64_t)(a * BS) * nb + s * BS, nb, pa, (T)1);
+  else {
+    store64<T, false>(WL + (int64_t)(a * BS) * nb + s * BS, nb, pa, (T)1);
+    if (Lf) store64f<T>(Lf + (int64_t)(a * BS) * nb + s * BS, nb, pa, (T)1);
+  }
   __syncthreads();
   v4 acc[4];
   zero4<T>(acc);
@@ -440,7 +498,9 @@ KRR_DEV void potrf_step_body(T *__restrict__ W, T *__restrict__ WL, int nb, int 
       }
     __syncthreads();
     diag64_body<T>(S, X, flag, colbase + (int64_t)a * BS);
-    diag64_store<T>(S, X, WL + (int64_t)(a * BS) * nb + a * BS, nb, Dinv + (int64_t)a * BS * BS);
+    diag64_store<T>(S, X, WL + (int64_t)(a * BS) * nb + a * BS, nb, Dinv + (int64_t)a * BS * BS,
+                    Lf ? Lf + (int64_t)(a * BS) * nb + a * BS : nullptr,
+                    If ? If + (int64_t)(a * BS) * nb + a * BS : nullptr);
   } else {
     store64<T, true>(Wab, nb, acc, (T)-1);
   }
@@ -449,8 +509,9 @@ KRR_DEV void potrf_step_body(T *__restrict__ W, T *__restrict__ WL, int nb, int 
 template <typename T>
 __global__ __launch_bounds__(256) void k_potrf_step(T *__restrict__ W, T *__restrict__ WL, int nb,
                                                     int s, T *__restrict__ Dinv, int32_t *flag,
-                                                    int64_t colbase) {
-  potrf_step_body<T>(W, WL, nb, s, Dinv, flag, colbase, blockIdx.x);
+                                                    int64_t colbase, int npairs, T *Winv,
+                                                    float *Lf, float *If) {
+  potrf_step_body<T>(W, WL, nb, s, Dinv, flag, colbase, blockIdx.x, npairs, Winv, Lf, If);
 }
 
 // Inverses of the diagonal tiles k0 .. k0+C-1 (tile c = blockIdx.y or
@@ -609,9 +670,13 @@ void launch_tile_inverses(float *Lst, float *Linv, int k_lo, int k_hi, const Til
 // tile -- and the difference formed in T.
 typedef GemmShape<64, 64, 2, 2> DiagUpdShape;
 
+// With If (the tile's FP32 inverse) the workgroup of block (bi, bj), bi > bj,
+// also zeroes block (bj, bi) above the diagonal of Akk and of If: the FP32
+// factor and inverse are then written into those tiles block by block during
+// the factorization, and their upper blocks stay zero.
 template <typename T>
-KRR_DEV void potrf_load_body(const float *__restrict__ Akk, T *__restrict__ W, int nb,
-                             const DiagUpdate &du, int bid) {
+KRR_DEV void potrf_load_body(float *__restrict__ Akk, T *__restrict__ W, int nb,
+                             const DiagUpdate &du, int bid, float *__restrict__ If = nullptr) {
   typedef DiagUpdShape S;
   __shared__ __attribute__((aligned(16))) uint8_t lds[S::LDS_BYTES];
   int bi, bj;
@@ -635,37 +700,73 @@ KRR_DEV void potrf_load_body(const float *__restrict__ Akk, T *__restrict__ W, i
         const int64_t o = (int64_t)r * nb + c;
         W[o] = (c <= r) ? (T)Akk[o] - (T)acc[tm][tn][e] : (T)0;
       }
+  if (If && bi > bj) {
+    __syncthreads();  // every read of this workgroup's block is done (it is not the zeroed one)
+    for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+      const int64_t o = (int64_t)(bj * 64 + e / 64) * nb + bi * 64 + e % 64;
+      Akk[o] = 0.0f;
+      If[o] = 0.0f;
+    }
+  }
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_potrf_load(const float *__restrict__ Akk, T *__restrict__ W,
-                                                    int nb, DiagUpdate du) {
-  potrf_load_body<T>(Akk, W, nb, du, blockIdx.x);
+__global__ __launch_bounds__(256) void k_potrf_load(float *__restrict__ Akk, T *__restrict__ W,
+                                                    int nb, DiagUpdate du, float *If) {
+  potrf_load_body<T>(Akk, W, nb, du, blockIdx.x, If);
+}
+
+// The FP64 (or FP32) inverse of tile k while it is formed in the steps: one of
+// two slots of the chunk buffer, so that the next tile's steps may run while
+// the last block row of this one is still being formed.
+template <typename T>
+static T *inv_slot(FactorWork &w, int k, int64_t te) {
+  return (T *)w.Winv64 + (int64_t)(k % 2) * te;
 }
 
 template <typename T>
 static void potrf_tile_t(float *Akk, int k, const TileLayout &L, FactorWork &w,
-                         const DiagUpdate &du, hipStream_t s) {
+                         const DiagUpdate &du, float *Linv_k, hipStream_t s) {
   const int nb = L.nb, NB = nb / BS;
   const int64_t te = (int64_t)nb * nb;
   T *W = (T *)w.W64, *WL = (T *)w.WL64 + k * te, *Dinv = (T *)w.Dinv64 + (int64_t)k * NB * BS * BS;
+  T *Winv = Linv_k ? inv_slot<T>(w, k, te) : nullptr;
+  float *Lf = Linv_k ? Akk : nullptr;
   const int64_t colbase = (int64_t)k * nb;
-  hipLaunchKernelGGL(k_potrf_load<T>, dim3(NB * (NB + 1) / 2), dim3(256), 0, s, Akk, W, nb, du);
+  hipLaunchKernelGGL(k_potrf_load<T>, dim3(NB * (NB + 1) / 2), dim3(256), 0, s, Akk, W, nb, du,
+                     Linv_k);
   hipLaunchKernelGGL(k_potrf_diag64<T>, dim3(1), dim3(256), 0, s, W, WL, nb, Dinv, w.flag,
-                     colbase);
+                     colbase, Lf, Linv_k);
   for (int st = 0; st + 1 < NB; ++st) {
-    const int rest = NB - 1 - st;
-    hipLaunchKernelGGL(k_potrf_step<T>, dim3(rest * (rest + 1) / 2), dim3(256), 0, s, W, WL, nb,
-                       st, Dinv, w.flag, colbase);
+    const int rest = NB - 1 - st, npairs = rest * (rest + 1) / 2;
+    hipLaunchKernelGGL(k_potrf_step<T>, dim3(npairs + (Winv ? st : 0)), dim3(256), 0, s, W, WL,
+                       nb, st, Dinv, w.flag, colbase, npairs, Winv, Lf, Linv_k);
   }
 }
 
 void launch_potrf_tile(float *Akk, int k, const TileLayout &L, bool fp64, FactorWork &w,
-                       const DiagUpdate &du, hipStream_t s) {
+                       const DiagUpdate &du, float *Linv_k, hipStream_t s) {
   if (fp64)
-    potrf_tile_t<double>(Akk, k, L, w, du, s);
+    potrf_tile_t<double>(Akk, k, L, w, du, Linv_k, s);
   else
-    potrf_tile_t<float>(Akk, k, L, w, du, s);
+    potrf_tile_t<float>(Akk, k, L, w, du, Linv_k, s);
+}
+
+void launch_tile_inverse_last_row(float *Linv_k, int k, const TileLayout &L, bool fp64,
+                                  FactorWork &w, hipStream_t s) {
+  const int nb = L.nb, NB = nb / BS;
+  const int64_t te = (int64_t)nb * nb;
+  if (NB < 2) return;
+  if (fp64)
+    hipLaunchKernelGGL(k_potrf_step<double>, dim3(NB - 1), dim3(256), 0, s, (double *)w.W64,
+                       (double *)w.WL64 + k * te, nb, NB - 1,
+                       (double *)w.Dinv64 + (int64_t)k * NB * BS * BS, w.flag, (int64_t)k * nb, 0,
+                       inv_slot<double>(w, k, te), (float *)nullptr, Linv_k);
+  else
+    hipLaunchKernelGGL(k_potrf_step<float>, dim3(NB - 1), dim3(256), 0, s, (float *)w.W64,
+                       (float *)w.WL64 + k * te, nb, NB - 1,
+                       (float *)w.Dinv64 + (int64_t)k * NB * BS * BS, w.flag, (int64_t)k * nb, 0,
+                       inv_slot<float>(w, k, te), (float *)nullptr, Linv_k);
 }
 
 // ---------------------------------------------------------------------------
@@ -1053,8 +1154,8 @@ void launch_convert_panel(float *Astore, int k, const TileLayout &L, FactorWork 
 //   A_ij -= sum_k L_ik L_jk^T   for the tiles (i, j), jlo <= j <= jhi, j <= i < NT,
 // one 256 x 256 (off-diagonal) or 128 x 128 (diagonal tiles, short column
 // ranges) block per workgroup, FP32 accumulation over all panels of the
-// group, added into C with one atomic FP32 add per element (so C is not read
-// by the workgroup, and each element gets one add per launch).  The operand
+// group, subtracted from C once per element (each element belongs to one
+// workgroup of the launch, and no other launch touches the tile meanwhile).  The operand
 // precision is chosen per (tile, panel), uniform across the workgroup:
 //   FP32 on diagonal tiles, on panels k < high_panels and under the FP32 policy;
 //   FIXED: fixed_prec; ADAPTIVE: lowest allowed p with
@@ -1237,19 +1338,25 @@ KRR_DEV void update_body(float *__restrict__ Astore, const PanelSet &ps, int k0,
 
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   float *C = Astore + (i * (i + 1) / 2 + j) * te + (int64_t)si * BM * nb + sj * BM;
+  // C -= acc by a plain read-modify-write, a block row of accumulators at a
+  // time (the loads of a row in flight together): the events that order the
+  // launches give each launch its tiles alone, and every element gets one
+  // subtraction per launch.  (One FP32 atomic add per element in L2 instead
+  // was measured 1 ms per step slower at n = 32768.)
 #pragma unroll
-  for (int tm = 0; tm < S::WTM; ++tm)
+  for (int tm = 0; tm < S::WTM; ++tm) {
+    float cv[S::WTN][16];
 #pragma unroll
     for (int tn = 0; tn < S::WTN; ++tn)
 #pragma unroll
-      for (int e = 0; e < 16; ++e) {
-        const int r = S::row(wave, tm, e, lane);
-        const int c = S::col(wave, tn, lane);
-        // one FP32 add per element in L2, no read round trip; every element
-        // gets exactly one add per launch, so the result is C - acc rounded
-        // once, as a plain read-modify-write would give
-        unsafeAtomicAdd(C + (int64_t)r * nb + c, -acc[tm][tn][e]);
-      }
+      for (int e = 0; e < 16; ++e)
+        cv[tn][e] = C[(int64_t)S::row(wave, tm, e, lane) * nb + S::col(wave, tn, lane)];
+#pragma unroll
+    for (int tn = 0; tn < S::WTN; ++tn)
+#pragma unroll
+      for (int e = 0; e < 16; ++e)
+        C[(int64_t)S::row(wave, tm, e, lane) * nb + S::col(wave, tn, lane)] = cv[tn][e] - acc[tm][tn][e];
+  }
 }
 
 template <class S, bool DIAG>

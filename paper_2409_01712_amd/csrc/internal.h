@@ -193,8 +193,14 @@ void launch_factor_lockstep(const FactorJob *jobs, const int *nts, int njobs, in
                             bool scale8, hipStream_t s);
 // Diagonal tile k: L_kk = chol(A_kk - sum_q P_q P_q^T) into the work's
 // factor store (tile k), with the inverses of its 64 x 64 diagonal blocks.
+// Linv_k (or null): also L_kk in FP32 into Akk and block rows 0 .. nb/64-2 of
+// inv(L_kk) in FP32 into Linv_k, formed in the same steps (the last block
+// row by launch_tile_inverse_last_row); needs at least two tiles of the
+// work's inverse chunk buffer.
 void launch_potrf_tile(float *Akk, int k, const TileLayout &L, bool fp64, FactorWork &w,
-                       const DiagUpdate &du, hipStream_t s);
+                       const DiagUpdate &du, float *Linv_k, hipStream_t s);
+void launch_tile_inverse_last_row(float *Linv_k, int k, const TileLayout &L, bool fp64,
+                                  FactorWork &w, hipStream_t s);
 // L_kk into the factor storage and inv(L_kk), FP32, for the diagonal tiles
 // k_lo .. k_hi-1 (factored before).
 void launch_tile_inverses(float *Lst, float *Linv, int k_lo, int k_hi, const TileLayout &L,
