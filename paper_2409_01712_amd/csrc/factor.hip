@@ -402,13 +402,29 @@ __device__ __forceinline__ void store_lds64(T (*dst)[BS + 1], const typename M16
 // diagonal step -- without writing it back.  Block column s of W is only
 // read in this step (the factor goes to WL), so the pairs need no ordering.
 //
-// With Winv (the tile's FP64 inverse, leading dimension nb), workgroups
-// bid >= npairs form block row s of inv(L_kk), whose L row and earlier
-// inverse rows are final by now:
-//   X_st = -inv(L_ss) sum_{p=t}^{s-1} L_sp X_pt,  t = bid - npairs < s
-// (X_tt = inv(L_tt) from Dinv), into Winv and, with If, the FP32 inverse
-// tile.  Lf (or null): the FP32 factor tile gets the panel blocks and the
+// With Winv (the tile's FP64 inverse, leading dimension nb), the workgroups
+// bid >= npairs build inv(L_kk) = X a block row at a time, its sums
+//   X_st = -inv(L_ss) sum_{p=t}^{s-1} L_sp X_pt   (X_tt = inv(L_tt) from Dinv)
+// accumulated in Winv as the rows become final, one product per workgroup
+// and step:
+//   finalize (extra < s): X_st = -inv(L_ss) (S_st + L_s,s-1 X_s-1,t), S_st the
+//     sum over p < s - 1 kept in Winv (none when t = s - 1);
+//   accumulate (the rest): S_rt += L_r,s-1 X_s-1,t for the later rows
+//     r > s and t < s (written, not added, when t = s - 1: the first term).
+// Each sum is formed in increasing p, one MFMA product per term as in a
+// single accumulator.  If (or null): the FP32 inverse tile gets the final
+// blocks.  Lf (or null): the FP32 factor tile gets the panel blocks and the
 // next diagonal block as they are written.
+template <typename T>
+KRR_DEV void load_acc64(const T *src, int64_t ld, typename M16<T>::v4 (&acc)[4]) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int ct = 0; ct < 4; ++ct)
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+      acc[ct][r] = src[(int64_t)(16 * wave + M16<T>::row(r, lane)) * ld + 16 * ct + (lane & 15)];
+}
+
 template <typename T>
 KRR_DEV void potrf_step_body(T *__restrict__ W, T *__restrict__ WL, int nb, int s,
                              T *__restrict__ Dinv, int32_t *flag, int64_t colbase, int bid,
@@ -417,28 +433,44 @@ KRR_DEV void potrf_step_body(T *__restrict__ W, T *__restrict__ WL, int nb, int 
   typedef typename M16<T>::v4 v4;
   __shared__ T buf[3][BS][BS + 1];
   if (bid >= npairs) {
-    const int t = bid - npairs;
+    const int extra = bid - npairs, p = s - 1;
+    int r, t;
+    bool fin;
+    if (extra < s) {
+      fin = true;
+      r = s;
+      t = extra;
+    } else {
+      fin = false;
+      r = s + 1 + (extra - s) / s;
+      t = (extra - s) % s;
+    }
     T(*Ab)[BS + 1] = buf[0];
     T(*Bb)[BS + 1] = buf[1];
     T(*Cb)[BS + 1] = buf[2];
+    T *Srt = Winv + (int64_t)(r * BS) * nb + t * BS;
     v4 acc[4];
-    zero4<T>(acc);
-    for (int p = t; p < s; ++p) {
-      load64(Ab, WL + (int64_t)(s * BS) * nb + p * BS, nb);
-      if (p == t) load64(Bb, Dinv + (int64_t)t * BS * BS, BS);
-      else load64(Bb, Winv + (int64_t)(p * BS) * nb + t * BS, nb);
-      __syncthreads();
-      mm64<T, false>(Ab, Bb, acc);
-      __syncthreads();
+    if (t < p) load_acc64<T>(Srt, nb, acc);  // the terms p' < s - 1 so far
+    else zero4<T>(acc);
+    // + L_r,s-1 X_s-1,t
+    load64(Ab, WL + (int64_t)(r * BS) * nb + p * BS, nb);
+    if (t == p) load64(Bb, Dinv + (int64_t)p * BS * BS, BS);
+    else load64(Bb, Winv + (int64_t)(p * BS) * nb + t * BS, nb);
+    __syncthreads();
+    mm64<T, false>(Ab, Bb, acc);
+    if (!fin) {
+      store64<T, false>(Srt, nb, acc, (T)1);
+      return;
     }
+    __syncthreads();
     store_lds64<T>(Cb, acc);
     load64(Ab, Dinv + (int64_t)s * BS * BS, BS);
     __syncthreads();
     v4 out[4];
     zero4<T>(out);
     mm64<T, false>(Ab, Cb, out);
-    store64<T, false>(Winv + (int64_t)(s * BS) * nb + t * BS, nb, out, (T)-1);
-    if (If) store64f<T>(If + (int64_t)(s * BS) * nb + t * BS, nb, out, (T)-1);
+    store64<T, false>(Srt, nb, out, (T)-1);
+    if (If) store64f<T>(If + (int64_t)(r * BS) * nb + t * BS, nb, out, (T)-1);
     return;
   }
   int a, b;
@@ -739,8 +771,10 @@ static void potrf_tile_t(float *Akk, int k, const TileLayout &L, FactorWork &w,
                      colbase, Lf, Linv_k);
   for (int st = 0; st + 1 < NB; ++st) {
     const int rest = NB - 1 - st, npairs = rest * (rest + 1) / 2;
-    hipLaunchKernelGGL(k_potrf_step<T>, dim3(npairs + (Winv ? st : 0)), dim3(256), 0, s, W, WL,
-                       nb, st, Dinv, w.flag, colbase, npairs, Winv, Lf, Linv_k);
+    // the inverse: row st finalized, the later rows' sums advanced by row st - 1
+    const int ninv = Winv ? st + (NB - 1 - st) * st : 0;
+    hipLaunchKernelGGL(k_potrf_step<T>, dim3(npairs + ninv), dim3(256), 0, s, W, WL, nb, st, Dinv,
+                       w.flag, colbase, npairs, Winv, Lf, Linv_k);
   }
 }
 
