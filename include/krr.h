@@ -436,8 +436,8 @@ typedef struct krr_tuning {
   int32_t lookahead;      /* 1: three-stream factorization schedule, 0: one stream (-1: 1) */
   int32_t aux_cu_eighths; /* eighths of the compute units the stream of the wide trailing
                              updates may use, 1 .. 8 (0: all); the rest stay free for the
-                             critical path (a CU mask over groups of eight CUs; not searched
-                             by krr_autotune) */
+                             critical path (a CU mask over groups of eight CUs: a hardware
+                             queue of its own; not searched by krr_autotune) */
 } krr_tuning;
 
 /* Set or read the context's tuning.  Changing the tile needs a context with

@@ -55,6 +55,7 @@ struct krr_context_s {
   hipStream_t aux = nullptr, side = nullptr, fmain = nullptr;
   hipStream_t cap = nullptr;  // graph capture
   int aux_e = 8;              // eighths of the CUs the aux stream uses
+  hipStream_t aux_by_e[9] = {};  // the aux streams made so far, by eighths (kept)
   std::vector<hipEvent_t> sched_ev;  // ordering events of the factorization schedule
 };
 
@@ -79,6 +80,8 @@ struct krr_kernel_s {
     return kind == KRR_KERNEL_IBS ? VAL_TABLE : kind == KRR_KERNEL_LINEAR ? VAL_LINEAR : VAL_EXP;
   }
   TileLayout L;
+  int8_t *Gs = nullptr;  // the Gram's genotypes slab-major, or null
+  int64_t gs_bytes = 0;
   int32_t *D = nullptr;  // exact distances, packed lower tiles
   float *A = nullptr;    // K + lambda I, FP32, packed lower tiles (null once consumed)
   int32_t *nrm = nullptr;
@@ -413,7 +416,13 @@ static void context_free(krr_context ctx) {
   timers_drain(ctx);
   for (hipEvent_t e : ctx->pool) (void)hipEventDestroy(e);
   cache_flush(ctx);
-  for (hipStream_t x : {ctx->aux, ctx->side, ctx->fmain, ctx->cap}) {
+  for (hipStream_t x : {ctx->side, ctx->fmain, ctx->cap}) {
+    if (x) {
+      (void)hipStreamSynchronize(x);
+      (void)hipStreamDestroy(x);
+    }
+  }
+  for (hipStream_t x : ctx->aux_by_e) {
     if (x) {
       (void)hipStreamSynchronize(x);
       (void)hipStreamDestroy(x);
@@ -427,40 +436,41 @@ static void context_free(krr_context ctx) {
 // (the critical path), a side stream and an aux stream.
 // The aux stream (the wide trailing updates, off the critical path) may be
 // limited to q eighths of the compute units, so that the main and side
-// streams find free ones: CU i is enabled when (i / 8) % 8 < q.  Not the
-// default and not searched by the autotuner: seven eighths took the adaptive
-// path at n = 32768 from 82 to 81 ms per step, but the plain FP32 path (whose
-// wide updates are most of its work) from 138 to 207 ms, and a masked stream
-// is a hardware queue of its own.  KRR_AUX_CU_EIGHTHS overrides the tuning.
-static krr_status context_aux(krr_context ctx) {
+// streams find free ones: CU i is enabled when (i / 8) % 8 < q.  Measured at
+// n = 32768, seven eighths took the adaptive path from 81.9-82.4 to
+// 80.8-81.3 ms per step (its diagonal chain no longer starves while the wide
+// update fills the chip at a group start) and the plain FP32 path, whose wide
+// updates are most of its work, from 138 to 207 ms; but a masked stream is a
+// hardware queue of its own, and with masked streams in one context a second
+// context's factorization in the same process ran 17% slower (161 against
+// 137 ms).  So no mask by default (tuning 0); each mask's stream is made once
+// per context and kept.  KRR_AUX_CU_EIGHTHS overrides the tuning.
+static krr_status context_aux(krr_context ctx, bool low_precision) {
+  (void)low_precision;
   for (hipStream_t *x : {&ctx->fmain, &ctx->side})
     if (!*x) HIPCHK(hipStreamCreateWithFlags(x, hipStreamNonBlocking));
   const char *e = getenv("KRR_AUX_CU_EIGHTHS");
   int q = e ? atoi(e) : ctx->tune.aux_cu_eighths;
-  if (q <= 0 || q > 8) q = 8;
-  if (ctx->aux && ctx->aux_e != q) {
-    HIPCHK(hipStreamSynchronize(ctx->aux));
-    HIPCHK(hipStreamDestroy(ctx->aux));
-    ctx->aux = nullptr;
-  }
-  if (!ctx->aux) {
+  if (q == 0) q = 8;
+  if (q < 0 || q > 8) q = 8;
+  if (!ctx->aux_by_e[q]) {
     int ncu = 0;
     HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, ctx->device));
-    bool masked = false;
+    hipStream_t st = nullptr;
     if (q < 8 && ncu > 0) {
       std::vector<uint32_t> mask((ncu + 31) / 32, 0u);
       for (int i = 0; i < ncu; ++i)
         if (((i >> 3) & 7) < q) mask[i / 32] |= 1u << (i % 32);
-      masked = hipExtStreamCreateWithCUMask(&ctx->aux, (uint32_t)mask.size(), mask.data()) ==
-               hipSuccess;
-      if (!masked) {
+      if (hipExtStreamCreateWithCUMask(&st, (uint32_t)mask.size(), mask.data()) != hipSuccess) {
         (void)hipGetLastError();
-        ctx->aux = nullptr;
+        st = nullptr;
       }
     }
-    if (!masked) HIPCHK(hipStreamCreateWithFlags(&ctx->aux, hipStreamNonBlocking));
-    ctx->aux_e = masked ? q : 8;
+    if (!st) HIPCHK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+    ctx->aux_by_e[q] = st;
   }
+  ctx->aux = ctx->aux_by_e[q];
+  ctx->aux_e = q;
   return KRR_SUCCESS;
 }
 
@@ -496,6 +506,7 @@ static void kernel_free(krr_kernel K) {
   dfree(c, K->Cc, (size_t)K->n * K->q * 8);
   dfree(c, K->Ec, (size_t)L.elems() * 8);
   dfree(c, K->tnorm, (size_t)L.ntiles() * 8);
+  dfree(c, K->Gs, (size_t)K->gs_bytes);
   const int sb = L.nb / 256;
   dfree(c, K->tnorm_part, (size_t)L.ntiles() * sb * sb * 8);
 }
@@ -619,9 +630,21 @@ krr_status krr_build_kernel_ex(krr_context ctx, const int8_t *G, int64_t n, int6
     else if (K->kind == KRR_KERNEL_GAUSSIAN) launch_exp_table(K->etab, K->etab_len, gamma, s);
     if (K->Ec) launch_conf_factor(K->Cc, n, K->q, K->q, gamma, L, K->Ec, s);
     {
+      // the genotypes slab-major for the Gram (kept with the kernel until its
+      // release); KRR_GRAM_SLAB=0 streams the row-major matrix instead
+      static const bool slab = [] {
+        const char *e = getenv("KRR_GRAM_SLAB");
+        return !e || atoi(e) != 0;
+      }();
+      if (slab) {
+        K->gs_bytes = L.np * ((K->gram_m() + 63) / 64) * 64;
+        if ((st = dalloc_t(ctx, &K->Gs, K->gs_bytes)) != KRR_SUCCESS) break;
+      }
       Stage t(ctx, KRR_STAGE_GRAM);
+      if (K->Gs)
+        launch_slab_major(K->gram_src(), n, L.np, K->gram_m(), K->gram_ld(), K->Gs, s);
       launch_gram_tiles(K->gram_src(), K->gram_m(), K->gram_ld(), K->nrm, K->etab, K->etab_len,
-                        lambda, L, K->D, K->A, K->tnorm_part, K->vmode(), K->Ec, s);
+                        lambda, L, K->D, K->A, K->tnorm_part, K->vmode(), K->Ec, K->Gs, s);
     }
     launch_tile_norms(K->tnorm_part, sb * sb, L.ntiles(), K->tnorm, s);
     st = launch_ok();
@@ -1159,7 +1182,7 @@ krr_status krr_factor(krr_context ctx, krr_kernel K, const krr_precision_policy 
   const char *la_env = getenv("KRR_NO_LOOKAHEAD");
   const bool lookahead = la_env ? atoi(la_env) == 0 : ctx->tune.lookahead != 0;
   const int g = group_size(ctx, fp);
-  if (lookahead) CHK(context_aux(ctx));
+  if (lookahead) CHK(context_aux(ctx, fp.allow8 || fp.allow16));
 
   krr_factorization F = new krr_factor_s();
   F->ctx = ctx;

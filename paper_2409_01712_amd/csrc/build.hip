@@ -74,6 +74,45 @@ void launch_row_norms(const int8_t *G, int64_t n, int64_t rows_padded, int64_t m
                      nrm, flag);
 }
 
+// The genotypes in slab-major order: slab s (bytes 64 s .. 64 s + 63 of every
+// row) of all np rows one after another, Gs[(s np + r) 64 + b], zero past m
+// and on the padding rows.  A block of the Gram then streams each slab of its
+// 256 rows as one contiguous 16 KiB run (whole 128-byte lines) instead of 256
+// runs of 64 bytes a row apart.
+__global__ void k_slab_major(const int8_t *__restrict__ G, int64_t n, int64_t np, int64_t m,
+                             int64_t ldg, int64_t nslab, int8_t *__restrict__ Gs) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;  // one 16-byte chunk
+  if (e >= nslab * np * 4) return;
+  const int c = (int)(e & 3);
+  const int64_t r = (e >> 2) % np, sl = (e >> 2) / np, kb = sl * 64 + 16 * c;
+  v4i v = {0, 0, 0, 0};
+  if (r < n && kb < m) {
+    v = *(const v4i *)(G + r * ldg + kb);
+    if (kb + 16 > m) v = mask_tail(v, m - kb);
+  }
+  *(v4i *)(Gs + e * 16) = v;
+}
+
+void launch_slab_major(const int8_t *G, int64_t n, int64_t np, int64_t m, int64_t ldg,
+                       int8_t *Gs, hipStream_t s) {
+  const int64_t nslab = (m + 63) / 64, cnt = nslab * np * 4;
+  hipLaunchKernelGGL(k_slab_major, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, G, n, np,
+                     m, ldg, nslab, Gs);
+}
+
+// K source over a slab-major matrix: slab s of rows ra .. (A) or rb .. (B),
+// rows 64 bytes apart.
+template <class Op>
+struct SlabSrc {
+  const uint8_t *Gs;
+  int64_t np, ra, rb;
+  Op o;
+  KRR_DEV const uint8_t *ptr(bool side_a, int64_t s) const {
+    return Gs + (s * np + (side_a ? ra : rb)) * 64;
+  }
+  KRR_DEV Op op(int64_t) const { return o; }
+};
+
 // Symmetric Gram over the lower tile triangle.  Block (BM x BN) = one
 // sub-block of tile (I, J); SB x SB sub-blocks per tile.  Epilogue per
 // entry: d = n_i + n_j - 2 S (int32), A = exp(-gamma d) (two-level table in
@@ -84,12 +123,14 @@ void launch_row_norms(const int8_t *G, int64_t n, int64_t rows_padded, int64_t m
 // lookup per entry; VAL_LINEAR the linear kernel: the Gram entry itself is
 // stored and is the value.  Ec (or null): FP64 confounder factors
 // exp(-gamma dc_ij) in the packed tile layout, multiplied in.
+// Gs (or null): the same genotypes slab-major (k_slab_major), read instead of G.
 template <class S>
 KRR_DEV void gram_block(const int8_t *__restrict__ G, int64_t n, int64_t m, int64_t ldg,
                         const int32_t *__restrict__ nrm, const double *__restrict__ etab,
                         int64_t etab_len, double lambda, int nb, int SB, int32_t *__restrict__ D,
                         float *__restrict__ A, double *part, int64_t bid, int vmode,
-                        const double *__restrict__ Ec) {
+                        const double *__restrict__ Ec, const int8_t *__restrict__ Gs = nullptr,
+                        int64_t np = 0) {
   constexpr int BM = S::kBM, BN = S::kBN, NW = S::THREADS / 64;
   extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
   __shared__ double shd[NW];
@@ -114,10 +155,16 @@ KRR_DEV void gram_block(const int8_t *__restrict__ G, int64_t n, int64_t m, int6
 
   OpI8::acc_t acc[S::WTM][S::WTN];
   zero_acc(acc);
-  if (arows > 0 && brows > 0)
-    gemm_nt_stream<OpI8, S>(
-        ContigSrc<OpI8>{(const uint8_t *)G + row0 * ldg, (const uint8_t *)G + col0 * ldg, OpI8{}},
-        ldg, arows, ldg, brows, m, acc, lds);
+  if (arows > 0 && brows > 0) {
+    if (Gs)
+      gemm_nt_stream<OpI8, S>(SlabSrc<OpI8>{(const uint8_t *)Gs, np, row0, col0, OpI8{}}, 64,
+                              arows, 64, brows, ((m + 63) / 64) * 64, acc, lds);
+    else
+      gemm_nt_stream<OpI8, S>(
+          ContigSrc<OpI8>{(const uint8_t *)G + row0 * ldg, (const uint8_t *)G + col0 * ldg,
+                          OpI8{}},
+          ldg, arows, ldg, brows, m, acc, lds);
+  }
   __syncthreads();  // the tables (also when the product was skipped)
 
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -165,9 +212,10 @@ __global__ __launch_bounds__(S::THREADS) void k_gram_tiles(const int8_t *__restr
                                                     int SB, int32_t *__restrict__ D,
                                                     float *__restrict__ A, double *part,
                                                     int vmode,
-                                                    const double *__restrict__ Ec) {
+                                                    const double *__restrict__ Ec,
+                                                    const int8_t *__restrict__ Gs, int64_t np) {
   gram_block<S>(G, n, m, ldg, nrm, etab, etab_len, lambda, nb, SB, D, A, part,
-                xcd_remap(blockIdx.x, gridDim.x), vmode, Ec);
+                xcd_remap(blockIdx.x, gridDim.x), vmode, Ec, Gs, np);
 }
 
 // Instance of a batch that owns workgroup `bid`: the last job whose first
@@ -199,7 +247,7 @@ typedef StreamShape<256, 256, 2, 4, 4> GramShape;
 void launch_gram_tiles(const int8_t *G, int64_t m, int64_t ldg, const int32_t *nrm,
                        const double *etab, int64_t etab_len, double lambda, const TileLayout &L,
                        int32_t *D, float *A, double *tnorm_part, int vmode,
-                       const double *Ec, hipStream_t s) {
+                       const double *Ec, const int8_t *Gs, hipStream_t s) {
   const int SB = L.nb / GramShape::kBM;
   const int64_t blocks = L.ntiles() * SB * SB;
   static bool attr = false;
@@ -210,7 +258,8 @@ void launch_gram_tiles(const int8_t *G, int64_t m, int64_t ldg, const int32_t *n
   }
   hipLaunchKernelGGL((k_gram_tiles<GramShape>), dim3((unsigned)blocks), dim3(GramShape::THREADS),
                      GramShape::LDS_BYTES, s, G, L.n, m,
-                     ldg, nrm, etab, etab_len, lambda, L.nb, SB, D, A, tnorm_part, vmode, Ec);
+                     ldg, nrm, etab, etab_len, lambda, L.nb, SB, D, A, tnorm_part, vmode, Ec, Gs,
+                     L.np);
 }
 
 int64_t gram_blocks(const TileLayout &L) {

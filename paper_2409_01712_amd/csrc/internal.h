@@ -76,10 +76,15 @@ void launch_row_norms(const int8_t *G, int64_t n, int64_t rows_padded, int64_t m
 // (linear kernel: the stored integer is the inner product, not a distance).
 enum { VAL_EXP = 0, VAL_TABLE = 1, VAL_LINEAR = 2 };
 // vmode: VAL_*; Ec: FP64 confounder factors in the packed tile layout, or null.
+// Gs (or null): G in slab-major order (launch_slab_major), read instead of G.
 void launch_gram_tiles(const int8_t *G, int64_t m, int64_t ldg, const int32_t *nrm,
                        const double *etab, int64_t etab_len, double lambda, const TileLayout &L,
                        int32_t *D, float *A, double *tnorm_part, int vmode,
-                       const double *Ec, hipStream_t s);
+                       const double *Ec, const int8_t *Gs, hipStream_t s);
+// Gs[(s np + r) 64 + b] = G[r, 64 s + b] (zero past m and for rows n .. np-1):
+// np * ceil(m / 64) * 64 bytes.
+void launch_slab_major(const int8_t *G, int64_t n, int64_t np, int64_t m, int64_t ldg,
+                       int8_t *Gs, hipStream_t s);
 void launch_tile_norms(const double *part, int parts, int64_t ntiles, double *tnorm, hipStream_t s);
 void launch_expand_tiles(const int32_t *D, const double *etab, int64_t etab_len, double lambda,
                          int vmode, const double *Ec, const TileLayout &L, float *A,
