@@ -55,11 +55,11 @@ def gram_source_hash():
     return h.hexdigest()
 
 
-def gram_traffic():
+def gram_traffic(tile=512):
     """HBM bytes per Gram launch from the committed PMC summary (FETCH_SIZE and
     WRITE_SIZE of the kernel, each scaled by what the counter reads for a
     device copy of known size), or None when the kernel's sources changed
-    since the counters were taken."""
+    since the counters were taken or the summary is of another tile size."""
     path = os.path.join(ROOT, TRAFFIC_FILE)
     if not os.path.exists(path):
         return None
@@ -75,7 +75,8 @@ def gram_traffic():
         cb = float(kv["copy_bytes"])
         fs = cb / (float(kv["copy_fetch_kib"]) * 1024.0)
         ws = cb / (float(kv["copy_write_kib"]) * 1024.0)
-        return (float(kv["fetch_kib"]) * 1024.0 * fs + float(kv["write_kib"]) * 1024.0 * ws)
+        return (float(kv["fetch_kib_t%d" % tile]) * 1024.0 * fs
+                + float(kv["write_kib_t%d" % tile]) * 1024.0 * ws)
     except (KeyError, ValueError, ZeroDivisionError):
         return None
 
@@ -268,7 +269,7 @@ def main():
     out["roofline"] = {
         "kernel": "k_gram_tiles (INT8 MFMA Gram + distance/exp epilogue)",
         "bound": "mfma", "achieved": achieved, "peak": PEAK["int8_TOPs"], "unit": "TOP/s",
-        "frac": achieved / PEAK["int8_TOPs"], "traffic": gram_traffic(),
+        "frac": achieved / PEAK["int8_TOPs"], "traffic": gram_traffic(nb),
         "avg_launch_ms": gram_avg_s * 1e3,
     }
     u_ms, u_cnt = stages["update"]

@@ -486,7 +486,8 @@ krr_status krr_tuning_cache_load(const char *path, const char *key, krr_tuning *
 /* ---- per-stage timers (HIP events on the context stream) -------------- */
 
 enum {
-  KRR_STAGE_ROW_NORMS = 0, /* genotype squared norms + value check */
+  KRR_STAGE_ROW_NORMS = 0, /* genotype squared norms + value check + the Gram's
+                              slab-major copy of the genotypes */
   KRR_STAGE_GRAM = 1,      /* INT8 symmetric Gram + distance/exp epilogue */
   KRR_STAGE_POTRF = 2,     /* diagonal-tile Cholesky + inverse */
   KRR_STAGE_TRSM = 3,      /* panel triangular solve */

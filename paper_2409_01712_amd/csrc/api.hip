@@ -607,13 +607,25 @@ krr_status krr_build_kernel_ex(krr_context ctx, const int8_t *G, int64_t n, int6
       }
     }
     launch_fill_i32(flag, 1, 0, s);
+    // the genotypes slab-major for the Gram (kept with the kernel until its
+    // release); KRR_GRAM_SLAB=0 streams the row-major matrix instead
+    static const bool slab = [] {
+      const char *e = getenv("KRR_GRAM_SLAB");
+      return !e || atoi(e) != 0;
+    }();
+    if (slab) {
+      K->gs_bytes = L.np * ((K->gram_m() + 63) / 64) * 64;
+      if ((st = dalloc_t(ctx, &K->Gs, K->gs_bytes)) != KRR_SUCCESS) break;
+    }
     {
-      Stage t(ctx, KRR_STAGE_ROW_NORMS);
+      Stage t(ctx, KRR_STAGE_ROW_NORMS);  // the genotypes' preparation
       launch_row_norms(G, n, L.np, m, ldg, K->nrm, flag, s);  // and the genotype check
       if (K->H) {
         launch_ibs_encode(G, n, m, ldg, K->H, K->ldh, s);
         launch_row_norms(K->H, n, L.np, K->ldh, K->ldh, K->nrm, flag, s);
       }
+      if (K->Gs)
+        launch_slab_major(K->gram_src(), n, L.np, K->gram_m(), K->gram_ld(), K->Gs, s);
     }
     int32_t hflag = 0;
     if (hipMemcpyAsync(&hflag, flag, 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
@@ -630,19 +642,7 @@ krr_status krr_build_kernel_ex(krr_context ctx, const int8_t *G, int64_t n, int6
     else if (K->kind == KRR_KERNEL_GAUSSIAN) launch_exp_table(K->etab, K->etab_len, gamma, s);
     if (K->Ec) launch_conf_factor(K->Cc, n, K->q, K->q, gamma, L, K->Ec, s);
     {
-      // the genotypes slab-major for the Gram (kept with the kernel until its
-      // release); KRR_GRAM_SLAB=0 streams the row-major matrix instead
-      static const bool slab = [] {
-        const char *e = getenv("KRR_GRAM_SLAB");
-        return !e || atoi(e) != 0;
-      }();
-      if (slab) {
-        K->gs_bytes = L.np * ((K->gram_m() + 63) / 64) * 64;
-        if ((st = dalloc_t(ctx, &K->Gs, K->gs_bytes)) != KRR_SUCCESS) break;
-      }
       Stage t(ctx, KRR_STAGE_GRAM);
-      if (K->Gs)
-        launch_slab_major(K->gram_src(), n, L.np, K->gram_m(), K->gram_ld(), K->Gs, s);
       launch_gram_tiles(K->gram_src(), K->gram_m(), K->gram_ld(), K->nrm, K->etab, K->etab_len,
                         lambda, L, K->D, K->A, K->tnorm_part, K->vmode(), K->Ec, K->Gs, s);
     }
