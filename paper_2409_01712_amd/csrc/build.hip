@@ -124,13 +124,46 @@ struct SlabSrc {
 // stored and is the value.  Ec (or null): FP64 confounder factors
 // exp(-gamma dc_ij) in the packed tile layout, multiplied in.
 // Gs (or null): the same genotypes slab-major (k_slab_major), read instead of G.
+// Block (bi, bj) -- 256-row blocks of the padded matrix -- that workgroup t
+// computes in the grouped order: super-rows of GRP block rows, column by
+// column within a super-row, the rows of one column consecutive.  The blocks
+// computed are those with tile(bi) >= tile(bj), tile(b) = b / SB (the lower
+// tiles, diagonal tiles whole).  The workgroups an XCD runs at one time then
+// cover a GRP x 8 patch of blocks, reading GRP + 8 blocks of rows per K slab,
+// in place of one block row of tiles (at tile 256: 1 + 32 blocks of rows).
+constexpr int GRAM_GRP = 4;
+KRR_DEV void gram_grouped(int64_t t, int nbk, int SB, int &bi, int &bj) {
+  for (int r0 = 0; r0 < nbk; r0 += GRAM_GRP) {
+    const int h = min(GRAM_GRP, nbk - r0);
+    const int64_t full = (int64_t)r0 * h;  // columns left of the super-row: every row
+    if (t < full) {
+      bj = (int)(t / h);
+      bi = r0 + (int)(t % h);
+      return;
+    }
+    t -= full;
+    const int cend = min(nbk, (r0 + h - 1) / SB * SB + SB);
+    for (int c = r0; c < cend; ++c) {
+      const int rfirst = max(r0, c / SB * SB);  // first row whose tile reaches column c's
+      const int cnt = r0 + h - rfirst;
+      if (t < cnt) {
+        bj = c;
+        bi = rfirst + (int)t;
+        return;
+      }
+      t -= cnt;
+    }
+  }
+  bi = bj = 0;  // t past the last block: not launched
+}
+
 template <class S>
 KRR_DEV void gram_block(const int8_t *__restrict__ G, int64_t n, int64_t m, int64_t ldg,
                         const int32_t *__restrict__ nrm, const double *__restrict__ etab,
                         int64_t etab_len, double lambda, int nb, int SB, int32_t *__restrict__ D,
                         float *__restrict__ A, double *part, int64_t bid, int vmode,
                         const double *__restrict__ Ec, const int8_t *__restrict__ Gs = nullptr,
-                        int64_t np = 0) {
+                        int64_t np = 0, bool grouped = false) {
   constexpr int BM = S::kBM, BN = S::kBN, NW = S::THREADS / 64;
   extern __shared__ __attribute__((aligned(16))) uint8_t lds[];
   __shared__ double shd[NW];
@@ -143,12 +176,17 @@ KRR_DEV void gram_block(const int8_t *__restrict__ G, int64_t n, int64_t m, int6
     for (int q = threadIdx.x; q < nhi; q += S::THREADS) ehi[q] = etab[(int64_t)q * EXP_LO];
   }
   const int nsub = SB * SB;
-  const int sub = (int)(bid % nsub);
-  const int64_t t = bid / nsub;  // tile in the order of the launch
-  int I, J;
-  tri_decode(t, I, J);
-  const int64_t tt = tri_index(I, J);  // its place in the packed storage
-  const int si = sub / SB, sj = sub % SB;
+  int I, J, si, sj;
+  if (grouped) {
+    int bi, bj;
+    gram_grouped(bid, (int)((n + nb - 1) / nb) * SB, SB, bi, bj);
+    I = bi / SB, J = bj / SB, si = bi % SB, sj = bj % SB;
+  } else {  // tiles in packed order, the sub-blocks of a tile consecutive
+    tri_decode(bid / nsub, I, J);
+    si = (int)(bid % nsub) / SB, sj = (int)(bid % nsub) % SB;
+  }
+  const int sub = si * SB + sj;
+  const int64_t tt = tri_index(I, J);  // the tile's place in the packed storage
   const int64_t row0 = (int64_t)I * nb + si * BM, col0 = (int64_t)J * nb + sj * BN;
   const int arows = (int)max((int64_t)0, min((int64_t)BM, n - row0));
   const int brows = (int)max((int64_t)0, min((int64_t)BN, n - col0));
@@ -213,9 +251,10 @@ __global__ __launch_bounds__(S::THREADS) void k_gram_tiles(const int8_t *__restr
                                                     float *__restrict__ A, double *part,
                                                     int vmode,
                                                     const double *__restrict__ Ec,
-                                                    const int8_t *__restrict__ Gs, int64_t np) {
+                                                    const int8_t *__restrict__ Gs, int64_t np,
+                                                    int grouped) {
   gram_block<S>(G, n, m, ldg, nrm, etab, etab_len, lambda, nb, SB, D, A, part,
-                xcd_remap(blockIdx.x, gridDim.x), vmode, Ec, Gs, np);
+                xcd_remap(blockIdx.x, gridDim.x), vmode, Ec, Gs, np, grouped != 0);
 }
 
 // Instance of a batch that owns workgroup `bid`: the last job whose first
@@ -249,6 +288,11 @@ void launch_gram_tiles(const int8_t *G, int64_t m, int64_t ldg, const int32_t *n
                        int32_t *D, float *A, double *tnorm_part, int vmode,
                        const double *Ec, const int8_t *Gs, hipStream_t s) {
   const int SB = L.nb / GramShape::kBM;
+  // KRR_GRAM_ORDER=0: tiles in packed order (for comparison); else grouped
+  static const int grouped = [] {
+    const char *e = getenv("KRR_GRAM_ORDER");
+    return (e && atoi(e) == 0) ? 0 : 1;
+  }();
   const int64_t blocks = L.ntiles() * SB * SB;
   static bool attr = false;
   if (!attr) {
@@ -259,7 +303,7 @@ void launch_gram_tiles(const int8_t *G, int64_t m, int64_t ldg, const int32_t *n
   hipLaunchKernelGGL((k_gram_tiles<GramShape>), dim3((unsigned)blocks), dim3(GramShape::THREADS),
                      GramShape::LDS_BYTES, s, G, L.n, m,
                      ldg, nrm, etab, etab_len, lambda, L.nb, SB, D, A, tnorm_part, vmode, Ec, Gs,
-                     L.np);
+                     L.np, grouped);
 }
 
 int64_t gram_blocks(const TileLayout &L) {

@@ -86,7 +86,7 @@ KRR_DEV float pow2_scale(float maxabs, float limit) {
 struct OpI8 {  // int8 x int8 -> int32 (v_mfma_i32_32x32x32_i8)
   typedef int8_t elem;
   typedef v16i acc_t;
-  static constexpr int ebytes = 1;
+  static constexpr int ebytes = 1, NMMA = 2;  // MFMA instructions per mma()
   KRR_DEV void mma(acc_t &c, const v4i &a0, const v4i &a1, const v4i &b0, const v4i &b1) const {
     c = __builtin_amdgcn_mfma_i32_32x32x32_i8(a0, b0, c, 0, 0, 0);
     c = __builtin_amdgcn_mfma_i32_32x32x32_i8(a1, b1, c, 0, 0, 0);
@@ -96,7 +96,7 @@ struct OpI8 {  // int8 x int8 -> int32 (v_mfma_i32_32x32x32_i8)
 struct OpF16 {  // fp16 x fp16 -> fp32 (v_mfma_f32_32x32x16_f16)
   typedef _Float16 elem;
   typedef v16f acc_t;
-  static constexpr int ebytes = 2;
+  static constexpr int ebytes = 2, NMMA = 2;
   KRR_DEV void mma(acc_t &c, const v4i &a0, const v4i &a1, const v4i &b0, const v4i &b1) const {
     c = __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(v8h, a0), __builtin_bit_cast(v8h, b0), c, 0, 0, 0);
     c = __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(v8h, a1), __builtin_bit_cast(v8h, b1), c, 0, 0, 0);
@@ -109,7 +109,7 @@ struct OpF16 {  // fp16 x fp16 -> fp32 (v_mfma_f32_32x32x16_f16)
 struct OpF8 {
   typedef uint8_t elem;
   typedef v16f acc_t;
-  static constexpr int ebytes = 1;
+  static constexpr int ebytes = 1, NMMA = 1;
   int sa = 127, sb = 127;
   KRR_DEV void mma(acc_t &c, const v4i &a0, const v4i &a1, const v4i &b0, const v4i &b1) const {
     v8i a = {a0[0], a0[1], a0[2], a0[3], a1[0], a1[1], a1[2], a1[3]};
@@ -122,7 +122,7 @@ struct OpF8 {
 struct OpF32 {  // fp32 x fp32 -> fp32 (v_mfma_f32_32x32x2f32, 8 per slab)
   typedef float elem;
   typedef v16f acc_t;
-  static constexpr int ebytes = 4;
+  static constexpr int ebytes = 4, NMMA = 8;
   KRR_DEV void mma(acc_t &c, const v4i &a0, const v4i &a1, const v4i &b0, const v4i &b1) const {
 #pragma unroll
     for (int e = 0; e < 4; ++e)
@@ -328,6 +328,36 @@ KRR_DEV void bar_nofence() {
   __builtin_amdgcn_sched_barrier(0);
 }
 
+// Instruction order of one streamed step, for the compiler's scheduler: one
+// MFMA, then one LDS fragment read, while both last; then one MFMA and one
+// direct load; then the MFMAs left.  Left to itself the scheduler puts every
+// fragment read after the step's last MFMA, so the next step's barrier waits
+// for all of the workgroup's LDS reads after its MFMAs instead of while they
+// run.  (Masks: 0x008 MFMA, 0x100 LDS read, 0x060 vector memory.)
+#ifndef KRR_GEMM_SCHED
+#define KRR_GEMM_SCHED 1
+#endif
+template <int NMM, int NDS, int NVM>
+KRR_DEV void sched_interleave() {
+#if KRR_GEMM_SCHED
+  constexpr int P = NMM < NDS ? NMM : NDS;
+  constexpr int Q = NMM - P < NVM ? NMM - P : NVM;
+#pragma unroll
+  for (int i = 0; i < P; ++i) {
+    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+    __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+  }
+  if (NDS > P) __builtin_amdgcn_sched_group_barrier(0x100, NDS - P, 0);
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+    __builtin_amdgcn_sched_group_barrier(0x060, 1, 0);
+  }
+  if (NVM > Q) __builtin_amdgcn_sched_group_barrier(0x060, NVM - Q, 0);
+  if (NMM > P + Q) __builtin_amdgcn_sched_group_barrier(0x008, NMM - P - Q, 0);
+#endif
+}
+
 // K source of one product: ptr(side_a, s) is the address of slab s (64 bytes
 // of K) in row 0 of A (side_a) or of B; op(s) is the MFMA operation for slab
 // s.  Both are branch-free.  Plain contiguous operands:
@@ -425,7 +455,8 @@ KRR_DEV void gemm_nt_stream(const Src &src, int64_t lda, int arows, int64_t ldb,
       issue((int)(s % NST), min(s + NST, last));
       frag((int)((s + 1) % NST), na0, na1, nb0, nb1);
       no = src.op(min(s + 1, last));
-      mma_rows(0, WTM, co, ca0, ca1, cb0, cb1);  // the compiler interleaves
+      mma_rows(0, WTM, co, ca0, ca1, cb0, cb1);
+      sched_interleave<WTM * WTN * Op::NMMA, 2 * (WTM + WTN), LPW>();
     };
     for (int64_t s = 0; s < nmain; s += 2) {
       step(s, ox, xa0, xa1, xb0, xb1, oy, ya0, ya1, yb0, yb1);
