@@ -306,6 +306,142 @@ __global__ __launch_bounds__(256) void k_sweep_panel2(const float *__restrict__ 
                         acc);
 }
 
+// Panel launch of a pair, wide form, built for latency.  Every wave first
+// issues all of its loads: the output block's current values, its share of
+// the pair's 2 nb right-hand-side rows of the workgroup's 16-column block
+// (1 KiB chunks straight into LDS, column stride 2 nb + 4 floats so that the
+// sixteen columns an LDS read touches fall on distinct banks), and its 32 k
+// blocks of L (128 floats a lane); one counter wait for the first two and
+// one barrier, then each wave sums its k blocks in k order as they land.  At
+// nb = 256 a wave owns a whole 16-row job (16 W rows for W waves); at
+// nb = 512 two waves split a job's k range in halves, added in half order
+// through LDS (8 W rows).  Columns past r read column r - 1 (their results
+// are not stored).  The 16-row form needs one round trip per phase of loads
+// and a reduction across all four waves.
+template <bool FWD, int NB, int W>
+__global__ __launch_bounds__(64 * W) void k_sweep_panel2w(const float *__restrict__ Lst,
+                                                          const float *V, float *In, int k, int r,
+                                                          int64_t ldv) {
+  typedef __attribute__((address_space(3))) void lds_void;
+  constexpr int S = NB / 256, ROWS = 16 * W / S, RB = NB / ROWS, VST = 2 * NB + 4;
+  constexpr int CPC = NB / 128, VCH = 16 * CPC / W;  // 1 KiB chunks a column; a wave
+  static_assert(VCH * W == 16 * CPC && RB * ROWS == NB, "shape");
+  extern __shared__ __attribute__((aligned(16))) float vs[];
+  __shared__ v4f red[W / 2][64];
+  const int CJ = (r + 15) / 16;
+  const int64_t t = blockIdx.x / (RB * CJ);
+  const int rem = (int)(blockIdx.x % (RB * CJ)), rj = rem / CJ, cj = rem % CJ;
+  const int64_t i = FWD ? k + 2 + t : t;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, lg = lane >> 4;
+  const int job = wave / S, part = wave % S;
+  const int row0 = rj * ROWS + job * 16, R = row0 + li;
+  const int col = 16 * cj + li;
+  const bool owner = part == 0 && col < r;
+  float4 *q = (float4 *)(In + tile_off<true>(i, NB, r) + (int64_t)min(col, r - 1) * ldv + row0 +
+                         4 * lg);
+  const float4 old = *q;  // this workgroup's alone in the launch
+  const float *Vk = V + tile_off<true>(k, NB, r);
+#pragma unroll
+  for (int u = 0; u < VCH; ++u) {
+    const int h = wave + W * u, c = h / CPC, hp = h % CPC;
+    const int cc = min(16 * cj + c, r - 1);
+    __builtin_amdgcn_global_load_lds((const void *)(Vk + (int64_t)cc * ldv + 256 * hp + 4 * lane),
+                                     (lds_void *)(vs + c * VST + 256 * hp), 16, 0, 0);
+  }
+  asm volatile("" ::: "memory");
+  const int64_t te = (int64_t)NB * NB;
+  const float *M1 = Lst + (FWD ? tri_index(i, k) : tri_index(k, i)) * te;
+  const float *M2 = Lst + (FWD ? tri_index(i, k + 1) : tri_index(k + 1, i)) * te;
+  constexpr int KBT = NB / 16;  // k blocks per tile
+  // A elements of k block kb = 32 part + u: lane (li, lg) holds M(R, 16 kb' +
+  // 4 lg + e) of the block's tile, read along k (forward) or down a column of
+  // the stored tile (backward, transposed)
+  float a[32][4];
+#pragma unroll
+  for (int u = 0; u < 32; ++u) {
+    const int kb = 32 * part + u;
+    const float *M = kb < KBT ? M1 : M2;
+    const int kk = 16 * (kb < KBT ? kb : kb - KBT) + 4 * lg;
+    if (FWD) {
+      const float4 v = *(const float4 *)(M + (int64_t)R * NB + kk);
+      a[u][0] = v.x; a[u][1] = v.y; a[u][2] = v.z; a[u][3] = v.w;
+    } else {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) a[u][e] = M[(int64_t)(kk + e) * NB + R];
+    }
+  }
+  // the loads of L are the last 32 (forward) or 128 (backward, one float a
+  // load) vector-memory operations of the wave: everything before them is done
+  vm_wait<FWD ? 32 : 63>();
+  bar_nofence();
+  const float *vl = vs + li * VST + 4 * lg + 16 * 32 * part;
+  v4f acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int u = 0; u < 32; ++u) {
+    const float4 b = *(const float4 *)(vl + 16 * u);
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u][0], b.x, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u][1], b.y, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u][2], b.z, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[u][3], b.w, acc, 0, 0, 0);
+  }
+  if (S == 2) {  // the second half's sum added to the first's
+    if (part == 1) red[job][lane] = acc;
+    __syncthreads();
+    if (part == 0) acc += red[job][lane];
+  }
+  if (owner) {
+    float4 v = old;
+    v.x -= acc[0]; v.y -= acc[1]; v.z -= acc[2]; v.w -= acc[3];
+    *q = v;
+  }
+}
+
+// Panel launches of the paired sweeps: k_sweep_panel2w with 4 waves a
+// workgroup, KRR_SWEEP_WIDE=8 with 8 (measured slower: a workgroup's latency
+// grows with its waves a SIMD), KRR_SWEEP_WIDE=0 the 16-row form (read per
+// launch).
+static int sweep_wide() {
+  const char *e = getenv("KRR_SWEEP_WIDE");
+  if (!e) return 4;
+  const int w = atoi(e);
+  return w == 0 ? 0 : (w == 8 ? 8 : 4);
+}
+
+template <bool FWD, int NB, int W>
+static void launch_panel2w(const float *Astore, const float *V, float *In, int k, int ntiles,
+                           int r, int64_t ldv, hipStream_t s) {
+  const size_t lds = (size_t)16 * (2 * NB + 4) * sizeof(float);  // 65.8 KB at nb = 512
+  static bool attr = false;
+  if (!attr) {
+    (void)hipFuncSetAttribute((const void *)k_sweep_panel2w<FWD, NB, W>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    attr = true;
+  }
+  const int64_t blocks = (int64_t)ntiles * (NB * (NB / 256) / (16 * W)) * ((r + 15) / 16);
+  hipLaunchKernelGGL((k_sweep_panel2w<FWD, NB, W>), dim3((unsigned)blocks), dim3(64 * W), lds, s,
+                     Astore, V, In, k, r, ldv);
+}
+
+template <bool FWD>
+static void launch_panel2(const float *Astore, const float *V, float *In, int k, int ntiles,
+                          int nb, int r, int64_t ldv, hipStream_t s) {
+  const int w = sweep_wide();
+  if (w == 4 && nb == 256) {
+    launch_panel2w<FWD, 256, 4>(Astore, V, In, k, ntiles, r, ldv, s);
+  } else if (w == 4 && nb == 512) {
+    launch_panel2w<FWD, 512, 4>(Astore, V, In, k, ntiles, r, ldv, s);
+  } else if (w && nb == 256) {
+    launch_panel2w<FWD, 256, 8>(Astore, V, In, k, ntiles, r, ldv, s);
+  } else if (w && nb == 512) {
+    launch_panel2w<FWD, 512, 8>(Astore, V, In, k, ntiles, r, ldv, s);
+  } else {
+    hipLaunchKernelGGL(k_sweep_panel2<FWD>,
+                       dim3((unsigned)((int64_t)ntiles * (nb / 16) * ((r + 15) / 16))), dim3(256),
+                       0, s, Astore, V, In, k, nb, r, ldv);
+  }
+}
+
 // The same steps for a batch of instances in lockstep (blockIdx.y = instance):
 // step k of instance j runs when k < its tile count; forward B -> Z, backward
 // Z -> X.  Workgroups without work return before any barrier.
@@ -359,9 +495,7 @@ void launch_fwd_sweep(const float *Astore, const float *Linv, const float *C, co
     if (C && k + 1 < NT) {
       hipLaunchKernelGGL(k_sweep_diag2<true>, dim3(2 * per), dim3(256), 0, s, Linv,
                          C + (int64_t)(k / 2) * te, B, Z, k, nb, r, ldv);
-      if (NT - 2 - k > 0)
-        hipLaunchKernelGGL(k_sweep_panel2<true>, dim3((unsigned)((NT - 2 - k) * per)), dim3(256),
-                           0, s, Astore, Z, B, k, nb, r, ldv);
+      if (NT - 2 - k > 0) launch_panel2<true>(Astore, Z, B, k, NT - 2 - k, nb, r, ldv, s);
       k += 2;
       continue;
     }
@@ -384,9 +518,7 @@ void launch_bwd_sweep(const float *Astore, const float *Linv, const float *C, co
       const int k0 = k - 1;
       hipLaunchKernelGGL(k_sweep_diag2<false>, dim3(2 * per), dim3(256), 0, s, Linv,
                          C + (int64_t)(k0 / 2) * te, Z, X, k0, nb, r, ldv);
-      if (k0 > 0)
-        hipLaunchKernelGGL(k_sweep_panel2<false>, dim3((unsigned)(k0 * per)), dim3(256), 0, s,
-                           Astore, X, Z, k0, nb, r, ldv);
+      if (k0 > 0) launch_panel2<false>(Astore, X, Z, k0, k0, nb, r, ldv, s);
       k -= 2;
       continue;
     }

@@ -249,6 +249,41 @@ def test_paired_sweeps_match_single_steps(monkeypatch, n):
     c.close()
 
 
+@pytest.mark.parametrize("n,r,tile", [(700, 5, 256), (1500, 17, 256), (1300, 40, 512),
+                                       (2600, 16, 512)])
+def test_wide_panel_sweeps_match_narrow(monkeypatch, n, r, tile):
+    """The paired sweeps' panel launches with 64-row workgroups (right-hand sides
+    staged in LDS, each wave summing its rows over all k) agree with the 16-row
+    form (k blocks dealt over the waves, summed across them) to FP32 rounding:
+    several panel tiles, 1-3 column blocks of right-hand sides, ragged n; the
+    refined result matches the oracle."""
+    m = 700
+    G = _gen(n, m, seed=n + 11)
+    Y = synth.phenotypes(G, r, n_pairs=5, n_add=3, seed=n + 12, h2=0.5)
+    gamma, lam = 1.0 / m, 0.1
+    c = krr.krr_create(0, tile=tile)
+    K = krr.krr_build_kernel(c, _dev(G), gamma, lam)
+    F = krr.krr_factor(c, K, krr.plain_fp32_policy())
+    none = krr.Refine(method=krr.KRR_REFINE_NONE)
+    Xw, _, _ = krr.krr_solve(c, F, _dev(Y), none)  # 4 waves a workgroup
+    monkeypatch.setenv("KRR_SWEEP_WIDE", "8")
+    X8, _, _ = krr.krr_solve(c, F, _dev(Y), none)
+    monkeypatch.setenv("KRR_SWEEP_WIDE", "0")
+    Xn, _, _ = krr.krr_solve(c, F, _dev(Y), none)
+    monkeypatch.delenv("KRR_SWEEP_WIDE")
+    # the same FP32 products summed in another order; a missed k block, a wrong
+    # tile or right-hand-side column would move X by O(1)
+    assert _colrel(Xw.cpu().numpy(), Xn.cpu().numpy()) <= 1e-4
+    # 4 or 8 waves a workgroup: the same sums in the same order
+    assert np.array_equal(Xw.cpu().numpy(), X8.cpu().numpy())
+    X, info, st = krr.krr_solve(c, F, _dev(Y), krr.Refine(tol=1e-8))
+    assert info.converged == 1
+    assert _colrel(X.cpu().numpy(), oracle.fit(G, Y, gamma, lam)) <= TOL
+    F.release()
+    K.release()
+    c.close()
+
+
 @pytest.mark.skip(reason="persistent one-launch sweeps are switched off (KRR_SWEEP_PAIRS=2 "
                   "returns KRR_ERROR_NOT_SUPPORTED): the first GPU runs hung at n=200 (one "
                   "tile), also with time-bounded waits, and the cause is not known")
