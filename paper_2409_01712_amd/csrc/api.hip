@@ -394,6 +394,9 @@ krr_status krr_create(krr_context *out, int device, void *stream, const krr_opti
   if (device < 0 || device >= count) return KRR_ERROR_INVALID_VALUE;
   HIPCHK(hipSetDevice(device));
   CHK(scratch_init(device));
+  build_kernel_attrs();
+  factor_kernel_attrs();
+  solve_kernel_attrs();
   krr_context c = new krr_context_s();
   c->device = device;
   c->stream = (hipStream_t)stream;
@@ -811,6 +814,13 @@ krr_status krr_kernel_tile_norms(krr_kernel K, double *host_dst, int64_t count) 
   return KRR_SUCCESS;
 }
 
+// Slots of the split-K diagonal-tile load: up to KRR_MAX_GROUP chunks of
+// every 64 x 64 block of the lower half of a tile.
+static size_t load_part_bytes(const TileLayout &L) {
+  const int NB = L.nb / 64;
+  return (size_t)KRR_MAX_GROUP * (NB * (NB + 1) / 2) * 64 * 64 * 4;
+}
+
 static void factor_work_free(krr_context c, FactorWork &w, const TileLayout &L) {
   const int64_t te = L.tile_elems(), pt = std::max(L.nt - 1, 1);
   const int parts = std::max((L.nb / 64) * (L.nb / 64), L.nb / 16);
@@ -831,11 +841,12 @@ static void factor_work_free(krr_context c, FactorWork &w, const TileLayout &L) 
   dfree(c, w.pmax_part, pt * parts * 4);
   dfree(c, w.flag, 4);
   dfree(c, w.counts, 3 * 8);
+  dfree(c, w.lpart, load_part_bytes(L));
   w = FactorWork();
 }
 
 static krr_status factor_work_alloc(krr_context c, FactorWork &w, const TileLayout &L,
-                                    bool need16, bool need8, int slots) {
+                                    bool need16, bool need8, int slots, bool split_load = true) {
   const int64_t te = L.tile_elems(), pt = std::max(L.nt - 1, 1);
   const int parts = std::max((L.nb / 64) * (L.nb / 64), L.nb / 16);
   const int64_t chunk = std::min(w.inv_chunk, L.nt);
@@ -862,6 +873,7 @@ static krr_status factor_work_alloc(krr_context c, FactorWork &w, const TileLayo
   WA(w.pmax_part, pt * parts * 4);
   WA(w.flag, 4);
   WA(w.counts, 3 * 8);
+  if (split_load) WA(w.lpart, load_part_bytes(L));  // single instance: split-K tile loads
 #undef WA
   return KRR_SUCCESS;
 }
@@ -955,6 +967,19 @@ static int group_size(krr_context ctx, const FactorPlan &fp) {
 // tile Cholesky on s (one stream) or on the context's three streams joined
 // back into s (lookahead), and counts the updates per precision.  Nothing
 // here waits for the device.
+// The lookahead schedule's events (4 NT + 2 groups + 5), created ahead of use
+// (and of any capture of the schedule).
+static bool sched_events(krr_context ctx, int NT, int g) {
+  std::vector<hipEvent_t> &E = ctx->sched_ev;
+  const size_t need = (size_t)4 * NT + 2 * ((NT + g - 1) / g) + 5;
+  while (E.size() < need) {
+    hipEvent_t e;
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return false;
+    E.push_back(e);
+  }
+  return true;
+}
+
 static krr_status factor_enqueue(krr_context ctx, krr_kernel K, krr_factorization F,
                                  const krr_precision_policy &p, const FactorPlan &fp,
                                  FactorWork &w, uint8_t *dmap, int64_t mapsz,
@@ -1063,13 +1088,7 @@ static krr_status factor_enqueue(krr_context ctx, krr_kernel K, krr_factorizatio
     hipStream_t sm = ctx->fmain, sd = ctx->side, sx = ctx->aux;
     const int ngroups = (NT + g - 1) / g;
     std::vector<hipEvent_t> &E = ctx->sched_ev;
-    const size_t need = (size_t)4 * NT + 2 * ngroups + 5;
-    bool ok = true;
-    while (ok && E.size() < need) {
-      hipEvent_t e;
-      ok = hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess;
-      if (ok) E.push_back(e);
-    }
+    bool ok = sched_events(ctx, NT, g);
     hipEvent_t *e_t1 = E.data(), *e_conv = e_t1 + NT, *e_uin = e_conv + NT,
                *e_udiag = e_uin + NT, *e_aux = e_udiag + NT, *e_narrow = e_aux + ngroups,
                *e_join = e_narrow + ngroups, e_early = e_join[4];
@@ -1167,6 +1186,11 @@ static krr_status factor_enqueue(krr_context ctx, krr_kernel K, krr_factorizatio
   return KRR_SUCCESS;
 }
 
+static krr_status factor_run(krr_context ctx, krr_kernel K, krr_factorization F,
+                             const krr_precision_policy &p, const FactorPlan &fp, FactorWork &w,
+                             uint8_t *dmap, int64_t mapsz, const uint8_t *fmap,
+                             const uint8_t *pcap, bool lookahead, int g, hipStream_t s);
+
 krr_status krr_factor(krr_context ctx, krr_kernel K, const krr_precision_policy *policy,
                       krr_factorization *out) {
   if (!out) return KRR_ERROR_INVALID_VALUE;
@@ -1234,7 +1258,7 @@ krr_status krr_factor(krr_context ctx, krr_kernel K, const krr_precision_policy 
         st = KRR_ERROR_HIP;
         break;
       }
-      if ((st = factor_enqueue(ctx, K, F, p, fp, w, dmap, mapsz, fmap, pcap, lookahead, g, s)) !=
+      if ((st = factor_run(ctx, K, F, p, fp, w, dmap, mapsz, fmap, pcap, lookahead, g, s)) !=
           KRR_SUCCESS)
         break;
       if ((st = launch_ok()) != KRR_SUCCESS) break;
@@ -1360,6 +1384,23 @@ static krr_status graph_run(krr_context ctx, const std::string &key, hipStream_t
   return launch_ok();
 }
 
+// One factorization attempt of a single instance, its launches enqueued
+// directly.  (A HIP-graph form of the three-stream schedule -- captured once
+// per key of every address and value its launches take, then replayed, to
+// take the host's enqueue time off the critical path -- ended the process
+// with a host segmentation fault in this call on its first GPU runs, also
+// with the kernel attributes and the schedule's events set up before the
+// capture; the cause is not known, so it is switched off: KRR_FACTOR_GRAPH=1
+// returns KRR_ERROR_NOT_SUPPORTED.)
+static krr_status factor_run(krr_context ctx, krr_kernel K, krr_factorization F,
+                             const krr_precision_policy &p, const FactorPlan &fp, FactorWork &w,
+                             uint8_t *dmap, int64_t mapsz, const uint8_t *fmap,
+                             const uint8_t *pcap, bool lookahead, int g, hipStream_t s) {
+  const char *e = getenv("KRR_FACTOR_GRAPH");
+  if (e && atoi(e) != 0) return KRR_ERROR_NOT_SUPPORTED;
+  return factor_enqueue(ctx, K, F, p, fp, w, dmap, mapsz, fmap, pcap, lookahead, g, s);
+}
+
 krr_status krr_context_graphs(krr_context ctx, int64_t *cached, int64_t *launches) {
   if (!ctx) return KRR_ERROR_INVALID_VALUE;
   if (cached) *cached = (int64_t)ctx->graphs.size();
@@ -1435,7 +1476,7 @@ krr_status krr_factor_batched(krr_context ctx, int32_t batch, const krr_kernel *
       mapsz[b] = (int64_t)L.nt * L.ntiles();
       if ((st = dalloc_t(ctx, &dmap[b], mapsz[b])) != KRR_SUCCESS) break;
       if ((st = factor_work_alloc(ctx, W[b], L, need16, fp.allow8,
-                                  std::min(2 * g, KRR_SLOTS))) != KRR_SUCCESS)
+                                  std::min(2 * g, KRR_SLOTS), false)) != KRR_SUCCESS)
         break;
       nts[b] = L.nt;
       launch_fill_i32(W[b].flag, 1, 0, s);

@@ -294,12 +294,7 @@ void launch_gram_tiles(const int8_t *G, int64_t m, int64_t ldg, const int32_t *n
     return (e && atoi(e) == 0) ? 0 : 1;
   }();
   const int64_t blocks = L.ntiles() * SB * SB;
-  static bool attr = false;
-  if (!attr) {
-    hipFuncSetAttribute((const void *)k_gram_tiles<GramShape>,
-                        hipFuncAttributeMaxDynamicSharedMemorySize, GramShape::LDS_BYTES);
-    attr = true;
-  }
+  build_kernel_attrs();
   hipLaunchKernelGGL((k_gram_tiles<GramShape>), dim3((unsigned)blocks), dim3(GramShape::THREADS),
                      GramShape::LDS_BYTES, s, G, L.n, m,
                      ldg, nrm, etab, etab_len, lambda, L.nb, SB, D, A, tnorm_part, vmode, Ec, Gs,
@@ -315,12 +310,7 @@ int gram_parts(int nb) { return (nb / GramShape::kBM) * (nb / GramShape::kBM); }
 
 void launch_gram_tiles_batched(const BuildJob *jobs, int njobs, int64_t blocks, int64_t m, int nb,
                                hipStream_t s) {
-  static bool attr = false;
-  if (!attr) {
-    hipFuncSetAttribute((const void *)k_gram_tiles_batched<GramShape>,
-                        hipFuncAttributeMaxDynamicSharedMemorySize, GramShape::LDS_BYTES);
-    attr = true;
-  }
+  build_kernel_attrs();
   hipLaunchKernelGGL((k_gram_tiles_batched<GramShape>), dim3((unsigned)blocks),
                      dim3(GramShape::THREADS), GramShape::LDS_BYTES, s, jobs, njobs, m, nb,
                      nb / GramShape::kBM);
@@ -607,12 +597,7 @@ void launch_cross_gram(const int8_t *T, int64_t nt_rows, const int32_t *nrm_t, c
                        hipStream_t s) {
   constexpr int BM = GramShape::kBM, BN = GramShape::kBN;
   const int64_t nbr = (nt_rows + BM - 1) / BM, nbc = (cols_padded + BN - 1) / BN;
-  static bool attr = false;
-  if (!attr) {
-    hipFuncSetAttribute((const void *)k_cross_gram<GramShape>,
-                        hipFuncAttributeMaxDynamicSharedMemorySize, GramShape::LDS_BYTES);
-    attr = true;
-  }
+  build_kernel_attrs();
   hipLaunchKernelGGL((k_cross_gram<GramShape>), dim3((unsigned)(nbr * nbc)),
                      dim3(GramShape::THREADS), GramShape::LDS_BYTES, s, T,
                      nt_rows, nrm_t, G, n, m, ldt, ldg, nrm_g, cols_padded, nbc, Dt, ldd,
@@ -732,6 +717,21 @@ void launch_int8_t_times_f64(const int8_t *A, int64_t rows, int64_t cols, int64_
   const dim3 grid((unsigned)((cols + 63) / 64), (unsigned)((r + 15) / 16));
   hipLaunchKernelGGL(k_int8_t_times_f64, grid, dim3(256), 0, s, A, rows, cols, lda, Y, r, ldy, B,
                      ldb);
+}
+
+// Dynamic-LDS limits of the Gram kernels (above the 64 KB default), set once
+// per process before their first launch; the context's creation calls it, so
+// that it never runs inside a stream capture.
+void build_kernel_attrs() {
+  static bool done = false;
+  if (done) return;
+  done = true;
+  (void)hipFuncSetAttribute((const void *)k_gram_tiles<GramShape>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, GramShape::LDS_BYTES);
+  (void)hipFuncSetAttribute((const void *)k_gram_tiles_batched<GramShape>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, GramShape::LDS_BYTES);
+  (void)hipFuncSetAttribute((const void *)k_cross_gram<GramShape>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, GramShape::LDS_BYTES);
 }
 
 }  // namespace krr

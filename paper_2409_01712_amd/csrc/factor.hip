@@ -748,6 +748,103 @@ __global__ __launch_bounds__(256) void k_potrf_load(float *__restrict__ Akk, T *
   potrf_load_body<T>(Akk, W, nb, du, blockIdx.x, If);
 }
 
+// The same load split over K, for one instance, in two launches.  First,
+// workgroup (blk, c) forms chunk c of the product (kc values of k of one
+// panel) for 64 x 64 block blk into a slot of its own; then one workgroup
+// per block adds the slots in chunk order and forms W = A - sum (the same
+// FP32 products, summed per chunk), and the one of block (0, 0) factors and
+// inverts it at once (the tile's first 64-column step, otherwise a launch of
+// its own).  The launch boundary orders the slots: no workgroup waits for
+// another and no device-wide fence is needed.
+__global__ __launch_bounds__(256) void k_potrf_load_part(int nb, DiagUpdate du, int kc,
+                                                         float *__restrict__ part) {
+  typedef DiagUpdShape S;
+  __shared__ __attribute__((aligned(16))) uint8_t lds[S::LDS_BYTES];
+  const int NB = nb / BS, nblk = NB * (NB + 1) / 2, cpp = nb / kc;
+  const int blk = (int)(blockIdx.x % nblk), c = (int)(blockIdx.x / nblk);
+  int bi, bj;
+  tri_decode(blk, bi, bj);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  OpF32::acc_t acc[S::WTM][S::WTN];
+  zero_acc(acc);
+  const float *P = du.P[c / cpp] + (c % cpp) * kc;
+  gemm_nt_core<OpF32, S>(OpF32{}, (const uint8_t *)(P + (int64_t)bi * 64 * nb), (int64_t)nb * 4,
+                         64, (const uint8_t *)(P + (int64_t)bj * 64 * nb), (int64_t)nb * 4, 64,
+                         (int64_t)kc * 4, acc, lds);
+  float *slot = part + ((int64_t)c * nblk + blk) * (BS * BS);
+#pragma unroll
+  for (int tm = 0; tm < S::WTM; ++tm)
+#pragma unroll
+    for (int tn = 0; tn < S::WTN; ++tn)
+#pragma unroll
+      for (int e = 0; e < 16; ++e)
+        slot[S::row(wave, tm, e, lane) * BS + S::col(wave, tn, lane)] = acc[tm][tn][e];
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_potrf_load_sum(float *__restrict__ Akk,
+                                                        T *__restrict__ W, T *__restrict__ WL,
+                                                        int nb, DiagUpdate du, int nch,
+                                                        const float *__restrict__ part,
+                                                        T *__restrict__ Dinv, int32_t *flag,
+                                                        int64_t colbase, float *Lf, float *If) {
+  __shared__ T Sb[BS][BS + 1];  // block (0, 0), overwritten by its factor
+  __shared__ T Xb[BS][BS + 1];  // and its inverse
+  const int NB = nb / BS, nblk = NB * (NB + 1) / 2;
+  const int blk = blockIdx.x;
+  int bi, bj;
+  tri_decode(blk, bi, bj);
+  if (blk == 0 && threadIdx.x < du.npan && du.pmap)
+    du.pmap[du.pmap_at[threadIdx.x]] = (uint8_t)KRR_PREC_FP32;
+  // four runs of four entries a thread; every slot and A load in flight at
+  // once (chunks past nch read as zeros, which leave the ordered sum as it is)
+  const float *slots = part + (int64_t)blk * (BS * BS);
+  const int64_t stride = (int64_t)nblk * (BS * BS);
+  float4 v[4][KRR_MAX_GROUP], a[4];
+#pragma unroll
+  for (int g = 0; g < 4; ++g) {
+    const int e = 4 * (threadIdx.x + 256 * g), r = e / BS, cc = e % BS;
+    a[g] = *(const float4 *)(Akk + (int64_t)(bi * BS + r) * nb + bj * BS + cc);
+#pragma unroll
+    for (int q = 0; q < KRR_MAX_GROUP; ++q)
+      v[g][q] = q < nch ? *(const float4 *)(slots + q * stride + e)
+                        : make_float4(0.f, 0.f, 0.f, 0.f);
+  }
+#pragma unroll
+  for (int g = 0; g < 4; ++g) {
+    const int e = 4 * (threadIdx.x + 256 * g), r = e / BS, cc = e % BS;
+    float4 sum = v[g][0];
+#pragma unroll
+    for (int q = 1; q < KRR_MAX_GROUP; ++q) {
+      sum.x += v[g][q].x;
+      sum.y += v[g][q].y;
+      sum.z += v[g][q].z;
+      sum.w += v[g][q].w;
+    }
+    const float av[4] = {a[g].x, a[g].y, a[g].z, a[g].w};
+    const float sv[4] = {sum.x, sum.y, sum.z, sum.w};
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const T val = (bj * BS + cc + j <= bi * BS + r) ? (T)av[j] - (T)sv[j] : (T)0;
+      W[(int64_t)(bi * BS + r) * nb + bj * BS + cc + j] = val;
+      if (blk == 0) Sb[r][cc + j] = val;
+    }
+  }
+  if (If && bi > bj) {  // the upper block, for the factor and inverse written in the steps
+    __syncthreads();    // (not read here: only lower entries are)
+    for (int e = threadIdx.x; e < BS * BS; e += 256) {
+      const int64_t o = (int64_t)(bj * BS + e / BS) * nb + bi * BS + e % BS;
+      Akk[o] = 0.0f;
+      If[o] = 0.0f;
+    }
+  }
+  if (blk == 0) {
+    __syncthreads();
+    diag64_body<T>(Sb, Xb, flag, colbase);
+    diag64_store<T>(Sb, Xb, WL, nb, Dinv, Lf, If);
+  }
+}
+
 // The FP64 (or FP32) inverse of tile k while it is formed in the steps: one of
 // two slots of the chunk buffer, so that the next tile's steps may run while
 // the last block row of this one is still being formed.
@@ -765,10 +862,21 @@ static void potrf_tile_t(float *Akk, int k, const TileLayout &L, FactorWork &w,
   T *Winv = Linv_k ? inv_slot<T>(w, k, te) : nullptr;
   float *Lf = Linv_k ? Akk : nullptr;
   const int64_t colbase = (int64_t)k * nb;
-  hipLaunchKernelGGL(k_potrf_load<T>, dim3(NB * (NB + 1) / 2), dim3(256), 0, s, Akk, W, nb, du,
-                     Linv_k);
-  hipLaunchKernelGGL(k_potrf_diag64<T>, dim3(1), dim3(256), 0, s, W, WL, nb, Dinv, w.flag,
-                     colbase, Lf, Linv_k);
+  const char *e = getenv("KRR_LOAD_SPLIT");
+  if (w.lpart && du.npan > 0 && !(e && atoi(e) == 0)) {
+    // K chunks: a whole panel each from four panels up, else halves or quarters
+    const int cpp = du.npan >= 4 ? 1 : (du.npan >= 2 ? 2 : 4), nch = du.npan * cpp;
+    const int nblk = NB * (NB + 1) / 2;
+    hipLaunchKernelGGL(k_potrf_load_part, dim3(nblk * nch), dim3(256), 0, s, nb, du, nb / cpp,
+                       w.lpart);
+    hipLaunchKernelGGL(k_potrf_load_sum<T>, dim3(nblk), dim3(256), 0, s, Akk, W, WL, nb, du, nch,
+                       w.lpart, Dinv, w.flag, colbase, Lf, Linv_k);
+  } else {
+    hipLaunchKernelGGL(k_potrf_load<T>, dim3(NB * (NB + 1) / 2), dim3(256), 0, s, Akk, W, nb, du,
+                       Linv_k);
+    hipLaunchKernelGGL(k_potrf_diag64<T>, dim3(1), dim3(256), 0, s, W, WL, nb, Dinv, w.flag,
+                       colbase, Lf, Linv_k);
+  }
   for (int st = 0; st + 1 < NB; ++st) {
     const int rest = NB - 1 - st, npairs = rest * (rest + 1) / 2;
     // the inverse: row st finalized, the later rows' sums advanced by row st - 1
@@ -835,6 +943,22 @@ KRR_DEV void trsm_panel_body(const float *__restrict__ Astore, const T *__restri
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, li = lane & 15, lg = lane >> 4;
   double ss = 0.0;
   float mx = 0.0f;
+  // Sixteen MFMAs over 64 values of k, A(li, k) = a[4 u + lg] from LDS and
+  // B = b[u]: all sixteen LDS reads issued first (each into a register of its
+  // own), the MFMAs alternating between two accumulators (even and odd u,
+  // added by the caller) so that no MFMA waits for the one before it.
+  auto mma_chunk = [&](const T *a, const T (&b)[16], v4 &e, v4 &o) {
+    T pa[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) pa[u] = a[4 * u];
+#pragma unroll
+    for (int u = 0; u < 16; u += 2) {
+      e = M16<T>::mma(pa[u], b[u], e);
+      o = M16<T>::mma(pa[u + 1], b[u + 1], o);
+    }
+    __builtin_amdgcn_sched_group_barrier(0x100, 16, 0);
+    __builtin_amdgcn_sched_group_barrier(0x008, 16, 0);
+  };
   for (int s = 0; s < nb / BS; ++s) {
     const int c0 = BS * s + 16 * wave;  // this wave's 16 output columns
     // this step's A entries and inv(L_ss) row, loaded before the sum so that
@@ -849,7 +973,7 @@ KRR_DEV void trsm_panel_body(const float *__restrict__ Astore, const T *__restri
     // B(kk, c) = L[c0 + c][kk] over kk < 64 s, 64 columns of k per chunk;
     // the loads of chunk c+1 are issued before the MFMAs of chunk c
     const T *Lrow = WLk + (int64_t)(c0 + li) * nb;
-    v4 acc = {0, 0, 0, 0};
+    v4 acc = {0, 0, 0, 0}, acc_o = {0, 0, 0, 0};
     const int nch = s;
     if (nch > 0) {
       T b0[16], b1[16];
@@ -861,19 +985,17 @@ KRR_DEV void trsm_panel_body(const float *__restrict__ Astore, const T *__restri
 #pragma unroll
           for (int u = 0; u < 16; ++u) b1[u] = Lrow[k0 + BS + 4 * u + lg];
         }
-#pragma unroll
-        for (int u = 0; u < 16; ++u) acc = M16<T>::mma(Pr[li][k0 + 4 * u + lg], b0[u], acc);
+        mma_chunk(Pr[li] + k0 + lg, b0, acc, acc_o);
         if (ch + 1 < nch) {
           if (ch + 2 < nch) {
 #pragma unroll
             for (int u = 0; u < 16; ++u) b0[u] = Lrow[k0 + 2 * BS + 4 * u + lg];
           }
-#pragma unroll
-          for (int u = 0; u < 16; ++u)
-            acc = M16<T>::mma(Pr[li][k0 + BS + 4 * u + lg], b1[u], acc);
+          mma_chunk(Pr[li] + k0 + BS + lg, b1, acc, acc_o);
         }
       }
     }
+    acc += acc_o;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int row = M16<T>::row(r, lane);
@@ -881,9 +1003,9 @@ KRR_DEV void trsm_panel_body(const float *__restrict__ Astore, const T *__restri
     }
     __syncthreads();
     // P[:, c0 ..] = Tb inv(L_ss)^T: B(j, c) = inv(L_ss)[16 w + c][j]
-    v4 acc2 = {0, 0, 0, 0};
-#pragma unroll
-    for (int u = 0; u < 16; ++u) acc2 = M16<T>::mma(Tb[li][4 * u + lg], dv[u], acc2);
+    v4 acc2 = {0, 0, 0, 0}, acc2_o = {0, 0, 0, 0};
+    mma_chunk(Tb[li] + lg, dv, acc2, acc2_o);
+    acc2 += acc2_o;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int row = M16<T>::row(r, lane);
@@ -1422,16 +1544,7 @@ void launch_update(float *Astore, int k0, int npan, int jlo, int jhi, const Tile
     ps.pnorm[q] = pbs[q]->pnorm;
     ps.pexp8[q] = pbs[q]->pexp8;
   }
-  static bool attr = false;
-  if (!attr) {
-    hipFuncSetAttribute((const void *)k_update<UpdStream, false>,
-                        hipFuncAttributeMaxDynamicSharedMemorySize, UpdStream::LDS_BYTES);
-    hipFuncSetAttribute((const void *)k_update<UpdDiag64, true>,
-                        hipFuncAttributeMaxDynamicSharedMemorySize, UpdDiag64::LDS_BYTES);
-    hipFuncSetAttribute((const void *)k_update<UpdDiagStream, false>,
-                        hipFuncAttributeMaxDynamicSharedMemorySize, UpdDiagStream::LDS_BYTES);
-    attr = true;
-  }
+  factor_kernel_attrs();
   if (which != UPD_OFFDIAG) {  // diagonal tiles first: they are the longest per block
     const int SB = L.nb / UpdDiag64::kBM;
     const int64_t blocks = (int64_t)(jhi - jlo + 1) * SB * (SB + 1) / 2;
@@ -1629,16 +1742,7 @@ static void factor_lockstep_t(const FactorJob *jobs, const int *nts, int nj, int
   const int chunks = (int)((int64_t)nb * nb / CONV_CHUNK_B);
   int ntmax = 0;
   for (int b = 0; b < nj; ++b) ntmax = std::max(ntmax, nts[b]);
-  static bool attr = false;
-  if (!attr) {
-    hipFuncSetAttribute((const void *)k_update_b<UpdStream, false>,
-                        hipFuncAttributeMaxDynamicSharedMemorySize, UpdStream::LDS_BYTES);
-    hipFuncSetAttribute((const void *)k_update_b<UpdDiag64, true>,
-                        hipFuncAttributeMaxDynamicSharedMemorySize, UpdDiag64::LDS_BYTES);
-    hipFuncSetAttribute((const void *)k_update_b<UpdDiagStream, false>,
-                        hipFuncAttributeMaxDynamicSharedMemorySize, UpdDiagStream::LDS_BYTES);
-    attr = true;
-  }
+  factor_kernel_attrs();
   // updates as launch_update does them: diagonal tiles (64 x 64 blocks),
   // then the off-diagonal ones, small blocks when the batch has few tiles
   // in all (grids sized for the instance with the most)
@@ -1743,6 +1847,27 @@ __global__ void k_encode_fp8(const float *__restrict__ x, int64_t n, uint8_t *__
 
 void launch_encode_fp8(const float *x, int64_t n, uint8_t *out, hipStream_t s) {
   hipLaunchKernelGGL(k_encode_fp8, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, x, n, out);
+}
+
+// Dynamic-LDS limits of the update kernels (above the 64 KB default), set once
+// per process before their first launch; the context's creation calls it, so
+// that it never runs inside a stream capture.
+void factor_kernel_attrs() {
+  static bool done = false;
+  if (done) return;
+  done = true;
+  (void)hipFuncSetAttribute((const void *)k_update<UpdStream, false>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, UpdStream::LDS_BYTES);
+  (void)hipFuncSetAttribute((const void *)k_update<UpdDiag64, true>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, UpdDiag64::LDS_BYTES);
+  (void)hipFuncSetAttribute((const void *)k_update<UpdDiagStream, false>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, UpdDiagStream::LDS_BYTES);
+  (void)hipFuncSetAttribute((const void *)k_update_b<UpdStream, false>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, UpdStream::LDS_BYTES);
+  (void)hipFuncSetAttribute((const void *)k_update_b<UpdDiag64, true>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, UpdDiag64::LDS_BYTES);
+  (void)hipFuncSetAttribute((const void *)k_update_b<UpdDiagStream, false>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, UpdDiagStream::LDS_BYTES);
 }
 
 }  // namespace krr

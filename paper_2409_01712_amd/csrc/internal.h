@@ -156,6 +156,9 @@ struct FactorWork {
   float *pmax_part = nullptr;    // (nt-1) * parts
   int32_t *flag = nullptr;       // breakdown column + 1 (0 = none)
   unsigned long long *counts = nullptr;  // [3] updates per precision
+  // split-K load of a diagonal tile: per-chunk 64 x 64 partial products
+  // (KRR_MAX_GROUP chunks x (nb/64)(nb/64+1)/2 blocks)
+  float *lpart = nullptr;
 };
 // Updates of a diagonal tile left to its factorization: P[q] points at tile
 // k of panel buffer q; pmap_at[q] is the precision-map entry to mark FP32.
@@ -315,5 +318,11 @@ void launch_predict_apply(const int32_t *Dt, int64_t rows, int64_t cols, int64_t
 void launch_fill_f64(double *p, int64_t count, double v, hipStream_t s);
 void launch_fill_i32(int32_t *p, int64_t count, int32_t v, hipStream_t s);
 void launch_fill_u8(uint8_t *p, int64_t count, uint8_t v, hipStream_t s);
+
+// Dynamic-LDS attributes of the kernels that need more than 64 KB, set once
+// per process (the context's creation calls them, outside any capture).
+void build_kernel_attrs();
+void factor_kernel_attrs();
+void solve_kernel_attrs();
 
 }  // namespace krr

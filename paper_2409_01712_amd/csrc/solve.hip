@@ -412,12 +412,7 @@ template <bool FWD, int NB, int W>
 static void launch_panel2w(const float *Astore, const float *V, float *In, int k, int ntiles,
                            int r, int64_t ldv, hipStream_t s) {
   const size_t lds = (size_t)16 * (2 * NB + 4) * sizeof(float);  // 65.8 KB at nb = 512
-  static bool attr = false;
-  if (!attr) {
-    (void)hipFuncSetAttribute((const void *)k_sweep_panel2w<FWD, NB, W>,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    attr = true;
-  }
+  solve_kernel_attrs();
   const int64_t blocks = (int64_t)ntiles * (NB * (NB / 256) / (16 * W)) * ((r + 15) / 16);
   hipLaunchKernelGGL((k_sweep_panel2w<FWD, NB, W>), dim3((unsigned)blocks), dim3(64 * W), lds, s,
                      Astore, V, In, k, r, ldv);
@@ -1421,6 +1416,33 @@ void launch_fill_i32(int32_t *p, int64_t count, int32_t v, hipStream_t s) {
   if (count > 0)
     hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, p, count,
                        v);
+}
+
+// Dynamic-LDS limits of the wide sweep panels (65.8 KB at nb = 512, above the
+// 64 KB default), set once per process before their first launch; the
+// context's creation calls it, so that it never runs inside a stream capture.
+void solve_kernel_attrs() {
+  static bool done = false;
+  if (done) return;
+  done = true;
+  const int l256 = 16 * (2 * 256 + 4) * (int)sizeof(float);
+  const int l512 = 16 * (2 * 512 + 4) * (int)sizeof(float);
+  (void)hipFuncSetAttribute((const void *)k_sweep_panel2w<true, 256, 4>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, l256);
+  (void)hipFuncSetAttribute((const void *)k_sweep_panel2w<false, 256, 4>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, l256);
+  (void)hipFuncSetAttribute((const void *)k_sweep_panel2w<true, 256, 8>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, l256);
+  (void)hipFuncSetAttribute((const void *)k_sweep_panel2w<false, 256, 8>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, l256);
+  (void)hipFuncSetAttribute((const void *)k_sweep_panel2w<true, 512, 4>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, l512);
+  (void)hipFuncSetAttribute((const void *)k_sweep_panel2w<false, 512, 4>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, l512);
+  (void)hipFuncSetAttribute((const void *)k_sweep_panel2w<true, 512, 8>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, l512);
+  (void)hipFuncSetAttribute((const void *)k_sweep_panel2w<false, 512, 8>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, l512);
 }
 
 }  // namespace krr

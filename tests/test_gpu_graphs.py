@@ -66,3 +66,53 @@ def test_batched_graph_replays_match_direct_launches(monkeypatch):
         Wo = oracle.fit(Gs[b], Ys[b], gammas[b], lams[b])
         assert np.max(np.abs(X[b].cpu().numpy() - Wo)) <= 1e-5 * np.max(np.abs(Wo))
     ctx.close()
+
+
+@pytest.mark.skip(reason="the single-instance factorization's HIP graph is switched off "
+                  "(KRR_FACTOR_GRAPH=1 returns KRR_ERROR_NOT_SUPPORTED): its first GPU runs "
+                  "ended with a host segmentation fault inside krr_factor during the first "
+                  "capture, also after moving the kernel attributes and event creation out of "
+                  "the capture, and the cause is not known")
+@pytest.mark.parametrize("n,tile", [(2600, 256), (3000, 512)])
+def test_factor_graph_replays_match_direct_launches(monkeypatch, n, tile):
+    """The single-instance factorization's three-stream schedule runs as a HIP
+    graph (captured on the first call with a key of every address and value its
+    launches take, replayed after).  Every replay -- with other work of the
+    program and synchronizations between replays -- gives the bits of direct
+    launches: the factor's solve, the update counts and the precision map."""
+    m, r = 700, 4
+    G = synth.genotypes(n, m, synth.maf_uniform(m, 0.05, 0.5, 5), 5)
+    Y = synth.phenotypes(G, r, n_pairs=5, n_add=5, seed=6, h2=0.5)
+    gamma, lam = 1.0 / m, 0.1
+    ctx = krr.krr_create(0, tile=tile)
+    none = krr.Refine(method=krr.KRR_REFINE_NONE)
+
+    def run():
+        K = krr.krr_build_kernel(ctx, _dev(G), gamma, lam)
+        F = krr.krr_factor(ctx, K)
+        X, _, _ = krr.krr_solve(ctx, F, _dev(Y), none)
+        info = krr.krr_factor_get_info(F)
+        out = (X.clone(), tuple(info.updates), krr.krr_factor_precision_map(F))
+        F.release()
+        K.release()
+        return out
+
+    monkeypatch.setenv("KRR_NO_GRAPH", "1")
+    X0, u0, m0 = run()
+    assert krr.krr_context_graphs(ctx) == (0, 0)
+    monkeypatch.delenv("KRR_NO_GRAPH")
+    for rep in range(4):
+        X, u, pm = run()
+        assert torch.equal(X, X0), rep
+        assert u == u0 and np.array_equal(pm, m0), rep
+        # other work of the program between replays, then a synchronization
+        Kb = krr.krr_build_kernel(ctx, _dev(G[: n // 2]), gamma, lam)
+        Fb = krr.krr_factor(ctx, Kb, krr.plain_fp32_policy())
+        krr.krr_solve(ctx, Fb, _dev(Y[: n // 2]), none)
+        Fb.release()
+        Kb.release()
+        torch.cuda.synchronize()
+    cached, launches = krr.krr_context_graphs(ctx)
+    # eight graphed factorizations, most of them replays of a cached graph
+    assert launches >= 8 and cached < launches
+    ctx.close()
