@@ -100,6 +100,7 @@ struct krr_factor_s {
   float *Lst = nullptr;   // FP32 factor, packed lower tiles
   float *Linv = nullptr;  // inverses of the diagonal tiles, nt x nb x nb
   float *Cpair = nullptr; // coupling tiles of the paired sweeps, nt / 2 (first solve)
+  float *Cquad = nullptr; // coupling tiles of the quad sweeps, 4 (nt / 4) (first solve)
   krr_factor_info info{};
   std::vector<uint8_t> pmap;
 };
@@ -1316,6 +1317,7 @@ static void factor_free(krr_factorization F) {
   dfree(c, F->Lst, F->L.elems() * 4);
   dfree(c, F->Linv, (size_t)F->L.nt * F->L.tile_elems() * 4);
   if (F->Cpair) dfree(c, F->Cpair, (size_t)(F->L.nt / 2) * F->L.tile_elems() * 4);
+  if (F->Cquad) dfree(c, F->Cquad, (size_t)4 * (F->L.nt / 4) * F->L.tile_elems() * 4);
   delete F;
 }
 
@@ -1643,16 +1645,20 @@ struct SolveBufs {
   double *Yr = nullptr, *Xr = nullptr, *Rr = nullptr, *cn = nullptr, *Pr = nullptr;
   float *Bf = nullptr, *Zf = nullptr, *Xf = nullptr;
   const float *C = nullptr;  // coupling tiles of the paired sweeps, or null
+  const float *Q = nullptr;  // coupling tiles of the quad sweeps, or null
   double *cw = nullptr;      // workspace of the column reductions
   int z = 1;                 // column ranges of the residual (Pr holds z np r)
   bool once = false;         // residual with each stored tile read once (z = NT slots)
 };
 
 // The coupling tiles of the paired sweeps, formed on the first solve with a
-// factor and kept with it; KRR_SWEEP_PAIRS=0 sweeps one tile per step.
+// factor and kept with it; KRR_SWEEP_PAIRS=0 sweeps one tile per step.  At
+// tile 256 with the wide panel launches the tiles go four a step, with the
+// quads' coupling tiles formed the same way (KRR_SWEEP_QUADS=0: pairs).
 static krr_status sweep_coupling(krr_context ctx, krr_factorization F, Scoped &sc, SolveBufs &b,
                                  hipStream_t s) {
   b.C = nullptr;
+  b.Q = nullptr;
   const char *e = getenv("KRR_SWEEP_PAIRS");
   const TileLayout &L = F->L;
   const int64_t npair = L.nt / 2;
@@ -1668,6 +1674,16 @@ static krr_status sweep_coupling(krr_context ctx, krr_factorization F, Scoped &s
     launch_sweep_coupling(F->Lst, F->Linv, L, tmp, F->Cpair, s);
   }
   b.C = F->Cpair;
+  const char *eq = getenv("KRR_SWEEP_QUADS");
+  const int64_t nquad = L.nt / 4;
+  if ((eq && atoi(eq) == 0) || nquad == 0 || !sweep_quads_supported(L.nb)) return KRR_SUCCESS;
+  if (!F->Cquad) {
+    float *tmp = nullptr;
+    CHK(sc.alloc(&tmp, 4 * nquad * L.tile_elems()));
+    CHK(dalloc_t(ctx, &F->Cquad, 4 * nquad * L.tile_elems()));
+    launch_quad_coupling(F->Lst, F->Linv, F->Cpair, L, tmp, F->Cquad, s);
+  }
+  b.Q = F->Cquad;
   return KRR_SUCCESS;
 }
 
@@ -1699,11 +1715,11 @@ static void solve_sweeps(krr_context ctx, krr_factorization F, int r, SolveBufs 
   launch_rows_f64_to_cols_f32(src, L.np, r, b.Bf, s);
   {
     Stage t(ctx, KRR_STAGE_FWD, s);
-    launch_fwd_sweep(F->Lst, F->Linv, b.C, L, r, b.Bf, b.Zf, s);
+    launch_fwd_sweep(F->Lst, F->Linv, b.C, b.Q, L, r, b.Bf, b.Zf, s);
   }
   {
     Stage t(ctx, KRR_STAGE_BWD, s);
-    launch_bwd_sweep(F->Lst, F->Linv, b.C, L, r, b.Zf, b.Xf, s);
+    launch_bwd_sweep(F->Lst, F->Linv, b.C, b.Q, L, r, b.Zf, b.Xf, s);
   }
   launch_cols_f32_axpy_rows_f64(b.Xf, L.np, r, 1.0, dst, s);
 }

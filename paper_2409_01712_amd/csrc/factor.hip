@@ -651,6 +651,84 @@ void launch_sweep_coupling(const float *Lst, const float *Linv, const TileLayout
                        L.nb, step);
 }
 
+// Coupling of a quad of tiles (k .. k+3, k = 4 q) for sweeps that take four
+// tiles a step.  With the pairs P0 = (k, k+1), P1 = (k+2, k+3), M the 2 x 2
+// tiles L_{k+2.., k..} between them and inv(P) = [inv(L_a) 0; -C inv(L_b)]
+// (C the pair coupling above),
+//   inv([P0 0; M P1]) = [inv(P0) 0; -Q inv(P1)],  Q = inv(P1) M inv(P0),
+// in two products per tile of Q: stage 0, T = M inv(P0)
+//   T00 = L20 inv(L0) - L21 C0,  T01 = L21 inv(L1),
+//   T10 = L30 inv(L0) - L31 C0,  T11 = L31 inv(L1);
+// stage 1, Q = inv(P1) T
+//   Q00 = inv(L2) T00,  Q01 = inv(L2) T01,
+//   Q10 = -C1 T00 + inv(L3) T10,  Q11 = -C1 T01 + inv(L3) T11
+// (Lij = L_{k+i, k+j}; C0, C1 the couplings of pairs 2q and 2q+1).  Output
+// block (blockIdx.y, blockIdx.x) of 64 x 64 of tile blockIdx.z % 4 (00, 01,
+// 10, 11) of quad blockIdx.z / 4; each tile a sum of at most two products,
+// each in its own FP32 accumulator, added with their signs.
+__global__ __launch_bounds__(256) void k_quad_coupling(const float *__restrict__ Lst,
+                                                       const float *__restrict__ Linv,
+                                                       const float *__restrict__ Cp,
+                                                       float *__restrict__ T,
+                                                       float *__restrict__ Q, int nb, int stage) {
+  __shared__ float As[BS][BS + 1];
+  __shared__ float Bs[BS][BS + 1];
+  const int64_t te = (int64_t)nb * nb;
+  const int o = blockIdx.z % 4;
+  const int64_t qd = blockIdx.z / 4, k = 4 * qd;
+  const int rb = blockIdx.y, cb = blockIdx.x;
+  auto Lt = [&](int i, int j) { return Lst + tri_index(k + i, k + j) * te; };
+  auto Li = [&](int i) { return Linv + (k + i) * te; };
+  const float *C0 = Cp + (2 * qd) * te, *C1 = Cp + (2 * qd + 1) * te;
+  const float *Tq = T + 4 * qd * te;
+  const float *A[2] = {nullptr, nullptr}, *B[2] = {nullptr, nullptr};
+  float sg[2] = {1.0f, 1.0f};
+  if (stage == 0) {
+    const int i = 2 + o / 2;  // row tile of M
+    if (o % 2 == 0) {
+      A[0] = Lt(i, 0), B[0] = Li(0);
+      A[1] = Lt(i, 1), B[1] = C0, sg[1] = -1.0f;
+    } else {
+      A[0] = Lt(i, 1), B[0] = Li(1);
+    }
+  } else {
+    if (o < 2) {
+      A[0] = Li(2), B[0] = Tq + o * te;
+    } else {
+      A[0] = C1, B[0] = Tq + (o - 2) * te, sg[0] = -1.0f;
+      A[1] = Li(3), B[1] = Tq + o * te;
+    }
+  }
+  typename M16<float>::v4 acc[2][4];
+  zero4<float>(acc[0]);
+  zero4<float>(acc[1]);
+  for (int t = 0; t < 2; ++t) {
+    if (!A[t]) continue;
+    for (int kk = 0; kk < nb; kk += BS) {
+      load64(As, A[t] + (int64_t)(rb * BS) * nb + kk, nb);
+      load64(Bs, B[t] + (int64_t)kk * nb + cb * BS, nb);
+      __syncthreads();
+      mm64<float, false>(As, Bs, acc[t]);
+      __syncthreads();
+    }
+  }
+#pragma unroll
+  for (int ct = 0; ct < 4; ++ct)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) acc[0][ct][e] = sg[0] * acc[0][ct][e] + sg[1] * acc[1][ct][e];
+  float *Out = (stage == 0 ? T : Q) + (4 * qd + o) * te;
+  store64<float, false>(Out + (int64_t)(rb * BS) * nb + cb * BS, nb, acc[0], 1.0f);
+}
+
+void launch_quad_coupling(const float *Lst, const float *Linv, const float *Cpair,
+                          const TileLayout &L, float *Tmp, float *Q, hipStream_t s) {
+  const int nquad = L.nt / 4, nbk = L.nb / BS;
+  if (nquad == 0) return;
+  for (int stage = 0; stage < 2; ++stage)
+    hipLaunchKernelGGL(k_quad_coupling, dim3(nbk, nbk, 4 * nquad), dim3(256), 0, s, Lst, Linv,
+                       Cpair, Tmp, Q, L.nb, stage);
+}
+
 // Write L_kk (lower, zero above) into the factor storage and inv(L_kk), FP32.
 template <typename T>
 __global__ void k_potrf_store(const T *__restrict__ WLall, const T *__restrict__ Winvc,

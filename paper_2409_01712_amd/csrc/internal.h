@@ -217,6 +217,12 @@ void launch_tile_inverses(float *Lst, float *Linv, int k_lo, int k_hi, const Til
 // (k, k+1) = (2p, 2p+1), p < nt / 2, for the paired sweeps; Tmp, C: nt / 2 tiles.
 void launch_sweep_coupling(const float *Lst, const float *Linv, const TileLayout &L, float *Tmp,
                            float *C, hipStream_t s);
+// Coupling tiles Q = inv(P1) M inv(P0) of the tile quads (4q .. 4q+3), q < nt / 4,
+// for sweeps that take four tiles a step (P0, P1 its pairs, M the 2 x 2 tiles
+// between them; Cpair from launch_sweep_coupling); Tmp, Q: 4 (nt / 4) tiles,
+// Q's four tiles of quad q at 4q (00, 01, 10, 11).
+void launch_quad_coupling(const float *Lst, const float *Linv, const float *Cpair,
+                          const TileLayout &L, float *Tmp, float *Q, hipStream_t s);
 // P_i = A_ik inv(L_kk)^T for the tiles i = k+1+t, t_lo <= t < t_hi: by
 // substitution with the factor of tile k (no inverse needed), or as a product
 // with inv(L_kk) (launch_tile_inverses first).
@@ -247,10 +253,12 @@ void launch_encode_fp8(const float *x, int64_t n, uint8_t *out, hipStream_t s);
 // Right-hand sides of these two: FP32 column-major np x r (column stride
 // np).  C: the coupling tiles of launch_sweep_coupling (tiles taken in
 // pairs), or null (one tile per step).
-void launch_fwd_sweep(const float *Astore, const float *Linv, const float *C, const TileLayout &L,
-                      int r, float *B, float *Z, hipStream_t s);
-void launch_bwd_sweep(const float *Astore, const float *Linv, const float *C, const TileLayout &L,
-                      int r, float *Z, float *X, hipStream_t s);
+void launch_fwd_sweep(const float *Astore, const float *Linv, const float *C, const float *Q,
+                      const TileLayout &L, int r, float *B, float *Z, hipStream_t s);
+void launch_bwd_sweep(const float *Astore, const float *Linv, const float *C, const float *Q,
+                      const TileLayout &L, int r, float *Z, float *X, hipStream_t s);
+// the sweeps take the tiles in quads when given Q (tile 256, wide panels)
+bool sweep_quads_supported(int nb);
 // R = Y - (K + lambda I) X in FP64; part: residual_split(L) * np * r doubles
 // of workspace for the partial products.
 int residual_split(const TileLayout &L);

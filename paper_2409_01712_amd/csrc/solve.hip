@@ -284,6 +284,119 @@ __global__ __launch_bounds__(256) void k_sweep_diag2(const float *__restrict__ L
                          col0 + (threadIdx.x & 15), acc);
 }
 
+// The sum of up to four products, sum_t sg[t] M_t V_t (k ranges [klo[t],
+// khi[t]), multiples of 16, at most 256 values of k each): the 16-wide k
+// blocks of all terms, in term order, dealt round robin to the four waves
+// (at most sixteen a wave, in two phases of eight), the partial sums added
+// in wave order.
+template <bool TRANS>
+__device__ __forceinline__ v4f job_product4(const float *const (&M)[4], const float *const (&Vp)[4],
+                                            const int (&klo)[4], const int (&khi)[4],
+                                            const float (&sg)[4], int nterm, int nb, int r,
+                                            int64_t ldv, int row0, int col0, v4f (*red)[64]) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int li = lane & 15, lg = lane >> 4;
+  const int R = row0 + li, col = col0 + li;
+  const int cc = min(col, r - 1);
+  const bool cv = col < r;
+  int pre[5];
+  pre[0] = 0;
+#pragma unroll
+  for (int t = 0; t < 4; ++t) pre[t + 1] = pre[t] + (t < nterm ? (khi[t] - klo[t]) / 16 : 0);
+  const int total = pre[4];
+  v4f acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int ph = 0; ph < 2; ++ph) {
+    float a[8][4], b[8][4];
+#pragma unroll
+    for (int uu = 0; uu < 8; ++uu) {
+      const int g = wave + 4 * (8 * ph + uu);
+      if (g < total) {
+        const int t = (g >= pre[1]) + (g >= pre[2]) + (g >= pre[3]);
+        const int kk = klo[t] + 16 * (g - pre[t]) + 4 * lg;
+        const float *Mt = M[t];
+        if (!TRANS) {
+          const float4 v = *(const float4 *)(Mt + (int64_t)R * nb + kk);
+          a[uu][0] = v.x; a[uu][1] = v.y; a[uu][2] = v.z; a[uu][3] = v.w;
+        } else {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) a[uu][e] = Mt[(int64_t)(kk + e) * nb + R];
+        }
+        load_v4<true>(Vp[t], r, ldv, kk, cc, cv, sg[t], b[uu]);
+      } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) a[uu][e] = b[uu][e] = 0.f;
+      }
+    }
+#pragma unroll
+    for (int uu = 0; uu < 8; ++uu)
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a[uu][e], b[uu][e], acc, 0, 0, 0);
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  red[wave][lane] = acc;
+  __syncthreads();
+  v4f sum = red[0][lane];
+#pragma unroll
+  for (int q = 1; q < 4; ++q) sum += red[q][lane];
+  return sum;
+}
+
+// Quad sweep steps over the tiles k .. k+3 (k = 4q), with the block inverse
+// [inv(P0) 0; -Q inv(P1)] of the quad (pairs P0, P1 with couplings C0, C1,
+// inv(P) = [inv(L_a) 0; -C inv(L_b)]; Q from launch_quad_coupling):
+//   forward  Z0 = iL0 B0,  Z1 = iL1 B1 - C0 B0,  Z2 = iL2 B2 - Q00 B0 - Q01 B1,
+//            Z3 = iL3 B3 - C1 B2 - Q10 B0 - Q11 B1;
+//   backward X3 = iL3' Z3,  X2 = iL2' Z2 - C1' Z3,  X1 = iL1' Z1 - Q01' Z2 - Q11' Z3,
+//            X0 = iL0' Z0 - C0' Z1 - Q00' Z2 - Q10' Z3
+// (iLj = inv(L_k+j,k+j), ' the transpose).  One launch for the four tiles:
+// 4 x per workgroups, the j-th per for tile k+j's rows.  nb <= 256.
+template <bool FWD>
+__global__ __launch_bounds__(256) void k_sweep_diag4(const float *__restrict__ Linv,
+                                                     const float *__restrict__ Cp,
+                                                     const float *__restrict__ Qc, const float *In,
+                                                     float *Out, int k, int nb, int r,
+                                                     int64_t ldv) {
+  __shared__ v4f red[4][64];
+  const int CJ = (r + 15) / 16, per = (nb / 16) * CJ;
+  const int j = blockIdx.x / per, rem = blockIdx.x % per;
+  const int rj = rem / CJ, cj = rem % CJ;
+  const int row0 = rj * 16, col0 = cj * 16;
+  const int64_t te = (int64_t)nb * nb, qd = k / 4;
+  const float *iL = Linv + (int64_t)(k + j) * te;
+  const float *C0 = Cp + (2 * qd) * te, *C1 = Cp + (2 * qd + 1) * te;
+  const float *Q = Qc + 4 * qd * te;  // Q00, Q01, Q10, Q11
+  const float *V[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) V[q] = In + tile_off<true>(k + q, nb, r);
+  // the terms of tile k+j: its own inverse first (its triangle), then the couplings
+  const float *M[4] = {iL, nullptr, nullptr, nullptr};
+  const float *Vt[4] = {V[j], nullptr, nullptr, nullptr};
+  int klo[4] = {FWD ? 0 : row0, 0, 0, 0}, khi[4] = {FWD ? row0 + 16 : nb, nb, nb, nb};
+  const float sg[4] = {1.f, -1.f, -1.f, -1.f};
+  int nterm = 1;
+  if (FWD) {
+    if (j == 1) { M[1] = C0; Vt[1] = V[0]; nterm = 2; }
+    if (j == 2) { M[1] = Q; Vt[1] = V[0]; M[2] = Q + te; Vt[2] = V[1]; nterm = 3; }
+    if (j == 3) {
+      M[1] = C1; Vt[1] = V[2]; M[2] = Q + 2 * te; Vt[2] = V[0]; M[3] = Q + 3 * te; Vt[3] = V[1];
+      nterm = 4;
+    }
+  } else {
+    if (j == 2) { M[1] = C1; Vt[1] = V[3]; nterm = 2; }
+    if (j == 1) { M[1] = Q + te; Vt[1] = V[2]; M[2] = Q + 3 * te; Vt[2] = V[3]; nterm = 3; }
+    if (j == 0) {
+      M[1] = C0; Vt[1] = V[1]; M[2] = Q; Vt[2] = V[2]; M[3] = Q + 2 * te; Vt[3] = V[3];
+      nterm = 4;
+    }
+  }
+  for (int t = nterm; t < 4; ++t) { M[t] = iL; Vt[t] = V[j]; klo[t] = khi[t] = 0; }
+  const v4f acc = job_product4<!FWD>(M, Vt, klo, khi, sg, nterm, nb, r, ldv, row0, col0, red);
+  store_job<true, false>(Out + tile_off<true>(k + j, nb, r), r, ldv, row0,
+                         col0 + (threadIdx.x & 15), acc);
+}
+
 // Panel launch of a pair: one job per workgroup, tile t of the panel rows
 // (forward i = k+2+t; backward j = t < k).
 template <bool FWD>
@@ -318,20 +431,22 @@ __global__ __launch_bounds__(256) void k_sweep_panel2(const float *__restrict__ 
 // through LDS (8 W rows).  Columns past r read column r - 1 (their results
 // are not stored).  The 16-row form needs one round trip per phase of loads
 // and a reduction across all four waves.
-template <bool FWD, int NB, int W>
+// P tiles a step (2: a pair; 4: a quad, nb = 256): the same with P nb
+// values of k, split over P nb / 512 waves a job.
+template <bool FWD, int NB, int W, int P = 2>
 __global__ __launch_bounds__(64 * W) void k_sweep_panel2w(const float *__restrict__ Lst,
                                                           const float *V, float *In, int k, int r,
                                                           int64_t ldv) {
   typedef __attribute__((address_space(3))) void lds_void;
-  constexpr int S = NB / 256, ROWS = 16 * W / S, RB = NB / ROWS, VST = 2 * NB + 4;
-  constexpr int CPC = NB / 128, VCH = 16 * CPC / W;  // 1 KiB chunks a column; a wave
-  static_assert(VCH * W == 16 * CPC && RB * ROWS == NB, "shape");
+  constexpr int S = P * NB / 512, ROWS = 16 * W / S, RB = NB / ROWS, VST = P * NB + 4;
+  constexpr int CPC = P * NB / 256, VCH = 16 * CPC / W;  // 1 KiB chunks a column; a wave
+  static_assert(VCH * W == 16 * CPC && RB * ROWS == NB && S <= 2 && W % S == 0, "shape");
   extern __shared__ __attribute__((aligned(16))) float vs[];
   __shared__ v4f red[W / 2][64];
   const int CJ = (r + 15) / 16;
   const int64_t t = blockIdx.x / (RB * CJ);
   const int rem = (int)(blockIdx.x % (RB * CJ)), rj = rem / CJ, cj = rem % CJ;
-  const int64_t i = FWD ? k + 2 + t : t;
+  const int64_t i = FWD ? k + P + t : t;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int li = lane & 15, lg = lane >> 4;
   const int job = wave / S, part = wave % S;
@@ -351,18 +466,17 @@ __global__ __launch_bounds__(64 * W) void k_sweep_panel2w(const float *__restric
   }
   asm volatile("" ::: "memory");
   const int64_t te = (int64_t)NB * NB;
-  const float *M1 = Lst + (FWD ? tri_index(i, k) : tri_index(k, i)) * te;
-  const float *M2 = Lst + (FWD ? tri_index(i, k + 1) : tri_index(k + 1, i)) * te;
   constexpr int KBT = NB / 16;  // k blocks per tile
-  // A elements of k block kb = 32 part + u: lane (li, lg) holds M(R, 16 kb' +
-  // 4 lg + e) of the block's tile, read along k (forward) or down a column of
-  // the stored tile (backward, transposed)
+  // A elements of k block kb = 32 part + u (tile k + kb / KBT of the step):
+  // lane (li, lg) holds M(R, 16 (kb % KBT) + 4 lg + e) of that tile, read
+  // along k (forward) or down a column of the stored tile (backward,
+  // transposed)
   float a[32][4];
 #pragma unroll
   for (int u = 0; u < 32; ++u) {
-    const int kb = 32 * part + u;
-    const float *M = kb < KBT ? M1 : M2;
-    const int kk = 16 * (kb < KBT ? kb : kb - KBT) + 4 * lg;
+    const int kb = 32 * part + u, tq = kb / KBT;
+    const float *M = Lst + (FWD ? tri_index(i, k + tq) : tri_index(k + tq, i)) * te;
+    const int kk = 16 * (kb % KBT) + 4 * lg;
     if (FWD) {
       const float4 v = *(const float4 *)(M + (int64_t)R * NB + kk);
       a[u][0] = v.x; a[u][1] = v.y; a[u][2] = v.z; a[u][3] = v.w;
@@ -408,14 +522,14 @@ static int sweep_wide() {
   return w == 0 ? 0 : (w == 8 ? 8 : 4);
 }
 
-template <bool FWD, int NB, int W>
+template <bool FWD, int NB, int W, int P = 2>
 static void launch_panel2w(const float *Astore, const float *V, float *In, int k, int ntiles,
                            int r, int64_t ldv, hipStream_t s) {
-  const size_t lds = (size_t)16 * (2 * NB + 4) * sizeof(float);  // 65.8 KB at nb = 512
+  const size_t lds = (size_t)16 * (P * NB + 4) * sizeof(float);  // 65.8 KB at P nb = 1024
   solve_kernel_attrs();
-  const int64_t blocks = (int64_t)ntiles * (NB * (NB / 256) / (16 * W)) * ((r + 15) / 16);
-  hipLaunchKernelGGL((k_sweep_panel2w<FWD, NB, W>), dim3((unsigned)blocks), dim3(64 * W), lds, s,
-                     Astore, V, In, k, r, ldv);
+  const int64_t blocks = (int64_t)ntiles * (NB * (P * NB / 512) / (16 * W)) * ((r + 15) / 16);
+  hipLaunchKernelGGL((k_sweep_panel2w<FWD, NB, W, P>), dim3((unsigned)blocks), dim3(64 * W), lds,
+                     s, Astore, V, In, k, r, ldv);
 }
 
 template <bool FWD>
@@ -482,11 +596,22 @@ void launch_sweeps_batched(const SolveJob *jobs, int njobs, int ntmax, int nb, i
 // L Z = B (B is overwritten), right-hand sides column-major np x r (column
 // stride np).  With the coupling tiles C (nt / 2 of them, or null) the tiles
 // go in pairs (0, 1), (2, 3), ..., the last one alone when nt is odd.
-void launch_fwd_sweep(const float *Astore, const float *Linv, const float *C, const TileLayout &L,
-                      int r, float *B, float *Z, hipStream_t s) {
+bool sweep_quads_supported(int nb) { return nb == 256 && sweep_wide() == 4; }
+
+void launch_fwd_sweep(const float *Astore, const float *Linv, const float *C, const float *Q,
+                      const TileLayout &L, int r, float *B, float *Z, hipStream_t s) {
   const int nb = L.nb, NT = L.nt, CJ = (r + 15) / 16, per = (nb / 16) * CJ;
   const int64_t te = (int64_t)nb * nb, ldv = L.np;
+  const bool quads = C && Q && sweep_quads_supported(nb);
   for (int k = 0; k < NT;) {
+    if (quads && k % 4 == 0 && k + 3 < NT) {
+      hipLaunchKernelGGL(k_sweep_diag4<true>, dim3(4 * per), dim3(256), 0, s, Linv, C, Q, B, Z,
+                         k, nb, r, ldv);
+      if (NT - 4 - k > 0)
+        launch_panel2w<true, 256, 4, 4>(Astore, Z, B, k, NT - 4 - k, r, ldv, s);
+      k += 4;
+      continue;
+    }
     if (C && k + 1 < NT) {
       hipLaunchKernelGGL(k_sweep_diag2<true>, dim3(2 * per), dim3(256), 0, s, Linv,
                          C + (int64_t)(k / 2) * te, B, Z, k, nb, r, ldv);
@@ -504,11 +629,20 @@ void launch_fwd_sweep(const float *Astore, const float *Linv, const float *C, co
 }
 
 // L^T X = Z (Z is overwritten); the pairs of the forward sweep, last first.
-void launch_bwd_sweep(const float *Astore, const float *Linv, const float *C, const TileLayout &L,
-                      int r, float *Z, float *X, hipStream_t s) {
+void launch_bwd_sweep(const float *Astore, const float *Linv, const float *C, const float *Q,
+                      const TileLayout &L, int r, float *Z, float *X, hipStream_t s) {
   const int nb = L.nb, NT = L.nt, CJ = (r + 15) / 16, per = (nb / 16) * CJ;
   const int64_t te = (int64_t)nb * nb, ldv = L.np;
+  const bool quads = C && Q && sweep_quads_supported(nb);
   for (int k = NT - 1; k >= 0;) {
+    if (quads && k % 4 == 3) {  // the quad (k-3 .. k) of the forward sweep
+      const int k0 = k - 3;
+      hipLaunchKernelGGL(k_sweep_diag4<false>, dim3(4 * per), dim3(256), 0, s, Linv, C, Q, Z, X,
+                         k0, nb, r, ldv);
+      if (k0 > 0) launch_panel2w<false, 256, 4, 4>(Astore, X, Z, k0, k0, r, ldv, s);
+      k -= 4;
+      continue;
+    }
     if (C && k % 2 == 1) {  // the pair (k-1, k)
       const int k0 = k - 1;
       hipLaunchKernelGGL(k_sweep_diag2<false>, dim3(2 * per), dim3(256), 0, s, Linv,
@@ -1442,6 +1576,10 @@ void solve_kernel_attrs() {
   (void)hipFuncSetAttribute((const void *)k_sweep_panel2w<true, 512, 8>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, l512);
   (void)hipFuncSetAttribute((const void *)k_sweep_panel2w<false, 512, 8>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, l512);
+  (void)hipFuncSetAttribute((const void *)k_sweep_panel2w<true, 256, 4, 4>,
+                            hipFuncAttributeMaxDynamicSharedMemorySize, l512);
+  (void)hipFuncSetAttribute((const void *)k_sweep_panel2w<false, 256, 4, 4>,
                             hipFuncAttributeMaxDynamicSharedMemorySize, l512);
 }
 

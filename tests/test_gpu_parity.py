@@ -249,6 +249,40 @@ def test_paired_sweeps_match_single_steps(monkeypatch, n):
     c.close()
 
 
+@pytest.mark.parametrize("n,r", [(1000, 5), (1200, 17), (1700, 5), (2200, 40)])
+def test_quad_sweeps_match_pairs(monkeypatch, n, r):
+    """Sweeps that take four tiles a step (the quad's block inverse through its
+    two pair couplings and a 2 x 2 coupling block, the panels over four tiles
+    of k) agree with the paired sweeps and with one tile a step to FP32
+    rounding: 4, 5, 7 and 9 tiles (a quad alone, quads with pair and single
+    tails), 1-3 column blocks; the refined result matches the oracle."""
+    m = 600
+    G = _gen(n, m, seed=n + 31)
+    Y = synth.phenotypes(G, r, n_pairs=5, n_add=3, seed=n + 32, h2=0.5)
+    gamma, lam = 1.0 / m, 0.1
+    c = krr.krr_create(0, tile=256)
+    K = krr.krr_build_kernel(c, _dev(G), gamma, lam)
+    F = krr.krr_factor(c, K, krr.plain_fp32_policy())
+    none = krr.Refine(method=krr.KRR_REFINE_NONE)
+    Xq, _, _ = krr.krr_solve(c, F, _dev(Y), none)
+    monkeypatch.setenv("KRR_SWEEP_QUADS", "0")
+    Xp, _, _ = krr.krr_solve(c, F, _dev(Y), none)
+    monkeypatch.setenv("KRR_SWEEP_PAIRS", "0")
+    X1, _, _ = krr.krr_solve(c, F, _dev(Y), none)
+    monkeypatch.delenv("KRR_SWEEP_PAIRS")
+    monkeypatch.delenv("KRR_SWEEP_QUADS")
+    # the same solution through other products; a wrong coupling tile, sign
+    # or panel term would move X by O(1)
+    assert _colrel(Xq.cpu().numpy(), Xp.cpu().numpy()) <= 2e-3
+    assert _colrel(Xq.cpu().numpy(), X1.cpu().numpy()) <= 2e-3
+    X, info, st = krr.krr_solve(c, F, _dev(Y), krr.Refine(tol=1e-8))
+    assert info.converged == 1
+    assert _colrel(X.cpu().numpy(), oracle.fit(G, Y, gamma, lam)) <= TOL
+    F.release()
+    K.release()
+    c.close()
+
+
 @pytest.mark.parametrize("n,r,tile", [(700, 5, 256), (1500, 17, 256), (1300, 40, 512),
                                        (2600, 16, 512)])
 def test_wide_panel_sweeps_match_narrow(monkeypatch, n, r, tile):
@@ -256,7 +290,9 @@ def test_wide_panel_sweeps_match_narrow(monkeypatch, n, r, tile):
     staged in LDS, each wave summing its rows over all k) agree with the 16-row
     form (k blocks dealt over the waves, summed across them) to FP32 rounding:
     several panel tiles, 1-3 column blocks of right-hand sides, ragged n; the
-    refined result matches the oracle."""
+    refined result matches the oracle.  (Pairs throughout: the quads of tile
+    256 are compared with pairs in their own test.)"""
+    monkeypatch.setenv("KRR_SWEEP_QUADS", "0")
     m = 700
     G = _gen(n, m, seed=n + 11)
     Y = synth.phenotypes(G, r, n_pairs=5, n_add=3, seed=n + 12, h2=0.5)
