@@ -382,12 +382,13 @@ def run_batched(args, steps, warmup, plain_steps):
     lams = [w.lam for w, _ in insts]
     m, r = insts[0][0].m, insts[0][0].r
     ns = [w.n for w, _ in insts]
-    ctx = krr.krr_create(0, tile=args.tile)
     adaptive = krr.Policy(eps=args.eps, high_panels=args.high_panels)
     refine = krr.Refine(method=krr.KRR_REFINE_IR if args.refine == "ir" else krr.KRR_REFINE_AUTO,
                         max_iters=30, tol=REFINE_TOL)
+    plain = krr.plain_fp32_policy()
+    no_refine = krr.Refine(method=krr.KRR_REFINE_NONE)
 
-    def step(policy, ref):
+    def step(policy, ref, ctx):
         Ks = krr.krr_build_kernel_batched(ctx, Gs, gammas, lams)
         Fs = krr.krr_factor_batched(ctx, Ks, policy)
         Xs, infos, st = krr.krr_solve_batched(ctx, Fs, Ys, ref, check=False)
@@ -397,14 +398,40 @@ def run_batched(args, steps, warmup, plain_steps):
             K.release()
         return infos
 
+    # the tile of each path: one warm and one timed step at each size (as the
+    # single workload's autotuner does for it), unless --no-tune
+    tiles = [args.tile] if args.no_tune else [256, 512]
+    ctxs = {t: krr.krr_create(0, tile=t) for t in tiles}
+
+    def pick(policy, ref):
+        best = None
+        for t in tiles:
+            if len(tiles) == 1:
+                return t
+            step(policy, ref, ctxs[t])
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            step(policy, ref, ctxs[t])
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            if best is None or el < best[1]:
+                best = (t, el)
+        return best[0]
+
+    tile_a = pick(adaptive, refine)
+    tile_p = pick(plain, no_refine) if not args.no_plain else tile_a
+    for t in list(ctxs):
+        if t not in (tile_a, tile_p):
+            ctxs.pop(t).close()
+    ctx = ctxs[tile_a]
     for _ in range(warmup):
-        step(adaptive, refine)
+        step(adaptive, refine, ctx)
     torch.cuda.synchronize()
     krr.krr_timers_enable_stages(ctx, ["gram"])
     t0 = time.perf_counter()
     worst, all_conv = 0.0, True
     for _ in range(steps):
-        infos = step(adaptive, refine)
+        infos = step(adaptive, refine, ctx)
         worst = max([worst] + [i.fwd_err_bound for i in infos])
         all_conv = all_conv and all(bool(i.converged) for i in infos)
     torch.cuda.synchronize()
@@ -412,7 +439,7 @@ def run_batched(args, steps, warmup, plain_steps):
     g_ms, g_cnt = krr.krr_timers_read(ctx)["gram"]
     # the stage breakdown from one more step with every stage timed (outside the timed region)
     krr.krr_timers_enable(ctx, True)
-    step(adaptive, refine)
+    step(adaptive, refine, ctx)
     torch.cuda.synchronize()
     stages = krr.krr_timers_read(ctx)
     krr.krr_timers_enable(ctx, False)
@@ -428,8 +455,8 @@ def run_batched(args, steps, warmup, plain_steps):
         "config": {
             "workload": "batch of %d KRR instances, n in [%d, %d] (sum %d), m=%d, r=%d, "
                         "gamma in {0.5,1,2}/m, lambda in {1e-3,1e-2,1e-1,1}, tile %d"
-                        % (len(ns), min(ns), max(ns), sum(ns), m, r, args.tile),
-            "batch": len(ns), "m": m, "nrhs": r, "tile": args.tile,
+                        % (len(ns), min(ns), max(ns), sum(ns), m, r, tile_a),
+            "batch": len(ns), "m": m, "nrhs": r, "tile": tile_a, "tile_plain_fp32": tile_p,
             "parallelism": "single GPU",
         },
         "ops_per_step": ops,
@@ -447,18 +474,18 @@ def run_batched(args, steps, warmup, plain_steps):
         "input_generation_s": gen_s,
     }
     if not args.no_plain:
-        plain = krr.plain_fp32_policy()
-        no_refine = krr.Refine(method=krr.KRR_REFINE_NONE)
-        step(plain, no_refine)
+        cp = ctxs[tile_p]
+        step(plain, no_refine, cp)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(plain_steps):
-            step(plain, no_refine)
+            step(plain, no_refine, cp)
         torch.cuda.synchronize()
         pdt = (time.perf_counter() - t0) / plain_steps
         out["plain_fp32"] = {"value": ops / pdt, "ms_per_step": pdt * 1e3, "steps": plain_steps}
         out["speedup_vs_plain_fp32"] = pdt / dt
-    ctx.close()
+    for c in ctxs.values():
+        c.close()
     del Gs, Ys
     torch.cuda.empty_cache()
     return out
