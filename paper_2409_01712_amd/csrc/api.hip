@@ -623,13 +623,17 @@ krr_status krr_build_kernel_ex(krr_context ctx, const int8_t *G, int64_t n, int6
     }
     {
       Stage t(ctx, KRR_STAGE_ROW_NORMS);  // the genotypes' preparation
-      launch_row_norms(G, n, L.np, m, ldg, K->nrm, flag, s);  // and the genotype check
-      if (K->H) {
-        launch_ibs_encode(G, n, m, ldg, K->H, K->ldh, s);
-        launch_row_norms(K->H, n, L.np, K->ldh, K->ldh, K->nrm, flag, s);
+      if (K->Gs && !K->H) {  // the slab-major copy, the row norms and the check in one pass
+        launch_slab_major_norms(G, n, L.np, m, ldg, K->Gs, K->nrm, flag, s);
+      } else {
+        launch_row_norms(G, n, L.np, m, ldg, K->nrm, flag, s);  // and the genotype check
+        if (K->H) {
+          launch_ibs_encode(G, n, m, ldg, K->H, K->ldh, s);
+          launch_row_norms(K->H, n, L.np, K->ldh, K->ldh, K->nrm, flag, s);
+        }
+        if (K->Gs)
+          launch_slab_major(K->gram_src(), n, L.np, K->gram_m(), K->gram_ld(), K->Gs, s);
       }
-      if (K->Gs)
-        launch_slab_major(K->gram_src(), n, L.np, K->gram_m(), K->gram_ld(), K->Gs, s);
     }
     int32_t hflag = 0;
     if (hipMemcpyAsync(&hflag, flag, 4, hipMemcpyDeviceToHost, s) != hipSuccess ||

@@ -93,6 +93,65 @@ __global__ void k_slab_major(const int8_t *__restrict__ G, int64_t n, int64_t np
   *(v4i *)(Gs + e * 16) = v;
 }
 
+// The slab-major copy and the row norms (with the genotype check) in one
+// pass over G: a workgroup takes 32 rows and a run of slab pairs, each row's
+// 128 bytes of a pair read by eight threads (whole lines) and written to its
+// two slabs; each thread sums the squares of its bytes over the run
+// (udot4), the eight of a row add theirs and one atomic add per row and
+// workgroup puts the sum into nrm (zeroed before: integer sums, so the order
+// does not matter).  Bytes above 2 (not a genotype) set flag.
+constexpr int SLAB_RUN = 64;  // slab pairs a workgroup
+__global__ __launch_bounds__(256) void k_slab_major_norms(const int8_t *__restrict__ G, int64_t n,
+                                                          int64_t np, int64_t m, int64_t ldg,
+                                                          int64_t nslab, int8_t *__restrict__ Gs,
+                                                          int32_t *__restrict__ nrm,
+                                                          int32_t *flag) {
+  const int tid = threadIdx.x, c = tid & 7;
+  const int64_t r = (int64_t)blockIdx.x * 32 + (tid >> 3);
+  const int64_t nsp = (nslab + 1) / 2, sp0 = (int64_t)blockIdx.y * SLAB_RUN;
+  const int64_t sp1 = min(nsp, sp0 + SLAB_RUN);
+  const int64_t slab_of = c >> 2, off = 16 * (c & 3);
+  uint32_t acc = 0, bad = 0;
+  for (int64_t sp = sp0; sp < sp1; sp += 8) {
+    v4i v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int64_t kb = (sp + u) * 128 + 16 * c;
+      v[u] = (v4i){0, 0, 0, 0};
+      if (sp + u < sp1 && r < n && kb < m) {
+        v[u] = *(const v4i *)(G + r * ldg + kb);
+        if (kb + 16 > m) v[u] = mask_tail(v[u], m - kb);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int64_t sl = 2 * (sp + u) + slab_of;
+      if (sp + u < sp1 && sl < nslab && r < np) *(v4i *)(Gs + (sl * np + r) * 64 + off) = v[u];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const uint32_t w = (uint32_t)v[u][q];
+        bad |= (w & 0xFCFCFCFCu) | ((w & (w >> 1)) & 0x01010101u);
+        acc = __builtin_amdgcn_udot4(w, w, acc, false);
+      }
+    }
+  }
+  int sum = (int)acc;
+  sum += __shfl_xor(sum, 1, 64);
+  sum += __shfl_xor(sum, 2, 64);
+  sum += __shfl_xor(sum, 4, 64);
+  if (c == 0 && r < n && sum != 0) atomicAdd(&nrm[r], sum);
+  if (bad) atomicOr(flag, 1);
+}
+
+void launch_slab_major_norms(const int8_t *G, int64_t n, int64_t np, int64_t m, int64_t ldg,
+                             int8_t *Gs, int32_t *nrm, int32_t *flag, hipStream_t s) {
+  const int64_t nslab = (m + 63) / 64, nsp = (nslab + 1) / 2;
+  launch_fill_i32(nrm, np, 0, s);
+  hipLaunchKernelGGL(k_slab_major_norms,
+                     dim3((unsigned)((np + 31) / 32), (unsigned)((nsp + SLAB_RUN - 1) / SLAB_RUN)),
+                     dim3(256), 0, s, G, n, np, m, ldg, nslab, Gs, nrm, flag);
+}
+
 void launch_slab_major(const int8_t *G, int64_t n, int64_t np, int64_t m, int64_t ldg,
                        int8_t *Gs, hipStream_t s) {
   const int64_t nslab = (m + 63) / 64, cnt = nslab * np * 4;

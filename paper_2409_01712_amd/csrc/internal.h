@@ -83,6 +83,10 @@ void launch_gram_tiles(const int8_t *G, int64_t m, int64_t ldg, const int32_t *n
                        const double *Ec, const int8_t *Gs, hipStream_t s);
 // Gs[(s np + r) 64 + b] = G[r, 64 s + b] (zero past m and for rows n .. np-1):
 // np * ceil(m / 64) * 64 bytes.
+// The slab-major copy of G with its row norms (nrm zeroed first, then summed
+// in) and the genotype check (flag |= 1 on a byte above 2), one pass.
+void launch_slab_major_norms(const int8_t *G, int64_t n, int64_t np, int64_t m, int64_t ldg,
+                             int8_t *Gs, int32_t *nrm, int32_t *flag, hipStream_t s);
 void launch_slab_major(const int8_t *G, int64_t n, int64_t np, int64_t m, int64_t ldg,
                        int8_t *Gs, hipStream_t s);
 void launch_tile_norms(const double *part, int parts, int64_t ntiles, double *tnorm, hipStream_t s);
