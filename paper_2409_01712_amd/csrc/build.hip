@@ -333,25 +333,32 @@ KRR_DEV int find_job(const BuildJob *jobs, int njobs, int64_t bid) {
 // and runs the same block as the single-instance kernel.
 template <class S>
 __global__ __launch_bounds__(S::THREADS) void k_gram_tiles_batched(const BuildJob *__restrict__ jobs,
-                                                            int njobs, int64_t m, int nb, int SB) {
+                                                            int njobs, int64_t m, int nb, int SB,
+                                                            int grouped) {
   const int64_t bid = xcd_remap(blockIdx.x, gridDim.x);
   const BuildJob &j = jobs[find_job<&BuildJob::block0>(jobs, njobs, bid)];
   gram_block<S>(j.G, j.n, m, j.ldg, j.nrm, j.etab, j.etab_len, j.lambda, nb, SB, j.D, j.A, j.part,
-                bid - j.block0, VAL_EXP, nullptr);
+                bid - j.block0, VAL_EXP, nullptr, nullptr, 0, grouped != 0);
 }
 
 typedef StreamShape<256, 256, 2, 4, 4> GramShape;
+
+// The Gram's blocks in the grouped order, unless KRR_GRAM_ORDER=0 (tiles in
+// packed order, for comparison).
+static int gram_grouped_order() {
+  static const int grouped = [] {
+    const char *e = getenv("KRR_GRAM_ORDER");
+    return (e && atoi(e) == 0) ? 0 : 1;
+  }();
+  return grouped;
+}
 
 void launch_gram_tiles(const int8_t *G, int64_t m, int64_t ldg, const int32_t *nrm,
                        const double *etab, int64_t etab_len, double lambda, const TileLayout &L,
                        int32_t *D, float *A, double *tnorm_part, int vmode,
                        const double *Ec, const int8_t *Gs, hipStream_t s) {
   const int SB = L.nb / GramShape::kBM;
-  // KRR_GRAM_ORDER=0: tiles in packed order (for comparison); else grouped
-  static const int grouped = [] {
-    const char *e = getenv("KRR_GRAM_ORDER");
-    return (e && atoi(e) == 0) ? 0 : 1;
-  }();
+  const int grouped = gram_grouped_order();
   const int64_t blocks = L.ntiles() * SB * SB;
   build_kernel_attrs();
   hipLaunchKernelGGL((k_gram_tiles<GramShape>), dim3((unsigned)blocks), dim3(GramShape::THREADS),
@@ -372,7 +379,7 @@ void launch_gram_tiles_batched(const BuildJob *jobs, int njobs, int64_t blocks, 
   build_kernel_attrs();
   hipLaunchKernelGGL((k_gram_tiles_batched<GramShape>), dim3((unsigned)blocks),
                      dim3(GramShape::THREADS), GramShape::LDS_BYTES, s, jobs, njobs, m, nb,
-                     nb / GramShape::kBM);
+                     nb / GramShape::kBM, gram_grouped_order());
 }
 
 __global__ __launch_bounds__(256) void k_row_norms_batched(const BuildJob *__restrict__ jobs,
