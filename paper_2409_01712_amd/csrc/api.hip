@@ -847,6 +847,7 @@ static void factor_work_free(krr_context c, FactorWork &w, const TileLayout &L) 
   dfree(c, w.flag, 4);
   dfree(c, w.counts, 3 * 8);
   dfree(c, w.lpart, load_part_bytes(L));
+  dfree(c, w.WX64, te * 8);
   w = FactorWork();
 }
 
@@ -878,7 +879,10 @@ static krr_status factor_work_alloc(krr_context c, FactorWork &w, const TileLayo
   WA(w.pmax_part, pt * parts * 4);
   WA(w.flag, 4);
   WA(w.counts, 3 * 8);
-  if (split_load) WA(w.lpart, load_part_bytes(L));  // single instance: split-K tile loads
+  if (split_load) {  // single instance: split-K tile loads, the next row's panel in the steps
+    WA(w.lpart, load_part_bytes(L));
+    WA(w.WX64, te * 8);
+  }
 #undef WA
   return KRR_SUCCESS;
 }
@@ -1017,8 +1021,9 @@ static krr_status factor_enqueue(krr_context ctx, krr_kernel K, krr_factorizatio
   auto panels = [&](int G0, int npan, const PanelBuf **ps) {
     for (int q = 0; q < npan; ++q) ps[q] = &slot(G0 + q);
   };
-  // POTRF(k); the updates of tile (k, k) by panels q0 .. q0+nq-1 are folded in
-  auto potrf = [&](int k, int q0, int nq, hipStream_t st) {
+  // POTRF(k); the updates of tile (k, k) by panels q0 .. q0+nq-1 are folded in;
+  // with row.A, the panel's row tile k+1 formed in the same steps
+  auto potrf = [&](int k, int q0, int nq, hipStream_t st, const RowPanel &row = RowPanel{}) {
     DiagUpdate du{};
     du.npan = nq;
     du.pmap = dmap;
@@ -1030,7 +1035,7 @@ static krr_status factor_enqueue(krr_context ctx, krr_kernel K, krr_factorizatio
     // with the lookahead schedule the steps also form the FP32 factor tile and
     // the tile inverse but for its last block row (off the side stream)
     launch_potrf_tile(F->Lst + TileLayout::tri(k, k) * te, k, L, fp.diag64, w, du,
-                      lookahead ? F->Linv + (int64_t)k * te : nullptr, st);
+                      lookahead ? F->Linv + (int64_t)k * te : nullptr, st, row);
   };
   // TRSM of panel k, tiles k+1+t_lo .. : by substitution (no inverse) or
   // as a product with inv(L_kk) after forming it
@@ -1092,6 +1097,13 @@ static krr_status factor_enqueue(krr_context ctx, krr_kernel K, krr_factorizatio
     // depend on the schedule.
     hipStream_t sm = ctx->fmain, sd = ctx->side, sx = ctx->aux;
     const int ngroups = (NT + g - 1) / g;
+    // KRR_ROW_IN_STEPS=1: row tile k+1 of panel k formed inside POTRF(k)'s
+    // steps, in place of the substitution TRSM launch after them.  Measured
+    // slower (72.4 against 66.7 ms a benchmark step at tile 256): the steps
+    // then wait for column k's updates on the side stream, which the later
+    // TRSM launch waits for only after the tile's factorization.
+    const char *ris = getenv("KRR_ROW_IN_STEPS");
+    const bool row_in_steps = w.WX64 && ris && atoi(ris) != 0;
     std::vector<hipEvent_t> &E = ctx->sched_ev;
     bool ok = sched_events(ctx, NT, g);
     hipEvent_t *e_t1 = E.data(), *e_conv = e_t1 + NT, *e_uin = e_conv + NT,
@@ -1120,20 +1132,32 @@ static krr_status factor_enqueue(krr_context ctx, krr_kernel K, krr_factorizatio
         // whole previous group (at its start); the earlier panels of the
         // group reached it through the side stream's diagonal updates
         if (k >= G0 + 2) wait(sm, e_udiag[k - 2]);
+        // row tile k+1 of the panel waits for column k's updates: the
+        // in-group ones (side), or the previous group's update of this
+        // group's columns (side)
+        hipEvent_t col_ready = k > G0 ? e_uin[k - 1] : (gi > 0 ? e_narrow[gi - 1] : nullptr);
+        RowPanel row;
+        if (row_in_steps && k + 1 < NT) {
+          row.A = F->Lst + TileLayout::tri(k + 1, k) * te;
+          row.P32 = slot(k).P32;
+          row.pnorm_part = w.pnorm_part;
+          row.pmax_part = w.pmax_part;
+          row.parts = trsm_parts(L.nb);
+          row.wait = col_ready;
+        }
         if (k > G0) {
-          potrf(k, k - 1, 1, sm);
+          potrf(k, k - 1, 1, sm, row);
         } else if (early0 && gi == 1) {  // panel 0 reached it through aux
           wait(sm, e_early);
-          potrf(k, 1, g - 1, sm);
+          potrf(k, 1, g - 1, sm, row);
         } else {
-          potrf(k, std::max(G0 - g, 0), G0 > 0 ? g : 0, sm);
+          potrf(k, std::max(G0 - g, 0), G0 > 0 ? g : 0, sm, row);
         }
         if (k + 1 >= NT) break;
-        // column k below the diagonal: in-group updates (side), or the
-        // previous group's update of this group's columns (side)
-        if (k > G0) wait(sm, e_uin[k - 1]);
-        else if (gi > 0) wait(sm, e_narrow[gi - 1]);
-        trsm_subst(k, 0, 1, sm);
+        if (!row_in_steps) {
+          if (col_ready) wait(sm, col_ready);
+          trsm_subst(k, 0, 1, sm);
+        }
         rec(e_t1[k], sm);
         wait(sd, e_t1[k]);
         trsm_gemm(k, 1, NT, sd);

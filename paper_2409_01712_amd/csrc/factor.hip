@@ -425,13 +425,95 @@ KRR_DEV void load_acc64(const T *src, int64_t ld, typename M16<T>::v4 (&acc)[4])
       acc[ct][r] = src[(int64_t)(16 * wave + M16<T>::row(r, lane)) * ld + 16 * ct + (lane & 15)];
 }
 
+// Device view of a RowPanel (WX in T); final: the launch after the last
+// step (one workgroup per block row, the last block column alone).
+template <typename T>
+struct RowPanelDev {
+  const float *A;
+  T *WX;
+  float *P32;
+  double *pnorm_part;
+  float *pmax_part;
+  int parts, final_launch;
+};
+
 template <typename T>
 KRR_DEV void potrf_step_body(T *__restrict__ W, T *__restrict__ WL, int nb, int s,
                              T *__restrict__ Dinv, int32_t *flag, int64_t colbase, int bid,
                              int npairs = 1 << 30, T *__restrict__ Winv = nullptr,
-                             float *Lf = nullptr, float *If = nullptr) {
+                             float *Lf = nullptr, float *If = nullptr, int ninv = 1 << 29,
+                             const RowPanelDev<T> *rp = nullptr) {
   typedef typename M16<T>::v4 v4;
   __shared__ T buf[3][BS][BS + 1];
+  if (rp && bid >= npairs + ninv) {
+    // The next row tile's panel, block column s: workgroup (x, b) forms
+    // L_x,s = WX_x,s inv(L_ss)^T and L_b,s, subtracts L_x,s L_b,s^T from
+    // WX_x,b (b > s; at s = 0 WX starts from A), and for b = s + 1 writes
+    // L_x,s out; after the last step, workgroup x forms L_x,NB-1 alone.
+    const int NB = nb / BS, e = bid - npairs - ninv;
+    __shared__ double shd[4];
+    __shared__ float shf[4];
+    const int x = rp->final_launch ? e : e / (NB - 1 - s);
+    const int b = rp->final_launch ? s : s + 1 + e % (NB - 1 - s);
+    T(*Xa)[BS + 1] = buf[0];
+    T(*Xb)[BS + 1] = buf[1];
+    T(*Li)[BS + 1] = buf[2];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int64_t oxs = (int64_t)(x * BS) * nb + s * BS, oxb = (int64_t)(x * BS) * nb + b * BS;
+    if (s == 0) {
+      for (int q = threadIdx.x; q < BS * BS; q += 256)
+        Xa[q / BS][q % BS] = (T)rp->A[oxs + (int64_t)(q / BS) * nb + q % BS];
+    } else {
+      load64(Xa, rp->WX + oxs, nb);
+    }
+    load64(Li, Dinv + (int64_t)s * BS * BS, BS);
+    if (!rp->final_launch) load64(Xb, W + (int64_t)(b * BS) * nb + s * BS, nb);
+    __syncthreads();
+    v4 pa[4], pb[4];
+    zero4<T>(pa);
+    mm64<T, true>(Xa, Li, pa);
+    if (!rp->final_launch) {
+      zero4<T>(pb);
+      mm64<T, true>(Xb, Li, pb);
+      __syncthreads();
+      store_lds64<T>(Xa, pa);
+      store_lds64<T>(Xb, pb);
+      __syncthreads();
+      v4 acc[4];
+      zero4<T>(acc);
+      mm64<T, true>(Xa, Xb, acc);
+#pragma unroll
+      for (int ct = 0; ct < 4; ++ct)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int64_t o = oxb + (int64_t)(16 * wave + M16<T>::row(r, lane)) * nb + 16 * ct +
+                            (lane & 15);
+          const T prev = s == 0 ? (T)rp->A[o] : rp->WX[o];
+          rp->WX[o] = prev - acc[ct][r];
+        }
+    }
+    if (rp->final_launch || b == s + 1) {  // L_x,s out, with its sum of squares and maximum
+      double ss = 0.0;
+      float mx = 0.0f;
+#pragma unroll
+      for (int ct = 0; ct < 4; ++ct)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const float f = (float)pa[ct][r];
+          rp->P32[oxs + (int64_t)(16 * wave + M16<T>::row(r, lane)) * nb + 16 * ct + (lane & 15)] =
+              f;
+          ss += (double)f * (double)f;
+          mx = fmaxf(mx, fabsf(f));
+        }
+      ss = block_sum<4>(ss, shd);
+      mx = block_max<4>(mx, shf);
+      if (threadIdx.x == 0) {
+        rp->pnorm_part[x * NB + s] = ss;
+        rp->pmax_part[x * NB + s] = mx;
+      }
+    }
+    return;
+  }
   if (bid >= npairs) {
     const int extra = bid - npairs, p = s - 1;
     int r, t;
@@ -544,6 +626,18 @@ __global__ __launch_bounds__(256) void k_potrf_step(T *__restrict__ W, T *__rest
                                                     int64_t colbase, int npairs, T *Winv,
                                                     float *Lf, float *If) {
   potrf_step_body<T>(W, WL, nb, s, Dinv, flag, colbase, blockIdx.x, npairs, Winv, Lf, If);
+}
+
+// The steps with the next row tile's panel formed beside them (extra
+// workgroups after the pairs and the inverse's).
+template <typename T>
+__global__ __launch_bounds__(256) void k_potrf_step_row(T *__restrict__ W, T *__restrict__ WL,
+                                                        int nb, int s, T *__restrict__ Dinv,
+                                                        int32_t *flag, int64_t colbase,
+                                                        int npairs, int ninv, T *Winv, float *Lf,
+                                                        float *If, RowPanelDev<T> rp) {
+  potrf_step_body<T>(W, WL, nb, s, Dinv, flag, colbase, blockIdx.x, npairs, Winv, Lf, If, ninv,
+                     &rp);
 }
 
 // Inverses of the diagonal tiles k0 .. k0+C-1 (tile c = blockIdx.y or
@@ -933,7 +1027,8 @@ static T *inv_slot(FactorWork &w, int k, int64_t te) {
 
 template <typename T>
 static void potrf_tile_t(float *Akk, int k, const TileLayout &L, FactorWork &w,
-                         const DiagUpdate &du, float *Linv_k, hipStream_t s) {
+                         const DiagUpdate &du, float *Linv_k, hipStream_t s,
+                         const RowPanel &row) {
   const int nb = L.nb, NB = nb / BS;
   const int64_t te = (int64_t)nb * nb;
   T *W = (T *)w.W64, *WL = (T *)w.WL64 + k * te, *Dinv = (T *)w.Dinv64 + (int64_t)k * NB * BS * BS;
@@ -955,21 +1050,33 @@ static void potrf_tile_t(float *Akk, int k, const TileLayout &L, FactorWork &w,
     hipLaunchKernelGGL(k_potrf_diag64<T>, dim3(1), dim3(256), 0, s, W, WL, nb, Dinv, w.flag,
                        colbase, Lf, Linv_k);
   }
+  const bool with_row = row.A && w.WX64;
+  RowPanelDev<T> rp{row.A, (T *)w.WX64, row.P32, row.pnorm_part, row.pmax_part, row.parts, 0};
+  if (with_row && row.wait) (void)hipStreamWaitEvent(s, row.wait, 0);  // A_k+1,k complete
   for (int st = 0; st + 1 < NB; ++st) {
     const int rest = NB - 1 - st, npairs = rest * (rest + 1) / 2;
     // the inverse: row st finalized, the later rows' sums advanced by row st - 1
     const int ninv = Winv ? st + (NB - 1 - st) * st : 0;
-    hipLaunchKernelGGL(k_potrf_step<T>, dim3(npairs + ninv), dim3(256), 0, s, W, WL, nb, st, Dinv,
-                       w.flag, colbase, npairs, Winv, Lf, Linv_k);
+    if (with_row)
+      hipLaunchKernelGGL(k_potrf_step_row<T>, dim3(npairs + ninv + NB * rest), dim3(256), 0, s, W,
+                         WL, nb, st, Dinv, w.flag, colbase, npairs, ninv, Winv, Lf, Linv_k, rp);
+    else
+      hipLaunchKernelGGL(k_potrf_step<T>, dim3(npairs + ninv), dim3(256), 0, s, W, WL, nb, st,
+                         Dinv, w.flag, colbase, npairs, Winv, Lf, Linv_k);
+  }
+  if (with_row) {  // the panel's last block column
+    rp.final_launch = 1;
+    hipLaunchKernelGGL(k_potrf_step_row<T>, dim3(NB), dim3(256), 0, s, W, WL, nb, NB - 1, Dinv,
+                       w.flag, colbase, 0, 0, Winv, Lf, Linv_k, rp);
   }
 }
 
 void launch_potrf_tile(float *Akk, int k, const TileLayout &L, bool fp64, FactorWork &w,
-                       const DiagUpdate &du, float *Linv_k, hipStream_t s) {
+                       const DiagUpdate &du, float *Linv_k, hipStream_t s, const RowPanel &row) {
   if (fp64)
-    potrf_tile_t<double>(Akk, k, L, w, du, Linv_k, s);
+    potrf_tile_t<double>(Akk, k, L, w, du, Linv_k, s, row);
   else
-    potrf_tile_t<float>(Akk, k, L, w, du, Linv_k, s);
+    potrf_tile_t<float>(Akk, k, L, w, du, Linv_k, s, row);
 }
 
 void launch_tile_inverse_last_row(float *Linv_k, int k, const TileLayout &L, bool fp64,
@@ -1121,7 +1228,7 @@ __global__ __launch_bounds__(256) void k_trsm_panel(const float *__restrict__ As
 
 // Partial-norm slots per tile: the substitution TRSM fills nb/16 of them, the
 // product form one per 64 x 64 block.
-static int trsm_parts(int nb) { return std::max((nb / 64) * (nb / 64), nb / TRSM_ROWS); }
+int trsm_parts(int nb) { return std::max((nb / 64) * (nb / 64), nb / TRSM_ROWS); }
 
 template <typename T>
 static void trsm_subst_t(const float *Astore, int k, const TileLayout &L, FactorWork &w,

@@ -163,6 +163,7 @@ struct FactorWork {
   // split-K load of a diagonal tile: per-chunk 64 x 64 partial products
   // (KRR_MAX_GROUP chunks x (nb/64)(nb/64+1)/2 blocks)
   float *lpart = nullptr;
+  double *WX64 = nullptr;  // nb x nb: the next row tile's panel while the steps form it
 };
 // Updates of a diagonal tile left to its factorization: P[q] points at tile
 // k of panel buffer q; pmap_at[q] is the precision-map entry to mark FP32.
@@ -209,8 +210,24 @@ void launch_factor_lockstep(const FactorJob *jobs, const int *nts, int njobs, in
 // inv(L_kk) in FP32 into Linv_k, formed in the same steps (the last block
 // row by launch_tile_inverse_last_row); needs at least two tiles of the
 // work's inverse chunk buffer.
+// The next row tile's panel formed in the same steps (RowPanel::A non-null):
+// P = A inv(L_kk)^T for A = A_k+1,k (FP32, row-major nb x nb), by the steps'
+// extra workgroups (right-looking, block column by block column, in the
+// work's WX64 tile), into P32 (FP32) with the per-64x64-block sums of squares
+// and maxima (parts slots a tile) the panel conversion reads; `wait`, if not
+// null, is waited for between the tile's load and its steps (A ready).
+struct RowPanel {
+  const float *A = nullptr;
+  float *P32 = nullptr;
+  double *pnorm_part = nullptr;
+  float *pmax_part = nullptr;
+  int parts = 0;
+  hipEvent_t wait = nullptr;
+};
 void launch_potrf_tile(float *Akk, int k, const TileLayout &L, bool fp64, FactorWork &w,
-                       const DiagUpdate &du, float *Linv_k, hipStream_t s);
+                       const DiagUpdate &du, float *Linv_k, hipStream_t s,
+                       const RowPanel &row = RowPanel{});
+int trsm_parts(int nb);  // partial-norm slots of a panel tile
 void launch_tile_inverse_last_row(float *Linv_k, int k, const TileLayout &L, bool fp64,
                                   FactorWork &w, hipStream_t s);
 // L_kk into the factor storage and inv(L_kk), FP32, for the diagonal tiles

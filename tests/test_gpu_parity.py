@@ -362,6 +362,44 @@ def test_split_load_matches_single_load(monkeypatch, n, tile):
     c.close()
 
 
+@pytest.mark.parametrize("n,tile", [(1500, 256), (2600, 512), (5000, 256)])
+def test_row_in_steps_matches_substitution(monkeypatch, n, tile):
+    """Row tile k+1 of each panel formed by extra workgroups of POTRF(k)'s
+    64-column steps (right-looking, from the stored tile, in FP64) gives the
+    panel of the separate substitution TRSM to FP32 rounding, the same bits on
+    a second run, and refined solutions that match the oracle (FP32 and
+    adaptive policies; n = 5000 at tile 256 crosses a panel group boundary)."""
+    m, r = 800, 6
+    G = _gen(n, m, seed=n + 41)
+    Y = synth.phenotypes(G, r, n_pairs=5, n_add=3, seed=n + 42, h2=0.5)
+    gamma, lam = 1.0 / m, 0.1
+    c = krr.krr_create(0, tile=tile)
+    K = krr.krr_build_kernel(c, _dev(G), gamma, lam)
+    none = krr.Refine(method=krr.KRR_REFINE_NONE)
+    Wo = oracle.fit(G, Y, gamma, lam)
+    for policy in (krr.plain_fp32_policy(), None):
+        xs, refined = [], []
+        for on in ("1", "1", "0"):
+            monkeypatch.setenv("KRR_ROW_IN_STEPS", on)
+            F = krr.krr_factor(c, K, policy)
+            X, _, _ = krr.krr_solve(c, F, _dev(Y), none)
+            xs.append(X.cpu().numpy())
+            X, info, st = krr.krr_solve(c, F, _dev(Y), krr.Refine(tol=1e-8))
+            assert info.converged == 1
+            refined.append(X.cpu().numpy())
+            F.release()
+        monkeypatch.delenv("KRR_ROW_IN_STEPS")
+        assert np.array_equal(xs[0], xs[1])
+        if policy is not None:
+            # the same panel by another order of FP64 products, rounded to
+            # FP32; a wrong block, sign or missed update would be O(1)
+            assert _colrel(xs[0], xs[2]) <= 1e-4
+        for Xr in refined:
+            assert _colrel(Xr, Wo) <= TOL
+    K.release()
+    c.close()
+
+
 @pytest.mark.skip(reason="persistent one-launch sweeps are switched off (KRR_SWEEP_PAIRS=2 "
                   "returns KRR_ERROR_NOT_SUPPORTED): the first GPU runs hung at n=200 (one "
                   "tile), also with time-bounded waits, and the cause is not known")
