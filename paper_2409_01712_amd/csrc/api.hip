@@ -57,6 +57,9 @@ struct krr_context_s {
   int aux_e = 8;              // eighths of the CUs the aux stream uses
   hipStream_t aux_by_e[9] = {};  // the aux streams made so far, by eighths (kept)
   std::vector<hipEvent_t> sched_ev;  // ordering events of the factorization schedule
+  // second stream and events of the split quad sweeps
+  hipStream_t sw2 = nullptr;
+  std::vector<hipEvent_t> sweep_ev;
 };
 
 struct krr_kernel_s {
@@ -420,7 +423,7 @@ static void context_free(krr_context ctx) {
   timers_drain(ctx);
   for (hipEvent_t e : ctx->pool) (void)hipEventDestroy(e);
   cache_flush(ctx);
-  for (hipStream_t x : {ctx->side, ctx->fmain, ctx->cap}) {
+  for (hipStream_t x : {ctx->side, ctx->fmain, ctx->cap, ctx->sw2}) {
     if (x) {
       (void)hipStreamSynchronize(x);
       (void)hipStreamDestroy(x);
@@ -433,6 +436,7 @@ static void context_free(krr_context ctx) {
     }
   }
   for (hipEvent_t e : ctx->sched_ev) (void)hipEventDestroy(e);
+  for (hipEvent_t e : ctx->sweep_ev) (void)hipEventDestroy(e);
   delete ctx;
 }
 
@@ -1735,19 +1739,42 @@ static krr_status solve_alloc(Scoped &sc, const TileLayout &L, int r, SolveBufs 
   return KRR_SUCCESS;
 }
 
+// The split quad sweeps' second stream and events (two per quad step), made
+// once per context and grown with the tile count; null when the sweeps do
+// not go by quads or KRR_SWEEP_SPLIT=0.
+static const SweepSplit *sweep_split(krr_context ctx, const TileLayout &L, const SolveBufs &b,
+                                     SweepSplit &sp) {
+  const char *e = getenv("KRR_SWEEP_SPLIT");
+  if ((e ? atoi(e) : 0) == 0 || !b.C || !b.Q || L.nt < 12) return nullptr;
+  if (!ctx->sw2 && hipStreamCreateWithFlags(&ctx->sw2, hipStreamNonBlocking) != hipSuccess) {
+    ctx->sw2 = nullptr;
+    return nullptr;
+  }
+  const size_t need = (size_t)2 * (L.nt / 4);
+  while (ctx->sweep_ev.size() < need) {
+    hipEvent_t ev;
+    if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) return nullptr;
+    ctx->sweep_ev.push_back(ev);
+  }
+  sp = SweepSplit{ctx->sw2, ctx->sweep_ev.data(), (int)need};
+  return &sp;
+}
+
 // dst += L^-T L^-1 src with FP32 sweeps (src, dst: FP64, row-major np x r;
 // the sweeps work on column-major FP32 copies).
 static void solve_sweeps(krr_context ctx, krr_factorization F, int r, SolveBufs &b,
                          const double *src, double *dst, hipStream_t s) {
   const TileLayout &L = F->L;
+  SweepSplit spb;
+  const SweepSplit *sp = sweep_split(ctx, L, b, spb);
   launch_rows_f64_to_cols_f32(src, L.np, r, b.Bf, s);
   {
     Stage t(ctx, KRR_STAGE_FWD, s);
-    launch_fwd_sweep(F->Lst, F->Linv, b.C, b.Q, L, r, b.Bf, b.Zf, s);
+    launch_fwd_sweep(F->Lst, F->Linv, b.C, b.Q, L, r, b.Bf, b.Zf, s, sp);
   }
   {
     Stage t(ctx, KRR_STAGE_BWD, s);
-    launch_bwd_sweep(F->Lst, F->Linv, b.C, b.Q, L, r, b.Zf, b.Xf, s);
+    launch_bwd_sweep(F->Lst, F->Linv, b.C, b.Q, L, r, b.Zf, b.Xf, s, sp);
   }
   launch_cols_f32_axpy_rows_f64(b.Xf, L.np, r, 1.0, dst, s);
 }

@@ -274,10 +274,21 @@ void launch_encode_fp8(const float *x, int64_t n, uint8_t *out, hipStream_t s);
 // Right-hand sides of these two: FP32 column-major np x r (column stride
 // np).  C: the coupling tiles of launch_sweep_coupling (tiles taken in
 // pairs), or null (one tile per step).
+// sp (or null): a second stream and nev events; with it each quad step's
+// panel is split in two launches, the next quad's tiles on s and the rest
+// on s2, so that the rest overlaps the next quad's diagonal step (s2 is
+// joined back into s before the sweep returns).
+struct SweepSplit {
+  hipStream_t s2;
+  hipEvent_t *ev;
+  int nev;
+};
 void launch_fwd_sweep(const float *Astore, const float *Linv, const float *C, const float *Q,
-                      const TileLayout &L, int r, float *B, float *Z, hipStream_t s);
+                      const TileLayout &L, int r, float *B, float *Z, hipStream_t s,
+                      const SweepSplit *sp = nullptr);
 void launch_bwd_sweep(const float *Astore, const float *Linv, const float *C, const float *Q,
-                      const TileLayout &L, int r, float *Z, float *X, hipStream_t s);
+                      const TileLayout &L, int r, float *Z, float *X, hipStream_t s,
+                      const SweepSplit *sp = nullptr);
 // the sweeps take the tiles in quads when given Q (tile 256, wide panels)
 bool sweep_quads_supported(int nb);
 // R = Y - (K + lambda I) X in FP64; part: residual_split(L) * np * r doubles

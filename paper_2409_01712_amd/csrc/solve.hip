@@ -76,12 +76,14 @@ __device__ __forceinline__ void store_job(float *o, int r, int64_t ldv, int row0
       *q = make_float4(acc[0], acc[1], acc[2], acc[3]);
     }
   } else {
+    float *q = o + (int64_t)rb * r + col;
+    float old[4] = {0.f, 0.f, 0.f, 0.f};
+    if (SUB) {  // the four loads in flight together, then the stores
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      float *q = o + (int64_t)(rb + e) * r + col;
-      if (SUB) *q -= acc[e];
-      else *q = acc[e];
+      for (int e = 0; e < 4; ++e) old[e] = q[(int64_t)e * r];
     }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) q[(int64_t)e * r] = SUB ? old[e] - acc[e] : acc[e];
   }
 }
 
@@ -94,25 +96,31 @@ __device__ __forceinline__ v4f job_product(const float *__restrict__ M, const fl
   const int R = row0 + li, col = col0 + li;
   const int cc = min(col, r - 1);  // in-bounds load, zeroed below when col >= r
   const bool cv = col < r;
+  // branch-free: blocks past khi load k block 0 (in bounds) and take zero
+  // right-hand sides, so that every load is in flight before the first wait
   float a[8][4], b[8][4];
+  bool okm[8];
 #pragma unroll
   for (int u = 0; u < 8; ++u) {
     const int k16 = klo + 16 * (wave + 4 * u);
-    const int kk = k16 + 4 * lg;
-    if (k16 < khi) {
-      if (!TRANS) {
-        const float4 v = *(const float4 *)(M + (int64_t)R * nb + kk);
-        a[u][0] = v.x; a[u][1] = v.y; a[u][2] = v.z; a[u][3] = v.w;
-      } else {
-#pragma unroll
-        for (int e = 0; e < 4; ++e) a[u][e] = M[(int64_t)(kk + e) * nb + R];
-      }
-      load_v4<CM>(V, r, ldv, kk, cc, cv, 1.f, b[u]);
+    const bool ok = k16 < khi;
+    const int kk = (ok ? k16 : 0) + 4 * lg;
+    if (!TRANS) {
+      const float4 v = *(const float4 *)(M + (int64_t)R * nb + kk);
+      a[u][0] = v.x; a[u][1] = v.y; a[u][2] = v.z; a[u][3] = v.w;
     } else {
 #pragma unroll
-      for (int e = 0; e < 4; ++e) a[u][e] = b[u][e] = 0.f;
+      for (int e = 0; e < 4; ++e) a[u][e] = M[(int64_t)(kk + e) * nb + R];
     }
+    load_v4<CM>(V, r, ldv, kk, cc, true, 1.f, b[u]);
+    okm[u] = cv && ok;
   }
+  // all loads issued before the first use of a loaded value
+  __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+  for (int u = 0; u < 8; ++u)
+#pragma unroll
+    for (int e = 0; e < 4; ++e) b[u][e] = okm[u] ? b[u][e] : 0.f;
   v4f acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
   for (int u = 0; u < 8; ++u)
@@ -148,29 +156,35 @@ __device__ __forceinline__ v4f job_product2(const float *__restrict__ M1, const 
   v4f acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
   for (int ph = 0; ph < 2; ++ph) {
-    float a[8][4], b[8][4];
+    float a[8][4], b[8][4], sgm[8];
+    bool okm[8];
 #pragma unroll
     for (int uu = 0; uu < 8; ++uu) {
       const int g = wave + 4 * (8 * ph + uu);
-      const bool first = g < n1;
-      if (g < n1 + n2) {
-        const float *M = first ? M1 : M2;
-        const float *V = first ? V1 : V2;
-        const int kk = (first ? klo1 + 16 * g : klo2 + 16 * (g - n1)) + 4 * lg;
-        const float sg = first ? 1.0f : sign2;
-        if (!TRANS) {
-          const float4 v = *(const float4 *)(M + (int64_t)R * nb + kk);
-          a[uu][0] = v.x; a[uu][1] = v.y; a[uu][2] = v.z; a[uu][3] = v.w;
-        } else {
-#pragma unroll
-          for (int e = 0; e < 4; ++e) a[uu][e] = M[(int64_t)(kk + e) * nb + R];
-        }
-        load_v4<CM>(V, r, ldv, kk, cc, cv, sg, b[uu]);
+      const bool first = g < n1, ok = g < n1 + n2;
+      const float *M = first ? M1 : M2;
+      const float *V = first ? V1 : V2;
+      // branch-free as in job_product: a block past both ranges loads k
+      // block 0 and takes zero right-hand sides
+      const int kk = (ok ? (first ? klo1 + 16 * g : klo2 + 16 * (g - n1)) : 0) + 4 * lg;
+      const float sg = first ? 1.0f : sign2;
+      if (!TRANS) {
+        const float4 v = *(const float4 *)(M + (int64_t)R * nb + kk);
+        a[uu][0] = v.x; a[uu][1] = v.y; a[uu][2] = v.z; a[uu][3] = v.w;
       } else {
 #pragma unroll
-        for (int e = 0; e < 4; ++e) a[uu][e] = b[uu][e] = 0.f;
+        for (int e = 0; e < 4; ++e) a[uu][e] = M[(int64_t)(kk + e) * nb + R];
       }
+      load_v4<CM>(V, r, ldv, kk, cc, true, 1.f, b[uu]);
+      okm[uu] = cv && ok;
+      sgm[uu] = sg;
     }
+    // all loads issued before the first use of a loaded value
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int uu = 0; uu < 8; ++uu)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) b[uu][e] = okm[uu] ? sgm[uu] * b[uu][e] : 0.f;
 #pragma unroll
     for (int uu = 0; uu < 8; ++uu)
 #pragma unroll
@@ -284,6 +298,13 @@ __global__ __launch_bounds__(256) void k_sweep_diag2(const float *__restrict__ L
                          col0 + (threadIdx.x & 15), acc);
 }
 
+// x[t] for t in 0..3 through selects (a dynamic index into a local array can
+// go through memory)
+template <typename T, int N>
+__device__ __forceinline__ T pick4(const T (&x)[N], int t) {
+  return t == 0 ? x[0] : t == 1 ? x[1] : t == 2 ? x[2] : x[3];
+}
+
 // The sum of up to four products, sum_t sg[t] M_t V_t (k ranges [klo[t],
 // khi[t]), multiples of 16, at most 256 values of k each): the 16-wide k
 // blocks of all terms, in term order, dealt round robin to the four waves
@@ -307,27 +328,36 @@ __device__ __forceinline__ v4f job_product4(const float *const (&M)[4], const fl
   v4f acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
   for (int ph = 0; ph < 2; ++ph) {
-    float a[8][4], b[8][4];
+    float a[8][4], b[8][4], sgm[8];
+    bool okm[8];
 #pragma unroll
     for (int uu = 0; uu < 8; ++uu) {
       const int g = wave + 4 * (8 * ph + uu);
-      if (g < total) {
-        const int t = (g >= pre[1]) + (g >= pre[2]) + (g >= pre[3]);
-        const int kk = klo[t] + 16 * (g - pre[t]) + 4 * lg;
-        const float *Mt = M[t];
-        if (!TRANS) {
-          const float4 v = *(const float4 *)(Mt + (int64_t)R * nb + kk);
-          a[uu][0] = v.x; a[uu][1] = v.y; a[uu][2] = v.z; a[uu][3] = v.w;
-        } else {
-#pragma unroll
-          for (int e = 0; e < 4; ++e) a[uu][e] = Mt[(int64_t)(kk + e) * nb + R];
-        }
-        load_v4<true>(Vp[t], r, ldv, kk, cc, cv, sg[t], b[uu]);
+      // branch-free, the term picked by selects (no indexed local arrays): a
+      // block past the last term loads k block 0 of term 0 and takes zero
+      // right-hand sides, so that all loads are in flight before one wait
+      const bool ok = g < total;
+      const int gg = ok ? g : 0;
+      const int t = (gg >= pre[1]) + (gg >= pre[2]) + (gg >= pre[3]);
+      const int kk = (ok ? pick4(klo, t) + 16 * (gg - pick4(pre, t)) : 0) + 4 * lg;
+      const float *Mt = pick4(M, t);
+      if (!TRANS) {
+        const float4 v = *(const float4 *)(Mt + (int64_t)R * nb + kk);
+        a[uu][0] = v.x; a[uu][1] = v.y; a[uu][2] = v.z; a[uu][3] = v.w;
       } else {
 #pragma unroll
-        for (int e = 0; e < 4; ++e) a[uu][e] = b[uu][e] = 0.f;
+        for (int e = 0; e < 4; ++e) a[uu][e] = Mt[(int64_t)(kk + e) * nb + R];
       }
+      load_v4<true>(pick4(Vp, t), r, ldv, kk, cc, true, 1.f, b[uu]);
+      okm[uu] = cv && ok;
+      sgm[uu] = pick4(sg, t);
     }
+    // all loads issued before the first use of a loaded value
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int uu = 0; uu < 8; ++uu)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) b[uu][e] = okm[uu] ? sgm[uu] * b[uu][e] : 0.f;
 #pragma unroll
     for (int uu = 0; uu < 8; ++uu)
 #pragma unroll
@@ -370,28 +400,22 @@ __global__ __launch_bounds__(256) void k_sweep_diag4(const float *__restrict__ L
   const float *V[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) V[q] = In + tile_off<true>(k + q, nb, r);
-  // the terms of tile k+j: its own inverse first (its triangle), then the couplings
-  const float *M[4] = {iL, nullptr, nullptr, nullptr};
-  const float *Vt[4] = {V[j], nullptr, nullptr, nullptr};
-  int klo[4] = {FWD ? 0 : row0, 0, 0, 0}, khi[4] = {FWD ? row0 + 16 : nb, nb, nb, nb};
+  // the terms of tile k+j: its own inverse first (its triangle), then the
+  // couplings; every slot set by selects on j (no indexed stores), slots past
+  // nterm empty
+  const int nterm = FWD ? j + 1 : 4 - j;
+  const float *M[4] = {
+      iL,
+      FWD ? (j == 1 ? C0 : j == 2 ? Q : C1) : (j == 2 ? C1 : j == 1 ? Q + te : C0),
+      FWD ? (j == 2 ? Q + te : Q + 2 * te) : (j == 1 ? Q + 3 * te : Q),
+      FWD ? Q + 3 * te : Q + 2 * te};
+  const float *Vt[4] = {
+      V[j], FWD ? (j == 1 ? V[0] : j == 2 ? V[0] : V[2]) : (j == 2 ? V[3] : j == 1 ? V[2] : V[1]),
+      FWD ? (j == 2 ? V[1] : V[0]) : (j == 1 ? V[3] : V[2]), FWD ? V[1] : V[3]};
+  const int klo[4] = {FWD ? 0 : row0, 0, 0, 0};
+  const int khi[4] = {FWD ? row0 + 16 : nb, nterm > 1 ? nb : 0, nterm > 2 ? nb : 0,
+                      nterm > 3 ? nb : 0};
   const float sg[4] = {1.f, -1.f, -1.f, -1.f};
-  int nterm = 1;
-  if (FWD) {
-    if (j == 1) { M[1] = C0; Vt[1] = V[0]; nterm = 2; }
-    if (j == 2) { M[1] = Q; Vt[1] = V[0]; M[2] = Q + te; Vt[2] = V[1]; nterm = 3; }
-    if (j == 3) {
-      M[1] = C1; Vt[1] = V[2]; M[2] = Q + 2 * te; Vt[2] = V[0]; M[3] = Q + 3 * te; Vt[3] = V[1];
-      nterm = 4;
-    }
-  } else {
-    if (j == 2) { M[1] = C1; Vt[1] = V[3]; nterm = 2; }
-    if (j == 1) { M[1] = Q + te; Vt[1] = V[2]; M[2] = Q + 3 * te; Vt[2] = V[3]; nterm = 3; }
-    if (j == 0) {
-      M[1] = C0; Vt[1] = V[1]; M[2] = Q; Vt[2] = V[2]; M[3] = Q + 2 * te; Vt[3] = V[3];
-      nterm = 4;
-    }
-  }
-  for (int t = nterm; t < 4; ++t) { M[t] = iL; Vt[t] = V[j]; klo[t] = khi[t] = 0; }
   const v4f acc = job_product4<!FWD>(M, Vt, klo, khi, sg, nterm, nb, r, ldv, row0, col0, red);
   store_job<true, false>(Out + tile_off<true>(k + j, nb, r), r, ldv, row0,
                          col0 + (threadIdx.x & 15), acc);
@@ -432,11 +456,13 @@ __global__ __launch_bounds__(256) void k_sweep_panel2(const float *__restrict__ 
 // are not stored).  The 16-row form needs one round trip per phase of loads
 // and a reduction across all four waves.
 // P tiles a step (2: a pair; 4: a quad, nb = 256): the same with P nb
-// values of k, split over P nb / 512 waves a job.
+// values of k, split over P nb / 512 waves a job.  t0: the launch covers
+// the panel's row tiles from t0 on (forward: tile k + P + t0 first;
+// backward: tile t0 first), so that a panel can be split over launches.
 template <bool FWD, int NB, int W, int P = 2>
 __global__ __launch_bounds__(64 * W) void k_sweep_panel2w(const float *__restrict__ Lst,
                                                           const float *V, float *In, int k, int r,
-                                                          int64_t ldv) {
+                                                          int64_t ldv, int t0) {
   typedef __attribute__((address_space(3))) void lds_void;
   constexpr int S = P * NB / 512, ROWS = 16 * W / S, RB = NB / ROWS, VST = P * NB + 4;
   constexpr int CPC = P * NB / 256, VCH = 16 * CPC / W;  // 1 KiB chunks a column; a wave
@@ -446,7 +472,7 @@ __global__ __launch_bounds__(64 * W) void k_sweep_panel2w(const float *__restric
   const int CJ = (r + 15) / 16;
   const int64_t t = blockIdx.x / (RB * CJ);
   const int rem = (int)(blockIdx.x % (RB * CJ)), rj = rem / CJ, cj = rem % CJ;
-  const int64_t i = FWD ? k + P + t : t;
+  const int64_t i = FWD ? k + P + t0 + t : t0 + t;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int li = lane & 15, lg = lane >> 4;
   const int job = wave / S, part = wave % S;
@@ -524,12 +550,12 @@ static int sweep_wide() {
 
 template <bool FWD, int NB, int W, int P = 2>
 static void launch_panel2w(const float *Astore, const float *V, float *In, int k, int ntiles,
-                           int r, int64_t ldv, hipStream_t s) {
+                           int r, int64_t ldv, hipStream_t s, int t0 = 0) {
   const size_t lds = (size_t)16 * (P * NB + 4) * sizeof(float);  // 65.8 KB at P nb = 1024
   solve_kernel_attrs();
   const int64_t blocks = (int64_t)ntiles * (NB * (P * NB / 512) / (16 * W)) * ((r + 15) / 16);
   hipLaunchKernelGGL((k_sweep_panel2w<FWD, NB, W, P>), dim3((unsigned)blocks), dim3(64 * W), lds,
-                     s, Astore, V, In, k, r, ldv);
+                     s, Astore, V, In, k, r, ldv, t0);
 }
 
 template <bool FWD>
@@ -598,20 +624,63 @@ void launch_sweeps_batched(const SolveJob *jobs, int njobs, int ntmax, int nb, i
 // go in pairs (0, 1), (2, 3), ..., the last one alone when nt is odd.
 bool sweep_quads_supported(int nb) { return nb == 256 && sweep_wide() == 4; }
 
+// The ordering of a split sweep: fork() lets the second stream start after
+// what s holds so far (the quad's diagonal step); join_later() marks the
+// launch just put on the second stream and makes s wait for the one before
+// it (the two update the same tiles); join() makes s wait for the last one.
+// Each record takes an event of its own.
+struct SplitChain {
+  const SweepSplit *sp;
+  hipStream_t s;
+  int used = 0;
+  hipEvent_t pend = nullptr;
+  SplitChain(const SweepSplit *sp_, hipStream_t s_) : sp(sp_), s(s_) {}
+  bool on() const { return sp && used + 2 <= sp->nev; }
+  void fork() {
+    hipEvent_t e = sp->ev[used++];
+    (void)hipEventRecord(e, s);
+    (void)hipStreamWaitEvent(sp->s2, e, 0);
+  }
+  void join_later() {
+    hipEvent_t e = sp->ev[used++];
+    (void)hipEventRecord(e, sp->s2);
+    if (pend) (void)hipStreamWaitEvent(s, pend, 0);
+    pend = e;
+  }
+  void join() {
+    if (pend) (void)hipStreamWaitEvent(s, pend, 0);
+    pend = nullptr;
+  }
+};
+
 void launch_fwd_sweep(const float *Astore, const float *Linv, const float *C, const float *Q,
-                      const TileLayout &L, int r, float *B, float *Z, hipStream_t s) {
+                      const TileLayout &L, int r, float *B, float *Z, hipStream_t s,
+                      const SweepSplit *sp) {
   const int nb = L.nb, NT = L.nt, CJ = (r + 15) / 16, per = (nb / 16) * CJ;
   const int64_t te = (int64_t)nb * nb, ldv = L.np;
   const bool quads = C && Q && sweep_quads_supported(nb);
+  SplitChain ch(sp, s);
   for (int k = 0; k < NT;) {
     if (quads && k % 4 == 0 && k + 3 < NT) {
       hipLaunchKernelGGL(k_sweep_diag4<true>, dim3(4 * per), dim3(256), 0, s, Linv, C, Q, B, Z,
                          k, nb, r, ldv);
-      if (NT - 4 - k > 0)
-        launch_panel2w<true, 256, 4, 4>(Astore, Z, B, k, NT - 4 - k, r, ldv, s);
+      const int rest = NT - 4 - k;
+      if (rest > 4 && ch.on()) {
+        // tiles k+8.. on the second stream once Z of this quad is out; the
+        // next quad's tiles here, after the previous step's second part (both
+        // update those tiles)
+        ch.fork();
+        launch_panel2w<true, 256, 4, 4>(Astore, Z, B, k, rest - 4, r, ldv, sp->s2, 4);
+        ch.join_later();
+        launch_panel2w<true, 256, 4, 4>(Astore, Z, B, k, 4, r, ldv, s, 0);
+      } else if (rest > 0) {
+        ch.join();
+        launch_panel2w<true, 256, 4, 4>(Astore, Z, B, k, rest, r, ldv, s);
+      }
       k += 4;
       continue;
     }
+    ch.join();
     if (C && k + 1 < NT) {
       hipLaunchKernelGGL(k_sweep_diag2<true>, dim3(2 * per), dim3(256), 0, s, Linv,
                          C + (int64_t)(k / 2) * te, B, Z, k, nb, r, ldv);
@@ -626,23 +695,35 @@ void launch_fwd_sweep(const float *Astore, const float *Linv, const float *C, co
                          s, Astore, Z + (int64_t)k * nb, B, k, nb, r, ldv);
     ++k;
   }
+  ch.join();
 }
 
 // L^T X = Z (Z is overwritten); the pairs of the forward sweep, last first.
 void launch_bwd_sweep(const float *Astore, const float *Linv, const float *C, const float *Q,
-                      const TileLayout &L, int r, float *Z, float *X, hipStream_t s) {
+                      const TileLayout &L, int r, float *Z, float *X, hipStream_t s,
+                      const SweepSplit *sp) {
   const int nb = L.nb, NT = L.nt, CJ = (r + 15) / 16, per = (nb / 16) * CJ;
   const int64_t te = (int64_t)nb * nb, ldv = L.np;
   const bool quads = C && Q && sweep_quads_supported(nb);
+  SplitChain ch(sp, s);
   for (int k = NT - 1; k >= 0;) {
     if (quads && k % 4 == 3) {  // the quad (k-3 .. k) of the forward sweep
       const int k0 = k - 3;
       hipLaunchKernelGGL(k_sweep_diag4<false>, dim3(4 * per), dim3(256), 0, s, Linv, C, Q, Z, X,
                          k0, nb, r, ldv);
-      if (k0 > 0) launch_panel2w<false, 256, 4, 4>(Astore, X, Z, k0, k0, r, ldv, s);
+      if (k0 > 4 && ch.on()) {  // tiles 0 .. k0-5 on the second stream, as forward
+        ch.fork();
+        launch_panel2w<false, 256, 4, 4>(Astore, X, Z, k0, k0 - 4, r, ldv, sp->s2, 0);
+        ch.join_later();
+        launch_panel2w<false, 256, 4, 4>(Astore, X, Z, k0, 4, r, ldv, s, k0 - 4);
+      } else if (k0 > 0) {
+        ch.join();
+        launch_panel2w<false, 256, 4, 4>(Astore, X, Z, k0, k0, r, ldv, s);
+      }
       k -= 4;
       continue;
     }
+    ch.join();
     if (C && k % 2 == 1) {  // the pair (k-1, k)
       const int k0 = k - 1;
       hipLaunchKernelGGL(k_sweep_diag2<false>, dim3(2 * per), dim3(256), 0, s, Linv,
@@ -658,6 +739,7 @@ void launch_bwd_sweep(const float *Astore, const float *Linv, const float *C, co
                          X + (int64_t)k * nb, Z, k, nb, r, ldv);
     --k;
   }
+  ch.join();
 }
 
 // Row-major FP64 np x r into column-major FP32 (column stride np), and back

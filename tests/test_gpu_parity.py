@@ -283,6 +283,37 @@ def test_quad_sweeps_match_pairs(monkeypatch, n, r):
     c.close()
 
 
+@pytest.mark.parametrize("n,r", [(3072, 16), (4500, 5), (6000, 33)])
+def test_split_quad_sweeps_match_one_stream(monkeypatch, n, r):
+    """Quad sweep steps whose panel is split in two launches (the next quad's
+    tiles on the solve's stream, the rest on a second stream that overlaps the
+    next diagonal step) give the bits of the one-launch panels: every tile is
+    updated by the same workgroup code in the same order.  12, 18 and 24 tiles
+    (quads only; quads with a pair tail; 1-3 column blocks), ragged n; and the
+    refined result matches the oracle."""
+    m = 500
+    G = _gen(n, m, seed=n + 41)
+    Y = synth.phenotypes(G, r, n_pairs=5, n_add=3, seed=n + 42, h2=0.5)
+    gamma, lam = 1.0 / m, 0.1
+    c = krr.krr_create(0, tile=256)
+    K = krr.krr_build_kernel(c, _dev(G), gamma, lam)
+    F = krr.krr_factor(c, K, krr.plain_fp32_policy())
+    none = krr.Refine(method=krr.KRR_REFINE_NONE)
+    monkeypatch.setenv("KRR_SWEEP_SPLIT", "0")
+    X0, _, _ = krr.krr_solve(c, F, _dev(Y), none)
+    monkeypatch.setenv("KRR_SWEEP_SPLIT", "1")
+    for rep in range(2):
+        Xs, _, _ = krr.krr_solve(c, F, _dev(Y), none)
+        assert torch.equal(Xs, X0), rep
+    X, info, st = krr.krr_solve(c, F, _dev(Y), krr.Refine(tol=1e-8))
+    monkeypatch.delenv("KRR_SWEEP_SPLIT")
+    assert info.converged == 1
+    assert _colrel(X.cpu().numpy(), oracle.fit(G, Y, gamma, lam)) <= TOL
+    F.release()
+    K.release()
+    c.close()
+
+
 @pytest.mark.parametrize("n,r,tile", [(700, 5, 256), (1500, 17, 256), (1300, 40, 512),
                                        (2600, 16, 512)])
 def test_wide_panel_sweeps_match_narrow(monkeypatch, n, r, tile):
