@@ -343,13 +343,22 @@ template <typename T, bool ADD>
 __device__ __forceinline__ void store64(T *dst, int64_t ld, const typename M16<T>::v4 (&acc)[4],
                                         T alpha) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  // ADD: all sixteen loads issued before the first store (the compiler may
+  // not move a load past a store to a possibly equal address)
+  T old[4][4] = {};
+  if (ADD) {
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        old[ct][r] = dst[(int64_t)(16 * wave + M16<T>::row(r, lane)) * ld + 16 * ct + (lane & 15)];
+  }
 #pragma unroll
   for (int ct = 0; ct < 4; ++ct)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       T *p = dst + (int64_t)(16 * wave + M16<T>::row(r, lane)) * ld + 16 * ct + (lane & 15);
-      if (ADD) *p += alpha * acc[ct][r];
-      else *p = alpha * acc[ct][r];
+      *p = ADD ? old[ct][r] + alpha * acc[ct][r] : alpha * acc[ct][r];
     }
 }
 
@@ -894,6 +903,25 @@ KRR_DEV void potrf_load_body(float *__restrict__ Akk, T *__restrict__ W, int nb,
   if (bid == 0 && threadIdx.x < du.npan && du.pmap)
     du.pmap[du.pmap_at[threadIdx.x]] = (uint8_t)KRR_PREC_FP32;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  // every entry of the block loaded (upper ones too: they are in the tile),
+  // all loads in flight before the first use: a load under the c <= r
+  // condition would take a round trip of its own
+  float av[S::WTM][S::WTN][16];
+#pragma unroll
+  for (int tm = 0; tm < S::WTM; ++tm)
+#pragma unroll
+    for (int tn = 0; tn < S::WTN; ++tn)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const int r = bi * 64 + S::row(wave, tm, e, lane), c = bj * 64 + S::col(wave, tn, lane);
+        av[tm][tn][e] = Akk[(int64_t)r * nb + c];
+      }
+#pragma unroll
+  for (int tm = 0; tm < S::WTM; ++tm)
+#pragma unroll
+    for (int tn = 0; tn < S::WTN; ++tn)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) asm volatile("" : "+v"(av[tm][tn][e]));
 #pragma unroll
   for (int tm = 0; tm < S::WTM; ++tm)
 #pragma unroll
@@ -902,7 +930,7 @@ KRR_DEV void potrf_load_body(float *__restrict__ Akk, T *__restrict__ W, int nb,
       for (int e = 0; e < 16; ++e) {
         const int r = bi * 64 + S::row(wave, tm, e, lane), c = bj * 64 + S::col(wave, tn, lane);
         const int64_t o = (int64_t)r * nb + c;
-        W[o] = (c <= r) ? (T)Akk[o] - (T)acc[tm][tn][e] : (T)0;
+        W[o] = (c <= r) ? (T)av[tm][tn][e] - (T)acc[tm][tn][e] : (T)0;
       }
   if (If && bi > bj) {
     __syncthreads();  // every read of this workgroup's block is done (it is not the zeroed one)
